@@ -1,0 +1,186 @@
+/*
+ * libls -- MI355X (gfx950) solver for the discretised 2D Lippmann-Schwinger equation
+ *
+ *     A psi = f,   A = I + s kappa^2 diag(q) V,   f = -s kappa^2 q u_inc
+ *
+ * (Gujjula & Ambikasaran, "A new Directional Algebraic Fast Multipole Method based
+ * iterative solver for the Lippmann-Schwinger equation accelerated with HODLR
+ * preconditioner": Section 1, Eqs. (eq:3), (eq:5), (eq:6); Section 2.2, Eqs. (eq:12a),
+ * (eq:13)).  V is the volume potential discretised on a uniform cell-centred grid with
+ * one collocation point per cell (p = 1): V_ij = h^2 (i/4) H0^(1)(kappa |x_i - x_j|)
+ * for i != j and the exact integral of G over the cell for i = j.  The physical sign is
+ * s = -1 (so psi = kappa^2 q u); s = +1 reproduces Eq. (eq:6) as printed.
+ *
+ * Products with V use the Directional Algebraic FMM of Section 4 with Nested Cross
+ * Approximation factors (Section 3); solves use GMRES (Section 5), optionally right-
+ * preconditioned by a fixed-rank HODLR approximation of A (Section 5, Eq. (eq:hybrid)).
+ *
+ * Conventions for every call below
+ *   - Setup inputs are HOST arrays and are copied.  Vectors passed to vector calls are
+ *     DEVICE pointers owned by the caller, complex interleaved (re, im): complex128
+ *     (double[2]) unless stated otherwise.  Several right-hand sides are stored
+ *     column-major, column j at offset j*ld (in complex elements), ld >= N.
+ *   - Vectors are in the caller's point order (the order of `points` given to ls_setup).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Vector calls are
+ *     asynchronous on it unless stated otherwise.
+ *   - Every call returns an ls_status; on a non-OK status ls_last_error() returns a
+ *     message for the calling thread.  A non-converged solve is not an error: it is
+ *     reported in ls_solve_info.status.
+ *   - A handle is immutable after ls_setup and may be used from one stream at a time.
+ */
+#ifndef LS_H
+#define LS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ls_problem ls_problem; /* opaque, owned by the library */
+
+typedef enum {
+  LS_OK = 0,
+  LS_EINVAL = -1,  /* invalid argument (message in ls_last_error) */
+  LS_ENOMEM = -2,  /* host or device allocation failed */
+  LS_EDEVICE = -3, /* a HIP runtime call failed */
+  LS_ENOTSUP = -4  /* input valid but outside what this build supports */
+} ls_status;
+
+typedef enum {
+  LS_FP64 = 0,  /* complex128 operator, complex128 accumulation */
+  LS_FP32 = 1,  /* complex64 operator and accumulation (near field, M2L, translations) */
+  LS_MIXED = 2  /* ls_solve only: FP32 inner GMRES, FP64 residual and refinement */
+} ls_prec;
+
+enum {
+  LS_CONVERGED = 0,
+  LS_MAXIT = 1,
+  LS_BREAKDOWN = 2,
+  LS_NAN = 3,
+  LS_REFINE_STAGNATED = 4,
+  LS_WARMSTART_REJECTED = 5
+};
+
+typedef struct {
+  int leaf_max;       /* max points per quadtree leaf (default 64) */
+  double T;           /* a box of half-width w is high-frequency iff (kappa w)^2 > T (default 16) */
+  int sign;           /* s in A = I + s kappa^2 diag(q) V; -1 (default) or +1 */
+  int hodlr_rank;     /* fixed off-diagonal rank r of the HODLR preconditioner; 0 = none (default 15) */
+  double eps_inner;   /* NCA tolerance of the FP32 operator; <= 0: cast of the FP64 operator (default 1e-7) */
+  int restart;        /* GMRES restart length m (default 200) */
+  int maxit;          /* max GMRES iterations per solve (default 2000) */
+  int prec;           /* ls_prec used by ls_solve (default LS_FP64) */
+  double inner_tol;   /* LS_MIXED: relative tolerance floor of each inner FP32 solve (default 1e-6) */
+  int max_refine;     /* LS_MIXED: max outer refinement steps (default 10) */
+  int build_fp32;     /* build the FP32 operator at setup (default 1) */
+} ls_options;
+
+typedef struct {
+  int iters;          /* total GMRES iterations (inner iterations summed in LS_MIXED) */
+  double relres;      /* final true relative residual ||f - A psi|| / ||f|| (FP64 operator) */
+  int status;         /* LS_CONVERGED, LS_MAXIT, ... */
+  int n_refine;       /* LS_MIXED: outer refinement steps taken */
+  double t_solve_ms;  /* wall time of the call */
+} ls_solve_info;
+
+typedef struct {
+  int64_t N;
+  int n;              /* grid side */
+  int levels;         /* quadtree leaf level L (root = 0) */
+  int leaf_side;      /* cells per leaf side */
+  int top_level;      /* coarsest level with a non-empty interaction list */
+  int nlevels_hf;     /* number of high-frequency levels with interaction lists */
+  int rank_max64;     /* largest NCA rank of the FP64 operator */
+  int rank_max32;     /* largest NCA rank of the FP32 operator */
+  int64_t entries_near;   /* near-field kernel entries applied per matvec (one RHS) */
+  int64_t entries_far64;  /* P2M+M2M+M2L+L2L+L2P entries applied per FP64 matvec */
+  int64_t entries_far32;  /* same for the FP32 operator */
+  int64_t m2l_pairs;      /* (box[,direction], source) M2L pairs over all levels */
+  int64_t stored_bytes64; /* device bytes of the FP64 DAFMM operators */
+  int64_t stored_bytes32;
+  int64_t hodlr_bytes;    /* device bytes of the HODLR factors */
+  double t_plan_ms, t_nca_ms, t_hodlr_ms, t_setup_ms;
+} ls_stats_t;
+
+/* Plan description for a uniform n x n grid on [-L, L]^2 (host only, no device use).
+ * Per level nu (0..levels): hf[nu], ndir[nu] (cones), il_pairs[nu] (in-domain M2L pairs
+ * over (box, direction)), max_il[nu]; near_pairs = ordered neighbouring leaf pairs.
+ * coverage_min/max: over all ordered leaf pairs, the number of times each pair is
+ * handled (near field or exactly one M2L); both must be 1 (Section 4: every
+ * interaction is either near field or transferred by one M2L).  Arrays hold 32 levels. */
+typedef struct {
+  int levels, leaf_side, top_level;
+  int hf[32], ndir[32], max_il[32];
+  int64_t il_pairs[32];
+  int64_t near_pairs;
+  int coverage_min, coverage_max;
+} ls_plan_info;
+
+void ls_default_options(ls_options* opt);
+
+/* Build the solver for the points of a uniform cell-centred n x n grid (any order).
+ *   points : host, N x 2 row-major (x1, x2); must form a uniform cell-centred square grid.
+ *   q      : host, N real contrast values q(x_i) in the same order.
+ *   kappa  : wavenumber > 0.   tol : NCA tolerance eps_NCA in (0, 1) (Section 3.2.2).
+ *   opt    : NULL for defaults.  *out receives the handle (NULL on error).
+ * Synchronous.  Uses the current HIP device.  Errors: LS_EINVAL (N <= 0, kappa <= 0,
+ * tol outside (0,1), non-finite or duplicate points, non-finite q, bad options);
+ * LS_ENOTSUP (points not a uniform square grid, or a grid the quadtree cannot split
+ * into leaves of <= leaf_max points). */
+ls_status ls_setup(const double* points, int64_t N, const double* q, double kappa, double tol,
+                   const ls_options* opt, ls_problem** out);
+
+/* y = A x (Eq. (eq:12a)) with the DAFMM product (Section 4) for V.
+ * x, y: device, N x nrhs complex128, leading dimension ld.  prec: LS_FP64 or LS_FP32
+ * (FP32 converts x to complex64 for the operator and accumulates the result in
+ * complex128).  x and y must not overlap. */
+ls_status ls_matvec(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld, int prec, void* stream);
+
+/* u = V psi: the scattered field on the grid (Section 5, last paragraph before 5.1). */
+ls_status ls_apply_V(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld, int prec, void* stream);
+
+/* z = A~^{-1} r with the fixed-rank HODLR approximation A~ of A (Section 5, Eq. (eq:hybrid)).
+ * prec LS_FP64: all factors complex128; LS_FP32: off-diagonal factors stored complex64,
+ * leaf and SMW core solves complex128.  LS_ENOTSUP when hodlr_rank = 0. */
+ls_status ls_precond_apply(ls_problem* P, const void* r, void* z, int nrhs, int64_t ld, int prec, void* stream);
+
+/* f_j = -s kappa^2 q u_inc(theta_j), u_inc = exp(i kappa (cos t x1 + sin t x2)) (Section 5.2).
+ * angles: host, nrhs values.  f: device, N x nrhs complex128. */
+ls_status ls_rhs_planewave(ls_problem* P, const double* angles, int nrhs, void* f, int64_t ld, void* stream);
+
+/* Solve A psi = f for nrhs columns by restarted GMRES with right HODLR preconditioning
+ * (when hodlr_rank > 0), stopping when ||f - A psi|| / ||f|| <= tol per column.
+ * f, psi: device, N x nrhs complex128.  x0_given != 0: psi holds the initial guess (a
+ * guess whose residual is not below ||f|| is replaced by zero, status bit
+ * LS_WARMSTART_REJECTED reported in info[j].status when the column otherwise converged).
+ * info: host array of nrhs entries (may be NULL).  Synchronous on `stream`. */
+ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld, double tol,
+                   int x0_given, ls_solve_info* info, void* stream);
+
+/* Table of V entries for grid offsets (Section 1 Green's function, Eq. (eq:13) at p = 1):
+ * out[(da + n-1) * (2n-1) + (db + n-1)] = h^2 (i/4) H0^(1)(kappa h |(da, db)|) for (da, db) != 0 and
+ * the exact integral of G over the cell at (0, 0); |da|, |db| <= n-1.  out: device, (2n-1)^2
+ * complex128, owned by the caller.  Synchronous on `stream`.  LS_ENOTSUP if kappa h >= 4/0.7072. */
+ls_status ls_green_table(int n, double h, double kappa, void* out, void* stream);
+
+/* Counters of the handle (ranks, entries applied per matvec, bytes, setup timings). */
+ls_status ls_stats(const ls_problem* P, ls_stats_t* out);
+void ls_destroy(ls_problem* P);
+const char* ls_last_error(void);
+
+/* Host-only: plan (quadtree, regimes, cones, lists, coverage) for an n x n grid on [-L,L]^2. */
+ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt, ls_plan_info* out);
+
+/* Kernel timing with HIP events recorded around every launch of one kernel class on
+ * the launch stream: class 0 = near field (P2P + M2L launch), 1 = HODLR level update,
+ * 2 = leaf solve, 3 = Arnoldi dot products.  enable = 1 starts (and clears) the
+ * counters, 0 stops.  ls_profile_read synchronises and returns the summed event time
+ * and the number of timed launches. */
+ls_status ls_profile_enable(ls_problem* P, int kernel_class, int enable);
+ls_status ls_profile_read(ls_problem* P, int kernel_class, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LS_H */

@@ -1,0 +1,1639 @@
+// C ABI of libls: setup, DAFMM matvec, HODLR preconditioner, GMRES solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/ls.h"
+#include "h0.h"
+#include "kernels.h"
+#include "plan.h"
+
+using ls::LsError;
+using ls::Off;
+using ls::zd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw LsError(LS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) b = 16;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw LsError(LS_ENOMEM, std::string("hipMalloc(") + std::to_string(b) + "): " + hipGetErrorString(e));
+    }
+    bytes = b;
+  }
+  void ensure(size_t b) {
+    if (bytes < b) alloc(b);
+  }
+  template <class T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+  template <class T>
+  void upload(const std::vector<T>& v) {
+    alloc(v.size() * sizeof(T));
+    if (!v.empty()) hip_check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+  }
+};
+
+template <class F>
+void parallel_for(int n, F f) {
+  int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  nt = std::min(nt, std::max(1, n));
+  std::atomic<int> next(0);
+  std::vector<std::thread> th;
+  std::vector<std::string> errs(nt);
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t]() {
+      try {
+        for (;;) {
+          int i = next.fetch_add(1);
+          if (i >= n) break;
+          f(i);
+        }
+      } catch (const std::exception& e) {
+        errs[t] = e.what();
+      }
+    });
+  for (auto& x : th) x.join();
+  for (auto& e : errs)
+    if (!e.empty()) throw LsError(LS_EINVAL, e);
+}
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// ---------------------------------------------------------------------------------------
+// Device-side DAFMM operator for one precision.
+// ---------------------------------------------------------------------------------------
+struct Phase {
+  DevBuf tasks, terms, blk;
+  int nblocks = 0;
+  int ntasks = 0;
+};
+
+struct FmmDev {
+  bool fp32 = false;
+  int esz = 16;  // bytes per complex element
+  DevBuf ops;    // packed operator matrices
+  // per-level multipole / local arrays (levels top..leaf), sized for nrhs_cap
+  DevBuf mult, loc, xs, ys;
+  std::vector<long long> lvl_off;    // element offset of level nu inside mult/loc (rhs 0)
+  std::vector<long long> lvl_size;   // elements per rhs of level nu
+  long long ml_rhs = 0;              // rhs stride of mult/loc
+  int nrhs_cap = 0;
+  Phase p2m, nearm2l, l2p;
+  std::vector<Phase> up;    // M2M, deepest parent first
+  std::vector<Phase> down;  // L2L, top parent first
+  // host copies of per-level ranks
+  std::vector<std::vector<int>> rank;
+  std::vector<int> kmax;
+  int kleaf = 0;
+  // operator locations (element offsets in ops) for descriptor building
+  long long off_U = 0, off_Ut = 0;
+  long long off_near[9] = {0};
+  std::vector<std::vector<std::vector<long long>>> off_C;    // [nu][dir][c]: M2M op = C (k_child x Mpad(k))
+  std::vector<std::vector<std::vector<long long>>> off_Ct;   // [nu][dir][c]: L2L op = C^T (k x Mpad(k_child))
+  std::vector<std::vector<std::vector<long long>>> off_K;    // [nu][dir][term]: M2L op = K^T
+  int64_t entries_far = 0;
+  int64_t stored_bytes = 0;
+};
+
+struct HodlrDev {
+  int r = 0, Lb = 0, nleaves = 0, lp = 0;
+  long long N = 0;
+  DevBuf Dinv, ident;
+  std::vector<DevBuf> Y64, W64, Y32, W32, coreinv;
+  DevBuf partial, svec;
+  std::vector<long long> chunk;  // per level
+  std::vector<int> nchunks, cpc;
+  int64_t bytes = 0;
+};
+
+struct ProfileClass {
+  bool enabled = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t used = 0;
+};
+
+}  // namespace
+
+struct ls_problem {
+  ls_options opt;
+  ls::Plan plan;
+  ls::NCA nca64, nca32;
+  long long N = 0;
+  int n = 0;
+  double kappa = 0, tol = 0, coef = 0;
+  // index maps (device): s2c/c2s caller <-> S, s2m/m2s Morton <-> S, m2c Morton -> caller
+  DevBuf s2c, c2s, s2m, m2s, m2c;
+  DevBuf q_c, q_m, px, py;
+  FmmDev f64, f32;
+  bool have32 = false;
+  HodlrDev hod;
+  bool have_hodlr = false;
+  // workspaces
+  DevBuf w_x, w_y, w_t;  // Morton-order vectors (nrhs_cap)
+  int ws_cap = 0;
+  ls_stats_t stats{};
+  ProfileClass prof[4];
+  // Krylov workspace
+  DevBuf kQ, kw, kz, kr, kh, kpart, knp, kno, kalpha, ky, kx, kf, kdx;
+  size_t kcap_key = 0;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------------------
+// profiling
+// ---------------------------------------------------------------------------------------
+struct ProfScope {
+  ProfileClass* pc;
+  hipStream_t s;
+  hipEvent_t e1 = nullptr;
+  ProfScope(ls_problem* P, int cls, hipStream_t st) : pc(&P->prof[cls]), s(st) {
+    if (!pc->enabled) {
+      pc = nullptr;
+      return;
+    }
+    if (pc->used == pc->ev.size()) {
+      hipEvent_t a, b;
+      hip_check(hipEventCreate(&a), "hipEventCreate");
+      hip_check(hipEventCreate(&b), "hipEventCreate");
+      pc->ev.push_back({a, b});
+    }
+    auto& pr = pc->ev[pc->used++];
+    hip_check(hipEventRecord(pr.first, s), "hipEventRecord");
+    e1 = pr.second;
+  }
+  ~ProfScope() {
+    if (pc) (void)hipEventRecord(e1, s);
+  }
+};
+
+// ---------------------------------------------------------------------------------------
+// operator upload and descriptor construction
+// ---------------------------------------------------------------------------------------
+struct OpPacker {
+  std::vector<zd> data;
+  // store X^T for X (M x K row-major): op[k][m], rows padded to Mpad
+  long long add_transposed(const std::vector<zd>& X, int M, int K) {
+    int Mpad = round_up(std::max(M, 1), lsk::kRowBlock);
+    long long off = (long long)data.size();
+    data.resize(data.size() + (size_t)K * Mpad, zd(0));
+    for (int m = 0; m < M; ++m)
+      for (int k = 0; k < K; ++k) data[off + (size_t)k * Mpad + m] = X[(size_t)m * K + k];
+    return off;
+  }
+  // store X (K x M row-major) directly as op[k][m] with padding
+  long long add_direct(const std::vector<zd>& X, int K, int M) {
+    int Mpad = round_up(std::max(M, 1), lsk::kRowBlock);
+    long long off = (long long)data.size();
+    data.resize(data.size() + (size_t)K * Mpad, zd(0));
+    for (int k = 0; k < K; ++k)
+      for (int m = 0; m < M; ++m) data[off + (size_t)k * Mpad + m] = X[(size_t)k * M + m];
+    return off;
+  }
+};
+
+void build_fmm_ops(ls_problem* P, const ls::NCA& nca, FmmDev& F, bool fp32) {
+  const ls::Plan& p = P->plan;
+  F.fp32 = fp32;
+  F.esz = fp32 ? 8 : 16;
+  const int leaf = p.leaf, s = p.leaf_side, s2 = s * s;
+  OpPacker pk;
+  for (int t = 0; t < 9; ++t) F.off_near[t] = pk.add_transposed(nca.near[t], s2, s2);
+  F.rank.assign(leaf + 1, {});
+  F.kmax.assign(leaf + 1, 0);
+  F.off_C.assign(leaf + 1, {});
+  F.off_Ct.assign(leaf + 1, {});
+  F.off_K.assign(leaf + 1, {});
+  F.entries_far = 0;
+  if (p.top <= leaf) {
+    F.kleaf = nca.kleaf;
+    // P2M op = U as [pt][rank]; L2P op = U^T as [rank][pt]
+    F.off_U = pk.add_direct(nca.U, s2, nca.kleaf);
+    F.off_Ut = pk.add_transposed(nca.U, s2, nca.kleaf);
+    F.entries_far += 2LL * (int64_t)p.lv[leaf].nb * p.lv[leaf].nb * s2 * nca.kleaf;
+    for (int nu = p.top; nu <= leaf; ++nu) {
+      const ls::LevelNCA& L = nca.lv[nu];
+      const ls::Level& l = p.lv[nu];
+      F.rank[nu] = L.rank;
+      F.kmax[nu] = L.kmax;
+      F.off_K[nu].assign(l.ndir, {});
+      for (int dir = 0; dir < l.ndir; ++dir) {
+        int ad = ls::antipodal(dir, l.ndir);
+        for (size_t t = 0; t < L.K[dir].size(); ++t)
+          F.off_K[nu][dir].push_back(pk.add_transposed(L.K[dir][t], L.rank[dir], L.rank[ad]));
+      }
+      if (nu < leaf) {
+        const ls::Level& cl = p.lv[nu + 1];
+        F.off_C[nu].assign(l.ndir, std::vector<long long>(4, 0));
+        F.off_Ct[nu].assign(l.ndir, std::vector<long long>(4, 0));
+        for (int dir = 0; dir < l.ndir; ++dir) {
+          int cd = cl.hf ? dir / 2 : 0;
+          int kc = nca.lv[nu + 1].rank[cd];
+          int k = L.rank[dir];
+          for (int c = 0; c < 4; ++c) {
+            const std::vector<zd>& C = L.C[dir][c];  // kc x k
+            F.off_C[nu][dir][c] = pk.add_direct(C, kc, k);
+            F.off_Ct[nu][dir][c] = pk.add_transposed(C, kc, k);
+            F.entries_far += 2LL * (int64_t)l.nb * l.nb * kc * k;  // M2M + L2L over all parent boxes
+          }
+        }
+      }
+      // M2L entries over in-domain pairs
+      int nh = l.nb / 2;
+      for (int c = 0; c < 4; ++c)
+        for (int dir = 0; dir < l.ndir; ++dir) {
+          int ad = ls::antipodal(dir, l.ndir);
+          for (const Off& d : l.terms[c * l.ndir + dir]) {
+            int ca = c >> 1, cb = c & 1, cnt_a = 0, cnt_b = 0;
+            for (int h = 0; h < nh; ++h) {
+              int sa = 2 * h + ca + d.a, sb = 2 * h + cb + d.b;
+              if (sa >= 0 && sa < l.nb) ++cnt_a;
+              if (sb >= 0 && sb < l.nb) ++cnt_b;
+            }
+            F.entries_far += (int64_t)cnt_a * cnt_b * L.rank[dir] * L.rank[ad];
+          }
+        }
+    }
+  }
+  if (fp32) {
+    std::vector<float> f(pk.data.size() * 2);
+    for (size_t i = 0; i < pk.data.size(); ++i) {
+      f[2 * i] = (float)pk.data[i].real();
+      f[2 * i + 1] = (float)pk.data[i].imag();
+    }
+    F.ops.upload(f);
+  } else {
+    F.ops.upload(pk.data);
+  }
+  F.stored_bytes = (int64_t)pk.data.size() * F.esz;
+}
+
+// Term/task descriptors for all phases, for the current mult/loc/xs/ys allocations.
+void build_phases(ls_problem* P, FmmDev& F) {
+  const ls::Plan& p = P->plan;
+  const int leaf = p.leaf, s2 = p.leaf_side * p.leaf_side;
+  const char* ops = F.ops.as<char>();
+  char* mult = F.mult.as<char>();
+  char* loc = F.loc.as<char>();
+  const long long es = F.esz;
+  auto opp = [&](long long off) { return (const void*)(ops + off * es); };
+  auto lvl_ptr = [&](char* base, int nu, int dir) {
+    const ls::Level& l = p.lv[nu];
+    long long nh = l.nb / 2;
+    return (void*)(base + (F.lvl_off[nu] + (long long)dir * F.kmax[nu] * 4 * nh * nh) * es);
+  };
+  const long long N = P->N;
+  auto make_phase = [&](Phase& ph, std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms) {
+    std::vector<int> blk;
+    for (size_t t = 0; t < tasks.size(); ++t) {
+      lsk::DTask& tk = tasks[t];
+      tk.Mpad = round_up(std::max(tk.M, 1), lsk::kRowBlock);
+      tk.nrb = tk.Mpad / lsk::kRowBlock;
+      tk.blk0 = (int)blk.size();
+      int nbb = (tk.nh * tk.nh + lsk::kBoxBlock - 1) / lsk::kBoxBlock;
+      for (int i = 0; i < nbb * tk.nrb; ++i) blk.push_back((int)t);
+    }
+    ph.tasks.upload(tasks);
+    ph.terms.upload(terms);
+    ph.blk.upload(blk);
+    ph.nblocks = (int)blk.size();
+    ph.ntasks = (int)tasks.size();
+  };
+  auto shift_term = [&](int c, Off d, int nh_in) {
+    lsk::DTerm tm{};
+    int ca = c >> 1, cb = c & 1;
+    int xa = ca + d.a, xb = cb + d.b;
+    tm.mode = lsk::MODE_SHIFT;
+    tm.cin = ((xa & 1) << 1) | (xb & 1);
+    tm.sha = (xa >= 0) ? xa / 2 : -((-xa + 1) / 2);
+    tm.shb = (xb >= 0) ? xb / 2 : -((-xb + 1) / 2);
+    tm.nh_in = nh_in;
+    return tm;
+  };
+  const int nhL = p.lv[leaf].nb / 2;
+  // ---- near field + M2L (one launch) ----
+  {
+    std::vector<lsk::DTask> tasks;
+    std::vector<lsk::DTerm> terms;
+    for (int c = 0; c < 4; ++c) {
+      lsk::DTask tk{};
+      tk.out = F.ys.p;
+      tk.out_rhs = N;
+      tk.M = s2;
+      tk.nh = nhL;
+      tk.cout = c;
+      tk.beta = 0;
+      tk.t0 = (int)terms.size();
+      for (int da = -1; da <= 1; ++da)
+        for (int db = -1; db <= 1; ++db) {
+          lsk::DTerm tm = shift_term(c, {da, db}, nhL);
+          tm.op = opp(F.off_near[(da + 1) * 3 + (db + 1)]);
+          tm.in = F.xs.p;
+          tm.in_rhs = N;
+          tm.K = s2;
+          terms.push_back(tm);
+        }
+      tk.t1 = (int)terms.size();
+      tasks.push_back(tk);
+    }
+    for (int nu = p.top; nu <= leaf; ++nu) {
+      const ls::Level& l = p.lv[nu];
+      int nh = l.nb / 2;
+      for (int dir = 0; dir < l.ndir; ++dir) {
+        int ad = ls::antipodal(dir, l.ndir);
+        // term index lookup for this direction's operator list
+        const auto& kofs = (F.fp32 ? P->nca32 : P->nca64).lv[nu].kofs[dir];
+        for (int c = 0; c < 4; ++c) {
+          lsk::DTask tk{};
+          tk.out = lvl_ptr(loc, nu, dir);
+          tk.out_rhs = F.ml_rhs;
+          tk.M = F.rank[nu][dir];
+          tk.nh = nh;
+          tk.cout = c;
+          tk.beta = 0;
+          tk.t0 = (int)terms.size();
+          if (F.rank[nu][ad] > 0)
+            for (const Off& d : l.terms[c * l.ndir + dir]) {
+              size_t ti = 0;
+              while (ti < kofs.size() && !(kofs[ti].a == d.a && kofs[ti].b == d.b)) ++ti;
+              if (ti == kofs.size()) throw LsError(LS_EINVAL, "internal: M2L offset missing");
+              lsk::DTerm tm = shift_term(c, d, nh);
+              tm.op = opp(F.off_K[nu][dir][ti]);
+              tm.in = lvl_ptr(mult, nu, ad);
+              tm.in_rhs = F.ml_rhs;
+              tm.K = F.rank[nu][ad];
+              terms.push_back(tm);
+            }
+          tk.t1 = (int)terms.size();
+          if (tk.M > 0) tasks.push_back(tk);
+        }
+      }
+    }
+    make_phase(F.nearm2l, tasks, terms);
+  }
+  if (p.top > leaf) return;
+  // ---- P2M ----
+  {
+    std::vector<lsk::DTask> tasks;
+    std::vector<lsk::DTerm> terms;
+    for (int c = 0; c < 4; ++c) {
+      lsk::DTask tk{};
+      tk.out = lvl_ptr(mult, leaf, 0);
+      tk.out_rhs = F.ml_rhs;
+      tk.M = F.kleaf;
+      tk.nh = nhL;
+      tk.cout = c;
+      tk.beta = 0;
+      tk.t0 = (int)terms.size();
+      lsk::DTerm tm{};
+      tm.mode = lsk::MODE_SAME;
+      tm.op = opp(F.off_U);
+      tm.in = F.xs.p;
+      tm.in_rhs = N;
+      tm.K = s2;
+      tm.nh_in = nhL;
+      terms.push_back(tm);
+      tk.t1 = (int)terms.size();
+      tasks.push_back(tk);
+    }
+    make_phase(F.p2m, tasks, terms);
+  }
+  // ---- L2P (accumulates onto the near field) ----
+  {
+    std::vector<lsk::DTask> tasks;
+    std::vector<lsk::DTerm> terms;
+    for (int c = 0; c < 4; ++c) {
+      lsk::DTask tk{};
+      tk.out = F.ys.p;
+      tk.out_rhs = N;
+      tk.M = s2;
+      tk.nh = nhL;
+      tk.cout = c;
+      tk.beta = 1;
+      tk.t0 = (int)terms.size();
+      lsk::DTerm tm{};
+      tm.mode = lsk::MODE_SAME;
+      tm.op = opp(F.off_Ut);
+      tm.in = lvl_ptr(loc, leaf, 0);
+      tm.in_rhs = F.ml_rhs;
+      tm.K = F.kleaf;
+      tm.nh_in = nhL;
+      terms.push_back(tm);
+      tk.t1 = (int)terms.size();
+      tasks.push_back(tk);
+    }
+    make_phase(F.l2p, tasks, terms);
+  }
+  // ---- M2M (parent nu from children nu+1), deepest first ----
+  F.up.clear();
+  F.up.resize(leaf - p.top);
+  for (int nu = leaf - 1; nu >= p.top; --nu) {
+    const ls::Level& l = p.lv[nu];
+    const ls::Level& cl = p.lv[nu + 1];
+    std::vector<lsk::DTask> tasks;
+    std::vector<lsk::DTerm> terms;
+    int nh = l.nb / 2;
+    for (int dir = 0; dir < l.ndir; ++dir) {
+      int cd = cl.hf ? dir / 2 : 0;
+      for (int c = 0; c < 4; ++c) {
+        lsk::DTask tk{};
+        tk.out = lvl_ptr(mult, nu, dir);
+        tk.out_rhs = F.ml_rhs;
+        tk.M = F.rank[nu][dir];
+        tk.nh = nh;
+        tk.cout = c;
+        tk.beta = 0;
+        tk.t0 = (int)terms.size();
+        for (int cc = 0; cc < 4; ++cc) {
+          lsk::DTerm tm{};
+          tm.mode = lsk::MODE_CHILD;
+          tm.cin = cc;
+          tm.op = opp(F.off_C[nu][dir][cc]);
+          tm.in = lvl_ptr(mult, nu + 1, cd);
+          tm.in_rhs = F.ml_rhs;
+          tm.K = F.rank[nu + 1][cd];
+          tm.nh_in = cl.nb / 2;
+          if (tm.K > 0) terms.push_back(tm);
+        }
+        tk.t1 = (int)terms.size();
+        if (tk.M > 0) tasks.push_back(tk);
+      }
+    }
+    make_phase(F.up[leaf - 1 - nu], tasks, terms);
+  }
+  // ---- L2L (parent nu -> children nu+1), top first ----
+  F.down.clear();
+  F.down.resize(leaf - p.top);
+  for (int nu = p.top; nu < leaf; ++nu) {
+    const ls::Level& l = p.lv[nu];
+    const ls::Level& cl = p.lv[nu + 1];
+    std::vector<lsk::DTask> tasks;
+    std::vector<lsk::DTerm> terms;
+    int nhc = cl.nb / 2;
+    for (int cdir = 0; cdir < cl.ndir; ++cdir) {
+      for (int c = 0; c < 4; ++c) {
+        lsk::DTask tk{};
+        tk.out = lvl_ptr(loc, nu + 1, cdir);
+        tk.out_rhs = F.ml_rhs;
+        tk.M = F.rank[nu + 1][cdir];
+        tk.nh = nhc;
+        tk.cout = c;
+        tk.beta = 1;
+        tk.t0 = (int)terms.size();
+        for (int dir = 0; dir < l.ndir; ++dir) {
+          int cd = cl.hf ? dir / 2 : 0;
+          if (cd != cdir) continue;
+          lsk::DTerm tm{};
+          tm.mode = lsk::MODE_PARENT;
+          tm.op = opp(F.off_Ct[nu][dir][c]);
+          tm.in = lvl_ptr(loc, nu, dir);
+          tm.in_rhs = F.ml_rhs;
+          tm.K = F.rank[nu][dir];
+          tm.nh_in = l.nb / 2;
+          if (tm.K > 0) terms.push_back(tm);
+        }
+        tk.t1 = (int)terms.size();
+        if (tk.M > 0) tasks.push_back(tk);
+      }
+    }
+    make_phase(F.down[nu - p.top], tasks, terms);
+  }
+}
+
+void ensure_fmm_capacity(ls_problem* P, FmmDev& F, int nrhs) {
+  if (F.nrhs_cap >= nrhs) return;
+  const ls::Plan& p = P->plan;
+  int cap = std::max(nrhs, 1);
+  F.lvl_off.assign(p.leaf + 1, 0);
+  F.lvl_size.assign(p.leaf + 1, 0);
+  long long tot = 0;
+  if (p.top <= p.leaf)
+    for (int nu = p.top; nu <= p.leaf; ++nu) {
+      long long nh = p.lv[nu].nb / 2;
+      F.lvl_off[nu] = tot;
+      F.lvl_size[nu] = (long long)p.lv[nu].ndir * F.kmax[nu] * 4 * nh * nh;
+      tot += F.lvl_size[nu];
+    }
+  F.ml_rhs = std::max(tot, 1LL);
+  F.mult.alloc((size_t)F.ml_rhs * cap * F.esz);
+  F.loc.alloc((size_t)F.ml_rhs * cap * F.esz);
+  F.xs.alloc((size_t)P->N * cap * F.esz);
+  F.ys.alloc((size_t)P->N * cap * F.esz);
+  F.nrhs_cap = cap;
+  build_phases(P, F);
+}
+
+void run_phase(ls_problem* P, FmmDev& F, Phase& ph, int nrhs, hipStream_t s, int prof_cls = -1) {
+  if (ph.nblocks == 0) return;
+  if (prof_cls >= 0) {
+    ProfScope ps(P, prof_cls, s);
+    lsk::launch_stencil(F.fp32, ph.tasks.as<lsk::DTask>(), ph.terms.as<lsk::DTerm>(), ph.blk.as<int>(), ph.nblocks,
+                        nrhs, s);
+  } else {
+    lsk::launch_stencil(F.fp32, ph.tasks.as<lsk::DTask>(), ph.terms.as<lsk::DTerm>(), ph.blk.as<int>(), ph.nblocks,
+                        nrhs, s);
+  }
+}
+
+// y = alpha x + coef diag(q) (V x) in Morton (mode 0) or caller (mode 1) order.
+void fmm_apply(ls_problem* P, bool fp32, const double2* x, long long ldx, double2* y, long long ldy, int nrhs,
+               double alpha, double coef, bool caller_order, hipStream_t s) {
+  FmmDev& F = fp32 ? P->f32 : P->f64;
+  if (fp32 && !P->have32) throw LsError(LS_ENOTSUP, "FP32 operator was not built (build_fp32 = 0)");
+  ensure_fmm_capacity(P, F, nrhs);
+  const long long N = P->N;
+  const int* gidx = caller_order ? P->s2c.as<int>() : P->s2m.as<int>();
+  const int* eidx = caller_order ? P->c2s.as<int>() : P->m2s.as<int>();
+  const double* q = caller_order ? P->q_c.as<double>() : P->q_m.as<double>();
+  lsk::launch_gather(fp32, x, ldx, F.xs.p, gidx, N, nrhs, s);
+  const ls::Plan& p = P->plan;
+  if (p.top <= p.leaf) {
+    run_phase(P, F, F.p2m, nrhs, s);
+    for (auto& ph : F.up) run_phase(P, F, ph, nrhs, s);
+  }
+  run_phase(P, F, F.nearm2l, nrhs, s, 0);
+  if (p.top <= p.leaf) {
+    for (auto& ph : F.down) run_phase(P, F, ph, nrhs, s);
+    run_phase(P, F, F.l2p, nrhs, s);
+  }
+  lsk::launch_epilogue(fp32, x, ldx, F.ys.p, eidx, q, alpha, coef, y, ldy, N, nrhs, s);
+  hip_check(hipGetLastError(), "fmm kernels");
+}
+
+// ---------------------------------------------------------------------------------------
+// HODLR
+// ---------------------------------------------------------------------------------------
+void hodlr_ensure_ws(ls_problem* P, int nrhs) {
+  HodlrDev& H = P->hod;
+  size_t needp = 0, needs = 0;
+  for (int l = 0; l < H.Lb; ++l) {
+    needp = std::max(needp, (size_t)H.nchunks[l] * H.r);
+    needs = std::max(needs, (size_t)(1LL << l) * 2 * H.r);
+  }
+  H.partial.ensure(std::max<size_t>(needp, 1) * nrhs * 16);
+  H.svec.ensure(std::max<size_t>(needs, 1) * nrhs * 16);
+}
+
+// z = (partial) HODLR inverse applied to b (Morton order): leaf solves, then levels
+// Lb-1 .. lstop.  b and z may be the same buffer.
+void hodlr_apply(ls_problem* P, bool fp32, const double2* b, long long ldb, double2* z, long long ldz, int nrhs,
+                 int lstop, hipStream_t s) {
+  HodlrDev& H = P->hod;
+  hodlr_ensure_ws(P, nrhs);
+  {
+    ProfScope ps(P, 2, s);
+    lsk::launch_leaf_apply(H.Dinv.as<double2>(), H.ident.as<unsigned char>(), b, ldb, z, ldz, H.lp, H.nleaves, nrhs,
+                           s);
+  }
+  for (int l = H.Lb - 1; l >= lstop; --l) {
+    const void* W = fp32 ? H.W32[l].p : H.W64[l].p;
+    const void* Y = fp32 ? H.Y32[l].p : H.Y64[l].p;
+    int nodes = 1 << l;
+    lsk::launch_hodlr_dot(fp32, W, z, ldz, H.partial.as<double2>(), H.N, H.r, H.chunk[l], H.nchunks[l], nrhs, s);
+    lsk::launch_hodlr_core(H.partial.as<double2>(), H.coreinv[l].as<double2>(), H.svec.as<double2>(), H.r, nodes,
+                           H.cpc[l], H.nchunks[l], true, nrhs, s);
+    ProfScope ps(P, 1, s);
+    lsk::launch_hodlr_update(fp32, Y, H.svec.as<double2>(), z, ldz, H.N, H.r, H.N >> l, nodes, nrhs, s);
+  }
+  hip_check(hipGetLastError(), "hodlr kernels");
+}
+
+void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mort_a, const std::vector<int>& mort_b,
+                 const std::vector<double>& qm) {
+  HodlrDev& H = P->hod;
+  const ls::Plan& p = P->plan;
+  const long long N = P->N;
+  const int r = P->opt.hodlr_rank;
+  H.r = r;
+  H.lp = p.leaf_side * p.leaf_side;
+  H.nleaves = (int)(N / H.lp);
+  H.Lb = 2 * p.leaf;
+  H.N = N;
+  const double coef = P->coef;
+  // leaf inverses (column-major per leaf)
+  const int lp = H.lp;
+  std::vector<zd> Vleaf((size_t)lp * lp);
+  for (int m = 0; m < lp; ++m)
+    for (int k = 0; k < lp; ++k) Vleaf[(size_t)m * lp + k] = W(mort_a[m] - mort_a[k], mort_b[m] - mort_b[k]);
+  std::vector<zd> Dinv((size_t)H.nleaves * lp * lp);
+  std::vector<unsigned char> ident(H.nleaves, 0);
+  parallel_for(H.nleaves, [&](int leafi) {
+    long long base = (long long)leafi * lp;
+    bool allzero = true;
+    for (int m = 0; m < lp; ++m)
+      if (qm[base + m] != 0.0) allzero = false;
+    zd* out = &Dinv[(size_t)leafi * lp * lp];
+    if (allzero) {
+      ident[leafi] = 1;
+      for (int k = 0; k < lp; ++k) out[(size_t)k * lp + k] = 1.0;
+      return;
+    }
+    std::vector<zd> A((size_t)lp * lp);
+    for (int m = 0; m < lp; ++m)
+      for (int k = 0; k < lp; ++k)
+        A[(size_t)m * lp + k] = (m == k ? zd(1.0) : zd(0.0)) + coef * qm[base + m] * Vleaf[(size_t)m * lp + k];
+    if (!ls::invert_inplace(A.data(), lp)) throw LsError(LS_EINVAL, "singular HODLR leaf block");
+    for (int m = 0; m < lp; ++m)
+      for (int k = 0; k < lp; ++k) out[(size_t)k * lp + m] = A[(size_t)m * lp + k];
+  });
+  H.Dinv.upload(Dinv);
+  H.ident.upload(ident);
+  H.bytes = (int64_t)Dinv.size() * 16;
+  Dinv.clear();
+  Dinv.shrink_to_fit();
+  // chunking of the binary levels
+  H.chunk.assign(H.Lb, 0);
+  H.nchunks.assign(H.Lb, 0);
+  H.cpc.assign(H.Lb, 0);
+  for (int l = 0; l < H.Lb; ++l) {
+    long long cs = N >> (l + 1);  // child size; chunks must tile it exactly
+    long long ch = cs;
+    while (ch > 8192 && ch % 2 == 0) ch /= 2;
+    H.chunk[l] = ch;
+    H.nchunks[l] = (int)(N / ch);
+    H.cpc[l] = (int)(cs / ch);
+  }
+  // off-diagonal ACA at fixed rank r (rows with q = 0 are known zero)
+  std::vector<std::vector<zd>> Uh(H.Lb), Wh(H.Lb);
+  for (int l = 0; l < H.Lb; ++l) {
+    Uh[l].assign((size_t)N * r, zd(0));
+    Wh[l].assign((size_t)N * r, zd(0));
+  }
+  std::vector<std::pair<int, int>> work;  // (level, node)
+  for (int l = 0; l < H.Lb; ++l)
+    for (int nd = 0; nd < (1 << l); ++nd) work.push_back({l, nd});
+  parallel_for((int)work.size() * 2, [&](int wi) {
+    int l = work[wi / 2].first, nd = work[wi / 2].second, which = wi % 2;
+    long long ns = N >> l, lo = (long long)nd * ns, mid = lo + ns / 2;
+    // which = 0: A[I1, I2] ~ P Q^T ; which = 1: A[I2, I1] ~ R S^T
+    long long r0 = which ? mid : lo, c0 = which ? lo : mid;
+    int m = (int)(ns / 2), n = (int)(ns / 2);
+    std::vector<char> rz(m);
+    for (int i = 0; i < m; ++i) rz[i] = qm[r0 + i] == 0.0;
+    auto rowfn = [&](int i, zd* out) {
+      long long gi = r0 + i;
+      double cq = coef * qm[gi];
+      int ai = mort_a[gi], bi = mort_b[gi];
+      for (int j = 0; j < n; ++j) out[j] = cq * W(ai - mort_a[c0 + j], bi - mort_b[c0 + j]);
+    };
+    auto colfn = [&](int j, zd* out) {
+      long long gj = c0 + j;
+      int aj = mort_a[gj], bj = mort_b[gj];
+      for (int i = 0; i < m; ++i) out[i] = coef * qm[r0 + i] * W(mort_a[r0 + i] - aj, mort_b[r0 + i] - bj);
+    };
+    ls::ACAResult R = ls::aca(m, n, r, 0.0, &rz, rowfn, colfn);
+    int k = (int)R.u.size();
+    for (int c = 0; c < k; ++c) {
+      for (int i = 0; i < m; ++i) Uh[l][(size_t)c * N + r0 + i] = R.u[c][i];
+      for (int j = 0; j < n; ++j) Wh[l][(size_t)c * N + c0 + j] = R.v[c][j];
+    }
+  });
+  // upload U (becomes Y in place) and W; compute Y_l = D_l^{-1} U_l and the SMW cores
+  H.Y64.resize(H.Lb);
+  H.W64.resize(H.Lb);
+  H.coreinv.resize(H.Lb);
+  for (int l = 0; l < H.Lb; ++l) {
+    H.Y64[l].upload(Uh[l]);
+    H.W64[l].upload(Wh[l]);
+    H.bytes += (int64_t)2 * N * r * 16;
+    Uh[l].clear();
+    Uh[l].shrink_to_fit();
+    Wh[l].clear();
+    Wh[l].shrink_to_fit();
+  }
+  hipStream_t s = nullptr;
+  hodlr_ensure_ws(P, r);
+  for (int l = H.Lb - 1; l >= 0; --l) {
+    double2* Y = H.Y64[l].as<double2>();
+    hodlr_apply(P, false, Y, N, Y, N, r, l + 1, s);
+    int nodes = 1 << l;
+    lsk::launch_hodlr_dot(false, H.W64[l].p, Y, N, H.partial.as<double2>(), N, r, H.chunk[l], H.nchunks[l], r, s);
+    lsk::launch_hodlr_core(H.partial.as<double2>(), nullptr, H.svec.as<double2>(), r, nodes, H.cpc[l], H.nchunks[l],
+                           false, r, s);
+    std::vector<zd> t((size_t)r * nodes * 2 * r);
+    hip_check(hipMemcpy(t.data(), H.svec.p, t.size() * 16, hipMemcpyDeviceToHost), "core download");
+    const int r2 = 2 * r;
+    std::vector<zd> cores((size_t)nodes * r2 * r2);
+    parallel_for(nodes, [&](int nd) {
+      zd* C = &cores[(size_t)nd * r2 * r2];
+      for (int i = 0; i < r2; ++i) C[(size_t)i * r2 + i] = 1.0;
+      for (int c = 0; c < r; ++c) {
+        const zd* tc = &t[((size_t)c * nodes + nd) * r2];
+        for (int i = 0; i < r; ++i) {
+          C[(size_t)i * r2 + (r + c)] += tc[i];       // Q^T Y2
+          C[(size_t)(r + i) * r2 + c] += tc[r + i];   // S^T Y1
+        }
+      }
+      if (!ls::invert_inplace(C, r2)) throw LsError(LS_EINVAL, "singular HODLR core");
+    });
+    H.coreinv[l].upload(cores);
+    H.bytes += (int64_t)cores.size() * 16;
+  }
+  hip_check(hipDeviceSynchronize(), "hodlr setup");
+  // FP32 copies of the off-diagonal factors
+  H.Y32.resize(H.Lb);
+  H.W32.resize(H.Lb);
+  for (int l = 0; l < H.Lb; ++l) {
+    H.Y32[l].alloc((size_t)N * r * 8);
+    H.W32[l].alloc((size_t)N * r * 8);
+    lsk::launch_cast(true, H.Y64[l].p, H.Y32[l].p, (long long)N * r, s);
+    lsk::launch_cast(true, H.W64[l].p, H.W32[l].p, (long long)N * r, s);
+    H.bytes += (int64_t)2 * N * r * 8;
+  }
+  hip_check(hipDeviceSynchronize(), "hodlr cast");
+}
+
+// ---------------------------------------------------------------------------------------
+// GMRES (Section 5): restarted, right-preconditioned, classical Gram-Schmidt with one
+// reorthogonalisation, Givens rotations on the host.  All vectors in Morton order.
+// ---------------------------------------------------------------------------------------
+struct GmresCfg {
+  bool op32 = false;     // FP32 operator
+  bool pc = false;       // use the HODLR preconditioner
+  bool pc32 = false;     // FP32 off-diagonal HODLR factors
+  int restart = 200;
+  int maxit = 2000;
+};
+
+struct ColState {
+  double fnorm = 0, tol = 0;
+  int its = 0, status = LS_MAXIT;
+  bool done = false;
+  double relres = 0;
+};
+
+void op_apply(ls_problem* P, bool op32, const double2* x, double2* y, int nrhs, hipStream_t s) {
+  fmm_apply(P, op32, x, P->N, y, P->N, nrhs, 1.0, P->coef, false, s);
+}
+
+// z (ld N) = M^{-1} x (ld ldx)
+void pc_apply(ls_problem* P, const GmresCfg& cfg, const double2* x, long long ldx, double2* z, int nrhs,
+              hipStream_t s) {
+  if (cfg.pc)
+    hodlr_apply(P, cfg.pc32, x, ldx, z, P->N, nrhs, 0, s);
+  else
+    lsk::launch_axpby(1.0, x, ldx, 0.0, x, ldx, z, P->N, P->N, nrhs, s);
+}
+
+int nchunks_for(long long N) { return (int)std::max<long long>(1, std::min<long long>(512, (N + 2047) / 2048)); }
+
+void norms(ls_problem* P, const double2* v, int nrhs, std::vector<double>& out, hipStream_t s) {
+  const long long N = P->N;
+  int nch = nchunks_for(N);
+  P->knp.ensure((size_t)nch * nrhs * 8);
+  P->kno.ensure((size_t)nrhs * 8);
+  lsk::launch_norm2(v, N, P->knp.as<double>(), N, nch, nrhs, s);
+  lsk::launch_norm2_finish(P->knp.as<double>(), nch, P->kno.as<double>(), nrhs, s);
+  out.resize(nrhs);
+  hip_check(hipMemcpyAsync(out.data(), P->kno.p, nrhs * 8, hipMemcpyDeviceToHost, s), "norm d2h");
+  hip_check(hipStreamSynchronize(s), "sync");
+  for (auto& x : out) x = std::sqrt(x);
+}
+
+// Solve op(A) x = f (Morton order, ld = N) from the x given; per-column tolerances.
+void gmres(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* x, int nrhs, std::vector<ColState>& st,
+           hipStream_t s) {
+  const long long N = P->N;
+  const int m = std::max(1, cfg.restart);
+  const int maxv = m + 1;
+  const int nch = nchunks_for(N);
+  P->kQ.ensure((size_t)nrhs * maxv * N * 16);
+  P->kw.ensure((size_t)nrhs * N * 16);
+  P->kz.ensure((size_t)nrhs * N * 16);
+  P->kr.ensure((size_t)nrhs * N * 16);
+  P->kh.ensure((size_t)nrhs * maxv * 16);
+  P->kpart.ensure((size_t)nrhs * nch * maxv * 16);
+  P->kalpha.ensure((size_t)nrhs * 8);
+  P->ky.ensure((size_t)nrhs * maxv * 16);
+  double2* Q = P->kQ.as<double2>();
+  double2* w = P->kw.as<double2>();
+  double2* z = P->kz.as<double2>();
+  double2* r = P->kr.as<double2>();
+  double2* hd = P->kh.as<double2>();
+  double2* part = P->kpart.as<double2>();
+  const long long ldqv = N, ldqr = (long long)maxv * N;
+  std::vector<std::vector<zd>> H(nrhs), g(nrhs), sn(nrhs);
+  std::vector<std::vector<double>> cs(nrhs);
+  std::vector<double> beta, alpha(nrhs), hnorm;
+  std::vector<zd> hh((size_t)nrhs * maxv);
+  std::vector<int> kcol(nrhs);
+  for (;;) {
+    // true residual r = f - A x
+    op_apply(P, cfg.op32, x, w, nrhs, s);
+    lsk::launch_axpby(1.0, f, N, -1.0, w, N, r, N, N, nrhs, s);
+    norms(P, r, nrhs, beta, s);
+    bool any = false;
+    for (int c = 0; c < nrhs; ++c) {
+      if (st[c].done) continue;
+      st[c].relres = beta[c] / st[c].fnorm;
+      if (!std::isfinite(beta[c])) {
+        st[c].done = true;
+        st[c].status = LS_NAN;
+      } else if (st[c].relres <= st[c].tol) {
+        st[c].done = true;
+        st[c].status = LS_CONVERGED;
+      } else if (st[c].its >= cfg.maxit) {
+        st[c].done = true;
+        st[c].status = LS_MAXIT;
+      } else {
+        any = true;
+      }
+    }
+    if (!any) return;
+    std::vector<char> active(nrhs, 0);
+    for (int c = 0; c < nrhs; ++c) {
+      active[c] = !st[c].done;
+      alpha[c] = active[c] ? 1.0 / beta[c] : 0.0;
+      H[c].assign((size_t)maxv * m, zd(0));
+      g[c].assign(maxv, zd(0));
+      g[c][0] = active[c] ? beta[c] : 0.0;
+      cs[c].assign(m, 0.0);
+      sn[c].assign(m, zd(0));
+      kcol[c] = 0;
+    }
+    hip_check(hipMemcpyAsync(P->kalpha.p, alpha.data(), nrhs * 8, hipMemcpyHostToDevice, s), "alpha");
+    lsk::launch_scale(r, N, P->kalpha.as<double>(), Q, ldqr, N, nrhs, s);
+    for (int j = 0; j < m; ++j) {
+      // w = A M^{-1} q_j
+      pc_apply(P, cfg, Q + (long long)j * ldqv, ldqr, z, nrhs, s);
+      op_apply(P, cfg.op32, z, w, nrhs, s);
+      // CGS2
+      {
+        ProfScope ps(P, 3, s);
+        lsk::launch_gs_dot(Q, ldqv, ldqr, j + 1, w, N, part, N, nch, maxv, nrhs, s);
+      }
+      lsk::launch_gs_finish(part, nch, j + 1, maxv, hd, 0, nrhs, s);
+      lsk::launch_gs_axpy(Q, ldqv, ldqr, j + 1, hd, maxv, -1.0, w, N, N, nrhs, s);
+      lsk::launch_gs_dot(Q, ldqv, ldqr, j + 1, w, N, part, N, nch, maxv, nrhs, s);
+      // second pass: store correction in the y buffer, then accumulate into hd
+      lsk::launch_gs_finish(part, nch, j + 1, maxv, P->ky.as<double2>(), 0, nrhs, s);
+      lsk::launch_gs_axpy(Q, ldqv, ldqr, j + 1, P->ky.as<double2>(), maxv, -1.0, w, N, N, nrhs, s);
+      lsk::launch_axpby(1.0, hd, maxv, 1.0, P->ky.as<double2>(), maxv, hd, maxv, j + 1, nrhs, s);
+      hip_check(hipMemcpyAsync(hh.data(), hd, (size_t)nrhs * maxv * 16, hipMemcpyDeviceToHost, s), "h d2h");
+      norms(P, w, nrhs, hnorm, s);
+      bool any_active = false;
+      for (int c = 0; c < nrhs; ++c) {
+        if (!active[c]) {
+          alpha[c] = 0.0;
+          continue;
+        }
+        zd* Hc = H[c].data();
+        for (int i = 0; i <= j; ++i) Hc[(size_t)i * m + j] = hh[(size_t)c * maxv + i];
+        Hc[(size_t)(j + 1) * m + j] = hnorm[c];
+        for (int i = 0; i < j; ++i) {
+          zd a = Hc[(size_t)i * m + j], b = Hc[(size_t)(i + 1) * m + j];
+          Hc[(size_t)i * m + j] = cs[c][i] * a + sn[c][i] * b;
+          Hc[(size_t)(i + 1) * m + j] = -std::conj(sn[c][i]) * a + cs[c][i] * b;
+        }
+        zd a = Hc[(size_t)j * m + j], b = Hc[(size_t)(j + 1) * m + j];
+        double cc;
+        zd ss;
+        if (b == zd(0)) {
+          cc = 1.0;
+          ss = 0.0;
+        } else if (a == zd(0)) {
+          cc = 0.0;
+          ss = std::conj(b) / std::abs(b);
+        } else {
+          double t = std::hypot(std::abs(a), std::abs(b));
+          cc = std::abs(a) / t;
+          ss = (a / std::abs(a)) * std::conj(b) / t;
+        }
+        cs[c][j] = cc;
+        sn[c][j] = ss;
+        Hc[(size_t)j * m + j] = cc * a + ss * b;
+        Hc[(size_t)(j + 1) * m + j] = 0.0;
+        g[c][j + 1] = -std::conj(ss) * g[c][j];
+        g[c][j] = cc * g[c][j];
+        st[c].its++;
+        kcol[c] = j + 1;
+        double est = std::abs(g[c][j + 1]) / st[c].fnorm;
+        bool stop = est <= st[c].tol || st[c].its >= cfg.maxit || hnorm[c] == 0.0 || !std::isfinite(est);
+        if (stop) {
+          active[c] = 0;
+          alpha[c] = 0.0;
+        } else {
+          alpha[c] = 1.0 / hnorm[c];
+          any_active = true;
+        }
+      }
+      if (!any_active || j + 1 == m) break;
+      hip_check(hipMemcpyAsync(P->kalpha.p, alpha.data(), nrhs * 8, hipMemcpyHostToDevice, s), "alpha");
+      lsk::launch_scale(w, N, P->kalpha.as<double>(), Q + (long long)(j + 1) * ldqv, ldqr, N, nrhs, s);
+    }
+    // y = R^{-1} g per column, x += M^{-1} (Q y)
+    std::vector<zd> y((size_t)nrhs * maxv, zd(0));
+    for (int c = 0; c < nrhs; ++c) {
+      int k = kcol[c];
+      const zd* Hc = H[c].data();
+      for (int i = k - 1; i >= 0; --i) {
+        zd acc = g[c][i];
+        for (int jj = i + 1; jj < k; ++jj) acc -= Hc[(size_t)i * m + jj] * y[(size_t)c * maxv + jj];
+        y[(size_t)c * maxv + i] = acc / Hc[(size_t)i * m + i];
+      }
+    }
+    hip_check(hipMemcpyAsync(P->ky.p, y.data(), y.size() * 16, hipMemcpyHostToDevice, s), "y h2d");
+    hip_check(hipMemsetAsync(w, 0, (size_t)nrhs * N * 16, s), "memset");
+    int kmaxc = 0;
+    for (int c = 0; c < nrhs; ++c) kmaxc = std::max(kmaxc, kcol[c]);
+    lsk::launch_gs_axpy(Q, ldqv, ldqr, kmaxc, P->ky.as<double2>(), maxv, 1.0, w, N, N, nrhs, s);
+    pc_apply(P, cfg, w, N, z, nrhs, s);
+    lsk::launch_axpby(1.0, x, N, 1.0, z, N, x, N, N, nrhs, s);
+    hip_check(hipStreamSynchronize(s), "gmres cycle");
+  }
+}
+
+// Exact integral of G = (i/4) H0(kappa |y|) over the square cell [-h/2, h/2]^2 (the diagonal
+// entry of Eq. (eq:13) at p = 1):  8 int_0^{pi/4} (i/4) [R H1(kappa R)/kappa + 2i/(pi kappa^2)] dtheta,
+// R = h / (2 cos theta), by 64-point Gauss-Legendre quadrature in theta.
+zd self_cell(double h, double kappa) {
+  const int nq = 64;
+  std::vector<double> xg(nq), wg(nq);
+  for (int i = 0; i < nq; ++i) {  // Gauss-Legendre nodes by Newton iteration on P_nq
+    double x = std::cos(lsk::kPi * (i + 0.75) / (nq + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1, p1 = x;
+      for (int k = 2; k <= nq; ++k) {
+        double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = nq * (x * p1 - p0) / (x * x - 1);
+      double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    double p0 = 1, p1 = x;
+    for (int k = 2; k <= nq; ++k) {
+      double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = nq * (x * p1 - p0) / (x * x - 1);
+    xg[i] = x;
+    wg[i] = 2.0 / ((1 - x * x) * dp * dp);
+  }
+  zd acc(0);
+  for (int i = 0; i < nq; ++i) {
+    double th = (xg[i] + 1.0) * (lsk::kPi / 8.0);
+    double R = 0.5 * h / std::cos(th);
+    lsk::cplx H1 = lsk::hankel1_small(kappa * R);
+    zd radial = R * zd(H1.re, H1.im) / kappa + zd(0, 2.0 / (lsk::kPi * kappa * kappa));
+    acc += wg[i] * (lsk::kPi / 8.0) * zd(0, 0.25) * radial;
+  }
+  return 8.0 * acc;
+}
+
+ls_status fail(const LsError& e) {
+  g_last_error = e.what();
+  return (ls_status)e.code;
+}
+
+}  // namespace
+
+// =========================================================================================
+// C ABI
+// =========================================================================================
+extern "C" {
+
+void ls_default_options(ls_options* o) {
+  if (!o) return;
+  o->leaf_max = 64;
+  o->T = 16.0;
+  o->sign = -1;
+  o->hodlr_rank = 15;
+  o->eps_inner = 1e-7;
+  o->restart = 200;
+  o->maxit = 2000;
+  o->prec = LS_FP64;
+  o->inner_tol = 1e-6;
+  o->max_refine = 10;
+  o->build_fp32 = 1;
+}
+
+const char* ls_last_error(void) { return g_last_error.c_str(); }
+
+static void validate_options(const ls_options& o) {
+  if (o.leaf_max < 1) throw LsError(LS_EINVAL, "leaf_max must be >= 1");
+  if (!(o.T > 0) || !std::isfinite(o.T)) throw LsError(LS_EINVAL, "T must be positive");
+  if (o.sign != -1 && o.sign != 1) throw LsError(LS_EINVAL, "sign must be -1 or +1");
+  if (o.hodlr_rank < 0 || o.hodlr_rank > 64) throw LsError(LS_EINVAL, "hodlr_rank must be in [0, 64]");
+  if (o.restart < 1) throw LsError(LS_EINVAL, "restart must be >= 1");
+  if (o.maxit < 0) throw LsError(LS_EINVAL, "maxit must be >= 0");
+  if (o.prec < 0 || o.prec > 2) throw LsError(LS_EINVAL, "prec must be LS_FP64, LS_FP32 or LS_MIXED");
+  if (!(o.inner_tol > 0) || o.inner_tol >= 1) throw LsError(LS_EINVAL, "inner_tol must be in (0, 1)");
+  if (o.max_refine < 1) throw LsError(LS_EINVAL, "max_refine must be >= 1");
+}
+
+ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt, ls_plan_info* out) {
+  try {
+    if (!out) throw LsError(LS_EINVAL, "out is NULL");
+    ls_options o;
+    ls_default_options(&o);
+    if (opt) o = *opt;
+    validate_options(o);
+    if (!(L > 0) || !std::isfinite(L)) throw LsError(LS_EINVAL, "L must be positive");
+    ls::PlanOptions po;
+    po.leaf_max = o.leaf_max;
+    po.T = o.T;
+    ls::Plan p = ls::make_plan(n, L, kappa, po);
+    if (p.leaf >= 32) throw LsError(LS_ENOTSUP, "too many levels");
+    std::memset(out, 0, sizeof(*out));
+    out->levels = p.leaf;
+    out->leaf_side = p.leaf_side;
+    out->top_level = p.top;
+    for (int nu = 0; nu <= p.leaf; ++nu) {
+      out->hf[nu] = p.lv[nu].hf;
+      out->ndir[nu] = p.lv[nu].ndir;
+      out->il_pairs[nu] = p.lv[nu].il_pairs;
+      out->max_il[nu] = p.lv[nu].max_il;
+    }
+    out->near_pairs = p.near_pairs;
+    ls::plan_coverage(p, out->coverage_min, out->coverage_max);
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LS_EINVAL;
+  }
+}
+
+ls_status ls_setup(const double* points, int64_t N, const double* q, double kappa, double tol, const ls_options* opt,
+                   ls_problem** out) {
+  if (out) *out = nullptr;
+  std::unique_ptr<ls_problem> P;
+  try {
+    double t0 = now_ms();
+    if (!out) throw LsError(LS_EINVAL, "out is NULL");
+    if (!points || !q) throw LsError(LS_EINVAL, "points and q must not be NULL");
+    if (N <= 0) throw LsError(LS_EINVAL, "N must be positive");
+    if (!(kappa > 0) || !std::isfinite(kappa)) throw LsError(LS_EINVAL, "kappa must be positive and finite");
+    if (!(tol > 0 && tol < 1)) throw LsError(LS_EINVAL, "tol must be in (0, 1)");
+    P.reset(new ls_problem());
+    ls_default_options(&P->opt);
+    if (opt) P->opt = *opt;
+    validate_options(P->opt);
+    for (int64_t i = 0; i < 2 * N; ++i)
+      if (!std::isfinite(points[i])) throw LsError(LS_EINVAL, "non-finite point coordinate");
+    for (int64_t i = 0; i < N; ++i)
+      if (!std::isfinite(q[i])) throw LsError(LS_EINVAL, "non-finite contrast value");
+    // ---- recognise the uniform cell-centred grid ----
+    int n = (int)std::llround(std::sqrt((double)N));
+    if ((int64_t)n * n != N) throw LsError(LS_ENOTSUP, "points do not form a square n x n grid (N not a square)");
+    double xmin = points[0], xmax = points[0], ymin = points[1], ymax = points[1];
+    for (int64_t i = 0; i < N; ++i) {
+      xmin = std::min(xmin, points[2 * i]);
+      xmax = std::max(xmax, points[2 * i]);
+      ymin = std::min(ymin, points[2 * i + 1]);
+      ymax = std::max(ymax, points[2 * i + 1]);
+    }
+    if (n < 2) throw LsError(LS_ENOTSUP, "grid side must be at least 2");
+    double h = (xmax - xmin) / (n - 1);
+    if (!(h > 0) || std::fabs((ymax - ymin) / (n - 1) - h) > 1e-9 * h)
+      throw LsError(LS_ENOTSUP, "points do not form a square grid with equal spacing");
+    std::vector<int> ca(N), cb(N), grid2caller((size_t)N, -1);
+    for (int64_t i = 0; i < N; ++i) {
+      double fa = (points[2 * i] - xmin) / h, fb = (points[2 * i + 1] - ymin) / h;
+      long a = std::lround(fa), b = std::lround(fb);
+      if (std::fabs(fa - a) > 1e-6 || std::fabs(fb - b) > 1e-6 || a < 0 || a >= n || b < 0 || b >= n)
+        throw LsError(LS_ENOTSUP, "points do not lie on a uniform grid");
+      int64_t g = (int64_t)a * n + b;
+      if (grid2caller[g] >= 0) throw LsError(LS_EINVAL, "duplicate points");
+      grid2caller[g] = (int)i;
+      ca[i] = (int)a;
+      cb[i] = (int)b;
+    }
+    P->N = N;
+    P->n = n;
+    P->kappa = kappa;
+    P->tol = tol;
+    P->coef = P->opt.sign * kappa * kappa;
+    const double L = 0.5 * n * h;
+    ls::PlanOptions po;
+    po.leaf_max = P->opt.leaf_max;
+    po.T = P->opt.T;
+    P->plan = ls::make_plan(n, L, kappa, po);
+    const ls::Plan& p = P->plan;
+    double t_plan = now_ms();
+    // ---- orders: Morton (solver) and S (DAFMM leaf arrays) ----
+    const int side = p.leaf_side, nbL = p.lv[p.leaf].nb, nhL = nbL / 2;
+    std::vector<int> mort_a(N), mort_b(N), m2c(N), c2m(N);
+    {
+      std::vector<std::pair<uint64_t, int>> leaves;
+      for (int la = 0; la < nbL; ++la)
+        for (int lb = 0; lb < nbL; ++lb) {
+          uint64_t code = 0;
+          for (int bit = 0; bit < 16; ++bit) {
+            code |= (uint64_t)((lb >> bit) & 1) << (2 * bit);
+            code |= (uint64_t)((la >> bit) & 1) << (2 * bit + 1);
+          }
+          leaves.push_back({code, la * nbL + lb});
+        }
+      std::sort(leaves.begin(), leaves.end());
+      int64_t t = 0;
+      for (auto& lf : leaves) {
+        int la = lf.second / nbL, lb = lf.second % nbL;
+        for (int a = 0; a < side; ++a)
+          for (int b = 0; b < side; ++b) {
+            int ga = la * side + a, gb = lb * side + b;
+            mort_a[t] = ga;
+            mort_b[t] = gb;
+            m2c[t] = grid2caller[(int64_t)ga * n + gb];
+            c2m[m2c[t]] = (int)t;
+            ++t;
+          }
+      }
+    }
+    std::vector<int> s2c(N), c2s(N), s2m(N), m2s(N);
+    {
+      const long long plane = (long long)nhL * nhL;
+      for (int ba = 0; ba < nbL; ++ba)
+        for (int bb = 0; bb < nbL; ++bb) {
+          int c = (ba & 1) * 2 + (bb & 1);
+          int ha = ba >> 1, hb = bb >> 1;
+          for (int pa = 0; pa < side; ++pa)
+            for (int pb = 0; pb < side; ++pb) {
+              long long sidx = (long long)(pa * side + pb) * 4 * plane + c * plane + (long long)ha * nhL + hb;
+              int ga = ba * side + pa, gb = bb * side + pb;
+              int ci = grid2caller[(int64_t)ga * n + gb];
+              s2c[sidx] = ci;
+              c2s[ci] = (int)sidx;
+              s2m[sidx] = c2m[ci];
+              m2s[c2m[ci]] = (int)sidx;
+            }
+        }
+    }
+    P->s2c.upload(s2c);
+    P->c2s.upload(c2s);
+    P->s2m.upload(s2m);
+    P->m2s.upload(m2s);
+    P->m2c.upload(m2c);
+    std::vector<double> qc(q, q + N), qm(N), pxv(N), pyv(N);
+    for (int64_t t = 0; t < N; ++t) qm[t] = q[m2c[t]];
+    for (int64_t i = 0; i < N; ++i) {
+      pxv[i] = points[2 * i];
+      pyv[i] = points[2 * i + 1];
+    }
+    P->q_c.upload(qc);
+    P->q_m.upload(qm);
+    P->px.upload(pxv);
+    P->py.upload(pyv);
+    // ---- W table on the device (H0 evaluator), self-cell term on the host ----
+    ls::WTable W;
+    W.n = n;
+    {
+      DevBuf wt;
+      size_t cnt = (size_t)(2 * n - 1) * (2 * n - 1);
+      wt.alloc(cnt * 16);
+      lsk::launch_wtable(wt.as<double2>(), n, h, kappa, nullptr);
+      hip_check(hipGetLastError(), "wtable");
+      W.w.resize(cnt);
+      hip_check(hipMemcpy(W.w.data(), wt.p, cnt * 16, hipMemcpyDeviceToHost), "wtable d2h");
+      W.w[(size_t)(n - 1) * (2 * n - 1) + (n - 1)] = self_cell(h, kappa);
+    }
+    // ---- NCA factors and device operators ----
+    double t_w = now_ms();
+    P->nca64 = ls::build_nca(p, W, tol);
+    build_fmm_ops(P.get(), P->nca64, P->f64, false);
+    if (P->opt.build_fp32) {
+      if (P->opt.eps_inner > 0 && P->opt.eps_inner > tol)
+        P->nca32 = ls::build_nca(p, W, P->opt.eps_inner);
+      else
+        P->nca32 = P->nca64;
+      build_fmm_ops(P.get(), P->nca32, P->f32, true);
+      P->have32 = true;
+    }
+    ensure_fmm_capacity(P.get(), P->f64, 1);
+    if (P->have32) ensure_fmm_capacity(P.get(), P->f32, 1);
+    double t_nca = now_ms();
+    // ---- HODLR preconditioner ----
+    if (P->opt.hodlr_rank > 0) {
+      build_hodlr(P.get(), W, mort_a, mort_b, qm);
+      P->have_hodlr = true;
+    }
+    double t_h = now_ms();
+    hip_check(hipDeviceSynchronize(), "setup");
+    // ---- stats ----
+    ls_stats_t& S = P->stats;
+    std::memset(&S, 0, sizeof(S));
+    S.N = N;
+    S.n = n;
+    S.levels = p.leaf;
+    S.leaf_side = side;
+    S.top_level = p.top;
+    for (int nu = p.top; nu <= p.leaf; ++nu)
+      if (p.lv[nu].hf) S.nlevels_hf++;
+    for (int nu = p.top; nu <= p.leaf; ++nu) {
+      S.rank_max64 = std::max(S.rank_max64, P->f64.kmax.empty() ? 0 : P->f64.kmax[nu]);
+      if (P->have32) S.rank_max32 = std::max(S.rank_max32, P->f32.kmax[nu]);
+      S.m2l_pairs += p.lv[nu].il_pairs;
+    }
+    S.entries_near = p.near_pairs * (int64_t)side * side * side * side;
+    S.entries_far64 = P->f64.entries_far;
+    S.entries_far32 = P->have32 ? P->f32.entries_far : 0;
+    S.stored_bytes64 = P->f64.stored_bytes;
+    S.stored_bytes32 = P->have32 ? P->f32.stored_bytes : 0;
+    S.hodlr_bytes = P->hod.bytes;
+    S.t_plan_ms = t_plan - t0;
+    S.t_nca_ms = t_nca - t_w;
+    S.t_hodlr_ms = t_h - t_nca;
+    S.t_setup_ms = now_ms() - t0;
+    *out = P.release();
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LS_EINVAL;
+  }
+}
+
+static void check_vec_args(ls_problem* P, const void* x, const void* y, int nrhs, int64_t ld) {
+  if (!P) throw LsError(LS_EINVAL, "problem is NULL");
+  if (!x || !y) throw LsError(LS_EINVAL, "vector pointer is NULL");
+  if (nrhs <= 0) throw LsError(LS_EINVAL, "nrhs must be positive");
+  if (ld < P->N) throw LsError(LS_EINVAL, "ld must be >= N");
+}
+
+ls_status ls_matvec(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld, int prec, void* stream) {
+  try {
+    check_vec_args(P, x, y, nrhs, ld);
+    if (prec != LS_FP64 && prec != LS_FP32) throw LsError(LS_EINVAL, "prec must be LS_FP64 or LS_FP32");
+    if (x == y) throw LsError(LS_EINVAL, "x and y must not overlap");
+    fmm_apply(P, prec == LS_FP32, (const double2*)x, ld, (double2*)y, ld, nrhs, 1.0, P->coef, true,
+              (hipStream_t)stream);
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
+}
+
+ls_status ls_apply_V(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld, int prec, void* stream) {
+  try {
+    check_vec_args(P, x, y, nrhs, ld);
+    if (prec != LS_FP64 && prec != LS_FP32) throw LsError(LS_EINVAL, "prec must be LS_FP64 or LS_FP32");
+    if (x == y) throw LsError(LS_EINVAL, "x and y must not overlap");
+    hipStream_t s = (hipStream_t)stream;
+    // y = V x : epilogue with alpha = 0, coef = 1 and no contrast
+    FmmDev& F = prec == LS_FP32 ? P->f32 : P->f64;
+    if (prec == LS_FP32 && !P->have32) throw LsError(LS_ENOTSUP, "FP32 operator was not built");
+    ensure_fmm_capacity(P, F, nrhs);
+    const long long N = P->N;
+    lsk::launch_gather(F.fp32, (const double2*)x, ld, F.xs.p, P->s2c.as<int>(), N, nrhs, s);
+    const ls::Plan& p = P->plan;
+    if (p.top <= p.leaf) {
+      run_phase(P, F, F.p2m, nrhs, s);
+      for (auto& ph : F.up) run_phase(P, F, ph, nrhs, s);
+    }
+    run_phase(P, F, F.nearm2l, nrhs, s);
+    if (p.top <= p.leaf) {
+      for (auto& ph : F.down) run_phase(P, F, ph, nrhs, s);
+      run_phase(P, F, F.l2p, nrhs, s);
+    }
+    lsk::launch_epilogue(F.fp32, (const double2*)x, ld, F.ys.p, P->c2s.as<int>(), nullptr, 0.0, 1.0, (double2*)y, ld,
+                         N, nrhs, s);
+    hip_check(hipGetLastError(), "apply_V");
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
+}
+
+static void ensure_ws(ls_problem* P, int nrhs) {
+  if (P->ws_cap >= nrhs) return;
+  P->w_x.alloc((size_t)P->N * nrhs * 16);
+  P->w_y.alloc((size_t)P->N * nrhs * 16);
+  P->w_t.alloc((size_t)P->N * nrhs * 16);
+  P->ws_cap = nrhs;
+}
+
+ls_status ls_precond_apply(ls_problem* P, const void* r, void* z, int nrhs, int64_t ld, int prec, void* stream) {
+  try {
+    check_vec_args(P, r, z, nrhs, ld);
+    if (prec != LS_FP64 && prec != LS_FP32) throw LsError(LS_EINVAL, "prec must be LS_FP64 or LS_FP32");
+    if (!P->have_hodlr) throw LsError(LS_ENOTSUP, "no HODLR preconditioner (hodlr_rank = 0)");
+    hipStream_t s = (hipStream_t)stream;
+    ensure_ws(P, nrhs);
+    const long long N = P->N;
+    double2* a = P->w_x.as<double2>();
+    lsk::launch_permute((const double2*)r, ld, a, N, P->m2c.as<int>(), N, nrhs, false, s);
+    hodlr_apply(P, prec == LS_FP32, a, N, a, N, nrhs, 0, s);
+    lsk::launch_permute(a, N, (double2*)z, ld, P->m2c.as<int>(), N, nrhs, true, s);
+    hip_check(hipGetLastError(), "precond");
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
+}
+
+ls_status ls_rhs_planewave(ls_problem* P, const double* angles, int nrhs, void* f, int64_t ld, void* stream) {
+  try {
+    if (!P || !angles || !f) throw LsError(LS_EINVAL, "NULL argument");
+    if (nrhs <= 0) throw LsError(LS_EINVAL, "nrhs must be positive");
+    if (ld < P->N) throw LsError(LS_EINVAL, "ld must be >= N");
+    for (int i = 0; i < nrhs; ++i)
+      if (!std::isfinite(angles[i])) throw LsError(LS_EINVAL, "non-finite angle");
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf ang;
+    ang.upload(std::vector<double>(angles, angles + nrhs));
+    lsk::launch_planewave(P->px.as<double>(), P->py.as<double>(), P->q_c.as<double>(), ang.as<double>(), P->kappa,
+                          -P->coef, (double2*)f, ld, P->N, nrhs, s);
+    hip_check(hipStreamSynchronize(s), "planewave");
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
+}
+
+ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld, double tol, int x0_given,
+                   ls_solve_info* info, void* stream) {
+  try {
+    double t0 = now_ms();
+    check_vec_args(P, f, psi, nrhs, ld);
+    if (!(tol > 0 && tol < 1)) throw LsError(LS_EINVAL, "tol must be in (0, 1)");
+    hipStream_t s = (hipStream_t)stream;
+    const long long N = P->N;
+    const int prec = P->opt.prec;
+    if ((prec == LS_FP32 || prec == LS_MIXED) && !P->have32) throw LsError(LS_ENOTSUP, "FP32 operator not built");
+    P->kf.ensure((size_t)N * nrhs * 16);
+    P->kx.ensure((size_t)N * nrhs * 16);
+    P->kdx.ensure((size_t)N * nrhs * 16);
+    double2* fm = P->kf.as<double2>();
+    double2* xm = P->kx.as<double2>();
+    double2* dm = P->kdx.as<double2>();
+    lsk::launch_permute((const double2*)f, ld, fm, N, P->m2c.as<int>(), N, nrhs, false, s);
+    std::vector<double> fn;
+    norms(P, fm, nrhs, fn, s);
+    std::vector<ColState> st(nrhs);
+    std::vector<int> warm_rejected(nrhs, 0);
+    for (int c = 0; c < nrhs; ++c) {
+      st[c].fnorm = fn[c] > 0 ? fn[c] : 1.0;
+      st[c].tol = tol;
+    }
+    if (x0_given) {
+      lsk::launch_permute((const double2*)psi, ld, xm, N, P->m2c.as<int>(), N, nrhs, false, s);
+      // reject a guess whose residual is not below ||f||
+      ensure_ws(P, nrhs);
+      double2* w = P->w_y.as<double2>();
+      op_apply(P, false, xm, w, nrhs, s);
+      lsk::launch_axpby(1.0, fm, N, -1.0, w, N, w, N, N, nrhs, s);
+      std::vector<double> rn;
+      norms(P, w, nrhs, rn, s);
+      std::vector<double> keep(nrhs);
+      bool any_rej = false;
+      for (int c = 0; c < nrhs; ++c) {
+        bool bad = !(rn[c] < fn[c]) || !std::isfinite(rn[c]);
+        warm_rejected[c] = bad;
+        any_rej |= bad;
+      }
+      if (any_rej)
+        for (int c = 0; c < nrhs; ++c)
+          if (warm_rejected[c]) hip_check(hipMemsetAsync(xm + (long long)c * N, 0, N * 16, s), "memset");
+    } else {
+      hip_check(hipMemsetAsync(xm, 0, (size_t)N * nrhs * 16, s), "memset");
+    }
+    for (int c = 0; c < nrhs; ++c)
+      if (fn[c] == 0) {
+        st[c].done = true;
+        st[c].status = LS_CONVERGED;
+        hip_check(hipMemsetAsync(xm + (long long)c * N, 0, N * 16, s), "memset");
+      }
+    GmresCfg cfg;
+    cfg.restart = P->opt.restart;
+    cfg.maxit = P->opt.maxit;
+    cfg.pc = P->have_hodlr;
+    std::vector<int> nref(nrhs, 0);
+    if (prec == LS_FP64 || prec == LS_FP32) {
+      cfg.op32 = prec == LS_FP32;
+      cfg.pc32 = prec == LS_FP32;
+      gmres(P, cfg, fm, xm, nrhs, st, s);
+    } else {
+      // mixed: outer FP64 residual and refinement, inner FP32-operator GMRES
+      cfg.op32 = true;
+      cfg.pc32 = true;
+      ensure_ws(P, nrhs);
+      double2* rr = P->w_t.as<double2>();
+      double2* w = P->w_y.as<double2>();
+      std::vector<double> prev(nrhs, 1e300);
+      std::vector<int> total_its(nrhs, 0);
+      for (int outer = 0;; ++outer) {
+        op_apply(P, false, xm, w, nrhs, s);
+        lsk::launch_axpby(1.0, fm, N, -1.0, w, N, rr, N, N, nrhs, s);
+        std::vector<double> rn;
+        norms(P, rr, nrhs, rn, s);
+        std::vector<ColState> inner(nrhs);
+        bool any = false;
+        for (int c = 0; c < nrhs; ++c) {
+          if (st[c].done && outer == 0) {
+            inner[c].done = true;
+            continue;
+          }
+          double rel = rn[c] / st[c].fnorm;
+          st[c].relres = rel;
+          if (!std::isfinite(rel)) {
+            st[c].done = true;
+            st[c].status = LS_NAN;
+          } else if (rel <= tol) {
+            st[c].done = true;
+            st[c].status = LS_CONVERGED;
+          } else if (outer >= P->opt.max_refine || total_its[c] >= cfg.maxit) {
+            st[c].done = true;
+            st[c].status = LS_MAXIT;
+          } else if (outer > 0 && rn[c] > 0.9 * prev[c]) {
+            st[c].done = true;
+            st[c].status = LS_REFINE_STAGNATED;
+          }
+          prev[c] = rn[c];
+          inner[c].done = st[c].done;
+          if (!st[c].done) {
+            any = true;
+            inner[c].fnorm = rn[c];
+            inner[c].tol = std::max(P->opt.inner_tol, 0.5 * tol * st[c].fnorm / rn[c]);
+            inner[c].tol = std::min(inner[c].tol, 0.5);
+            nref[c] = outer + 1;
+          }
+        }
+        if (!any) break;
+        hip_check(hipMemsetAsync(dm, 0, (size_t)N * nrhs * 16, s), "memset");
+        GmresCfg ic = cfg;
+        ic.maxit = cfg.maxit;
+        for (int c = 0; c < nrhs; ++c) inner[c].its = 0;
+        gmres(P, ic, rr, dm, nrhs, inner, s);
+        for (int c = 0; c < nrhs; ++c) {
+          if (!st[c].done) {
+            st[c].its += inner[c].its;
+            total_its[c] += inner[c].its;
+          }
+        }
+        // x += d only for columns still iterating (others have d = 0 anyway)
+        lsk::launch_axpby(1.0, xm, N, 1.0, dm, N, xm, N, N, nrhs, s);
+      }
+      // stagnated columns: finish with the FP64 operator
+      bool fallback = false;
+      for (int c = 0; c < nrhs; ++c)
+        if (st[c].status == LS_REFINE_STAGNATED) fallback = true;
+      if (fallback) {
+        std::vector<ColState> f64st = st;
+        for (int c = 0; c < nrhs; ++c) {
+          f64st[c].done = st[c].status != LS_REFINE_STAGNATED;
+          f64st[c].its = st[c].its;
+        }
+        GmresCfg c64 = cfg;
+        c64.op32 = false;
+        c64.pc32 = false;
+        gmres(P, c64, fm, xm, nrhs, f64st, s);
+        for (int c = 0; c < nrhs; ++c)
+          if (st[c].status == LS_REFINE_STAGNATED) {
+            st[c].its = f64st[c].its;
+            st[c].status = f64st[c].status == LS_CONVERGED ? LS_REFINE_STAGNATED : f64st[c].status;
+          }
+      }
+    }
+    // final true residual with the FP64 operator
+    ensure_ws(P, nrhs);
+    double2* w = P->w_y.as<double2>();
+    op_apply(P, false, xm, w, nrhs, s);
+    lsk::launch_axpby(1.0, fm, N, -1.0, w, N, w, N, N, nrhs, s);
+    std::vector<double> rn;
+    norms(P, w, nrhs, rn, s);
+    lsk::launch_permute(xm, N, (double2*)psi, ld, P->m2c.as<int>(), N, nrhs, true, s);
+    hip_check(hipStreamSynchronize(s), "solve");
+    double t1 = now_ms();
+    if (info)
+      for (int c = 0; c < nrhs; ++c) {
+        info[c].iters = st[c].its;
+        info[c].relres = fn[c] > 0 ? rn[c] / fn[c] : 0.0;
+        info[c].status = st[c].status;
+        if (warm_rejected[c] && st[c].status == LS_CONVERGED) info[c].status = LS_WARMSTART_REJECTED;
+        info[c].n_refine = nref[c];
+        info[c].t_solve_ms = t1 - t0;
+      }
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
+}
+
+ls_status ls_green_table(int n, double h, double kappa, void* out, void* stream) {
+  try {
+    if (n < 1 || !(h > 0) || !std::isfinite(h)) throw LsError(LS_EINVAL, "n must be >= 1 and h > 0");
+    if (!(kappa > 0) || !std::isfinite(kappa)) throw LsError(LS_EINVAL, "kappa must be positive and finite");
+    if (!out) throw LsError(LS_EINVAL, "out is NULL");
+    if (kappa * h * 0.7072 >= 4.0) throw LsError(LS_ENOTSUP, "kappa * h too large for the self-cell series");
+    hipStream_t s = (hipStream_t)stream;
+    lsk::launch_wtable((double2*)out, n, h, kappa, s);
+    hip_check(hipGetLastError(), "wtable");
+    zd w0 = self_cell(h, kappa);
+    double2 v = make_double2(w0.real(), w0.imag());
+    hip_check(hipMemcpyAsync((double2*)out + (size_t)(n - 1) * (2 * n - 1) + (n - 1), &v, 16, hipMemcpyHostToDevice, s),
+              "w0");
+    hip_check(hipStreamSynchronize(s), "sync");
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
+}
+
+ls_status ls_stats(const ls_problem* P, ls_stats_t* out) {
+  if (!P || !out) {
+    g_last_error = "NULL argument";
+    return LS_EINVAL;
+  }
+  *out = P->stats;
+  return LS_OK;
+}
+
+void ls_destroy(ls_problem* P) {
+  if (!P) return;
+  for (auto& pc : P->prof)
+    for (auto& e : pc.ev) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  delete P;
+}
+
+ls_status ls_profile_enable(ls_problem* P, int cls, int enable) {
+  if (!P || cls < 0 || cls > 3) {
+    g_last_error = "bad arguments";
+    return LS_EINVAL;
+  }
+  P->prof[cls].enabled = enable != 0;
+  if (enable) P->prof[cls].used = 0;
+  return LS_OK;
+}
+
+ls_status ls_profile_read(ls_problem* P, int cls, double* total_ms, int64_t* launches) {
+  try {
+    if (!P || cls < 0 || cls > 3 || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
+    ProfileClass& pc = P->prof[cls];
+    double tot = 0;
+    for (size_t i = 0; i < pc.used; ++i) {
+      hip_check(hipEventSynchronize(pc.ev[i].second), "event sync");
+      float ms = 0;
+      hip_check(hipEventElapsedTime(&ms, pc.ev[i].first, pc.ev[i].second), "elapsed");
+      tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)pc.used;
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Launch wrappers for the device kernels (implemented in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lsk {
+
+// ---- stencil GEMM: out[m][box] (+)= sum_terms sum_k op[k][m] * in[k][src(box, term)] ----
+enum TermMode { MODE_SAME = 0, MODE_SHIFT = 1, MODE_CHILD = 2, MODE_PARENT = 3 };
+
+struct DTerm {
+  const void* op;   // complex [K][Mpad] (row = inner index k)
+  const void* in;   // input base of (level, direction) for rhs 0
+  long long in_rhs; // rhs stride of the input, complex elements
+  int K;            // inner dimension
+  int mode;         // TermMode
+  int cin;          // SHIFT: source class; CHILD: child class
+  int sha, shb;     // SHIFT: shift in the class half-grid
+  int nh_in;        // half-grid side of the input level
+  int pad;
+};
+
+struct DTask {
+  void* out;         // output base of (level, direction) for rhs 0
+  long long out_rhs; // rhs stride of the output
+  int M, Mpad;       // output rows (exact / padded to the row block)
+  int nh;            // half-grid side of the output level
+  int cout;          // output class
+  int t0, t1;        // term range
+  int beta;          // 0: overwrite, 1: accumulate
+  int nrb;           // row blocks = Mpad / kRowBlock
+  int blk0;          // first workgroup of this task
+  int pad;
+};
+
+constexpr int kRowBlock = 8;
+constexpr int kBoxBlock = 64;
+
+void launch_stencil(bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks, int nrhs,
+                    hipStream_t s);
+
+// ---- setup ----
+void launch_wtable(double2* W, int n, double h, double kappa, hipStream_t s);
+
+// ---- permutations / epilogue ----
+// xs[rhs*N + t] = (T) x[rhs*ldx + idx[t]]
+void launch_gather(bool to_fp32, const double2* x, long long ldx, void* xs, const int* idx, long long N, int nrhs,
+                   hipStream_t s);
+// y[rhs*ldy + i] = alpha * x[rhs*ldx + i] + coef * q[i] * ys[rhs*N + idx[i]]
+void launch_epilogue(bool from_fp32, const double2* x, long long ldx, const void* ys, const int* idx, const double* q,
+                     double alpha, double coef, double2* y, long long ldy, long long N, int nrhs, hipStream_t s);
+// y[rhs*ldy + perm[i]] = x[rhs*ldx + i]    (scatter) / y[rhs*ldy + i] = x[rhs*ldx + perm[i]] (gather)
+void launch_permute(const double2* x, long long ldx, double2* y, long long ldy, const int* perm, long long N, int nrhs,
+                    bool scatter, hipStream_t s);
+void launch_planewave(const double* px, const double* py, const double* q, const double* angles, double kappa,
+                      double coef, double2* f, long long ldf, long long N, int nrhs, hipStream_t s);
+
+// ---- HODLR ----
+void launch_leaf_apply(const double2* Dinv, const unsigned char* ident, const double2* b, long long ldb, double2* z,
+                       long long ldz, int lp, int nleaves, int nrhs, hipStream_t s);
+void launch_hodlr_dot(bool fp32, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
+                      long long chunk, int nchunks, int nrhs, hipStream_t s);
+void launch_hodlr_core(const double2* partial, const double2* coreinv, double2* sout, int r, int nodes,
+                       int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s);
+void launch_hodlr_update(bool fp32, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
+                         long long nodesize, int nodes, int nrhs, hipStream_t s);
+
+// ---- Krylov vector kernels (complex128) ----
+void launch_gs_dot(const double2* Q, long long ldq_vec, long long ldq_rhs, int nv, const double2* w, long long ldw,
+                   double2* partial, long long N, int nchunks, int maxv, int nrhs, hipStream_t s);
+void launch_gs_finish(const double2* partial, int nchunks, int nv, int maxv, double2* h, int accumulate, int nrhs,
+                      hipStream_t s);
+void launch_gs_axpy(const double2* Q, long long ldq_vec, long long ldq_rhs, int nv, const double2* h, int maxv,
+                    double sign, double2* w, long long ldw, long long N, int nrhs, hipStream_t s);
+void launch_norm2(const double2* w, long long ldw, double* partial, long long N, int nchunks, int nrhs, hipStream_t s);
+void launch_norm2_finish(const double* partial, int nchunks, double* out, int nrhs, hipStream_t s);
+void launch_scale(const double2* w, long long ldw, const double* alpha, double2* out, long long ldo, long long N,
+                  int nrhs, hipStream_t s);
+void launch_axpby(double a, const double2* x, long long ldx, double b, const double2* y, long long ldy, double2* out,
+                  long long ldo, long long N, int nrhs, hipStream_t s);
+void launch_cast(bool to_fp32, const void* in, void* out, long long n, hipStream_t s);
+
+}  // namespace lsk

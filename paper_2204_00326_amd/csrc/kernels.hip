@@ -1,0 +1,609 @@
+// Device kernels for gfx950 (CDNA4, wave64).
+#include <hip/hip_runtime.h>
+
+#include "h0.h"
+#include "kernels.h"
+
+namespace lsk {
+
+template <typename T>
+struct V2;
+template <>
+struct V2<double> {
+  using type = double2;
+};
+template <>
+struct V2<float> {
+  using type = float2;
+};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-wide sum of (re, im) for a block of `nt` threads (multiple of 64, <= 1024).
+// `red` is a __shared__ buffer of 2 * 16 doubles.  Result valid in all threads.
+__device__ inline double2 block_sum2(double re, double im, double* red) {
+  re = wave_sum(re);
+  im = wave_sum(im);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    red[2 * wid] = re;
+    red[2 * wid + 1] = im;
+  }
+  __syncthreads();
+  double a = 0, b = 0;
+  for (int w = 0; w < nw; ++w) {
+    a += red[2 * w];
+    b += red[2 * w + 1];
+  }
+  return make_double2(a, b);
+}
+
+// =====================================================================================
+// Stencil GEMM over boxes with operators shared by all boxes of a level (DAFMM passes).
+// One thread = one box of the task's class; it accumulates kRowBlock output rows.
+// Operator entries are uniform across the wave (scalar loads); inputs are coalesced
+// along the box index of the class half-grid.
+// =====================================================================================
+template <typename T>
+__global__ __launch_bounds__(kBoxBlock) void k_stencil(const DTask* __restrict__ tasks,
+                                                       const DTerm* __restrict__ terms,
+                                                       const int* __restrict__ blk_task) {
+  using C2 = typename V2<T>::type;
+  const int blk = blockIdx.x;
+  const int rhs = blockIdx.y;
+  const int ti = __builtin_amdgcn_readfirstlane(blk_task[blk]);
+  const DTask& tk = tasks[ti];
+  const int local = blk - tk.blk0;
+  const int rb = local % tk.nrb;
+  const int bb = local / tk.nrb;
+  const int nh = tk.nh;
+  const int box = bb * kBoxBlock + (int)threadIdx.x;
+  const bool active = box < nh * nh;
+  const int ha = active ? box / nh : 0;
+  const int hb = active ? box - ha * nh : 0;
+  const int m0 = rb * kRowBlock;
+  const int Mpad = tk.Mpad;
+  T ar[kRowBlock], ai[kRowBlock];
+#pragma unroll
+  for (int r = 0; r < kRowBlock; ++r) {
+    ar[r] = 0;
+    ai[r] = 0;
+  }
+  for (int t = tk.t0; t < tk.t1; ++t) {
+    const DTerm& tm = terms[t];
+    const int nhi = tm.nh_in;
+    const long long plane = (long long)nhi * nhi;
+    long long src = 0;
+    bool ok = active;
+    switch (tm.mode) {
+      case MODE_SAME:
+        src = (long long)tk.cout * plane + box;
+        break;
+      case MODE_SHIFT: {
+        const int sa = ha + tm.sha, sb = hb + tm.shb;
+        ok = ok && sa >= 0 && sa < nhi && sb >= 0 && sb < nhi;
+        src = (long long)tm.cin * plane + (long long)sa * nhi + sb;
+      } break;
+      case MODE_CHILD: {
+        const int pa = 2 * ha + (tk.cout >> 1), pb = 2 * hb + (tk.cout & 1);
+        src = (long long)tm.cin * plane + (long long)pa * nhi + pb;
+      } break;
+      default: {  // MODE_PARENT: the parent of (class cout, ha, hb) has full coords (ha, hb)
+        const int pc = ((ha & 1) << 1) | (hb & 1);
+        src = (long long)pc * plane + (long long)(ha >> 1) * nhi + (hb >> 1);
+      } break;
+    }
+    if (ok) {
+      const C2* __restrict__ in = reinterpret_cast<const C2*>(tm.in) + rhs * tm.in_rhs + src;
+      const C2* __restrict__ op = reinterpret_cast<const C2*>(tm.op) + m0;
+      const long long ks = 4 * plane;
+      const int K = tm.K;
+      int k = 0;
+      for (; k + 2 <= K; k += 2) {
+        const C2 x0 = in[(long long)k * ks];
+        const C2 x1 = in[(long long)(k + 1) * ks];
+        const C2* o0 = op + (long long)k * Mpad;
+        const C2* o1 = o0 + Mpad;
+#pragma unroll
+        for (int r = 0; r < kRowBlock; ++r) {
+          const C2 a = o0[r];
+          ar[r] = fma(a.x, x0.x, ar[r]);
+          ar[r] = fma(-a.y, x0.y, ar[r]);
+          ai[r] = fma(a.x, x0.y, ai[r]);
+          ai[r] = fma(a.y, x0.x, ai[r]);
+          const C2 b = o1[r];
+          ar[r] = fma(b.x, x1.x, ar[r]);
+          ar[r] = fma(-b.y, x1.y, ar[r]);
+          ai[r] = fma(b.x, x1.y, ai[r]);
+          ai[r] = fma(b.y, x1.x, ai[r]);
+        }
+      }
+      for (; k < K; ++k) {
+        const C2 x0 = in[(long long)k * ks];
+        const C2* o0 = op + (long long)k * Mpad;
+#pragma unroll
+        for (int r = 0; r < kRowBlock; ++r) {
+          const C2 a = o0[r];
+          ar[r] = fma(a.x, x0.x, ar[r]);
+          ar[r] = fma(-a.y, x0.y, ar[r]);
+          ai[r] = fma(a.x, x0.y, ai[r]);
+          ai[r] = fma(a.y, x0.x, ai[r]);
+        }
+      }
+    }
+  }
+  if (!active) return;
+  C2* out = reinterpret_cast<C2*>(tk.out) + rhs * tk.out_rhs + (long long)tk.cout * nh * nh + box;
+  const long long ks = 4LL * nh * nh;
+#pragma unroll
+  for (int r = 0; r < kRowBlock; ++r) {
+    const int m = m0 + r;
+    if (m < tk.M) {
+      C2 v;
+      v.x = ar[r];
+      v.y = ai[r];
+      if (tk.beta) {
+        const C2 o = out[(long long)m * ks];
+        v.x += o.x;
+        v.y += o.y;
+      }
+      out[(long long)m * ks] = v;
+    }
+  }
+}
+
+void launch_stencil(bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks, int nrhs,
+                    hipStream_t s) {
+  if (nblocks <= 0) return;
+  dim3 grid(nblocks, nrhs);
+  if (fp32)
+    k_stencil<float><<<grid, kBoxBlock, 0, s>>>(tasks, terms, blk_task);
+  else
+    k_stencil<double><<<grid, kBoxBlock, 0, s>>>(tasks, terms, blk_task);
+}
+
+// =====================================================================================
+// Offset table W(da, db) = h^2 (i/4) H0(kappa h |(da, db)|); the (0,0) entry is set on
+// the host (exact self-cell integral).
+// =====================================================================================
+__global__ void k_wtable(double2* W, int n, double h, double kappa) {
+  const int m = 2 * n - 1;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)m * m) return;
+  const int da = (int)(idx / m) - (n - 1);
+  const int db = (int)(idx % m) - (n - 1);
+  if (da == 0 && db == 0) {
+    W[idx] = make_double2(0.0, 0.0);
+    return;
+  }
+  const double r = h * sqrt((double)da * da + (double)db * db);
+  const cplx H = hankel0(kappa * r);
+  // (i/4)(J0 + i Y0) = (-Y0/4) + i (J0/4)
+  W[idx] = make_double2(-0.25 * H.im * h * h, 0.25 * H.re * h * h);
+}
+
+void launch_wtable(double2* W, int n, double h, double kappa, hipStream_t s) {
+  const long long tot = (long long)(2 * n - 1) * (2 * n - 1);
+  k_wtable<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(W, n, h, kappa);
+}
+
+// =====================================================================================
+// Permutations and the operator epilogue y = alpha x + coef * q * (V x)
+// =====================================================================================
+template <typename T>
+__global__ void k_gather(const double2* __restrict__ x, long long ldx, typename V2<T>::type* __restrict__ xs,
+                         const int* __restrict__ idx, long long N) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (t >= N) return;
+  const double2 v = x[rhs * ldx + idx[t]];
+  typename V2<T>::type o;
+  o.x = (T)v.x;
+  o.y = (T)v.y;
+  xs[rhs * N + t] = o;
+}
+
+void launch_gather(bool to_fp32, const double2* x, long long ldx, void* xs, const int* idx, long long N, int nrhs,
+                   hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), nrhs);
+  if (to_fp32)
+    k_gather<float><<<grid, 256, 0, s>>>(x, ldx, (float2*)xs, idx, N);
+  else
+    k_gather<double><<<grid, 256, 0, s>>>(x, ldx, (double2*)xs, idx, N);
+}
+
+template <typename T>
+__global__ void k_epilogue(const double2* __restrict__ x, long long ldx, const typename V2<T>::type* __restrict__ ys,
+                           const int* __restrict__ idx, const double* __restrict__ q, double alpha, double coef,
+                           double2* __restrict__ y, long long ldy, long long N) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (i >= N) return;
+  const typename V2<T>::type v = ys[rhs * N + idx[i]];
+  const double c = q ? coef * q[i] : coef;
+  double2 o = make_double2(c * (double)v.x, c * (double)v.y);
+  if (alpha != 0.0) {
+    const double2 xv = x[rhs * ldx + i];
+    o.x += alpha * xv.x;
+    o.y += alpha * xv.y;
+  }
+  y[rhs * ldy + i] = o;
+}
+
+void launch_epilogue(bool from_fp32, const double2* x, long long ldx, const void* ys, const int* idx, const double* q,
+                     double alpha, double coef, double2* y, long long ldy, long long N, int nrhs, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), nrhs);
+  if (from_fp32)
+    k_epilogue<float><<<grid, 256, 0, s>>>(x, ldx, (const float2*)ys, idx, q, alpha, coef, y, ldy, N);
+  else
+    k_epilogue<double><<<grid, 256, 0, s>>>(x, ldx, (const double2*)ys, idx, q, alpha, coef, y, ldy, N);
+}
+
+__global__ void k_permute(const double2* __restrict__ x, long long ldx, double2* __restrict__ y, long long ldy,
+                          const int* __restrict__ perm, long long N, int scatter) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (i >= N) return;
+  if (scatter)
+    y[rhs * ldy + perm[i]] = x[rhs * ldx + i];
+  else
+    y[rhs * ldy + i] = x[rhs * ldx + perm[i]];
+}
+
+void launch_permute(const double2* x, long long ldx, double2* y, long long ldy, const int* perm, long long N, int nrhs,
+                    bool scatter, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), nrhs);
+  k_permute<<<grid, 256, 0, s>>>(x, ldx, y, ldy, perm, N, scatter ? 1 : 0);
+}
+
+__global__ void k_planewave(const double* px, const double* py, const double* q, const double* angles, double kappa,
+                            double coef, double2* f, long long ldf, long long N) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (i >= N) return;
+  const double th = angles[rhs];
+  const double ph = kappa * (cos(th) * px[i] + sin(th) * py[i]);
+  const double c = coef * q[i];
+  f[rhs * ldf + i] = make_double2(c * cos(ph), c * sin(ph));
+}
+
+void launch_planewave(const double* px, const double* py, const double* q, const double* angles, double kappa,
+                      double coef, double2* f, long long ldf, long long N, int nrhs, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), nrhs);
+  k_planewave<<<grid, 256, 0, s>>>(px, py, q, angles, kappa, coef, f, ldf, N);
+}
+
+// =====================================================================================
+// HODLR apply: leaf solves, then per binary level  z -= Y core^{-1} (W^T z).
+// =====================================================================================
+__global__ __launch_bounds__(64) void k_leaf_apply(const double2* __restrict__ Dinv,
+                                                   const unsigned char* __restrict__ ident,
+                                                   const double2* b, long long ldb, double2* z, long long ldz, int lp) {
+  __shared__ double2 bl[64];
+  const int leaf = blockIdx.x, rhs = blockIdx.y, t = threadIdx.x;
+  const long long base = (long long)leaf * lp;
+  if (t < lp) bl[t] = b[rhs * ldb + base + t];
+  __syncthreads();
+  if (t >= lp) return;
+  if (ident[leaf]) {
+    z[rhs * ldz + base + t] = bl[t];
+    return;
+  }
+  const double2* D = Dinv + (long long)leaf * lp * lp;
+  double re = 0, im = 0;
+  for (int k = 0; k < lp; ++k) {
+    const double2 a = D[(long long)k * lp + t];
+    const double2 x = bl[k];
+    re = fma(a.x, x.x, re);
+    re = fma(-a.y, x.y, re);
+    im = fma(a.x, x.y, im);
+    im = fma(a.y, x.x, im);
+  }
+  z[rhs * ldz + base + t] = make_double2(re, im);
+}
+
+void launch_leaf_apply(const double2* Dinv, const unsigned char* ident, const double2* b, long long ldb, double2* z,
+                       long long ldz, int lp, int nleaves, int nrhs, hipStream_t s) {
+  dim3 grid(nleaves, nrhs);
+  k_leaf_apply<<<grid, 64, 0, s>>>(Dinv, ident, b, ldb, z, ldz, lp);
+}
+
+// partial[(rhs*nchunks + chunk)*r + c] = sum_{i in chunk} W[c*N + i] z[i]
+template <typename T>
+__global__ __launch_bounds__(256) void k_hodlr_dot(const typename V2<T>::type* __restrict__ W,
+                                                   const double2* __restrict__ z, long long ldz,
+                                                   double2* __restrict__ partial, long long N, int r, long long chunk,
+                                                   int nchunks) {
+  __shared__ double red[32];
+  const int ch = blockIdx.x, rhs = blockIdx.y;
+  const long long i0 = (long long)ch * chunk;
+  for (int c = 0; c < r; ++c) {
+    double re = 0, im = 0;
+    for (long long i = i0 + threadIdx.x; i < i0 + chunk; i += blockDim.x) {
+      const typename V2<T>::type w = W[(long long)c * N + i];
+      const double2 x = z[rhs * ldz + i];
+      re += (double)w.x * x.x - (double)w.y * x.y;
+      im += (double)w.x * x.y + (double)w.y * x.x;
+    }
+    const double2 sum = block_sum2(re, im, red);
+    if (threadIdx.x == 0) partial[((long long)rhs * nchunks + ch) * r + c] = sum;
+  }
+}
+
+void launch_hodlr_dot(bool fp32, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
+                      long long chunk, int nchunks, int nrhs, hipStream_t s) {
+  dim3 grid(nchunks, nrhs);
+  int nt = chunk >= 256 ? 256 : (int)((chunk + 63) / 64) * 64;
+  if (fp32)
+    k_hodlr_dot<float><<<grid, nt, 0, s>>>((const float2*)W, z, ldz, partial, N, r, chunk, nchunks);
+  else
+    k_hodlr_dot<double><<<grid, nt, 0, s>>>((const double2*)W, z, ldz, partial, N, r, chunk, nchunks);
+}
+
+// t = [t_A; t_B]: t_A from the chunks of the second child (rows paired with Q), t_B from
+// the first child (rows paired with S).  apply: s = coreinv * t, else s = t.
+__global__ __launch_bounds__(64) void k_hodlr_core(const double2* __restrict__ partial,
+                                                   const double2* __restrict__ coreinv, double2* __restrict__ sout,
+                                                   int r, int nodes, int cpc, int nchunks, int apply) {
+  __shared__ double2 t[128];
+  const int node = blockIdx.x, rhs = blockIdx.y;
+  const int r2 = 2 * r;
+  for (int i = threadIdx.x; i < r2; i += blockDim.x) {
+    const int half = i < r ? 1 : 0;  // t_A sums the second child
+    const int c = i < r ? i : i - r;
+    const long long ch0 = (long long)node * 2 * cpc + (long long)half * cpc;
+    double re = 0, im = 0;
+    for (int k = 0; k < cpc; ++k) {
+      const double2 v = partial[((long long)rhs * nchunks + ch0 + k) * r + c];
+      re += v.x;
+      im += v.y;
+    }
+    t[i] = make_double2(re, im);
+  }
+  __syncthreads();
+  double2* so = sout + ((long long)rhs * nodes + node) * r2;
+  if (!apply) {
+    for (int i = threadIdx.x; i < r2; i += blockDim.x) so[i] = t[i];
+    return;
+  }
+  const double2* Ci = coreinv + (long long)node * r2 * r2;
+  for (int i = threadIdx.x; i < r2; i += blockDim.x) {
+    double re = 0, im = 0;
+    for (int j = 0; j < r2; ++j) {
+      const double2 a = Ci[(long long)i * r2 + j];
+      const double2 x = t[j];
+      re += a.x * x.x - a.y * x.y;
+      im += a.x * x.y + a.y * x.x;
+    }
+    so[i] = make_double2(re, im);
+  }
+}
+
+void launch_hodlr_core(const double2* partial, const double2* coreinv, double2* sout, int r, int nodes,
+                       int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s) {
+  dim3 grid(nodes, nrhs);
+  k_hodlr_core<<<grid, 64, 0, s>>>(partial, coreinv, sout, r, nodes, chunks_per_child, nchunks, apply ? 1 : 0);
+}
+
+// z[i] -= sum_c Y[c*N + i] * s[node][half*r + c]
+template <typename T>
+__global__ __launch_bounds__(256) void k_hodlr_update(const typename V2<T>::type* __restrict__ Y,
+                                                      const double2* __restrict__ sv, double2* __restrict__ z,
+                                                      long long ldz, long long N, int r, long long nodesize,
+                                                      int nodes) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (i >= N) return;
+  const long long node = i / nodesize;
+  const int half = (i - node * nodesize) >= (nodesize >> 1) ? 1 : 0;
+  const double2* s = sv + ((long long)rhs * nodes + node) * 2 * r + half * r;
+  double re = 0, im = 0;
+  for (int c = 0; c < r; ++c) {
+    const typename V2<T>::type y = Y[(long long)c * N + i];
+    const double2 x = s[c];
+    re += (double)y.x * x.x - (double)y.y * x.y;
+    im += (double)y.x * x.y + (double)y.y * x.x;
+  }
+  double2 o = z[rhs * ldz + i];
+  o.x -= re;
+  o.y -= im;
+  z[rhs * ldz + i] = o;
+}
+
+void launch_hodlr_update(bool fp32, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
+                         long long nodesize, int nodes, int nrhs, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), nrhs);
+  if (fp32)
+    k_hodlr_update<float><<<grid, 256, 0, s>>>((const float2*)Y, sv, z, ldz, N, r, nodesize, nodes);
+  else
+    k_hodlr_update<double><<<grid, 256, 0, s>>>((const double2*)Y, sv, z, ldz, N, r, nodesize, nodes);
+}
+
+// =====================================================================================
+// Krylov (Arnoldi) kernels: classical Gram-Schmidt dot products and updates.
+// =====================================================================================
+// partial[(rhs*nchunks + chunk)*maxv + v] = sum_{i in chunk} conj(Q_v[i]) w[i]
+__global__ __launch_bounds__(256) void k_gs_dot(const double2* __restrict__ Q, long long ldq_vec, long long ldq_rhs,
+                                                int nv, const double2* __restrict__ w, long long ldw,
+                                                double2* __restrict__ partial, long long N, int nchunks, int maxv) {
+  __shared__ double red[32];
+  const int ch = blockIdx.x, rhs = blockIdx.y;
+  const long long per = (N + nchunks - 1) / nchunks;
+  const long long i0 = (long long)ch * per;
+  const long long i1 = i0 + per < N ? i0 + per : N;
+  const double2* wr = w + rhs * ldw;
+  for (int v = 0; v < nv; ++v) {
+    const double2* q = Q + rhs * ldq_rhs + v * ldq_vec;
+    double re = 0, im = 0;
+    for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      const double2 a = q[i], x = wr[i];
+      re += a.x * x.x + a.y * x.y;
+      im += a.x * x.y - a.y * x.x;
+    }
+    const double2 sum = block_sum2(re, im, red);
+    if (threadIdx.x == 0) partial[((long long)rhs * nchunks + ch) * maxv + v] = sum;
+  }
+}
+
+void launch_gs_dot(const double2* Q, long long ldq_vec, long long ldq_rhs, int nv, const double2* w, long long ldw,
+                   double2* partial, long long N, int nchunks, int maxv, int nrhs, hipStream_t s) {
+  dim3 grid(nchunks, nrhs);
+  k_gs_dot<<<grid, 256, 0, s>>>(Q, ldq_vec, ldq_rhs, nv, w, ldw, partial, N, nchunks, maxv);
+}
+
+__global__ void k_gs_finish(const double2* __restrict__ partial, int nchunks, int nv, int maxv, double2* h,
+                            int accumulate) {
+  const int rhs = blockIdx.y;
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  double re = 0, im = 0;
+  for (int c = 0; c < nchunks; ++c) {
+    const double2 p = partial[((long long)rhs * nchunks + c) * maxv + v];
+    re += p.x;
+    im += p.y;
+  }
+  double2* o = h + (long long)rhs * maxv + v;
+  if (accumulate) {
+    re += o->x;
+    im += o->y;
+  }
+  *o = make_double2(re, im);
+}
+
+void launch_gs_finish(const double2* partial, int nchunks, int nv, int maxv, double2* h, int accumulate, int nrhs,
+                      hipStream_t s) {
+  dim3 grid((nv + 63) / 64, nrhs);
+  k_gs_finish<<<grid, 64, 0, s>>>(partial, nchunks, nv, maxv, h, accumulate);
+}
+
+// w[i] += sign * sum_v Q_v[i] h[v]
+__global__ __launch_bounds__(256) void k_gs_axpy(const double2* __restrict__ Q, long long ldq_vec, long long ldq_rhs,
+                                                 int nv, const double2* __restrict__ h, int maxv, double sign,
+                                                 double2* __restrict__ w, long long ldw, long long N) {
+  __shared__ double2 hs[256];
+  const int rhs = blockIdx.y;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double re = 0, im = 0;
+  for (int v0 = 0; v0 < nv; v0 += 256) {
+    const int cnt = nv - v0 < 256 ? nv - v0 : 256;
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) hs[threadIdx.x] = h[(long long)rhs * maxv + v0 + threadIdx.x];
+    __syncthreads();
+    if (i < N) {
+      const double2* q = Q + rhs * ldq_rhs + (long long)v0 * ldq_vec + i;
+      for (int v = 0; v < cnt; ++v) {
+        const double2 a = q[(long long)v * ldq_vec];
+        const double2 b = hs[v];
+        re += a.x * b.x - a.y * b.y;
+        im += a.x * b.y + a.y * b.x;
+      }
+    }
+  }
+  if (i < N) {
+    double2 o = w[rhs * ldw + i];
+    o.x += sign * re;
+    o.y += sign * im;
+    w[rhs * ldw + i] = o;
+  }
+}
+
+void launch_gs_axpy(const double2* Q, long long ldq_vec, long long ldq_rhs, int nv, const double2* h, int maxv,
+                    double sign, double2* w, long long ldw, long long N, int nrhs, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), nrhs);
+  k_gs_axpy<<<grid, 256, 0, s>>>(Q, ldq_vec, ldq_rhs, nv, h, maxv, sign, w, ldw, N);
+}
+
+__global__ __launch_bounds__(256) void k_norm2(const double2* __restrict__ w, long long ldw, double* partial,
+                                               long long N, int nchunks) {
+  __shared__ double red[32];
+  const int ch = blockIdx.x, rhs = blockIdx.y;
+  const long long per = (N + nchunks - 1) / nchunks;
+  const long long i0 = (long long)ch * per;
+  const long long i1 = i0 + per < N ? i0 + per : N;
+  double acc = 0;
+  for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const double2 a = w[rhs * ldw + i];
+    acc += a.x * a.x + a.y * a.y;
+  }
+  const double2 sum = block_sum2(acc, 0.0, red);
+  if (threadIdx.x == 0) partial[(long long)rhs * nchunks + ch] = sum.x;
+}
+
+void launch_norm2(const double2* w, long long ldw, double* partial, long long N, int nchunks, int nrhs,
+                  hipStream_t s) {
+  dim3 grid(nchunks, nrhs);
+  k_norm2<<<grid, 256, 0, s>>>(w, ldw, partial, N, nchunks);
+}
+
+__global__ void k_norm2_finish(const double* partial, int nchunks, double* out) {
+  const int rhs = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double s = 0;
+  for (int c = 0; c < nchunks; ++c) s += partial[(long long)rhs * nchunks + c];
+  out[rhs] = s;
+}
+
+void launch_norm2_finish(const double* partial, int nchunks, double* out, int nrhs, hipStream_t s) {
+  k_norm2_finish<<<nrhs, 64, 0, s>>>(partial, nchunks, out);
+}
+
+__global__ void k_scale(const double2* __restrict__ w, long long ldw, const double* __restrict__ alpha,
+                        double2* __restrict__ out, long long ldo, long long N) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (i >= N) return;
+  const double a = alpha[rhs];
+  const double2 v = w[rhs * ldw + i];
+  out[rhs * ldo + i] = make_double2(a * v.x, a * v.y);
+}
+
+void launch_scale(const double2* w, long long ldw, const double* alpha, double2* out, long long ldo, long long N,
+                  int nrhs, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), nrhs);
+  k_scale<<<grid, 256, 0, s>>>(w, ldw, alpha, out, ldo, N);
+}
+
+__global__ void k_axpby(double a, const double2* x, long long ldx, double b, const double2* y, long long ldy,
+                        double2* out, long long ldo, long long N) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (i >= N) return;
+  const double2 xv = x[rhs * ldx + i];
+  double2 o = make_double2(a * xv.x, a * xv.y);
+  if (b != 0.0) {
+    const double2 yv = y[rhs * ldy + i];
+    o.x += b * yv.x;
+    o.y += b * yv.y;
+  }
+  out[rhs * ldo + i] = o;
+}
+
+void launch_axpby(double a, const double2* x, long long ldx, double b, const double2* y, long long ldy, double2* out,
+                  long long ldo, long long N, int nrhs, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), nrhs);
+  k_axpby<<<grid, 256, 0, s>>>(a, x, ldx, b, y, ldy, out, ldo, N);
+}
+
+__global__ void k_cast(int to_fp32, const void* in, void* out, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (to_fp32) {
+    const double2 v = reinterpret_cast<const double2*>(in)[i];
+    reinterpret_cast<float2*>(out)[i] = make_float2((float)v.x, (float)v.y);
+  } else {
+    const float2 v = reinterpret_cast<const float2*>(in)[i];
+    reinterpret_cast<double2*>(out)[i] = make_double2((double)v.x, (double)v.y);
+  }
+}
+
+void launch_cast(bool to_fp32, const void* in, void* out, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  k_cast<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(to_fp32 ? 1 : 0, in, out, n);
+}
+
+}  // namespace lsk

@@ -1,0 +1,244 @@
+"""ctypes binding of libls (argument marshalling only; every step runs in the library).
+
+Vectors are torch tensors on the GPU, complex128, shaped (N,) or (nrhs, N) (row j of a
+2-D tensor is right-hand side j, i.e. column-major N x nrhs with ld = N), in the
+caller's point order.  The library raises if it was not built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libls.so")
+
+LS_OK, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_ENOTSUP = 0, -1, -2, -3, -4
+LS_FP64, LS_FP32, LS_MIXED = 0, 1, 2
+STATUS = {0: "CONVERGED", 1: "MAXIT", 2: "BREAKDOWN", 3: "NAN", 4: "REFINE_STAGNATED", 5: "WARMSTART_REJECTED"}
+PROFILE_CLASSES = {"near_m2l": 0, "hodlr_update": 1, "leaf_solve": 2, "gs_dot": 3}
+
+
+class LsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libls error {code}: {msg}")
+        self.code = code
+
+
+class _Options(C.Structure):
+    _fields_ = [("leaf_max", C.c_int), ("T", C.c_double), ("sign", C.c_int), ("hodlr_rank", C.c_int),
+                ("eps_inner", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("prec", C.c_int),
+                ("inner_tol", C.c_double), ("max_refine", C.c_int), ("build_fp32", C.c_int)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("iters", C.c_int), ("relres", C.c_double), ("status", C.c_int), ("n_refine", C.c_int),
+                ("t_solve_ms", C.c_double)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("N", C.c_int64), ("n", C.c_int), ("levels", C.c_int), ("leaf_side", C.c_int),
+                ("top_level", C.c_int), ("nlevels_hf", C.c_int), ("rank_max64", C.c_int), ("rank_max32", C.c_int),
+                ("entries_near", C.c_int64), ("entries_far64", C.c_int64), ("entries_far32", C.c_int64),
+                ("m2l_pairs", C.c_int64), ("stored_bytes64", C.c_int64), ("stored_bytes32", C.c_int64),
+                ("hodlr_bytes", C.c_int64), ("t_plan_ms", C.c_double), ("t_nca_ms", C.c_double),
+                ("t_hodlr_ms", C.c_double), ("t_setup_ms", C.c_double)]
+
+
+class _PlanInfo(C.Structure):
+    _fields_ = [("levels", C.c_int), ("leaf_side", C.c_int), ("top_level", C.c_int), ("hf", C.c_int * 32),
+                ("ndir", C.c_int * 32), ("max_il", C.c_int * 32), ("il_pairs", C.c_int64 * 32),
+                ("near_pairs", C.c_int64), ("coverage_min", C.c_int), ("coverage_max", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libls.so (built in-tree by paper_2204_00326_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2204_00326_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, ci, cd = C.c_void_p, C.c_int64, C.c_int, C.c_double
+    L.ls_default_options.argtypes = [C.POINTER(_Options)]
+    L.ls_default_options.restype = None
+    L.ls_last_error.restype = C.c_char_p
+    L.ls_setup.argtypes = [vp, i64, vp, cd, cd, C.POINTER(_Options), C.POINTER(vp)]
+    for name in ("ls_matvec", "ls_apply_V", "ls_precond_apply"):
+        getattr(L, name).argtypes = [vp, vp, vp, ci, i64, ci, vp]
+    L.ls_rhs_planewave.argtypes = [vp, vp, ci, vp, i64, vp]
+    L.ls_solve.argtypes = [vp, vp, vp, ci, i64, cd, ci, C.POINTER(_Info), vp]
+    L.ls_stats.argtypes = [vp, C.POINTER(_Stats)]
+    L.ls_destroy.argtypes = [vp]
+    L.ls_destroy.restype = None
+    L.ls_plan_describe.argtypes = [ci, cd, cd, C.POINTER(_Options), C.POINTER(_PlanInfo)]
+    L.ls_green_table.argtypes = [ci, cd, cd, vp, vp]
+    L.ls_profile_enable.argtypes = [vp, ci, ci]
+    L.ls_profile_read.argtypes = [vp, ci, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    for name in ("ls_setup", "ls_matvec", "ls_apply_V", "ls_precond_apply", "ls_rhs_planewave", "ls_solve",
+                 "ls_stats", "ls_plan_describe", "ls_profile_enable", "ls_profile_read", "ls_green_table"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != LS_OK:
+        raise LsError(code, lib().ls_last_error().decode())
+
+
+@dataclass
+class Options:
+    leaf_max: int = 64
+    T: float = 16.0
+    sign: int = -1
+    hodlr_rank: int = 15
+    eps_inner: float = 1e-7
+    restart: int = 200
+    maxit: int = 2000
+    prec: int = LS_FP64
+    inner_tol: float = 1e-6
+    max_refine: int = 10
+    build_fp32: int = 1
+
+    def _c(self) -> _Options:
+        o = _Options()
+        for f in fields(self):
+            setattr(o, f.name, getattr(self, f.name))
+        return o
+
+
+def plan_describe(n: int, L: float, kappa: float, options: Options | None = None) -> dict:
+    """Quadtree / cone / list summary and the coverage count (host only)."""
+    info = _PlanInfo()
+    o = (options or Options())._c()
+    _check(lib().ls_plan_describe(n, L, kappa, C.byref(o), C.byref(info)))
+    lv = info.levels
+    return {
+        "levels": lv, "leaf_side": info.leaf_side, "top_level": info.top_level,
+        "hf": [bool(info.hf[i]) for i in range(lv + 1)], "ndir": [info.ndir[i] for i in range(lv + 1)],
+        "il_pairs": [info.il_pairs[i] for i in range(lv + 1)], "max_il": [info.max_il[i] for i in range(lv + 1)],
+        "near_pairs": info.near_pairs, "coverage": (info.coverage_min, info.coverage_max),
+    }
+
+
+def green_table(n: int, h: float, kappa: float, stream=None):
+    """Device table of V entries for grid offsets, shape (2n-1, 2n-1) complex128 (index da+n-1, db+n-1)."""
+    import torch
+    out = torch.empty((2 * n - 1, 2 * n - 1), dtype=torch.complex128, device="cuda")
+    _check(lib().ls_green_table(n, float(h), float(kappa), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _vec(t, N: int):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError("expected a complex128 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if t.dim() == 1:
+        if t.shape[0] != N:
+            raise ValueError(f"expected length {N}")
+        return 1
+    if t.dim() == 2 and t.shape[1] == N:
+        return t.shape[0]
+    raise ValueError(f"expected shape (N,) or (nrhs, N) with N = {N}")
+
+
+class Problem:
+    """Handle of an ls_setup()-built solver."""
+
+    def __init__(self, points: np.ndarray, q: np.ndarray, kappa: float, tol: float = 1e-10,
+                 options: Options | None = None):
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        qq = np.ascontiguousarray(q, dtype=np.float64)
+        if pts.ndim != 2 or pts.shape[1] != 2 or qq.shape != (pts.shape[0],):
+            raise ValueError("points must be (N, 2) and q (N,)")
+        self.N = int(pts.shape[0])
+        self.options = options or Options()
+        o = self.options._c()
+        h = C.c_void_p()
+        _check(lib().ls_setup(pts.ctypes.data, self.N, qq.ctypes.data, float(kappa), float(tol), C.byref(o),
+                              C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().ls_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _out(self, x, y):
+        import torch
+        return torch.empty_like(x) if y is None else y
+
+    def matvec(self, x, y=None, prec: int = LS_FP64, stream=None):
+        nrhs = _vec(x, self.N)
+        y = self._out(x, y)
+        _vec(y, self.N)
+        _check(lib().ls_matvec(self._h, x.data_ptr(), y.data_ptr(), nrhs, self.N, prec, _stream(stream)))
+        return y
+
+    def apply_V(self, x, y=None, prec: int = LS_FP64, stream=None):
+        nrhs = _vec(x, self.N)
+        y = self._out(x, y)
+        _check(lib().ls_apply_V(self._h, x.data_ptr(), y.data_ptr(), nrhs, self.N, prec, _stream(stream)))
+        return y
+
+    def precond_apply(self, r, z=None, prec: int = LS_FP64, stream=None):
+        nrhs = _vec(r, self.N)
+        z = self._out(r, z)
+        _check(lib().ls_precond_apply(self._h, r.data_ptr(), z.data_ptr(), nrhs, self.N, prec, _stream(stream)))
+        return z
+
+    def rhs_planewave(self, angles, stream=None):
+        import torch
+        ang = np.ascontiguousarray(np.atleast_1d(np.asarray(angles, dtype=np.float64)))
+        nrhs = ang.shape[0]
+        f = torch.empty((nrhs, self.N) if nrhs > 1 else (self.N,), dtype=torch.complex128, device="cuda")
+        _check(lib().ls_rhs_planewave(self._h, ang.ctypes.data, nrhs, f.data_ptr(), self.N, _stream(stream)))
+        return f
+
+    def solve(self, f, psi=None, tol: float = 1e-8, x0: bool = False, stream=None):
+        import torch
+        nrhs = _vec(f, self.N)
+        if psi is None:
+            psi = torch.zeros_like(f)
+        infos = (_Info * nrhs)()
+        _check(lib().ls_solve(self._h, f.data_ptr(), psi.data_ptr(), nrhs, self.N, float(tol), int(bool(x0)),
+                              infos, _stream(stream)))
+        out = [{"iters": i.iters, "relres": i.relres, "status": STATUS.get(i.status, str(i.status)),
+                "n_refine": i.n_refine, "t_solve_ms": i.t_solve_ms} for i in infos]
+        return psi, out
+
+    def stats(self) -> dict:
+        s = _Stats()
+        _check(lib().ls_stats(self._h, C.byref(s)))
+        return {f[0]: getattr(s, f[0]) for f in _Stats._fields_}
+
+    def profile_enable(self, cls: str, enable: bool = True):
+        _check(lib().ls_profile_enable(self._h, PROFILE_CLASSES[cls], int(enable)))
+
+    def profile_read(self, cls: str):
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(lib().ls_profile_read(self._h, PROFILE_CLASSES[cls], C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
