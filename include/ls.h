@@ -50,7 +50,8 @@ typedef enum {
 typedef enum {
   LS_FP64 = 0,  /* complex128 operator, complex128 accumulation */
   LS_FP32 = 1,  /* complex64 operator and accumulation (near field, M2L, translations) */
-  LS_MIXED = 2  /* ls_solve only: FP32 inner GMRES, FP64 residual and refinement */
+  LS_MIXED = 2  /* ls_solve only: flexible GMRES with FP32 products once the residual is small,
+                   FP32 off-diagonal HODLR factors, FP64 Arnoldi and FP64 residual at each restart */
 } ls_prec;
 
 enum {
@@ -71,16 +72,22 @@ typedef struct {
   int restart;        /* GMRES restart length m (default 200) */
   int maxit;          /* max GMRES iterations per solve (default 2000) */
   int prec;           /* ls_prec used by ls_solve (default LS_FP64) */
-  double inner_tol;   /* LS_MIXED: relative tolerance floor of each inner FP32 solve (default 1e-6) */
+  double inner_tol;   /* LS_MIXED: relative accuracy delta of the FP32 operator; products switch to FP32
+                         once every residual estimate is below tol / delta (default 1e-5) */
   int max_refine;     /* LS_MIXED: max outer refinement steps (default 10) */
   int build_fp32;     /* build the FP32 operator at setup (default 1) */
+  int hodlr_rank_div; /* 0 (default): rank hodlr_rank at every HODLR level, as in the paper;
+                         d > 0: rank min(hodlr_rank, child block size / d) per level */
 } ls_options;
 
 typedef struct {
-  int iters;          /* total GMRES iterations (inner iterations summed in LS_MIXED) */
+  int iters;          /* total GMRES (Arnoldi) iterations */
   double relres;      /* final true relative residual ||f - A psi|| / ||f|| (FP64 operator) */
-  int status;         /* LS_CONVERGED, LS_MAXIT, ... */
-  int n_refine;       /* LS_MIXED: outer refinement steps taken */
+  int status;         /* LS_CONVERGED; LS_MAXIT (maxit reached); LS_NAN (non-finite residual);
+                         LS_WARMSTART_REJECTED (converged, but the given x0 was replaced by zero);
+                         LS_REFINE_STAGNATED (LS_MIXED: FP32 products stopped reducing the FP64
+                         residual, the column was finished with FP64 products and converged) */
+  int n_refine;       /* LS_MIXED: Krylov cycles, each started from an FP64 residual f - A x */
   double t_solve_ms;  /* wall time of the call */
 } ls_solve_info;
 
@@ -96,6 +103,8 @@ typedef struct {
   int64_t entries_near;   /* near-field kernel entries applied per matvec (one RHS) */
   int64_t entries_far64;  /* P2M+M2M+M2L+L2L+L2P entries applied per FP64 matvec */
   int64_t entries_far32;  /* same for the FP32 operator */
+  int64_t entries_m2l64;  /* M2L part of entries_far64 */
+  int64_t entries_m2l32;  /* M2L part of entries_far32 */
   int64_t m2l_pairs;      /* (box[,direction], source) M2L pairs over all levels */
   int64_t stored_bytes64; /* device bytes of the FP64 DAFMM operators */
   int64_t stored_bytes32;
@@ -151,12 +160,13 @@ ls_status ls_rhs_planewave(ls_problem* P, const double* angles, int nrhs, void* 
 
 /* Solve A psi = f for nrhs columns by restarted GMRES with right HODLR preconditioning
  * (when hodlr_rank > 0), stopping when ||f - A psi|| / ||f|| <= tol per column.
+ * prec: LS_FP64, LS_FP32, LS_MIXED, or -1 for the precision given in the options.
  * f, psi: device, N x nrhs complex128.  x0_given != 0: psi holds the initial guess (a
  * guess whose residual is not below ||f|| is replaced by zero, status bit
  * LS_WARMSTART_REJECTED reported in info[j].status when the column otherwise converged).
  * info: host array of nrhs entries (may be NULL).  Synchronous on `stream`. */
 ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld, double tol,
-                   int x0_given, ls_solve_info* info, void* stream);
+                   int x0_given, int prec, ls_solve_info* info, void* stream);
 
 /* Table of V entries for grid offsets (Section 1 Green's function, Eq. (eq:13) at p = 1):
  * out[(da + n-1) * (2n-1) + (db + n-1)] = h^2 (i/4) H0^(1)(kappa h |(da, db)|) for (da, db) != 0 and
@@ -173,8 +183,9 @@ const char* ls_last_error(void);
 ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt, ls_plan_info* out);
 
 /* Kernel timing with HIP events recorded around every launch of one kernel class on
- * the launch stream: class 0 = near field (P2P + M2L launch), 1 = HODLR level update,
- * 2 = leaf solve, 3 = Arnoldi dot products.  enable = 1 starts (and clears) the
+ * the launch stream: class 0 = near field + M2L launch (FP64 operator), 1 = HODLR level
+ * update, 2 = HODLR leaf solve, 3 = Arnoldi dot products, 4 = near field + M2L launch
+ * (FP32 operator).  enable = 1 starts (and clears) the
  * counters, 0 stops.  ls_profile_read synchronises and returns the summed event time
  * and the number of timed launches. */
 ls_status ls_profile_enable(ls_problem* P, int kernel_class, int enable);

@@ -118,6 +118,7 @@ struct Phase {
   DevBuf tasks, terms, blk;
   int nblocks = 0;
   int ntasks = 0;
+  int tag = 0;  // 0 near+M2L, 1 P2M, 2 M2M, 3 L2L, 4 L2P
 };
 
 struct FmmDev {
@@ -144,11 +145,13 @@ struct FmmDev {
   std::vector<std::vector<std::vector<long long>>> off_Ct;   // [nu][dir][c]: L2L op = C^T (k x Mpad(k_child))
   std::vector<std::vector<std::vector<long long>>> off_K;    // [nu][dir][term]: M2L op = K^T
   int64_t entries_far = 0;
+  int64_t entries_m2l = 0;
   int64_t stored_bytes = 0;
 };
 
 struct HodlrDev {
   int r = 0, Lb = 0, nleaves = 0, lp = 0;
+  std::vector<int> rank;  // per binary level
   long long N = 0;
   DevBuf Dinv, ident;
   std::vector<DevBuf> Y64, W64, Y32, W32, coreinv;
@@ -184,9 +187,9 @@ struct ls_problem {
   DevBuf w_x, w_y, w_t;  // Morton-order vectors (nrhs_cap)
   int ws_cap = 0;
   ls_stats_t stats{};
-  ProfileClass prof[4];
+  ProfileClass prof[5];
   // Krylov workspace
-  DevBuf kQ, kw, kz, kr, kh, kpart, knp, kno, kalpha, ky, kx, kf, kdx;
+  DevBuf kQ, kZ, kw, kz, kr, kh, kpart, knp, kno, kalpha, ky, kx, kf, kdx;
   size_t kcap_key = 0;
 };
 
@@ -303,6 +306,7 @@ void build_fmm_ops(ls_problem* P, const ls::NCA& nca, FmmDev& F, bool fp32) {
               if (sb >= 0 && sb < l.nb) ++cnt_b;
             }
             F.entries_far += (int64_t)cnt_a * cnt_b * L.rank[dir] * L.rank[ad];
+            F.entries_m2l += (int64_t)cnt_a * cnt_b * L.rank[dir] * L.rank[ad];
           }
         }
     }
@@ -339,6 +343,12 @@ void build_phases(ls_problem* P, FmmDev& F) {
     std::vector<int> blk;
     for (size_t t = 0; t < tasks.size(); ++t) {
       lsk::DTask& tk = tasks[t];
+      int kb = 0;
+      for (int q = tk.t0; q < tk.t1; ++q) {
+        terms[q].kbase = kb;
+        kb += terms[q].K;
+      }
+      tk.ktot = kb;
       tk.Mpad = round_up(std::max(tk.M, 1), lsk::kRowBlock);
       tk.nrb = tk.Mpad / lsk::kRowBlock;
       tk.blk0 = (int)blk.size();
@@ -422,6 +432,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
       }
     }
     make_phase(F.nearm2l, tasks, terms);
+    F.nearm2l.tag = 0;
   }
   if (p.top > leaf) return;
   // ---- P2M ----
@@ -449,6 +460,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
       tasks.push_back(tk);
     }
     make_phase(F.p2m, tasks, terms);
+    F.p2m.tag = 1;
   }
   // ---- L2P (accumulates onto the near field) ----
   {
@@ -475,6 +487,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
       tasks.push_back(tk);
     }
     make_phase(F.l2p, tasks, terms);
+    F.l2p.tag = 4;
   }
   // ---- M2M (parent nu from children nu+1), deepest first ----
   F.up.clear();
@@ -512,6 +525,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
       }
     }
     make_phase(F.up[leaf - 1 - nu], tasks, terms);
+    F.up[leaf - 1 - nu].tag = 2;
   }
   // ---- L2L (parent nu -> children nu+1), top first ----
   F.down.clear();
@@ -549,6 +563,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
       }
     }
     make_phase(F.down[nu - p.top], tasks, terms);
+    F.down[nu - p.top].tag = 3;
   }
 }
 
@@ -579,11 +594,11 @@ void run_phase(ls_problem* P, FmmDev& F, Phase& ph, int nrhs, hipStream_t s, int
   if (ph.nblocks == 0) return;
   if (prof_cls >= 0) {
     ProfScope ps(P, prof_cls, s);
-    lsk::launch_stencil(F.fp32, ph.tasks.as<lsk::DTask>(), ph.terms.as<lsk::DTerm>(), ph.blk.as<int>(), ph.nblocks,
-                        nrhs, s);
+    lsk::launch_stencil(ph.tag, F.fp32, ph.tasks.as<lsk::DTask>(), ph.terms.as<lsk::DTerm>(), ph.blk.as<int>(),
+                        ph.nblocks, nrhs, s);
   } else {
-    lsk::launch_stencil(F.fp32, ph.tasks.as<lsk::DTask>(), ph.terms.as<lsk::DTerm>(), ph.blk.as<int>(), ph.nblocks,
-                        nrhs, s);
+    lsk::launch_stencil(ph.tag, F.fp32, ph.tasks.as<lsk::DTask>(), ph.terms.as<lsk::DTerm>(), ph.blk.as<int>(),
+                        ph.nblocks, nrhs, s);
   }
 }
 
@@ -603,7 +618,7 @@ void fmm_apply(ls_problem* P, bool fp32, const double2* x, long long ldx, double
     run_phase(P, F, F.p2m, nrhs, s);
     for (auto& ph : F.up) run_phase(P, F, ph, nrhs, s);
   }
-  run_phase(P, F, F.nearm2l, nrhs, s, 0);
+  run_phase(P, F, F.nearm2l, nrhs, s, fp32 ? 4 : 0);
   if (p.top <= p.leaf) {
     for (auto& ph : F.down) run_phase(P, F, ph, nrhs, s);
     run_phase(P, F, F.l2p, nrhs, s);
@@ -619,8 +634,8 @@ void hodlr_ensure_ws(ls_problem* P, int nrhs) {
   HodlrDev& H = P->hod;
   size_t needp = 0, needs = 0;
   for (int l = 0; l < H.Lb; ++l) {
-    needp = std::max(needp, (size_t)H.nchunks[l] * H.r);
-    needs = std::max(needs, (size_t)(1LL << l) * 2 * H.r);
+    needp = std::max(needp, (size_t)H.nchunks[l] * H.rank[l]);
+    needs = std::max(needs, (size_t)(1LL << l) * 2 * H.rank[l]);
   }
   H.partial.ensure(std::max<size_t>(needp, 1) * nrhs * 16);
   H.svec.ensure(std::max<size_t>(needs, 1) * nrhs * 16);
@@ -641,11 +656,13 @@ void hodlr_apply(ls_problem* P, bool fp32, const double2* b, long long ldb, doub
     const void* W = fp32 ? H.W32[l].p : H.W64[l].p;
     const void* Y = fp32 ? H.Y32[l].p : H.Y64[l].p;
     int nodes = 1 << l;
-    lsk::launch_hodlr_dot(fp32, W, z, ldz, H.partial.as<double2>(), H.N, H.r, H.chunk[l], H.nchunks[l], nrhs, s);
-    lsk::launch_hodlr_core(H.partial.as<double2>(), H.coreinv[l].as<double2>(), H.svec.as<double2>(), H.r, nodes,
+    const int rl = H.rank[l];
+    if (rl == 0) continue;
+    lsk::launch_hodlr_dot(fp32, W, z, ldz, H.partial.as<double2>(), H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s);
+    lsk::launch_hodlr_core(H.partial.as<double2>(), H.coreinv[l].as<double2>(), H.svec.as<double2>(), rl, nodes,
                            H.cpc[l], H.nchunks[l], true, nrhs, s);
     ProfScope ps(P, 1, s);
-    lsk::launch_hodlr_update(fp32, Y, H.svec.as<double2>(), z, ldz, H.N, H.r, H.N >> l, nodes, nrhs, s);
+    lsk::launch_hodlr_update(fp32, Y, H.svec.as<double2>(), z, ldz, H.N, rl, H.N >> l, nodes, nrhs, s);
   }
   hip_check(hipGetLastError(), "hodlr kernels");
 }
@@ -700,16 +717,20 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
   for (int l = 0; l < H.Lb; ++l) {
     long long cs = N >> (l + 1);  // child size; chunks must tile it exactly
     long long ch = cs;
-    while (ch > 8192 && ch % 2 == 0) ch /= 2;
+    while (ch > 512 && ch % 2 == 0) ch /= 2;
     H.chunk[l] = ch;
     H.nchunks[l] = (int)(N / ch);
     H.cpc[l] = (int)(cs / ch);
   }
-  // off-diagonal ACA at fixed rank r (rows with q = 0 are known zero)
+  // off-diagonal ACA at fixed rank (rows with q = 0 are known zero)
+  H.rank.assign(H.Lb, r);
+  if (P->opt.hodlr_rank_div > 0)
+    for (int l = 0; l < H.Lb; ++l)
+      H.rank[l] = (int)std::max<long long>(1, std::min<long long>(r, (N >> (l + 1)) / P->opt.hodlr_rank_div));
   std::vector<std::vector<zd>> Uh(H.Lb), Wh(H.Lb);
   for (int l = 0; l < H.Lb; ++l) {
-    Uh[l].assign((size_t)N * r, zd(0));
-    Wh[l].assign((size_t)N * r, zd(0));
+    Uh[l].assign((size_t)N * H.rank[l], zd(0));
+    Wh[l].assign((size_t)N * H.rank[l], zd(0));
   }
   std::vector<std::pair<int, int>> work;  // (level, node)
   for (int l = 0; l < H.Lb; ++l)
@@ -733,7 +754,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
       int aj = mort_a[gj], bj = mort_b[gj];
       for (int i = 0; i < m; ++i) out[i] = coef * qm[r0 + i] * W(mort_a[r0 + i] - aj, mort_b[r0 + i] - bj);
     };
-    ls::ACAResult R = ls::aca(m, n, r, 0.0, &rz, rowfn, colfn);
+    ls::ACAResult R = ls::aca(m, n, H.rank[l], 0.0, &rz, rowfn, colfn);
     int k = (int)R.u.size();
     for (int c = 0; c < k; ++c) {
       for (int i = 0; i < m; ++i) Uh[l][(size_t)c * N + r0 + i] = R.u[c][i];
@@ -747,15 +768,18 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
   for (int l = 0; l < H.Lb; ++l) {
     H.Y64[l].upload(Uh[l]);
     H.W64[l].upload(Wh[l]);
-    H.bytes += (int64_t)2 * N * r * 16;
+    H.bytes += (int64_t)2 * N * H.rank[l] * 16;
     Uh[l].clear();
     Uh[l].shrink_to_fit();
     Wh[l].clear();
     Wh[l].shrink_to_fit();
   }
   hipStream_t s = nullptr;
-  hodlr_ensure_ws(P, r);
+  int rmax = 0;
+  for (int l = 0; l < H.Lb; ++l) rmax = std::max(rmax, H.rank[l]);
+  hodlr_ensure_ws(P, std::max(rmax, 1));
   for (int l = H.Lb - 1; l >= 0; --l) {
+    const int r = H.rank[l];
     double2* Y = H.Y64[l].as<double2>();
     hodlr_apply(P, false, Y, N, Y, N, r, l + 1, s);
     int nodes = 1 << l;
@@ -777,6 +801,8 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
         }
       }
       if (!ls::invert_inplace(C, r2)) throw LsError(LS_EINVAL, "singular HODLR core");
+      for (int i = 0; i < r2; ++i)  // to column-major for the device apply
+        for (int j = i + 1; j < r2; ++j) std::swap(C[(size_t)i * r2 + j], C[(size_t)j * r2 + i]);
     });
     H.coreinv[l].upload(cores);
     H.bytes += (int64_t)cores.size() * 16;
@@ -786,6 +812,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
   H.Y32.resize(H.Lb);
   H.W32.resize(H.Lb);
   for (int l = 0; l < H.Lb; ++l) {
+    const int r = H.rank[l];
     H.Y32[l].alloc((size_t)N * r * 8);
     H.W32[l].alloc((size_t)N * r * 8);
     lsk::launch_cast(true, H.Y64[l].p, H.Y32[l].p, (long long)N * r, s);
@@ -800,6 +827,10 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
 // reorthogonalisation, Givens rotations on the host.  All vectors in Morton order.
 // ---------------------------------------------------------------------------------------
 struct GmresCfg {
+  bool flexible = false;        // keep z_j = M^{-1} q_j and update x += Z y (variable preconditioner / operator)
+  double relax = 0.0;           // > 0: use the FP32 operator once every active residual estimate is <= relax
+  bool trust_estimate = false;  // inner solves: stop on the Arnoldi residual estimate
+  bool x_zero = false;          // the initial guess is zero (skip the first product)
   bool op32 = false;     // FP32 operator
   bool pc = false;       // use the HODLR preconditioner
   bool pc32 = false;     // FP32 off-diagonal HODLR factors
@@ -811,6 +842,11 @@ struct ColState {
   double fnorm = 0, tol = 0;
   int its = 0, status = LS_MAXIT;
   bool done = false;
+  bool est_converged = false;
+  double last_est = 1.0;
+  int cycles = 0;            // Krylov cycles started, each after an FP64 true residual
+  double prev_true = 1e300;  // true residual at the previous cycle start
+  bool fell_back = false;    // relaxed (FP32) products stagnated; finished with FP64 products
   double relres = 0;
 };
 
@@ -827,7 +863,7 @@ void pc_apply(ls_problem* P, const GmresCfg& cfg, const double2* x, long long ld
     lsk::launch_axpby(1.0, x, ldx, 0.0, x, ldx, z, P->N, P->N, nrhs, s);
 }
 
-int nchunks_for(long long N) { return (int)std::max<long long>(1, std::min<long long>(512, (N + 2047) / 2048)); }
+int nchunks_for(long long N) { return (int)std::max<long long>(1, std::min<long long>(1024, (N + 1023) / 1024)); }
 
 void norms(ls_problem* P, const double2* v, int nrhs, std::vector<double>& out, hipStream_t s) {
   const long long N = P->N;
@@ -857,7 +893,10 @@ void gmres(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* x, int
   P->kpart.ensure((size_t)nrhs * nch * maxv * 16);
   P->kalpha.ensure((size_t)nrhs * 8);
   P->ky.ensure((size_t)nrhs * maxv * 16);
+  if (cfg.flexible) P->kZ.ensure((size_t)nrhs * m * N * 16);
   double2* Q = P->kQ.as<double2>();
+  double2* Zb = cfg.flexible ? P->kZ.as<double2>() : nullptr;
+  const long long ldzr = (long long)m * N;
   double2* w = P->kw.as<double2>();
   double2* z = P->kz.as<double2>();
   double2* r = P->kr.as<double2>();
@@ -869,10 +908,20 @@ void gmres(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* x, int
   std::vector<double> beta, alpha(nrhs), hnorm;
   std::vector<zd> hh((size_t)nrhs * maxv);
   std::vector<int> kcol(nrhs);
+  bool first = true;
+  bool relax_enabled = cfg.relax > 0;
   for (;;) {
+    bool all_done = true;
+    for (int c = 0; c < nrhs; ++c) all_done &= st[c].done;
+    if (all_done) return;
     // true residual r = f - A x
-    op_apply(P, cfg.op32, x, w, nrhs, s);
-    lsk::launch_axpby(1.0, f, N, -1.0, w, N, r, N, N, nrhs, s);
+    if (first && cfg.x_zero) {
+      lsk::launch_axpby(1.0, f, N, 0.0, f, N, r, N, N, nrhs, s);
+    } else {
+      op_apply(P, cfg.op32, x, w, nrhs, s);
+      lsk::launch_axpby(1.0, f, N, -1.0, w, N, r, N, N, nrhs, s);
+    }
+    first = false;
     norms(P, r, nrhs, beta, s);
     bool any = false;
     for (int c = 0; c < nrhs; ++c) {
@@ -889,6 +938,12 @@ void gmres(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* x, int
         st[c].status = LS_MAXIT;
       } else {
         any = true;
+        st[c].cycles++;
+        if (relax_enabled && st[c].cycles > 1 && beta[c] > 0.9 * st[c].prev_true) {
+          relax_enabled = false;  // FP32 products stopped reducing the true residual
+          st[c].fell_back = true;
+        }
+        st[c].prev_true = beta[c];
       }
     }
     if (!any) return;
@@ -905,10 +960,20 @@ void gmres(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* x, int
     }
     hip_check(hipMemcpyAsync(P->kalpha.p, alpha.data(), nrhs * 8, hipMemcpyHostToDevice, s), "alpha");
     lsk::launch_scale(r, N, P->kalpha.as<double>(), Q, ldqr, N, nrhs, s);
+    bool relaxed = false;
     for (int j = 0; j < m; ++j) {
-      // w = A M^{-1} q_j
-      pc_apply(P, cfg, Q + (long long)j * ldqv, ldqr, z, nrhs, s);
-      op_apply(P, cfg.op32, z, w, nrhs, s);
+      // w = A M^{-1} q_j  (flexible: z_j kept for the update)
+      if (cfg.flexible) {
+        double2* zj = Zb + (long long)j * N;
+        if (cfg.pc)
+          hodlr_apply(P, cfg.pc32, Q + (long long)j * ldqv, ldqr, zj, ldzr, nrhs, 0, s);
+        else
+          lsk::launch_axpby(1.0, Q + (long long)j * ldqv, ldqr, 0.0, Q, ldqr, zj, ldzr, N, nrhs, s);
+        fmm_apply(P, cfg.op32 || relaxed, zj, ldzr, w, N, nrhs, 1.0, P->coef, false, s);
+      } else {
+        pc_apply(P, cfg, Q + (long long)j * ldqv, ldqr, z, nrhs, s);
+        op_apply(P, cfg.op32 || relaxed, z, w, nrhs, s);
+      }
       // CGS2
       {
         ProfScope ps(P, 3, s);
@@ -961,6 +1026,8 @@ void gmres(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* x, int
         kcol[c] = j + 1;
         double est = std::abs(g[c][j + 1]) / st[c].fnorm;
         bool stop = est <= st[c].tol || st[c].its >= cfg.maxit || hnorm[c] == 0.0 || !std::isfinite(est);
+        if (est <= st[c].tol) st[c].est_converged = true;
+        st[c].last_est = est;
         if (stop) {
           active[c] = 0;
           alpha[c] = 0.0;
@@ -970,6 +1037,12 @@ void gmres(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* x, int
         }
       }
       if (!any_active || j + 1 == m) break;
+      if (relax_enabled && !relaxed) {
+        bool all_small = true;
+        for (int c = 0; c < nrhs; ++c)
+          if (active[c] && st[c].last_est > cfg.relax) all_small = false;
+        relaxed = all_small;
+      }
       hip_check(hipMemcpyAsync(P->kalpha.p, alpha.data(), nrhs * 8, hipMemcpyHostToDevice, s), "alpha");
       lsk::launch_scale(w, N, P->kalpha.as<double>(), Q + (long long)(j + 1) * ldqv, ldqr, N, nrhs, s);
     }
@@ -985,13 +1058,23 @@ void gmres(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* x, int
       }
     }
     hip_check(hipMemcpyAsync(P->ky.p, y.data(), y.size() * 16, hipMemcpyHostToDevice, s), "y h2d");
-    hip_check(hipMemsetAsync(w, 0, (size_t)nrhs * N * 16, s), "memset");
     int kmaxc = 0;
     for (int c = 0; c < nrhs; ++c) kmaxc = std::max(kmaxc, kcol[c]);
-    lsk::launch_gs_axpy(Q, ldqv, ldqr, kmaxc, P->ky.as<double2>(), maxv, 1.0, w, N, N, nrhs, s);
-    pc_apply(P, cfg, w, N, z, nrhs, s);
-    lsk::launch_axpby(1.0, x, N, 1.0, z, N, x, N, N, nrhs, s);
+    if (cfg.flexible) {
+      lsk::launch_gs_axpy(Zb, N, ldzr, kmaxc, P->ky.as<double2>(), maxv, 1.0, x, N, N, nrhs, s);
+    } else {
+      hip_check(hipMemsetAsync(w, 0, (size_t)nrhs * N * 16, s), "memset");
+      lsk::launch_gs_axpy(Q, ldqv, ldqr, kmaxc, P->ky.as<double2>(), maxv, 1.0, w, N, N, nrhs, s);
+      pc_apply(P, cfg, w, N, z, nrhs, s);
+      lsk::launch_axpby(1.0, x, N, 1.0, z, N, x, N, N, nrhs, s);
+    }
     hip_check(hipStreamSynchronize(s), "gmres cycle");
+    if (cfg.trust_estimate)
+      for (int c = 0; c < nrhs; ++c)
+        if (!st[c].done && st[c].est_converged) {
+          st[c].done = true;
+          st[c].status = LS_CONVERGED;
+        }
   }
 }
 
@@ -1059,9 +1142,10 @@ void ls_default_options(ls_options* o) {
   o->restart = 200;
   o->maxit = 2000;
   o->prec = LS_FP64;
-  o->inner_tol = 1e-6;
+  o->inner_tol = 1e-5;
   o->max_refine = 10;
   o->build_fp32 = 1;
+  o->hodlr_rank_div = 0;
 }
 
 const char* ls_last_error(void) { return g_last_error.c_str(); }
@@ -1076,6 +1160,7 @@ static void validate_options(const ls_options& o) {
   if (o.prec < 0 || o.prec > 2) throw LsError(LS_EINVAL, "prec must be LS_FP64, LS_FP32 or LS_MIXED");
   if (!(o.inner_tol > 0) || o.inner_tol >= 1) throw LsError(LS_EINVAL, "inner_tol must be in (0, 1)");
   if (o.max_refine < 1) throw LsError(LS_EINVAL, "max_refine must be >= 1");
+  if (o.hodlr_rank_div < 0) throw LsError(LS_EINVAL, "hodlr_rank_div must be >= 0");
 }
 
 ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt, ls_plan_info* out) {
@@ -1285,6 +1370,8 @@ ls_status ls_setup(const double* points, int64_t N, const double* q, double kapp
     S.entries_near = p.near_pairs * (int64_t)side * side * side * side;
     S.entries_far64 = P->f64.entries_far;
     S.entries_far32 = P->have32 ? P->f32.entries_far : 0;
+    S.entries_m2l64 = P->f64.entries_m2l;
+    S.entries_m2l32 = P->have32 ? P->f32.entries_m2l : 0;
     S.stored_bytes64 = P->f64.stored_bytes;
     S.stored_bytes32 = P->have32 ? P->f32.stored_bytes : 0;
     S.hodlr_bytes = P->hod.bytes;
@@ -1400,14 +1487,15 @@ ls_status ls_rhs_planewave(ls_problem* P, const double* angles, int nrhs, void* 
 }
 
 ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld, double tol, int x0_given,
-                   ls_solve_info* info, void* stream) {
+                   int prec_override, ls_solve_info* info, void* stream) {
   try {
     double t0 = now_ms();
     check_vec_args(P, f, psi, nrhs, ld);
     if (!(tol > 0 && tol < 1)) throw LsError(LS_EINVAL, "tol must be in (0, 1)");
     hipStream_t s = (hipStream_t)stream;
     const long long N = P->N;
-    const int prec = P->opt.prec;
+    if (prec_override < -1 || prec_override > 2) throw LsError(LS_EINVAL, "prec must be -1, LS_FP64, LS_FP32 or LS_MIXED");
+    const int prec = prec_override >= 0 ? prec_override : P->opt.prec;
     if ((prec == LS_FP32 || prec == LS_MIXED) && !P->have32) throw LsError(LS_ENOTSUP, "FP32 operator not built");
     P->kf.ensure((size_t)N * nrhs * 16);
     P->kx.ensure((size_t)N * nrhs * 16);
@@ -1462,85 +1550,18 @@ ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld
       cfg.pc32 = prec == LS_FP32;
       gmres(P, cfg, fm, xm, nrhs, st, s);
     } else {
-      // mixed: outer FP64 residual and refinement, inner FP32-operator GMRES
-      cfg.op32 = true;
+      // mixed: flexible GMRES whose products switch from the FP64 to the FP32 operator once
+      // every residual estimate is below tol / delta32 (relaxation of inexact Krylov methods),
+      // FP32 off-diagonal HODLR factors throughout; each restart recomputes the true FP64
+      // residual f - A x (iterative refinement), at most max_refine restarts.
+      cfg.op32 = false;
       cfg.pc32 = true;
-      ensure_ws(P, nrhs);
-      double2* rr = P->w_t.as<double2>();
-      double2* w = P->w_y.as<double2>();
-      std::vector<double> prev(nrhs, 1e300);
-      std::vector<int> total_its(nrhs, 0);
-      for (int outer = 0;; ++outer) {
-        op_apply(P, false, xm, w, nrhs, s);
-        lsk::launch_axpby(1.0, fm, N, -1.0, w, N, rr, N, N, nrhs, s);
-        std::vector<double> rn;
-        norms(P, rr, nrhs, rn, s);
-        std::vector<ColState> inner(nrhs);
-        bool any = false;
-        for (int c = 0; c < nrhs; ++c) {
-          if (st[c].done && outer == 0) {
-            inner[c].done = true;
-            continue;
-          }
-          double rel = rn[c] / st[c].fnorm;
-          st[c].relres = rel;
-          if (!std::isfinite(rel)) {
-            st[c].done = true;
-            st[c].status = LS_NAN;
-          } else if (rel <= tol) {
-            st[c].done = true;
-            st[c].status = LS_CONVERGED;
-          } else if (outer >= P->opt.max_refine || total_its[c] >= cfg.maxit) {
-            st[c].done = true;
-            st[c].status = LS_MAXIT;
-          } else if (outer > 0 && rn[c] > 0.9 * prev[c]) {
-            st[c].done = true;
-            st[c].status = LS_REFINE_STAGNATED;
-          }
-          prev[c] = rn[c];
-          inner[c].done = st[c].done;
-          if (!st[c].done) {
-            any = true;
-            inner[c].fnorm = rn[c];
-            inner[c].tol = std::max(P->opt.inner_tol, 0.5 * tol * st[c].fnorm / rn[c]);
-            inner[c].tol = std::min(inner[c].tol, 0.5);
-            nref[c] = outer + 1;
-          }
-        }
-        if (!any) break;
-        hip_check(hipMemsetAsync(dm, 0, (size_t)N * nrhs * 16, s), "memset");
-        GmresCfg ic = cfg;
-        ic.maxit = cfg.maxit;
-        for (int c = 0; c < nrhs; ++c) inner[c].its = 0;
-        gmres(P, ic, rr, dm, nrhs, inner, s);
-        for (int c = 0; c < nrhs; ++c) {
-          if (!st[c].done) {
-            st[c].its += inner[c].its;
-            total_its[c] += inner[c].its;
-          }
-        }
-        // x += d only for columns still iterating (others have d = 0 anyway)
-        lsk::launch_axpby(1.0, xm, N, 1.0, dm, N, xm, N, N, nrhs, s);
-      }
-      // stagnated columns: finish with the FP64 operator
-      bool fallback = false;
-      for (int c = 0; c < nrhs; ++c)
-        if (st[c].status == LS_REFINE_STAGNATED) fallback = true;
-      if (fallback) {
-        std::vector<ColState> f64st = st;
-        for (int c = 0; c < nrhs; ++c) {
-          f64st[c].done = st[c].status != LS_REFINE_STAGNATED;
-          f64st[c].its = st[c].its;
-        }
-        GmresCfg c64 = cfg;
-        c64.op32 = false;
-        c64.pc32 = false;
-        gmres(P, c64, fm, xm, nrhs, f64st, s);
-        for (int c = 0; c < nrhs; ++c)
-          if (st[c].status == LS_REFINE_STAGNATED) {
-            st[c].its = f64st[c].its;
-            st[c].status = f64st[c].status == LS_CONVERGED ? LS_REFINE_STAGNATED : f64st[c].status;
-          }
+      cfg.flexible = true;
+      cfg.relax = std::min(0.5, tol / P->opt.inner_tol);
+      gmres(P, cfg, fm, xm, nrhs, st, s);
+      for (int c = 0; c < nrhs; ++c) {
+        nref[c] = st[c].cycles;
+        if (st[c].fell_back && st[c].status == LS_CONVERGED) st[c].status = LS_REFINE_STAGNATED;
       }
     }
     // final true residual with the FP64 operator
@@ -1608,7 +1629,7 @@ void ls_destroy(ls_problem* P) {
 }
 
 ls_status ls_profile_enable(ls_problem* P, int cls, int enable) {
-  if (!P || cls < 0 || cls > 3) {
+  if (!P || cls < 0 || cls > 4) {
     g_last_error = "bad arguments";
     return LS_EINVAL;
   }
@@ -1619,7 +1640,7 @@ ls_status ls_profile_enable(ls_problem* P, int cls, int enable) {
 
 ls_status ls_profile_read(ls_problem* P, int cls, double* total_ms, int64_t* launches) {
   try {
-    if (!P || cls < 0 || cls > 3 || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
+    if (!P || cls < 0 || cls > 4 || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
     ProfileClass& pc = P->prof[cls];
     double tot = 0;
     for (size_t i = 0; i < pc.used; ++i) {

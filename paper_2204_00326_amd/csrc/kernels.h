@@ -18,7 +18,7 @@ struct DTerm {
   int cin;          // SHIFT: source class; CHILD: child class
   int sha, shb;     // SHIFT: shift in the class half-grid
   int nh_in;        // half-grid side of the input level
-  int pad;
+  int kbase;        // sum of K over the task's earlier terms
 };
 
 struct DTask {
@@ -31,14 +31,16 @@ struct DTask {
   int beta;          // 0: overwrite, 1: accumulate
   int nrb;           // row blocks = Mpad / kRowBlock
   int blk0;          // first workgroup of this task
-  int pad;
+  int ktot;          // sum of K over the task's terms
 };
 
 constexpr int kRowBlock = 8;
 constexpr int kBoxBlock = 64;
+constexpr int kStencilWaves = 4;
+constexpr int kStencilThreads = 64 * kStencilWaves;
 
-void launch_stencil(bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks, int nrhs,
-                    hipStream_t s);
+void launch_stencil(int tag, bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
+                    int nrhs, hipStream_t s);
 
 // ---- setup ----
 void launch_wtable(double2* W, int n, double h, double kappa, hipStream_t s);

@@ -1,6 +1,8 @@
 // Device kernels for gfx950 (CDNA4, wave64).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "h0.h"
 #include "kernels.h"
 
@@ -45,24 +47,65 @@ __device__ inline double2 block_sum2(double re, double im, double* red) {
 
 // =====================================================================================
 // Stencil GEMM over boxes with operators shared by all boxes of a level (DAFMM passes).
-// One thread = one box of the task's class; it accumulates kRowBlock output rows.
-// Operator entries are uniform across the wave (scalar loads); inputs are coalesced
-// along the box index of the class half-grid.
+// A workgroup owns 64 boxes of one task (one output level/direction/class) and
+// kRowBlock output rows; its 4 waves split the task's flattened (term, k) range evenly and
+// are summed in a fixed order through LDS, so results are deterministic.  Operator
+// entries are wave-uniform and read through the scalar cache; inputs are coalesced along
+// the box index of the class half-grid.
 // =====================================================================================
+// Plain aggregates for loads through address-space-qualified pointers.
+struct alignas(16) PD2 {
+  double x, y;
+};
+struct alignas(8) PF2 {
+  float x, y;
+};
 template <typename T>
-__global__ __launch_bounds__(kBoxBlock) void k_stencil(const DTask* __restrict__ tasks,
-                                                       const DTerm* __restrict__ terms,
-                                                       const int* __restrict__ blk_task) {
-  using C2 = typename V2<T>::type;
+struct P2;
+template <>
+struct P2<double> {
+  using type = PD2;
+};
+template <>
+struct P2<float> {
+  using type = PF2;
+};
+template <typename T>
+using ConstPtr = __attribute__((address_space(4))) const typename P2<T>::type*;
+template <typename T>
+using GlobalPtr = __attribute__((address_space(1))) const typename P2<T>::type*;
+template <typename T>
+__device__ inline typename P2<T>::type ldc(ConstPtr<T> p, long long i) {
+  typename P2<T>::type v;
+  v.x = p[i].x;
+  v.y = p[i].y;
+  return v;
+}
+template <typename T>
+__device__ inline typename P2<T>::type ldg(GlobalPtr<T> p, long long i) {
+  typename P2<T>::type v;
+  v.x = p[i].x;
+  v.y = p[i].y;
+  return v;
+}
+
+template <typename T, int Tag>
+__global__ __launch_bounds__(kStencilThreads) void k_stencil(const DTask* __restrict__ tasks,
+                                                             const DTerm* __restrict__ terms,
+                                                             const int* __restrict__ blk_task) {
+  using C2 = typename P2<T>::type;
+  __shared__ C2 red[kStencilWaves - 1][kRowBlock][kBoxBlock];
   const int blk = blockIdx.x;
   const int rhs = blockIdx.y;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int ti = __builtin_amdgcn_readfirstlane(blk_task[blk]);
   const DTask& tk = tasks[ti];
   const int local = blk - tk.blk0;
   const int rb = local % tk.nrb;
   const int bb = local / tk.nrb;
   const int nh = tk.nh;
-  const int box = bb * kBoxBlock + (int)threadIdx.x;
+  const int box = bb * kBoxBlock + lane;
   const bool active = box < nh * nh;
   const int ha = active ? box / nh : 0;
   const int hb = active ? box - ha * nh : 0;
@@ -74,8 +117,17 @@ __global__ __launch_bounds__(kBoxBlock) void k_stencil(const DTask* __restrict__
     ar[r] = 0;
     ai[r] = 0;
   }
-  for (int t = tk.t0; t < tk.t1; ++t) {
+  // this wave's share of the flattened (term, k) range
+  const int P = tk.ktot;
+  const int p0 = (int)(((long long)P * wave) / kStencilWaves);
+  const int p1 = (int)(((long long)P * (wave + 1)) / kStencilWaves);
+  int t = tk.t0;
+  while (t < tk.t1 && terms[t].kbase + terms[t].K <= p0) ++t;
+  for (; t < tk.t1; ++t) {
     const DTerm& tm = terms[t];
+    if (tm.kbase >= p1) break;
+    const int kb = p0 > tm.kbase ? p0 - tm.kbase : 0;
+    const int ke = (p1 - tm.kbase) < tm.K ? (p1 - tm.kbase) : tm.K;
     const int nhi = tm.nh_in;
     const long long plane = (long long)nhi * nhi;
     long long src = 0;
@@ -99,36 +151,35 @@ __global__ __launch_bounds__(kBoxBlock) void k_stencil(const DTask* __restrict__
       } break;
     }
     if (ok) {
-      const C2* __restrict__ in = reinterpret_cast<const C2*>(tm.in) + rhs * tm.in_rhs + src;
-      const C2* __restrict__ op = reinterpret_cast<const C2*>(tm.op) + m0;
+      GlobalPtr<T> in = (GlobalPtr<T>)(reinterpret_cast<const C2*>(tm.in) + rhs * tm.in_rhs + src);
+      ConstPtr<T> op = (ConstPtr<T>)(reinterpret_cast<const C2*>(tm.op) + m0);
       const long long ks = 4 * plane;
-      const int K = tm.K;
-      int k = 0;
-      for (; k + 2 <= K; k += 2) {
-        const C2 x0 = in[(long long)k * ks];
-        const C2 x1 = in[(long long)(k + 1) * ks];
-        const C2* o0 = op + (long long)k * Mpad;
-        const C2* o1 = o0 + Mpad;
+      int k = kb;
+      for (; k + 2 <= ke; k += 2) {
+        const C2 x0 = ldg<T>(in, (long long)k * ks);
+        const C2 x1 = ldg<T>(in, (long long)(k + 1) * ks);
 #pragma unroll
         for (int r = 0; r < kRowBlock; ++r) {
-          const C2 a = o0[r];
+          const C2 a = ldc<T>(op, (long long)k * Mpad + r);
           ar[r] = fma(a.x, x0.x, ar[r]);
           ar[r] = fma(-a.y, x0.y, ar[r]);
           ai[r] = fma(a.x, x0.y, ai[r]);
           ai[r] = fma(a.y, x0.x, ai[r]);
-          const C2 b = o1[r];
+        }
+#pragma unroll
+        for (int r = 0; r < kRowBlock; ++r) {
+          const C2 b = ldc<T>(op, (long long)(k + 1) * Mpad + r);
           ar[r] = fma(b.x, x1.x, ar[r]);
           ar[r] = fma(-b.y, x1.y, ar[r]);
           ai[r] = fma(b.x, x1.y, ai[r]);
           ai[r] = fma(b.y, x1.x, ai[r]);
         }
       }
-      for (; k < K; ++k) {
-        const C2 x0 = in[(long long)k * ks];
-        const C2* o0 = op + (long long)k * Mpad;
+      if (k < ke) {
+        const C2 x0 = ldg<T>(in, (long long)k * ks);
 #pragma unroll
         for (int r = 0; r < kRowBlock; ++r) {
-          const C2 a = o0[r];
+          const C2 a = ldc<T>(op, (long long)k * Mpad + r);
           ar[r] = fma(a.x, x0.x, ar[r]);
           ar[r] = fma(-a.y, x0.y, ar[r]);
           ai[r] = fma(a.x, x0.y, ai[r]);
@@ -137,7 +188,25 @@ __global__ __launch_bounds__(kBoxBlock) void k_stencil(const DTask* __restrict__
       }
     }
   }
-  if (!active) return;
+  if (wave > 0) {
+#pragma unroll
+    for (int r = 0; r < kRowBlock; ++r) {
+      C2 v;
+      v.x = ar[r];
+      v.y = ai[r];
+      red[wave - 1][r][lane] = v;
+    }
+  }
+  __syncthreads();
+  if (wave != 0 || !active) return;
+#pragma unroll
+  for (int w = 0; w < kStencilWaves - 1; ++w)
+#pragma unroll
+    for (int r = 0; r < kRowBlock; ++r) {
+      const C2 v = red[w][r][lane];
+      ar[r] += v.x;
+      ai[r] += v.y;
+    }
   C2* out = reinterpret_cast<C2*>(tk.out) + rhs * tk.out_rhs + (long long)tk.cout * nh * nh + box;
   const long long ks = 4LL * nh * nh;
 #pragma unroll
@@ -157,14 +226,26 @@ __global__ __launch_bounds__(kBoxBlock) void k_stencil(const DTask* __restrict__
   }
 }
 
-void launch_stencil(bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks, int nrhs,
-                    hipStream_t s) {
-  if (nblocks <= 0) return;
+template <int Tag>
+static void launch_stencil_t(bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
+                             int nrhs, hipStream_t s) {
   dim3 grid(nblocks, nrhs);
   if (fp32)
-    k_stencil<float><<<grid, kBoxBlock, 0, s>>>(tasks, terms, blk_task);
+    k_stencil<float, Tag><<<grid, kStencilThreads, 0, s>>>(tasks, terms, blk_task);
   else
-    k_stencil<double><<<grid, kBoxBlock, 0, s>>>(tasks, terms, blk_task);
+    k_stencil<double, Tag><<<grid, kStencilThreads, 0, s>>>(tasks, terms, blk_task);
+}
+
+void launch_stencil(int tag, bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
+                    int nrhs, hipStream_t s) {
+  if (nblocks <= 0) return;
+  switch (tag) {
+    case 0: launch_stencil_t<0>(fp32, tasks, terms, blk_task, nblocks, nrhs, s); break;
+    case 1: launch_stencil_t<1>(fp32, tasks, terms, blk_task, nblocks, nrhs, s); break;
+    case 2: launch_stencil_t<2>(fp32, tasks, terms, blk_task, nblocks, nrhs, s); break;
+    case 3: launch_stencil_t<3>(fp32, tasks, terms, blk_task, nblocks, nrhs, s); break;
+    default: launch_stencil_t<4>(fp32, tasks, terms, blk_task, nblocks, nrhs, s); break;
+  }
 }
 
 // =====================================================================================
@@ -279,6 +360,107 @@ void launch_planewave(const double* px, const double* py, const double* q, const
 }
 
 // =====================================================================================
+// Tall-skinny products  partial[(rhs*nchunks + ch)*ldp + c] = sum_{i in chunk ch} op(A_c[i]) x[i]
+// with A_c = A + c*lda + rhs*lda_rhs (column c of a column-major block), op = identity or
+// complex conjugate, for c < ncols.  A workgroup is 4 waves; each wave owns 16 columns and
+// walks the chunk's rows with its 64 lanes (coalesced), accumulating in registers; waves of
+// one column group split the rows when there are fewer than 4 groups.  One wave reduction
+// per column at the end.
+// =====================================================================================
+template <typename T, bool CONJ>
+__global__ __launch_bounds__(256) void k_tsdot(const typename V2<T>::type* __restrict__ A, long long lda,
+                                               long long lda_rhs, int ncols, const double2* __restrict__ x,
+                                               long long ldx, double2* __restrict__ partial, int ldp, long long chunk,
+                                               int nchunks, int wpg, long long nrows) {
+  constexpr int G = 16;
+  __shared__ double lds[4][2 * G];
+  const int ch = blockIdx.x, rhs = blockIdx.z;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int gpb = 4 / wpg;                           // column groups per block
+  const int grp = blockIdx.y * gpb + w / wpg;        // this wave's column group
+  const int rp = w % wpg;                            // this wave's row part
+  const int c0 = grp * G;
+  const long long i0 = (long long)ch * chunk;
+  const long long i1 = i0 + chunk < nrows ? i0 + chunk : nrows;
+  const typename V2<T>::type* Ab = A + rhs * lda_rhs;
+  const double2* xb = x + rhs * ldx;
+  double acc[2 * G];
+#pragma unroll
+  for (int c = 0; c < 2 * G; ++c) acc[c] = 0;
+  if (c0 < ncols) {
+    // columns past ncols re-read the last column (unconditional loads keep all 16 in
+    // flight); their sums are never stored
+    long long coff[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) coff[c] = (long long)(c0 + c < ncols ? c0 + c : ncols - 1) * lda;
+    for (long long i = i0 + rp * 64 + lane; i < i1; i += 64 * wpg) {
+      const double2 xv = xb[i];
+      typename V2<T>::type a[G];
+#pragma unroll
+      for (int c = 0; c < G; ++c) a[c] = Ab[coff[c] + i];
+#pragma unroll
+      for (int c = 0; c < G; ++c) {
+        const double ax = (double)a[c].x, ay = CONJ ? -(double)a[c].y : (double)a[c].y;
+        acc[2 * c] = fma(ax, xv.x, acc[2 * c]);
+        acc[2 * c] = fma(-ay, xv.y, acc[2 * c]);
+        acc[2 * c + 1] = fma(ax, xv.y, acc[2 * c + 1]);
+        acc[2 * c + 1] = fma(ay, xv.x, acc[2 * c + 1]);
+      }
+      // schedule all G + 1 loads of the row before its FMAs (memory-level parallelism)
+      __builtin_amdgcn_sched_group_barrier(0x0020, G + 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x0002, 8 * G, 0);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 2 * G; ++c) acc[c] = wave_sum(acc[c]);
+  if (wpg > 1) {
+    if (lane == 0)
+#pragma unroll
+      for (int c = 0; c < 2 * G; ++c) lds[w][c] = acc[c];
+    __syncthreads();
+    if (rp != 0) return;
+    for (int q = 1; q < wpg; ++q)
+#pragma unroll
+      for (int c = 0; c < 2 * G; ++c) acc[c] += lds[w + q][c];
+  }
+  if (c0 >= ncols) return;
+  if (lane < G && c0 + lane < ncols) {
+    double re = 0, im = 0;
+#pragma unroll
+    for (int c = 0; c < G; ++c)
+      if (c == lane) {
+        re = acc[2 * c];
+        im = acc[2 * c + 1];
+      }
+    partial[((long long)rhs * nchunks + ch) * ldp + c0 + lane] = make_double2(re, im);
+  }
+}
+
+static void tsdot(bool fp32, bool conj, const void* A, long long lda, long long lda_rhs, int ncols, const double2* x,
+                  long long ldx, double2* partial, int ldp, long long chunk, int nchunks, long long nrows, int nrhs,
+                  hipStream_t s) {
+  const int groups = (ncols + 15) / 16;
+  const int wpg = groups >= 4 ? 1 : (groups == 1 ? 4 : 2);
+  const int gpb = 4 / wpg;
+  dim3 grid(nchunks, (groups + gpb - 1) / gpb, nrhs);
+  if (fp32) {
+    if (conj)
+      k_tsdot<float, true><<<grid, 256, 0, s>>>((const float2*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk,
+                                               nchunks, wpg, nrows);
+    else
+      k_tsdot<float, false><<<grid, 256, 0, s>>>((const float2*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk,
+                                                nchunks, wpg, nrows);
+  } else {
+    if (conj)
+      k_tsdot<double, true><<<grid, 256, 0, s>>>((const double2*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk,
+                                                nchunks, wpg, nrows);
+    else
+      k_tsdot<double, false><<<grid, 256, 0, s>>>((const double2*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp,
+                                                 chunk, nchunks, wpg, nrows);
+  }
+}
+
+// =====================================================================================
 // HODLR apply: leaf solves, then per binary level  z -= Y core^{-1} (W^T z).
 // =====================================================================================
 __global__ __launch_bounds__(64) void k_leaf_apply(const double2* __restrict__ Dinv,
@@ -314,80 +496,73 @@ void launch_leaf_apply(const double2* Dinv, const unsigned char* ident, const do
 }
 
 // partial[(rhs*nchunks + chunk)*r + c] = sum_{i in chunk} W[c*N + i] z[i]
-template <typename T>
-__global__ __launch_bounds__(256) void k_hodlr_dot(const typename V2<T>::type* __restrict__ W,
-                                                   const double2* __restrict__ z, long long ldz,
-                                                   double2* __restrict__ partial, long long N, int r, long long chunk,
-                                                   int nchunks) {
-  __shared__ double red[32];
-  const int ch = blockIdx.x, rhs = blockIdx.y;
-  const long long i0 = (long long)ch * chunk;
-  for (int c = 0; c < r; ++c) {
-    double re = 0, im = 0;
-    for (long long i = i0 + threadIdx.x; i < i0 + chunk; i += blockDim.x) {
-      const typename V2<T>::type w = W[(long long)c * N + i];
-      const double2 x = z[rhs * ldz + i];
-      re += (double)w.x * x.x - (double)w.y * x.y;
-      im += (double)w.x * x.y + (double)w.y * x.x;
-    }
-    const double2 sum = block_sum2(re, im, red);
-    if (threadIdx.x == 0) partial[((long long)rhs * nchunks + ch) * r + c] = sum;
-  }
-}
-
 void launch_hodlr_dot(bool fp32, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
                       long long chunk, int nchunks, int nrhs, hipStream_t s) {
-  dim3 grid(nchunks, nrhs);
-  int nt = chunk >= 256 ? 256 : (int)((chunk + 63) / 64) * 64;
-  if (fp32)
-    k_hodlr_dot<float><<<grid, nt, 0, s>>>((const float2*)W, z, ldz, partial, N, r, chunk, nchunks);
-  else
-    k_hodlr_dot<double><<<grid, nt, 0, s>>>((const double2*)W, z, ldz, partial, N, r, chunk, nchunks);
+  tsdot(fp32, false, W, N, 0, r, z, ldz, partial, r, chunk, nchunks, N, nrhs, s);
 }
 
 // t = [t_A; t_B]: t_A from the chunks of the second child (rows paired with Q), t_B from
-// the first child (rows paired with S).  apply: s = coreinv * t, else s = t.
-__global__ __launch_bounds__(64) void k_hodlr_core(const double2* __restrict__ partial,
-                                                   const double2* __restrict__ coreinv, double2* __restrict__ sout,
-                                                   int r, int nodes, int cpc, int nchunks, int apply) {
+// the first child (rows paired with S).  apply: s = coreinv * t, else s = t.  256 threads per
+// node: thread (i, h) handles entry i and half h of the summation range; LDS combines.
+__global__ __launch_bounds__(256) void k_hodlr_core(const double2* __restrict__ partial,
+                                                    const double2* __restrict__ coreinv, double2* __restrict__ sout,
+                                                    int r, int nodes, int cpc, int nchunks, int apply) {
   __shared__ double2 t[128];
+  __shared__ double2 part[128];
   const int node = blockIdx.x, rhs = blockIdx.y;
   const int r2 = 2 * r;
-  for (int i = threadIdx.x; i < r2; i += blockDim.x) {
+  const int i = threadIdx.x & 127, h = threadIdx.x >> 7;
+  double tre = 0, tim = 0;
+  if (i < r2) {
     const int half = i < r ? 1 : 0;  // t_A sums the second child
     const int c = i < r ? i : i - r;
     const long long ch0 = (long long)node * 2 * cpc + (long long)half * cpc;
-    double re = 0, im = 0;
-    for (int k = 0; k < cpc; ++k) {
+    const int k0 = h * ((cpc + 1) >> 1), k1 = h ? cpc : ((cpc + 1) >> 1);
+    for (int k = k0; k < k1; ++k) {
       const double2 v = partial[((long long)rhs * nchunks + ch0 + k) * r + c];
-      re += v.x;
-      im += v.y;
+      tre += v.x;
+      tim += v.y;
     }
-    t[i] = make_double2(re, im);
+  }
+  if (h && i < r2) part[i] = make_double2(tre, tim);
+  __syncthreads();
+  if (!h && i < r2) {
+    const double2 o = part[i];
+    t[i] = make_double2(tre + o.x, tim + o.y);
   }
   __syncthreads();
   double2* so = sout + ((long long)rhs * nodes + node) * r2;
   if (!apply) {
-    for (int i = threadIdx.x; i < r2; i += blockDim.x) so[i] = t[i];
+    if (!h && i < r2) so[i] = t[i];
     return;
   }
-  const double2* Ci = coreinv + (long long)node * r2 * r2;
-  for (int i = threadIdx.x; i < r2; i += blockDim.x) {
-    double re = 0, im = 0;
-    for (int j = 0; j < r2; ++j) {
-      const double2 a = Ci[(long long)i * r2 + j];
+  const double2* Ci = coreinv + (long long)node * r2 * r2;  // column-major: entry (i, j) at j * r2 + i
+  double re = 0, im = 0;
+  if (i < r2) {
+    const int j0 = h * r, j1 = h ? r2 : r;
+#pragma unroll 4
+    for (int j = j0; j < j1; ++j) {
+      const double2 a = Ci[(long long)j * r2 + i];
       const double2 x = t[j];
-      re += a.x * x.x - a.y * x.y;
-      im += a.x * x.y + a.y * x.x;
+      re = fma(a.x, x.x, re);
+      re = fma(-a.y, x.y, re);
+      im = fma(a.x, x.y, im);
+      im = fma(a.y, x.x, im);
     }
-    so[i] = make_double2(re, im);
+  }
+  __syncthreads();
+  if (h && i < r2) part[i] = make_double2(re, im);
+  __syncthreads();
+  if (!h && i < r2) {
+    const double2 o = part[i];
+    so[i] = make_double2(re + o.x, im + o.y);
   }
 }
 
 void launch_hodlr_core(const double2* partial, const double2* coreinv, double2* sout, int r, int nodes,
                        int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s) {
   dim3 grid(nodes, nrhs);
-  k_hodlr_core<<<grid, 64, 0, s>>>(partial, coreinv, sout, r, nodes, chunks_per_child, nchunks, apply ? 1 : 0);
+  k_hodlr_core<<<grid, 256, 0, s>>>(partial, coreinv, sout, r, nodes, chunks_per_child, nchunks, apply ? 1 : 0);
 }
 
 // z[i] -= sum_c Y[c*N + i] * s[node][half*r + c]
@@ -403,11 +578,26 @@ __global__ __launch_bounds__(256) void k_hodlr_update(const typename V2<T>::type
   const int half = (i - node * nodesize) >= (nodesize >> 1) ? 1 : 0;
   const double2* s = sv + ((long long)rhs * nodes + node) * 2 * r + half * r;
   double re = 0, im = 0;
-  for (int c = 0; c < r; ++c) {
-    const typename V2<T>::type y = Y[(long long)c * N + i];
-    const double2 x = s[c];
-    re += (double)y.x * x.x - (double)y.y * x.y;
-    im += (double)y.x * x.y + (double)y.y * x.x;
+  for (int c0 = 0; c0 < r; c0 += 8) {
+    // unconditional loads (clamped column, zero weight past r) keep 8 loads in flight
+    typename V2<T>::type y[8];
+    double2 x[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int cc = c0 + c < r ? c0 + c : r - 1;
+      y[c] = Y[(long long)cc * N + i];
+      x[c] = s[cc];
+      if (c0 + c >= r) x[c] = make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      re = fma((double)y[c].x, x[c].x, re);
+      re = fma(-(double)y[c].y, x[c].y, re);
+      im = fma((double)y[c].x, x[c].y, im);
+      im = fma((double)y[c].y, x[c].x, im);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x0020, 16, 0);
+    __builtin_amdgcn_sched_group_barrier(0x0002, 40, 0);
   }
   double2 o = z[rhs * ldz + i];
   o.x -= re;
@@ -428,57 +618,41 @@ void launch_hodlr_update(bool fp32, const void* Y, const double2* sv, double2* z
 // Krylov (Arnoldi) kernels: classical Gram-Schmidt dot products and updates.
 // =====================================================================================
 // partial[(rhs*nchunks + chunk)*maxv + v] = sum_{i in chunk} conj(Q_v[i]) w[i]
-__global__ __launch_bounds__(256) void k_gs_dot(const double2* __restrict__ Q, long long ldq_vec, long long ldq_rhs,
-                                                int nv, const double2* __restrict__ w, long long ldw,
-                                                double2* __restrict__ partial, long long N, int nchunks, int maxv) {
-  __shared__ double red[32];
-  const int ch = blockIdx.x, rhs = blockIdx.y;
-  const long long per = (N + nchunks - 1) / nchunks;
-  const long long i0 = (long long)ch * per;
-  const long long i1 = i0 + per < N ? i0 + per : N;
-  const double2* wr = w + rhs * ldw;
-  for (int v = 0; v < nv; ++v) {
-    const double2* q = Q + rhs * ldq_rhs + v * ldq_vec;
-    double re = 0, im = 0;
-    for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-      const double2 a = q[i], x = wr[i];
-      re += a.x * x.x + a.y * x.y;
-      im += a.x * x.y - a.y * x.x;
-    }
-    const double2 sum = block_sum2(re, im, red);
-    if (threadIdx.x == 0) partial[((long long)rhs * nchunks + ch) * maxv + v] = sum;
-  }
-}
-
 void launch_gs_dot(const double2* Q, long long ldq_vec, long long ldq_rhs, int nv, const double2* w, long long ldw,
                    double2* partial, long long N, int nchunks, int maxv, int nrhs, hipStream_t s) {
-  dim3 grid(nchunks, nrhs);
-  k_gs_dot<<<grid, 256, 0, s>>>(Q, ldq_vec, ldq_rhs, nv, w, ldw, partial, N, nchunks, maxv);
+  const long long chunk = (N + nchunks - 1) / nchunks;  // the last chunk is clipped at N
+  tsdot(false, true, Q, ldq_vec, ldq_rhs, nv, w, ldw, partial, maxv, chunk, nchunks, N, nrhs, s);
 }
 
-__global__ void k_gs_finish(const double2* __restrict__ partial, int nchunks, int nv, int maxv, double2* h,
-                            int accumulate) {
+// h[rhs*maxv + v] (+)= sum_c partial[(rhs*nchunks + c)*maxv + v]; one wave per value
+__global__ __launch_bounds__(256) void k_gs_finish(const double2* __restrict__ partial, int nchunks, int nv, int maxv,
+                                                   double2* h, int accumulate) {
   const int rhs = blockIdx.y;
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (v >= nv) return;
   double re = 0, im = 0;
-  for (int c = 0; c < nchunks; ++c) {
+  for (int c = lane; c < nchunks; c += 64) {
     const double2 p = partial[((long long)rhs * nchunks + c) * maxv + v];
     re += p.x;
     im += p.y;
   }
-  double2* o = h + (long long)rhs * maxv + v;
-  if (accumulate) {
-    re += o->x;
-    im += o->y;
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane == 0) {
+    double2* o = h + (long long)rhs * maxv + v;
+    if (accumulate) {
+      re += o->x;
+      im += o->y;
+    }
+    *o = make_double2(re, im);
   }
-  *o = make_double2(re, im);
 }
 
 void launch_gs_finish(const double2* partial, int nchunks, int nv, int maxv, double2* h, int accumulate, int nrhs,
                       hipStream_t s) {
-  dim3 grid((nv + 63) / 64, nrhs);
-  k_gs_finish<<<grid, 64, 0, s>>>(partial, nchunks, nv, maxv, h, accumulate);
+  dim3 grid((nv + 3) / 4, nrhs);
+  k_gs_finish<<<grid, 256, 0, s>>>(partial, nchunks, nv, maxv, h, accumulate);
 }
 
 // w[i] += sign * sum_v Q_v[i] h[v]

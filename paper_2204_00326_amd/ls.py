@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libls.so")
 LS_OK, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_ENOTSUP = 0, -1, -2, -3, -4
 LS_FP64, LS_FP32, LS_MIXED = 0, 1, 2
 STATUS = {0: "CONVERGED", 1: "MAXIT", 2: "BREAKDOWN", 3: "NAN", 4: "REFINE_STAGNATED", 5: "WARMSTART_REJECTED"}
-PROFILE_CLASSES = {"near_m2l": 0, "hodlr_update": 1, "leaf_solve": 2, "gs_dot": 3}
+PROFILE_CLASSES = {"near_m2l64": 0, "hodlr_update": 1, "leaf_solve": 2, "gs_dot": 3, "near_m2l32": 4}
 
 
 class LsError(RuntimeError):
@@ -30,7 +30,8 @@ class LsError(RuntimeError):
 class _Options(C.Structure):
     _fields_ = [("leaf_max", C.c_int), ("T", C.c_double), ("sign", C.c_int), ("hodlr_rank", C.c_int),
                 ("eps_inner", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("prec", C.c_int),
-                ("inner_tol", C.c_double), ("max_refine", C.c_int), ("build_fp32", C.c_int)]
+                ("inner_tol", C.c_double), ("max_refine", C.c_int), ("build_fp32", C.c_int),
+                ("hodlr_rank_div", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -42,6 +43,7 @@ class _Stats(C.Structure):
     _fields_ = [("N", C.c_int64), ("n", C.c_int), ("levels", C.c_int), ("leaf_side", C.c_int),
                 ("top_level", C.c_int), ("nlevels_hf", C.c_int), ("rank_max64", C.c_int), ("rank_max32", C.c_int),
                 ("entries_near", C.c_int64), ("entries_far64", C.c_int64), ("entries_far32", C.c_int64),
+                ("entries_m2l64", C.c_int64), ("entries_m2l32", C.c_int64),
                 ("m2l_pairs", C.c_int64), ("stored_bytes64", C.c_int64), ("stored_bytes32", C.c_int64),
                 ("hodlr_bytes", C.c_int64), ("t_plan_ms", C.c_double), ("t_nca_ms", C.c_double),
                 ("t_hodlr_ms", C.c_double), ("t_setup_ms", C.c_double)]
@@ -72,7 +74,7 @@ def lib():
     for name in ("ls_matvec", "ls_apply_V", "ls_precond_apply"):
         getattr(L, name).argtypes = [vp, vp, vp, ci, i64, ci, vp]
     L.ls_rhs_planewave.argtypes = [vp, vp, ci, vp, i64, vp]
-    L.ls_solve.argtypes = [vp, vp, vp, ci, i64, cd, ci, C.POINTER(_Info), vp]
+    L.ls_solve.argtypes = [vp, vp, vp, ci, i64, cd, ci, ci, C.POINTER(_Info), vp]
     L.ls_stats.argtypes = [vp, C.POINTER(_Stats)]
     L.ls_destroy.argtypes = [vp]
     L.ls_destroy.restype = None
@@ -102,9 +104,10 @@ class Options:
     restart: int = 200
     maxit: int = 2000
     prec: int = LS_FP64
-    inner_tol: float = 1e-6
+    inner_tol: float = 1e-5
     max_refine: int = 10
     build_fp32: int = 1
+    hodlr_rank_div: int = 0
 
     def _c(self) -> _Options:
         o = _Options()
@@ -216,14 +219,14 @@ class Problem:
         _check(lib().ls_rhs_planewave(self._h, ang.ctypes.data, nrhs, f.data_ptr(), self.N, _stream(stream)))
         return f
 
-    def solve(self, f, psi=None, tol: float = 1e-8, x0: bool = False, stream=None):
+    def solve(self, f, psi=None, tol: float = 1e-8, x0: bool = False, prec: int = -1, stream=None):
         import torch
         nrhs = _vec(f, self.N)
         if psi is None:
             psi = torch.zeros_like(f)
         infos = (_Info * nrhs)()
         _check(lib().ls_solve(self._h, f.data_ptr(), psi.data_ptr(), nrhs, self.N, float(tol), int(bool(x0)),
-                              infos, _stream(stream)))
+                              int(prec), infos, _stream(stream)))
         out = [{"iters": i.iters, "relres": i.relres, "status": STATUS.get(i.status, str(i.status)),
                 "n_refine": i.n_refine, "t_solve_ms": i.t_solve_ms} for i in infos]
         return psi, out
