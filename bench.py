@@ -44,10 +44,12 @@ def cpu_baseline(n, kappa, q, seconds=20.0):
     Vop = lsop.FFTApplyV(n, 1.0, kappa, workers=cores)
     f = lsop.rhs_planewave(n, 1.0, kappa, q, 0.0)
     A = lambda v: lsop.apply_A(Vop, v, q, kappa)
+    # size the sample: a short probe run, then the MGS cost model t(n) ~ n^2 for the budget
+    n1 = 20
     t0 = time.perf_counter()
-    A(f)
-    t_mv = time.perf_counter() - t0
-    nit = max(5, int(seconds / (2.5 * t_mv)))
+    og.gmres(A, f, 1e-8, restart=200, maxit=n1)
+    t1 = time.perf_counter() - t0
+    nit = int(max(n1, min(200, n1 * math.sqrt(max(seconds, t1) / t1))))
     t1 = time.perf_counter()
     _, its, hist = og.gmres(A, f, 1e-8, restart=200, maxit=nit)
     t_run = time.perf_counter() - t1
@@ -155,33 +157,38 @@ def main():
         rates[name] = 1e3 / float(np.median(ts))
     log("matvec/s", rates)
 
-    # roofline of the dominant kernel class over the timed region
+    # roofline of the dominant kernel class over the timed region: achieved = algorithmic
+    # bytes (or flops) of all timed launches / their summed event time
     N = n * n
     r = args.rank
+    rs, lb = st["hodlr_rank_sum"], st["hodlr_levels"]
+    nap_u = prof["hodlr_update"][1] / max(lb, 1)   # preconditioner applies (one update launch per level)
     work = {
-        "near_m2l64": ("alu", "f64", 8.0 * (st["entries_near"] + st["entries_m2l64"]) / 1e12),
-        "near_m2l32": ("alu", "f32", 8.0 * (st["entries_near"] + st["entries_m2l32"]) / 1e12),
-        # FP32 Y factor of one level (N x r complex64) + z read and written (complex128)
-        "hodlr_update": ("hbm", None, (N * r * 8 + 2 * N * 16) / 1e9),
+        # flops of one near-field + M2L launch (8 real flops per complex multiply-add)
+        "near_m2l64": ("alu", "f64", 8.0 * (st["entries_near"] + st["entries_m2l64"]) * prof["near_m2l64"][1] / 1e12),
+        "near_m2l32": ("alu", "f32", 8.0 * (st["entries_near"] + st["entries_m2l32"]) * prof["near_m2l32"][1] / 1e12),
+        # per apply: complex64 Y of every level (N x r_l) + z read and written per level (complex128)
+        "hodlr_update": ("hbm", None, nap_u * (N * rs * 8 + lb * 2 * N * 16) / 1e9),
+        # per apply: complex64 W of every level + z read per level
+        "hodlr_dot": ("hbm", None, nap_u * (N * rs * 8 + lb * N * 16) / 1e9),
     }
     cand = {c: prof[c] for c in work if prof[c][1] > 0}
     dom = max(cand, key=lambda c: cand[c][0])
     tot_ms, launches = cand[dom]
-    avg_s = tot_ms / launches / 1e3
     bound, dt, amount = work[dom]
+    achieved = amount / (tot_ms / 1e3)
     if bound == "hbm":
-        achieved = amount / avg_s
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
     else:
-        achieved = amount / avg_s
         peak = VALU_PEAK_TFLOPS[dt]
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None}
-    roof["kernel"] = {"near_m2l64": "k_stencil<double> (near field + M2L launch)",
-                      "near_m2l32": "k_stencil<float> (near field + M2L launch)",
-                      "hodlr_update": "k_hodlr_update<float>"}[dom]
-    roof["avg_launch_us"] = round(avg_s * 1e6, 2)
+    roof["kernel"] = {"near_m2l64": "k_stencil<double,0> (near field + M2L launch)",
+                      "near_m2l32": "k_stencil<float,0> (near field + M2L launch)",
+                      "hodlr_update": "k_hodlr_update<float>",
+                      "hodlr_dot": "k_tsdot<float,false> (HODLR W^T z)"}[dom]
+    roof["avg_launch_us"] = round(tot_ms / launches * 1e3, 2)
     roof["launches"] = launches
     roof["class_ms"] = {c: round(v[0], 3) for c, v in prof.items()}
 

@@ -109,6 +109,9 @@ typedef struct {
   int64_t stored_bytes64; /* device bytes of the FP64 DAFMM operators */
   int64_t stored_bytes32;
   int64_t hodlr_bytes;    /* device bytes of the HODLR factors */
+  int hodlr_levels;       /* binary levels above the HODLR leaves */
+  int hodlr_rank_sum;     /* sum over binary levels of the off-diagonal rank */
+  int64_t hodlr_dense_leaves; /* leaves whose diagonal block is not the identity */
   double t_plan_ms, t_nca_ms, t_hodlr_ms, t_setup_ms;
 } ls_stats_t;
 
@@ -185,7 +188,7 @@ ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt,
 /* Kernel timing with HIP events recorded around every launch of one kernel class on
  * the launch stream: class 0 = near field + M2L launch (FP64 operator), 1 = HODLR level
  * update, 2 = HODLR leaf solve, 3 = Arnoldi dot products, 4 = near field + M2L launch
- * (FP32 operator).  enable = 1 starts (and clears) the
+ * (FP32 operator), 5 = HODLR level dot products (W^T z).  enable = 1 starts (and clears) the
  * counters, 0 stops.  ls_profile_read synchronises and returns the summed event time
  * and the number of timed launches. */
 ls_status ls_profile_enable(ls_problem* P, int kernel_class, int enable);

@@ -151,6 +151,7 @@ struct FmmDev {
 
 struct HodlrDev {
   int r = 0, Lb = 0, nleaves = 0, lp = 0;
+  int64_t dense_leaves = 0;
   std::vector<int> rank;  // per binary level
   long long N = 0;
   DevBuf Dinv, ident;
@@ -187,7 +188,7 @@ struct ls_problem {
   DevBuf w_x, w_y, w_t;  // Morton-order vectors (nrhs_cap)
   int ws_cap = 0;
   ls_stats_t stats{};
-  ProfileClass prof[5];
+  ProfileClass prof[6];
   // Krylov workspace
   DevBuf kQ, kZ, kw, kz, kr, kh, kpart, knp, kno, kalpha, ky, kx, kf, kdx;
   size_t kcap_key = 0;
@@ -658,7 +659,10 @@ void hodlr_apply(ls_problem* P, bool fp32, const double2* b, long long ldb, doub
     int nodes = 1 << l;
     const int rl = H.rank[l];
     if (rl == 0) continue;
-    lsk::launch_hodlr_dot(fp32, W, z, ldz, H.partial.as<double2>(), H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s);
+    {
+      ProfScope pd(P, 5, s);
+      lsk::launch_hodlr_dot(fp32, W, z, ldz, H.partial.as<double2>(), H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s);
+    }
     lsk::launch_hodlr_core(H.partial.as<double2>(), H.coreinv[l].as<double2>(), H.svec.as<double2>(), rl, nodes,
                            H.cpc[l], H.nchunks[l], true, nrhs, s);
     ProfScope ps(P, 1, s);
@@ -707,6 +711,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
   });
   H.Dinv.upload(Dinv);
   H.ident.upload(ident);
+  for (unsigned char v : ident) H.dense_leaves += v ? 0 : 1;
   H.bytes = (int64_t)Dinv.size() * 16;
   Dinv.clear();
   Dinv.shrink_to_fit();
@@ -1375,6 +1380,9 @@ ls_status ls_setup(const double* points, int64_t N, const double* q, double kapp
     S.stored_bytes64 = P->f64.stored_bytes;
     S.stored_bytes32 = P->have32 ? P->f32.stored_bytes : 0;
     S.hodlr_bytes = P->hod.bytes;
+    S.hodlr_levels = P->have_hodlr ? P->hod.Lb : 0;
+    for (int l = 0; P->have_hodlr && l < P->hod.Lb; ++l) S.hodlr_rank_sum += P->hod.rank[l];
+    S.hodlr_dense_leaves = P->have_hodlr ? P->hod.dense_leaves : 0;
     S.t_plan_ms = t_plan - t0;
     S.t_nca_ms = t_nca - t_w;
     S.t_hodlr_ms = t_h - t_nca;
@@ -1629,7 +1637,7 @@ void ls_destroy(ls_problem* P) {
 }
 
 ls_status ls_profile_enable(ls_problem* P, int cls, int enable) {
-  if (!P || cls < 0 || cls > 4) {
+  if (!P || cls < 0 || cls > 5) {
     g_last_error = "bad arguments";
     return LS_EINVAL;
   }
@@ -1640,7 +1648,7 @@ ls_status ls_profile_enable(ls_problem* P, int cls, int enable) {
 
 ls_status ls_profile_read(ls_problem* P, int cls, double* total_ms, int64_t* launches) {
   try {
-    if (!P || cls < 0 || cls > 4 || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
+    if (!P || cls < 0 || cls > 5 || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
     ProfileClass& pc = P->prof[cls];
     double tot = 0;
     for (size_t i = 0; i < pc.used; ++i) {

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libls.so")
 LS_OK, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_ENOTSUP = 0, -1, -2, -3, -4
 LS_FP64, LS_FP32, LS_MIXED = 0, 1, 2
 STATUS = {0: "CONVERGED", 1: "MAXIT", 2: "BREAKDOWN", 3: "NAN", 4: "REFINE_STAGNATED", 5: "WARMSTART_REJECTED"}
-PROFILE_CLASSES = {"near_m2l64": 0, "hodlr_update": 1, "leaf_solve": 2, "gs_dot": 3, "near_m2l32": 4}
+PROFILE_CLASSES = {"near_m2l64": 0, "hodlr_update": 1, "leaf_solve": 2, "gs_dot": 3, "near_m2l32": 4,
+                   "hodlr_dot": 5}
 
 
 class LsError(RuntimeError):
@@ -45,7 +46,8 @@ class _Stats(C.Structure):
                 ("entries_near", C.c_int64), ("entries_far64", C.c_int64), ("entries_far32", C.c_int64),
                 ("entries_m2l64", C.c_int64), ("entries_m2l32", C.c_int64),
                 ("m2l_pairs", C.c_int64), ("stored_bytes64", C.c_int64), ("stored_bytes32", C.c_int64),
-                ("hodlr_bytes", C.c_int64), ("t_plan_ms", C.c_double), ("t_nca_ms", C.c_double),
+                ("hodlr_bytes", C.c_int64), ("hodlr_levels", C.c_int), ("hodlr_rank_sum", C.c_int),
+                ("hodlr_dense_leaves", C.c_int64), ("t_plan_ms", C.c_double), ("t_nca_ms", C.c_double),
                 ("t_hodlr_ms", C.c_double), ("t_setup_ms", C.c_double)]
 
 
