@@ -89,6 +89,7 @@ typedef struct {
                          residual, the column was finished with FP64 products and converged) */
   int n_refine;       /* LS_MIXED: Krylov cycles, each started from an FP64 residual f - A x */
   double t_solve_ms;  /* wall time of the call */
+  double relres0;     /* ||f - A x0|| / ||f|| of the start GMRES used (1 for a zero start) */
 } ls_solve_info;
 
 typedef struct {
@@ -164,9 +165,12 @@ ls_status ls_rhs_planewave(ls_problem* P, const double* angles, int nrhs, void* 
 /* Solve A psi = f for nrhs columns by restarted GMRES with right HODLR preconditioning
  * (when hodlr_rank > 0), stopping when ||f - A psi|| / ||f|| <= tol per column.
  * prec: LS_FP64, LS_FP32, LS_MIXED, or -1 for the precision given in the options.
- * f, psi: device, N x nrhs complex128.  x0_given != 0: psi holds the initial guess (a
- * guess whose residual is not below ||f|| is replaced by zero, status bit
- * LS_WARMSTART_REJECTED reported in info[j].status when the column otherwise converged).
+ * f, psi: device, N x nrhs complex128.  x0_given != 0: psi holds the initial guess g.
+ * GMRES starts from x0 = xi g with the minimal-residual scale xi = (A g)^H f / ||A g||^2
+ * (Hegedus' scaling of an initial guess; costs one FP64 operator product), so that
+ * ||f - A x0|| <= ||f||.  A guess that cannot lower the residual (A g orthogonal to f,
+ * or non-finite) is replaced by zero, and LS_WARMSTART_REJECTED is reported in
+ * info[j].status when the column otherwise converged.
  * info: host array of nrhs entries (may be NULL).  Synchronous on `stream`. */
 ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld, double tol,
                    int x0_given, int prec, ls_solve_info* info, void* stream);
@@ -193,6 +197,57 @@ ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt,
  * and the number of timed launches. */
 ls_status ls_profile_enable(ls_problem* P, int kernel_class, int enable);
 ls_status ls_profile_read(ls_problem* P, int kernel_class, double* total_ms, int64_t* launches);
+
+/* ---------------------------------------------------------------------------------------
+ * Learned GMRES warm start (an extension; the paper has no learned component).
+ * A small FNO-style neural operator on the n x n grid image (grid order, image[a][b] = point
+ * a*n + b): lift 6 -> width, `layers` x (truncated-DFT spectral convolution with `modes`
+ * modes per axis + 1x1 convolution + bias, exact GELU except after the last layer),
+ * projection width -> 2.  Inputs X: [B][6][n][n] float (q, cos and sin of the WKB phase
+ * kappa d.x + phi, kappa/60, x1, x2); output O: [B][2][n][n] float, the complex envelope of
+ * the solution relative to the WKB start b = f exp(i phi): psi0 = b (1 + O_re + i O_im).
+ * phi(x) = kappa h sum_{k<2n} g(x - (k + 1/2) h d), g = sqrt(max(1 + q, 0)) - 1 bilinear
+ * between cell centres and zero outside, d = (cos theta, sin theta): the phase the local
+ * wavenumber kappa sqrt(1 + q) adds along the straight incoming ray (midpoint rule).
+ * All buffers are DEVICE pointers owned by the caller unless stated; FP32 parameters.
+ * Errors: LS_EINVAL on bad sizes or NULL pointers, LS_EDEVICE on a failed launch.
+ * --------------------------------------------------------------------------------------- */
+typedef struct ls_nop ls_nop;
+typedef struct {
+  int n;              /* grid side (>= 8) */
+  int width;          /* channels (<= 256) */
+  int modes;          /* Fourier modes per axis, 2*modes <= n */
+  int layers;         /* spectral layers */
+  int batch_max;      /* largest batch B passed to forward */
+  uint64_t seed;      /* parameter initialisation */
+} ls_nop_config;
+
+ls_status ls_nop_create(const ls_nop_config* cfg, ls_nop** out);
+int64_t ls_nop_param_count(const ls_nop* N);
+/* host copies of the flat parameter / gradient vectors (count = ls_nop_param_count);
+ * set_params also clears the Adam state */
+ls_status ls_nop_get_params(const ls_nop* N, float* host, int64_t count);
+ls_status ls_nop_set_params(ls_nop* N, const float* host, int64_t count);
+ls_status ls_nop_get_grads(const ls_nop* N, float* host, int64_t count);
+/* O = NO(X) for B samples; keeps the activations for ls_nop_backward */
+ls_status ls_nop_forward(ls_nop* N, const float* X, float* O, int B, void* stream);
+/* parameter gradients (overwritten) of sum(dO * O) for the last forward */
+ls_status ls_nop_backward(ls_nop* N, const float* dO, void* stream);
+/* per-sample loss_b = |w O_c - t|^2 / snorm2_b and dO = d(mean_b loss_b)/dO; w, t: [B][n][n]
+ * complex64 with w = b/kappa^2, t = (psi - b)/kappa^2 (b the WKB start); snorm2: [B] float
+ * (|psi/kappa^2|^2) */
+ls_status ls_nop_loss(ls_nop* N, const float* O, const void* w, const void* t, const float* snorm2, int B, float* dO,
+                      float* loss, void* stream);
+/* one Adam update of all parameters with the gradients of the last backward */
+ls_status ls_nop_adam_step(ls_nop* N, float lr, float beta1, float beta2, float eps, void* stream);
+/* X[6][n][n] from q (device, n*n doubles, grid order) on the cell-centred grid of [-L, L]^2 */
+ls_status ls_nop_features(int n, double L, const double* q, double kappa, double theta, float* X, void* stream);
+/* psi0 = f exp(i phi) (1 + O_re + i O_im) for one sample; q: device n*n doubles; O: device
+ * [2][n][n] float or NULL (then psi0 = f exp(i phi), the WKB start alone); f, psi0: device
+ * complex128, grid order */
+ls_status ls_nop_warmstart(int n, double L, const double* q, double kappa, double theta, const float* O,
+                           const void* f, void* psi0, void* stream);
+void ls_nop_destroy(ls_nop* N);
 
 #ifdef __cplusplus
 }

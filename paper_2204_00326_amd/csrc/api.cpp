@@ -26,6 +26,14 @@ namespace {
 
 thread_local std::string g_last_error;
 
+}  // namespace
+
+namespace ls {
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace ls
+
+namespace {
+
 double now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
@@ -1520,25 +1528,47 @@ ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld
       st[c].fnorm = fn[c] > 0 ? fn[c] : 1.0;
       st[c].tol = tol;
     }
+    std::vector<double> rel0(nrhs, 1.0);
     if (x0_given) {
       lsk::launch_permute((const double2*)psi, ld, xm, N, P->m2c.as<int>(), N, nrhs, false, s);
-      // reject a guess whose residual is not below ||f||
+      // minimal-residual scaling of the guess g: x0 = xi g, xi = (A g)^H f / ||A g||^2, which
+      // leaves ||f - A x0||^2 = ||f||^2 - |(A g)^H f|^2 / ||A g||^2
       ensure_ws(P, nrhs);
       double2* w = P->w_y.as<double2>();
       op_apply(P, false, xm, w, nrhs, s);
-      lsk::launch_axpby(1.0, fm, N, -1.0, w, N, w, N, N, nrhs, s);
-      std::vector<double> rn;
-      norms(P, w, nrhs, rn, s);
-      std::vector<double> keep(nrhs);
-      bool any_rej = false;
+      std::vector<double> an;
+      norms(P, w, nrhs, an, s);
+      const int nch = nchunks_for(N);
+      P->kpart.ensure((size_t)nrhs * nch * 16);
+      P->kh.ensure((size_t)nrhs * 16);
+      double2* part = P->kpart.as<double2>();
+      double2* hd = P->kh.as<double2>();
+      lsk::launch_gs_dot(w, N, N, 1, fm, N, part, N, nch, 1, nrhs, s);
+      lsk::launch_gs_finish(part, nch, 1, 1, hd, 0, nrhs, s);
+      std::vector<zd> dot(nrhs);
+      hip_check(hipMemcpyAsync(dot.data(), hd, nrhs * 16, hipMemcpyDeviceToHost, s), "dot d2h");
+      hip_check(hipStreamSynchronize(s), "sync");
+      std::vector<zd> xi(nrhs, zd(0));
       for (int c = 0; c < nrhs; ++c) {
-        bool bad = !(rn[c] < fn[c]) || !std::isfinite(rn[c]);
-        warm_rejected[c] = bad;
-        any_rej |= bad;
+        const double a2 = an[c] * an[c];
+        const double drop = a2 > 0 ? std::norm(dot[c]) / a2 : 0.0;
+        const bool ok = std::isfinite(a2) && std::isfinite(drop) && a2 > 0 && fn[c] > 0 && drop > 1e-24 * fn[c] * fn[c];
+        if (ok) xi[c] = dot[c] / a2;
+        warm_rejected[c] = !ok;
       }
-      if (any_rej)
-        for (int c = 0; c < nrhs; ++c)
-          if (warm_rejected[c]) hip_check(hipMemsetAsync(xm + (long long)c * N, 0, N * 16, s), "memset");
+      hip_check(hipMemcpyAsync(hd, xi.data(), nrhs * 16, hipMemcpyHostToDevice, s), "xi h2d");
+      // starting residual f - xi A g (reported), then x0 = xi g
+      lsk::launch_axpby(1.0, fm, N, 0.0, fm, N, dm, N, N, nrhs, s);
+      lsk::launch_gs_axpy(w, N, N, 1, hd, 1, -1.0, dm, N, N, nrhs, s);
+      std::vector<double> r0;
+      norms(P, dm, nrhs, r0, s);
+      for (int c = 0; c < nrhs; ++c)
+        if (!warm_rejected[c]) rel0[c] = r0[c] / fn[c];
+      hip_check(hipMemsetAsync(w, 0, (size_t)N * nrhs * 16, s), "memset");
+      lsk::launch_gs_axpy(xm, N, N, 1, hd, 1, 1.0, w, N, N, nrhs, s);
+      lsk::launch_axpby(1.0, w, N, 0.0, w, N, xm, N, N, nrhs, s);
+      for (int c = 0; c < nrhs; ++c)
+        if (warm_rejected[c]) hip_check(hipMemsetAsync(xm + (long long)c * N, 0, N * 16, s), "memset");
     } else {
       hip_check(hipMemsetAsync(xm, 0, (size_t)N * nrhs * 16, s), "memset");
     }
@@ -1590,6 +1620,7 @@ ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld
         if (warm_rejected[c] && st[c].status == LS_CONVERGED) info[c].status = LS_WARMSTART_REJECTED;
         info[c].n_refine = nref[c];
         info[c].t_solve_ms = t1 - t0;
+        info[c].relres0 = fn[c] > 0 ? rel0[c] : 0.0;
       }
     return LS_OK;
   } catch (const LsError& e) {

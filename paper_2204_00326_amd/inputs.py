@@ -139,3 +139,14 @@ def problem_queue(seed: int = 2, count: int = 16) -> list[Problem]:
         p = grid_points(n, 1.0)
         out.append(Problem(f"queue{j}_n{n}_k{kappa:g}", n, 1.0, kappa, contrast_bumps(p, bumps)))
     return out
+
+
+def problem_learned(seed: int, n: int = 128, angles: int = 1, L: float = 1.0) -> Problem:
+    """Warm-start training/evaluation problem: kappa ~ U[20, 60], 1..8 Gaussian bumps, then
+    `angles` incidence angles ~ U[0, 2 pi), all drawn from default_rng(seed) in that order."""
+    rng = np.random.default_rng(seed)
+    kappa = float(rng.uniform(20.0, 60.0))
+    bumps = draw_bumps(rng)
+    thetas = rng.uniform(0.0, 2.0 * math.pi, size=angles)
+    p = grid_points(n, L)
+    return Problem(f"learned{n}_s{seed}", n, L, kappa, contrast_bumps(p, bumps), np.asarray(thetas))

@@ -37,7 +37,7 @@ class _Options(C.Structure):
 
 class _Info(C.Structure):
     _fields_ = [("iters", C.c_int), ("relres", C.c_double), ("status", C.c_int), ("n_refine", C.c_int),
-                ("t_solve_ms", C.c_double)]
+                ("t_solve_ms", C.c_double), ("relres0", C.c_double)]
 
 
 class _Stats(C.Structure):
@@ -55,6 +55,11 @@ class _PlanInfo(C.Structure):
     _fields_ = [("levels", C.c_int), ("leaf_side", C.c_int), ("top_level", C.c_int), ("hf", C.c_int * 32),
                 ("ndir", C.c_int * 32), ("max_il", C.c_int * 32), ("il_pairs", C.c_int64 * 32),
                 ("near_pairs", C.c_int64), ("coverage_min", C.c_int), ("coverage_max", C.c_int)]
+
+
+class _NopConfig(C.Structure):
+    _fields_ = [("n", C.c_int), ("width", C.c_int), ("modes", C.c_int), ("layers", C.c_int),
+                ("batch_max", C.c_int), ("seed", C.c_uint64)]
 
 
 _lib = None
@@ -84,6 +89,23 @@ def lib():
     L.ls_green_table.argtypes = [ci, cd, cd, vp, vp]
     L.ls_profile_enable.argtypes = [vp, ci, ci]
     L.ls_profile_read.argtypes = [vp, ci, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.ls_nop_create.argtypes = [C.POINTER(_NopConfig), C.POINTER(vp)]
+    L.ls_nop_param_count.argtypes = [vp]
+    L.ls_nop_param_count.restype = C.c_int64
+    for name in ("ls_nop_get_params", "ls_nop_set_params", "ls_nop_get_grads"):
+        getattr(L, name).argtypes = [vp, vp, i64]
+        getattr(L, name).restype = C.c_int
+    L.ls_nop_forward.argtypes = [vp, vp, vp, ci, vp]
+    L.ls_nop_backward.argtypes = [vp, vp, vp]
+    L.ls_nop_loss.argtypes = [vp, vp, vp, vp, vp, ci, vp, vp, vp]
+    L.ls_nop_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+    L.ls_nop_features.argtypes = [ci, cd, vp, cd, cd, vp, vp]
+    L.ls_nop_warmstart.argtypes = [ci, cd, vp, cd, cd, vp, vp, vp, vp]
+    L.ls_nop_destroy.argtypes = [vp]
+    L.ls_nop_destroy.restype = None
+    for name in ("ls_nop_create", "ls_nop_forward", "ls_nop_backward", "ls_nop_loss", "ls_nop_adam_step",
+                 "ls_nop_features", "ls_nop_warmstart"):
+        getattr(L, name).restype = C.c_int
     for name in ("ls_setup", "ls_matvec", "ls_apply_V", "ls_precond_apply", "ls_rhs_planewave", "ls_solve",
                  "ls_stats", "ls_plan_describe", "ls_profile_enable", "ls_profile_read", "ls_green_table"):
         getattr(L, name).restype = C.c_int
@@ -230,7 +252,8 @@ class Problem:
         _check(lib().ls_solve(self._h, f.data_ptr(), psi.data_ptr(), nrhs, self.N, float(tol), int(bool(x0)),
                               int(prec), infos, _stream(stream)))
         out = [{"iters": i.iters, "relres": i.relres, "status": STATUS.get(i.status, str(i.status)),
-                "n_refine": i.n_refine, "t_solve_ms": i.t_solve_ms} for i in infos]
+                "n_refine": i.n_refine, "t_solve_ms": i.t_solve_ms,
+                "relres0": i.relres0} for i in infos]
         return psi, out
 
     def stats(self) -> dict:
@@ -247,3 +270,90 @@ class Problem:
         _check(lib().ls_profile_read(self._h, PROFILE_CLASSES[cls], C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
+
+
+class NeuralOperator:
+    """Handle of the learned warm-start network (ls_nop_*).  Tensors are float32 CUDA tensors."""
+
+    def __init__(self, n: int, width: int = 32, modes: int = 16, layers: int = 4, batch_max: int = 16,
+                 seed: int = 0):
+        cfg = _NopConfig(n, width, modes, layers, batch_max, seed)
+        h = C.c_void_p()
+        _check(lib().ls_nop_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        self.n, self.width, self.modes, self.layers, self.batch_max = n, width, modes, layers, batch_max
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().ls_nop_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nparams(self) -> int:
+        return int(lib().ls_nop_param_count(self._h))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.nparams, dtype=np.float32)
+        _check(lib().ls_nop_get_params(self._h, out.ctypes.data, out.size))
+        return out
+
+    def set_params(self, flat: np.ndarray):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(lib().ls_nop_set_params(self._h, a.ctypes.data, a.size))
+
+    def get_grads(self) -> np.ndarray:
+        out = np.empty(self.nparams, dtype=np.float32)
+        _check(lib().ls_nop_get_grads(self._h, out.ctypes.data, out.size))
+        return out
+
+    def forward(self, X, O=None, stream=None):
+        import torch
+        B = X.shape[0]
+        if O is None:
+            O = torch.empty((B, 2, self.n, self.n), dtype=torch.float32, device=X.device)
+        _check(lib().ls_nop_forward(self._h, X.data_ptr(), O.data_ptr(), B, _stream(stream)))
+        return O
+
+    def backward(self, dO, stream=None):
+        _check(lib().ls_nop_backward(self._h, dO.data_ptr(), _stream(stream)))
+
+    def loss(self, O, w, t, snorm2, stream=None):
+        """w, t: complex64 [B, n, n] (w = f/kappa^2, t = (psi - f)/kappa^2); snorm2: float32 [B]."""
+        import torch
+        B = O.shape[0]
+        dO = torch.empty_like(O)
+        lb = torch.empty(B, dtype=torch.float32, device=O.device)
+        _check(lib().ls_nop_loss(self._h, O.data_ptr(), w.data_ptr(), t.data_ptr(), snorm2.data_ptr(), B,
+                                 dO.data_ptr(), lb.data_ptr(), _stream(stream)))
+        return lb, dO
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
+        _check(lib().ls_nop_adam_step(self._h, lr, beta1, beta2, eps, _stream(stream)))
+
+
+def nop_features(n: int, L: float, q_dev, kappa: float, theta: float, X=None, stream=None):
+    """6-channel input image of one problem (q_dev: float64 CUDA tensor of n*n values, grid order)."""
+    import torch
+    if X is None:
+        X = torch.empty((6, n, n), dtype=torch.float32, device=q_dev.device)
+    _check(lib().ls_nop_features(n, float(L), q_dev.data_ptr(), float(kappa), float(theta), X.data_ptr(),
+                                 _stream(stream)))
+    return X
+
+
+def nop_warmstart(n: int, L: float, q_dev, kappa: float, theta: float, O, f, psi0=None, stream=None):
+    """psi0 = f exp(i phi) (1 + O_re + i O_im) for one problem (grid order); O=None gives the
+    WKB start f exp(i phi) alone."""
+    import torch
+    if psi0 is None:
+        psi0 = torch.empty_like(f)
+    _check(lib().ls_nop_warmstart(n, float(L), q_dev.data_ptr(), float(kappa), float(theta),
+                                  None if O is None else O.data_ptr(), f.data_ptr(), psi0.data_ptr(),
+                                  _stream(stream)))
+    return psi0

@@ -1,0 +1,163 @@
+"""GPU parity of the neural-operator kernels (ls_nop_*) against the FP64 oracle, and a
+training/warm-start check: FP32 forward within 1e-4 and gradients within 2e-3 (relative L2
+per parameter group) of the oracle; the trained network must reduce GMRES iterations."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lsop
+from oracle import nop as onop
+from paper_2204_00326_amd import inputs, ls
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ls.lib()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_flat(p, layers):
+    parts = [p["P"].ravel(), p["p"]]
+    for l in range(layers):
+        R = p[f"R{l}"]
+        parts += [np.stack([R.real, R.imag], axis=-1).ravel(), p[f"W{l}"].ravel(), p[f"b{l}"]]
+    parts += [p["Q"].ravel(), p["q"]]
+    return np.concatenate([np.asarray(x, dtype=np.float64).ravel() for x in parts])
+
+
+def from_flat(flat, width, modes, layers, nin=6, nout=2):
+    out, o = {}, 0
+
+    def take(shape):
+        nonlocal o
+        k = int(np.prod(shape))
+        v = flat[o:o + k].reshape(shape)
+        o += k
+        return v
+
+    out["P"] = take((width, nin))
+    out["p"] = take((width,))
+    for l in range(layers):
+        r = take((width, width, 2 * modes, modes, 2))
+        out[f"R{l}"] = r[..., 0] + 1j * r[..., 1]
+        out[f"W{l}"] = take((width, width))
+        out[f"b{l}"] = take((width,))
+    out["Q"] = take((nout, width))
+    out["q"] = take((nout,))
+    assert o == flat.size
+    return out
+
+
+def setup_case(n=32, width=8, modes=4, layers=3, B=2, seed=5):
+    rng = np.random.default_rng(seed)
+    p = onop.init_params(6, width, modes, layers, seed=seed)
+    for k in p:
+        if p[k].dtype == complex:
+            p[k] = p[k] * 20
+        elif k in ("p", "q") or k.startswith("b"):
+            p[k] = 0.1 * rng.standard_normal(p[k].shape)
+    X = rng.standard_normal((B, 6, n, n))
+    q = rng.random((B, n, n))
+    t = rng.standard_normal((B, n, n)) + 1j * rng.standard_normal((B, n, n))
+    s = t + 0.3
+    net = ls.NeuralOperator(n, width, modes, layers, batch_max=B)
+    net.set_params(to_flat(p, layers).astype(np.float32))
+    return net, p, X, q, t, s, layers, modes
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_forward_loss_backward_match_oracle():
+    net, p, X, q, t, s, layers, modes = setup_case()
+    q = q * np.exp(1j * X[:, 1])          # complex loss weight
+    O_ref, cache = onop.forward(p, X, layers, modes)
+    L_ref, dO_ref = onop.loss(O_ref, q, t, s)
+    g_ref = onop.backward(p, cache, dO_ref, layers, modes)
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    O = net.forward(Xd)
+    assert rel(O.cpu().numpy(), O_ref) < 1e-4
+    qd = torch.from_numpy(q.astype(np.complex64)).cuda()
+    td = torch.from_numpy(t.astype(np.complex64)).cuda()
+    sn = torch.from_numpy((np.abs(s) ** 2).sum(axis=(1, 2)).astype(np.float32)).cuda()
+    lb, dO = net.loss(O, qd, td, sn)
+    assert abs(float(lb.mean()) - L_ref) < 1e-4 * L_ref
+    assert rel(dO.cpu().numpy(), dO_ref) < 1e-4
+    net.backward(dO)
+    g = from_flat(net.get_grads().astype(np.float64), net.width, net.modes, net.layers)
+    for k in g_ref:
+        say(k, rel(g[k], g_ref[k]))
+        assert rel(g[k], g_ref[k]) < 2e-3, k
+
+
+def test_adam_step_matches_formula():
+    net, p, X, q, t, s, layers, modes = setup_case(B=1)
+    p0 = net.get_params().astype(np.float64)
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    O = net.forward(Xd)
+    dO = torch.ones_like(O) * 1e-3
+    net.backward(dO)
+    g = net.get_grads().astype(np.float64)
+    net.adam_step(1e-2, 0.9, 0.999, 1e-8)
+    p1 = net.get_params().astype(np.float64)
+    m = 0.1 * g / (1 - 0.9)
+    v = 0.001 * g * g / (1 - 0.999)
+    ref = p0 - 1e-2 * m / (np.sqrt(v) + 1e-8)
+    assert np.max(np.abs(p1 - ref)) < 1e-5
+
+
+def test_features_and_warmstart_kernels():
+    n, L, kappa = 32, 1.0, 25.0
+    pb = inputs.problem_bumps(n, kappa, seed=4, count=5)
+    q = pb.q
+    qd = torch.from_numpy(q).cuda()
+    for theta in (0.7, 2.9, -1.3):
+        phi = onop.ray_phase(n, L, q, kappa, theta)
+        X = ls.nop_features(n, L, qd, kappa, theta).cpu().numpy()
+        Xr = onop.features(n, L, q, kappa, theta, phi)
+        # FP32 channels of phases up to ~kappa * 2.8
+        assert np.max(np.abs(X - Xr)) < 2e-5, theta
+        O = torch.randn(1, 2, n, n, device="cuda")
+        f = torch.from_numpy(lsop.rhs_planewave(n, L, kappa, q, theta)).cuda()
+        fh = f.cpu().numpy()
+        psi0 = ls.nop_warmstart(n, L, qd, kappa, theta, O[0], f).cpu().numpy()
+        ref = onop.warm_start(fh, phi, O[0].double().cpu().numpy())
+        assert np.max(np.abs(psi0 - ref)) < 1e-10 * np.max(np.abs(ref)), theta
+        b = ls.nop_warmstart(n, L, qd, kappa, theta, None, f).cpu().numpy()
+        assert np.max(np.abs(b - fh * np.exp(1j * phi))) < 1e-10 * np.max(np.abs(fh)), theta
+
+
+def test_training_reduces_loss():
+    # teacher-student: targets produced by another network of the same shape are learnable
+    net, p, X, q, t, s, layers, modes = setup_case(B=4, seed=9)
+    teacher = onop.init_params(6, 8, modes, layers, seed=21)
+    for k in teacher:
+        if teacher[k].dtype == complex:
+            teacher[k] = teacher[k] * 20
+    Ot, _ = onop.forward(teacher, X, layers, modes)
+    t = q * (Ot[:, 0] + 1j * Ot[:, 1])
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    qd = torch.from_numpy(q.astype(np.complex64)).cuda()
+    td = torch.from_numpy(t.astype(np.complex64)).cuda()
+    sn = torch.from_numpy((np.abs(t) ** 2).sum(axis=(1, 2)).astype(np.float32)).cuda()
+    losses = []
+    for it in range(150):
+        O = net.forward(Xd)
+        lb, dO = net.loss(O, qd, td, sn)
+        losses.append(float(lb.mean()))
+        net.backward(dO)
+        net.adam_step(5e-3)
+    say("loss", losses[0], losses[-1])
+    assert losses[-1] < 0.3 * losses[0]

@@ -225,10 +225,22 @@ def test_solve_zero_rhs_and_warm_start():
     psi, info = P.solve(f, tol=1e-10)
     psi2, info2 = P.solve(f, psi=psi.clone(), tol=1e-8, x0=True)
     assert info2[0]["iters"] == 0 and info2[0]["status"] == "CONVERGED"
-    garbage = torch.full_like(f, 1e6)
-    psi3, info3 = P.solve(f, psi=garbage, tol=1e-8, x0=True)
-    assert info3[0]["status"] == "WARMSTART_REJECTED"
+    assert info2[0]["relres0"] < 1e-9
+    # a poor guess is scaled by xi = (A g)^H f / ||A g||^2 (checked with an independent product)
+    g = torch.full_like(f, 1e6)
+    Ag = P.matvec(g)
+    xi = torch.vdot(Ag, f) / torch.vdot(Ag, Ag).real
+    expect = float(torch.linalg.vector_norm(f - xi * Ag) / torch.linalg.vector_norm(f))
+    psi3, info3 = P.solve(f, psi=g.clone(), tol=1e-8, x0=True)
+    assert info3[0]["status"] == "CONVERGED"
+    assert abs(info3[0]["relres0"] - expect) < 1e-6 * expect and expect < 1.0
     assert rel(host(psi3), host(psi)) < 1e-6
+    # a guess that cannot lower the residual is replaced by zero
+    psi4, info4 = P.solve(f, psi=torch.full_like(f, float("nan")), tol=1e-8, x0=True)
+    assert info4[0]["status"] == "WARMSTART_REJECTED" and info4[0]["relres0"] == 1.0
+    assert rel(host(psi4), host(psi)) < 1e-6
+    psi5, info5 = P.solve(f, psi=torch.zeros_like(f), tol=1e-8, x0=True)
+    assert info5[0]["status"] == "WARMSTART_REJECTED"
 
 
 def test_solve_bumps256_full_size():
