@@ -78,6 +78,10 @@ typedef struct {
   int build_fp32;     /* build the FP32 operator at setup (default 1) */
   int hodlr_rank_div; /* 0 (default): rank hodlr_rank at every HODLR level, as in the paper;
                          d > 0: rank min(hodlr_rank, child block size / d) per level */
+  int graph_iters;    /* > 0: GMRES iterations run as device-driven Arnoldi steps (Arnoldi index,
+                         Givens rotations and stop test on the device), captured into a HIP graph of
+                         this many iterations and replayed, one host synchronisation per replay;
+                         0: one host round trip per iteration (default 0) */
 } ls_options;
 
 typedef struct {
@@ -174,6 +178,32 @@ ls_status ls_rhs_planewave(ls_problem* P, const double* angles, int nrhs, void* 
  * info: host array of nrhs entries (may be NULL).  Synchronous on `stream`. */
 ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld, double tol,
                    int x0_given, int prec, ls_solve_info* info, void* stream);
+
+/* Queue of independent problems (Section 5's solver applied to each): solves
+ * A_p psi_p = f_p for p < nprob, one right-hand side each, from a zero start, to
+ * ||f_p - A_p psi_p|| / ||f_p|| <= tol.  Problems are taken largest first by `nworkers` host
+ * threads (0 = 4), each driving its own HIP stream (default priority); every solve uses the
+ * graph-captured GMRES driver with `graph_iters` Arnoldi steps per graph (0 = 8) and runs
+ * ls_autotune on a problem not tuned before.  prec as in ls_solve (-1 = each problem's
+ * options).  probs, f, psi, info: host arrays of nprob entries; f[p], psi[p] are device
+ * vectors of N_p complex128 in problem p's point order.  A problem may appear once.
+ * Synchronous.  Errors: LS_EINVAL for bad arguments; the first error of any problem is
+ * returned (the others still run); per-problem results in info[p]. */
+ls_status ls_solve_queue(ls_problem* const* probs, int nprob, const void* const* f, void* const* psi, double tol,
+                         int prec, int nworkers, int graph_iters, ls_solve_info* info);
+
+/* Launch-shape autotuner: times the Arnoldi reductions (dot products of 32 basis vectors and a
+ * norm) for 128/256/512/1024/2048 rows per workgroup chunk, and the HODLR preconditioner apply
+ * for at most 64/128/256/512/1024 rows per level-reduction chunk, on this problem's sizes, and
+ * keeps the fastest of each for all later calls on P.  out (may be NULL) receives the choices
+ * and the measured times.  Synchronous on `stream`. */
+typedef struct {
+  int gs_rows;       /* chosen rows per chunk, Arnoldi reductions */
+  int hodlr_rows;    /* chosen max rows per chunk, HODLR level reductions */
+  double gs_us[5];   /* microseconds per candidate 128, 256, 512, 1024, 2048 */
+  double pc_us[5];   /* microseconds per candidate 64, 128, 256, 512, 1024 (0 without HODLR) */
+} ls_tune_info;
+ls_status ls_autotune(ls_problem* P, ls_tune_info* out, void* stream);
 
 /* Table of V entries for grid offsets (Section 1 Green's function, Eq. (eq:13) at p = 1):
  * out[(da + n-1) * (2n-1) + (db + n-1)] = h^2 (i/4) H0^(1)(kappa h |(da, db)|) for (da, db) != 0 and

@@ -170,6 +170,33 @@ struct HodlrDev {
   int64_t bytes = 0;
 };
 
+// Device-driven GMRES of one problem: control words, Hessenberg and rotations in device
+// memory, and the captured graphs of graph_iters Arnoldi steps (FP64 / FP32 operator).
+struct KrylovDev {
+  DevBuf ictl;    // int: [0] = j, then state[nrhs], its[nrhs], kfin[nrhs]
+  DevBuf dctl;    // double: fnorm[nrhs], tol[nrhs], est[nrhs], alpha[nrhs]
+  DevBuf H, cs, sn, g, vin, tmp;
+  int* host = nullptr;  // pinned mirror of ictl (plus est as doubles after it)
+  size_t host_bytes = 0;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  std::vector<uintptr_t> key[2];
+  KrylovDev() = default;
+  KrylovDev(const KrylovDev&) = delete;
+  KrylovDev& operator=(const KrylovDev&) = delete;
+  void drop(int v) {
+    if (exec[v]) (void)hipGraphExecDestroy(exec[v]);
+    exec[v] = nullptr;
+    key[v].clear();
+  }
+  ~KrylovDev() {
+    drop(0);
+    drop(1);
+    if (host) (void)hipHostFree(host);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
 struct ProfileClass {
   bool enabled = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -200,6 +227,13 @@ struct ls_problem {
   // Krylov workspace
   DevBuf kQ, kZ, kw, kz, kr, kh, kpart, knp, kno, kalpha, ky, kx, kf, kdx;
   size_t kcap_key = 0;
+  KrylovDev kd;
+  bool capturing = false;  // launches are being recorded into a graph (no event timers)
+  struct {
+    int gs_rows = 1024;    // rows per chunk of the Arnoldi reductions
+    int hodlr_rows = 512;  // max rows per chunk of the HODLR level reductions
+    bool done = false;
+  } tune;
 };
 
 namespace {
@@ -212,7 +246,7 @@ struct ProfScope {
   hipStream_t s;
   hipEvent_t e1 = nullptr;
   ProfScope(ls_problem* P, int cls, hipStream_t st) : pc(&P->prof[cls]), s(st) {
-    if (!pc->enabled) {
+    if (!pc->enabled || P->capturing) {
       pc = nullptr;
       return;
     }
@@ -679,6 +713,23 @@ void hodlr_apply(ls_problem* P, bool fp32, const double2* b, long long ldb, doub
   hip_check(hipGetLastError(), "hodlr kernels");
 }
 
+// chunking of the binary levels for the W^T z reductions: chunks tile every child block
+// exactly and hold at most max_rows rows where the block size allows
+void hodlr_chunks(HodlrDev& H, long long max_rows) {
+  const long long N = H.N;
+  H.chunk.assign(H.Lb, 0);
+  H.nchunks.assign(H.Lb, 0);
+  H.cpc.assign(H.Lb, 0);
+  for (int l = 0; l < H.Lb; ++l) {
+    long long cs = N >> (l + 1);
+    long long ch = cs;
+    while (ch > max_rows && ch % 2 == 0) ch /= 2;
+    H.chunk[l] = ch;
+    H.nchunks[l] = (int)(N / ch);
+    H.cpc[l] = (int)(cs / ch);
+  }
+}
+
 void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mort_a, const std::vector<int>& mort_b,
                  const std::vector<double>& qm) {
   HodlrDev& H = P->hod;
@@ -723,18 +774,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
   H.bytes = (int64_t)Dinv.size() * 16;
   Dinv.clear();
   Dinv.shrink_to_fit();
-  // chunking of the binary levels
-  H.chunk.assign(H.Lb, 0);
-  H.nchunks.assign(H.Lb, 0);
-  H.cpc.assign(H.Lb, 0);
-  for (int l = 0; l < H.Lb; ++l) {
-    long long cs = N >> (l + 1);  // child size; chunks must tile it exactly
-    long long ch = cs;
-    while (ch > 512 && ch % 2 == 0) ch /= 2;
-    H.chunk[l] = ch;
-    H.nchunks[l] = (int)(N / ch);
-    H.cpc[l] = (int)(cs / ch);
-  }
+  hodlr_chunks(H, P->tune.hodlr_rows);
   // off-diagonal ACA at fixed rank (rows with q = 0 are known zero)
   H.rank.assign(H.Lb, r);
   if (P->opt.hodlr_rank_div > 0)
@@ -876,11 +916,15 @@ void pc_apply(ls_problem* P, const GmresCfg& cfg, const double2* x, long long ld
     lsk::launch_axpby(1.0, x, ldx, 0.0, x, ldx, z, P->N, P->N, nrhs, s);
 }
 
-int nchunks_for(long long N) { return (int)std::max<long long>(1, std::min<long long>(1024, (N + 1023) / 1024)); }
+// row chunks of the Arnoldi reductions (rows per chunk chosen by ls_autotune, default 1024)
+int nchunks_for(const ls_problem* P) {
+  const long long rows = std::max(1, P->tune.gs_rows);
+  return (int)std::max<long long>(1, std::min<long long>(1024, (P->N + rows - 1) / rows));
+}
 
 void norms(ls_problem* P, const double2* v, int nrhs, std::vector<double>& out, hipStream_t s) {
   const long long N = P->N;
-  int nch = nchunks_for(N);
+  int nch = nchunks_for(P);
   P->knp.ensure((size_t)nch * nrhs * 8);
   P->kno.ensure((size_t)nrhs * 8);
   lsk::launch_norm2(v, N, P->knp.as<double>(), N, nch, nrhs, s);
@@ -897,7 +941,7 @@ void gmres(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* x, int
   const long long N = P->N;
   const int m = std::max(1, cfg.restart);
   const int maxv = m + 1;
-  const int nch = nchunks_for(N);
+  const int nch = nchunks_for(P);
   P->kQ.ensure((size_t)nrhs * maxv * N * 16);
   P->kw.ensure((size_t)nrhs * N * 16);
   P->kz.ensure((size_t)nrhs * N * 16);
@@ -1091,6 +1135,308 @@ void gmres(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* x, int
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// GMRES with device-driven Arnoldi steps, graph_iters of them captured into one HIP graph.
+// Same method as gmres() above (right preconditioning, CGS2, Givens, restarts from the true
+// residual, flexible variant with precision relaxation); the Arnoldi index, the rotations and
+// the stop test live on the device, so the host synchronises once per replay instead of
+// once per iteration.  Steps replayed after a column has stopped leave it untouched.
+// ---------------------------------------------------------------------------------------
+struct KdView {
+  long long N;
+  int nrhs, m, maxv, nch;
+  int *jd, *state, *its, *kfin;
+  double *fnorm, *tol, *est, *alpha;
+};
+
+KdView kd_view(ls_problem* P, int nrhs, int m) {
+  KdView v;
+  v.N = P->N;
+  v.nrhs = nrhs;
+  v.m = m;
+  v.maxv = m + 1;
+  v.nch = nchunks_for(P);
+  int* ic = P->kd.ictl.as<int>();
+  v.jd = ic;
+  v.state = ic + 1;
+  v.its = ic + 1 + nrhs;
+  v.kfin = ic + 1 + 2 * nrhs;
+  double* dc = P->kd.dctl.as<double>();
+  v.fnorm = dc;
+  v.tol = dc + nrhs;
+  v.est = dc + 2 * nrhs;
+  v.alpha = dc + 3 * nrhs;
+  return v;
+}
+
+void kd_ensure(ls_problem* P, const GmresCfg& cfg, int nrhs) {
+  const long long N = P->N;
+  const int m = std::max(1, cfg.restart), maxv = m + 1, nch = nchunks_for(P);
+  P->kQ.ensure((size_t)nrhs * maxv * N * 16);
+  if (cfg.flexible) P->kZ.ensure((size_t)nrhs * m * N * 16);
+  P->kw.ensure((size_t)nrhs * N * 16);
+  P->kz.ensure((size_t)nrhs * N * 16);
+  P->kr.ensure((size_t)nrhs * N * 16);
+  P->kpart.ensure((size_t)nrhs * nch * maxv * 16);
+  P->knp.ensure((size_t)nch * nrhs * 8);
+  P->ky.ensure((size_t)nrhs * maxv * 16);
+  P->kalpha.ensure((size_t)nrhs * 8);
+  KrylovDev& K = P->kd;
+  K.ictl.ensure((size_t)(1 + 3 * nrhs) * 4);
+  K.dctl.ensure((size_t)4 * nrhs * 8);
+  K.H.ensure((size_t)nrhs * m * maxv * 16);
+  K.cs.ensure((size_t)nrhs * m * 8);
+  K.sn.ensure((size_t)nrhs * m * 16);
+  K.g.ensure((size_t)nrhs * maxv * 16);
+  K.vin.ensure((size_t)nrhs * N * 16);
+  K.tmp.ensure((size_t)nrhs * maxv * 16);
+  const size_t hb = (size_t)(1 + 3 * nrhs) * 4 + 8 + (size_t)nrhs * 8;
+  if (K.host_bytes < hb) {
+    if (K.host) hip_check(hipHostFree(K.host), "hipHostFree");
+    K.host = nullptr;
+    K.host_bytes = 0;
+    hip_check(hipHostMalloc((void**)&K.host, hb, hipHostMallocDefault), "hipHostMalloc");
+    K.host_bytes = hb;
+  }
+  ensure_fmm_capacity(P, P->f64, nrhs);
+  if (P->have32) ensure_fmm_capacity(P, P->f32, nrhs);
+  if (P->have_hodlr) hodlr_ensure_ws(P, nrhs);
+  if (!K.cap) hip_check(hipStreamCreateWithFlags(&K.cap, hipStreamNonBlocking), "hipStreamCreate");
+}
+
+void kd_key_phase(std::vector<uintptr_t>& k, const Phase& ph) {
+  k.push_back((uintptr_t)ph.tasks.p);
+  k.push_back((uintptr_t)ph.terms.p);
+  k.push_back((uintptr_t)ph.blk.p);
+}
+
+void kd_key_fmm(std::vector<uintptr_t>& k, const FmmDev& F) {
+  for (const DevBuf* b : {&F.ops, &F.mult, &F.loc, &F.xs, &F.ys}) k.push_back((uintptr_t)b->p);
+  k.push_back((uintptr_t)F.nrhs_cap);
+  kd_key_phase(k, F.p2m);
+  kd_key_phase(k, F.nearm2l);
+  kd_key_phase(k, F.l2p);
+  for (const Phase& ph : F.up) kd_key_phase(k, ph);
+  for (const Phase& ph : F.down) kd_key_phase(k, ph);
+}
+
+// everything a captured step depends on: sizes, modes and every device address it touches
+std::vector<uintptr_t> kd_key(ls_problem* P, const GmresCfg& cfg, bool op32, int nrhs, int steps) {
+  std::vector<uintptr_t> k = {(uintptr_t)nrhs, (uintptr_t)cfg.restart, (uintptr_t)steps, (uintptr_t)cfg.flexible,
+                              (uintptr_t)cfg.pc, (uintptr_t)cfg.pc32, (uintptr_t)op32, (uintptr_t)cfg.maxit,
+                              (uintptr_t)P->tune.gs_rows, (uintptr_t)P->tune.hodlr_rows};
+  for (const DevBuf* b : {&P->kQ, &P->kZ, &P->kw, &P->kz, &P->kpart, &P->knp, &P->kd.ictl, &P->kd.dctl, &P->kd.H,
+                          &P->kd.cs, &P->kd.sn, &P->kd.g, &P->kd.vin, &P->kd.tmp})
+    k.push_back((uintptr_t)b->p);
+  kd_key_fmm(k, op32 ? P->f32 : P->f64);
+  if (P->have_hodlr) {
+    k.push_back((uintptr_t)P->hod.partial.p);
+    k.push_back((uintptr_t)P->hod.svec.p);
+  }
+  return k;
+}
+
+// one Arnoldi step: q_j -> (z_j) -> w = A M^{-1} q_j, CGS2, Givens, q_{j+1}
+void kd_step(ls_problem* P, const GmresCfg& cfg, bool op32, const KdView& v, hipStream_t s) {
+  const long long N = v.N;
+  const int nrhs = v.nrhs, m = v.m, maxv = v.maxv, nch = v.nch;
+  double2* Q = P->kQ.as<double2>();
+  const long long ldqv = N, ldqr = (long long)maxv * N;
+  double2* w = P->kw.as<double2>();
+  double2* z = P->kz.as<double2>();
+  double2* vin = P->kd.vin.as<double2>();
+  double2* H = P->kd.H.as<double2>();
+  double2* part = P->kpart.as<double2>();
+  const long long hr = (long long)m * maxv;
+  lsk::launch_kd_copy(Q, ldqr, ldqv, vin, N, 0, N, v.jd, v.state, nrhs, s);
+  if (cfg.pc)
+    hodlr_apply(P, cfg.pc32, vin, N, z, N, nrhs, 0, s);
+  else
+    lsk::launch_axpby(1.0, vin, N, 0.0, vin, N, z, N, N, nrhs, s);
+  if (cfg.flexible)
+    lsk::launch_kd_copy(z, N, 0, P->kZ.as<double2>(), (long long)m * N, N, N, v.jd, v.state, nrhs, s);
+  fmm_apply(P, op32, z, N, w, N, nrhs, 1.0, P->coef, false, s);
+  lsk::launch_kd_dot(Q, ldqv, ldqr, maxv, w, N, part, N, nch, v.jd, v.state, nrhs, s);
+  lsk::launch_kd_finish(part, nch, maxv, H, hr, maxv, 0, v.jd, v.state, nrhs, s);
+  lsk::launch_kd_axpy(Q, ldqv, ldqr, H, hr, maxv, -1.0, w, N, N, v.jd, v.state, nrhs, s);
+  lsk::launch_kd_dot(Q, ldqv, ldqr, maxv, w, N, part, N, nch, v.jd, v.state, nrhs, s);
+  double2* t = P->kd.tmp.as<double2>();
+  lsk::launch_kd_finish(part, nch, maxv, t, maxv, 0, 0, v.jd, v.state, nrhs, s);
+  lsk::launch_kd_axpy(Q, ldqv, ldqr, t, maxv, 0, -1.0, w, N, N, v.jd, v.state, nrhs, s);
+  lsk::launch_kd_finish(part, nch, maxv, H, hr, maxv, 1, v.jd, v.state, nrhs, s);
+  lsk::launch_norm2(w, N, P->knp.as<double>(), N, nch, nrhs, s);
+  lsk::launch_kd_givens(P->knp.as<double>(), nch, H, m, maxv, P->kd.cs.as<double>(), P->kd.sn.as<double2>(),
+                        P->kd.g.as<double2>(), v.jd, v.state, v.its, v.kfin, v.est, v.fnorm, v.tol, cfg.maxit,
+                        v.alpha, nrhs, s);
+  lsk::launch_kd_next(w, N, v.alpha, Q, ldqv, ldqr, N, v.jd, v.state, nrhs, s);
+}
+
+hipGraphExec_t kd_graph(ls_problem* P, const GmresCfg& cfg, bool op32, const KdView& v, int steps) {
+  KrylovDev& K = P->kd;
+  const int slot = op32 ? 1 : 0;
+  std::vector<uintptr_t> key = kd_key(P, cfg, op32, v.nrhs, steps);
+  if (K.exec[slot] && K.key[slot] == key) return K.exec[slot];
+  K.drop(slot);
+  hipGraph_t g = nullptr;
+  hip_check(hipStreamBeginCapture(K.cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  P->capturing = true;
+  try {
+    for (int i = 0; i < steps; ++i) kd_step(P, cfg, op32, v, K.cap);
+  } catch (...) {
+    P->capturing = false;
+    (void)hipStreamEndCapture(K.cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  P->capturing = false;
+  hip_check(hipStreamEndCapture(K.cap, &g), "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  hip_check(e, "hipGraphInstantiate");
+  K.exec[slot] = ex;
+  K.key[slot] = std::move(key);
+  return ex;
+}
+
+void gmres_graph(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* x, int nrhs,
+                 std::vector<ColState>& st, int steps_in, hipStream_t s) {
+  const long long N = P->N;
+  const int m = std::max(1, cfg.restart);
+  const int maxv = m + 1;
+  const int steps = std::max(1, steps_in);
+  kd_ensure(P, cfg, nrhs);
+  const KdView v = kd_view(P, nrhs, m);
+  KrylovDev& K = P->kd;
+  double2* w = P->kw.as<double2>();
+  double2* z = P->kz.as<double2>();
+  double2* r = P->kr.as<double2>();
+  double2* Q = P->kQ.as<double2>();
+  const long long ldqr = (long long)maxv * N;
+  std::vector<double> beta;
+  std::vector<int> hi(1 + 3 * nrhs);
+  std::vector<double> hd(4 * nrhs);
+  bool first = true;
+  bool relax_enabled = cfg.relax > 0;
+  for (;;) {
+    bool all_done = true;
+    for (int c = 0; c < nrhs; ++c) all_done &= st[c].done;
+    if (all_done) return;
+    if (first && cfg.x_zero) {
+      lsk::launch_axpby(1.0, f, N, 0.0, f, N, r, N, N, nrhs, s);
+    } else {
+      op_apply(P, cfg.op32, x, w, nrhs, s);
+      lsk::launch_axpby(1.0, f, N, -1.0, w, N, r, N, N, nrhs, s);
+    }
+    first = false;
+    norms(P, r, nrhs, beta, s);
+    bool any = false;
+    for (int c = 0; c < nrhs; ++c) {
+      if (st[c].done) continue;
+      st[c].relres = beta[c] / st[c].fnorm;
+      if (!std::isfinite(beta[c])) {
+        st[c].done = true;
+        st[c].status = LS_NAN;
+      } else if (st[c].relres <= st[c].tol) {
+        st[c].done = true;
+        st[c].status = LS_CONVERGED;
+      } else if (st[c].its >= cfg.maxit) {
+        st[c].done = true;
+        st[c].status = LS_MAXIT;
+      } else {
+        any = true;
+        st[c].cycles++;
+        if (relax_enabled && st[c].cycles > 1 && beta[c] > 0.9 * st[c].prev_true) {
+          relax_enabled = false;
+          st[c].fell_back = true;
+        }
+        st[c].prev_true = beta[c];
+      }
+    }
+    if (!any) return;
+    // cycle start on the device: j = 0, g = (beta, 0, ...), q_0 = r / beta
+    hi.assign(1 + 3 * nrhs, 0);
+    std::vector<zd> g0((size_t)nrhs * maxv, zd(0));
+    for (int c = 0; c < nrhs; ++c) {
+      const bool act = !st[c].done;
+      hi[1 + c] = act ? 0 : 2;
+      hi[1 + nrhs + c] = st[c].its;
+      hd[c] = st[c].fnorm;
+      hd[nrhs + c] = st[c].tol;
+      hd[2 * nrhs + c] = 1.0;
+      hd[3 * nrhs + c] = act ? 1.0 / beta[c] : 0.0;
+      g0[(size_t)c * maxv] = act ? beta[c] : 0.0;
+    }
+    hip_check(hipMemcpyAsync(K.ictl.p, hi.data(), hi.size() * 4, hipMemcpyHostToDevice, s), "ctl h2d");
+    hip_check(hipMemcpyAsync(K.dctl.p, hd.data(), hd.size() * 8, hipMemcpyHostToDevice, s), "ctl h2d");
+    hip_check(hipMemcpyAsync(K.g.p, g0.data(), g0.size() * 16, hipMemcpyHostToDevice, s), "g h2d");
+    lsk::launch_scale(r, N, v.alpha, Q, ldqr, N, nrhs, s);
+    bool relaxed = false;
+    std::vector<double> est(nrhs, 1.0);
+    for (;;) {
+      hip_check(hipGraphLaunch(kd_graph(P, cfg, cfg.op32 || relaxed, v, steps), s), "hipGraphLaunch");
+      hip_check(hipMemcpyAsync(K.host, K.ictl.p, (size_t)(1 + 3 * nrhs) * 4, hipMemcpyDeviceToHost, s), "ctl d2h");
+      hip_check(hipMemcpyAsync(est.data(), v.est, (size_t)nrhs * 8, hipMemcpyDeviceToHost, s), "est d2h");
+      hip_check(hipStreamSynchronize(s), "gmres steps");
+      bool active = false;
+      for (int c = 0; c < nrhs; ++c) active |= K.host[1 + c] == 0;
+      if (!active) break;
+      if (relax_enabled && !relaxed) {
+        bool all_small = true;
+        for (int c = 0; c < nrhs; ++c)
+          if (K.host[1 + c] == 0 && est[c] > cfg.relax) all_small = false;
+        relaxed = all_small;
+      }
+    }
+    // y = R^{-1} g per column (host), x += Z y (flexible) or x += M^{-1} (Q y)
+    std::vector<zd> y((size_t)nrhs * maxv, zd(0));
+    int kmaxc = 0;
+    std::vector<zd> R, gh(maxv);
+    for (int c = 0; c < nrhs; ++c) {
+      st[c].its = K.host[1 + nrhs + c];
+      st[c].last_est = est[c];
+      if (st[c].done) continue;
+      const int k = K.host[1 + 2 * nrhs + c];
+      if (est[c] <= st[c].tol) st[c].est_converged = true;
+      if (k <= 0) continue;
+      kmaxc = std::max(kmaxc, k);
+      R.resize((size_t)k * maxv);
+      hip_check(hipMemcpyAsync(R.data(), K.H.as<double2>() + (size_t)c * m * maxv, (size_t)k * maxv * 16,
+                               hipMemcpyDeviceToHost, s),
+                "R d2h");
+      hip_check(hipMemcpyAsync(gh.data(), K.g.as<double2>() + (size_t)c * maxv, (size_t)maxv * 16,
+                               hipMemcpyDeviceToHost, s),
+                "g d2h");
+      hip_check(hipStreamSynchronize(s), "sync");
+      // R column jj holds rows 0..jj at R[jj*maxv + i]
+      for (int i = k - 1; i >= 0; --i) {
+        zd acc = gh[i];
+        for (int jj = i + 1; jj < k; ++jj) acc -= R[(size_t)jj * maxv + i] * y[(size_t)c * maxv + jj];
+        y[(size_t)c * maxv + i] = acc / R[(size_t)i * maxv + i];
+      }
+    }
+    if (kmaxc > 0) {
+      hip_check(hipMemcpyAsync(P->ky.p, y.data(), y.size() * 16, hipMemcpyHostToDevice, s), "y h2d");
+      if (cfg.flexible) {
+        lsk::launch_gs_axpy(P->kZ.as<double2>(), N, (long long)m * N, kmaxc, P->ky.as<double2>(), maxv, 1.0, x, N,
+                            N, nrhs, s);
+      } else {
+        hip_check(hipMemsetAsync(w, 0, (size_t)nrhs * N * 16, s), "memset");
+        lsk::launch_gs_axpy(Q, N, ldqr, kmaxc, P->ky.as<double2>(), maxv, 1.0, w, N, N, nrhs, s);
+        pc_apply(P, cfg, w, N, z, nrhs, s);
+        lsk::launch_axpby(1.0, x, N, 1.0, z, N, x, N, N, nrhs, s);
+      }
+    }
+    hip_check(hipStreamSynchronize(s), "gmres cycle");
+    if (cfg.trust_estimate)
+      for (int c = 0; c < nrhs; ++c)
+        if (!st[c].done && st[c].est_converged) {
+          st[c].done = true;
+          st[c].status = LS_CONVERGED;
+        }
+  }
+}
+
 // Exact integral of G = (i/4) H0(kappa |y|) over the square cell [-h/2, h/2]^2 (the diagonal
 // entry of Eq. (eq:13) at p = 1):  8 int_0^{pi/4} (i/4) [R H1(kappa R)/kappa + 2i/(pi kappa^2)] dtheta,
 // R = h / (2 cos theta), by 64-point Gauss-Legendre quadrature in theta.
@@ -1159,6 +1505,7 @@ void ls_default_options(ls_options* o) {
   o->max_refine = 10;
   o->build_fp32 = 1;
   o->hodlr_rank_div = 0;
+  o->graph_iters = 0;
 }
 
 const char* ls_last_error(void) { return g_last_error.c_str(); }
@@ -1174,6 +1521,7 @@ static void validate_options(const ls_options& o) {
   if (!(o.inner_tol > 0) || o.inner_tol >= 1) throw LsError(LS_EINVAL, "inner_tol must be in (0, 1)");
   if (o.max_refine < 1) throw LsError(LS_EINVAL, "max_refine must be >= 1");
   if (o.hodlr_rank_div < 0) throw LsError(LS_EINVAL, "hodlr_rank_div must be >= 0");
+  if (o.graph_iters < 0 || o.graph_iters > 64) throw LsError(LS_EINVAL, "graph_iters must be in [0, 64]");
 }
 
 ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt, ls_plan_info* out) {
@@ -1502,9 +1850,10 @@ ls_status ls_rhs_planewave(ls_problem* P, const double* angles, int nrhs, void* 
   }
 }
 
-ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld, double tol, int x0_given,
-                   int prec_override, ls_solve_info* info, void* stream) {
-  try {
+// ls_solve's body; graph_iters > 0 selects the graph-captured GMRES driver
+static void solve_impl(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld, double tol, int x0_given,
+                       int prec_override, ls_solve_info* info, hipStream_t stream, int graph_iters) {
+  {
     double t0 = now_ms();
     check_vec_args(P, f, psi, nrhs, ld);
     if (!(tol > 0 && tol < 1)) throw LsError(LS_EINVAL, "tol must be in (0, 1)");
@@ -1538,7 +1887,7 @@ ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld
       op_apply(P, false, xm, w, nrhs, s);
       std::vector<double> an;
       norms(P, w, nrhs, an, s);
-      const int nch = nchunks_for(N);
+      const int nch = nchunks_for(P);
       P->kpart.ensure((size_t)nrhs * nch * 16);
       P->kh.ensure((size_t)nrhs * 16);
       double2* part = P->kpart.as<double2>();
@@ -1586,7 +1935,10 @@ ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld
     if (prec == LS_FP64 || prec == LS_FP32) {
       cfg.op32 = prec == LS_FP32;
       cfg.pc32 = prec == LS_FP32;
-      gmres(P, cfg, fm, xm, nrhs, st, s);
+      if (graph_iters > 0)
+        gmres_graph(P, cfg, fm, xm, nrhs, st, graph_iters, s);
+      else
+        gmres(P, cfg, fm, xm, nrhs, st, s);
     } else {
       // mixed: flexible GMRES whose products switch from the FP64 to the FP32 operator once
       // every residual estimate is below tol / delta32 (relaxation of inexact Krylov methods),
@@ -1596,7 +1948,10 @@ ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld
       cfg.pc32 = true;
       cfg.flexible = true;
       cfg.relax = std::min(0.5, tol / P->opt.inner_tol);
-      gmres(P, cfg, fm, xm, nrhs, st, s);
+      if (graph_iters > 0)
+        gmres_graph(P, cfg, fm, xm, nrhs, st, graph_iters, s);
+      else
+        gmres(P, cfg, fm, xm, nrhs, st, s);
       for (int c = 0; c < nrhs; ++c) {
         nref[c] = st[c].cycles;
         if (st[c].fell_back && st[c].status == LS_CONVERGED) st[c].status = LS_REFINE_STAGNATED;
@@ -1622,6 +1977,155 @@ ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld
         info[c].t_solve_ms = t1 - t0;
         info[c].relres0 = fn[c] > 0 ? rel0[c] : 0.0;
       }
+  }
+}
+
+ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld, double tol, int x0_given,
+                   int prec_override, ls_solve_info* info, void* stream) {
+  try {
+    if (!P) throw LsError(LS_EINVAL, "NULL problem");
+    solve_impl(P, f, psi, nrhs, ld, tol, x0_given, prec_override, info, (hipStream_t)stream, P->opt.graph_iters);
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
+}
+
+// Autotuner: times the launch shapes of the two reduction kernels on this problem's own sizes
+// and keeps the fastest (rows per workgroup chunk of the Arnoldi dot products and norms; max
+// rows per chunk of the HODLR level reductions).  Small problems want short chunks (more
+// workgroups), large ones long chunks (fewer partial sums).
+static const int kGsRows[5] = {128, 256, 512, 1024, 2048};
+static const int kPcRows[5] = {64, 128, 256, 512, 1024};
+
+static void autotune_impl(ls_problem* P, ls_tune_info* out, hipStream_t s) {
+  const long long N = P->N;
+  const int ncols = 32, reps = 5;
+  DevBuf A, w, w2, part, np, no;
+  A.alloc((size_t)ncols * N * 16);
+  w.alloc((size_t)N * 16);
+  w2.alloc((size_t)N * 16);
+  part.alloc((size_t)1025 * ncols * 16);  // partials of up to 1024 chunks, then the sums
+  np.alloc((size_t)1024 * 8);
+  no.alloc(64);
+  hip_check(hipMemsetAsync(A.p, 0, A.bytes, s), "memset");
+  hip_check(hipMemsetAsync(w.p, 0, w.bytes, s), "memset");
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "hipEventCreate");
+  hip_check(hipEventCreate(&e1), "hipEventCreate");
+  auto timed = [&](auto&& body) {
+    body();  // warm-up
+    hip_check(hipEventRecord(e0, s), "hipEventRecord");
+    for (int r = 0; r < reps; ++r) body();
+    hip_check(hipEventRecord(e1, s), "hipEventRecord");
+    hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0;
+    hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    return 1e3 * (double)ms / reps;
+  };
+  ls_tune_info info{};
+  double best = 1e300;
+  int best_gs = P->tune.gs_rows;
+  for (int i = 0; i < 5; ++i) {
+    P->tune.gs_rows = kGsRows[i];
+    const int nch = nchunks_for(P);
+    info.gs_us[i] = timed([&] {
+      lsk::launch_gs_dot(A.as<double2>(), N, 0, ncols, w.as<double2>(), N, part.as<double2>(), N, nch, ncols, 1, s);
+      lsk::launch_gs_finish(part.as<double2>(), nch, ncols, ncols, part.as<double2>() + (size_t)1024 * ncols, 0, 1,
+                            s);
+      lsk::launch_norm2(w.as<double2>(), N, np.as<double>(), N, nch, 1, s);
+      lsk::launch_norm2_finish(np.as<double>(), nch, no.as<double>(), 1, s);
+    });
+    if (info.gs_us[i] < best) {
+      best = info.gs_us[i];
+      best_gs = kGsRows[i];
+    }
+  }
+  P->tune.gs_rows = best_gs;
+  info.gs_rows = best_gs;
+  info.hodlr_rows = P->tune.hodlr_rows;
+  if (P->have_hodlr) {
+    best = 1e300;
+    int best_pc = P->tune.hodlr_rows;
+    for (int i = 0; i < 5; ++i) {
+      hodlr_chunks(P->hod, kPcRows[i]);
+      hodlr_ensure_ws(P, 1);
+      info.pc_us[i] = timed([&] { hodlr_apply(P, P->have32, w.as<double2>(), N, w2.as<double2>(), N, 1, 0, s); });
+      if (info.pc_us[i] < best) {
+        best = info.pc_us[i];
+        best_pc = kPcRows[i];
+      }
+    }
+    P->tune.hodlr_rows = best_pc;
+    hodlr_chunks(P->hod, best_pc);
+    info.hodlr_rows = best_pc;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  hip_check(hipStreamSynchronize(s), "autotune");
+  P->tune.done = true;
+  if (out) *out = info;
+}
+
+ls_status ls_autotune(ls_problem* P, ls_tune_info* out, void* stream) {
+  try {
+    if (!P) throw LsError(LS_EINVAL, "NULL problem");
+    autotune_impl(P, out, (hipStream_t)stream);
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
+}
+
+// Queue of independent problems: largest first, pulled dynamically by worker threads, each
+// with its own HIP stream; every solve runs the graph-captured GMRES driver.
+ls_status ls_solve_queue(ls_problem* const* probs, int nprob, const void* const* f, void* const* psi, double tol,
+                         int prec, int nworkers, int graph_iters, ls_solve_info* info) {
+  try {
+    if (!probs || !f || !psi || !info || nprob < 1) throw LsError(LS_EINVAL, "NULL argument or nprob < 1");
+    if (nworkers < 0 || nworkers > 16) throw LsError(LS_EINVAL, "nworkers must be in [0, 16]");
+    if (graph_iters < 0 || graph_iters > 64) throw LsError(LS_EINVAL, "graph_iters must be in [0, 64]");
+    if (!(tol > 0 && tol < 1)) throw LsError(LS_EINVAL, "tol must be in (0, 1)");
+    if (prec < -1 || prec > 2) throw LsError(LS_EINVAL, "prec must be -1, LS_FP64, LS_FP32 or LS_MIXED");
+    for (int i = 0; i < nprob; ++i) {
+      if (!probs[i] || !f[i] || !psi[i]) throw LsError(LS_EINVAL, "NULL problem or vector in the queue");
+      for (int j = 0; j < i; ++j)
+        if (probs[j] == probs[i]) throw LsError(LS_EINVAL, "a problem appears twice in the queue");
+    }
+    const int nw = std::min(nprob, nworkers == 0 ? 4 : nworkers);
+    const int gi = graph_iters == 0 ? 8 : graph_iters;
+    std::vector<int> order(nprob);
+    for (int i = 0; i < nprob; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a]->N > probs[b]->N; });
+    std::vector<hipStream_t> streams(nw, nullptr);
+    for (auto& st : streams) hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+    std::atomic<int> next{0};
+    std::mutex mu;
+    std::string err;
+    ls_status err_code = LS_OK;
+    auto worker = [&](int wi) {
+      hipStream_t s = streams[wi];
+      for (;;) {
+        const int k = next.fetch_add(1);
+        if (k >= nprob) return;
+        const int p = order[k];
+        try {
+          if (!probs[p]->tune.done) autotune_impl(probs[p], nullptr, s);
+          solve_impl(probs[p], f[p], psi[p], 1, probs[p]->N, tol, 0, prec, &info[p], s, gi);
+        } catch (const LsError& e) {
+          std::lock_guard<std::mutex> lk(mu);
+          if (err_code == LS_OK) {
+            err_code = (ls_status)e.code;
+            err = std::string("queue problem ") + std::to_string(p) + ": " + e.what();
+          }
+        }
+      }
+    };
+    std::vector<std::thread> th;
+    for (int wi = 0; wi < nw; ++wi) th.emplace_back(worker, wi);
+    for (auto& t : th) t.join();
+    for (auto& st : streams) (void)hipStreamDestroy(st);
+    if (err_code != LS_OK) throw LsError(err_code, err);
     return LS_OK;
   } catch (const LsError& e) {
     return fail(e);

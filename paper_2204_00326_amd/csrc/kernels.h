@@ -83,4 +83,26 @@ void launch_axpby(double a, const double2* x, long long ldx, double b, const dou
                   long long ldo, long long N, int nrhs, hipStream_t s);
 void launch_cast(bool to_fp32, const void* in, void* out, long long n, hipStream_t s);
 
+
+// ---- device-driven Arnoldi step (the Arnoldi index j lives in device memory) ----
+// dst column j = src column j for active columns (state[rhs] == 0)
+void launch_kd_copy(const double2* src, long long src_ldr, long long src_ldj, double2* dst, long long dst_ldr,
+                    long long dst_ldj, long long N, const int* jdev, const int* state, int nrhs, hipStream_t s);
+// partial dot products of Q columns 0..j with w (conjugated Q)
+void launch_kd_dot(const double2* Q, long long ldq_vec, long long ldq_rhs, int maxv, const double2* w, long long ldw,
+                   double2* partial, long long N, int nchunks, const int* jdev, const int* state, int nrhs,
+                   hipStream_t s);
+void launch_kd_finish(const double2* partial, int nchunks, int maxv, double2* out, long long out_ldr,
+                      long long out_ldj, int accumulate, const int* jdev, const int* state, int nrhs, hipStream_t s);
+// w += sign * Q[:, 0..j] h(j), h(j) = h + rhs*h_ldr + j*h_ldj
+void launch_kd_axpy(const double2* Q, long long ldq_vec, long long ldq_rhs, const double2* h, long long h_ldr,
+                    long long h_ldj, double sign, double2* w, long long ldw, long long N, const int* jdev,
+                    const int* state, int nrhs, hipStream_t s);
+void launch_kd_givens(const double* npart, int nchunks, double2* H, int m, int maxv, double* cs, double2* sn,
+                      double2* g, const int* jdev, int* state, int* its, int* kfin, double* est, const double* fnorm,
+                      const double* tol, int maxit, double* alpha, int nrhs, hipStream_t s);
+// Q_{j+1} = alpha w (active columns), then j += 1 if any column is active
+void launch_kd_next(const double2* w, long long ldw, const double* alpha, double2* Q, long long ldq_vec,
+                    long long ldq_rhs, long long N, int* jdev, const int* state, int nrhs, hipStream_t s);
+
 }  // namespace lsk

@@ -371,10 +371,13 @@ template <typename T, bool CONJ>
 __global__ __launch_bounds__(256) void k_tsdot(const typename V2<T>::type* __restrict__ A, long long lda,
                                                long long lda_rhs, int ncols, const double2* __restrict__ x,
                                                long long ldx, double2* __restrict__ partial, int ldp, long long chunk,
-                                               int nchunks, int wpg, long long nrows) {
+                                               int nchunks, int wpg, long long nrows, const int* __restrict__ jdev,
+                                               const int* __restrict__ skip) {
   constexpr int G = 16;
   __shared__ double lds[4][2 * G];
   const int ch = blockIdx.x, rhs = blockIdx.z;
+  if (skip && skip[rhs] != 0) return;  // uniform per block
+  if (jdev) ncols = *jdev + 1;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gpb = 4 / wpg;                           // column groups per block
   const int grp = blockIdx.y * gpb + w / wpg;        // this wave's column group
@@ -436,9 +439,10 @@ __global__ __launch_bounds__(256) void k_tsdot(const typename V2<T>::type* __res
   }
 }
 
+// ncols columns, or (jdev != NULL) *jdev + 1 of at most ncols; rhs with skip[rhs] != 0 untouched
 static void tsdot(bool fp32, bool conj, const void* A, long long lda, long long lda_rhs, int ncols, const double2* x,
                   long long ldx, double2* partial, int ldp, long long chunk, int nchunks, long long nrows, int nrhs,
-                  hipStream_t s) {
+                  hipStream_t s, const int* jdev = nullptr, const int* skip = nullptr) {
   const int groups = (ncols + 15) / 16;
   const int wpg = groups >= 4 ? 1 : (groups == 1 ? 4 : 2);
   const int gpb = 4 / wpg;
@@ -446,17 +450,17 @@ static void tsdot(bool fp32, bool conj, const void* A, long long lda, long long 
   if (fp32) {
     if (conj)
       k_tsdot<float, true><<<grid, 256, 0, s>>>((const float2*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk,
-                                               nchunks, wpg, nrows);
+                                               nchunks, wpg, nrows, jdev, skip);
     else
       k_tsdot<float, false><<<grid, 256, 0, s>>>((const float2*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk,
-                                                nchunks, wpg, nrows);
+                                                nchunks, wpg, nrows, jdev, skip);
   } else {
     if (conj)
       k_tsdot<double, true><<<grid, 256, 0, s>>>((const double2*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk,
-                                                nchunks, wpg, nrows);
+                                                nchunks, wpg, nrows, jdev, skip);
     else
       k_tsdot<double, false><<<grid, 256, 0, s>>>((const double2*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp,
-                                                 chunk, nchunks, wpg, nrows);
+                                                 chunk, nchunks, wpg, nrows, jdev, skip);
   }
 }
 
@@ -656,17 +660,27 @@ void launch_gs_finish(const double2* partial, int nchunks, int nv, int maxv, dou
 }
 
 // w[i] += sign * sum_v Q_v[i] h[v]
+// Device-driven form (jdev != NULL): nv = *jdev + 1 and h advanced by *jdev * h_ldj; rhs with
+// skip[rhs] != 0 untouched.
 __global__ __launch_bounds__(256) void k_gs_axpy(const double2* __restrict__ Q, long long ldq_vec, long long ldq_rhs,
-                                                 int nv, const double2* __restrict__ h, int maxv, double sign,
-                                                 double2* __restrict__ w, long long ldw, long long N) {
+                                                 int nv, const double2* __restrict__ h, long long h_ldr, double sign,
+                                                 double2* __restrict__ w, long long ldw, long long N,
+                                                 const int* __restrict__ jdev, long long h_ldj,
+                                                 const int* __restrict__ skip) {
   __shared__ double2 hs[256];
   const int rhs = blockIdx.y;
+  if (skip && skip[rhs] != 0) return;  // uniform per block
+  if (jdev) {
+    const int j = *jdev;
+    nv = j + 1;
+    h += (long long)j * h_ldj;
+  }
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   double re = 0, im = 0;
   for (int v0 = 0; v0 < nv; v0 += 256) {
     const int cnt = nv - v0 < 256 ? nv - v0 : 256;
     __syncthreads();
-    if ((int)threadIdx.x < cnt) hs[threadIdx.x] = h[(long long)rhs * maxv + v0 + threadIdx.x];
+    if ((int)threadIdx.x < cnt) hs[threadIdx.x] = h[(long long)rhs * h_ldr + v0 + threadIdx.x];
     __syncthreads();
     if (i < N) {
       const double2* q = Q + rhs * ldq_rhs + (long long)v0 * ldq_vec + i;
@@ -689,7 +703,7 @@ __global__ __launch_bounds__(256) void k_gs_axpy(const double2* __restrict__ Q, 
 void launch_gs_axpy(const double2* Q, long long ldq_vec, long long ldq_rhs, int nv, const double2* h, int maxv,
                     double sign, double2* w, long long ldw, long long N, int nrhs, hipStream_t s) {
   dim3 grid((unsigned)((N + 255) / 256), nrhs);
-  k_gs_axpy<<<grid, 256, 0, s>>>(Q, ldq_vec, ldq_rhs, nv, h, maxv, sign, w, ldw, N);
+  k_gs_axpy<<<grid, 256, 0, s>>>(Q, ldq_vec, ldq_rhs, nv, h, maxv, sign, w, ldw, N, nullptr, 0, nullptr);
 }
 
 __global__ __launch_bounds__(256) void k_norm2(const double2* __restrict__ w, long long ldw, double* partial,
@@ -778,6 +792,192 @@ __global__ void k_cast(int to_fp32, const void* in, void* out, long long n) {
 void launch_cast(bool to_fp32, const void* in, void* out, long long n, hipStream_t s) {
   if (n <= 0) return;
   k_cast<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(to_fp32 ? 1 : 0, in, out, n);
+}
+
+
+// =====================================================================================
+// Device-driven Arnoldi step.  The Arnoldi index j of the current cycle lives in device
+// memory (*jdev), so one step is a fixed launch sequence that a HIP graph can capture and
+// replay.  Per right-hand side, state[rhs] = 0 while the cycle runs, 1 once it has ended
+// (kfin[rhs] columns), 2 when the column is idle (converged or stopped); kernels leave
+// non-active columns untouched.  Layouts: Q and Z column j of rhs at rhs*ld_rhs + j*ld_vec;
+// Hessenberg H[rhs][j][0..maxv) (column j contiguous), cs[rhs][m], sn[rhs][m], g[rhs][maxv].
+// =====================================================================================
+__global__ void k_kd_copy(const double2* __restrict__ src, long long src_ldr, long long src_ldj,
+                          double2* __restrict__ dst, long long dst_ldr, long long dst_ldj, long long N,
+                          const int* __restrict__ jdev, const int* __restrict__ state) {
+  const int rhs = blockIdx.y;
+  if (state[rhs] != 0) return;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const long long j = *jdev;
+  dst[rhs * dst_ldr + j * dst_ldj + i] = src[rhs * src_ldr + j * src_ldj + i];
+}
+
+void launch_kd_copy(const double2* src, long long src_ldr, long long src_ldj, double2* dst, long long dst_ldr,
+                    long long dst_ldj, long long N, const int* jdev, const int* state, int nrhs, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), nrhs);
+  k_kd_copy<<<grid, 256, 0, s>>>(src, src_ldr, src_ldj, dst, dst_ldr, dst_ldj, N, jdev, state);
+}
+
+void launch_kd_dot(const double2* Q, long long ldq_vec, long long ldq_rhs, int maxv, const double2* w, long long ldw,
+                   double2* partial, long long N, int nchunks, const int* jdev, const int* state, int nrhs,
+                   hipStream_t s) {
+  const long long chunk = (N + nchunks - 1) / nchunks;
+  tsdot(false, true, Q, ldq_vec, ldq_rhs, maxv, w, ldw, partial, maxv, chunk, nchunks, N, nrhs, s, jdev, state);
+}
+
+// out[rhs*out_ldr + j*out_ldj + v] (+)= sum_c partial[(rhs*nchunks + c)*maxv + v], v <= j
+__global__ __launch_bounds__(256) void k_kd_finish(const double2* __restrict__ partial, int nchunks, int maxv,
+                                                   double2* out, long long out_ldr, long long out_ldj, int accumulate,
+                                                   const int* __restrict__ jdev, const int* __restrict__ state) {
+  const int rhs = blockIdx.y;
+  if (state[rhs] != 0) return;
+  const int j = *jdev;
+  const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (v > j) return;
+  double re = 0, im = 0;
+  for (int c = lane; c < nchunks; c += 64) {
+    const double2 p = partial[((long long)rhs * nchunks + c) * maxv + v];
+    re += p.x;
+    im += p.y;
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane == 0) {
+    double2* o = out + rhs * out_ldr + (long long)j * out_ldj + v;
+    if (accumulate) {
+      re += o->x;
+      im += o->y;
+    }
+    *o = make_double2(re, im);
+  }
+}
+
+void launch_kd_finish(const double2* partial, int nchunks, int maxv, double2* out, long long out_ldr,
+                      long long out_ldj, int accumulate, const int* jdev, const int* state, int nrhs, hipStream_t s) {
+  dim3 grid((maxv + 3) / 4, nrhs);
+  k_kd_finish<<<grid, 256, 0, s>>>(partial, nchunks, maxv, out, out_ldr, out_ldj, accumulate, jdev, state);
+}
+
+void launch_kd_axpy(const double2* Q, long long ldq_vec, long long ldq_rhs, const double2* h, long long h_ldr,
+                    long long h_ldj, double sign, double2* w, long long ldw, long long N, const int* jdev,
+                    const int* state, int nrhs, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), nrhs);
+  k_gs_axpy<<<grid, 256, 0, s>>>(Q, ldq_vec, ldq_rhs, 0, h, h_ldr, sign, w, ldw, N, jdev, h_ldj, state);
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ inline double cabs2(double2 a) { return hypot(a.x, a.y); }
+
+// One wave per rhs: ||w|| from the norm partials, H[j+1][j] = ||w||, the previous Givens
+// rotations applied to column j, a new rotation annihilating H[j+1][j], g updated, the
+// residual estimate |g[j+1]| / fnorm, and the stop decision (estimate <= tol, maxit, restart
+// length, breakdown or a non-finite value).  alpha[rhs] = 1/||w|| for a column that goes on.
+__global__ __launch_bounds__(64) void k_kd_givens(const double* __restrict__ npart, int nchunks, double2* H, int m,
+                                                  int maxv, double* cs, double2* sn, double2* g,
+                                                  const int* __restrict__ jdev, int* state, int* its, int* kfin,
+                                                  double* est, const double* __restrict__ fnorm,
+                                                  const double* __restrict__ tol, int maxit, double* alpha) {
+  const int rhs = blockIdx.x, lane = threadIdx.x;
+  if (state[rhs] != 0) {
+    if (lane == 0) alpha[rhs] = 0.0;
+    return;
+  }
+  double ssq = 0;
+  for (int c = lane; c < nchunks; c += 64) ssq += npart[(long long)rhs * nchunks + c];
+  ssq = wave_sum(ssq);
+  if (lane != 0) return;
+  const int j = *jdev;
+  const double hn = sqrt(ssq);
+  double2* h = H + ((long long)rhs * m + j) * maxv;
+  double* c_ = cs + (long long)rhs * m;
+  double2* s_ = sn + (long long)rhs * m;
+  double2* gg = g + (long long)rhs * maxv;
+  h[j + 1] = make_double2(hn, 0.0);
+  for (int i = 0; i < j; ++i) {
+    const double2 a = h[i], b = h[i + 1];
+    const double ci = c_[i];
+    const double2 si = s_[i];
+    const double2 sb = cmul(si, b), sa = cmul(cconj(si), a);
+    h[i] = make_double2(ci * a.x + sb.x, ci * a.y + sb.y);
+    h[i + 1] = make_double2(ci * b.x - sa.x, ci * b.y - sa.y);
+  }
+  const double2 a = h[j], b = h[j + 1];
+  const double aa = cabs2(a), ab = cabs2(b);
+  double cc;
+  double2 ss;
+  if (ab == 0.0) {
+    cc = 1.0;
+    ss = make_double2(0.0, 0.0);
+  } else if (aa == 0.0) {
+    cc = 0.0;
+    ss = make_double2(b.x / ab, -b.y / ab);
+  } else {
+    const double t = hypot(aa, ab);
+    cc = aa / t;
+    const double2 ph = make_double2(a.x / aa, a.y / aa);
+    const double2 q = cmul(ph, cconj(b));
+    ss = make_double2(q.x / t, q.y / t);
+  }
+  c_[j] = cc;
+  s_[j] = ss;
+  const double2 sb = cmul(ss, b);
+  h[j] = make_double2(cc * a.x + sb.x, cc * a.y + sb.y);
+  h[j + 1] = make_double2(0.0, 0.0);
+  const double2 gj = gg[j];
+  const double2 t1 = cmul(cconj(ss), gj);
+  gg[j + 1] = make_double2(-t1.x, -t1.y);
+  gg[j] = make_double2(cc * gj.x, cc * gj.y);
+  const int it = its[rhs] + 1;
+  its[rhs] = it;
+  const double e = cabs2(gg[j + 1]) / fnorm[rhs];
+  est[rhs] = e;
+  const bool stop = e <= tol[rhs] || it >= maxit || j + 1 >= m || hn == 0.0 || !isfinite(e);
+  if (stop) {
+    state[rhs] = 1;
+    kfin[rhs] = j + 1;
+    alpha[rhs] = 0.0;
+  } else {
+    alpha[rhs] = 1.0 / hn;
+  }
+}
+
+void launch_kd_givens(const double* npart, int nchunks, double2* H, int m, int maxv, double* cs, double2* sn,
+                      double2* g, const int* jdev, int* state, int* its, int* kfin, double* est, const double* fnorm,
+                      const double* tol, int maxit, double* alpha, int nrhs, hipStream_t s) {
+  k_kd_givens<<<nrhs, 64, 0, s>>>(npart, nchunks, H, m, maxv, cs, sn, g, jdev, state, its, kfin, est, fnorm, tol,
+                                  maxit, alpha);
+}
+
+// Q_{j+1} = alpha w for columns still active after the rotation
+__global__ void k_kd_next(const double2* __restrict__ w, long long ldw, const double* __restrict__ alpha,
+                          double2* __restrict__ Q, long long ldq_vec, long long ldq_rhs, long long N,
+                          const int* __restrict__ jdev, const int* __restrict__ state) {
+  const int rhs = blockIdx.y;
+  if (state[rhs] != 0) return;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double a = alpha[rhs];
+  const double2 v = w[rhs * ldw + i];
+  Q[rhs * ldq_rhs + (long long)(*jdev + 1) * ldq_vec + i] = make_double2(a * v.x, a * v.y);
+}
+
+// j += 1 when any column is still active (one thread)
+__global__ void k_kd_advance(int* jdev, const int* __restrict__ state, int nrhs) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  bool any = false;
+  for (int r = 0; r < nrhs; ++r) any |= state[r] == 0;
+  if (any) *jdev += 1;
+}
+
+void launch_kd_next(const double2* w, long long ldw, const double* alpha, double2* Q, long long ldq_vec,
+                    long long ldq_rhs, long long N, int* jdev, const int* state, int nrhs, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), nrhs);
+  k_kd_next<<<grid, 256, 0, s>>>(w, ldw, alpha, Q, ldq_vec, ldq_rhs, N, jdev, state);
+  k_kd_advance<<<1, 64, 0, s>>>(jdev, state, nrhs);
 }
 
 }  // namespace lsk

@@ -32,7 +32,7 @@ class _Options(C.Structure):
     _fields_ = [("leaf_max", C.c_int), ("T", C.c_double), ("sign", C.c_int), ("hodlr_rank", C.c_int),
                 ("eps_inner", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("prec", C.c_int),
                 ("inner_tol", C.c_double), ("max_refine", C.c_int), ("build_fp32", C.c_int),
-                ("hodlr_rank_div", C.c_int)]
+                ("hodlr_rank_div", C.c_int), ("graph_iters", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -55,6 +55,10 @@ class _PlanInfo(C.Structure):
     _fields_ = [("levels", C.c_int), ("leaf_side", C.c_int), ("top_level", C.c_int), ("hf", C.c_int * 32),
                 ("ndir", C.c_int * 32), ("max_il", C.c_int * 32), ("il_pairs", C.c_int64 * 32),
                 ("near_pairs", C.c_int64), ("coverage_min", C.c_int), ("coverage_max", C.c_int)]
+
+
+class _TuneInfo(C.Structure):
+    _fields_ = [("gs_rows", C.c_int), ("hodlr_rows", C.c_int), ("gs_us", C.c_double * 5), ("pc_us", C.c_double * 5)]
 
 
 class _NopConfig(C.Structure):
@@ -83,6 +87,8 @@ def lib():
     L.ls_rhs_planewave.argtypes = [vp, vp, ci, vp, i64, vp]
     L.ls_solve.argtypes = [vp, vp, vp, ci, i64, cd, ci, ci, C.POINTER(_Info), vp]
     L.ls_stats.argtypes = [vp, C.POINTER(_Stats)]
+    L.ls_solve_queue.argtypes = [vp, ci, vp, vp, cd, ci, ci, ci, C.POINTER(_Info)]
+    L.ls_autotune.argtypes = [vp, C.POINTER(_TuneInfo), vp]
     L.ls_destroy.argtypes = [vp]
     L.ls_destroy.restype = None
     L.ls_plan_describe.argtypes = [ci, cd, cd, C.POINTER(_Options), C.POINTER(_PlanInfo)]
@@ -107,7 +113,8 @@ def lib():
                  "ls_nop_features", "ls_nop_warmstart"):
         getattr(L, name).restype = C.c_int
     for name in ("ls_setup", "ls_matvec", "ls_apply_V", "ls_precond_apply", "ls_rhs_planewave", "ls_solve",
-                 "ls_stats", "ls_plan_describe", "ls_profile_enable", "ls_profile_read", "ls_green_table"):
+                 "ls_stats", "ls_plan_describe", "ls_profile_enable", "ls_profile_read", "ls_green_table",
+                 "ls_solve_queue", "ls_autotune"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -132,6 +139,7 @@ class Options:
     max_refine: int = 10
     build_fp32: int = 1
     hodlr_rank_div: int = 0
+    graph_iters: int = 0
 
     def _c(self) -> _Options:
         o = _Options()
@@ -256,6 +264,11 @@ class Problem:
                 "relres0": i.relres0} for i in infos]
         return psi, out
 
+    def autotune(self, stream=None) -> dict:
+        t = _TuneInfo()
+        _check(lib().ls_autotune(self._h, C.byref(t), _stream(stream)))
+        return {"gs_rows": t.gs_rows, "hodlr_rows": t.hodlr_rows, "gs_us": list(t.gs_us), "pc_us": list(t.pc_us)}
+
     def stats(self) -> dict:
         s = _Stats()
         _check(lib().ls_stats(self._h, C.byref(s)))
@@ -357,3 +370,28 @@ def nop_warmstart(n: int, L: float, q_dev, kappa: float, theta: float, O, f, psi
                                   None if O is None else O.data_ptr(), f.data_ptr(), psi0.data_ptr(),
                                   _stream(stream)))
     return psi0
+
+
+def _info_dict(i) -> dict:
+    return {"iters": i.iters, "relres": i.relres, "status": STATUS.get(i.status, str(i.status)),
+            "n_refine": i.n_refine, "t_solve_ms": i.t_solve_ms, "relres0": i.relres0}
+
+
+def solve_queue(problems, fs, tol: float = 1e-8, prec: int = -1, nworkers: int = 0, graph_iters: int = 0):
+    """ls_solve_queue: one right-hand side per problem (complex128 CUDA tensors of N_p entries);
+    returns the solutions and one info dict per problem."""
+    import torch
+    n = len(problems)
+    if len(fs) != n:
+        raise ValueError("one right-hand side per problem")
+    psis = [torch.zeros_like(f) for f in fs]
+    for P, f in zip(problems, fs):
+        if f.dtype != torch.complex128 or not f.is_cuda or f.numel() != P.N or not f.is_contiguous():
+            raise ValueError("right-hand sides must be contiguous complex128 CUDA tensors of N entries")
+    hs = (C.c_void_p * n)(*[P._h.value for P in problems])
+    fp = (C.c_void_p * n)(*[f.data_ptr() for f in fs])
+    pp = (C.c_void_p * n)(*[p.data_ptr() for p in psis])
+    infos = (_Info * n)()
+    _check(lib().ls_solve_queue(hs, n, fp, pp, float(tol), int(prec), int(nworkers), int(graph_iters), infos))
+    return psis, [_info_dict(i) for i in infos]
+
