@@ -82,6 +82,8 @@ typedef struct {
                          Givens rotations and stop test on the device), captured into a HIP graph of
                          this many iterations and replayed, one host synchronisation per replay;
                          0: one host round trip per iteration (default 0) */
+  int stencil_mfma;   /* 1 (default): every DAFMM pass (near field, P2M, M2M, M2L, L2L, L2P) on the
+                         matrix cores (16x16x4 MFMA); 0: the same sums on the vector ALUs */
 } ls_options;
 
 typedef struct {

@@ -126,7 +126,8 @@ struct Phase {
   DevBuf tasks, terms, blk;
   int nblocks = 0;
   int ntasks = 0;
-  int tag = 0;  // 0 near+M2L, 1 P2M, 2 M2M, 3 L2L, 4 L2P
+  int tag = 0;        // 0 near+M2L, 1 P2M, 2 M2M, 3 L2L, 4 L2P
+  bool mfma = false;  // matrix-core form of the stencil
 };
 
 struct FmmDev {
@@ -404,6 +405,40 @@ void build_phases(ls_problem* P, FmmDev& F) {
     ph.nblocks = (int)blk.size();
     ph.ntasks = (int)tasks.size();
   };
+  // matrix-core form: 16-row tiles, k in 4-deep blocks, kps waves per box sub-tile split the
+  // blocks (more splitting for long tasks and for levels with at most 16 boxes per class)
+  auto make_phase_mfma = [&](Phase& ph, std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms) {
+    std::vector<int> blk;
+    for (size_t t = 0; t < tasks.size(); ++t) {
+      lsk::DTask& tk = tasks[t];
+      int kb = 0;
+      for (int q = tk.t0; q < tk.t1; ++q) {
+        terms[q].kbase = kb;
+        kb += (terms[q].K + 3) / 4;
+      }
+      tk.ktot = kb;
+      tk.Mpad = round_up(std::max(tk.M, 1), lsk::kRowBlock);
+      tk.nrb = (tk.M + 15) / 16;
+      const int nbox = tk.nh * tk.nh;
+      tk.kps = (nbox <= 16 || kb > 160) ? 4 : (kb > 48 ? 2 : 1);
+      const int per = 16 * (4 / tk.kps);
+      const int nbb = (nbox + per - 1) / per;
+      tk.blk0 = (int)blk.size();
+      for (int i = 0; i < nbb * tk.nrb; ++i) blk.push_back((int)t);
+    }
+    ph.tasks.upload(tasks);
+    ph.terms.upload(terms);
+    ph.blk.upload(blk);
+    ph.nblocks = (int)blk.size();
+    ph.ntasks = (int)tasks.size();
+    ph.mfma = true;
+  };
+  auto mk_phase = [&](Phase& ph, std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms) {
+    if (P->opt.stencil_mfma)
+      make_phase_mfma(ph, tasks, terms);
+    else
+      make_phase(ph, tasks, terms);
+  };
   auto shift_term = [&](int c, Off d, int nh_in) {
     lsk::DTerm tm{};
     int ca = c >> 1, cb = c & 1;
@@ -474,7 +509,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
         }
       }
     }
-    make_phase(F.nearm2l, tasks, terms);
+    mk_phase(F.nearm2l, tasks, terms);
     F.nearm2l.tag = 0;
   }
   if (p.top > leaf) return;
@@ -502,7 +537,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
       tk.t1 = (int)terms.size();
       tasks.push_back(tk);
     }
-    make_phase(F.p2m, tasks, terms);
+    mk_phase(F.p2m, tasks, terms);
     F.p2m.tag = 1;
   }
   // ---- L2P (accumulates onto the near field) ----
@@ -529,7 +564,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
       tk.t1 = (int)terms.size();
       tasks.push_back(tk);
     }
-    make_phase(F.l2p, tasks, terms);
+    mk_phase(F.l2p, tasks, terms);
     F.l2p.tag = 4;
   }
   // ---- M2M (parent nu from children nu+1), deepest first ----
@@ -567,7 +602,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
         if (tk.M > 0) tasks.push_back(tk);
       }
     }
-    make_phase(F.up[leaf - 1 - nu], tasks, terms);
+    mk_phase(F.up[leaf - 1 - nu], tasks, terms);
     F.up[leaf - 1 - nu].tag = 2;
   }
   // ---- L2L (parent nu -> children nu+1), top first ----
@@ -605,7 +640,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
         if (tk.M > 0) tasks.push_back(tk);
       }
     }
-    make_phase(F.down[nu - p.top], tasks, terms);
+    mk_phase(F.down[nu - p.top], tasks, terms);
     F.down[nu - p.top].tag = 3;
   }
 }
@@ -635,6 +670,17 @@ void ensure_fmm_capacity(ls_problem* P, FmmDev& F, int nrhs) {
 
 void run_phase(ls_problem* P, FmmDev& F, Phase& ph, int nrhs, hipStream_t s, int prof_cls = -1) {
   if (ph.nblocks == 0) return;
+  if (ph.mfma) {
+    if (prof_cls >= 0) {
+      ProfScope ps(P, prof_cls, s);
+      lsk::launch_stencil_mfma(F.fp32, ph.tasks.as<lsk::DTask>(), ph.terms.as<lsk::DTerm>(), ph.blk.as<int>(),
+                               ph.nblocks, nrhs, s);
+    } else {
+      lsk::launch_stencil_mfma(F.fp32, ph.tasks.as<lsk::DTask>(), ph.terms.as<lsk::DTerm>(), ph.blk.as<int>(),
+                               ph.nblocks, nrhs, s);
+    }
+    return;
+  }
   if (prof_cls >= 0) {
     ProfScope ps(P, prof_cls, s);
     lsk::launch_stencil(ph.tag, F.fp32, ph.tasks.as<lsk::DTask>(), ph.terms.as<lsk::DTerm>(), ph.blk.as<int>(),
@@ -1506,6 +1552,7 @@ void ls_default_options(ls_options* o) {
   o->build_fp32 = 1;
   o->hodlr_rank_div = 0;
   o->graph_iters = 0;
+  o->stencil_mfma = 1;
 }
 
 const char* ls_last_error(void) { return g_last_error.c_str(); }
@@ -1522,6 +1569,7 @@ static void validate_options(const ls_options& o) {
   if (o.max_refine < 1) throw LsError(LS_EINVAL, "max_refine must be >= 1");
   if (o.hodlr_rank_div < 0) throw LsError(LS_EINVAL, "hodlr_rank_div must be >= 0");
   if (o.graph_iters < 0 || o.graph_iters > 64) throw LsError(LS_EINVAL, "graph_iters must be in [0, 64]");
+  if (o.stencil_mfma != 0 && o.stencil_mfma != 1) throw LsError(LS_EINVAL, "stencil_mfma must be 0 or 1");
 }
 
 ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt, ls_plan_info* out) {

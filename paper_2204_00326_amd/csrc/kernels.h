@@ -29,9 +29,10 @@ struct DTask {
   int cout;          // output class
   int t0, t1;        // term range
   int beta;          // 0: overwrite, 1: accumulate
-  int nrb;           // row blocks = Mpad / kRowBlock
+  int nrb;           // row blocks = Mpad / kRowBlock (MFMA form: 16-row tiles)
   int blk0;          // first workgroup of this task
-  int ktot;          // sum of K over the task's terms
+  int ktot;          // sum of K over the task's terms (MFMA form: of the 4-deep k-blocks)
+  int kps;           // MFMA form: waves of a workgroup that split the k-blocks (1, 2 or 4)
 };
 
 constexpr int kRowBlock = 8;
@@ -39,6 +40,10 @@ constexpr int kBoxBlock = 64;
 constexpr int kStencilWaves = 4;
 constexpr int kStencilThreads = 64 * kStencilWaves;
 
+// MFMA form of the stencil (any term modes): a workgroup computes 16 rows x (64 / kps)
+// boxes; complex products as four real 16x16x4 matrix-core operations per k-block.
+void launch_stencil_mfma(bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
+                         int nrhs, hipStream_t s);
 void launch_stencil(int tag, bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
                     int nrhs, hipStream_t s);
 

@@ -249,6 +249,216 @@ void launch_stencil(int tag, bool fp32, const DTask* tasks, const DTerm* terms, 
 }
 
 // =====================================================================================
+// Stencil GEMM on the matrix cores.  For one task (output level/direction/class) and one
+// 16-row tile of the output, out[m][box] = sum_terms sum_k op_t[k][m] in_t[k][src_t(box)] is a
+// sum of 16 x 4 by 4 x 16 products, one per 4-deep k-block of a term (a term's K is padded to
+// the block by zeros).  Complex entries: Re += Ar Xr - Ai Xi, Im += Ar Xi + Ai Xr, four real
+// 16x16x4 MFMAs.  A workgroup's 4 waves cover 64 / kps boxes in sub-tiles of 16 boxes, and
+// kps waves per sub-tile split the task's k-blocks; the parts are summed through LDS in a fixed
+// order (deterministic).  Lane l: A element (row l % 16, k l / 16), B element (k l / 16,
+// box l % 16); the accumulator element v of lane l is (row l/16 + 4v) for FP64 and
+// (row 4(l/16) + v) for FP32, box l % 16.  Loads use clamped in-range addresses and are
+// zeroed by selects, so all of a block's loads can be in flight together.
+// =====================================================================================
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+typedef float mf32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<double> {
+  using type = mf64x4;
+  __device__ static inline mf64x4 mma(double a, double b, mf64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct MfmaAcc<float> {
+  using type = mf32x4;
+  __device__ static inline mf32x4 mma(float a, float b, mf32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_stencil_mfma(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms,
+                                                      const int* __restrict__ blk_task) {
+  using C2 = typename P2<T>::type;
+  using MA = MfmaAcc<T>;
+  using V4 = typename MA::type;
+  __shared__ T red[3][8][64];
+  const int blk = blockIdx.x;
+  const int rhs = blockIdx.y;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int ti = __builtin_amdgcn_readfirstlane(blk_task[blk]);
+  const DTask& tk = tasks[ti];
+  const int local = blk - tk.blk0;
+  const int rt = local % tk.nrb;
+  const int bb = local / tk.nrb;
+  const int kps = tk.kps;             // 1, 2 or 4
+  const int nsub = 4 / kps;           // box sub-tiles per workgroup
+  const int sub = wave % nsub, kpart = wave / nsub;
+  const int nh = tk.nh, nbox = nh * nh;
+  const int li = lane & 15, lk = lane >> 4;
+  const int box = (bb * nsub + sub) * 16 + li;
+  const bool bact = box < nbox;
+  const int ha = bact ? box / nh : 0;
+  const int hb = bact ? box - ha * nh : 0;
+  const int mrow = rt * 16 + li;
+  const bool arow = mrow < tk.M;
+  const long long mcl = arow ? mrow : 0;
+  V4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+  const int nblk = tk.ktot;
+  const int b0 = (int)(((long long)nblk * kpart) / kps);
+  const int b1 = (int)(((long long)nblk * (kpart + 1)) / kps);
+  // Prefetch cursor over (term, block) pairs, running 4 blocks ahead of the products so that
+  // a block's loads are in flight while the three blocks before it are multiplied.
+  int t = tk.t0;
+  while (t < tk.t1 && terms[t].kbase + ((terms[t].K + 3) >> 2) <= b0) ++t;  // skips empty terms too
+  int pb = 0, pnb = 0, pK = 0;     // block inside the term, blocks and K of the term
+  bool pok = false;
+  const C2* pin = nullptr;
+  const C2* pop = nullptr;
+  long long pks = 0;
+  auto open_term = [&](int tt, int first_block) {
+    const DTerm& tm = terms[tt];
+    pK = tm.K;
+    pnb = (tm.K + 3) >> 2;
+    pb = first_block;
+    const int nhi = tm.nh_in;
+    const long long plane = (long long)nhi * nhi;
+    long long src = 0;
+    bool ok = bact;
+    switch (tm.mode) {
+      case MODE_SAME:
+        src = (long long)tk.cout * plane + box;
+        break;
+      case MODE_SHIFT: {
+        const int sa = ha + tm.sha, sb = hb + tm.shb;
+        ok = ok && sa >= 0 && sa < nhi && sb >= 0 && sb < nhi;
+        src = (long long)tm.cin * plane + (long long)sa * nhi + sb;
+      } break;
+      case MODE_CHILD: {
+        const int pa = 2 * ha + (tk.cout >> 1), pc = 2 * hb + (tk.cout & 1);
+        src = (long long)tm.cin * plane + (long long)pa * nhi + pc;
+      } break;
+      default: {
+        const int pc = ((ha & 1) << 1) | (hb & 1);
+        src = (long long)pc * plane + (long long)(ha >> 1) * nhi + (hb >> 1);
+      } break;
+    }
+    pok = ok;
+    if (!ok) src = 0;
+    pin = reinterpret_cast<const C2*>(tm.in) + rhs * tm.in_rhs + src;
+    pop = reinterpret_cast<const C2*>(tm.op) + mcl;
+    pks = 4 * plane;
+  };
+  if (b0 < b1) open_term(t, b0 - terms[t].kbase);
+  const long long Mp = tk.Mpad;
+  // fetch the next block into (a, x) with its validity flags; past b1 the slot is empty
+  int g = b0;  // global index of the next block to fetch
+  auto fetch = [&](C2& a, C2& x, bool& va, bool& vx) {
+    if (g >= b1) {
+      va = vx = false;
+      a.x = a.y = 0;
+      x.x = x.y = 0;
+      return;
+    }
+    const int k = 4 * pb + lk;
+    const bool vk = k < pK;
+    a = pop[(long long)(vk ? k : 0) * Mp];
+    x = pin[(long long)(vk ? k : 0) * pks];
+    va = vk && arow;
+    vx = vk && pok;
+    ++g;
+    if (++pb == pnb && g < b1) {
+      do ++t;
+      while (terms[t].K == 0);  // empty terms own no blocks
+      open_term(t, 0);
+    }
+  };
+  auto mac = [&](const C2& a, const C2& x, bool va, bool vx) {
+    const T zr = 0;
+    const T ar = va ? a.x : zr, ai = va ? a.y : zr;
+    const T xr = vx ? x.x : zr, xi = vx ? x.y : zr;
+    cre = MA::mma(ar, xr, cre);
+    cim = MA::mma(ar, xi, cim);
+    cre = MA::mma(-ai, xi, cre);
+    cim = MA::mma(ai, xr, cim);
+  };
+  if (b0 < b1) {
+    C2 a0, a1, a2, a3, x0, x1, x2, x3;
+    bool va0, va1, va2, va3, vx0, vx1, vx2, vx3;
+    fetch(a0, x0, va0, vx0);
+    fetch(a1, x1, va1, vx1);
+    fetch(a2, x2, va2, vx2);
+    fetch(a3, x3, va3, vx3);
+    for (int c = b0; c < b1; c += 4) {
+      mac(a0, x0, va0, vx0);
+      fetch(a0, x0, va0, vx0);
+      mac(a1, x1, va1, vx1);
+      fetch(a1, x1, va1, vx1);
+      mac(a2, x2, va2, vx2);
+      fetch(a2, x2, va2, vx2);
+      mac(a3, x3, va3, vx3);
+      fetch(a3, x3, va3, vx3);
+    }
+  }
+  // k-parts 1..kps-1 of each sub-tile hand their sums to part 0 through LDS; waves 1..3
+  // own slots 0..2 (wave w = kpart * nsub + sub, so part 0 waves are 0..nsub-1)
+  if (kps > 1) {
+    if (wave > 0 && kpart > 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        red[wave - 1][v][lane] = cre[v];
+        red[wave - 1][4 + v][lane] = cim[v];
+      }
+    }
+    __syncthreads();
+    if (kpart != 0) return;
+    for (int q = 1; q < kps; ++q) {
+      const int w = q * nsub + sub;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        cre[v] += red[w - 1][v][lane];
+        cim[v] += red[w - 1][4 + v][lane];
+      }
+    }
+  }
+  if (!bact) return;
+  C2* out = reinterpret_cast<C2*>(tk.out) + rhs * tk.out_rhs + (long long)tk.cout * nbox + box;
+  const long long kso = 4LL * nbox;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int m = rt * 16 + MA::row(lane, v);
+    if (m < tk.M) {
+      C2 o;
+      o.x = cre[v];
+      o.y = cim[v];
+      if (tk.beta) {
+        const C2 p = out[(long long)m * kso];
+        o.x += p.x;
+        o.y += p.y;
+      }
+      out[(long long)m * kso] = o;
+    }
+  }
+}
+
+void launch_stencil_mfma(bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
+                         int nrhs, hipStream_t s) {
+  if (nblocks <= 0) return;
+  dim3 grid(nblocks, nrhs);
+  if (fp32)
+    k_stencil_mfma<float><<<grid, 256, 0, s>>>(tasks, terms, blk_task);
+  else
+    k_stencil_mfma<double><<<grid, 256, 0, s>>>(tasks, terms, blk_task);
+}
+
+// =====================================================================================
 // Offset table W(da, db) = h^2 (i/4) H0(kappa h |(da, db)|); the (0,0) entry is set on
 // the host (exact self-cell integral).
 // =====================================================================================

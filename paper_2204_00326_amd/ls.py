@@ -32,7 +32,8 @@ class _Options(C.Structure):
     _fields_ = [("leaf_max", C.c_int), ("T", C.c_double), ("sign", C.c_int), ("hodlr_rank", C.c_int),
                 ("eps_inner", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("prec", C.c_int),
                 ("inner_tol", C.c_double), ("max_refine", C.c_int), ("build_fp32", C.c_int),
-                ("hodlr_rank_div", C.c_int), ("graph_iters", C.c_int)]
+                ("hodlr_rank_div", C.c_int), ("graph_iters", C.c_int),
+                ("stencil_mfma", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -140,6 +141,7 @@ class Options:
     build_fp32: int = 1
     hodlr_rank_div: int = 0
     graph_iters: int = 0
+    stencil_mfma: int = 1
 
     def _c(self) -> _Options:
         o = _Options()
