@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--restart", type=int, default=500)
     ap.add_argument("--rank-div", type=int, default=4)
     ap.add_argument("--delta32", type=float, default=1e-4)
+    ap.add_argument("--graph-iters", type=int, default=0, help="Arnoldi steps per captured graph (0: host-driven)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
@@ -99,8 +101,11 @@ def main():
     t0 = time.perf_counter()
     P = ls.Problem(pb.points(), pb.q, kappa, 1e-10,
                    ls.Options(hodlr_rank=args.rank, hodlr_rank_div=args.rank_div, prec=ls.LS_MIXED,
-                              eps_inner=1e-7, inner_tol=args.delta32, restart=args.restart, maxit=2000))
+                              eps_inner=1e-7, inner_tol=args.delta32, restart=args.restart, maxit=2000,
+                              graph_iters=args.graph_iters))
+    tune = P.autotune() if args.autotune else None
     t_setup = time.perf_counter() - t0
+    log("autotune", tune)
     st = P.stats()
     log(f"setup {t_setup:.2f} s", st)
     f = P.rhs_planewave([0.0])

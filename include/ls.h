@@ -84,6 +84,10 @@ typedef struct {
                          0: one host round trip per iteration (default 0) */
   int stencil_mfma;   /* 1 (default): every DAFMM pass (near field, P2M, M2M, M2L, L2L, L2P) on the
                          matrix cores (16x16x4 MFMA); 0: the same sums on the vector ALUs */
+  int pc_bf16;        /* 1 (default): also keep the HODLR off-diagonal factors in complex bfloat16 and
+                         use them in LS_MIXED solves and LS_MIXED preconditioner applies (half the
+                         traffic of complex64; flexible GMRES absorbs the inexact preconditioner);
+                         0: LS_MIXED uses the complex64 factors */
 } ls_options;
 
 typedef struct {
@@ -160,8 +164,10 @@ ls_status ls_matvec(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld,
 ls_status ls_apply_V(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld, int prec, void* stream);
 
 /* z = A~^{-1} r with the fixed-rank HODLR approximation A~ of A (Section 5, Eq. (eq:hybrid)).
- * prec LS_FP64: all factors complex128; LS_FP32: off-diagonal factors stored complex64,
- * leaf and SMW core solves complex128.  LS_ENOTSUP when hodlr_rank = 0. */
+ * prec LS_FP64: all factors complex128; LS_FP32: off-diagonal factors stored complex64;
+ * LS_MIXED: off-diagonal factors complex bfloat16 when pc_bf16 = 1 (else complex64); leaf
+ * and SMW core solves complex128 and all sums in FP64 in every case.  LS_ENOTSUP when
+ * hodlr_rank = 0. */
 ls_status ls_precond_apply(ls_problem* P, const void* r, void* z, int nrhs, int64_t ld, int prec, void* stream);
 
 /* f_j = -s kappa^2 q u_inc(theta_j), u_inc = exp(i kappa (cos t x1 + sin t x2)) (Section 5.2).

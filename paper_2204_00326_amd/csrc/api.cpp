@@ -164,7 +164,8 @@ struct HodlrDev {
   std::vector<int> rank;  // per binary level
   long long N = 0;
   DevBuf Dinv, ident;
-  std::vector<DevBuf> Y64, W64, Y32, W32, coreinv;
+  std::vector<DevBuf> Y64, W64, Y32, W32, Y16, W16, coreinv;  // 16: complex bfloat16
+  bool have16 = false;
   DevBuf partial, svec;
   std::vector<long long> chunk;  // per level
   std::vector<int> nchunks, cpc;
@@ -732,7 +733,7 @@ void hodlr_ensure_ws(ls_problem* P, int nrhs) {
 
 // z = (partial) HODLR inverse applied to b (Morton order): leaf solves, then levels
 // Lb-1 .. lstop.  b and z may be the same buffer.
-void hodlr_apply(ls_problem* P, bool fp32, const double2* b, long long ldb, double2* z, long long ldz, int nrhs,
+void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double2* z, long long ldz, int nrhs,
                  int lstop, hipStream_t s) {
   HodlrDev& H = P->hod;
   hodlr_ensure_ws(P, nrhs);
@@ -742,19 +743,19 @@ void hodlr_apply(ls_problem* P, bool fp32, const double2* b, long long ldb, doub
                            s);
   }
   for (int l = H.Lb - 1; l >= lstop; --l) {
-    const void* W = fp32 ? H.W32[l].p : H.W64[l].p;
-    const void* Y = fp32 ? H.Y32[l].p : H.Y64[l].p;
+    const void* W = fmt == 2 ? H.W16[l].p : (fmt == 1 ? H.W32[l].p : H.W64[l].p);
+    const void* Y = fmt == 2 ? H.Y16[l].p : (fmt == 1 ? H.Y32[l].p : H.Y64[l].p);
     int nodes = 1 << l;
     const int rl = H.rank[l];
     if (rl == 0) continue;
     {
       ProfScope pd(P, 5, s);
-      lsk::launch_hodlr_dot(fp32, W, z, ldz, H.partial.as<double2>(), H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s);
+      lsk::launch_hodlr_dot(fmt, W, z, ldz, H.partial.as<double2>(), H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s);
     }
     lsk::launch_hodlr_core(H.partial.as<double2>(), H.coreinv[l].as<double2>(), H.svec.as<double2>(), rl, nodes,
                            H.cpc[l], H.nchunks[l], true, nrhs, s);
     ProfScope ps(P, 1, s);
-    lsk::launch_hodlr_update(fp32, Y, H.svec.as<double2>(), z, ldz, H.N, rl, H.N >> l, nodes, nrhs, s);
+    lsk::launch_hodlr_update(fmt, Y, H.svec.as<double2>(), z, ldz, H.N, rl, H.N >> l, nodes, nrhs, s);
   }
   hip_check(hipGetLastError(), "hodlr kernels");
 }
@@ -880,9 +881,9 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
   for (int l = H.Lb - 1; l >= 0; --l) {
     const int r = H.rank[l];
     double2* Y = H.Y64[l].as<double2>();
-    hodlr_apply(P, false, Y, N, Y, N, r, l + 1, s);
+    hodlr_apply(P, 0, Y, N, Y, N, r, l + 1, s);
     int nodes = 1 << l;
-    lsk::launch_hodlr_dot(false, H.W64[l].p, Y, N, H.partial.as<double2>(), N, r, H.chunk[l], H.nchunks[l], r, s);
+    lsk::launch_hodlr_dot(0, H.W64[l].p, Y, N, H.partial.as<double2>(), N, r, H.chunk[l], H.nchunks[l], r, s);
     lsk::launch_hodlr_core(H.partial.as<double2>(), nullptr, H.svec.as<double2>(), r, nodes, H.cpc[l], H.nchunks[l],
                            false, r, s);
     std::vector<zd> t((size_t)r * nodes * 2 * r);
@@ -918,6 +919,19 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     lsk::launch_cast(true, H.W64[l].p, H.W32[l].p, (long long)N * r, s);
     H.bytes += (int64_t)2 * N * r * 8;
   }
+  if (P->opt.pc_bf16) {
+    H.Y16.resize(H.Lb);
+    H.W16.resize(H.Lb);
+    for (int l = 0; l < H.Lb; ++l) {
+      const int r = H.rank[l];
+      H.Y16[l].alloc((size_t)N * r * 4);
+      H.W16[l].alloc((size_t)N * r * 4);
+      lsk::launch_cast_bf16(H.Y64[l].p, H.Y16[l].p, (long long)N * r, s);
+      lsk::launch_cast_bf16(H.W64[l].p, H.W16[l].p, (long long)N * r, s);
+      H.bytes += (int64_t)2 * N * r * 4;
+    }
+    H.have16 = true;
+  }
   hip_check(hipDeviceSynchronize(), "hodlr cast");
 }
 
@@ -932,7 +946,7 @@ struct GmresCfg {
   bool x_zero = false;          // the initial guess is zero (skip the first product)
   bool op32 = false;     // FP32 operator
   bool pc = false;       // use the HODLR preconditioner
-  bool pc32 = false;     // FP32 off-diagonal HODLR factors
+  int pcf = 0;           // HODLR off-diagonal factors: 0 complex128, 1 complex64, 2 complex bfloat16
   int restart = 200;
   int maxit = 2000;
 };
@@ -957,7 +971,7 @@ void op_apply(ls_problem* P, bool op32, const double2* x, double2* y, int nrhs, 
 void pc_apply(ls_problem* P, const GmresCfg& cfg, const double2* x, long long ldx, double2* z, int nrhs,
               hipStream_t s) {
   if (cfg.pc)
-    hodlr_apply(P, cfg.pc32, x, ldx, z, P->N, nrhs, 0, s);
+    hodlr_apply(P, cfg.pcf, x, ldx, z, P->N, nrhs, 0, s);
   else
     lsk::launch_axpby(1.0, x, ldx, 0.0, x, ldx, z, P->N, P->N, nrhs, s);
 }
@@ -1069,7 +1083,7 @@ void gmres(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* x, int
       if (cfg.flexible) {
         double2* zj = Zb + (long long)j * N;
         if (cfg.pc)
-          hodlr_apply(P, cfg.pc32, Q + (long long)j * ldqv, ldqr, zj, ldzr, nrhs, 0, s);
+          hodlr_apply(P, cfg.pcf, Q + (long long)j * ldqv, ldqr, zj, ldzr, nrhs, 0, s);
         else
           lsk::launch_axpby(1.0, Q + (long long)j * ldqv, ldqr, 0.0, Q, ldqr, zj, ldzr, N, nrhs, s);
         fmm_apply(P, cfg.op32 || relaxed, zj, ldzr, w, N, nrhs, 1.0, P->coef, false, s);
@@ -1269,7 +1283,7 @@ void kd_key_fmm(std::vector<uintptr_t>& k, const FmmDev& F) {
 // everything a captured step depends on: sizes, modes and every device address it touches
 std::vector<uintptr_t> kd_key(ls_problem* P, const GmresCfg& cfg, bool op32, int nrhs, int steps) {
   std::vector<uintptr_t> k = {(uintptr_t)nrhs, (uintptr_t)cfg.restart, (uintptr_t)steps, (uintptr_t)cfg.flexible,
-                              (uintptr_t)cfg.pc, (uintptr_t)cfg.pc32, (uintptr_t)op32, (uintptr_t)cfg.maxit,
+                              (uintptr_t)cfg.pc, (uintptr_t)cfg.pcf, (uintptr_t)op32, (uintptr_t)cfg.maxit,
                               (uintptr_t)P->tune.gs_rows, (uintptr_t)P->tune.hodlr_rows};
   for (const DevBuf* b : {&P->kQ, &P->kZ, &P->kw, &P->kz, &P->kpart, &P->knp, &P->kd.ictl, &P->kd.dctl, &P->kd.H,
                           &P->kd.cs, &P->kd.sn, &P->kd.g, &P->kd.vin, &P->kd.tmp})
@@ -1296,7 +1310,7 @@ void kd_step(ls_problem* P, const GmresCfg& cfg, bool op32, const KdView& v, hip
   const long long hr = (long long)m * maxv;
   lsk::launch_kd_copy(Q, ldqr, ldqv, vin, N, 0, N, v.jd, v.state, nrhs, s);
   if (cfg.pc)
-    hodlr_apply(P, cfg.pc32, vin, N, z, N, nrhs, 0, s);
+    hodlr_apply(P, cfg.pcf, vin, N, z, N, nrhs, 0, s);
   else
     lsk::launch_axpby(1.0, vin, N, 0.0, vin, N, z, N, N, nrhs, s);
   if (cfg.flexible)
@@ -1553,6 +1567,7 @@ void ls_default_options(ls_options* o) {
   o->hodlr_rank_div = 0;
   o->graph_iters = 0;
   o->stencil_mfma = 1;
+  o->pc_bf16 = 1;
 }
 
 const char* ls_last_error(void) { return g_last_error.c_str(); }
@@ -1570,6 +1585,7 @@ static void validate_options(const ls_options& o) {
   if (o.hodlr_rank_div < 0) throw LsError(LS_EINVAL, "hodlr_rank_div must be >= 0");
   if (o.graph_iters < 0 || o.graph_iters > 64) throw LsError(LS_EINVAL, "graph_iters must be in [0, 64]");
   if (o.stencil_mfma != 0 && o.stencil_mfma != 1) throw LsError(LS_EINVAL, "stencil_mfma must be 0 or 1");
+  if (o.pc_bf16 != 0 && o.pc_bf16 != 1) throw LsError(LS_EINVAL, "pc_bf16 must be 0 or 1");
 }
 
 ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt, ls_plan_info* out) {
@@ -1811,7 +1827,8 @@ static void check_vec_args(ls_problem* P, const void* x, const void* y, int nrhs
 ls_status ls_matvec(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld, int prec, void* stream) {
   try {
     check_vec_args(P, x, y, nrhs, ld);
-    if (prec != LS_FP64 && prec != LS_FP32) throw LsError(LS_EINVAL, "prec must be LS_FP64 or LS_FP32");
+    if (prec != LS_FP64 && prec != LS_FP32 && prec != LS_MIXED)
+      throw LsError(LS_EINVAL, "prec must be LS_FP64, LS_FP32 or LS_MIXED");
     if (x == y) throw LsError(LS_EINVAL, "x and y must not overlap");
     fmm_apply(P, prec == LS_FP32, (const double2*)x, ld, (double2*)y, ld, nrhs, 1.0, P->coef, true,
               (hipStream_t)stream);
@@ -1824,7 +1841,8 @@ ls_status ls_matvec(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld,
 ls_status ls_apply_V(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld, int prec, void* stream) {
   try {
     check_vec_args(P, x, y, nrhs, ld);
-    if (prec != LS_FP64 && prec != LS_FP32) throw LsError(LS_EINVAL, "prec must be LS_FP64 or LS_FP32");
+    if (prec != LS_FP64 && prec != LS_FP32 && prec != LS_MIXED)
+      throw LsError(LS_EINVAL, "prec must be LS_FP64, LS_FP32 or LS_MIXED");
     if (x == y) throw LsError(LS_EINVAL, "x and y must not overlap");
     hipStream_t s = (hipStream_t)stream;
     // y = V x : epilogue with alpha = 0, coef = 1 and no contrast
@@ -1863,14 +1881,16 @@ static void ensure_ws(ls_problem* P, int nrhs) {
 ls_status ls_precond_apply(ls_problem* P, const void* r, void* z, int nrhs, int64_t ld, int prec, void* stream) {
   try {
     check_vec_args(P, r, z, nrhs, ld);
-    if (prec != LS_FP64 && prec != LS_FP32) throw LsError(LS_EINVAL, "prec must be LS_FP64 or LS_FP32");
+    if (prec != LS_FP64 && prec != LS_FP32 && prec != LS_MIXED)
+      throw LsError(LS_EINVAL, "prec must be LS_FP64, LS_FP32 or LS_MIXED");
     if (!P->have_hodlr) throw LsError(LS_ENOTSUP, "no HODLR preconditioner (hodlr_rank = 0)");
     hipStream_t s = (hipStream_t)stream;
     ensure_ws(P, nrhs);
     const long long N = P->N;
     double2* a = P->w_x.as<double2>();
     lsk::launch_permute((const double2*)r, ld, a, N, P->m2c.as<int>(), N, nrhs, false, s);
-    hodlr_apply(P, prec == LS_FP32, a, N, a, N, nrhs, 0, s);
+    const int fmt = prec == LS_FP64 ? 0 : (prec == LS_MIXED && P->hod.have16 ? 2 : 1);
+    hodlr_apply(P, fmt, a, N, a, N, nrhs, 0, s);
     lsk::launch_permute(a, N, (double2*)z, ld, P->m2c.as<int>(), N, nrhs, true, s);
     hip_check(hipGetLastError(), "precond");
     return LS_OK;
@@ -1982,7 +2002,7 @@ static void solve_impl(ls_problem* P, const void* f, void* psi, int nrhs, int64_
     std::vector<int> nref(nrhs, 0);
     if (prec == LS_FP64 || prec == LS_FP32) {
       cfg.op32 = prec == LS_FP32;
-      cfg.pc32 = prec == LS_FP32;
+      cfg.pcf = prec == LS_FP32 ? 1 : 0;
       if (graph_iters > 0)
         gmres_graph(P, cfg, fm, xm, nrhs, st, graph_iters, s);
       else
@@ -1993,7 +2013,7 @@ static void solve_impl(ls_problem* P, const void* f, void* psi, int nrhs, int64_
       // FP32 off-diagonal HODLR factors throughout; each restart recomputes the true FP64
       // residual f - A x (iterative refinement), at most max_refine restarts.
       cfg.op32 = false;
-      cfg.pc32 = true;
+      cfg.pcf = P->hod.have16 ? 2 : 1;
       cfg.flexible = true;
       cfg.relax = std::min(0.5, tol / P->opt.inner_tol);
       if (graph_iters > 0)
@@ -2098,7 +2118,8 @@ static void autotune_impl(ls_problem* P, ls_tune_info* out, hipStream_t s) {
     for (int i = 0; i < 5; ++i) {
       hodlr_chunks(P->hod, kPcRows[i]);
       hodlr_ensure_ws(P, 1);
-      info.pc_us[i] = timed([&] { hodlr_apply(P, P->have32, w.as<double2>(), N, w2.as<double2>(), N, 1, 0, s); });
+      const int fmt = P->hod.have16 ? 2 : (P->have32 ? 1 : 0);
+      info.pc_us[i] = timed([&] { hodlr_apply(P, fmt, w.as<double2>(), N, w2.as<double2>(), N, 1, 0, s); });
       if (info.pc_us[i] < best) {
         best = info.pc_us[i];
         best_pc = kPcRows[i];

@@ -66,11 +66,11 @@ void launch_planewave(const double* px, const double* py, const double* q, const
 // ---- HODLR ----
 void launch_leaf_apply(const double2* Dinv, const unsigned char* ident, const double2* b, long long ldb, double2* z,
                        long long ldz, int lp, int nleaves, int nrhs, hipStream_t s);
-void launch_hodlr_dot(bool fp32, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
+void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
                       long long chunk, int nchunks, int nrhs, hipStream_t s);
 void launch_hodlr_core(const double2* partial, const double2* coreinv, double2* sout, int r, int nodes,
                        int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s);
-void launch_hodlr_update(bool fp32, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
+void launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
                          long long nodesize, int nodes, int nrhs, hipStream_t s);
 
 // ---- Krylov vector kernels (complex128) ----
@@ -87,6 +87,8 @@ void launch_scale(const double2* w, long long ldw, const double* alpha, double2*
 void launch_axpby(double a, const double2* x, long long ldx, double b, const double2* y, long long ldy, double2* out,
                   long long ldo, long long N, int nrhs, hipStream_t s);
 void launch_cast(bool to_fp32, const void* in, void* out, long long n, hipStream_t s);
+// complex128 -> complex bfloat16 (round to nearest even)
+void launch_cast_bf16(const void* in, void* out, long long n, hipStream_t s);
 
 
 // ---- device-driven Arnoldi step (the Arnoldi index j lives in device memory) ----

@@ -18,6 +18,20 @@ template <>
 struct V2<float> {
   using type = float2;
 };
+// complex bfloat16 storage (factor matrices read at half the FP32 traffic)
+struct bf16 {};
+struct alignas(4) BF2 {
+  unsigned short x, y;
+};
+template <>
+struct V2<bf16> {
+  using type = BF2;
+};
+__device__ inline double2 to_d2(const double2& v) { return v; }
+__device__ inline double2 to_d2(const float2& v) { return make_double2((double)v.x, (double)v.y); }
+__device__ inline double2 to_d2(const BF2& v) {
+  return make_double2((double)__uint_as_float((unsigned)v.x << 16), (double)__uint_as_float((unsigned)v.y << 16));
+}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -613,7 +627,8 @@ __global__ __launch_bounds__(256) void k_tsdot(const typename V2<T>::type* __res
       for (int c = 0; c < G; ++c) a[c] = Ab[coff[c] + i];
 #pragma unroll
       for (int c = 0; c < G; ++c) {
-        const double ax = (double)a[c].x, ay = CONJ ? -(double)a[c].y : (double)a[c].y;
+        const double2 av = to_d2(a[c]);
+        const double ax = av.x, ay = CONJ ? -av.y : av.y;
         acc[2 * c] = fma(ax, xv.x, acc[2 * c]);
         acc[2 * c] = fma(-ay, xv.y, acc[2 * c]);
         acc[2 * c + 1] = fma(ax, xv.y, acc[2 * c + 1]);
@@ -649,29 +664,34 @@ __global__ __launch_bounds__(256) void k_tsdot(const typename V2<T>::type* __res
   }
 }
 
-// ncols columns, or (jdev != NULL) *jdev + 1 of at most ncols; rhs with skip[rhs] != 0 untouched
-static void tsdot(bool fp32, bool conj, const void* A, long long lda, long long lda_rhs, int ncols, const double2* x,
-                  long long ldx, double2* partial, int ldp, long long chunk, int nchunks, long long nrows, int nrhs,
-                  hipStream_t s, const int* jdev = nullptr, const int* skip = nullptr) {
+// ncols columns, or (jdev != NULL) *jdev + 1 of at most ncols; rhs with skip[rhs] != 0 untouched.
+// fmt: storage of A, 0 complex128, 1 complex64, 2 complex bfloat16.
+template <typename T>
+static void tsdot_t(bool conj, const void* A, long long lda, long long lda_rhs, int ncols, const double2* x,
+                    long long ldx, double2* partial, int ldp, long long chunk, int nchunks, long long nrows, int nrhs,
+                    hipStream_t s, const int* jdev, const int* skip) {
   const int groups = (ncols + 15) / 16;
   const int wpg = groups >= 4 ? 1 : (groups == 1 ? 4 : 2);
   const int gpb = 4 / wpg;
   dim3 grid(nchunks, (groups + gpb - 1) / gpb, nrhs);
-  if (fp32) {
-    if (conj)
-      k_tsdot<float, true><<<grid, 256, 0, s>>>((const float2*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk,
-                                               nchunks, wpg, nrows, jdev, skip);
-    else
-      k_tsdot<float, false><<<grid, 256, 0, s>>>((const float2*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk,
-                                                nchunks, wpg, nrows, jdev, skip);
-  } else {
-    if (conj)
-      k_tsdot<double, true><<<grid, 256, 0, s>>>((const double2*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk,
-                                                nchunks, wpg, nrows, jdev, skip);
-    else
-      k_tsdot<double, false><<<grid, 256, 0, s>>>((const double2*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp,
-                                                 chunk, nchunks, wpg, nrows, jdev, skip);
-  }
+  using S = typename V2<T>::type;
+  if (conj)
+    k_tsdot<T, true><<<grid, 256, 0, s>>>((const S*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk, nchunks, wpg,
+                                          nrows, jdev, skip);
+  else
+    k_tsdot<T, false><<<grid, 256, 0, s>>>((const S*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk, nchunks,
+                                           wpg, nrows, jdev, skip);
+}
+
+static void tsdot(int fmt, bool conj, const void* A, long long lda, long long lda_rhs, int ncols, const double2* x,
+                  long long ldx, double2* partial, int ldp, long long chunk, int nchunks, long long nrows, int nrhs,
+                  hipStream_t s, const int* jdev = nullptr, const int* skip = nullptr) {
+  if (fmt == 2)
+    tsdot_t<bf16>(conj, A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk, nchunks, nrows, nrhs, s, jdev, skip);
+  else if (fmt == 1)
+    tsdot_t<float>(conj, A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk, nchunks, nrows, nrhs, s, jdev, skip);
+  else
+    tsdot_t<double>(conj, A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk, nchunks, nrows, nrhs, s, jdev, skip);
 }
 
 // =====================================================================================
@@ -710,9 +730,9 @@ void launch_leaf_apply(const double2* Dinv, const unsigned char* ident, const do
 }
 
 // partial[(rhs*nchunks + chunk)*r + c] = sum_{i in chunk} W[c*N + i] z[i]
-void launch_hodlr_dot(bool fp32, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
+void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
                       long long chunk, int nchunks, int nrhs, hipStream_t s) {
-  tsdot(fp32, false, W, N, 0, r, z, ldz, partial, r, chunk, nchunks, N, nrhs, s);
+  tsdot(fmt, false, W, N, 0, r, z, ldz, partial, r, chunk, nchunks, N, nrhs, s);
 }
 
 // t = [t_A; t_B]: t_A from the chunks of the second child (rows paired with Q), t_B from
@@ -805,10 +825,11 @@ __global__ __launch_bounds__(256) void k_hodlr_update(const typename V2<T>::type
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      re = fma((double)y[c].x, x[c].x, re);
-      re = fma(-(double)y[c].y, x[c].y, re);
-      im = fma((double)y[c].x, x[c].y, im);
-      im = fma((double)y[c].y, x[c].x, im);
+      const double2 yv = to_d2(y[c]);
+      re = fma(yv.x, x[c].x, re);
+      re = fma(-yv.y, x[c].y, re);
+      im = fma(yv.x, x[c].y, im);
+      im = fma(yv.y, x[c].x, im);
     }
     __builtin_amdgcn_sched_group_barrier(0x0020, 16, 0);
     __builtin_amdgcn_sched_group_barrier(0x0002, 40, 0);
@@ -819,10 +840,12 @@ __global__ __launch_bounds__(256) void k_hodlr_update(const typename V2<T>::type
   z[rhs * ldz + i] = o;
 }
 
-void launch_hodlr_update(bool fp32, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
+void launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
                          long long nodesize, int nodes, int nrhs, hipStream_t s) {
   dim3 grid((unsigned)((N + 255) / 256), nrhs);
-  if (fp32)
+  if (fmt == 2)
+    k_hodlr_update<bf16><<<grid, 256, 0, s>>>((const BF2*)Y, sv, z, ldz, N, r, nodesize, nodes);
+  else if (fmt == 1)
     k_hodlr_update<float><<<grid, 256, 0, s>>>((const float2*)Y, sv, z, ldz, N, r, nodesize, nodes);
   else
     k_hodlr_update<double><<<grid, 256, 0, s>>>((const double2*)Y, sv, z, ldz, N, r, nodesize, nodes);
@@ -835,7 +858,7 @@ void launch_hodlr_update(bool fp32, const void* Y, const double2* sv, double2* z
 void launch_gs_dot(const double2* Q, long long ldq_vec, long long ldq_rhs, int nv, const double2* w, long long ldw,
                    double2* partial, long long N, int nchunks, int maxv, int nrhs, hipStream_t s) {
   const long long chunk = (N + nchunks - 1) / nchunks;  // the last chunk is clipped at N
-  tsdot(false, true, Q, ldq_vec, ldq_rhs, nv, w, ldw, partial, maxv, chunk, nchunks, N, nrhs, s);
+  tsdot(0, true, Q, ldq_vec, ldq_rhs, nv, w, ldw, partial, maxv, chunk, nchunks, N, nrhs, s);
 }
 
 // h[rhs*maxv + v] (+)= sum_c partial[(rhs*nchunks + c)*maxv + v]; one wave per value
@@ -1004,6 +1027,26 @@ void launch_cast(bool to_fp32, const void* in, void* out, long long n, hipStream
   k_cast<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(to_fp32 ? 1 : 0, in, out, n);
 }
 
+// complex128 -> complex bfloat16, rounding the FP32 value to nearest even in its top 16 bits
+__device__ inline unsigned short bf16_rne(double d) {
+  const unsigned u = __float_as_uint((float)d);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__global__ void k_cast_bf16(const double2* __restrict__ in, BF2* __restrict__ out, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 v = in[i];
+  BF2 o;
+  o.x = bf16_rne(v.x);
+  o.y = bf16_rne(v.y);
+  out[i] = o;
+}
+
+void launch_cast_bf16(const void* in, void* out, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  k_cast_bf16<<<(unsigned)((n + 255) / 256), 256, 0, s>>>((const double2*)in, (BF2*)out, n);
+}
+
 
 // =====================================================================================
 // Device-driven Arnoldi step.  The Arnoldi index j of the current cycle lives in device
@@ -1034,7 +1077,7 @@ void launch_kd_dot(const double2* Q, long long ldq_vec, long long ldq_rhs, int m
                    double2* partial, long long N, int nchunks, const int* jdev, const int* state, int nrhs,
                    hipStream_t s) {
   const long long chunk = (N + nchunks - 1) / nchunks;
-  tsdot(false, true, Q, ldq_vec, ldq_rhs, maxv, w, ldw, partial, maxv, chunk, nchunks, N, nrhs, s, jdev, state);
+  tsdot(0, true, Q, ldq_vec, ldq_rhs, maxv, w, ldw, partial, maxv, chunk, nchunks, N, nrhs, s, jdev, state);
 }
 
 // out[rhs*out_ldr + j*out_ldj + v] (+)= sum_c partial[(rhs*nchunks + c)*maxv + v], v <= j

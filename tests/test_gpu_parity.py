@@ -165,6 +165,21 @@ def test_precond_full_rank_is_inverse():
     assert rel(z, np.linalg.solve(A, b)) < 1e-11
 
 
+def test_precond_bf16_factors_close_to_fp64():
+    # complex bfloat16 off-diagonal factors (8-bit mantissa): the apply stays within 1e-2 of
+    # the complex128 one; complex64 factors within 1e-5
+    n, kappa = 128, 40.0
+    pb = inputs.problem_bumps(n, kappa, seed=2, count=5)
+    P = problem("bumps128-bf16", n, kappa, pb.q, hodlr_rank=15)
+    b = dev(inputs.random_vector(n * n, seed=8))
+    z64 = host(P.precond_apply(b, prec=ls.LS_FP64))
+    z32 = host(P.precond_apply(b, prec=ls.LS_FP32))
+    z16 = host(P.precond_apply(b, prec=ls.LS_MIXED))
+    say("precond bf16 vs fp64", rel(z16, z64), "fp32", rel(z32, z64))
+    assert rel(z32, z64) < 1e-5
+    assert 1e-6 < rel(z16, z64) < 1e-2
+
+
 def test_solve_gaussian32_unpreconditioned():
     n, kappa, q = gauss32()
     P = problem("gauss32-noprec", n, kappa, q, hodlr_rank=0)
