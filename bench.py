@@ -80,8 +80,10 @@ def main():
     ap.add_argument("--restart", type=int, default=500)
     ap.add_argument("--rank-div", type=int, default=4)
     ap.add_argument("--delta32", type=float, default=1e-4)
-    ap.add_argument("--graph-iters", type=int, default=0, help="Arnoldi steps per captured graph (0: host-driven)")
+    ap.add_argument("--graph-iters", type=int, default=8, help="Arnoldi steps per captured graph (0: host-driven)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false")
+    ap.add_argument("--sample-every", type=int, default=7, help="time every k-th launch of a kernel class")
+    ap.add_argument("--pc-bf16", type=int, default=1, help="bfloat16 HODLR factors in mixed solves (0: complex64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
@@ -102,8 +104,9 @@ def main():
     P = ls.Problem(pb.points(), pb.q, kappa, 1e-10,
                    ls.Options(hodlr_rank=args.rank, hodlr_rank_div=args.rank_div, prec=ls.LS_MIXED,
                               eps_inner=1e-7, inner_tol=args.delta32, restart=args.restart, maxit=2000,
-                              graph_iters=args.graph_iters))
+                              graph_iters=args.graph_iters, pc_bf16=args.pc_bf16))
     tune = P.autotune() if args.autotune else None
+    pc_fmt = "bf16" if args.pc_bf16 else "c64"
     t_setup = time.perf_counter() - t0
     log("autotune", tune)
     st = P.stats()
@@ -119,8 +122,10 @@ def main():
         solve(ls.LS_MIXED)
         log("warmup done")
     torch.cuda.synchronize()
+    # every 7th launch of each class is timed (7 is coprime with the HODLR level count, so
+    # every level is sampled alike; timed dispatches run one at a time)
     for c in ls.PROFILE_CLASSES:
-        P.profile_enable(c, True)
+        P.profile_enable(c, args.sample_every)
     infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -131,9 +136,22 @@ def main():
     t_total = time.perf_counter() - t0
     prof = {c: P.profile_read(c) for c in ls.PROFILE_CLASSES}
     for c in ls.PROFILE_CLASSES:
-        P.profile_enable(c, False)
+        P.profile_enable(c, 0)
     log("timed steps", infos)
     ms_step = 1e3 * t_total / args.steps
+
+    # the same mixed solve replayed from captured graphs (kernel timers off), outside the
+    # timed region: what a caller without timers gets
+    ms_graph = None
+    if args.graph_iters > 0:
+        solve(ls.LS_MIXED)   # capture
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            solve(ls.LS_MIXED)
+        torch.cuda.synchronize()
+        ms_graph = 1e3 * (time.perf_counter() - t1) / args.steps
+        log(f"graph-replayed mixed solve {ms_graph:.1f} ms")
 
     # FP64 comparison solve (outside the timed region)
     t1 = time.perf_counter()
@@ -162,27 +180,26 @@ def main():
     log("matvec/s", rates)
 
     # roofline of the dominant kernel class over the timed region: achieved = algorithmic
-    # bytes (or flops) of all timed launches / their summed event time
+    # bytes (or flops) per launch / average duration of the timed launches of the class
     N = n * n
     r = args.rank
     rs, lb = st["hodlr_rank_sum"], st["hodlr_levels"]
-    nap_u = prof["hodlr_update"][1] / max(lb, 1)   # preconditioner applies (one update launch per level)
-    work = {
-        # flops of one near-field + M2L launch (8 real flops per complex multiply-add)
-        # (matrix cores: 16x16x4 FP64 / FP32 MFMA)
-        "near_m2l64": ("mfma", "f64", 8.0 * (st["entries_near"] + st["entries_m2l64"]) * prof["near_m2l64"][1] / 1e12),
-        "near_m2l32": ("mfma", "f32", 8.0 * (st["entries_near"] + st["entries_m2l32"]) * prof["near_m2l32"][1] / 1e12),
-        # per apply: complex64 Y of every level (N x r_l) + z read and written per level (complex128)
-        "hodlr_update": ("hbm", None, nap_u * (N * rs * 8 + lb * 2 * N * 16) / 1e9),
-        # per apply: complex64 W of every level + z read per level
-        "hodlr_dot": ("hbm", None, nap_u * (N * rs * 8 + lb * N * 16) / 1e9),
+    fsz = {"bf16": 4, "c64": 8}[pc_fmt]   # bytes per stored HODLR factor entry in mixed solves
+    per_launch = {
+        # flops of one near-field + M2L launch (8 real flops per complex multiply-add), matrix cores
+        "near_m2l64": ("mfma", "f64", 8.0 * (st["entries_near"] + st["entries_m2l64"]) / 1e12),
+        "near_m2l32": ("mfma", "f32", 8.0 * (st["entries_near"] + st["entries_m2l32"]) / 1e12),
+        # per level launch, averaged over the levels: the level's factor (N x r_l entries) and z
+        # (complex128) read, plus z written by the update
+        "hodlr_update": ("hbm", None, (N * rs * fsz + lb * 2 * N * 16) / lb / 1e9),
+        "hodlr_dot": ("hbm", None, (N * rs * fsz + lb * N * 16) / lb / 1e9),
     }
-    cand = {c: prof[c] for c in work if prof[c][1] > 0}
+    cand = {c: prof[c] for c in per_launch if prof[c][1] > 0}
 
     def roof_of(c):
-        tot_ms, launches = cand[c]
-        bound, dt, amount = work[c]
-        achieved = amount / (tot_ms / 1e3)
+        tot_ms, timed, _ = cand[c]
+        bound, dt, amount = per_launch[c]
+        achieved = amount / (tot_ms / timed / 1e3)
         if bound == "hbm":
             return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
@@ -190,19 +207,21 @@ def main():
         return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None}
 
-    dom = max(cand, key=lambda c: cand[c][0])
+    # dominant: largest estimated total time (average timed duration x all launches)
+    dom = max(cand, key=lambda c: cand[c][0] / cand[c][1] * cand[c][2])
     roof = roof_of(dom)
-    tot_ms, launches = cand[dom]
+    tot_ms, launches, all_launches = cand[dom]
     roof["kernel"] = {"near_m2l64": "k_stencil_mfma<double> (near field + M2L launch)",
                       "near_m2l32": "k_stencil_mfma<float> (near field + M2L launch)",
-                      "hodlr_update": "k_hodlr_update<float>",
-                      "hodlr_dot": "k_tsdot<float,false> (HODLR W^T z)"}[dom]
+                      "hodlr_update": f"k_hodlr_update<{'bf16' if args.pc_bf16 else 'float'}>",
+                      "hodlr_dot": f"k_tsdot<{'bf16' if args.pc_bf16 else 'float'},false> (HODLR W^T z)"}[dom]
     roof["avg_launch_us"] = round(tot_ms / launches * 1e3, 2)
-    roof["launches"] = launches
-    roof["class_ms"] = {c: round(v[0], 3) for c, v in prof.items()}
+    roof["launches_timed"] = launches
+    roof["launches"] = all_launches
     # every measured class against its own roof (the dominant one is reported above)
     roof["classes"] = {c: dict(roof_of(c), avg_launch_us=round(cand[c][0] / cand[c][1] * 1e3, 2),
-                               launches=cand[c][1]) for c in cand}
+                               launches_timed=cand[c][1], launches=cand[c][2],
+                               est_total_ms=round(cand[c][0] / cand[c][1] * cand[c][2], 3)) for c in cand}
     for v in roof["classes"].values():
         v.pop("traffic", None)
 
@@ -217,13 +236,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 operator + c128 Krylov/refinement (mixed)",
+        "dtype": "c64 operator + bf16/c64 HODLR factors + c128 Krylov/refinement (mixed)",
         "data": "synthetic",
         "config": {"workload": f"disc{n}_k{kappa:g}_mixed_hodlr{r}", "n": n, "N": N, "kappa": kappa,
                    "contrast": "disc R=0.6 q=1", "eps_nca": 1e-10, "eps_inner": 1e-7, "hodlr_rank": r,
                    "tol": 1e-8, "nrhs": 1, "gmres_restart": args.restart, "hodlr_rank_div": args.rank_div,
-                   "fp32_relax_delta": args.delta32},
-        "time_to_1e8_ms": {"mixed": round(ms_step, 3), "fp64": round(t_fp64 * 1e3, 3)},
+                   "fp32_relax_delta": args.delta32, "hodlr_factors_mixed": pc_fmt,
+                   "gmres_driver": f"device-driven, {args.graph_iters} steps per graph" if args.graph_iters
+                   else "host-driven"},
+        "time_to_1e8_ms": {"mixed": round(ms_step, 3), "fp64": round(t_fp64 * 1e3, 3),
+                           "mixed_graph_replay": None if ms_graph is None else round(ms_graph, 3)},
         "mixed_speedup_vs_fp64": round(t_fp64 * 1e3 / ms_step, 3),
         "iters": {"mixed": infos[-1]["iters"], "fp64": info_d["iters"], "n_refine": infos[-1]["n_refine"]},
         "relres": {"mixed": infos[-1]["relres"], "fp64": info_d["relres"]},

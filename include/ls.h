@@ -227,14 +227,20 @@ const char* ls_last_error(void);
 /* Host-only: plan (quadtree, regimes, cones, lists, coverage) for an n x n grid on [-L,L]^2. */
 ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt, ls_plan_info* out);
 
-/* Kernel timing with HIP events recorded around every launch of one kernel class on
- * the launch stream: class 0 = near field + M2L launch (FP64 operator), 1 = HODLR level
- * update, 2 = HODLR leaf solve, 3 = Arnoldi dot products, 4 = near field + M2L launch
- * (FP32 operator), 5 = HODLR level dot products (W^T z).  enable = 1 starts (and clears) the
- * counters, 0 stops.  ls_profile_read synchronises and returns the summed event time
- * and the number of timed launches. */
-ls_status ls_profile_enable(ls_problem* P, int kernel_class, int enable);
-ls_status ls_profile_read(ls_problem* P, int kernel_class, double* total_ms, int64_t* launches);
+/* Kernel timing: the timed launches of one kernel class are made with AMD's extended launch,
+ * whose dispatch stamps a start and a stop event on the launch stream.  Classes: 0 = near
+ * field + M2L launch (FP64 operator), 1 = HODLR level update, 2 = HODLR leaf solve,
+ * 3 = Arnoldi dot products, 4 = near field + M2L launch (FP32 operator), 5 = HODLR level dot
+ * products (W^T z).  every > 0 starts (and clears) the counters and times every every-th
+ * launch of the class (timed dispatches run one at a time, so sparse sampling keeps the
+ * timed run close to an untimed one); 0 stops.  ls_profile_read synchronises and returns the
+ * summed time and number of the timed launches, and (all_launches, may be NULL) the number
+ * of launches of the class since enabling.  While a class is enabled, graph_iters > 0 solves
+ * enqueue their device-driven steps eagerly instead of replaying captured graphs (same
+ * kernels and launch shapes). */
+ls_status ls_profile_enable(ls_problem* P, int kernel_class, int every);
+ls_status ls_profile_read(ls_problem* P, int kernel_class, double* total_ms, int64_t* launches,
+                          int64_t* all_launches);
 
 /* ---------------------------------------------------------------------------------------
  * Learned GMRES warm start (an extension; the paper has no learned component).

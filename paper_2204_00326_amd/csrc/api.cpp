@@ -201,8 +201,10 @@ struct KrylovDev {
 
 struct ProfileClass {
   bool enabled = false;
+  int every = 1;       // time every `every`-th launch
+  int64_t count = 0;   // launches of the class since enabling
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-  size_t used = 0;
+  size_t used = 0;     // timed launches
 };
 
 }  // namespace
@@ -246,9 +248,8 @@ namespace {
 struct ProfScope {
   ProfileClass* pc;
   hipStream_t s;
-  hipEvent_t e1 = nullptr;
   ProfScope(ls_problem* P, int cls, hipStream_t st) : pc(&P->prof[cls]), s(st) {
-    if (!pc->enabled || P->capturing) {
+    if (!pc->enabled || P->capturing || (pc->count++ % pc->every) != 0) {
       pc = nullptr;
       return;
     }
@@ -259,11 +260,14 @@ struct ProfScope {
       pc->ev.push_back({a, b});
     }
     auto& pr = pc->ev[pc->used++];
-    hip_check(hipEventRecord(pr.first, s), "hipEventRecord");
-    e1 = pr.second;
+    lsk::set_next_launch_events(pr.first, pr.second);
   }
   ~ProfScope() {
-    if (pc) (void)hipEventRecord(e1, s);
+    // the wrapped code made no timed launch: drop the pair
+    if (pc && lsk::next_launch_events_pending()) {
+      lsk::clear_next_launch_events();
+      pc->used--;
+    }
   }
 };
 
@@ -1316,7 +1320,10 @@ void kd_step(ls_problem* P, const GmresCfg& cfg, bool op32, const KdView& v, hip
   if (cfg.flexible)
     lsk::launch_kd_copy(z, N, 0, P->kZ.as<double2>(), (long long)m * N, N, N, v.jd, v.state, nrhs, s);
   fmm_apply(P, op32, z, N, w, N, nrhs, 1.0, P->coef, false, s);
-  lsk::launch_kd_dot(Q, ldqv, ldqr, maxv, w, N, part, N, nch, v.jd, v.state, nrhs, s);
+  {
+    ProfScope ps(P, 3, s);
+    lsk::launch_kd_dot(Q, ldqv, ldqr, maxv, w, N, part, N, nch, v.jd, v.state, nrhs, s);
+  }
   lsk::launch_kd_finish(part, nch, maxv, H, hr, maxv, 0, v.jd, v.state, nrhs, s);
   lsk::launch_kd_axpy(Q, ldqv, ldqr, H, hr, maxv, -1.0, w, N, N, v.jd, v.state, nrhs, s);
   lsk::launch_kd_dot(Q, ldqv, ldqr, maxv, w, N, part, N, nch, v.jd, v.state, nrhs, s);
@@ -1377,6 +1384,8 @@ void gmres_graph(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* 
   std::vector<int> hi(1 + 3 * nrhs);
   std::vector<double> hd(4 * nrhs);
   bool first = true;
+  bool timed = false;
+  for (const ProfileClass& pc : P->prof) timed |= pc.enabled;
   bool relax_enabled = cfg.relax > 0;
   for (;;) {
     bool all_done = true;
@@ -1434,7 +1443,13 @@ void gmres_graph(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* 
     bool relaxed = false;
     std::vector<double> est(nrhs, 1.0);
     for (;;) {
-      hip_check(hipGraphLaunch(kd_graph(P, cfg, cfg.op32 || relaxed, v, steps), s), "hipGraphLaunch");
+      const bool use32 = cfg.op32 || relaxed;
+      if (timed) {
+        // kernel timers are on: the same steps enqueued eagerly, so every launch has its events
+        for (int i = 0; i < steps; ++i) kd_step(P, cfg, use32, v, s);
+      } else {
+        hip_check(hipGraphLaunch(kd_graph(P, cfg, use32, v, steps), s), "hipGraphLaunch");
+      }
       hip_check(hipMemcpyAsync(K.host, K.ictl.p, (size_t)(1 + 3 * nrhs) * 4, hipMemcpyDeviceToHost, s), "ctl d2h");
       hip_check(hipMemcpyAsync(est.data(), v.est, (size_t)nrhs * 8, hipMemcpyDeviceToHost, s), "est d2h");
       hip_check(hipStreamSynchronize(s), "gmres steps");
@@ -2240,17 +2255,22 @@ void ls_destroy(ls_problem* P) {
   delete P;
 }
 
-ls_status ls_profile_enable(ls_problem* P, int cls, int enable) {
-  if (!P || cls < 0 || cls > 5) {
+ls_status ls_profile_enable(ls_problem* P, int cls, int every) {
+  if (!P || cls < 0 || cls > 5 || every < 0) {
     g_last_error = "bad arguments";
     return LS_EINVAL;
   }
-  P->prof[cls].enabled = enable != 0;
-  if (enable) P->prof[cls].used = 0;
+  ProfileClass& pc = P->prof[cls];
+  pc.enabled = every != 0;
+  if (every) {
+    pc.every = every;
+    pc.used = 0;
+    pc.count = 0;
+  }
   return LS_OK;
 }
 
-ls_status ls_profile_read(ls_problem* P, int cls, double* total_ms, int64_t* launches) {
+ls_status ls_profile_read(ls_problem* P, int cls, double* total_ms, int64_t* launches, int64_t* all_launches) {
   try {
     if (!P || cls < 0 || cls > 5 || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
     ProfileClass& pc = P->prof[cls];
@@ -2263,6 +2283,7 @@ ls_status ls_profile_read(ls_problem* P, int cls, double* total_ms, int64_t* lau
     }
     *total_ms = tot;
     *launches = (int64_t)pc.used;
+    if (all_launches) *all_launches = pc.count;
     return LS_OK;
   } catch (const LsError& e) {
     return fail(e);

@@ -6,6 +6,14 @@
 
 namespace lsk {
 
+// Time the next timed kernel launch on this host thread: it is made with AMD's extended
+// launch, which stamps `start` and `stop` from the dispatch (no separate event packets).
+// Timed launches: stencil (both forms), HODLR leaf solve, HODLR level dot and update,
+// Arnoldi dot products.
+void set_next_launch_events(hipEvent_t start, hipEvent_t stop);
+bool next_launch_events_pending();
+void clear_next_launch_events();
+
 // ---- stencil GEMM: out[m][box] (+)= sum_terms sum_k op[k][m] * in[k][src(box, term)] ----
 enum TermMode { MODE_SAME = 0, MODE_SHIFT = 1, MODE_CHILD = 2, MODE_PARENT = 3 };
 

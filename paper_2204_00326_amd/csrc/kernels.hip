@@ -1,4 +1,5 @@
 // Device kernels for gfx950 (CDNA4, wave64).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -7,6 +8,32 @@
 #include "kernels.h"
 
 namespace lsk {
+
+// Timing of the next timed launch on this host thread (set by the caller): the launch is made
+// with AMD's extended launch, which stamps `start` and `stop` from the dispatch itself.
+static thread_local hipEvent_t g_next_start = nullptr, g_next_stop = nullptr;
+void set_next_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_next_start = start;
+  g_next_stop = stop;
+}
+bool next_launch_events_pending() { return g_next_start != nullptr; }
+void clear_next_launch_events() { g_next_start = g_next_stop = nullptr; }
+static inline bool take_launch_events(hipEvent_t* a, hipEvent_t* b) {
+  if (!g_next_start) return false;
+  *a = g_next_start;
+  *b = g_next_stop;
+  g_next_start = g_next_stop = nullptr;
+  return true;
+}
+// launch kernel K (a name, possibly a template-id) timed if events are pending
+#define LSK_LAUNCH(K, GRID, BLOCK, SHM, STREAM, ...)                                   \
+  do {                                                                                 \
+    hipEvent_t e0_, e1_;                                                               \
+    if (take_launch_events(&e0_, &e1_))                                                \
+      hipExtLaunchKernelGGL(K, dim3(GRID), dim3(BLOCK), SHM, STREAM, e0_, e1_, 0, __VA_ARGS__); \
+    else                                                                               \
+      K<<<GRID, BLOCK, SHM, STREAM>>>(__VA_ARGS__);                                    \
+  } while (0)
 
 template <typename T>
 struct V2;
@@ -244,10 +271,13 @@ template <int Tag>
 static void launch_stencil_t(bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
                              int nrhs, hipStream_t s) {
   dim3 grid(nblocks, nrhs);
-  if (fp32)
-    k_stencil<float, Tag><<<grid, kStencilThreads, 0, s>>>(tasks, terms, blk_task);
-  else
-    k_stencil<double, Tag><<<grid, kStencilThreads, 0, s>>>(tasks, terms, blk_task);
+  if (fp32) {
+    auto kern = k_stencil<float, Tag>;
+    LSK_LAUNCH(kern, grid, kStencilThreads, 0, s, tasks, terms, blk_task);
+  } else {
+    auto kern = k_stencil<double, Tag>;
+    LSK_LAUNCH(kern, grid, kStencilThreads, 0, s, tasks, terms, blk_task);
+  }
 }
 
 void launch_stencil(int tag, bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
@@ -466,10 +496,13 @@ void launch_stencil_mfma(bool fp32, const DTask* tasks, const DTerm* terms, cons
                          int nrhs, hipStream_t s) {
   if (nblocks <= 0) return;
   dim3 grid(nblocks, nrhs);
-  if (fp32)
-    k_stencil_mfma<float><<<grid, 256, 0, s>>>(tasks, terms, blk_task);
-  else
-    k_stencil_mfma<double><<<grid, 256, 0, s>>>(tasks, terms, blk_task);
+  if (fp32) {
+    auto kern = k_stencil_mfma<float>;
+    LSK_LAUNCH(kern, grid, 256, 0, s, tasks, terms, blk_task);
+  } else {
+    auto kern = k_stencil_mfma<double>;
+    LSK_LAUNCH(kern, grid, 256, 0, s, tasks, terms, blk_task);
+  }
 }
 
 // =====================================================================================
@@ -591,7 +624,13 @@ void launch_planewave(const double* px, const double* py, const double* q, const
 // one column group split the rows when there are fewer than 4 groups.  One wave reduction
 // per column at the end.
 // =====================================================================================
-template <typename T, bool CONJ>
+// R consecutive complex entries in one 16-byte load (R = 4 bfloat16, 2 complex64, 1 complex128)
+template <typename T, int R>
+struct alignas(16) Pack {
+  typename V2<T>::type v[R];
+};
+
+template <typename T, bool CONJ, int R = 1>
 __global__ __launch_bounds__(256) void k_tsdot(const typename V2<T>::type* __restrict__ A, long long lda,
                                                long long lda_rhs, int ncols, const double2* __restrict__ x,
                                                long long ldx, double2* __restrict__ partial, int ldp, long long chunk,
@@ -620,23 +659,28 @@ __global__ __launch_bounds__(256) void k_tsdot(const typename V2<T>::type* __res
     long long coff[G];
 #pragma unroll
     for (int c = 0; c < G; ++c) coff[c] = (long long)(c0 + c < ncols ? c0 + c : ncols - 1) * lda;
-    for (long long i = i0 + rp * 64 + lane; i < i1; i += 64 * wpg) {
-      const double2 xv = xb[i];
-      typename V2<T>::type a[G];
+    // each lane takes R consecutive rows per step (chunks and column offsets are multiples of R)
+    for (long long i = i0 + (long long)(rp * 64 + lane) * R; i < i1; i += 64LL * wpg * R) {
+      double2 xv[R];
 #pragma unroll
-      for (int c = 0; c < G; ++c) a[c] = Ab[coff[c] + i];
+      for (int q = 0; q < R; ++q) xv[q] = xb[i + q];
+      Pack<T, R> a[G];
 #pragma unroll
-      for (int c = 0; c < G; ++c) {
-        const double2 av = to_d2(a[c]);
-        const double ax = av.x, ay = CONJ ? -av.y : av.y;
-        acc[2 * c] = fma(ax, xv.x, acc[2 * c]);
-        acc[2 * c] = fma(-ay, xv.y, acc[2 * c]);
-        acc[2 * c + 1] = fma(ax, xv.y, acc[2 * c + 1]);
-        acc[2 * c + 1] = fma(ay, xv.x, acc[2 * c + 1]);
-      }
-      // schedule all G + 1 loads of the row before its FMAs (memory-level parallelism)
-      __builtin_amdgcn_sched_group_barrier(0x0020, G + 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x0002, 8 * G, 0);
+      for (int c = 0; c < G; ++c) a[c] = *reinterpret_cast<const Pack<T, R>*>(Ab + coff[c] + i);
+#pragma unroll
+      for (int c = 0; c < G; ++c)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const double2 av = to_d2(a[c].v[q]);
+          const double ax = av.x, ay = CONJ ? -av.y : av.y;
+          acc[2 * c] = fma(ax, xv[q].x, acc[2 * c]);
+          acc[2 * c] = fma(-ay, xv[q].y, acc[2 * c]);
+          acc[2 * c + 1] = fma(ax, xv[q].y, acc[2 * c + 1]);
+          acc[2 * c + 1] = fma(ay, xv[q].x, acc[2 * c + 1]);
+        }
+      // schedule all of the step's loads before its FMAs (memory-level parallelism)
+      __builtin_amdgcn_sched_group_barrier(0x0020, G + R, 0);
+      __builtin_amdgcn_sched_group_barrier(0x0002, 8 * G * R, 0);
     }
   }
 #pragma unroll
@@ -675,12 +719,16 @@ static void tsdot_t(bool conj, const void* A, long long lda, long long lda_rhs, 
   const int gpb = 4 / wpg;
   dim3 grid(nchunks, (groups + gpb - 1) / gpb, nrhs);
   using S = typename V2<T>::type;
-  if (conj)
-    k_tsdot<T, true><<<grid, 256, 0, s>>>((const S*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk, nchunks, wpg,
-                                          nrows, jdev, skip);
-  else
-    k_tsdot<T, false><<<grid, 256, 0, s>>>((const S*)A, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk, nchunks,
-                                           wpg, nrows, jdev, skip);
+  const S* As = (const S*)A;
+  if (conj) {
+    auto kern = k_tsdot<T, true>;
+    LSK_LAUNCH(kern, grid, 256, 0, s, As, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk, nchunks, wpg, nrows, jdev,
+               skip);
+  } else {
+    auto kern = k_tsdot<T, false>;
+    LSK_LAUNCH(kern, grid, 256, 0, s, As, lda, lda_rhs, ncols, x, ldx, partial, ldp, chunk, nchunks, wpg, nrows, jdev,
+               skip);
+  }
 }
 
 static void tsdot(int fmt, bool conj, const void* A, long long lda, long long lda_rhs, int ncols, const double2* x,
@@ -726,13 +774,110 @@ __global__ __launch_bounds__(64) void k_leaf_apply(const double2* __restrict__ D
 void launch_leaf_apply(const double2* Dinv, const unsigned char* ident, const double2* b, long long ldb, double2* z,
                        long long ldz, int lp, int nleaves, int nrhs, hipStream_t s) {
   dim3 grid(nleaves, nrhs);
-  k_leaf_apply<<<grid, 64, 0, s>>>(Dinv, ident, b, ldb, z, ldz, lp);
+  LSK_LAUNCH(k_leaf_apply, grid, 64, 0, s, Dinv, ident, b, ldb, z, ldz, lp);
 }
 
 // partial[(rhs*nchunks + chunk)*r + c] = sum_{i in chunk} W[c*N + i] z[i]
+// W^T z for the HODLR levels: partial[(rhs*nchunks + ch)*r + c] = sum_{i in chunk ch} W[c*N + i] z[i].
+// A segment of lc lanes (a power of two, 16 <= lc <= 64) owns one chunk and one group of 16
+// columns; each lane takes R consecutive rows per step (one 16-byte pack per column), the
+// segment is summed by butterfly shuffles, and a wave holds 64 / lc chunks: no LDS, no idle
+// waves for short chunks.
+template <typename T, int R>
+__global__ __launch_bounds__(256) void k_hodlr_dot_seg(const typename V2<T>::type* __restrict__ W, long long N, int r,
+                                                       const double2* __restrict__ z, long long ldz,
+                                                       double2* __restrict__ partial, long long chunk, int nchunks,
+                                                       int lc) {
+  constexpr int G = 16;
+  const int rhs = blockIdx.z, grp = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int spw = 64 / lc;
+  const int seg = lane / lc, sl = lane - seg * lc;
+  const long long ch = ((long long)blockIdx.x * 4 + wave) * spw + seg;
+  const bool valid = ch < nchunks;
+  const int c0 = grp * G;
+  const double2* zb = z + rhs * ldz;
+  double acc[2 * G];
+#pragma unroll
+  for (int c = 0; c < 2 * G; ++c) acc[c] = 0;
+  if (valid) {
+    long long coff[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) coff[c] = (long long)(c0 + c < r ? c0 + c : r - 1) * N;
+    const long long i0 = ch * chunk, i1 = i0 + chunk;
+    for (long long i = i0 + (long long)sl * R; i < i1; i += (long long)lc * R) {
+      double2 xv[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) xv[q] = zb[i + q];
+      Pack<T, R> a[G];
+#pragma unroll
+      for (int c = 0; c < G; ++c) a[c] = *reinterpret_cast<const Pack<T, R>*>(W + coff[c] + i);
+#pragma unroll
+      for (int c = 0; c < G; ++c)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const double2 av = to_d2(a[c].v[q]);
+          acc[2 * c] = fma(av.x, xv[q].x, acc[2 * c]);
+          acc[2 * c] = fma(-av.y, xv[q].y, acc[2 * c]);
+          acc[2 * c + 1] = fma(av.x, xv[q].y, acc[2 * c + 1]);
+          acc[2 * c + 1] = fma(av.y, xv[q].x, acc[2 * c + 1]);
+        }
+      __builtin_amdgcn_sched_group_barrier(0x0020, G + R, 0);
+      __builtin_amdgcn_sched_group_barrier(0x0002, 8 * G * R, 0);
+    }
+  }
+  // butterfly inside the segment (offsets below lc keep to it); every lane takes part
+  for (int off = lc >> 1; off > 0; off >>= 1)
+#pragma unroll
+    for (int c = 0; c < 2 * G; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+  if (!valid || sl >= G || c0 + sl >= r) return;
+  double re = 0, im = 0;
+#pragma unroll
+  for (int c = 0; c < G; ++c)
+    if (c == sl) {
+      re = acc[2 * c];
+      im = acc[2 * c + 1];
+    }
+  partial[((long long)rhs * nchunks + ch) * r + c0 + sl] = make_double2(re, im);
+}
+
+template <typename T, int R>
+static void hodlr_dot_seg(const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
+                          long long chunk, int nchunks, int nrhs, hipStream_t s) {
+  int lc = 64;
+  while (lc > chunk / R) lc >>= 1;
+  const int per_wg = 4 * (64 / lc);
+  dim3 grid((unsigned)((nchunks + per_wg - 1) / per_wg), (r + 15) / 16, nrhs);
+  using S = typename V2<T>::type;
+  const S* Ws = (const S*)W;
+  auto kern = k_hodlr_dot_seg<T, R>;
+  LSK_LAUNCH(kern, grid, 256, 0, s, Ws, N, r, z, ldz, partial, chunk, nchunks, lc);
+}
+
+// 16-byte packs when the chunk and N allow them (chunk a multiple of R holding at least 16
+// packs), single entries otherwise
+template <typename T>
+static void hodlr_dot_fmt(const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
+                          long long chunk, int nchunks, int nrhs, hipStream_t s) {
+  constexpr int RW = 16 / (int)sizeof(typename V2<T>::type);
+  if (RW > 1 && chunk % RW == 0 && N % RW == 0 && chunk / RW >= 16)
+    hodlr_dot_seg<T, RW>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s);
+  else
+    hodlr_dot_seg<T, 1>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s);
+}
+
 void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
                       long long chunk, int nchunks, int nrhs, hipStream_t s) {
-  tsdot(fmt, false, W, N, 0, r, z, ldz, partial, r, chunk, nchunks, N, nrhs, s);
+  if (chunk < 16) {  // tiny leaves: plain tall-skinny reduction
+    tsdot(fmt, false, W, N, 0, r, z, ldz, partial, r, chunk, nchunks, N, nrhs, s);
+    return;
+  }
+  if (fmt == 2)
+    hodlr_dot_fmt<bf16>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s);
+  else if (fmt == 1)
+    hodlr_dot_fmt<float>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s);
+  else
+    hodlr_dot_fmt<double>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s);
 }
 
 // t = [t_A; t_B]: t_A from the chunks of the second child (rows paired with Q), t_B from
@@ -793,8 +938,78 @@ __global__ __launch_bounds__(256) void k_hodlr_core(const double2* __restrict__ 
   }
 }
 
+// Apply form split by rows: workgroup (node, slice) sums t from the partials (every slice of a
+// node recomputes the same 2r sums, in the same order) and computes 32 rows of s = coreinv t,
+// each row's dot product split over 8 column ranges and summed through LDS in a fixed order.
+__global__ __launch_bounds__(256) void k_hodlr_core_rows(const double2* __restrict__ partial,
+                                                         const double2* __restrict__ coreinv,
+                                                         double2* __restrict__ sout, int r, int nodes, int cpc,
+                                                         int nchunks) {
+  __shared__ double2 t[128];
+  __shared__ double2 tp[256];
+  __shared__ double2 part[8][32];
+  const int node = blockIdx.x, slice = blockIdx.y, rhs = blockIdx.z;
+  const int r2 = 2 * r;
+  // t from the chunk partials: nks threads per value take every nks-th chunk, then a fixed-order sum
+  const int nks = 256 / r2;
+  if ((int)threadIdx.x < r2 * nks) {
+    const int v = threadIdx.x % r2, ks = threadIdx.x / r2;
+    const int half = v < r ? 1 : 0;  // t_A sums the second child
+    const int c = v < r ? v : v - r;
+    const long long ch0 = (long long)node * 2 * cpc + (long long)half * cpc;
+    double re = 0, im = 0;
+#pragma unroll 4
+    for (int k = ks; k < cpc; k += nks) {
+      const double2 p = partial[((long long)rhs * nchunks + ch0 + k) * r + c];
+      re += p.x;
+      im += p.y;
+    }
+    tp[ks * r2 + v] = make_double2(re, im);
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < r2) {
+    double re = 0, im = 0;
+    for (int ks = 0; ks < nks; ++ks) {
+      re += tp[ks * r2 + threadIdx.x].x;
+      im += tp[ks * r2 + threadIdx.x].y;
+    }
+    t[threadIdx.x] = make_double2(re, im);
+  }
+  __syncthreads();
+  const int li = threadIdx.x & 31, jp = threadIdx.x >> 5;
+  const int i = slice * 32 + li;
+  const int per = (r2 + 7) / 8;
+  const int j0 = jp * per, j1 = j0 + per < r2 ? j0 + per : r2;
+  const double2* Ci = coreinv + (long long)node * r2 * r2;  // column-major: (i, j) at j * r2 + i
+  double re = 0, im = 0;
+  if (i < r2) {
+#pragma unroll 4
+    for (int j = j0; j < j1; ++j) {
+      const double2 a = Ci[(long long)j * r2 + i];
+      const double2 x = t[j];
+      re = fma(a.x, x.x, re);
+      re = fma(-a.y, x.y, re);
+      im = fma(a.x, x.y, im);
+      im = fma(a.y, x.x, im);
+    }
+  }
+  part[jp][li] = make_double2(re, im);
+  __syncthreads();
+  if (jp != 0 || i >= r2) return;
+  for (int q = 1; q < 8; ++q) {
+    re += part[q][li].x;
+    im += part[q][li].y;
+  }
+  sout[((long long)rhs * nodes + node) * r2 + i] = make_double2(re, im);
+}
+
 void launch_hodlr_core(const double2* partial, const double2* coreinv, double2* sout, int r, int nodes,
                        int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s) {
+  if (apply && 2 * r <= 128) {
+    dim3 grid(nodes, (2 * r + 31) / 32, nrhs);
+    k_hodlr_core_rows<<<grid, 256, 0, s>>>(partial, coreinv, sout, r, nodes, chunks_per_child, nchunks);
+    return;
+  }
   dim3 grid(nodes, nrhs);
   k_hodlr_core<<<grid, 256, 0, s>>>(partial, coreinv, sout, r, nodes, chunks_per_child, nchunks, apply ? 1 : 0);
 }
@@ -840,15 +1055,80 @@ __global__ __launch_bounds__(256) void k_hodlr_update(const typename V2<T>::type
   z[rhs * ldz + i] = o;
 }
 
+// 16-byte-pack form: a thread owns R consecutive rows (one node half, as halves are multiples
+// of 64 rows)
+template <typename T>
+__global__ __launch_bounds__(256) void k_hodlr_update_wide(const typename V2<T>::type* __restrict__ Y,
+                                                           const double2* __restrict__ sv, double2* __restrict__ z,
+                                                           long long ldz, long long N, int r, long long nodesize,
+                                                           int nodes) {
+  constexpr int R = 16 / (int)sizeof(typename V2<T>::type);
+  const long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * R;
+  const int rhs = blockIdx.y;
+  if (i >= N) return;
+  const long long node = i / nodesize;
+  const int half = (i - node * nodesize) >= (nodesize >> 1) ? 1 : 0;
+  const double2* s = sv + ((long long)rhs * nodes + node) * 2 * r + half * r;
+  double re[R], im[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) re[q] = im[q] = 0;
+  for (int c0 = 0; c0 < r; c0 += 8) {
+    Pack<T, R> y[8];
+    double2 x[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int cc = c0 + c < r ? c0 + c : r - 1;
+      y[c] = *reinterpret_cast<const Pack<T, R>*>(Y + (long long)cc * N + i);
+      x[c] = s[cc];
+      if (c0 + c >= r) x[c] = make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const double2 yv = to_d2(y[c].v[q]);
+        re[q] = fma(yv.x, x[c].x, re[q]);
+        re[q] = fma(-yv.y, x[c].y, re[q]);
+        im[q] = fma(yv.x, x[c].y, im[q]);
+        im[q] = fma(yv.y, x[c].x, im[q]);
+      }
+    __builtin_amdgcn_sched_group_barrier(0x0020, 16, 0);
+    __builtin_amdgcn_sched_group_barrier(0x0002, 32 * R, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    double2 o = z[rhs * ldz + i + q];
+    o.x -= re[q];
+    o.y -= im[q];
+    z[rhs * ldz + i + q] = o;
+  }
+}
+
 void launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
                          long long nodesize, int nodes, int nrhs, hipStream_t s) {
+  if (fmt != 0 && N % 64 == 0 && nodesize % 128 == 0) {
+    const int R = fmt == 2 ? 4 : 2;
+    dim3 gridw((unsigned)((N / R + 255) / 256), nrhs);
+    if (fmt == 2) {
+      auto kern = k_hodlr_update_wide<bf16>;
+      LSK_LAUNCH(kern, gridw, 256, 0, s, (const BF2*)Y, sv, z, ldz, N, r, nodesize, nodes);
+    } else {
+      auto kern = k_hodlr_update_wide<float>;
+      LSK_LAUNCH(kern, gridw, 256, 0, s, (const float2*)Y, sv, z, ldz, N, r, nodesize, nodes);
+    }
+    return;
+  }
   dim3 grid((unsigned)((N + 255) / 256), nrhs);
-  if (fmt == 2)
-    k_hodlr_update<bf16><<<grid, 256, 0, s>>>((const BF2*)Y, sv, z, ldz, N, r, nodesize, nodes);
-  else if (fmt == 1)
-    k_hodlr_update<float><<<grid, 256, 0, s>>>((const float2*)Y, sv, z, ldz, N, r, nodesize, nodes);
-  else
-    k_hodlr_update<double><<<grid, 256, 0, s>>>((const double2*)Y, sv, z, ldz, N, r, nodesize, nodes);
+  if (fmt == 2) {
+    auto kern = k_hodlr_update<bf16>;
+    LSK_LAUNCH(kern, grid, 256, 0, s, (const BF2*)Y, sv, z, ldz, N, r, nodesize, nodes);
+  } else if (fmt == 1) {
+    auto kern = k_hodlr_update<float>;
+    LSK_LAUNCH(kern, grid, 256, 0, s, (const float2*)Y, sv, z, ldz, N, r, nodesize, nodes);
+  } else {
+    auto kern = k_hodlr_update<double>;
+    LSK_LAUNCH(kern, grid, 256, 0, s, (const double2*)Y, sv, z, ldz, N, r, nodesize, nodes);
+  }
 }
 
 // =====================================================================================

@@ -95,7 +95,7 @@ def lib():
     L.ls_plan_describe.argtypes = [ci, cd, cd, C.POINTER(_Options), C.POINTER(_PlanInfo)]
     L.ls_green_table.argtypes = [ci, cd, cd, vp, vp]
     L.ls_profile_enable.argtypes = [vp, ci, ci]
-    L.ls_profile_read.argtypes = [vp, ci, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.ls_profile_read.argtypes = [vp, ci, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.ls_nop_create.argtypes = [C.POINTER(_NopConfig), C.POINTER(vp)]
     L.ls_nop_param_count.argtypes = [vp]
     L.ls_nop_param_count.restype = C.c_int64
@@ -277,14 +277,17 @@ class Problem:
         _check(lib().ls_stats(self._h, C.byref(s)))
         return {f[0]: getattr(s, f[0]) for f in _Stats._fields_}
 
-    def profile_enable(self, cls: str, enable: bool = True):
-        _check(lib().ls_profile_enable(self._h, PROFILE_CLASSES[cls], int(enable)))
+    def profile_enable(self, cls: str, every: int = 1):
+        """Time every `every`-th launch of a kernel class (0 or False: stop)."""
+        _check(lib().ls_profile_enable(self._h, PROFILE_CLASSES[cls], int(every)))
 
     def profile_read(self, cls: str):
+        """(summed ms of the timed launches, timed launches, all launches since enabling)"""
         ms = C.c_double()
         n = C.c_int64()
-        _check(lib().ls_profile_read(self._h, PROFILE_CLASSES[cls], C.byref(ms), C.byref(n)))
-        return ms.value, n.value
+        a = C.c_int64()
+        _check(lib().ls_profile_read(self._h, PROFILE_CLASSES[cls], C.byref(ms), C.byref(n), C.byref(a)))
+        return ms.value, n.value, a.value
 
 
 
