@@ -69,6 +69,88 @@ def cpu_baseline(n, kappa, q, seconds=20.0):
     }
 
 
+COPY_BYTES = 256 << 20   # calibration copy: bytes read and bytes written
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_disc512_k80.txt")  # JSON text
+KERNELS_SRC = os.path.join(ROOT, "paper_2204_00326_amd", "csrc", "kernels.hip")
+# kernel names (before the argument list) of the classes the roofline may report
+# (the HBM-bound ones; the matrix-core stencil kernel serves every DAFMM pass under one name)
+COUNTED = {"hodlr_dot": "lsk::k_hodlr_dot_seg<lsk::bf16, 4>", "hodlr_update": "lsk::k_hodlr_update_wide<lsk::bf16>"}
+
+
+def _sha256(path):
+    import hashlib
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def _read_counters(path, counter):
+    """per-dispatch values of one counter from a rocprofv3 counter_collection.csv: {name: [KiB, ...]}"""
+    import csv
+    per = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            if row.get("Counter_Name") != counter:
+                continue
+            key = (row["Kernel_Name"], int(row["Dispatch_Id"]))
+            per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    out = {}
+    for (name, did), v in sorted(per.items(), key=lambda kv: kv[0][1]):
+        out.setdefault(name, []).append(v)
+    return out
+
+
+def pmc_summary(fetch_csv, write_csv, cmd_fetch, cmd_write):
+    """Turn two rocprofv3 --pmc runs of this bench (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch)
+    into HBM bytes per launch of the roofline kernels, each counter scaled by what it reads for
+    the calibration copy of COPY_BYTES (the largest copyBuffer dispatch)."""
+    fetch, write = _read_counters(fetch_csv, "FETCH_SIZE"), _read_counters(write_csv, "WRITE_SIZE")
+    def copy_val(d):
+        vals = [v for name, vs in d.items() if "copyBuffer" in name for v in vs]
+        return max(vals)
+    f_fetch = COPY_BYTES / 1024.0 / copy_val(fetch)
+    f_write = COPY_BYTES / 1024.0 / copy_val(write)
+    res = {"source_sha256": _sha256(KERNELS_SRC), "copy_bytes": COPY_BYTES,
+           "scale": {"FETCH_SIZE": f_fetch, "WRITE_SIZE": f_write}, "commands": [cmd_fetch, cmd_write], "kernels": {}}
+    for cls, prefix in COUNTED.items():
+        fv = [v for name, vs in fetch.items() if prefix + "(" in name for v in vs]
+        wv = [v for name, vs in write.items() if prefix + "(" in name for v in vs]
+        if not fv or not wv:
+            continue
+        # the last 80 % of the dispatches: the timed solves, past the autotuner's trial shapes
+        fv, wv = fv[len(fv) // 5:], wv[len(wv) // 5:]
+        fk, wk = sum(fv) / len(fv), sum(wv) / len(wv)
+        res["kernels"][cls] = {"kernel": prefix, "dispatches": len(fv), "fetch_kib": fk, "write_kib": wk,
+                               "hbm_bytes_per_launch": (fk * f_fetch + wk * f_write) * 1024.0}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(res, fh, indent=1)
+    md = TRAFFIC_FILE[:-4] + ".md"
+    with open(md, "w") as fh:
+        fh.write("# HBM traffic per launch (rocprofv3 counters), disc 512x512, kappa 80, mixed bench\n\n")
+        fh.write("Commands (repository root, one MI355X):\n\n```\n" + cmd_fetch + "\n" + cmd_write + "\n```\n\n")
+        fh.write(f"Calibration: a device copy of {COPY_BYTES >> 20} MiB reads FETCH_SIZE x {f_fetch:.4f} and "
+                 f"WRITE_SIZE x {f_write:.4f} of its true bytes; both factors are applied below.\n\n")
+        fh.write("| class | kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB per launch |\n|---|---|---:|---:|---:|---:|\n")
+        for cls, v in res["kernels"].items():
+            fh.write(f"| {cls} | `{v['kernel']}` | {v['dispatches']} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | "
+                     f"{v['hbm_bytes_per_launch'] / 1e6:.2f} |\n")
+        fh.write(f"\nkernels.hip sha256 {res['source_sha256']} (bench.py reports traffic only for this source).\n")
+    print(json.dumps(res, indent=1))
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of a class from the committed counter summary, or None when absent or
+    taken on a different kernel source"""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+        if t["source_sha256"] != _sha256(KERNELS_SRC) or cls not in t["kernels"]:
+            return None
+        return t["kernels"][cls]["hbm_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,7 +168,12 @@ def main():
     ap.add_argument("--pc-bf16", type=int, default=1, help="bfloat16 HODLR factors in mixed solves (0: complex64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"),
+                    help="summarise two rocprofv3 --pmc runs of this bench into the traffic file and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the batch axes shard without exchange; "
               "see the multi-GPU paragraph of the design notes); run with --gpus 1", file=sys.stderr)
@@ -179,6 +266,13 @@ def main():
         rates[name] = 1e3 / float(np.median(ts))
     log("matvec/s", rates)
 
+    # calibration copy of COPY_BYTES for the HBM counters (read and written once)
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
     # roofline of the dominant kernel class over the timed region: achieved = algorithmic
     # bytes (or flops) per launch / average duration of the timed launches of the class
     N = n * n
@@ -201,8 +295,12 @@ def main():
         bound, dt, amount = per_launch[c]
         achieved = amount / (tot_ms / timed / 1e3)
         if bound == "hbm":
+            tb = measured_traffic(c) if pc_fmt == "bf16" else None
             return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    # measured HBM bytes per launch (counters, copy-calibrated) vs the algorithmic bytes
+                    "traffic": None if tb is None else round(tb / 1e9, 6),
+                    "traffic_unit": "GB per launch", "algorithmic_per_launch": round(amount, 6)}
         peak = MFMA_PEAK_TFLOPS[dt]
         return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None}
@@ -213,8 +311,8 @@ def main():
     tot_ms, launches, all_launches = cand[dom]
     roof["kernel"] = {"near_m2l64": "k_stencil_mfma<double> (near field + M2L launch)",
                       "near_m2l32": "k_stencil_mfma<float> (near field + M2L launch)",
-                      "hodlr_update": f"k_hodlr_update<{'bf16' if args.pc_bf16 else 'float'}>",
-                      "hodlr_dot": f"k_tsdot<{'bf16' if args.pc_bf16 else 'float'},false> (HODLR W^T z)"}[dom]
+                      "hodlr_update": f"k_hodlr_update_wide<{'bf16' if args.pc_bf16 else 'float'}>",
+                      "hodlr_dot": f"k_hodlr_dot_seg<{'bf16, 4' if args.pc_bf16 else 'float, 2'}> (HODLR W^T z)"}[dom]
     roof["avg_launch_us"] = round(tot_ms / launches * 1e3, 2)
     roof["launches_timed"] = launches
     roof["launches"] = all_launches
@@ -222,8 +320,7 @@ def main():
     roof["classes"] = {c: dict(roof_of(c), avg_launch_us=round(cand[c][0] / cand[c][1] * 1e3, 2),
                                launches_timed=cand[c][1], launches=cand[c][2],
                                est_total_ms=round(cand[c][0] / cand[c][1] * cand[c][2], 3)) for c in cand}
-    for v in roof["classes"].values():
-        v.pop("traffic", None)
+
 
     line = {
         "metric": METRIC,

@@ -747,9 +747,13 @@ static void tsdot(int fmt, bool conj, const void* A, long long lda, long long ld
 // =====================================================================================
 __global__ __launch_bounds__(64) void k_leaf_apply(const double2* __restrict__ Dinv,
                                                    const unsigned char* __restrict__ ident,
-                                                   const double2* b, long long ldb, double2* z, long long ldz, int lp) {
+                                                   const double2* b, long long ldb, double2* z, long long ldz, int lp,
+                                                   int nrf) {
   __shared__ double2 bl[64];
-  const int leaf = blockIdx.x, rhs = blockIdx.y, t = threadIdx.x;
+  // nrf > 0: the right-hand sides are the fastest grid index, so the workgroups that use one
+  // factor block run back to back and find it in L2
+  const int leaf = nrf ? blockIdx.x / nrf : blockIdx.x, rhs = nrf ? blockIdx.x % nrf : blockIdx.y;
+  const int t = threadIdx.x;
   const long long base = (long long)leaf * lp;
   if (t < lp) bl[t] = b[rhs * ldb + base + t];
   __syncthreads();
@@ -773,11 +777,11 @@ __global__ __launch_bounds__(64) void k_leaf_apply(const double2* __restrict__ D
 
 void launch_leaf_apply(const double2* Dinv, const unsigned char* ident, const double2* b, long long ldb, double2* z,
                        long long ldz, int lp, int nleaves, int nrhs, hipStream_t s) {
-  dim3 grid(nleaves, nrhs);
-  LSK_LAUNCH(k_leaf_apply, grid, 64, 0, s, Dinv, ident, b, ldb, z, ldz, lp);
+  const int nrf = nrhs > 1 ? nrhs : 0;
+  dim3 grid(nrf ? nleaves * nrhs : nleaves, nrf ? 1 : nrhs);
+  LSK_LAUNCH(k_leaf_apply, grid, 64, 0, s, Dinv, ident, b, ldb, z, ldz, lp, nrf);
 }
 
-// partial[(rhs*nchunks + chunk)*r + c] = sum_{i in chunk} W[c*N + i] z[i]
 // W^T z for the HODLR levels: partial[(rhs*nchunks + ch)*r + c] = sum_{i in chunk ch} W[c*N + i] z[i].
 // A segment of lc lanes (a power of two, 16 <= lc <= 64) owns one chunk and one group of 16
 // columns; each lane takes R consecutive rows per step (one 16-byte pack per column), the
@@ -787,13 +791,15 @@ template <typename T, int R>
 __global__ __launch_bounds__(256) void k_hodlr_dot_seg(const typename V2<T>::type* __restrict__ W, long long N, int r,
                                                        const double2* __restrict__ z, long long ldz,
                                                        double2* __restrict__ partial, long long chunk, int nchunks,
-                                                       int lc) {
+                                                       int lc, int nrf) {
   constexpr int G = 16;
-  const int rhs = blockIdx.z, grp = blockIdx.y;
+  // nrf > 0: right-hand sides fastest in grid.x (factor tiles reused from L2 across them)
+  const int rhs = nrf ? blockIdx.x % nrf : blockIdx.z, grp = blockIdx.y;
+  const long long bx = nrf ? blockIdx.x / nrf : blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int spw = 64 / lc;
   const int seg = lane / lc, sl = lane - seg * lc;
-  const long long ch = ((long long)blockIdx.x * 4 + wave) * spw + seg;
+  const long long ch = (bx * 4 + wave) * spw + seg;
   const bool valid = ch < nchunks;
   const int c0 = grp * G;
   const double2* zb = z + rhs * ldz;
@@ -847,11 +853,13 @@ static void hodlr_dot_seg(const void* W, const double2* z, long long ldz, double
   int lc = 64;
   while (lc > chunk / R) lc >>= 1;
   const int per_wg = 4 * (64 / lc);
-  dim3 grid((unsigned)((nchunks + per_wg - 1) / per_wg), (r + 15) / 16, nrhs);
+  const unsigned nbx = (unsigned)((nchunks + per_wg - 1) / per_wg);
+  const int nrf = nrhs > 1 ? nrhs : 0;
+  dim3 grid(nrf ? nbx * nrhs : nbx, (r + 15) / 16, nrf ? 1 : nrhs);
   using S = typename V2<T>::type;
   const S* Ws = (const S*)W;
   auto kern = k_hodlr_dot_seg<T, R>;
-  LSK_LAUNCH(kern, grid, 256, 0, s, Ws, N, r, z, ldz, partial, chunk, nchunks, lc);
+  LSK_LAUNCH(kern, grid, 256, 0, s, Ws, N, r, z, ldz, partial, chunk, nchunks, lc, nrf);
 }
 
 // 16-byte packs when the chunk and N allow them (chunk a multiple of R holding at least 16
@@ -944,11 +952,12 @@ __global__ __launch_bounds__(256) void k_hodlr_core(const double2* __restrict__ 
 __global__ __launch_bounds__(256) void k_hodlr_core_rows(const double2* __restrict__ partial,
                                                          const double2* __restrict__ coreinv,
                                                          double2* __restrict__ sout, int r, int nodes, int cpc,
-                                                         int nchunks) {
+                                                         int nchunks, int nrf) {
   __shared__ double2 t[128];
   __shared__ double2 tp[256];
   __shared__ double2 part[8][32];
-  const int node = blockIdx.x, slice = blockIdx.y, rhs = blockIdx.z;
+  const int node = nrf ? blockIdx.x / nrf : blockIdx.x, slice = blockIdx.y;
+  const int rhs = nrf ? blockIdx.x % nrf : blockIdx.z;
   const int r2 = 2 * r;
   // t from the chunk partials: nks threads per value take every nks-th chunk, then a fixed-order sum
   const int nks = 256 / r2;
@@ -1006,8 +1015,9 @@ __global__ __launch_bounds__(256) void k_hodlr_core_rows(const double2* __restri
 void launch_hodlr_core(const double2* partial, const double2* coreinv, double2* sout, int r, int nodes,
                        int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s) {
   if (apply && 2 * r <= 128) {
-    dim3 grid(nodes, (2 * r + 31) / 32, nrhs);
-    k_hodlr_core_rows<<<grid, 256, 0, s>>>(partial, coreinv, sout, r, nodes, chunks_per_child, nchunks);
+    const int nrf = nrhs > 1 ? nrhs : 0;
+    dim3 grid(nrf ? nodes * nrhs : nodes, (2 * r + 31) / 32, nrf ? 1 : nrhs);
+    k_hodlr_core_rows<<<grid, 256, 0, s>>>(partial, coreinv, sout, r, nodes, chunks_per_child, nchunks, nrf);
     return;
   }
   dim3 grid(nodes, nrhs);
@@ -1061,10 +1071,11 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_hodlr_update_wide(const typename V2<T>::type* __restrict__ Y,
                                                            const double2* __restrict__ sv, double2* __restrict__ z,
                                                            long long ldz, long long N, int r, long long nodesize,
-                                                           int nodes) {
+                                                           int nodes, int nrf) {
   constexpr int R = 16 / (int)sizeof(typename V2<T>::type);
-  const long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * R;
-  const int rhs = blockIdx.y;
+  const long long bx = nrf ? blockIdx.x / nrf : blockIdx.x;
+  const int rhs = nrf ? blockIdx.x % nrf : blockIdx.y;
+  const long long i = (bx * blockDim.x + threadIdx.x) * R;
   if (i >= N) return;
   const long long node = i / nodesize;
   const int half = (i - node * nodesize) >= (nodesize >> 1) ? 1 : 0;
@@ -1108,13 +1119,15 @@ void launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, 
                          long long nodesize, int nodes, int nrhs, hipStream_t s) {
   if (fmt != 0 && N % 64 == 0 && nodesize % 128 == 0) {
     const int R = fmt == 2 ? 4 : 2;
-    dim3 gridw((unsigned)((N / R + 255) / 256), nrhs);
+    const unsigned nbx = (unsigned)((N / R + 255) / 256);
+    const int nrf = nrhs > 1 ? nrhs : 0;
+    dim3 gridw(nrf ? nbx * nrhs : nbx, nrf ? 1 : nrhs);
     if (fmt == 2) {
       auto kern = k_hodlr_update_wide<bf16>;
-      LSK_LAUNCH(kern, gridw, 256, 0, s, (const BF2*)Y, sv, z, ldz, N, r, nodesize, nodes);
+      LSK_LAUNCH(kern, gridw, 256, 0, s, (const BF2*)Y, sv, z, ldz, N, r, nodesize, nodes, nrf);
     } else {
       auto kern = k_hodlr_update_wide<float>;
-      LSK_LAUNCH(kern, gridw, 256, 0, s, (const float2*)Y, sv, z, ldz, N, r, nodesize, nodes);
+      LSK_LAUNCH(kern, gridw, 256, 0, s, (const float2*)Y, sv, z, ldz, N, r, nodesize, nodes, nrf);
     }
     return;
   }

@@ -180,6 +180,20 @@ def test_precond_bf16_factors_close_to_fp64():
     assert 1e-6 < rel(z16, z64) < 1e-2
 
 
+def test_precond_multi_rhs_equals_single_columns():
+    # several right-hand sides take the right-hand-side-fastest launch shapes; each column must
+    # equal its single-column apply exactly (the same sums in the same order)
+    n, kappa = 128, 40.0
+    pb = inputs.problem_bumps(n, kappa, seed=2, count=5)
+    P = problem("bumps128-bf16", n, kappa, pb.q, hodlr_rank=15)
+    B = torch.stack([dev(inputs.random_vector(n * n, seed=20 + j)) for j in range(3)])
+    for prec in (ls.LS_FP64, ls.LS_FP32, ls.LS_MIXED):
+        Z = host(P.precond_apply(B, prec=prec))
+        for j in range(3):
+            z1 = host(P.precond_apply(B[j].contiguous(), prec=prec))
+            assert np.max(np.abs(Z[j] - z1)) <= 1e-14 * np.max(np.abs(z1)), (prec, j)
+
+
 def test_solve_gaussian32_unpreconditioned():
     n, kappa, q = gauss32()
     P = problem("gauss32-noprec", n, kappa, q, hodlr_rank=0)
