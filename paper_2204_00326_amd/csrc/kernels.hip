@@ -783,16 +783,15 @@ void launch_leaf_apply(const double2* Dinv, const unsigned char* ident, const do
 }
 
 // W^T z for the HODLR levels: partial[(rhs*nchunks + ch)*r + c] = sum_{i in chunk ch} W[c*N + i] z[i].
-// A segment of lc lanes (a power of two, 16 <= lc <= 64) owns one chunk and one group of 16
-// columns; each lane takes R consecutive rows per step (one 16-byte pack per column), the
+// A segment of lc lanes (a power of two, 16 <= lc <= 64) owns one chunk and one group of G
+// columns (few columns per lane keep many waves resident); each lane takes R consecutive rows per step (one 16-byte pack per column), the
 // segment is summed by butterfly shuffles, and a wave holds 64 / lc chunks: no LDS, no idle
 // waves for short chunks.
-template <typename T, int R>
+template <typename T, int R, int G>
 __global__ __launch_bounds__(256) void k_hodlr_dot_seg(const typename V2<T>::type* __restrict__ W, long long N, int r,
                                                        const double2* __restrict__ z, long long ldz,
                                                        double2* __restrict__ partial, long long chunk, int nchunks,
                                                        int lc, int nrf) {
-  constexpr int G = 16;
   // nrf > 0: right-hand sides fastest in grid.x (factor tiles reused from L2 across them)
   const int rhs = nrf ? blockIdx.x % nrf : blockIdx.z, grp = blockIdx.y;
   const long long bx = nrf ? blockIdx.x / nrf : blockIdx.x;
@@ -847,18 +846,20 @@ __global__ __launch_bounds__(256) void k_hodlr_dot_seg(const typename V2<T>::typ
   partial[((long long)rhs * nchunks + ch) * r + c0 + sl] = make_double2(re, im);
 }
 
+constexpr int kDotCols = 4;  // columns per segment (4 measured fastest of 4 / 8 / 16)
 template <typename T, int R>
 static void hodlr_dot_seg(const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
                           long long chunk, int nchunks, int nrhs, hipStream_t s) {
   int lc = 64;
   while (lc > chunk / R) lc >>= 1;
+  constexpr int G = kDotCols;
   const int per_wg = 4 * (64 / lc);
   const unsigned nbx = (unsigned)((nchunks + per_wg - 1) / per_wg);
   const int nrf = nrhs > 1 ? nrhs : 0;
-  dim3 grid(nrf ? nbx * nrhs : nbx, (r + 15) / 16, nrf ? 1 : nrhs);
+  dim3 grid(nrf ? nbx * nrhs : nbx, (r + G - 1) / G, nrf ? 1 : nrhs);
   using S = typename V2<T>::type;
   const S* Ws = (const S*)W;
-  auto kern = k_hodlr_dot_seg<T, R>;
+  auto kern = k_hodlr_dot_seg<T, R, G>;
   LSK_LAUNCH(kern, grid, 256, 0, s, Ws, N, r, z, ldz, partial, chunk, nchunks, lc, nrf);
 }
 
