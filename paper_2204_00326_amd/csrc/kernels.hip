@@ -784,9 +784,9 @@ void launch_leaf_apply(const double2* Dinv, const unsigned char* ident, const do
 
 // W^T z for the HODLR levels: partial[(rhs*nchunks + ch)*r + c] = sum_{i in chunk ch} W[c*N + i] z[i].
 // A segment of lc lanes (a power of two, 16 <= lc <= 64) owns one chunk and one group of G
-// columns (few columns per lane keep many waves resident); each lane takes R consecutive rows per step (one 16-byte pack per column), the
-// segment is summed by butterfly shuffles, and a wave holds 64 / lc chunks: no LDS, no idle
-// waves for short chunks.
+// columns (few columns per lane keep many waves resident); each lane takes R consecutive rows
+// per step (one 16-byte pack per column), the segment is summed by butterfly shuffles, and a
+// wave holds 64 / lc chunks: no LDS, no idle waves for short chunks.
 template <typename T, int R, int G>
 __global__ __launch_bounds__(256) void k_hodlr_dot_seg(const typename V2<T>::type* __restrict__ W, long long N, int r,
                                                        const double2* __restrict__ z, long long ldz,
@@ -1443,16 +1443,20 @@ __global__ __launch_bounds__(64) void k_kd_givens(const double* __restrict__ npa
   double* c_ = cs + (long long)rhs * m;
   double2* s_ = sn + (long long)rhs * m;
   double2* gg = g + (long long)rhs * maxv;
-  h[j + 1] = make_double2(hn, 0.0);
+  // rotation i maps (h[i], h[i+1]) to new values; the new h[i+1] is the next rotation's first
+  // entry, so it is carried in registers and only the untouched h[i+1], c_i, s_i are loaded
+  // (independent of the carry, so the loads run ahead of the chain)
+  double2 carry = h[0];
+#pragma unroll 4
   for (int i = 0; i < j; ++i) {
-    const double2 a = h[i], b = h[i + 1];
+    const double2 a = carry, b = h[i + 1];
     const double ci = c_[i];
     const double2 si = s_[i];
     const double2 sb = cmul(si, b), sa = cmul(cconj(si), a);
     h[i] = make_double2(ci * a.x + sb.x, ci * a.y + sb.y);
-    h[i + 1] = make_double2(ci * b.x - sa.x, ci * b.y - sa.y);
+    carry = make_double2(ci * b.x - sa.x, ci * b.y - sa.y);
   }
-  const double2 a = h[j], b = h[j + 1];
+  const double2 a = carry, b = make_double2(hn, 0.0);
   const double aa = cabs2(a), ab = cabs2(b);
   double cc;
   double2 ss;
