@@ -264,6 +264,9 @@ typedef struct {
   int layers;         /* spectral layers */
   int batch_max;      /* largest batch B passed to forward */
   uint64_t seed;      /* parameter initialisation */
+  int bf16;           /* 1: the channel-mixing layers (lift, 1x1 convolutions, projection, their
+                         gradients) on the matrix cores with BF16 inputs and FP32 accumulation,
+                         weights kept FP32; 0: FP32 throughout */
 } ls_nop_config;
 
 ls_status ls_nop_create(const ls_nop_config* cfg, ls_nop** out);
@@ -275,7 +278,8 @@ ls_status ls_nop_set_params(ls_nop* N, const float* host, int64_t count);
 ls_status ls_nop_get_grads(const ls_nop* N, float* host, int64_t count);
 /* O = NO(X) for B samples; keeps the activations for ls_nop_backward */
 ls_status ls_nop_forward(ls_nop* N, const float* X, float* O, int B, void* stream);
-/* parameter gradients (overwritten) of sum(dO * O) for the last forward */
+/* parameter gradients (overwritten) of sum(dO * O) for the last forward; reads that forward's
+ * input X, which must still be valid */
 ls_status ls_nop_backward(ls_nop* N, const float* dO, void* stream);
 /* per-sample loss_b = |w O_c - t|^2 / snorm2_b and dO = d(mean_b loss_b)/dO; w, t: [B][n][n]
  * complex64 with w = b/kappa^2, t = (psi - b)/kappa^2 (b the WKB start); snorm2: [B] float

@@ -20,6 +20,8 @@ struct Net {
   std::vector<float2*> act_A2;       // A2 of each layer (kept for the weight gradient)
   float2 *buf_A1 = nullptr, *buf_S = nullptr, *buf_G = nullptr;
   float *buf_dV = nullptr, *buf_dZ = nullptr;
+  float* buf_wpart = nullptr;  // BF16 mode: split partials of the channel-mixing weight gradients
+  bool bf16 = false;           // channel mixing on the matrix cores with BF16 inputs
   const float* X_last = nullptr;
   int B_last = 0;
   int step_count = 0;
@@ -30,6 +32,10 @@ struct Net {
   float2* cgrad(long long off) const { return reinterpret_cast<float2*>(grads + off); }
 
   void init_twiddles(hipStream_t s);
+  void pointwise(const float* W, const float* bias, const float* X, float* Z, int Cin, int Cout, int B,
+                 hipStream_t s);
+  void pointwise_bwd(const float* W, const float* dZ, float* dX, int Cin, int Cout, int B, hipStream_t s);
+  void wgrad(const float* dZ, const float* X, float* dW, float* db, int B, int Cin, int Cout, hipStream_t s);
   void forward(const float* X, float* O, int B, hipStream_t s);
   void backward(const float* dO, hipStream_t s);
   void loss(const float* O, const float2* w, const float2* t, const float* snorm2, float* dO, float* lossb, int B,

@@ -68,9 +68,9 @@ __global__ void k_pointwise_bwd(const float* __restrict__ W, const float* __rest
 // dW[o][c] = sum_{b,p} dZ[b][o][p] V[b][c][p]  (c < Cin);  db[o] = sum dZ[b][o][p]  (c == Cin)
 __global__ __launch_bounds__(256) void k_wgrad(const float* __restrict__ dZ, const float* __restrict__ V,
                                                float* __restrict__ dW, float* __restrict__ db, int B, int Cin,
-                                               int Cout, int P) {
+                                               int Cout, int P, int c0) {
   __shared__ float red[4];
-  const int o = blockIdx.y, c = blockIdx.x;  // c == Cin -> bias
+  const int o = blockIdx.y, c = blockIdx.x + c0;  // c == Cin -> bias
   float acc = 0.f;
   for (int b = 0; b < B; ++b) {
     const float* dz = dZ + ((long long)b * Cout + o) * P;
@@ -91,6 +91,115 @@ __global__ __launch_bounds__(256) void k_wgrad(const float* __restrict__ dZ, con
 }
 
 // ---- GELU ---------------------------------------------------------------------------------
+// ---- channel mixing on the matrix cores (BF16 inputs, FP32 accumulation) ----------------
+// v_mfma_f32_16x16x16_bf16: lane l supplies A[l % 16][4 (l / 16) + t] and B[4 (l / 16) + t][l % 16]
+// (t < 4) and receives D[4 (l / 16) + v][l % 16] (v < 4).  FP32 values are rounded to bfloat16
+// (nearest even) as they are loaded; weights stay FP32 in memory.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ inline short f2bf(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Z_b[o][p] = (accumulate ? Z_b[o][p] : 0) + bias[o] + sum_c A[o*sao + c*sac] X_b[c][p]; a wave owns
+// 16 pixels and every output row (tiles of 16), a workgroup 64 pixels of one sample.
+__global__ __launch_bounds__(256) void k_pw_mfma(const float* __restrict__ A, int sao, int sac,
+                                                 const float* __restrict__ bias, const float* __restrict__ X,
+                                                 float* __restrict__ Z, int K, int M, int P, int accumulate) {
+  constexpr int MT = 16;  // at most 256 output rows
+  const int b = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int p0 = (blockIdx.x * 4 + wave) * 16;
+  const int p = p0 + li;
+  const bool pin = p < P;
+  const float* Xb = X + (long long)b * K * P;
+  const int mt = (M + 15) / 16;
+  f32x4 acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    bf16x4 bx;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = k0 + 4 * lg + t;
+      bx[t] = f2bf((pin && k < K) ? Xb[(long long)k * P + p] : 0.f);
+    }
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti) {
+      if (ti >= mt) break;
+      const int o = ti * 16 + li;
+      bf16x4 ax;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = k0 + 4 * lg + t;
+        ax[t] = f2bf((o < M && k < K) ? A[(long long)o * sao + (long long)k * sac] : 0.f);
+      }
+      acc[ti] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ax, bx, acc[ti], 0, 0, 0);
+    }
+  }
+  if (!pin) return;
+  float* Zb = Z + (long long)b * M * P;
+#pragma unroll
+  for (int ti = 0; ti < MT; ++ti) {
+    if (ti >= mt) break;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int o = ti * 16 + 4 * lg + v;
+      if (o >= M) continue;
+      float r = acc[ti][v] + (bias ? bias[o] : 0.f);
+      float* z = Zb + (long long)o * P + p;
+      *z = accumulate ? *z + r : r;
+    }
+  }
+}
+
+// partial[split][o][c] = sum over the split's pixels of dZ_b[o][p] V_b[c][p]; split = (sample,
+// range of KS pixels); the waves of a workgroup take the 16x16 tiles of the (o, c) block in turn
+__global__ __launch_bounds__(256) void k_wgrad_mfma(const float* __restrict__ dZ, const float* __restrict__ V,
+                                                    float* __restrict__ part, int Cin, int Cout, int P, int KS,
+                                                    int nsp) {
+  const int split = blockIdx.x;
+  const int b = split / nsp, sp = split - b * nsp;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int mt = (Cout + 15) / 16, nt = (Cin + 15) / 16;
+  const int pb = sp * KS, pe = pb + KS < P ? pb + KS : P;
+  const float* dZb = dZ + (long long)b * Cout * P;
+  const float* Vb = V + (long long)b * Cin * P;
+  float* out = part + (long long)split * Cout * Cin;
+  for (int tile = wave; tile < mt * nt; tile += 4) {
+    const int o = (tile / nt) * 16 + li, c = (tile % nt) * 16 + li;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = pb; k0 < pe; k0 += 16) {
+      const int k = k0 + 4 * lg;  // 4 consecutive pixels
+      bf16x4 ax, bx;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bool kin = k + t < pe;
+        ax[t] = f2bf((o < Cout && kin) ? dZb[(long long)o * P + k + t] : 0.f);
+        bx[t] = f2bf((c < Cin && kin) ? Vb[(long long)c * P + k + t] : 0.f);
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ax, bx, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int oo = (tile / nt) * 16 + 4 * lg + v;
+      if (oo < Cout && c < Cin) out[(long long)oo * Cin + c] = acc[v];
+    }
+  }
+}
+
+// dW[e] = sum_s part[s][e] in split order (deterministic)
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int nsplit, float* __restrict__ dW, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float acc = 0.f;
+  for (int q = 0; q < nsplit; ++q) acc += part[(long long)q * n + e];
+  dW[e] = acc;
+}
+
 __global__ void k_gelu(const float* __restrict__ Z, float* __restrict__ V, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -376,15 +485,47 @@ void Net::init_twiddles(hipStream_t s) {
   k_twiddles<<<nblk((long long)n * 2 * M), 256, 0, s>>>(tw_w, tw_h, n, M);
 }
 
+// Z_b = W X_b + bias for each sample (W: Cout x Cin), on the matrix cores in BF16 mode
+void Net::pointwise(const float* W, const float* bias, const float* X, float* Z, int Cin, int Cout, int B,
+                    hipStream_t s) {
+  const int P = n * n;
+  if (bf16)
+    k_pw_mfma<<<dim3((P + 63) / 64, B), 256, 0, s>>>(W, Cin, 1, bias, X, Z, Cin, Cout, P, 0);
+  else
+    k_pointwise<<<dim3(nblk(P), Cout, B), 256, 0, s>>>(W, bias, X, Z, Cin, Cout, P, 0);
+}
+
+// dX_b = W^T dZ_b
+void Net::pointwise_bwd(const float* W, const float* dZ, float* dX, int Cin, int Cout, int B, hipStream_t s) {
+  const int P = n * n;
+  if (bf16)
+    k_pw_mfma<<<dim3((P + 63) / 64, B), 256, 0, s>>>(W, 1, Cin, nullptr, dZ, dX, Cout, Cin, P, 0);
+  else
+    k_pointwise_bwd<<<dim3(nblk(P), Cin, B), 256, 0, s>>>(W, dZ, dX, Cin, Cout, P, 0);
+}
+
+// dW = sum_b dZ_b X_b^T, db = sum_b sum_p dZ_b
+void Net::wgrad(const float* dZ, const float* X, float* dW, float* db, int B, int Cin, int Cout, hipStream_t s) {
+  const int P = n * n;
+  if (bf16) {
+    const int KS = 1024, nsp = (P + KS - 1) / KS, nsplit = B * nsp;
+    k_wgrad_mfma<<<nsplit, 256, 0, s>>>(dZ, X, buf_wpart, Cin, Cout, P, KS, nsp);
+    k_wgrad_reduce<<<nblk((long long)Cout * Cin), 256, 0, s>>>(buf_wpart, nsplit, dW, Cout * Cin);
+    k_wgrad<<<dim3(1, Cout), 256, 0, s>>>(dZ, X, dW, db, B, Cin, Cout, P, Cin);  // bias only
+  } else {
+    k_wgrad<<<dim3(Cin + 1, Cout), 256, 0, s>>>(dZ, X, dW, db, B, Cin, Cout, P, 0);
+  }
+}
+
 void Net::forward(const float* X, float* O, int B, hipStream_t s) {
   const int P = n * n, NM = 2 * M * M;
   const long long BC = (long long)B * C;
   // lift
-  k_pointwise<<<dim3(nblk(P), C, B), 256, 0, s>>>(param(OFF_P), param(OFF_p), X, act_V[0], nin, C, P, 0);
+  pointwise(param(OFF_P), param(OFF_p), X, act_V[0], nin, C, B, s);
   for (int l = 0; l < L; ++l) {
     const float* V = act_V[l];
     float* Z = act_Z[l];
-    k_pointwise<<<dim3(nblk(P), C, B), 256, 0, s>>>(param(off_W[l]), param(off_b[l]), V, Z, C, C, P, 0);
+    pointwise(param(off_W[l]), param(off_b[l]), V, Z, C, C, B, s);
     k_dft_w<<<nblk(BC * n * M), 256, 0, s>>>(V, tw_w, buf_A1, BC * n, n, M);
     k_dft_h<<<nblk(BC * NM), 256, 0, s>>>(buf_A1, tw_h, act_A2[l], BC, n, M);
     k_mix<<<nblk(BC * NM), 256, 0, s>>>(act_A2[l], cparam(off_R[l]), buf_S, B, C, NM);
@@ -395,7 +536,7 @@ void Net::forward(const float* X, float* O, int B, hipStream_t s) {
     else
       hipMemcpyAsync(act_V[l + 1], Z, sizeof(float) * BC * P, hipMemcpyDeviceToDevice, s);
   }
-  k_pointwise<<<dim3(nblk(P), nout, B), 256, 0, s>>>(param(OFF_Q), param(OFF_q), act_V[L], O, C, nout, P, 0);
+  pointwise(param(OFF_Q), param(OFF_q), act_V[L], O, C, nout, B, s);
   X_last = X;
   B_last = B;
 }
@@ -404,8 +545,8 @@ void Net::backward(const float* dO, hipStream_t s) {
   const int B = B_last, P = n * n, NM = 2 * M * M;
   const long long BC = (long long)B * C;
   // projection
-  k_wgrad<<<dim3(C + 1, nout), 256, 0, s>>>(dO, act_V[L], grad(OFF_Q), grad(OFF_q), B, C, nout, P);
-  k_pointwise_bwd<<<dim3(nblk(P), C, B), 256, 0, s>>>(param(OFF_Q), dO, buf_dV, C, nout, P, 0);
+  wgrad(dO, act_V[L], grad(OFF_Q), grad(OFF_q), B, C, nout, s);
+  pointwise_bwd(param(OFF_Q), dO, buf_dV, C, nout, B, s);
   for (int l = L - 1; l >= 0; --l) {
     // dZ
     if (l < L - 1)
@@ -413,8 +554,8 @@ void Net::backward(const float* dO, hipStream_t s) {
     else
       hipMemcpyAsync(buf_dZ, buf_dV, sizeof(float) * BC * P, hipMemcpyDeviceToDevice, s);
     const float* Vin = act_V[l];
-    k_wgrad<<<dim3(C + 1, C), 256, 0, s>>>(buf_dZ, Vin, grad(off_W[l]), grad(off_b[l]), B, C, C, P);
-    k_pointwise_bwd<<<dim3(nblk(P), C, B), 256, 0, s>>>(param(off_W[l]), buf_dZ, buf_dV, C, C, P, 0);
+    wgrad(buf_dZ, Vin, grad(off_W[l]), grad(off_b[l]), B, C, C, s);
+    pointwise_bwd(param(off_W[l]), buf_dZ, buf_dV, C, C, B, s);
     // spectral adjoint
     k_adj_idft_w<<<nblk(BC * n * M), 256, 0, s>>>(buf_dZ, tw_w, buf_A1, BC * n, n, M);
     k_dft_h<<<nblk(BC * NM), 256, 0, s>>>(buf_A1, tw_h, buf_S, BC, n, M);  // gS
@@ -424,7 +565,7 @@ void Net::backward(const float* dO, hipStream_t s) {
     k_adj_dft_w<<<nblk(BC * P), 256, 0, s>>>(buf_A1, tw_w, buf_dV, BC * n, n, M);
   }
   // lift
-  k_wgrad<<<dim3(nin + 1, C), 256, 0, s>>>(buf_dV, X_last, grad(OFF_P), grad(OFF_p), B, nin, C, P);
+  wgrad(buf_dV, X_last, grad(OFF_P), grad(OFF_p), B, nin, C, s);
 }
 
 void Net::loss(const float* O, const float2* w, const float2* t, const float* snorm2, float* dO, float* lossb, int B,

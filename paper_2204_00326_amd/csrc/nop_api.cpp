@@ -1,6 +1,7 @@
 // C ABI of the neural-operator warm start (ls_nop_*).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -60,7 +61,7 @@ ls_status ls_nop_create(const ls_nop_config* cfg, ls_nop** out) {
   if (out) *out = nullptr;
   if (!cfg || !out) return nfail(LS_EINVAL, "NULL argument");
   if (cfg->n < 8 || cfg->width < 1 || cfg->width > 256 || cfg->modes < 1 || 2 * cfg->modes > cfg->n ||
-      cfg->layers < 1 || cfg->batch_max < 1)
+      cfg->layers < 1 || cfg->batch_max < 1 || (cfg->bf16 != 0 && cfg->bf16 != 1))
     return nfail(LS_EINVAL, "invalid network configuration");
   ls_nop* N = nullptr;
   try {
@@ -107,6 +108,12 @@ ls_status ls_nop_create(const ls_nop_config* cfg, ls_nop** out) {
     net.buf_G = N->alloc<float2>(BCS);
     net.buf_dV = N->alloc<float>(BCP);
     net.buf_dZ = N->alloc<float>(BCP);
+    net.bf16 = cfg->bf16 != 0;
+    if (net.bf16) {
+      const long long nsplit = (long long)net.Bmax * ((P + 1023) / 1024);
+      const long long cmax = std::max<long long>(C, net.nin);
+      net.buf_wpart = N->alloc<float>(nsplit * cmax * C);
+    }
     // initial parameters (host), same scales as a standard FNO initialisation
     std::vector<float> h(off, 0.f);
     Rng rng{cfg->seed * 0x2545F4914F6CDD1DULL + 1};

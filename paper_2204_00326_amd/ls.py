@@ -64,7 +64,7 @@ class _TuneInfo(C.Structure):
 
 class _NopConfig(C.Structure):
     _fields_ = [("n", C.c_int), ("width", C.c_int), ("modes", C.c_int), ("layers", C.c_int),
-                ("batch_max", C.c_int), ("seed", C.c_uint64)]
+                ("batch_max", C.c_int), ("seed", C.c_uint64), ("bf16", C.c_int)]
 
 
 _lib = None
@@ -295,12 +295,13 @@ class NeuralOperator:
     """Handle of the learned warm-start network (ls_nop_*).  Tensors are float32 CUDA tensors."""
 
     def __init__(self, n: int, width: int = 32, modes: int = 16, layers: int = 4, batch_max: int = 16,
-                 seed: int = 0):
-        cfg = _NopConfig(n, width, modes, layers, batch_max, seed)
+                 seed: int = 0, bf16: bool = False):
+        cfg = _NopConfig(n, width, modes, layers, batch_max, seed, int(bool(bf16)))
         h = C.c_void_p()
         _check(lib().ls_nop_create(C.byref(cfg), C.byref(h)))
         self._h = h
         self.n, self.width, self.modes, self.layers, self.batch_max = n, width, modes, layers, batch_max
+        self.bf16 = bool(bf16)
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

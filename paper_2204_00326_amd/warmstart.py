@@ -193,6 +193,7 @@ def main():
     ap.add_argument("--modes", type=int, default=12)
     ap.add_argument("--layers", type=int, default=4)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--bf16", type=int, default=1, help="channel mixing on BF16 matrix cores (0: FP32)")
     args = ap.parse_args()
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
@@ -201,7 +202,8 @@ def main():
     t_gen = time.perf_counter() - t0
     log(f"dataset {data.X.shape[0]} samples in {t_gen:.1f}s")
     val = generate(range(50000, 50000 + args.val), args.n, 1) if args.val > 0 else None
-    net = ls.NeuralOperator(args.n, args.width, args.modes, args.layers, batch_max=args.batch, seed=0)
+    net = ls.NeuralOperator(args.n, args.width, args.modes, args.layers, batch_max=args.batch, seed=0,
+                            bf16=bool(args.bf16))
     t0 = time.perf_counter()
     out = train(net, data, args.epochs, args.batch, args.lr, log=log, val=val)
     hist, vhist = out if val is not None else (out, [])
@@ -209,7 +211,8 @@ def main():
     t_train = time.perf_counter() - t0
     seeds = range(100000, 100000 + args.test)
     res = {"n": args.n, "train_solutions": int(data.X.shape[0]), "epochs": args.epochs,
-           "net": {"width": args.width, "modes": args.modes, "layers": args.layers, "params": net.nparams},
+           "net": {"width": args.width, "modes": args.modes, "layers": args.layers, "params": net.nparams,
+                   "bf16_channel_mixing": bool(args.bf16)},
            "t_generate_s": t_gen, "t_train_s": t_train, "loss_first": hist[0], "loss_last": hist[-1],
            "val_loss_best": min(vhist) if vhist else None,
            "val_epoch_best": int(np.argmin(vhist)) if vhist else None}

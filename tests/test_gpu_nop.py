@@ -59,7 +59,7 @@ def from_flat(flat, width, modes, layers, nin=6, nout=2):
     return out
 
 
-def setup_case(n=32, width=8, modes=4, layers=3, B=2, seed=5):
+def setup_case(n=32, width=8, modes=4, layers=3, B=2, seed=5, bf16=False):
     rng = np.random.default_rng(seed)
     p = onop.init_params(6, width, modes, layers, seed=seed)
     for k in p:
@@ -71,7 +71,7 @@ def setup_case(n=32, width=8, modes=4, layers=3, B=2, seed=5):
     q = rng.random((B, n, n))
     t = rng.standard_normal((B, n, n)) + 1j * rng.standard_normal((B, n, n))
     s = t + 0.3
-    net = ls.NeuralOperator(n, width, modes, layers, batch_max=B)
+    net = ls.NeuralOperator(n, width, modes, layers, batch_max=B, bf16=bf16)
     net.set_params(to_flat(p, layers).astype(np.float32))
     return net, p, X, q, t, s, layers, modes
 
@@ -100,6 +100,26 @@ def test_forward_loss_backward_match_oracle():
     for k in g_ref:
         say(k, rel(g[k], g_ref[k]))
         assert rel(g[k], g_ref[k]) < 2e-3, k
+
+
+def test_bf16_channel_mixing_matches_oracle_to_bf16_accuracy():
+    # BF16 matrix-core channel mixing: forward and gradients within bfloat16 accuracy (8-bit
+    # mantissa, rounding of activations and weights in every mixing layer), and visibly less
+    # exact than the FP32 path, which shows the BF16 kernels ran
+    errs = {}
+    for bf16 in (False, True):
+        net, p, X, q, t, s, layers, modes = setup_case(width=32, n=32, B=2, bf16=bf16)
+        O_ref, cache = onop.forward(p, X, layers, modes)
+        L_ref, dO_ref = onop.loss(O_ref, q, t, s)
+        g_ref = onop.backward(p, cache, dO_ref, layers, modes)
+        Xd = torch.from_numpy(X.astype(np.float32)).cuda()   # kept alive: backward reads it
+        O = net.forward(Xd)
+        net.backward(torch.from_numpy(dO_ref.astype(np.float32)).cuda())
+        g = from_flat(net.get_grads().astype(np.float64), net.width, net.modes, net.layers)
+        errs[bf16] = (rel(O.cpu().numpy(), O_ref), max(rel(g[k], g_ref[k]) for k in g_ref))
+    say("fp32 (forward, worst gradient group)", errs[False], "bf16", errs[True])
+    assert errs[True][0] < 2e-2 and errs[True][1] < 3e-2
+    assert errs[True][0] > 10 * errs[False][0]
 
 
 def test_adam_step_matches_formula():
@@ -139,9 +159,10 @@ def test_features_and_warmstart_kernels():
         assert np.max(np.abs(b - fh * np.exp(1j * phi))) < 1e-10 * np.max(np.abs(fh)), theta
 
 
-def test_training_reduces_loss():
+@pytest.mark.parametrize("bf16", [False, True])
+def test_training_reduces_loss(bf16):
     # teacher-student: targets produced by another network of the same shape are learnable
-    net, p, X, q, t, s, layers, modes = setup_case(B=4, seed=9)
+    net, p, X, q, t, s, layers, modes = setup_case(B=4, seed=9, bf16=bf16)
     teacher = onop.init_params(6, 8, modes, layers, seed=21)
     for k in teacher:
         if teacher[k].dtype == complex:

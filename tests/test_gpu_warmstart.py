@@ -17,7 +17,7 @@ def test_learned_start_reduces_iterations():
         pytest.skip("no GPU")
     n = 32
     data = warmstart.generate(range(0, 96), n, angles_per_contrast=2, tol=1e-8)
-    net = ls.NeuralOperator(n, width=16, modes=8, layers=4, batch_max=16, seed=1)
+    net = ls.NeuralOperator(n, width=16, modes=8, layers=4, batch_max=16, seed=1, bf16=True)
     hist = warmstart.train(net, data, epochs=40, batch=16, lr=3e-3)
     print("loss", hist[0], hist[-1], flush=True)
     rows = warmstart.evaluate(net, range(100000, 100016), n, hodlr_rank=0)
