@@ -414,22 +414,28 @@ void build_phases(ls_problem* P, FmmDev& F) {
   // blocks (more splitting for long tasks and for levels with at most 16 boxes per class)
   auto make_phase_mfma = [&](Phase& ph, std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms) {
     std::vector<int> blk;
-    for (size_t t = 0; t < tasks.size(); ++t) {
-      lsk::DTask& tk = tasks[t];
-      int kb = 0;
-      for (int q = tk.t0; q < tk.t1; ++q) {
-        terms[q].kbase = kb;
-        kb += (terms[q].K + 3) / 4;
+    // a pass that would fill fewer than two workgroups per CU splits every task's k-range over
+    // all 4 waves (4x the workgroups, shorter dependent chains)
+    for (int pass = 0; pass < 2; ++pass) {
+      blk.clear();
+      for (size_t t = 0; t < tasks.size(); ++t) {
+        lsk::DTask& tk = tasks[t];
+        int kb = 0;
+        for (int q = tk.t0; q < tk.t1; ++q) {
+          terms[q].kbase = kb;
+          kb += (terms[q].K + 3) / 4;
+        }
+        tk.ktot = kb;
+        tk.Mpad = round_up(std::max(tk.M, 1), lsk::kRowBlock);
+        tk.nrb = (tk.M + 15) / 16;
+        const int nbox = tk.nh * tk.nh;
+        tk.kps = (pass == 1 || nbox <= 16 || kb > 160) ? 4 : (kb > 48 ? 2 : 1);
+        const int per = 16 * (4 / tk.kps);
+        const int nbb = (nbox + per - 1) / per;
+        tk.blk0 = (int)blk.size();
+        for (int i = 0; i < nbb * tk.nrb; ++i) blk.push_back((int)t);
       }
-      tk.ktot = kb;
-      tk.Mpad = round_up(std::max(tk.M, 1), lsk::kRowBlock);
-      tk.nrb = (tk.M + 15) / 16;
-      const int nbox = tk.nh * tk.nh;
-      tk.kps = (nbox <= 16 || kb > 160) ? 4 : (kb > 48 ? 2 : 1);
-      const int per = 16 * (4 / tk.kps);
-      const int nbb = (nbox + per - 1) / per;
-      tk.blk0 = (int)blk.size();
-      for (int i = 0; i < nbb * tk.nrb; ++i) blk.push_back((int)t);
+      if (blk.size() >= 512) break;
     }
     ph.tasks.upload(tasks);
     ph.terms.upload(terms);
