@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -437,9 +438,22 @@ void build_phases(ls_problem* P, FmmDev& F) {
       }
       if (blk.size() >= 512) break;
     }
+    // dispatch order: blocks with the most k-blocks per wave first (the long ones start early
+    // instead of forming the tail); entries are (task, block within the task) pairs
+    std::vector<std::array<int, 3>> order;  // work, task, local
+    for (size_t q = 0; q < blk.size(); ++q) {
+      const lsk::DTask& tk = tasks[blk[q]];
+      order.push_back({(tk.ktot + tk.kps - 1) / tk.kps, blk[q], (int)q - tk.blk0});
+    }
+    std::stable_sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a[0] > b[0]; });
+    std::vector<int> pairs;
+    for (const auto& o : order) {
+      pairs.push_back(o[1]);
+      pairs.push_back(o[2]);
+    }
     ph.tasks.upload(tasks);
     ph.terms.upload(terms);
-    ph.blk.upload(blk);
+    ph.blk.upload(pairs);
     ph.nblocks = (int)blk.size();
     ph.ntasks = (int)tasks.size();
     ph.mfma = true;

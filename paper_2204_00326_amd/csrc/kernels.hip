@@ -337,9 +337,10 @@ __global__ __launch_bounds__(256) void k_stencil_mfma(const DTask* __restrict__ 
   const int rhs = blockIdx.y;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int ti = __builtin_amdgcn_readfirstlane(blk_task[blk]);
+  // blk_task holds (task, block within the task) pairs in dispatch order, heaviest blocks first
+  const int ti = __builtin_amdgcn_readfirstlane(blk_task[2 * blk]);
   const DTask& tk = tasks[ti];
-  const int local = blk - tk.blk0;
+  const int local = __builtin_amdgcn_readfirstlane(blk_task[2 * blk + 1]);
   const int rt = local % tk.nrb;
   const int bb = local / tk.nrb;
   const int kps = tk.kps;             // 1, 2 or 4
