@@ -165,7 +165,8 @@ struct HodlrDev {
   std::vector<int> rank;  // per binary level
   long long N = 0;
   DevBuf Dinv, ident;
-  std::vector<DevBuf> Y64, W64, Y32, W32, Y16, W16, coreinv;  // 16: complex bfloat16
+  std::vector<DevBuf> Y64, W64, Y32, W32, Y16, W16;  // 16: complex bfloat16
+  std::vector<DevBuf> coreinv, core32, core16;      // SMW core inverses, column-major per node
   bool have16 = false;
   DevBuf partial, svec;
   std::vector<long long> chunk;  // per level
@@ -776,8 +777,11 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
       ProfScope pd(P, 5, s);
       lsk::launch_hodlr_dot(fmt, W, z, ldz, H.partial.as<double2>(), H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s);
     }
-    lsk::launch_hodlr_core(H.partial.as<double2>(), H.coreinv[l].as<double2>(), H.svec.as<double2>(), rl, nodes,
-                           H.cpc[l], H.nchunks[l], true, nrhs, s);
+    // core inverses in the factors' precision (complex128 past rank 64)
+    const int cf = rl <= 64 ? fmt : 0;
+    const void* C = cf == 2 ? H.core16[l].p : (cf == 1 ? H.core32[l].p : H.coreinv[l].p);
+    lsk::launch_hodlr_core(cf, C, H.partial.as<double2>(), H.svec.as<double2>(), rl, nodes, H.cpc[l], H.nchunks[l],
+                           true, nrhs, s);
     ProfScope ps(P, 1, s);
     lsk::launch_hodlr_update(fmt, Y, H.svec.as<double2>(), z, ldz, H.N, rl, H.N >> l, nodes, nrhs, s);
   }
@@ -908,8 +912,8 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     hodlr_apply(P, 0, Y, N, Y, N, r, l + 1, s);
     int nodes = 1 << l;
     lsk::launch_hodlr_dot(0, H.W64[l].p, Y, N, H.partial.as<double2>(), N, r, H.chunk[l], H.nchunks[l], r, s);
-    lsk::launch_hodlr_core(H.partial.as<double2>(), nullptr, H.svec.as<double2>(), r, nodes, H.cpc[l], H.nchunks[l],
-                           false, r, s);
+    lsk::launch_hodlr_core(0, nullptr, H.partial.as<double2>(), H.svec.as<double2>(), r, nodes, H.cpc[l],
+                           H.nchunks[l], false, r, s);
     std::vector<zd> t((size_t)r * nodes * 2 * r);
     hip_check(hipMemcpy(t.data(), H.svec.p, t.size() * 16, hipMemcpyDeviceToHost), "core download");
     const int r2 = 2 * r;
@@ -932,27 +936,35 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     H.bytes += (int64_t)cores.size() * 16;
   }
   hip_check(hipDeviceSynchronize(), "hodlr setup");
-  // FP32 copies of the off-diagonal factors
+  // FP32 copies of the off-diagonal factors and of the core inverses
   H.Y32.resize(H.Lb);
   H.W32.resize(H.Lb);
+  H.core32.resize(H.Lb);
   for (int l = 0; l < H.Lb; ++l) {
     const int r = H.rank[l];
+    const long long nc = (1LL << l) * 4LL * r * r;
     H.Y32[l].alloc((size_t)N * r * 8);
     H.W32[l].alloc((size_t)N * r * 8);
+    H.core32[l].alloc((size_t)nc * 8);
     lsk::launch_cast(true, H.Y64[l].p, H.Y32[l].p, (long long)N * r, s);
     lsk::launch_cast(true, H.W64[l].p, H.W32[l].p, (long long)N * r, s);
-    H.bytes += (int64_t)2 * N * r * 8;
+    lsk::launch_cast(true, H.coreinv[l].p, H.core32[l].p, nc, s);
+    H.bytes += (int64_t)2 * N * r * 8 + nc * 8;
   }
   if (P->opt.pc_bf16) {
     H.Y16.resize(H.Lb);
     H.W16.resize(H.Lb);
+    H.core16.resize(H.Lb);
     for (int l = 0; l < H.Lb; ++l) {
       const int r = H.rank[l];
+      const long long nc = (1LL << l) * 4LL * r * r;
       H.Y16[l].alloc((size_t)N * r * 4);
       H.W16[l].alloc((size_t)N * r * 4);
+      H.core16[l].alloc((size_t)nc * 4);
       lsk::launch_cast_bf16(H.Y64[l].p, H.Y16[l].p, (long long)N * r, s);
       lsk::launch_cast_bf16(H.W64[l].p, H.W16[l].p, (long long)N * r, s);
-      H.bytes += (int64_t)2 * N * r * 4;
+      lsk::launch_cast_bf16(H.coreinv[l].p, H.core16[l].p, nc, s);
+      H.bytes += (int64_t)2 * N * r * 4 + nc * 4;
     }
     H.have16 = true;
   }

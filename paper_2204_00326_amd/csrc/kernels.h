@@ -76,7 +76,9 @@ void launch_leaf_apply(const double2* Dinv, const unsigned char* ident, const do
                        long long ldz, int lp, int nleaves, int nrhs, hipStream_t s);
 void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
                       long long chunk, int nchunks, int nrhs, hipStream_t s);
-void launch_hodlr_core(const double2* partial, const double2* coreinv, double2* sout, int r, int nodes,
+// cfmt: storage of the core inverses, 0 complex128, 1 complex64, 2 complex bfloat16 (1 and 2
+// need r <= 64); coreinv unused when !apply
+void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, double2* sout, int r, int nodes,
                        int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s);
 void launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
                          long long nodesize, int nodes, int nrhs, hipStream_t s);

@@ -2,6 +2,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <stdexcept>
 #include <type_traits>
 
 #include "h0.h"
@@ -951,8 +952,9 @@ __global__ __launch_bounds__(256) void k_hodlr_core(const double2* __restrict__ 
 // Apply form split by rows: workgroup (node, slice) sums t from the partials (every slice of a
 // node recomputes the same 2r sums, in the same order) and computes 32 rows of s = coreinv t,
 // each row's dot product split over 8 column ranges and summed through LDS in a fixed order.
+template <typename TC>
 __global__ __launch_bounds__(256) void k_hodlr_core_rows(const double2* __restrict__ partial,
-                                                         const double2* __restrict__ coreinv,
+                                                         const typename V2<TC>::type* __restrict__ coreinv,
                                                          double2* __restrict__ sout, int r, int nodes, int cpc,
                                                          int nchunks, int nrf) {
   __shared__ double2 t[128];
@@ -991,12 +993,12 @@ __global__ __launch_bounds__(256) void k_hodlr_core_rows(const double2* __restri
   const int i = slice * 32 + li;
   const int per = (r2 + 7) / 8;
   const int j0 = jp * per, j1 = j0 + per < r2 ? j0 + per : r2;
-  const double2* Ci = coreinv + (long long)node * r2 * r2;  // column-major: (i, j) at j * r2 + i
+  const typename V2<TC>::type* Ci = coreinv + (long long)node * r2 * r2;  // column-major: (i, j) at j * r2 + i
   double re = 0, im = 0;
   if (i < r2) {
 #pragma unroll 4
     for (int j = j0; j < j1; ++j) {
-      const double2 a = Ci[(long long)j * r2 + i];
+      const double2 a = to_d2(Ci[(long long)j * r2 + i]);
       const double2 x = t[j];
       re = fma(a.x, x.x, re);
       re = fma(-a.y, x.y, re);
@@ -1014,16 +1016,26 @@ __global__ __launch_bounds__(256) void k_hodlr_core_rows(const double2* __restri
   sout[((long long)rhs * nodes + node) * r2 + i] = make_double2(re, im);
 }
 
-void launch_hodlr_core(const double2* partial, const double2* coreinv, double2* sout, int r, int nodes,
+void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, double2* sout, int r, int nodes,
                        int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s) {
   if (apply && 2 * r <= 128) {
     const int nrf = nrhs > 1 ? nrhs : 0;
     dim3 grid(nrf ? nodes * nrhs : nodes, (2 * r + 31) / 32, nrf ? 1 : nrhs);
-    k_hodlr_core_rows<<<grid, 256, 0, s>>>(partial, coreinv, sout, r, nodes, chunks_per_child, nchunks, nrf);
+    if (cfmt == 2)
+      k_hodlr_core_rows<bf16><<<grid, 256, 0, s>>>(partial, (const BF2*)coreinv, sout, r, nodes, chunks_per_child,
+                                                   nchunks, nrf);
+    else if (cfmt == 1)
+      k_hodlr_core_rows<float><<<grid, 256, 0, s>>>(partial, (const float2*)coreinv, sout, r, nodes, chunks_per_child,
+                                                    nchunks, nrf);
+    else
+      k_hodlr_core_rows<double><<<grid, 256, 0, s>>>(partial, (const double2*)coreinv, sout, r, nodes,
+                                                     chunks_per_child, nchunks, nrf);
     return;
   }
+  if (apply && cfmt != 0) throw std::runtime_error("reduced-precision HODLR cores need rank <= 64");
   dim3 grid(nodes, nrhs);
-  k_hodlr_core<<<grid, 256, 0, s>>>(partial, coreinv, sout, r, nodes, chunks_per_child, nchunks, apply ? 1 : 0);
+  k_hodlr_core<<<grid, 256, 0, s>>>(partial, (const double2*)coreinv, sout, r, nodes, chunks_per_child, nchunks,
+                                    apply ? 1 : 0);
 }
 
 // z[i] -= sum_c Y[c*N + i] * s[node][half*r + c]
