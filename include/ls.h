@@ -88,6 +88,12 @@ typedef struct {
                          use them in LS_MIXED solves and LS_MIXED preconditioner applies (half the
                          traffic of complex64; flexible GMRES absorbs the inexact preconditioner);
                          0: LS_MIXED uses the complex64 factors */
+  int dcgs2;          /* device-driven GMRES (graph_iters > 0): 1 (default) delayed classical
+                         Gram-Schmidt with reorthogonalisation, the second pass of step j folded
+                         into step j+1: one reduction pass and one update pass over the basis per
+                         iteration instead of two of each; the stop test then runs one operator
+                         application behind (the last application of a cycle is unused);
+                         0: CGS2 as in the host-driven loop */
 } ls_options;
 
 typedef struct {

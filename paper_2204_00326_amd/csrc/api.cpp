@@ -180,6 +180,7 @@ struct KrylovDev {
   DevBuf ictl;    // int: [0] = j, then state[nrhs], its[nrhs], kfin[nrhs]
   DevBuf dctl;    // double: fnorm[nrhs], tol[nrhs], est[nrhs], alpha[nrhs]
   DevBuf H, cs, sn, g, vin, tmp;
+  DevBuf Hr, T, coef;   // delayed CGS2: unrotated Hessenberg, basis change of Z, update coefficients
   int* host = nullptr;  // pinned mirror of ictl (plus est as doubles after it)
   size_t host_bytes = 0;
   hipStream_t cap = nullptr;
@@ -238,6 +239,7 @@ struct ls_problem {
   struct {
     int gs_rows = 1024;    // rows per chunk of the Arnoldi reductions
     int hodlr_rows = 512;  // max rows per chunk of the HODLR level reductions
+    int dot2_rows = 1024;  // rows per workgroup of the delayed-CGS2 inner products
     bool done = false;
   } tune;
 };
@@ -983,6 +985,7 @@ struct GmresCfg {
   bool op32 = false;     // FP32 operator
   bool pc = false;       // use the HODLR preconditioner
   int pcf = 0;           // HODLR off-diagonal factors: 0 complex128, 1 complex64, 2 complex bfloat16
+  bool dcgs2 = false;    // device-driven steps: delayed CGS2 (one reduction, one update pass)
   int restart = 200;
   int maxit = 2000;
 };
@@ -1269,11 +1272,18 @@ void kd_ensure(ls_problem* P, const GmresCfg& cfg, int nrhs) {
   const long long N = P->N;
   const int m = std::max(1, cfg.restart), maxv = m + 1, nch = nchunks_for(P);
   P->kQ.ensure((size_t)nrhs * maxv * N * 16);
-  if (cfg.flexible) P->kZ.ensure((size_t)nrhs * m * N * 16);
+  if (cfg.flexible) P->kZ.ensure((size_t)nrhs * (cfg.dcgs2 ? maxv : m) * N * 16);
   P->kw.ensure((size_t)nrhs * N * 16);
   P->kz.ensure((size_t)nrhs * N * 16);
   P->kr.ensure((size_t)nrhs * N * 16);
   P->kpart.ensure((size_t)nrhs * nch * maxv * 16);
+  if (cfg.dcgs2) {
+    const long long nblk = (N + P->tune.dot2_rows - 1) / P->tune.dot2_rows;
+    P->kpart.ensure((size_t)nrhs * (nblk + 1) * 2 * maxv * 16);
+    P->kd.Hr.ensure((size_t)nrhs * maxv * maxv * 16);
+    P->kd.T.ensure((size_t)nrhs * maxv * maxv * 16);
+    P->kd.coef.ensure((size_t)nrhs * 2 * maxv * 16);
+  }
   P->knp.ensure((size_t)nch * nrhs * 8);
   P->ky.ensure((size_t)nrhs * maxv * 16);
   P->kalpha.ensure((size_t)nrhs * 8);
@@ -1320,9 +1330,10 @@ void kd_key_fmm(std::vector<uintptr_t>& k, const FmmDev& F) {
 std::vector<uintptr_t> kd_key(ls_problem* P, const GmresCfg& cfg, bool op32, int nrhs, int steps) {
   std::vector<uintptr_t> k = {(uintptr_t)nrhs, (uintptr_t)cfg.restart, (uintptr_t)steps, (uintptr_t)cfg.flexible,
                               (uintptr_t)cfg.pc, (uintptr_t)cfg.pcf, (uintptr_t)op32, (uintptr_t)cfg.maxit,
-                              (uintptr_t)P->tune.gs_rows, (uintptr_t)P->tune.hodlr_rows};
+                              (uintptr_t)cfg.dcgs2, (uintptr_t)P->tune.gs_rows, (uintptr_t)P->tune.hodlr_rows,
+                              (uintptr_t)P->tune.dot2_rows};
   for (const DevBuf* b : {&P->kQ, &P->kZ, &P->kw, &P->kz, &P->kpart, &P->knp, &P->kd.ictl, &P->kd.dctl, &P->kd.H,
-                          &P->kd.cs, &P->kd.sn, &P->kd.g, &P->kd.vin, &P->kd.tmp})
+                          &P->kd.cs, &P->kd.sn, &P->kd.g, &P->kd.vin, &P->kd.tmp, &P->kd.Hr, &P->kd.T, &P->kd.coef})
     k.push_back((uintptr_t)b->p);
   kd_key_fmm(k, op32 ? P->f32 : P->f64);
   if (P->have_hodlr) {
@@ -1350,8 +1361,25 @@ void kd_step(ls_problem* P, const GmresCfg& cfg, bool op32, const KdView& v, hip
   else
     lsk::launch_axpby(1.0, vin, N, 0.0, vin, N, z, N, N, nrhs, s);
   if (cfg.flexible)
-    lsk::launch_kd_copy(z, N, 0, P->kZ.as<double2>(), (long long)m * N, N, N, v.jd, v.state, nrhs, s);
+    lsk::launch_kd_copy(z, N, 0, P->kZ.as<double2>(), (long long)(cfg.dcgs2 ? maxv : m) * N, N, N, v.jd, v.state,
+                        nrhs, s);
   fmm_apply(P, op32, z, N, w, N, nrhs, 1.0, P->coef, false, s);
+  if (cfg.dcgs2) {
+    // delayed CGS2: slot j holds u_j; one pass of inner products, the small O(j^2) update of
+    // the Hessenberg column, one pass writing q_j and u_{j+1}
+    {
+      ProfScope ps(P, 3, s);
+      lsk::launch_kd_dot2(Q, ldqv, ldqr, maxv, w, N, part, N, P->tune.dot2_rows, v.jd, v.state, nrhs, s);
+    }
+    const long long nblk = (N + P->tune.dot2_rows - 1) / P->tune.dot2_rows;
+    const double2* cd = part + (long long)nrhs * nblk * 2 * maxv;
+    lsk::launch_kd_dcgs2(cd, P->kd.Hr.as<double2>(), H, m, maxv, P->kd.cs.as<double>(), P->kd.sn.as<double2>(),
+                         P->kd.g.as<double2>(), P->kd.T.as<double2>(), P->kd.coef.as<double2>(), v.jd, v.state,
+                         v.its, v.kfin, v.est, v.fnorm, v.tol, cfg.maxit, v.alpha, nrhs, s);
+    lsk::launch_kd_dcgs2_axpy(Q, ldqv, ldqr, w, N, P->kd.coef.as<double2>(), maxv, v.alpha, N, v.jd, v.state, nrhs,
+                              s);
+    return;
+  }
   {
     ProfScope ps(P, 3, s);
     lsk::launch_kd_dot(Q, ldqv, ldqr, maxv, w, N, part, N, nch, v.jd, v.state, nrhs, s);
@@ -1521,12 +1549,27 @@ void gmres_graph(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* 
         for (int jj = i + 1; jj < k; ++jj) acc -= R[(size_t)jj * maxv + i] * y[(size_t)c * maxv + jj];
         y[(size_t)c * maxv + i] = acc / R[(size_t)i * maxv + i];
       }
+      if (cfg.dcgs2 && cfg.flexible) {
+        // the stored z~ are Z T (T upper triangular, column jj = (c, beta) of step jj):
+        // x += Z y = Z~ (T^{-1} y)
+        std::vector<zd> Tc((size_t)k * maxv);
+        hip_check(hipMemcpyAsync(Tc.data(), P->kd.T.as<double2>() + (size_t)c * maxv * maxv, Tc.size() * 16,
+                                 hipMemcpyDeviceToHost, s),
+                  "T d2h");
+        hip_check(hipStreamSynchronize(s), "sync");
+        zd* yc = &y[(size_t)c * maxv];
+        for (int i = k - 1; i >= 0; --i) {
+          zd acc = yc[i];
+          for (int jj = i + 1; jj < k; ++jj) acc -= Tc[(size_t)jj * maxv + i] * yc[jj];
+          yc[i] = acc / Tc[(size_t)i * maxv + i];
+        }
+      }
     }
     if (kmaxc > 0) {
       hip_check(hipMemcpyAsync(P->ky.p, y.data(), y.size() * 16, hipMemcpyHostToDevice, s), "y h2d");
       if (cfg.flexible) {
-        lsk::launch_gs_axpy(P->kZ.as<double2>(), N, (long long)m * N, kmaxc, P->ky.as<double2>(), maxv, 1.0, x, N,
-                            N, nrhs, s);
+        lsk::launch_gs_axpy(P->kZ.as<double2>(), N, (long long)(cfg.dcgs2 ? maxv : m) * N, kmaxc,
+                            P->ky.as<double2>(), maxv, 1.0, x, N, N, nrhs, s);
       } else {
         hip_check(hipMemsetAsync(w, 0, (size_t)nrhs * N * 16, s), "memset");
         lsk::launch_gs_axpy(Q, N, ldqr, kmaxc, P->ky.as<double2>(), maxv, 1.0, w, N, N, nrhs, s);
@@ -1615,6 +1658,7 @@ void ls_default_options(ls_options* o) {
   o->graph_iters = 0;
   o->stencil_mfma = 1;
   o->pc_bf16 = 1;
+  o->dcgs2 = 1;
 }
 
 const char* ls_last_error(void) { return g_last_error.c_str(); }
@@ -1633,6 +1677,7 @@ static void validate_options(const ls_options& o) {
   if (o.graph_iters < 0 || o.graph_iters > 64) throw LsError(LS_EINVAL, "graph_iters must be in [0, 64]");
   if (o.stencil_mfma != 0 && o.stencil_mfma != 1) throw LsError(LS_EINVAL, "stencil_mfma must be 0 or 1");
   if (o.pc_bf16 != 0 && o.pc_bf16 != 1) throw LsError(LS_EINVAL, "pc_bf16 must be 0 or 1");
+  if (o.dcgs2 != 0 && o.dcgs2 != 1) throw LsError(LS_EINVAL, "dcgs2 must be 0 or 1");
 }
 
 ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt, ls_plan_info* out) {
@@ -2044,6 +2089,7 @@ static void solve_impl(ls_problem* P, const void* f, void* psi, int nrhs, int64_
       }
     GmresCfg cfg;
     cfg.restart = P->opt.restart;
+    cfg.dcgs2 = P->opt.dcgs2 != 0;
     cfg.maxit = P->opt.maxit;
     cfg.pc = P->have_hodlr;
     std::vector<int> nref(nrhs, 0);

@@ -122,4 +122,20 @@ void launch_kd_givens(const double* npart, int nchunks, double2* H, int m, int m
 void launch_kd_next(const double2* w, long long ldw, const double* alpha, double2* Q, long long ldq_vec,
                     long long ldq_rhs, long long N, int* jdev, const int* state, int nrhs, hipStream_t s);
 
+// ---- delayed CGS2 step (slot j of Q holds u_j, not yet reorthogonalised) ----
+// inner products of Q_0..Q_j with u_j and w, blocks of rpb rows, reduced into
+// cd = partial + nrhs * nblk * 2 * maxv: cd[(rhs*2 + x)*maxv + v] (x = 0: u_j, 1: w)
+void launch_kd_dot2(const double2* Q, long long ldq_vec, long long ldq_rhs, int maxv, const double2* w, long long ldw,
+                    double2* partial, long long N, int rpb, const int* jdev, const int* state, int nrhs,
+                    hipStream_t s);
+// completes Hessenberg column j-1 (Hr unrotated, H rotated), the Givens rotation, the stop test,
+// T column j and the update coefficients coef[rhs][2][maxv], alpha = 1/beta
+void launch_kd_dcgs2(const double2* cd, double2* Hr, double2* H, int m, int maxv, double* cs, double2* sn, double2* g,
+                     double2* T, double2* coef, const int* jdev, int* state, int* its, int* kfin, double* est,
+                     const double* fnorm, const double* tol, int maxit, double* alpha, int nrhs, hipStream_t s);
+// slot j := q_j, slot j+1 := u_{j+1}; then j += 1 if any column is active
+void launch_kd_dcgs2_axpy(double2* Q, long long ldq_vec, long long ldq_rhs, const double2* w, long long ldw,
+                          const double2* coef, int maxv, const double* alpha, long long N, int* jdev,
+                          const int* state, int nrhs, hipStream_t s);
+
 }  // namespace lsk

@@ -1544,4 +1544,302 @@ void launch_kd_next(const double2* w, long long ldw, const double* alpha, double
   k_kd_advance<<<1, 64, 0, s>>>(jdev, state, nrhs);
 }
 
+
+// ---- delayed CGS2: one reduction and one update pass over the basis per step ----
+// Slot j of Q holds u_j, the new direction after one Gram-Schmidt pass, not yet normalised.
+// One pass over Q_0..Q_j gives every inner product the step needs (Q_j = u_j itself gives
+// u_j^H u_j and u_j^H w):  partial[((rhs*nblk + b)*2 + x)*maxv + v] = sum over the rows of
+// block b of conj(Q_v) y_x, y_0 = u_j, y_1 = w, v <= j.
+template <int G>
+__global__ __launch_bounds__(256) void k_kd_dot2(const double2* __restrict__ Q, long long ldq_vec, long long ldq_rhs,
+                                                 const double2* __restrict__ w, long long ldw,
+                                                 double2* __restrict__ partial, int maxv, long long N, int rpb,
+                                                 int nblk, const int* __restrict__ jdev,
+                                                 const int* __restrict__ state) {
+  __shared__ double lds[4][4 * G];
+  const int rhs = blockIdx.z;
+  if (state[rhs] != 0) return;  // uniform per block
+  const int j = *jdev;
+  const int c0 = blockIdx.y * G;
+  if (c0 > j) return;
+  const int ng = j + 1 - c0 < G ? j + 1 - c0 : G;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double2* Qb = Q + rhs * ldq_rhs;
+  const double2* u = Qb + (long long)j * ldq_vec;
+  const double2* wb = w + rhs * ldw;
+  const long long i0 = (long long)blockIdx.x * rpb;
+  const long long i1 = i0 + rpb < N ? i0 + rpb : N;
+  double acc[4 * G];
+#pragma unroll
+  for (int c = 0; c < 4 * G; ++c) acc[c] = 0;
+  // columns past j re-read column j (loads stay unconditional); their sums are not stored
+  long long coff[G];
+#pragma unroll
+  for (int c = 0; c < G; ++c) coff[c] = (long long)(c0 + (c < ng ? c : ng - 1)) * ldq_vec;
+  for (long long i = i0 + threadIdx.x; i < i1; i += 256) {
+    const double2 uv = u[i], xv = wb[i];
+    double2 a[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) a[c] = Qb[coff[c] + i];
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      acc[4 * c] = fma(a[c].x, uv.x, fma(a[c].y, uv.y, acc[4 * c]));
+      acc[4 * c + 1] = fma(a[c].x, uv.y, fma(-a[c].y, uv.x, acc[4 * c + 1]));
+      acc[4 * c + 2] = fma(a[c].x, xv.x, fma(a[c].y, xv.y, acc[4 * c + 2]));
+      acc[4 * c + 3] = fma(a[c].x, xv.y, fma(-a[c].y, xv.x, acc[4 * c + 3]));
+    }
+    __builtin_amdgcn_sched_group_barrier(0x0020, G + 2, 0);
+    __builtin_amdgcn_sched_group_barrier(0x0002, 16 * G, 0);
+  }
+#pragma unroll
+  for (int c = 0; c < 4 * G; ++c) acc[c] = wave_sum(acc[c]);
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < 4 * G; ++c) lds[wv][c] = acc[c];
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t >= 4 * G) return;
+  const int c = t >> 2, x = (t >> 1) & 1, comp = t & 1;
+  if (c >= ng) return;
+  const double v = lds[0][t] + lds[1][t] + lds[2][t] + lds[3][t];
+  double* out = reinterpret_cast<double*>(partial + (((long long)rhs * nblk + blockIdx.x) * 2 + x) * maxv + c0 + c);
+  out[comp] = v;
+}
+
+// cd[(rhs*2 + x)*maxv + v] = sum_b partial[((rhs*nblk + b)*2 + x)*maxv + v] for v <= j
+__global__ __launch_bounds__(256) void k_kd_finish2(const double2* __restrict__ partial, int nblk, int maxv,
+                                                    double2* __restrict__ cd, const int* __restrict__ jdev,
+                                                    const int* __restrict__ state) {
+  const int rhs = blockIdx.y;
+  if (state[rhs] != 0) return;
+  const int j = *jdev;
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int x = k & 1, v = k >> 1;
+  if (v > j) return;
+  double re = 0, im = 0;
+  for (int b = lane; b < nblk; b += 64) {
+    const double2 p = partial[(((long long)rhs * nblk + b) * 2 + x) * maxv + v];
+    re += p.x;
+    im += p.y;
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane == 0) cd[((long long)rhs * 2 + x) * maxv + v] = make_double2(re, im);
+}
+
+// One block per right-hand side; completes step j from cd = (c, d), where c_v = q_v^H u_j and
+// d_v = q_v^H w for v < j, c_j = u_j^H u_j and d_j = u_j^H w:
+//  * beta = sqrt(c_j - |c|^2) is the norm of q_j' = u_j - Q c (second Gram-Schmidt pass), so
+//    column j-1 of the Hessenberg matrix becomes final: Hr[j-1][v] += c_v, Hr[j-1][j] = beta.
+//    Its copy in H is rotated (previous Givens rotations, then a new one), g is updated and the
+//    column stops on the estimate |g_j| / ||f|| <= tol, maxit, the restart length or breakdown
+//    (kfin = j columns).
+//  * A column that goes on: q_j = q_j' / beta and z_j = (z~_j - Z c) / beta give
+//    A z_j = (w - Q_j Hbar c) / beta (Hbar = columns 0..j-1 of Hr), so the first-pass
+//    coefficients h = Q_j^H A z_j follow from c and d without touching the basis again:
+//    h_v = (d_v - (Hbar c)_v) / beta for v < j, h_j = ((d_j - c^H d) / beta - (Hbar c)_j) / beta.
+//    h is stored as Hr[j] (the next step adds its own second-pass part), T[j] = (c, beta)
+//    relates the stored z~ to z, and the update pass gets coef = (c, e), e = Hbar c / beta + h,
+//    alpha = 1 / beta.
+__global__ __launch_bounds__(256) void k_kd_dcgs2(const double2* __restrict__ cd, double2* Hr, double2* H, int m,
+                                                  int maxv, double* cs, double2* sn, double2* g, double2* T,
+                                                  double2* coef, const int* __restrict__ jdev, int* state, int* its,
+                                                  int* kfin, double* est, const double* __restrict__ fnorm,
+                                                  const double* __restrict__ tol, int maxit, double* alpha) {
+  __shared__ double red[32];
+  __shared__ int stop_s;
+  const int rhs = blockIdx.x, t = threadIdx.x;
+  if (state[rhs] != 0) {
+    if (t == 0) alpha[rhs] = 0.0;
+    return;
+  }
+  const int j = *jdev;
+  const double2* c = cd + (long long)rhs * 2 * maxv;
+  const double2* d = c + maxv;
+  double2* hr = Hr + (long long)rhs * (m + 1) * maxv;  // column k at hr + k * maxv
+  double ss = 0;
+  for (int v = t; v < j; v += 256) ss += c[v].x * c[v].x + c[v].y * c[v].y;
+  const double ssq = block_sum2(ss, 0.0, red).x;
+  const double b2 = c[j].x - ssq;
+  const double beta = b2 > 0 ? sqrt(b2) : 0.0;
+  double2* hcol = H + ((long long)rhs * m + (j > 0 ? j - 1 : 0)) * maxv;
+  if (j >= 1)
+    for (int v = t; v <= j; v += 256) {
+      double2 hv = hr[(long long)(j - 1) * maxv + v];
+      if (v < j) {
+        hv.x += c[v].x;
+        hv.y += c[v].y;
+      } else {
+        hv = make_double2(beta, 0.0);
+      }
+      hr[(long long)(j - 1) * maxv + v] = hv;
+      hcol[v] = hv;
+    }
+  __syncthreads();
+  if (t == 0) {
+    bool stop = !(beta > 0) || !isfinite(beta);
+    if (j >= 1) {
+      const int jc = j - 1;
+      double* c_ = cs + (long long)rhs * m;
+      double2* s_ = sn + (long long)rhs * m;
+      double2* gg = g + (long long)rhs * maxv;
+      double2 carry = hcol[0];
+      for (int i = 0; i < jc; ++i) {
+        const double2 a = carry, b = hcol[i + 1];
+        const double ci = c_[i];
+        const double2 si = s_[i];
+        const double2 sb = cmul(si, b), sa = cmul(cconj(si), a);
+        hcol[i] = make_double2(ci * a.x + sb.x, ci * a.y + sb.y);
+        carry = make_double2(ci * b.x - sa.x, ci * b.y - sa.y);
+      }
+      const double2 a = carry, b = make_double2(beta, 0.0);
+      const double aa = cabs2(a), ab = cabs2(b);
+      double cc;
+      double2 sg;
+      if (ab == 0.0) {
+        cc = 1.0;
+        sg = make_double2(0.0, 0.0);
+      } else if (aa == 0.0) {
+        cc = 0.0;
+        sg = make_double2(b.x / ab, -b.y / ab);
+      } else {
+        const double tt = hypot(aa, ab);
+        cc = aa / tt;
+        const double2 ph = make_double2(a.x / aa, a.y / aa);
+        const double2 q = cmul(ph, cconj(b));
+        sg = make_double2(q.x / tt, q.y / tt);
+      }
+      c_[jc] = cc;
+      s_[jc] = sg;
+      const double2 sb = cmul(sg, b);
+      hcol[jc] = make_double2(cc * a.x + sb.x, cc * a.y + sb.y);
+      hcol[jc + 1] = make_double2(0.0, 0.0);
+      const double2 gj = gg[jc];
+      const double2 t1 = cmul(cconj(sg), gj);
+      gg[jc + 1] = make_double2(-t1.x, -t1.y);
+      gg[jc] = make_double2(cc * gj.x, cc * gj.y);
+      const int it = its[rhs] + 1;
+      its[rhs] = it;
+      const double e = cabs2(gg[jc + 1]) / fnorm[rhs];
+      est[rhs] = e;
+      stop = stop || e <= tol[rhs] || it >= maxit || j >= m || !isfinite(e);
+    }
+    if (stop) {
+      state[rhs] = 1;
+      kfin[rhs] = j;
+      alpha[rhs] = 0.0;
+    } else {
+      alpha[rhs] = 1.0 / beta;
+    }
+    stop_s = stop ? 1 : 0;
+  }
+  __syncthreads();
+  if (stop_s) return;
+  const double ib = 1.0 / beta;
+  double2* tc = T + ((long long)rhs * (m + 1) + j) * maxv;
+  double sr = 0, si = 0;
+  for (int v = t; v <= j; v += 256) {
+    tc[v] = v < j ? c[v] : make_double2(beta, 0.0);
+    if (v < j) {
+      sr += c[v].x * d[v].x + c[v].y * d[v].y;
+      si += c[v].x * d[v].y - c[v].y * d[v].x;
+    }
+  }
+  const double2 chd = block_sum2(sr, si, red);
+  double2* cf = coef + (long long)rhs * 2 * maxv;
+  for (int v = t; v <= j; v += 256) {
+    double hx = 0, hy = 0;  // (Hbar c)_v; column k of Hbar is zero below row k + 1
+    for (int k = v > 0 ? v - 1 : 0; k < j; ++k) {
+      const double2 a = hr[(long long)k * maxv + v], b = c[k];
+      hx += a.x * b.x - a.y * b.y;
+      hy += a.x * b.y + a.y * b.x;
+    }
+    double2 h;
+    if (v < j)
+      h = make_double2((d[v].x - hx) * ib, (d[v].y - hy) * ib);
+    else
+      h = make_double2(((d[j].x - chd.x) * ib - hx) * ib, ((d[j].y - chd.y) * ib - hy) * ib);
+    hr[(long long)j * maxv + v] = h;
+    cf[v] = v < j ? c[v] : make_double2(0.0, 0.0);
+    cf[maxv + v] = make_double2(hx * ib + h.x, hy * ib + h.y);
+  }
+}
+
+// slot j := q_j = (u_j - sum_{v<j} Q_v c_v) / beta and slot j+1 := u_{j+1} = w / beta -
+// sum_{v<j} Q_v e_v - q_j e_j in one pass over Q_0..Q_{j-1} (coef = (c, e), alpha = 1/beta)
+__global__ __launch_bounds__(256) void k_kd_dcgs2_axpy(double2* __restrict__ Q, long long ldq_vec, long long ldq_rhs,
+                                                       const double2* __restrict__ w, long long ldw,
+                                                       const double2* __restrict__ coef, int maxv,
+                                                       const double* __restrict__ alpha, long long N,
+                                                       const int* __restrict__ jdev, const int* __restrict__ state) {
+  __shared__ double2 cs_[256], es_[256];
+  const int rhs = blockIdx.y;
+  if (state[rhs] != 0) return;  // uniform per block
+  const int j = *jdev;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const double2* cf = coef + (long long)rhs * 2 * maxv;
+  double2* Qb = Q + rhs * ldq_rhs;
+  double ax = 0, ay = 0, bx = 0, by = 0;
+  for (int v0 = 0; v0 < j; v0 += 256) {
+    const int cnt = j - v0 < 256 ? j - v0 : 256;
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+      cs_[threadIdx.x] = cf[v0 + threadIdx.x];
+      es_[threadIdx.x] = cf[maxv + v0 + threadIdx.x];
+    }
+    __syncthreads();
+    if (i < N) {
+      const double2* q = Qb + (long long)v0 * ldq_vec + i;
+#pragma unroll 4
+      for (int v = 0; v < cnt; ++v) {
+        const double2 a = q[(long long)v * ldq_vec];
+        const double2 p = cs_[v], e = es_[v];
+        ax += a.x * p.x - a.y * p.y;
+        ay += a.x * p.y + a.y * p.x;
+        bx += a.x * e.x - a.y * e.y;
+        by += a.x * e.y + a.y * e.x;
+      }
+    }
+  }
+  if (i >= N) return;
+  const double ib = alpha[rhs];
+  const double2 u = Qb[(long long)j * ldq_vec + i];
+  const double2 x = w[rhs * ldw + i];
+  const double2 ej = cf[maxv + j];
+  const double2 qj = make_double2((u.x - ax) * ib, (u.y - ay) * ib);
+  const double2 un = make_double2(x.x * ib - bx - (qj.x * ej.x - qj.y * ej.y),
+                                  x.y * ib - by - (qj.x * ej.y + qj.y * ej.x));
+  Qb[(long long)j * ldq_vec + i] = qj;
+  Qb[(long long)(j + 1) * ldq_vec + i] = un;
+}
+
+constexpr int kDot2Cols = 8;
+
+void launch_kd_dot2(const double2* Q, long long ldq_vec, long long ldq_rhs, int maxv, const double2* w, long long ldw,
+                    double2* partial, long long N, int rpb, const int* jdev, const int* state, int nrhs,
+                    hipStream_t s) {
+  const int nblk = (int)((N + rpb - 1) / rpb);
+  dim3 grid(nblk, (maxv + kDot2Cols - 1) / kDot2Cols, nrhs);
+  auto kern = k_kd_dot2<kDot2Cols>;
+  LSK_LAUNCH(kern, grid, 256, 0, s, Q, ldq_vec, ldq_rhs, w, ldw, partial, maxv, N, rpb, nblk, jdev, state);
+  dim3 g2((2 * maxv + 3) / 4, nrhs);
+  k_kd_finish2<<<g2, 256, 0, s>>>(partial, nblk, maxv, partial + (long long)nrhs * nblk * 2 * maxv, jdev, state);
+}
+
+void launch_kd_dcgs2(const double2* cd, double2* Hr, double2* H, int m, int maxv, double* cs, double2* sn, double2* g,
+                     double2* T, double2* coef, const int* jdev, int* state, int* its, int* kfin, double* est,
+                     const double* fnorm, const double* tol, int maxit, double* alpha, int nrhs, hipStream_t s) {
+  k_kd_dcgs2<<<nrhs, 256, 0, s>>>(cd, Hr, H, m, maxv, cs, sn, g, T, coef, jdev, state, its, kfin, est, fnorm, tol,
+                                  maxit, alpha);
+}
+
+void launch_kd_dcgs2_axpy(double2* Q, long long ldq_vec, long long ldq_rhs, const double2* w, long long ldw,
+                          const double2* coef, int maxv, const double* alpha, long long N, int* jdev,
+                          const int* state, int nrhs, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), nrhs);
+  k_kd_dcgs2_axpy<<<grid, 256, 0, s>>>(Q, ldq_vec, ldq_rhs, w, ldw, coef, maxv, alpha, N, jdev, state);
+  k_kd_advance<<<1, 64, 0, s>>>(jdev, state, nrhs);
+}
+
 }  // namespace lsk

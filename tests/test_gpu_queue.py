@@ -1,10 +1,11 @@
 """Graph-captured GMRES driver and the multi-problem queue, through the C ABI.
 
 The device-driven driver (Arnoldi index, Givens rotations and stop test on the device,
-graph_iters steps per HIP graph) runs the same method as the host-driven one: it must take
-the same number of iterations (within one, for rounding in the rotations) and give the same
-solution to 1e-9, across restarts that end in the middle of a graph, for several right-hand
-sides that stop at different iterations, and in mixed precision.  Every solution of the
+graph_iters steps per HIP graph; delayed CGS2 by default, CGS2 on request) runs the same
+method as the host-driven one (CGS2): it must take the same number of iterations (within
+one, for rounding in the rotations and the orthogonalisation) and give the same solution to
+1e-9, across restarts that end in the middle of a graph, for several right-hand sides that
+stop at different iterations, and in mixed precision.  Every solution of the
 queue must equal the single-problem FP64 solve to 1e-6 and reach the tolerance; the
 FP64 oracle pins the small case.
 """
@@ -98,6 +99,27 @@ def test_graph_driver_mixed_precision():
     assert im[0]["status"] in ("CONVERGED", "REFINE_STAGNATED") and im[0]["relres"] <= 1e-8
     assert rel(host(xm), host(x64)) < 1e-6
     assert abs(im[0]["iters"] - ih[0]["iters"]) <= 3
+
+
+@pytest.mark.parametrize("prec", [ls.LS_FP64, ls.LS_MIXED])
+def test_delayed_cgs2_matches_cgs2(prec):
+    # delayed CGS2 (one reduction and one update pass per step) against two-pass CGS2 in the
+    # same device-driven driver: same iteration count within one, same solution, and the
+    # basis stays orthonormal enough that the Arnoldi estimate matches the true residual
+    n, kappa = 128, 40.0
+    pb = inputs.problem_bumps(n, kappa, seed=5, count=6)
+    pts = inputs.grid_points(n)
+    opt = dict(hodlr_rank=15, restart=300, graph_iters=8, inner_tol=1e-4)
+    A = ls.Problem(pts, pb.q, kappa, 1e-10, ls.Options(dcgs2=0, **opt))
+    B = ls.Problem(pts, pb.q, kappa, 1e-10, ls.Options(dcgs2=1, **opt))
+    F = A.rhs_planewave([0.3, 2.0])
+    xa, ia = A.solve(F, tol=1e-9, prec=prec)
+    xb, ib = B.solve(F, tol=1e-9, prec=prec)
+    say(prec, [(i["iters"], i["relres"]) for i in ia], [(i["iters"], i["relres"]) for i in ib])
+    for c in range(2):
+        assert ib[c]["status"] in ("CONVERGED", "REFINE_STAGNATED") and ib[c]["relres"] <= 1e-9
+        assert abs(ia[c]["iters"] - ib[c]["iters"]) <= 1
+        assert rel(host(xb)[c], host(xa)[c]) < 1e-7
 
 
 def test_autotune_choices_and_solution_unchanged():
