@@ -165,6 +165,7 @@ struct HodlrDev {
   std::vector<int> rank;  // per binary level
   long long N = 0;
   DevBuf Dinv, ident;
+  DevBuf Dinv32, Dinv16;  // leaf inverses in complex64 / complex bfloat16
   std::vector<DevBuf> Y64, W64, Y32, W32, Y16, W16;  // 16: complex bfloat16
   std::vector<DevBuf> coreinv, core32, core16;      // SMW core inverses, column-major per node
   bool have16 = false;
@@ -761,13 +762,16 @@ void hodlr_ensure_ws(ls_problem* P, int nrhs) {
 // z = (partial) HODLR inverse applied to b (Morton order): leaf solves, then levels
 // Lb-1 .. lstop.  b and z may be the same buffer.
 void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double2* z, long long ldz, int nrhs,
-                 int lstop, hipStream_t s) {
+                 int lstop, hipStream_t s, const int* jdev = nullptr, long long bldj = 0) {
   HodlrDev& H = P->hod;
   hodlr_ensure_ws(P, nrhs);
   {
     ProfScope ps(P, 2, s);
-    lsk::launch_leaf_apply(H.Dinv.as<double2>(), H.ident.as<unsigned char>(), b, ldb, z, ldz, H.lp, H.nleaves, nrhs,
-                           s);
+    // leaf inverses in the factors' precision
+    const void* D = fmt == 2 && H.Dinv16.p ? H.Dinv16.p : (fmt >= 1 && H.Dinv32.p ? H.Dinv32.p : H.Dinv.p);
+    const int df = D == H.Dinv16.p ? 2 : (D == H.Dinv32.p ? 1 : 0);
+    lsk::launch_leaf_apply(df, D, H.ident.as<unsigned char>(), b, ldb, z, ldz, H.lp, H.nleaves, nrhs, s, jdev,
+                           bldj);
   }
   for (int l = H.Lb - 1; l >= lstop; --l) {
     const void* W = fmt == 2 ? H.W16[l].p : (fmt == 1 ? H.W32[l].p : H.W64[l].p);
@@ -938,7 +942,11 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     H.bytes += (int64_t)cores.size() * 16;
   }
   hip_check(hipDeviceSynchronize(), "hodlr setup");
-  // FP32 copies of the off-diagonal factors and of the core inverses
+  // FP32 copies of the leaf inverses, the off-diagonal factors and the core inverses
+  const long long nd = (long long)H.nleaves * H.lp * H.lp;
+  H.Dinv32.alloc((size_t)nd * 8);
+  lsk::launch_cast(true, H.Dinv.p, H.Dinv32.p, nd, s);
+  H.bytes += nd * 8;
   H.Y32.resize(H.Lb);
   H.W32.resize(H.Lb);
   H.core32.resize(H.Lb);
@@ -954,6 +962,9 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     H.bytes += (int64_t)2 * N * r * 8 + nc * 8;
   }
   if (P->opt.pc_bf16) {
+    H.Dinv16.alloc((size_t)nd * 4);
+    lsk::launch_cast_bf16(H.Dinv.p, H.Dinv16.p, nd, s);
+    H.bytes += nd * 4;
     H.Y16.resize(H.Lb);
     H.W16.resize(H.Lb);
     H.core16.resize(H.Lb);
@@ -1355,11 +1366,13 @@ void kd_step(ls_problem* P, const GmresCfg& cfg, bool op32, const KdView& v, hip
   double2* H = P->kd.H.as<double2>();
   double2* part = P->kpart.as<double2>();
   const long long hr = (long long)m * maxv;
-  lsk::launch_kd_copy(Q, ldqr, ldqv, vin, N, 0, N, v.jd, v.state, nrhs, s);
-  if (cfg.pc)
-    hodlr_apply(P, cfg.pcf, vin, N, z, N, nrhs, 0, s);
-  else
+  if (cfg.pc) {
+    // the leaf solves read q_j straight from the basis (column index on the device)
+    hodlr_apply(P, cfg.pcf, Q, ldqr, z, N, nrhs, 0, s, v.jd, ldqv);
+  } else {
+    lsk::launch_kd_copy(Q, ldqr, ldqv, vin, N, 0, N, v.jd, v.state, nrhs, s);
     lsk::launch_axpby(1.0, vin, N, 0.0, vin, N, z, N, N, nrhs, s);
+  }
   if (cfg.flexible)
     lsk::launch_kd_copy(z, N, 0, P->kZ.as<double2>(), (long long)(cfg.dcgs2 ? maxv : m) * N, N, N, v.jd, v.state,
                         nrhs, s);

@@ -72,8 +72,11 @@ void launch_planewave(const double* px, const double* py, const double* q, const
                       double coef, double2* f, long long ldf, long long N, int nrhs, hipStream_t s);
 
 // ---- HODLR ----
-void launch_leaf_apply(const double2* Dinv, const unsigned char* ident, const double2* b, long long ldb, double2* z,
-                       long long ldz, int lp, int nleaves, int nrhs, hipStream_t s);
+// dfmt: storage of the leaf inverses, 0 complex128, 1 complex64, 2 complex bfloat16
+// jdev != NULL: b is advanced by *jdev * bldj on the device (column j of a basis)
+void launch_leaf_apply(int dfmt, const void* Dinv, const unsigned char* ident, const double2* b, long long ldb,
+                       double2* z, long long ldz, int lp, int nleaves, int nrhs, hipStream_t s,
+                       const int* jdev = nullptr, long long bldj = 0);
 void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
                       long long chunk, int nchunks, int nrhs, hipStream_t s);
 // cfmt: storage of the core inverses, 0 complex128, 1 complex64, 2 complex bfloat16 (1 and 2

@@ -747,11 +747,13 @@ static void tsdot(int fmt, bool conj, const void* A, long long lda, long long ld
 // =====================================================================================
 // HODLR apply: leaf solves, then per binary level  z -= Y core^{-1} (W^T z).
 // =====================================================================================
-__global__ __launch_bounds__(64) void k_leaf_apply(const double2* __restrict__ Dinv,
+template <typename TD>
+__global__ __launch_bounds__(64) void k_leaf_apply(const typename V2<TD>::type* __restrict__ Dinv,
                                                    const unsigned char* __restrict__ ident,
                                                    const double2* b, long long ldb, double2* z, long long ldz, int lp,
-                                                   int nrf) {
+                                                   int nrf, const int* __restrict__ jdev, long long bldj) {
   __shared__ double2 bl[64];
+  if (jdev) b += (long long)(*jdev) * bldj;  // b = column *jdev of a basis
   // nrf > 0: the right-hand sides are the fastest grid index, so the workgroups that use one
   // factor block run back to back and find it in L2
   const int leaf = nrf ? blockIdx.x / nrf : blockIdx.x, rhs = nrf ? blockIdx.x % nrf : blockIdx.y;
@@ -764,10 +766,10 @@ __global__ __launch_bounds__(64) void k_leaf_apply(const double2* __restrict__ D
     z[rhs * ldz + base + t] = bl[t];
     return;
   }
-  const double2* D = Dinv + (long long)leaf * lp * lp;
+  const typename V2<TD>::type* D = Dinv + (long long)leaf * lp * lp;
   double re = 0, im = 0;
   for (int k = 0; k < lp; ++k) {
-    const double2 a = D[(long long)k * lp + t];
+    const double2 a = to_d2(D[(long long)k * lp + t]);
     const double2 x = bl[k];
     re = fma(a.x, x.x, re);
     re = fma(-a.y, x.y, re);
@@ -777,11 +779,21 @@ __global__ __launch_bounds__(64) void k_leaf_apply(const double2* __restrict__ D
   z[rhs * ldz + base + t] = make_double2(re, im);
 }
 
-void launch_leaf_apply(const double2* Dinv, const unsigned char* ident, const double2* b, long long ldb, double2* z,
-                       long long ldz, int lp, int nleaves, int nrhs, hipStream_t s) {
+void launch_leaf_apply(int dfmt, const void* Dinv, const unsigned char* ident, const double2* b, long long ldb,
+                       double2* z, long long ldz, int lp, int nleaves, int nrhs, hipStream_t s, const int* jdev,
+                       long long bldj) {
   const int nrf = nrhs > 1 ? nrhs : 0;
   dim3 grid(nrf ? nleaves * nrhs : nleaves, nrf ? 1 : nrhs);
-  LSK_LAUNCH(k_leaf_apply, grid, 64, 0, s, Dinv, ident, b, ldb, z, ldz, lp, nrf);
+  if (dfmt == 2) {
+    auto kern = k_leaf_apply<bf16>;
+    LSK_LAUNCH(kern, grid, 64, 0, s, (const BF2*)Dinv, ident, b, ldb, z, ldz, lp, nrf, jdev, bldj);
+  } else if (dfmt == 1) {
+    auto kern = k_leaf_apply<float>;
+    LSK_LAUNCH(kern, grid, 64, 0, s, (const float2*)Dinv, ident, b, ldb, z, ldz, lp, nrf, jdev, bldj);
+  } else {
+    auto kern = k_leaf_apply<double>;
+    LSK_LAUNCH(kern, grid, 64, 0, s, (const double2*)Dinv, ident, b, ldb, z, ldz, lp, nrf, jdev, bldj);
+  }
 }
 
 // W^T z for the HODLR levels: partial[(rhs*nchunks + ch)*r + c] = sum_{i in chunk ch} W[c*N + i] z[i].
