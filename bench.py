@@ -74,7 +74,34 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_disc512_k80.txt")  # 
 KERNELS_SRC = os.path.join(ROOT, "paper_2204_00326_amd", "csrc", "kernels.hip")
 # kernel names (before the argument list) of the classes the roofline may report
 # (the HBM-bound ones; the matrix-core stencil kernel serves every DAFMM pass under one name)
-COUNTED = {"hodlr_dot": "lsk::k_hodlr_dot_seg<lsk::bf16, 4>", "hodlr_update": "lsk::k_hodlr_update_wide<lsk::bf16>"}
+COUNTED = {"hodlr_dot": "lsk::k_hodlr_dot_seg<lsk::bf16, 4>", "hodlr_update": "lsk::k_hodlr_update_wide<lsk::bf16>",
+           "hodlr_upd_dot": "lsk::k_hodlr_upd_dot<1024>"}
+
+
+def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok):
+    """Algorithmic HBM bytes per launch of the HODLR level kernels of one apply (one right-hand
+    side), averaged over the launches of each class: a level's factor (N x r_l entries of fsz
+    bytes) plus z (complex128) read, and z written by an update.  Mirrors the library's level
+    plan: rank min(rank, child size / rank_div), chunks of at most max_rows rows, and an update
+    fused with the next level's dot where that level's chunks are 256, 512 or 1024 rows."""
+    ranks = [max(1, min(rank, (N >> (l + 1)) // rank_div)) if rank_div > 0 else rank for l in range(levels)]
+    def chunk(l):
+        ch = N >> (l + 1)
+        while ch > max_rows and ch % 2 == 0:
+            ch //= 2
+        return ch
+    cls = {"hodlr_dot": [], "hodlr_update": [], "hodlr_upd_dot": []}
+    pend = -1
+    for l in range(levels - 1, -1, -1):
+        if pend >= 0 and fused_ok and N % 1024 == 0 and (N >> pend) % 128 == 0 and chunk(l) in (256, 512, 1024):
+            cls["hodlr_upd_dot"].append(N * (ranks[pend] + ranks[l]) * fsz + 2 * N * 16)
+        else:
+            if pend >= 0:
+                cls["hodlr_update"].append(N * ranks[pend] * fsz + 2 * N * 16)
+            cls["hodlr_dot"].append(N * ranks[l] * fsz + N * 16)
+        pend = l
+    cls["hodlr_update"].append(N * ranks[pend] * fsz + 2 * N * 16)
+    return {c: sum(v) / len(v) / 1e9 for c, v in cls.items() if v}
 
 
 def _sha256(path):
@@ -276,17 +303,16 @@ def main():
     # roofline of the dominant kernel class over the timed region: achieved = algorithmic
     # bytes (or flops) per launch / average duration of the timed launches of the class
     N = n * n
-    r = args.rank
-    rs, lb = st["hodlr_rank_sum"], st["hodlr_levels"]
+    lb = st["hodlr_levels"]
     fsz = {"bf16": 4, "c64": 8}[pc_fmt]   # bytes per stored HODLR factor entry in mixed solves
+    hb = hodlr_launch_bytes(N, lb, args.rank, args.rank_div, tune["hodlr_rows"] if tune else 512, fsz,
+                            pc_fmt == "bf16")
     per_launch = {
         # flops of one near-field + M2L launch (8 real flops per complex multiply-add), matrix cores
         "near_m2l64": ("mfma", "f64", 8.0 * (st["entries_near"] + st["entries_m2l64"]) / 1e12),
         "near_m2l32": ("mfma", "f32", 8.0 * (st["entries_near"] + st["entries_m2l32"]) / 1e12),
-        # per level launch, averaged over the levels: the level's factor (N x r_l entries) and z
-        # (complex128) read, plus z written by the update
-        "hodlr_update": ("hbm", None, (N * rs * fsz + lb * 2 * N * 16) / lb / 1e9),
-        "hodlr_dot": ("hbm", None, (N * rs * fsz + lb * N * 16) / lb / 1e9),
+        # HODLR level launches (unfused dot, unfused update, update fused with the next dot)
+        **{c: ("hbm", None, v) for c, v in hb.items()},
     }
     cand = {c: prof[c] for c in per_launch if prof[c][1] > 0}
 
@@ -312,7 +338,8 @@ def main():
     roof["kernel"] = {"near_m2l64": "k_stencil_mfma<double> (near field + M2L launch)",
                       "near_m2l32": "k_stencil_mfma<float> (near field + M2L launch)",
                       "hodlr_update": f"k_hodlr_update_wide<{'bf16' if args.pc_bf16 else 'float'}>",
-                      "hodlr_dot": f"k_hodlr_dot_seg<{'bf16, 4' if args.pc_bf16 else 'float, 2'}> (HODLR W^T z)"}[dom]
+                      "hodlr_dot": f"k_hodlr_dot_seg<{'bf16, 4' if args.pc_bf16 else 'float, 2'}> (HODLR W^T z)",
+                      "hodlr_upd_dot": "k_hodlr_upd_dot<1024> (HODLR z -= Y s fused with the next level's W^T z)"}[dom]
     roof["avg_launch_us"] = round(tot_ms / launches * 1e3, 2)
     roof["launches_timed"] = launches
     roof["launches"] = all_launches

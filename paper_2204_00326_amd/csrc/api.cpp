@@ -231,7 +231,7 @@ struct ls_problem {
   DevBuf w_x, w_y, w_t;  // Morton-order vectors (nrhs_cap)
   int ws_cap = 0;
   ls_stats_t stats{};
-  ProfileClass prof[6];
+  ProfileClass prof[7];
   // Krylov workspace
   DevBuf kQ, kZ, kw, kz, kr, kh, kpart, knp, kno, kalpha, ky, kx, kf, kdx;
   size_t kcap_key = 0;
@@ -773,24 +773,38 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
     lsk::launch_leaf_apply(df, D, H.ident.as<unsigned char>(), b, ldb, z, ldz, H.lp, H.nleaves, nrhs, s, jdev,
                            bldj);
   }
+  // level by level: dot (W^T z), core solve, update (z -= Y s).  With complex bfloat16
+  // factors and one right-hand side, an update and the next level's dot share one launch
+  // where the next level's chunks are 1024 rows.
+  int pend = -1;  // level whose update is still to be applied
+  auto update = [&](int a) {
+    const void* Y = fmt == 2 ? H.Y16[a].p : (fmt == 1 ? H.Y32[a].p : H.Y64[a].p);
+    ProfScope ps(P, 1, s);
+    lsk::launch_hodlr_update(fmt, Y, H.svec.as<double2>(), z, ldz, H.N, H.rank[a], H.N >> a, 1 << a, nrhs, s);
+  };
   for (int l = H.Lb - 1; l >= lstop; --l) {
     const void* W = fmt == 2 ? H.W16[l].p : (fmt == 1 ? H.W32[l].p : H.W64[l].p);
-    const void* Y = fmt == 2 ? H.Y16[l].p : (fmt == 1 ? H.Y32[l].p : H.Y64[l].p);
     int nodes = 1 << l;
     const int rl = H.rank[l];
     if (rl == 0) continue;
-    {
+    if (pend >= 0 && fmt == 2 && nrhs == 1 && ldz == H.N && lsk::hodlr_upd_dot_ok(H.N, H.N >> pend, H.chunk[l])) {
+      ProfScope pf(P, 6, s);
+      lsk::launch_hodlr_upd_dot(H.Y16[pend].p, H.rank[pend], H.svec.as<double2>(), H.N >> pend, 1 << pend, W, rl, z,
+                                H.N, H.partial.as<double2>(), H.chunk[l], s);
+    } else {
+      if (pend >= 0) update(pend);
       ProfScope pd(P, 5, s);
       lsk::launch_hodlr_dot(fmt, W, z, ldz, H.partial.as<double2>(), H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s);
     }
+    pend = -1;
     // core inverses in the factors' precision (complex128 past rank 64)
     const int cf = rl <= 64 ? fmt : 0;
     const void* C = cf == 2 ? H.core16[l].p : (cf == 1 ? H.core32[l].p : H.coreinv[l].p);
     lsk::launch_hodlr_core(cf, C, H.partial.as<double2>(), H.svec.as<double2>(), rl, nodes, H.cpc[l], H.nchunks[l],
                            true, nrhs, s);
-    ProfScope ps(P, 1, s);
-    lsk::launch_hodlr_update(fmt, Y, H.svec.as<double2>(), z, ldz, H.N, rl, H.N >> l, nodes, nrhs, s);
+    pend = l;
   }
+  if (pend >= 0) update(pend);
   hip_check(hipGetLastError(), "hodlr kernels");
 }
 
@@ -2347,7 +2361,7 @@ void ls_destroy(ls_problem* P) {
 }
 
 ls_status ls_profile_enable(ls_problem* P, int cls, int every) {
-  if (!P || cls < 0 || cls > 5 || every < 0) {
+  if (!P || cls < 0 || cls > 6 || every < 0) {
     g_last_error = "bad arguments";
     return LS_EINVAL;
   }
@@ -2363,7 +2377,7 @@ ls_status ls_profile_enable(ls_problem* P, int cls, int every) {
 
 ls_status ls_profile_read(ls_problem* P, int cls, double* total_ms, int64_t* launches, int64_t* all_launches) {
   try {
-    if (!P || cls < 0 || cls > 5 || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
+    if (!P || cls < 0 || cls > 6 || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
     ProfileClass& pc = P->prof[cls];
     double tot = 0;
     for (size_t i = 0; i < pc.used; ++i) {

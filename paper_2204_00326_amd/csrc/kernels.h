@@ -77,6 +77,12 @@ void launch_planewave(const double* px, const double* py, const double* q, const
 void launch_leaf_apply(int dfmt, const void* Dinv, const unsigned char* ident, const double2* b, long long ldb,
                        double2* z, long long ldz, int lp, int nleaves, int nrhs, hipStream_t s,
                        const int* jdev = nullptr, long long bldj = 0);
+// complex bfloat16 factors, one right-hand side: z -= Y_a s_a (update of level a, node size
+// nodesize_a) and the chunk partials of W_b^T z (dot of level b, chunks of 256, 512 or 1024
+// rows) in one launch; the same sums as launch_hodlr_update followed by launch_hodlr_dot
+bool hodlr_upd_dot_ok(long long N, long long nodesize_a, long long chunk_b);
+void launch_hodlr_upd_dot(const void* Y, int ra, const double2* sv, long long nodesize, int nodes, const void* W,
+                          int rb, double2* z, long long N, double2* partial, long long chunk, hipStream_t s);
 void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
                       long long chunk, int nchunks, int nrhs, hipStream_t s);
 // cfmt: storage of the core inverses, 0 complex128, 1 complex64, 2 complex bfloat16 (1 and 2

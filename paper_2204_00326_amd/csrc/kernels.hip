@@ -1141,6 +1141,137 @@ __global__ __launch_bounds__(256) void k_hodlr_update_wide(const typename V2<T>:
   }
 }
 
+// Update of one level fused with the W^T z reduction of the next: workgroup bx owns rows
+// [1024 bx, 1024 bx + 1024).  Its threads first apply z -= Y s of level "a" to 4 rows each (the
+// arithmetic of k_hodlr_update_wide), keep the new rows in LDS and store them, then its waves
+// form the partial sums of W^T z over the 1024 / chunk chunks of those rows for the 4-column
+// groups of level "b" with the lane and row order of k_hodlr_dot_seg (chunk 256, 512 or 1024,
+// 64-lane segments): the same sums, bit for bit, without a second launch or a second read of z.
+template <int CH>
+__global__ __launch_bounds__(256) void k_hodlr_upd_dot(const BF2* __restrict__ Y, int ra,
+                                                       const double2* __restrict__ sv, long long nodesize, int nodes,
+                                                       const BF2* __restrict__ W, int rb, double2* __restrict__ z,
+                                                       long long N, double2* __restrict__ partial) {
+  constexpr int chunk = CH, NS = CH / 256;  // rows per chunk, steps per lane
+  constexpr int R = 4, G = 4;
+  __shared__ double2 zs[1024];
+  const long long bx = blockIdx.x;
+  const int t = threadIdx.x;
+  {
+    const long long i = bx * 1024 + (long long)t * R;
+    const long long node = i / nodesize;
+    const int half = (i - node * nodesize) >= (nodesize >> 1) ? 1 : 0;
+    const double2* s = sv + node * 2 * ra + half * ra;
+    double re[R], im[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) re[q] = im[q] = 0;
+    for (int c0 = 0; c0 < ra; c0 += 8) {
+      Pack<bf16, R> y[8];
+      double2 x[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int cc = c0 + c < ra ? c0 + c : ra - 1;
+        y[c] = *reinterpret_cast<const Pack<bf16, R>*>(Y + (long long)cc * N + i);
+        x[c] = s[cc];
+        if (c0 + c >= ra) x[c] = make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const double2 yv = to_d2(y[c].v[q]);
+          re[q] = fma(yv.x, x[c].x, re[q]);
+          re[q] = fma(-yv.y, x[c].y, re[q]);
+          im[q] = fma(yv.x, x[c].y, im[q]);
+          im[q] = fma(yv.y, x[c].x, im[q]);
+        }
+      __builtin_amdgcn_sched_group_barrier(0x0020, 16, 0);
+      __builtin_amdgcn_sched_group_barrier(0x0002, 32 * R, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      double2 o = z[i + q];
+      o.x -= re[q];
+      o.y -= im[q];
+      z[i + q] = o;
+      zs[t * R + q] = o;
+    }
+  }
+  __syncthreads();
+  const int wave = t >> 6, sl = t & 63;
+  const int ngrp = (rb + G - 1) / G;
+  const int kc = 1024 / chunk;  // chunks of this workgroup
+  for (int pr = wave; pr < ngrp * kc; pr += 4) {
+    const int grp = pr % ngrp, kk = pr / ngrp;
+    const int c0 = grp * G;
+    double acc[2 * G];
+#pragma unroll
+    for (int c = 0; c < 2 * G; ++c) acc[c] = 0;
+    long long coff[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) coff[c] = (long long)(c0 + c < rb ? c0 + c : rb - 1) * N;
+    // every step's loads first (NS x G packs in flight), then the sums in the step order
+    Pack<bf16, R> a[NS][G];
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+      for (int c = 0; c < G; ++c)
+        a[k][c] = *reinterpret_cast<const Pack<bf16, R>*>(W + coff[c] + bx * 1024 + kk * chunk + sl * R + k * 64 * R);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int li = kk * chunk + sl * R + k * 64 * R;
+      double2 xv[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) xv[q] = zs[li + q];
+#pragma unroll
+      for (int c = 0; c < G; ++c)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const double2 av = to_d2(a[k][c].v[q]);
+          acc[2 * c] = fma(av.x, xv[q].x, acc[2 * c]);
+          acc[2 * c] = fma(-av.y, xv[q].y, acc[2 * c]);
+          acc[2 * c + 1] = fma(av.x, xv[q].y, acc[2 * c + 1]);
+          acc[2 * c + 1] = fma(av.y, xv[q].x, acc[2 * c + 1]);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int c = 0; c < 2 * G; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+    if (sl < G && c0 + sl < rb) {
+      double re = 0, im = 0;
+#pragma unroll
+      for (int c = 0; c < G; ++c)
+        if (c == sl) {
+          re = acc[2 * c];
+          im = acc[2 * c + 1];
+        }
+      partial[(bx * kc + kk) * rb + c0 + sl] = make_double2(re, im);
+    }
+  }
+}
+
+bool hodlr_upd_dot_ok(long long N, long long nodesize_a, long long chunk_b) {
+  return N % 1024 == 0 && nodesize_a % 128 == 0 && (chunk_b == 256 || chunk_b == 512 || chunk_b == 1024);
+}
+
+void launch_hodlr_upd_dot(const void* Y, int ra, const double2* sv, long long nodesize, int nodes, const void* W,
+                          int rb, double2* z, long long N, double2* partial, long long chunk, hipStream_t s) {
+  const dim3 grid((unsigned)(N / 1024));
+  const BF2 *Yb = (const BF2*)Y, *Wb = (const BF2*)W;
+  if (chunk == 1024) {
+    auto kern = k_hodlr_upd_dot<1024>;
+    LSK_LAUNCH(kern, grid, 256, 0, s, Yb, ra, sv, nodesize, nodes, Wb, rb, z, N, partial);
+  } else if (chunk == 512) {
+    auto kern = k_hodlr_upd_dot<512>;
+    LSK_LAUNCH(kern, grid, 256, 0, s, Yb, ra, sv, nodesize, nodes, Wb, rb, z, N, partial);
+  } else if (chunk == 256) {
+    auto kern = k_hodlr_upd_dot<256>;
+    LSK_LAUNCH(kern, grid, 256, 0, s, Yb, ra, sv, nodesize, nodes, Wb, rb, z, N, partial);
+  } else {
+    throw std::runtime_error("fused HODLR update/dot needs chunks of 256, 512 or 1024 rows");
+  }
+}
+
 void launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
                          long long nodesize, int nodes, int nrhs, hipStream_t s) {
   if (fmt != 0 && N % 64 == 0 && nodesize % 128 == 0) {
