@@ -303,6 +303,7 @@ def main():
     # roofline of the dominant kernel class over the timed region: achieved = algorithmic
     # bytes (or flops) per launch / average duration of the timed launches of the class
     N = n * n
+    r = args.rank
     lb = st["hodlr_levels"]
     fsz = {"bf16": 4, "c64": 8}[pc_fmt]   # bytes per stored HODLR factor entry in mixed solves
     hb = hodlr_launch_bytes(N, lb, args.rank, args.rank_div, tune["hodlr_rows"] if tune else 512, fsz,

@@ -1771,27 +1771,24 @@ __global__ __launch_bounds__(256) void k_kd_finish2(const double2* __restrict__ 
   if (lane == 0) cd[((long long)rhs * 2 + x) * maxv + v] = make_double2(re, im);
 }
 
-// One block per right-hand side; completes step j from cd = (c, d), where c_v = q_v^H u_j and
-// d_v = q_v^H w for v < j, c_j = u_j^H u_j and d_j = u_j^H w:
+// Step j of delayed CGS2 from cd = (c, d), where c_v = q_v^H u_j and d_v = q_v^H w for v < j,
+// c_j = u_j^H u_j and d_j = u_j^H w.  First kernel, one block per right-hand side:
 //  * beta = sqrt(c_j - |c|^2) is the norm of q_j' = u_j - Q c (second Gram-Schmidt pass), so
 //    column j-1 of the Hessenberg matrix becomes final: Hr[j-1][v] += c_v, Hr[j-1][j] = beta.
 //    Its copy in H is rotated (previous Givens rotations, then a new one), g is updated and the
 //    column stops on the estimate |g_j| / ||f|| <= tol, maxit, the restart length or breakdown
-//    (kfin = j columns).
-//  * A column that goes on: q_j = q_j' / beta and z_j = (z~_j - Z c) / beta give
-//    A z_j = (w - Q_j Hbar c) / beta (Hbar = columns 0..j-1 of Hr), so the first-pass
-//    coefficients h = Q_j^H A z_j follow from c and d without touching the basis again:
-//    h_v = (d_v - (Hbar c)_v) / beta for v < j, h_j = ((d_j - c^H d) / beta - (Hbar c)_j) / beta.
-//    h is stored as Hr[j] (the next step adds its own second-pass part), T[j] = (c, beta)
-//    relates the stored z~ to z, and the update pass gets coef = (c, e), e = Hbar c / beta + h,
-//    alpha = 1 / beta.
+//    (kfin = j columns).  A column that goes on gets T[j] = (c, beta), which relates the stored
+//    z~ to z, and alpha = 1 / beta.
 __global__ __launch_bounds__(256) void k_kd_dcgs2(const double2* __restrict__ cd, double2* Hr, double2* H, int m,
                                                   int maxv, double* cs, double2* sn, double2* g, double2* T,
-                                                  double2* coef, const int* __restrict__ jdev, int* state, int* its,
-                                                  int* kfin, double* est, const double* __restrict__ fnorm,
+                                                  const int* __restrict__ jdev, int* state, int* its, int* kfin,
+                                                  double* est, const double* __restrict__ fnorm,
                                                   const double* __restrict__ tol, int maxit, double* alpha) {
+  constexpr int TILE = 512;
   __shared__ double red[32];
   __shared__ int stop_s;
+  __shared__ double2 hb_s[TILE], sn_s[TILE];
+  __shared__ double cs_s[TILE];
   const int rhs = blockIdx.x, t = threadIdx.x;
   if (state[rhs] != 0) {
     if (t == 0) alpha[rhs] = 0.0;
@@ -1799,43 +1796,56 @@ __global__ __launch_bounds__(256) void k_kd_dcgs2(const double2* __restrict__ cd
   }
   const int j = *jdev;
   const double2* c = cd + (long long)rhs * 2 * maxv;
-  const double2* d = c + maxv;
   double2* hr = Hr + (long long)rhs * (m + 1) * maxv;  // column k at hr + k * maxv
   double ss = 0;
   for (int v = t; v < j; v += 256) ss += c[v].x * c[v].x + c[v].y * c[v].y;
   const double ssq = block_sum2(ss, 0.0, red).x;
   const double b2 = c[j].x - ssq;
   const double beta = b2 > 0 ? sqrt(b2) : 0.0;
-  double2* hcol = H + ((long long)rhs * m + (j > 0 ? j - 1 : 0)) * maxv;
+  const int jc = j - 1;
+  double2* hcol = H + ((long long)rhs * m + (j > 0 ? jc : 0)) * maxv;
   if (j >= 1)
     for (int v = t; v <= j; v += 256) {
-      double2 hv = hr[(long long)(j - 1) * maxv + v];
+      double2 hv = hr[(long long)jc * maxv + v];
       if (v < j) {
         hv.x += c[v].x;
         hv.y += c[v].y;
       } else {
         hv = make_double2(beta, 0.0);
       }
-      hr[(long long)(j - 1) * maxv + v] = hv;
+      hr[(long long)jc * maxv + v] = hv;
       hcol[v] = hv;
     }
   __syncthreads();
+  // previous rotations on column j-1: the entries, cosines and sines are staged through LDS
+  // a tile at a time, so the serial chain of thread 0 waits on LDS rather than on memory
+  double* c_ = cs + (long long)rhs * m;
+  double2* s_ = sn + (long long)rhs * m;
+  double2 carry = make_double2(0.0, 0.0);
+  if (j >= 1 && t == 0) carry = hcol[0];
+  for (int i0 = 0; i0 < jc; i0 += TILE) {
+    const int cnt = jc - i0 < TILE ? jc - i0 : TILE;
+    for (int k = t; k < cnt; k += 256) {
+      hb_s[k] = hcol[i0 + k + 1];
+      cs_s[k] = c_[i0 + k];
+      sn_s[k] = s_[i0 + k];
+    }
+    __syncthreads();
+    if (t == 0)
+      for (int k = 0; k < cnt; ++k) {
+        const double2 a = carry, b = hb_s[k];
+        const double ci = cs_s[k];
+        const double2 si = sn_s[k];
+        const double2 sb = cmul(si, b), sa = cmul(cconj(si), a);
+        hcol[i0 + k] = make_double2(ci * a.x + sb.x, ci * a.y + sb.y);
+        carry = make_double2(ci * b.x - sa.x, ci * b.y - sa.y);
+      }
+    __syncthreads();
+  }
   if (t == 0) {
     bool stop = !(beta > 0) || !isfinite(beta);
     if (j >= 1) {
-      const int jc = j - 1;
-      double* c_ = cs + (long long)rhs * m;
-      double2* s_ = sn + (long long)rhs * m;
       double2* gg = g + (long long)rhs * maxv;
-      double2 carry = hcol[0];
-      for (int i = 0; i < jc; ++i) {
-        const double2 a = carry, b = hcol[i + 1];
-        const double ci = c_[i];
-        const double2 si = s_[i];
-        const double2 sb = cmul(si, b), sa = cmul(cconj(si), a);
-        hcol[i] = make_double2(ci * a.x + sb.x, ci * a.y + sb.y);
-        carry = make_double2(ci * b.x - sa.x, ci * b.y - sa.y);
-      }
       const double2 a = carry, b = make_double2(beta, 0.0);
       const double aa = cabs2(a), ab = cabs2(b);
       double cc;
@@ -1879,34 +1889,56 @@ __global__ __launch_bounds__(256) void k_kd_dcgs2(const double2* __restrict__ cd
   }
   __syncthreads();
   if (stop_s) return;
-  const double ib = 1.0 / beta;
   double2* tc = T + ((long long)rhs * (m + 1) + j) * maxv;
-  double sr = 0, si = 0;
-  for (int v = t; v <= j; v += 256) {
-    tc[v] = v < j ? c[v] : make_double2(beta, 0.0);
-    if (v < j) {
-      sr += c[v].x * d[v].x + c[v].y * d[v].y;
-      si += c[v].x * d[v].y - c[v].y * d[v].x;
-    }
+  for (int v = t; v <= j; v += 256) tc[v] = v < j ? c[v] : make_double2(beta, 0.0);
+}
+
+// Second kernel, one wave per entry v <= j of a column that goes on: q_j = q_j' / beta and
+// z_j = (z~_j - Z c) / beta give A z_j = (w - Q_j Hbar c) / beta (Hbar = columns 0..j-1 of Hr),
+// so the first-pass coefficients h = Q_j^H A z_j follow from c and d without touching the basis:
+// h_v = (d_v - (Hbar c)_v) / beta for v < j, h_j = ((d_j - c^H d) / beta - (Hbar c)_j) / beta.
+// h is stored as Hr[j] (the next step adds its own second-pass part), and the update pass gets
+// coef = (c, e), e = Hbar c / beta + h.
+__global__ __launch_bounds__(256) void k_kd_dcgs2_h(const double2* __restrict__ cd, double2* Hr, int m, int maxv,
+                                                    double2* __restrict__ coef, const int* __restrict__ jdev,
+                                                    const int* __restrict__ state, const double* __restrict__ alpha) {
+  const int rhs = blockIdx.y;
+  if (state[rhs] != 0) return;
+  const int j = *jdev;
+  const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (v > j) return;
+  const double ib = alpha[rhs];
+  const double2* c = cd + (long long)rhs * 2 * maxv;
+  const double2* d = c + maxv;
+  const double2* hr = Hr + (long long)rhs * (m + 1) * maxv;
+  // (Hbar c)_v: column k of Hbar is zero below row k + 1
+  double hx = 0, hy = 0;
+  for (int k = (v > 0 ? v - 1 : 0) + lane; k < j; k += 64) {
+    const double2 a = hr[(long long)k * maxv + v], b = c[k];
+    hx += a.x * b.x - a.y * b.y;
+    hy += a.x * b.y + a.y * b.x;
   }
-  const double2 chd = block_sum2(sr, si, red);
+  hx = wave_sum(hx);
+  hy = wave_sum(hy);
+  double2 h;
+  if (v < j) {
+    h = make_double2((d[v].x - hx) * ib, (d[v].y - hy) * ib);
+  } else {
+    double sr = 0, si = 0;  // c^H d
+    for (int k = lane; k < j; k += 64) {
+      sr += c[k].x * d[k].x + c[k].y * d[k].y;
+      si += c[k].x * d[k].y - c[k].y * d[k].x;
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    h = make_double2(((d[j].x - sr) * ib - hx) * ib, ((d[j].y - si) * ib - hy) * ib);
+  }
+  if (lane != 0) return;
+  Hr[(long long)rhs * (m + 1) * maxv + (long long)j * maxv + v] = h;
   double2* cf = coef + (long long)rhs * 2 * maxv;
-  for (int v = t; v <= j; v += 256) {
-    double hx = 0, hy = 0;  // (Hbar c)_v; column k of Hbar is zero below row k + 1
-    for (int k = v > 0 ? v - 1 : 0; k < j; ++k) {
-      const double2 a = hr[(long long)k * maxv + v], b = c[k];
-      hx += a.x * b.x - a.y * b.y;
-      hy += a.x * b.y + a.y * b.x;
-    }
-    double2 h;
-    if (v < j)
-      h = make_double2((d[v].x - hx) * ib, (d[v].y - hy) * ib);
-    else
-      h = make_double2(((d[j].x - chd.x) * ib - hx) * ib, ((d[j].y - chd.y) * ib - hy) * ib);
-    hr[(long long)j * maxv + v] = h;
-    cf[v] = v < j ? c[v] : make_double2(0.0, 0.0);
-    cf[maxv + v] = make_double2(hx * ib + h.x, hy * ib + h.y);
-  }
+  cf[v] = v < j ? c[v] : make_double2(0.0, 0.0);
+  cf[maxv + v] = make_double2(hx * ib + h.x, hy * ib + h.y);
 }
 
 // slot j := q_j = (u_j - sum_{v<j} Q_v c_v) / beta and slot j+1 := u_{j+1} = w / beta -
@@ -1973,8 +2005,10 @@ void launch_kd_dot2(const double2* Q, long long ldq_vec, long long ldq_rhs, int 
 void launch_kd_dcgs2(const double2* cd, double2* Hr, double2* H, int m, int maxv, double* cs, double2* sn, double2* g,
                      double2* T, double2* coef, const int* jdev, int* state, int* its, int* kfin, double* est,
                      const double* fnorm, const double* tol, int maxit, double* alpha, int nrhs, hipStream_t s) {
-  k_kd_dcgs2<<<nrhs, 256, 0, s>>>(cd, Hr, H, m, maxv, cs, sn, g, T, coef, jdev, state, its, kfin, est, fnorm, tol,
-                                  maxit, alpha);
+  k_kd_dcgs2<<<nrhs, 256, 0, s>>>(cd, Hr, H, m, maxv, cs, sn, g, T, jdev, state, its, kfin, est, fnorm, tol, maxit,
+                                  alpha);
+  dim3 grid((maxv + 3) / 4, nrhs);
+  k_kd_dcgs2_h<<<grid, 256, 0, s>>>(cd, Hr, m, maxv, coef, jdev, state, alpha);
 }
 
 void launch_kd_dcgs2_axpy(double2* Q, long long ldq_vec, long long ldq_rhs, const double2* w, long long ldw,
