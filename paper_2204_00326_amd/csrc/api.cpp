@@ -761,8 +761,11 @@ void hodlr_ensure_ws(ls_problem* P, int nrhs) {
 
 // z = (partial) HODLR inverse applied to b (Morton order): leaf solves, then levels
 // Lb-1 .. lstop.  b and z may be the same buffer.
+// jdev != NULL: b is column *jdev of a basis (b + *jdev * bldj); zcopy != NULL: the result is
+// also stored in column *jdev of zcopy (ld per right-hand side zldr, per column zldj)
 void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double2* z, long long ldz, int nrhs,
-                 int lstop, hipStream_t s, const int* jdev = nullptr, long long bldj = 0) {
+                 int lstop, hipStream_t s, const int* jdev = nullptr, long long bldj = 0, double2* zcopy = nullptr,
+                 long long zldr = 0, long long zldj = 0) {
   HodlrDev& H = P->hod;
   hodlr_ensure_ws(P, nrhs);
   {
@@ -777,10 +780,12 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
   // factors and one right-hand side, an update and the next level's dot share one launch
   // where the next level's chunks are 1024 rows.
   int pend = -1;  // level whose update is still to be applied
-  auto update = [&](int a) {
+  bool copied = false;
+  auto update = [&](int a, bool last) {
     const void* Y = fmt == 2 ? H.Y16[a].p : (fmt == 1 ? H.Y32[a].p : H.Y64[a].p);
     ProfScope ps(P, 1, s);
-    lsk::launch_hodlr_update(fmt, Y, H.svec.as<double2>(), z, ldz, H.N, H.rank[a], H.N >> a, 1 << a, nrhs, s);
+    copied = lsk::launch_hodlr_update(fmt, Y, H.svec.as<double2>(), z, ldz, H.N, H.rank[a], H.N >> a, 1 << a, nrhs,
+                                      s, last ? zcopy : nullptr, zldr, jdev, zldj);
   };
   for (int l = H.Lb - 1; l >= lstop; --l) {
     const void* W = fmt == 2 ? H.W16[l].p : (fmt == 1 ? H.W32[l].p : H.W64[l].p);
@@ -792,7 +797,7 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
       lsk::launch_hodlr_upd_dot(H.Y16[pend].p, H.rank[pend], H.svec.as<double2>(), H.N >> pend, 1 << pend, W, rl, z,
                                 H.N, H.partial.as<double2>(), H.chunk[l], s);
     } else {
-      if (pend >= 0) update(pend);
+      if (pend >= 0) update(pend, false);
       ProfScope pd(P, 5, s);
       lsk::launch_hodlr_dot(fmt, W, z, ldz, H.partial.as<double2>(), H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s);
     }
@@ -804,7 +809,8 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
                            true, nrhs, s);
     pend = l;
   }
-  if (pend >= 0) update(pend);
+  if (pend >= 0) update(pend, true);
+  if (zcopy && !copied) lsk::launch_kd_copy(z, ldz, 0, zcopy, zldr, zldj, H.N, jdev, nullptr, nrhs, s);
   hip_check(hipGetLastError(), "hodlr kernels");
 }
 
@@ -1382,14 +1388,16 @@ void kd_step(ls_problem* P, const GmresCfg& cfg, bool op32, const KdView& v, hip
   const long long hr = (long long)m * maxv;
   if (cfg.pc) {
     // the leaf solves read q_j straight from the basis (column index on the device)
-    hodlr_apply(P, cfg.pcf, Q, ldqr, z, N, nrhs, 0, s, v.jd, ldqv);
+    // and the last level's update also stores z~_j into Z (flexible)
+    hodlr_apply(P, cfg.pcf, Q, ldqr, z, N, nrhs, 0, s, v.jd, ldqv, cfg.flexible ? P->kZ.as<double2>() : nullptr,
+                (long long)(cfg.dcgs2 ? maxv : m) * N, N);
   } else {
     lsk::launch_kd_copy(Q, ldqr, ldqv, vin, N, 0, N, v.jd, v.state, nrhs, s);
     lsk::launch_axpby(1.0, vin, N, 0.0, vin, N, z, N, N, nrhs, s);
+    if (cfg.flexible)
+      lsk::launch_kd_copy(z, N, 0, P->kZ.as<double2>(), (long long)(cfg.dcgs2 ? maxv : m) * N, N, N, v.jd, v.state,
+                          nrhs, s);
   }
-  if (cfg.flexible)
-    lsk::launch_kd_copy(z, N, 0, P->kZ.as<double2>(), (long long)(cfg.dcgs2 ? maxv : m) * N, N, N, v.jd, v.state,
-                        nrhs, s);
   fmm_apply(P, op32, z, N, w, N, nrhs, 1.0, P->coef, false, s);
   if (cfg.dcgs2) {
     // delayed CGS2: slot j holds u_j; one pass of inner products, the small O(j^2) update of

@@ -89,8 +89,11 @@ void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, d
 // need r <= 64); coreinv unused when !apply
 void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, double2* sout, int r, int nodes,
                        int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s);
-void launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
-                         long long nodesize, int nodes, int nrhs, hipStream_t s);
+// z -= Y s per level.  z2 != NULL asks for a copy of the result in column *jdev of a basis
+// (z2 + rhs*z2ldr + *jdev*z2ldj); returns whether the launch made it (the caller copies otherwise)
+bool launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
+                         long long nodesize, int nodes, int nrhs, hipStream_t s, double2* z2 = nullptr,
+                         long long z2ldr = 0, const int* jdev = nullptr, long long z2ldj = 0);
 
 // ---- Krylov vector kernels (complex128) ----
 void launch_gs_dot(const double2* Q, long long ldq_vec, long long ldq_rhs, int nv, const double2* w, long long ldw,
@@ -111,7 +114,7 @@ void launch_cast_bf16(const void* in, void* out, long long n, hipStream_t s);
 
 
 // ---- device-driven Arnoldi step (the Arnoldi index j lives in device memory) ----
-// dst column j = src column j for active columns (state[rhs] == 0)
+// dst column j = src column j for active columns (state[rhs] == 0; state NULL: every column)
 void launch_kd_copy(const double2* src, long long src_ldr, long long src_ldj, double2* dst, long long dst_ldr,
                     long long dst_ldj, long long N, const int* jdev, const int* state, int nrhs, hipStream_t s);
 // partial dot products of Q columns 0..j with w (conjugated Q)

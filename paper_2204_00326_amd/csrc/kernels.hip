@@ -1097,7 +1097,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_hodlr_update_wide(const typename V2<T>::type* __restrict__ Y,
                                                            const double2* __restrict__ sv, double2* __restrict__ z,
                                                            long long ldz, long long N, int r, long long nodesize,
-                                                           int nodes, int nrf) {
+                                                           int nodes, int nrf, double2* __restrict__ z2,
+                                                           long long z2ldr, const int* __restrict__ jdev,
+                                                           long long z2ldj) {
   constexpr int R = 16 / (int)sizeof(typename V2<T>::type);
   const long long bx = nrf ? blockIdx.x / nrf : blockIdx.x;
   const int rhs = nrf ? blockIdx.x % nrf : blockIdx.y;
@@ -1132,12 +1134,15 @@ __global__ __launch_bounds__(256) void k_hodlr_update_wide(const typename V2<T>:
     __builtin_amdgcn_sched_group_barrier(0x0020, 16, 0);
     __builtin_amdgcn_sched_group_barrier(0x0002, 32 * R, 0);
   }
+  // z2 != NULL: the result also goes to column *jdev of a basis (the stored z~ of flexible GMRES)
+  double2* zc = z2 ? z2 + rhs * z2ldr + (long long)(*jdev) * z2ldj : nullptr;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     double2 o = z[rhs * ldz + i + q];
     o.x -= re[q];
     o.y -= im[q];
     z[rhs * ldz + i + q] = o;
+    if (zc) zc[i + q] = o;
   }
 }
 
@@ -1272,8 +1277,9 @@ void launch_hodlr_upd_dot(const void* Y, int ra, const double2* sv, long long no
   }
 }
 
-void launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
-                         long long nodesize, int nodes, int nrhs, hipStream_t s) {
+bool launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
+                         long long nodesize, int nodes, int nrhs, hipStream_t s, double2* z2, long long z2ldr,
+                         const int* jdev, long long z2ldj) {
   if (fmt != 0 && N % 64 == 0 && nodesize % 128 == 0) {
     const int R = fmt == 2 ? 4 : 2;
     const unsigned nbx = (unsigned)((N / R + 255) / 256);
@@ -1281,12 +1287,14 @@ void launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, 
     dim3 gridw(nrf ? nbx * nrhs : nbx, nrf ? 1 : nrhs);
     if (fmt == 2) {
       auto kern = k_hodlr_update_wide<bf16>;
-      LSK_LAUNCH(kern, gridw, 256, 0, s, (const BF2*)Y, sv, z, ldz, N, r, nodesize, nodes, nrf);
+      LSK_LAUNCH(kern, gridw, 256, 0, s, (const BF2*)Y, sv, z, ldz, N, r, nodesize, nodes, nrf, z2, z2ldr, jdev,
+                 z2ldj);
     } else {
       auto kern = k_hodlr_update_wide<float>;
-      LSK_LAUNCH(kern, gridw, 256, 0, s, (const float2*)Y, sv, z, ldz, N, r, nodesize, nodes, nrf);
+      LSK_LAUNCH(kern, gridw, 256, 0, s, (const float2*)Y, sv, z, ldz, N, r, nodesize, nodes, nrf, z2, z2ldr, jdev,
+                 z2ldj);
     }
-    return;
+    return z2 != nullptr;
   }
   dim3 grid((unsigned)((N + 255) / 256), nrhs);
   if (fmt == 2) {
@@ -1299,6 +1307,7 @@ void launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, 
     auto kern = k_hodlr_update<double>;
     LSK_LAUNCH(kern, grid, 256, 0, s, (const double2*)Y, sv, z, ldz, N, r, nodesize, nodes);
   }
+  return false;
 }
 
 // =====================================================================================
@@ -1510,7 +1519,7 @@ __global__ void k_kd_copy(const double2* __restrict__ src, long long src_ldr, lo
                           double2* __restrict__ dst, long long dst_ldr, long long dst_ldj, long long N,
                           const int* __restrict__ jdev, const int* __restrict__ state) {
   const int rhs = blockIdx.y;
-  if (state[rhs] != 0) return;
+  if (state && state[rhs] != 0) return;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const long long j = *jdev;
