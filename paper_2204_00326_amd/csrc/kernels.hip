@@ -1998,7 +1998,7 @@ __global__ __launch_bounds__(256) void k_kd_dcgs2_axpy(double2* __restrict__ Q, 
   Qb[(long long)(j + 1) * ldq_vec + i] = un;
 }
 
-constexpr int kDot2Cols = 8;
+constexpr int kDot2Cols = 4;
 
 void launch_kd_dot2(const double2* Q, long long ldq_vec, long long ldq_rhs, int maxv, const double2* w, long long ldw,
                     double2* partial, long long N, int rpb, const int* jdev, const int* state, int nrhs,
