@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--sample-every", type=int, default=7, help="time every k-th launch of a kernel class")
     ap.add_argument("--pc-bf16", type=int, default=1, help="bfloat16 HODLR factors in mixed solves (0: complex64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tradeoff-rank", type=int, default=128,
+                    help="also time the mixed solve with this HODLR rank (setup against solve time); 0: skip")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"),
                     help="summarise two rocprofv3 --pmc runs of this bench into the traffic file and exit")
@@ -380,6 +382,35 @@ def main():
         "ranks": {"fp64": st["rank_max64"], "fp32": st["rank_max32"]},
         "roofline": roof,
     }
+    if args.tradeoff_rank > 0:
+        # the same problem with a higher-rank preconditioner: longer setup (host-side HODLR
+        # factorisation), fewer iterations; reported beside the headline, not in it
+        P.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P2 = ls.Problem(pb.points(), pb.q, kappa, 1e-10,
+                        ls.Options(hodlr_rank=args.tradeoff_rank, hodlr_rank_div=args.rank_div, prec=ls.LS_MIXED,
+                                   eps_inner=1e-7, inner_tol=args.delta32, restart=args.restart, maxit=2000,
+                                   graph_iters=args.graph_iters, pc_bf16=args.pc_bf16))
+        if args.autotune:
+            P2.autotune()
+        t_setup2 = time.perf_counter() - t0
+        f2 = P2.rhs_planewave([0.0])
+        P2.solve(f2, tol=1e-8, prec=ls.LS_MIXED)
+        torch.cuda.synchronize()
+        ts2 = []
+        for _ in range(max(2, min(args.steps, 5))):
+            t1 = time.perf_counter()
+            psi2, i2 = P2.solve(f2, tol=1e-8, prec=ls.LS_MIXED)
+            torch.cuda.synchronize()
+            ts2.append(time.perf_counter() - t1)
+        d2 = float(torch.linalg.vector_norm(psi2 - psi_d) / torch.linalg.vector_norm(psi_d))
+        line["rank_tradeoff"] = {"hodlr_rank": args.tradeoff_rank, "setup_s": round(t_setup2, 3),
+                                 "time_to_1e8_ms": round(1e3 * float(np.median(ts2)), 3), "iters": i2[0]["iters"],
+                                 "relres": i2[0]["relres"], "vs_fp64_rel_diff": d2,
+                                 "headline_setup_s": round(t_setup, 3), "headline_ms": round(ms_step, 3)}
+        log("rank tradeoff", line["rank_tradeoff"])
+        P2.close()
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         line["cpu_baseline"] = cpu_baseline(n, kappa, pb.q, args.cpu_seconds)

@@ -67,7 +67,8 @@ typedef struct {
   int leaf_max;       /* max points per quadtree leaf (default 64) */
   double T;           /* a box of half-width w is high-frequency iff (kappa w)^2 > T (default 16) */
   int sign;           /* s in A = I + s kappa^2 diag(q) V; -1 (default) or +1 */
-  int hodlr_rank;     /* fixed off-diagonal rank r of the HODLR preconditioner; 0 = none (default 15) */
+  int hodlr_rank;     /* fixed off-diagonal rank r of the HODLR preconditioner, 0..128; 0 = none
+                         (default 15) */
   double eps_inner;   /* NCA tolerance of the FP32 operator; <= 0: cast of the FP64 operator (default 1e-7) */
   int restart;        /* GMRES restart length m (default 200) */
   int maxit;          /* max GMRES iterations per solve (default 2000) */
@@ -94,6 +95,10 @@ typedef struct {
                          iteration instead of two of each; the stop test then runs one operator
                          application behind (the last application of a cycle is unused);
                          0: CGS2 as in the host-driven loop */
+  int pc_lowp_solves; /* 0 (default): the HODLR leaf solves and SMW core solves stay complex128 in
+                         every preconditioner apply; 1: LS_MIXED and LS_FP32 applies also keep the
+                         leaf and core inverses in the off-diagonal factors' precision (complex
+                         bfloat16 or complex64: less traffic, a less exact preconditioner) */
 } ls_options;
 
 typedef struct {
@@ -172,8 +177,8 @@ ls_status ls_apply_V(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld
 /* z = A~^{-1} r with the fixed-rank HODLR approximation A~ of A (Section 5, Eq. (eq:hybrid)).
  * prec LS_FP64: all factors complex128; LS_FP32: off-diagonal factors stored complex64;
  * LS_MIXED: off-diagonal factors complex bfloat16 when pc_bf16 = 1 (else complex64); leaf
- * and SMW core solves complex128 and all sums in FP64 in every case.  LS_ENOTSUP when
- * hodlr_rank = 0. */
+ * and SMW core solves complex128 (unless pc_lowp_solves = 1) and all sums in FP64 in every
+ * case.  LS_ENOTSUP when hodlr_rank = 0. */
 ls_status ls_precond_apply(ls_problem* P, const void* r, void* z, int nrhs, int64_t ld, int prec, void* stream);
 
 /* f_j = -s kappa^2 q u_inc(theta_j), u_inc = exp(i kappa (cos t x1 + sin t x2)) (Section 5.2).

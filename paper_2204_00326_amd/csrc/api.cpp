@@ -770,8 +770,9 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
   hodlr_ensure_ws(P, nrhs);
   {
     ProfScope ps(P, 2, s);
-    // leaf inverses in the factors' precision
-    const void* D = fmt == 2 && H.Dinv16.p ? H.Dinv16.p : (fmt >= 1 && H.Dinv32.p ? H.Dinv32.p : H.Dinv.p);
+    // leaf inverses in complex128, or in the factors' precision on request
+    const int lf = P->opt.pc_lowp_solves ? fmt : 0;
+    const void* D = lf == 2 && H.Dinv16.p ? H.Dinv16.p : (lf >= 1 && H.Dinv32.p ? H.Dinv32.p : H.Dinv.p);
     const int df = D == H.Dinv16.p ? 2 : (D == H.Dinv32.p ? 1 : 0);
     lsk::launch_leaf_apply(df, D, H.ident.as<unsigned char>(), b, ldb, z, ldz, H.lp, H.nleaves, nrhs, s, jdev,
                            bldj);
@@ -802,8 +803,8 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
       lsk::launch_hodlr_dot(fmt, W, z, ldz, H.partial.as<double2>(), H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s);
     }
     pend = -1;
-    // core inverses in the factors' precision (complex128 past rank 64)
-    const int cf = rl <= 64 ? fmt : 0;
+    // core inverses in complex128, or in the factors' precision on request
+    const int cf = P->opt.pc_lowp_solves ? fmt : 0;
     const void* C = cf == 2 ? H.core16[l].p : (cf == 1 ? H.core32[l].p : H.coreinv[l].p);
     lsk::launch_hodlr_core(cf, C, H.partial.as<double2>(), H.svec.as<double2>(), rl, nodes, H.cpc[l], H.nchunks[l],
                            true, nrhs, s);
@@ -1693,6 +1694,7 @@ void ls_default_options(ls_options* o) {
   o->graph_iters = 0;
   o->stencil_mfma = 1;
   o->pc_bf16 = 1;
+  o->pc_lowp_solves = 0;
   o->dcgs2 = 1;
 }
 
@@ -1702,7 +1704,7 @@ static void validate_options(const ls_options& o) {
   if (o.leaf_max < 1) throw LsError(LS_EINVAL, "leaf_max must be >= 1");
   if (!(o.T > 0) || !std::isfinite(o.T)) throw LsError(LS_EINVAL, "T must be positive");
   if (o.sign != -1 && o.sign != 1) throw LsError(LS_EINVAL, "sign must be -1 or +1");
-  if (o.hodlr_rank < 0 || o.hodlr_rank > 64) throw LsError(LS_EINVAL, "hodlr_rank must be in [0, 64]");
+  if (o.hodlr_rank < 0 || o.hodlr_rank > 128) throw LsError(LS_EINVAL, "hodlr_rank must be in [0, 128]");
   if (o.restart < 1) throw LsError(LS_EINVAL, "restart must be >= 1");
   if (o.maxit < 0) throw LsError(LS_EINVAL, "maxit must be >= 0");
   if (o.prec < 0 || o.prec > 2) throw LsError(LS_EINVAL, "prec must be LS_FP64, LS_FP32 or LS_MIXED");
@@ -1712,6 +1714,7 @@ static void validate_options(const ls_options& o) {
   if (o.graph_iters < 0 || o.graph_iters > 64) throw LsError(LS_EINVAL, "graph_iters must be in [0, 64]");
   if (o.stencil_mfma != 0 && o.stencil_mfma != 1) throw LsError(LS_EINVAL, "stencil_mfma must be 0 or 1");
   if (o.pc_bf16 != 0 && o.pc_bf16 != 1) throw LsError(LS_EINVAL, "pc_bf16 must be 0 or 1");
+  if (o.pc_lowp_solves != 0 && o.pc_lowp_solves != 1) throw LsError(LS_EINVAL, "pc_lowp_solves must be 0 or 1");
   if (o.dcgs2 != 0 && o.dcgs2 != 1) throw LsError(LS_EINVAL, "dcgs2 must be 0 or 1");
 }
 

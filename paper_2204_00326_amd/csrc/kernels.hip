@@ -905,60 +905,57 @@ void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, d
 
 // t = [t_A; t_B]: t_A from the chunks of the second child (rows paired with Q), t_B from
 // the first child (rows paired with S).  apply: s = coreinv * t, else s = t.  256 threads per
-// node: thread (i, h) handles entry i and half h of the summation range; LDS combines.
+// node (2r <= 256): nks = 256 / 2r threads per entry take every nks-th chunk, then a fixed-order
+// sum in LDS.
 __global__ __launch_bounds__(256) void k_hodlr_core(const double2* __restrict__ partial,
                                                     const double2* __restrict__ coreinv, double2* __restrict__ sout,
                                                     int r, int nodes, int cpc, int nchunks, int apply) {
-  __shared__ double2 t[128];
-  __shared__ double2 part[128];
+  __shared__ double2 t[256];
+  __shared__ double2 tp[256];
   const int node = blockIdx.x, rhs = blockIdx.y;
   const int r2 = 2 * r;
-  const int i = threadIdx.x & 127, h = threadIdx.x >> 7;
-  double tre = 0, tim = 0;
-  if (i < r2) {
-    const int half = i < r ? 1 : 0;  // t_A sums the second child
-    const int c = i < r ? i : i - r;
+  const int nks = 256 / r2;
+  if ((int)threadIdx.x < r2 * nks) {
+    const int v = threadIdx.x % r2, ks = threadIdx.x / r2;
+    const int half = v < r ? 1 : 0;  // t_A sums the second child
+    const int c = v < r ? v : v - r;
     const long long ch0 = (long long)node * 2 * cpc + (long long)half * cpc;
-    const int k0 = h * ((cpc + 1) >> 1), k1 = h ? cpc : ((cpc + 1) >> 1);
-    for (int k = k0; k < k1; ++k) {
-      const double2 v = partial[((long long)rhs * nchunks + ch0 + k) * r + c];
-      tre += v.x;
-      tim += v.y;
+    double re = 0, im = 0;
+    for (int k = ks; k < cpc; k += nks) {
+      const double2 p = partial[((long long)rhs * nchunks + ch0 + k) * r + c];
+      re += p.x;
+      im += p.y;
     }
+    tp[ks * r2 + v] = make_double2(re, im);
   }
-  if (h && i < r2) part[i] = make_double2(tre, tim);
   __syncthreads();
-  if (!h && i < r2) {
-    const double2 o = part[i];
-    t[i] = make_double2(tre + o.x, tim + o.y);
+  if ((int)threadIdx.x < r2) {
+    double re = 0, im = 0;
+    for (int ks = 0; ks < nks; ++ks) {
+      re += tp[ks * r2 + threadIdx.x].x;
+      im += tp[ks * r2 + threadIdx.x].y;
+    }
+    t[threadIdx.x] = make_double2(re, im);
   }
   __syncthreads();
   double2* so = sout + ((long long)rhs * nodes + node) * r2;
+  const int i = threadIdx.x;
+  if (i >= r2) return;
   if (!apply) {
-    if (!h && i < r2) so[i] = t[i];
+    so[i] = t[i];
     return;
   }
   const double2* Ci = coreinv + (long long)node * r2 * r2;  // column-major: entry (i, j) at j * r2 + i
   double re = 0, im = 0;
-  if (i < r2) {
-    const int j0 = h * r, j1 = h ? r2 : r;
-#pragma unroll 4
-    for (int j = j0; j < j1; ++j) {
-      const double2 a = Ci[(long long)j * r2 + i];
-      const double2 x = t[j];
-      re = fma(a.x, x.x, re);
-      re = fma(-a.y, x.y, re);
-      im = fma(a.x, x.y, im);
-      im = fma(a.y, x.x, im);
-    }
+  for (int j = 0; j < r2; ++j) {
+    const double2 a = Ci[(long long)j * r2 + i];
+    const double2 x = t[j];
+    re = fma(a.x, x.x, re);
+    re = fma(-a.y, x.y, re);
+    im = fma(a.x, x.y, im);
+    im = fma(a.y, x.x, im);
   }
-  __syncthreads();
-  if (h && i < r2) part[i] = make_double2(re, im);
-  __syncthreads();
-  if (!h && i < r2) {
-    const double2 o = part[i];
-    so[i] = make_double2(re + o.x, im + o.y);
-  }
+  so[i] = make_double2(re, im);
 }
 
 // Apply form split by rows: workgroup (node, slice) sums t from the partials (every slice of a
@@ -969,7 +966,7 @@ __global__ __launch_bounds__(256) void k_hodlr_core_rows(const double2* __restri
                                                          const typename V2<TC>::type* __restrict__ coreinv,
                                                          double2* __restrict__ sout, int r, int nodes, int cpc,
                                                          int nchunks, int nrf) {
-  __shared__ double2 t[128];
+  __shared__ double2 t[256];
   __shared__ double2 tp[256];
   __shared__ double2 part[8][32];
   const int node = nrf ? blockIdx.x / nrf : blockIdx.x, slice = blockIdx.y;
@@ -983,7 +980,7 @@ __global__ __launch_bounds__(256) void k_hodlr_core_rows(const double2* __restri
     const int c = v < r ? v : v - r;
     const long long ch0 = (long long)node * 2 * cpc + (long long)half * cpc;
     double re = 0, im = 0;
-#pragma unroll 4
+#pragma unroll 16
     for (int k = ks; k < cpc; k += nks) {
       const double2 p = partial[((long long)rhs * nchunks + ch0 + k) * r + c];
       re += p.x;
@@ -1030,7 +1027,7 @@ __global__ __launch_bounds__(256) void k_hodlr_core_rows(const double2* __restri
 
 void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, double2* sout, int r, int nodes,
                        int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s) {
-  if (apply && 2 * r <= 128) {
+  if (apply && 2 * r <= 256) {
     const int nrf = nrhs > 1 ? nrhs : 0;
     dim3 grid(nrf ? nodes * nrhs : nodes, (2 * r + 31) / 32, nrf ? 1 : nrhs);
     if (cfmt == 2)
@@ -1044,7 +1041,7 @@ void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, do
                                                      chunks_per_child, nchunks, nrf);
     return;
   }
-  if (apply && cfmt != 0) throw std::runtime_error("reduced-precision HODLR cores need rank <= 64");
+  if (2 * r > 256) throw std::runtime_error("HODLR cores need rank <= 128");
   dim3 grid(nodes, nrhs);
   k_hodlr_core<<<grid, 256, 0, s>>>(partial, (const double2*)coreinv, sout, r, nodes, chunks_per_child, nchunks,
                                     apply ? 1 : 0);

@@ -33,7 +33,7 @@ class _Options(C.Structure):
                 ("eps_inner", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("prec", C.c_int),
                 ("inner_tol", C.c_double), ("max_refine", C.c_int), ("build_fp32", C.c_int),
                 ("hodlr_rank_div", C.c_int), ("graph_iters", C.c_int),
-                ("stencil_mfma", C.c_int), ("pc_bf16", C.c_int), ("dcgs2", C.c_int)]
+                ("stencil_mfma", C.c_int), ("pc_bf16", C.c_int), ("dcgs2", C.c_int), ("pc_lowp_solves", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -144,6 +144,7 @@ class Options:
     stencil_mfma: int = 1
     pc_bf16: int = 1
     dcgs2: int = 1
+    pc_lowp_solves: int = 0
 
     def _c(self) -> _Options:
         o = _Options()

@@ -180,6 +180,24 @@ def test_precond_bf16_factors_close_to_fp64():
     assert 1e-6 < rel(z16, z64) < 1e-2
 
 
+def test_precond_low_precision_leaf_and_core_solves():
+    # pc_lowp_solves = 1 keeps the leaf and SMW core inverses in the factors' precision too: the
+    # mixed apply moves away from the complex128 one but stays within bfloat16 accuracy, and the
+    # default (complex128 leaf and core solves) is closer
+    n, kappa = 128, 40.0
+    pb = inputs.problem_bumps(n, kappa, seed=2, count=5)
+    P = problem("bumps128-bf16", n, kappa, pb.q, hodlr_rank=15)
+    L = problem("bumps128-lowp", n, kappa, pb.q, hodlr_rank=15, pc_lowp_solves=1)
+    b = dev(inputs.random_vector(n * n, seed=8))
+    z64 = host(P.precond_apply(b, prec=ls.LS_FP64))
+    z16 = host(P.precond_apply(b, prec=ls.LS_MIXED))
+    l16 = host(L.precond_apply(b, prec=ls.LS_MIXED))
+    l32 = host(L.precond_apply(b, prec=ls.LS_FP32))
+    say("lowp solves: bf16", rel(l16, z64), "c64", rel(l32, z64), "default bf16", rel(z16, z64))
+    assert rel(l16, z64) < 2e-2 and rel(l32, z64) < 1e-5
+    assert rel(z16, z64) < rel(l16, z64)
+
+
 def test_precond_multi_rhs_equals_single_columns():
     # several right-hand sides take the right-hand-side-fastest launch shapes; each column must
     # equal its single-column apply exactly (the same sums in the same order)
