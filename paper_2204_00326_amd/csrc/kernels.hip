@@ -328,7 +328,7 @@ struct MfmaAcc<float> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_stencil_mfma(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms,
+__global__ __launch_bounds__(256, 6) void k_stencil_mfma(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms,
                                                       const int* __restrict__ blk_task) {
   using C2 = typename P2<T>::type;
   using MA = MfmaAcc<T>;
