@@ -75,7 +75,7 @@ KERNELS_SRC = os.path.join(ROOT, "paper_2204_00326_amd", "csrc", "kernels.hip")
 # kernel names (before the argument list) of the classes the roofline may report
 # (the HBM-bound ones; the matrix-core stencil kernel serves every DAFMM pass under one name)
 COUNTED = {"hodlr_dot": "lsk::k_hodlr_dot_seg<lsk::bf16, 4>", "hodlr_update": "lsk::k_hodlr_update_wide<lsk::bf16>",
-           "hodlr_upd_dot": "lsk::k_hodlr_upd_dot<1024>"}
+           "hodlr_upd_dot": "lsk::k_hodlr_upd_dot<"}   # any chunk instantiation: same bytes per launch
 
 
 def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok):
@@ -139,8 +139,9 @@ def pmc_summary(fetch_csv, write_csv, cmd_fetch, cmd_write):
     res = {"source_sha256": _sha256(KERNELS_SRC), "copy_bytes": COPY_BYTES,
            "scale": {"FETCH_SIZE": f_fetch, "WRITE_SIZE": f_write}, "commands": [cmd_fetch, cmd_write], "kernels": {}}
     for cls, prefix in COUNTED.items():
-        fv = [v for name, vs in fetch.items() if prefix + "(" in name for v in vs]
-        wv = [v for name, vs in write.items() if prefix + "(" in name for v in vs]
+        hit = lambda name: (prefix in name) if prefix.endswith("<") else (prefix + "(" in name)
+        fv = [v for name, vs in fetch.items() if hit(name) for v in vs]
+        wv = [v for name, vs in write.items() if hit(name) for v in vs]
         if not fv or not wv:
             continue
         # the last 80 % of the dispatches: the timed solves, past the autotuner's trial shapes
@@ -308,7 +309,7 @@ def main():
     r = args.rank
     lb = st["hodlr_levels"]
     fsz = {"bf16": 4, "c64": 8}[pc_fmt]   # bytes per stored HODLR factor entry in mixed solves
-    hb = hodlr_launch_bytes(N, lb, args.rank, args.rank_div, tune["hodlr_rows"] if tune else 512, fsz,
+    hb = hodlr_launch_bytes(N, lb, args.rank, args.rank_div, tune["hodlr_rows"] if tune else 1024, fsz,
                             pc_fmt == "bf16")
     per_launch = {
         # flops of one near-field + M2L launch (8 real flops per complex multiply-add), matrix cores

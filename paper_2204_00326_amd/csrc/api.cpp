@@ -239,7 +239,7 @@ struct ls_problem {
   bool capturing = false;  // launches are being recorded into a graph (no event timers)
   struct {
     int gs_rows = 1024;    // rows per chunk of the Arnoldi reductions
-    int hodlr_rows = 512;  // max rows per chunk of the HODLR level reductions
+    int hodlr_rows = 1024;  // max rows per chunk of the HODLR level reductions
     int dot2_rows = 1024;  // rows per workgroup of the delayed-CGS2 inner products
     bool done = false;
   } tune;
