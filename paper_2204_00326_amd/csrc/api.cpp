@@ -793,7 +793,7 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
     int nodes = 1 << l;
     const int rl = H.rank[l];
     if (rl == 0) continue;
-    if (pend >= 0 && fmt == 2 && nrhs == 1 && ldz == H.N && lsk::hodlr_upd_dot_ok(H.N, H.N >> pend, H.chunk[l])) {
+    if (pend >= 0 && fmt == 2 && nrhs == 1 && lsk::hodlr_upd_dot_ok(H.N, H.N >> pend, H.chunk[l])) {
       ProfScope pf(P, 6, s);
       lsk::launch_hodlr_upd_dot(H.Y16[pend].p, H.rank[pend], H.svec.as<double2>(), H.N >> pend, 1 << pend, W, rl, z,
                                 H.N, H.partial.as<double2>(), H.chunk[l], s);
