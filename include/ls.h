@@ -230,6 +230,28 @@ ls_status ls_autotune(ls_problem* P, ls_tune_info* out, void* stream);
  * complex128, owned by the caller.  Synchronous on `stream`.  LS_ENOTSUP if kappa h >= 4/0.7072. */
 ls_status ls_green_table(int n, double h, double kappa, void* out, void* stream);
 
+/* Off-grid volume potential (Section 5, the paragraph before Section 5.1: u_scat = V[psi] from
+ * the discrete density).  At p = 1 the density is constant on each cell, so
+ *   u[t] = sum_j psi_j int_{cell j} G(|x_t - y|) dy,   G = (i/4) H0^(1)(kappa r),
+ * for any points x_t, inside or outside the grid.  Cells two or more cells away from the one
+ * containing x_t use a tensor Gauss-Legendre rule whose order is set by the distance and by
+ * kappa h; the 3 x 3 cells around x_t are integrated in polar coordinates about x_t with graded
+ * pieces along each edge.  Accuracy about 1e-10 relative per cell for kappa h <= 1.5 (the
+ * polar rules), falling slowly beyond.  targets: DEVICE, M x 2 doubles (x1, x2); psi: DEVICE complex128, N, the caller's point
+ * order; u: DEVICE complex128, M.  Direct summation over the N cells (O(M N)); asynchronous on
+ * `stream`.  LS_EINVAL for M < 0 or NULL buffers (M = 0 does nothing). */
+ls_status ls_field_eval(ls_problem* P, const double* targets, int64_t M, const void* psi, void* u, void* stream);
+
+/* The error function of Eq. (eq:error) at p = 1, the residual of the continuous equation at
+ * any points x_t:
+ *   E[t] = | psi(x_t) + s kappa^2 q_t[t] u(x_t) - f(x_t) | / kappa^2,  f = -s kappa^2 q u_inc,
+ * with u as in ls_field_eval, psi(x_t) the density of the cell containing x_t (0 outside the
+ * grid), q_t[t] the contrast at x_t itself (DEVICE, M doubles, from the caller's definition of
+ * q, so that f does not depend on the grid) and u_inc = exp(i kappa (cos theta x1 + sin theta x2)).
+ * E: DEVICE, M doubles.  Same errors as ls_field_eval. */
+ls_status ls_error_eval(ls_problem* P, const double* targets, int64_t M, const double* q_t, double theta,
+                        const void* psi, double* E, void* stream);
+
 /* Counters of the handle (ranks, entries applied per matvec, bytes, setup timings). */
 ls_status ls_stats(const ls_problem* P, ls_stats_t* out);
 void ls_destroy(ls_problem* P);

@@ -6,6 +6,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -16,6 +17,7 @@
 
 #include "../../include/ls.h"
 #include "h0.h"
+#include "field.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -223,6 +225,8 @@ struct ls_problem {
   // index maps (device): s2c/c2s caller <-> S, s2m/m2s Morton <-> S, m2c Morton -> caller
   DevBuf s2c, c2s, s2m, m2s, m2c;
   DevBuf q_c, q_m, px, py;
+  DevBuf g2c;                    // grid index a*n + b -> caller index
+  double gx0 = 0, gy0 = 0, gh = 0;  // centre of cell (0, 0) and the cell side
   FmmDev f64, f32;
   bool have32 = false;
   HodlrDev hod;
@@ -1799,6 +1803,10 @@ ls_status ls_setup(const double* points, int64_t N, const double* q, double kapp
     }
     P->N = N;
     P->n = n;
+    P->gx0 = xmin;
+    P->gy0 = ymin;
+    P->gh = h;
+    P->g2c.upload(grid2caller);
     P->kappa = kappa;
     P->tol = tol;
     P->coef = P->opt.sign * kappa * kappa;
@@ -2326,6 +2334,80 @@ ls_status ls_solve_queue(ls_problem* const* probs, int nprob, const void* const*
     for (auto& t : th) t.join();
     for (auto& st : streams) (void)hipStreamDestroy(st);
     if (err_code != LS_OK) throw LsError(err_code, err);
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
+}
+
+namespace {
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on P_n
+void gauss_legendre(int n, double* t, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(lsk::kPi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    t[i] = x;
+    w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+}
+
+const lsk::FieldRules& field_rules() {
+  static lsk::FieldRules R = [] {
+    lsk::FieldRules r{};
+    const int orders[lsk::kFieldRules] = {3, 4, 5, 6, 8, 10, 12, 16, 24, 10};
+    int off = 0;
+    for (int k = 0; k < lsk::kFieldRules; ++k) {
+      r.off[k] = off;
+      r.n[k] = orders[k];
+      gauss_legendre(orders[k], r.t + off, r.w + off);
+      off += orders[k];
+    }
+    return r;
+  }();
+  return R;
+}
+
+void field_impl(ls_problem* P, const double* targets, int64_t M, const void* psi, int mode, const double* q_t,
+                double theta, void* u, double* E, void* stream) {
+  if (!P) throw LsError(LS_EINVAL, "NULL problem");
+  if (M < 0) throw LsError(LS_EINVAL, "M must be >= 0");
+  if (M == 0) return;
+  if (!targets || !psi || (mode == 0 && !u) || (mode == 1 && (!q_t || !E)))
+    throw LsError(LS_EINVAL, "NULL buffer");
+  if (!std::isfinite(theta)) throw LsError(LS_EINVAL, "theta must be finite");
+  if (M > (int64_t)INT32_MAX) throw LsError(LS_EINVAL, "too many targets");
+  lsk::launch_field_eval(targets, M, P->n, P->gx0, P->gy0, P->gh, P->kappa, psi, P->g2c.as<int>(), field_rules(),
+                         mode, q_t, theta, (double)P->opt.sign, u, E, (hipStream_t)stream);
+  hip_check(hipGetLastError(), "field kernel");
+}
+
+}  // namespace
+
+ls_status ls_field_eval(ls_problem* P, const double* targets, int64_t M, const void* psi, void* u, void* stream) {
+  try {
+    field_impl(P, targets, M, psi, 0, nullptr, 0.0, u, nullptr, stream);
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
+}
+
+ls_status ls_error_eval(ls_problem* P, const double* targets, int64_t M, const double* q_t, double theta,
+                        const void* psi, double* E, void* stream) {
+  try {
+    field_impl(P, targets, M, psi, 1, q_t, theta, nullptr, E, stream);
     return LS_OK;
   } catch (const LsError& e) {
     return fail(e);

@@ -94,6 +94,8 @@ def lib():
     L.ls_destroy.restype = None
     L.ls_plan_describe.argtypes = [ci, cd, cd, C.POINTER(_Options), C.POINTER(_PlanInfo)]
     L.ls_green_table.argtypes = [ci, cd, cd, vp, vp]
+    L.ls_field_eval.argtypes = [vp, vp, i64, vp, vp, vp]
+    L.ls_error_eval.argtypes = [vp, vp, i64, vp, cd, vp, vp, vp]
     L.ls_profile_enable.argtypes = [vp, ci, ci]
     L.ls_profile_read.argtypes = [vp, ci, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.ls_nop_create.argtypes = [C.POINTER(_NopConfig), C.POINTER(vp)]
@@ -119,6 +121,13 @@ def lib():
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
+
+
+def _targets(t):
+    import torch
+    if t.dtype != torch.float64 or t.dim() != 2 or t.shape[1] != 2 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("targets must be a contiguous device float64 tensor of shape [M, 2]")
+    return t
 
 
 def _check(code: int):
@@ -247,6 +256,30 @@ class Problem:
         z = self._out(r, z)
         _check(lib().ls_precond_apply(self._h, r.data_ptr(), z.data_ptr(), nrhs, self.N, prec, _stream(stream)))
         return z
+
+    def field_eval(self, targets, psi, stream=None):
+        """(V psi)(x_t) at arbitrary points: targets a device float64 tensor [M, 2], psi a device
+        complex128 vector of N in the caller's point order; returns complex128 [M]."""
+        import torch
+        tg = _targets(targets)
+        if _vec(psi, self.N) != 1:
+            raise ValueError("psi must be one vector of length N")
+        u = torch.empty(tg.shape[0], dtype=torch.complex128, device=tg.device)
+        _check(lib().ls_field_eval(self._h, tg.data_ptr(), tg.shape[0], psi.data_ptr(), u.data_ptr(), _stream(stream)))
+        return u
+
+    def error_eval(self, targets, q_t, theta: float, psi, stream=None):
+        """E(x_t) of Eq. (eq:error): q_t = q(x_t) (device float64 [M]); returns float64 [M]."""
+        import torch
+        tg = _targets(targets)
+        if q_t.dtype != torch.float64 or not q_t.is_contiguous() or q_t.numel() != tg.shape[0] or not q_t.is_cuda:
+            raise ValueError("q_t must be a contiguous device float64 tensor with one value per target")
+        if _vec(psi, self.N) != 1:
+            raise ValueError("psi must be one vector of length N")
+        E = torch.empty(tg.shape[0], dtype=torch.float64, device=tg.device)
+        _check(lib().ls_error_eval(self._h, tg.data_ptr(), tg.shape[0], q_t.data_ptr(), float(theta),
+                                   psi.data_ptr(), E.data_ptr(), _stream(stream)))
+        return E
 
     def rhs_planewave(self, angles, stream=None):
         import torch

@@ -1,0 +1,112 @@
+"""GPU parity of the off-grid volume potential and the error function E(x) (ls_field_eval,
+ls_error_eval; Section 5 and Eq. (eq:error)) against the FP64 oracle, which integrates every
+cell by adaptive quadrature (near the target) or a 12 x 12 Gauss-Legendre rule: targets at cell
+centres, inside cells, next to edges and corners, just outside the grid and far away; points
+passed in a shuffled order so that the caller-order mapping is exercised."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import field as ofield
+from oracle import lsop
+from paper_2204_00326_amd import inputs, ls
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ls.lib()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def case(n=8, kappa=6.0, seed=11):
+    L = 1.0
+    h = 2 * L / n
+    x = lsop.grid_coords(n, L)
+    rng = np.random.default_rng(seed)
+    q = inputs.contrast_gaussian(x, 1.5, 10.0)
+    perm = rng.permutation(n * n)           # caller order = perm of the grid order
+    P = ls.Problem(x[perm], q[perm], kappa, 1e-10, ls.Options(hodlr_rank=0))
+    psi_grid = rng.standard_normal(n * n) + 1j * rng.standard_normal(n * n)
+    psi_caller = torch.from_numpy(psi_grid[perm]).cuda()
+    x0 = -L + 0.5 * h
+    targets = np.array([
+        x[0], x[27],                                     # cell centres
+        x[10] + [0.31 * h, -0.12 * h], x[45] + [-0.44 * h, 0.27 * h],
+        [x0 + 2.5 * h - 1e-7, x0 + 3.1 * h],             # next to an edge
+        [x0 + 4.5 * h + 2e-6, x0 + 5.5 * h - 3e-6],      # next to a corner
+        [L + 0.1, 0.3], [-L - 0.02, -L - 0.05],          # just outside the grid
+        [3.0, -2.0],                                     # far away
+    ])
+    return P, n, L, h, kappa, x0, psi_grid, psi_caller, targets
+
+
+def test_field_eval_matches_oracle():
+    P, n, L, h, kappa, x0, psi_grid, psi_c, targets = case()
+    tg = torch.from_numpy(targets).cuda()
+    u = P.field_eval(tg, psi_c).cpu().numpy()
+    ref = ofield.field(targets, n, x0, x0, h, kappa, psi_grid)
+    scale = np.abs(psi_grid).max() * h * h
+    for t in range(len(targets)):
+        err = abs(u[t] - ref[t]) / max(abs(ref[t]), scale)
+        say(t, targets[t], u[t], ref[t], err)
+        assert err < 1e-8, (t, err)
+
+
+def test_error_eval_matches_oracle_and_field():
+    P, n, L, h, kappa, x0, psi_grid, psi_c, targets = case(seed=12)
+    qx = inputs.contrast_gaussian(targets, 1.5, 10.0)
+    theta = 0.4
+    tg = torch.from_numpy(targets).cuda()
+    E = P.error_eval(tg, torch.from_numpy(qx).cuda(), theta, psi_c).cpu().numpy()
+    ref = ofield.error_function(targets, qx, theta, n, x0, x0, h, kappa, psi_grid)
+    for t in range(len(targets)):
+        assert abs(E[t] - ref[t]) <= 1e-8 * max(ref[t], 1e-3), (t, E[t], ref[t])
+
+
+def test_error_function_of_a_solve_is_small_at_cell_centres_and_larger_between():
+    # E at the cell centres of a converged FP64 solve reflects only the quadrature difference
+    # (exact cell integrals against the one-point rule of the discretisation); between the
+    # centres the piecewise-constant density adds the discretisation error
+    n, L, kappa = 64, 1.0, 20.0
+    pb = inputs.problem_bumps(n, kappa, seed=4, count=4)
+    P = ls.Problem(pb.points(), pb.q, kappa, 1e-10, ls.Options(hodlr_rank=15))
+    f = P.rhs_planewave([0.0])
+    psi, info = P.solve(f, tol=1e-10)
+    assert info[0]["status"] == "CONVERGED"
+    rng = np.random.default_rng(5)
+    x = pb.points()
+    h = 2 * L / n
+    strong = np.flatnonzero(pb.q > 0.3 * pb.q.max())   # where the contrast (and psi) is large
+    idx = rng.choice(strong, min(64, strong.size), replace=False)
+    centres = x[idx]
+    between = centres + rng.uniform(-0.5, 0.5, centres.shape) * h
+    qc = torch.from_numpy(pb.q[idx].copy()).cuda()
+    bumps = inputs.draw_bumps(np.random.default_rng(4), 4)   # the contrast of problem_bumps(seed 4)
+    assert np.allclose(inputs.contrast_bumps(x, bumps), pb.q)
+    qb = torch.from_numpy(inputs.contrast_bumps(between, bumps)).cuda()
+    Ec = P.error_eval(torch.from_numpy(centres).cuda(), qc, 0.0, psi).cpu().numpy()
+    Eb = P.error_eval(torch.from_numpy(between).cuda(), qb, 0.0, psi).cpu().numpy()
+    scale = np.abs(psi.cpu().numpy()).max() / kappa ** 2
+    say("E centres median", np.median(Ec) / scale, "between", np.median(Eb) / scale)
+    assert np.median(Ec) < 0.02 * scale          # exact vs one-point rule: about (kappa h)^2 / 24
+    assert np.median(Eb) > 3 * np.median(Ec)     # the piecewise-constant density between centres
+
+
+def test_bad_arguments():
+    P, n, L, h, kappa, x0, psi_grid, psi_c, targets = case()
+    with pytest.raises(ValueError):
+        P.field_eval(torch.zeros(3, 3, dtype=torch.float64, device="cuda"), psi_c)
+    code = ls.lib().ls_field_eval(P._h, None, 3, psi_c.data_ptr(), None, None)
+    assert code == ls.LS_EINVAL
+    assert ls.lib().ls_field_eval(P._h, None, 0, None, None, None) == ls.LS_OK
