@@ -278,6 +278,32 @@ def main():
     err_mixed = float(torch.linalg.vector_norm(psi_m - psi_d) / torch.linalg.vector_norm(psi_d))
     log("fp64 solve", info_d, f"{t_fp64*1e3:.1f} ms; mixed vs fp64 rel diff {err_mixed:.2e}")
 
+    # the error function E(x) of the mixed solution at random points of the domain (off the
+    # grid), Eq. (eq:error): the paper's accuracy measure; direct summation over the cells
+    rng = np.random.default_rng(7)
+    M = 256
+    pts = rng.uniform(-1.0, 1.0, (M, 2))
+    qx = (np.hypot(pts[:, 0], pts[:, 1]) < 0.6).astype(np.float64)
+    tg = torch.from_numpy(pts).cuda()
+    qd = torch.from_numpy(qx).cuda()
+    P.error_eval(tg, qd, 0.0, psi_m)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    E = P.error_eval(tg, qd, 0.0, psi_m)
+    torch.cuda.synchronize()
+    t_err = time.perf_counter() - t1
+    E = E.cpu().numpy()
+    inside = qx > 0
+    psi_scale = float(torch.linalg.vector_norm(psi_m, ord=float("inf"))) / kappa ** 2
+    err_fn = {"targets": M, "ms": round(1e3 * t_err, 3), "cells_per_target": n * n,
+              "cell_integrals_per_s": round(M * n * n / t_err, 1),
+              "E_median_in_disc": float(np.median(E[inside])) / psi_scale,
+              "E_max_in_disc": float(E[inside].max()) / psi_scale,
+              "E_median_outside": float(np.median(E[~inside])) / psi_scale,
+              "scale": "E / (max|psi| / kappa^2)",
+              "note": "per target all n^2 cells are visited; cells with zero density are skipped"}
+    log("error function", err_fn)
+
     # matvec rates
     x = torch.randn(n * n, dtype=torch.complex128, device="cuda")
     y = torch.empty_like(x)
@@ -382,6 +408,7 @@ def main():
         "setup_s": round(t_setup, 3),
         "ranks": {"fp64": st["rank_max64"], "fp32": st["rank_max32"]},
         "roofline": roof,
+        "error_function": err_fn,
     }
     if args.tradeoff_rank > 0:
         # the same problem with a higher-rank preconditioner: longer setup (host-side HODLR
