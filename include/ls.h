@@ -99,6 +99,11 @@ typedef struct {
                          every preconditioner apply; 1: LS_MIXED and LS_FP32 applies also keep the
                          leaf and core inverses in the off-diagonal factors' precision (complex
                          bfloat16 or complex64: less traffic, a less exact preconditioner) */
+  double hodlr_tol;   /* 0 (default): every off-diagonal HODLR block at the fixed rank (the
+                         preconditioner of Section 5); eps > 0: each block's ACA stops at
+                         ||u_k|| ||v_k|| <= eps ||S_k||_F (the HODLR factorisation at a fixed
+                         tolerance, Section 5), its rank still capped by hodlr_rank; for
+                         ls_direct_solve */
 } ls_options;
 
 typedef struct {
@@ -135,6 +140,9 @@ typedef struct {
   int hodlr_rank_sum;     /* sum over binary levels of the off-diagonal rank */
   int64_t hodlr_dense_leaves; /* leaves whose diagonal block is not the identity */
   double t_plan_ms, t_nca_ms, t_hodlr_ms, t_setup_ms;
+  int64_t hodlr_rank_used_sum;  /* sum of the ranks the ACA reached over the off-diagonal blocks */
+  int64_t hodlr_blocks;         /* number of off-diagonal blocks */
+  int hodlr_rank_used_max;      /* largest of them */
 } ls_stats_t;
 
 /* Plan description for a uniform n x n grid on [-L, L]^2 (host only, no device use).
@@ -173,6 +181,16 @@ ls_status ls_matvec(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld,
 
 /* u = V psi: the scattered field on the grid (Section 5, last paragraph before 5.1). */
 ls_status ls_apply_V(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld, int prec, void* stream);
+
+/* HODLR direct solver (Section 5: the factorisation used as the solver, the paper's choice for
+ * many right-hand sides): psi = A~^{-1} f, then iterative refinement psi += A~^{-1} (f - A psi)
+ * with FP64 DAFMM products until ||f - A psi|| <= tol ||f|| for every column or max_refine steps
+ * (tol = 0: exactly max_refine steps).  A~ is the factorisation built at setup; with hodlr_tol > 0
+ * it holds each off-diagonal block to that tolerance.  Same vector conventions as ls_solve; info
+ * (host, nrhs, may be NULL): iters = n_refine = refinement steps, relres = final FP64 residual,
+ * status LS_CONVERGED (<= tol), LS_MAXIT or LS_NAN.  Synchronous.  LS_ENOTSUP when hodlr_rank = 0. */
+ls_status ls_direct_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld, double tol, int max_refine,
+                          ls_solve_info* info, void* stream);
 
 /* z = A~^{-1} r with the fixed-rank HODLR approximation A~ of A (Section 5, Eq. (eq:hybrid)).
  * prec LS_FP64: all factors complex128; LS_FP32: off-diagonal factors stored complex64;

@@ -171,6 +171,8 @@ struct HodlrDev {
   std::vector<DevBuf> Y64, W64, Y32, W32, Y16, W16;  // 16: complex bfloat16
   std::vector<DevBuf> coreinv, core32, core16;      // SMW core inverses, column-major per node
   bool have16 = false;
+  int64_t used_rank_sum = 0, blocks = 0;  // ACA ranks reached, over all off-diagonal blocks
+  int used_rank_max = 0;
   DevBuf partial, svec;
   std::vector<long long> chunk;  // per level
   std::vector<int> nchunks, cpc;
@@ -894,6 +896,9 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
   std::vector<std::pair<int, int>> work;  // (level, node)
   for (int l = 0; l < H.Lb; ++l)
     for (int nd = 0; nd < (1 << l); ++nd) work.push_back({l, nd});
+  // ranks the ACA reached per block (below the cap when hodlr_tol > 0 stops it early; the
+  // factor columns past a block's rank stay zero, which leaves identity rows in its core)
+  std::vector<int> used_rank(work.size() * 2, 0);
   parallel_for((int)work.size() * 2, [&](int wi) {
     int l = work[wi / 2].first, nd = work[wi / 2].second, which = wi % 2;
     long long ns = N >> l, lo = (long long)nd * ns, mid = lo + ns / 2;
@@ -913,13 +918,21 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
       int aj = mort_a[gj], bj = mort_b[gj];
       for (int i = 0; i < m; ++i) out[i] = coef * qm[r0 + i] * W(mort_a[r0 + i] - aj, mort_b[r0 + i] - bj);
     };
-    ls::ACAResult R = ls::aca(m, n, H.rank[l], 0.0, &rz, rowfn, colfn);
+    ls::ACAResult R = ls::aca(m, n, H.rank[l], P->opt.hodlr_tol, &rz, rowfn, colfn);
     int k = (int)R.u.size();
+    used_rank[wi] = k;
     for (int c = 0; c < k; ++c) {
       for (int i = 0; i < m; ++i) Uh[l][(size_t)c * N + r0 + i] = R.u[c][i];
       for (int j = 0; j < n; ++j) Wh[l][(size_t)c * N + c0 + j] = R.v[c][j];
     }
   });
+  H.used_rank_sum = 0;
+  H.used_rank_max = 0;
+  for (int k : used_rank) {
+    H.used_rank_sum += k;
+    H.used_rank_max = std::max(H.used_rank_max, k);
+  }
+  H.blocks = (int64_t)used_rank.size();
   // upload U (becomes Y in place) and W; compute Y_l = D_l^{-1} U_l and the SMW cores
   H.Y64.resize(H.Lb);
   H.W64.resize(H.Lb);
@@ -1699,6 +1712,7 @@ void ls_default_options(ls_options* o) {
   o->stencil_mfma = 1;
   o->pc_bf16 = 1;
   o->pc_lowp_solves = 0;
+  o->hodlr_tol = 0.0;
   o->dcgs2 = 1;
 }
 
@@ -1719,6 +1733,7 @@ static void validate_options(const ls_options& o) {
   if (o.stencil_mfma != 0 && o.stencil_mfma != 1) throw LsError(LS_EINVAL, "stencil_mfma must be 0 or 1");
   if (o.pc_bf16 != 0 && o.pc_bf16 != 1) throw LsError(LS_EINVAL, "pc_bf16 must be 0 or 1");
   if (o.pc_lowp_solves != 0 && o.pc_lowp_solves != 1) throw LsError(LS_EINVAL, "pc_lowp_solves must be 0 or 1");
+  if (!(o.hodlr_tol >= 0 && o.hodlr_tol < 1)) throw LsError(LS_EINVAL, "hodlr_tol must be in [0, 1)");
   if (o.dcgs2 != 0 && o.dcgs2 != 1) throw LsError(LS_EINVAL, "dcgs2 must be 0 or 1");
 }
 
@@ -1941,6 +1956,9 @@ ls_status ls_setup(const double* points, int64_t N, const double* q, double kapp
     S.hodlr_levels = P->have_hodlr ? P->hod.Lb : 0;
     for (int l = 0; P->have_hodlr && l < P->hod.Lb; ++l) S.hodlr_rank_sum += P->hod.rank[l];
     S.hodlr_dense_leaves = P->have_hodlr ? P->hod.dense_leaves : 0;
+    S.hodlr_rank_used_sum = P->have_hodlr ? P->hod.used_rank_sum : 0;
+    S.hodlr_blocks = P->have_hodlr ? P->hod.blocks : 0;
+    S.hodlr_rank_used_max = P->have_hodlr ? P->hod.used_rank_max : 0;
     S.t_plan_ms = t_plan - t0;
     S.t_nca_ms = t_nca - t_w;
     S.t_hodlr_ms = t_h - t_nca;
@@ -2031,6 +2049,60 @@ ls_status ls_precond_apply(ls_problem* P, const void* r, void* z, int nrhs, int6
     hodlr_apply(P, fmt, a, N, a, N, nrhs, 0, s);
     lsk::launch_permute(a, N, (double2*)z, ld, P->m2c.as<int>(), N, nrhs, true, s);
     hip_check(hipGetLastError(), "precond");
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
+}
+
+ls_status ls_direct_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld, double tol, int max_refine,
+                          ls_solve_info* info, void* stream) {
+  try {
+    const double t0 = now_ms();
+    check_vec_args(P, f, psi, nrhs, ld);
+    if (!P->have_hodlr) throw LsError(LS_ENOTSUP, "no HODLR factorisation (hodlr_rank = 0)");
+    if (!(tol >= 0 && tol < 1)) throw LsError(LS_EINVAL, "tol must be in [0, 1)");
+    if (max_refine < 0) throw LsError(LS_EINVAL, "max_refine must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const long long N = P->N;
+    P->kf.ensure((size_t)N * nrhs * 16);
+    P->kx.ensure((size_t)N * nrhs * 16);
+    P->kdx.ensure((size_t)N * nrhs * 16);
+    ensure_ws(P, nrhs);
+    double2* fm = P->kf.as<double2>();
+    double2* xm = P->kx.as<double2>();
+    double2* dm = P->kdx.as<double2>();
+    double2* w = P->w_y.as<double2>();
+    lsk::launch_permute((const double2*)f, ld, fm, N, P->m2c.as<int>(), N, nrhs, false, s);
+    std::vector<double> fn, rn;
+    norms(P, fm, nrhs, fn, s);
+    // x = A~^{-1} f, then refinement x += A~^{-1} (f - A x) with FP64 DAFMM products
+    hodlr_apply(P, 0, fm, N, xm, N, nrhs, 0, s);
+    int steps = 0;
+    for (;;) {
+      op_apply(P, false, xm, w, nrhs, s);
+      lsk::launch_axpby(1.0, fm, N, -1.0, w, N, w, N, N, nrhs, s);
+      norms(P, w, nrhs, rn, s);
+      bool ok = true;
+      for (int c = 0; c < nrhs; ++c) ok &= !(rn[c] > tol * (fn[c] > 0 ? fn[c] : 1.0));
+      if (ok || steps >= max_refine) break;
+      hodlr_apply(P, 0, w, N, dm, N, nrhs, 0, s);
+      lsk::launch_axpby(1.0, xm, N, 1.0, dm, N, xm, N, N, nrhs, s);
+      ++steps;
+    }
+    lsk::launch_permute(xm, N, (double2*)psi, ld, P->m2c.as<int>(), N, nrhs, true, s);
+    hip_check(hipStreamSynchronize(s), "direct solve");
+    const double t1 = now_ms();
+    if (info)
+      for (int c = 0; c < nrhs; ++c) {
+        const double rel = fn[c] > 0 ? rn[c] / fn[c] : 0.0;
+        info[c].iters = steps;
+        info[c].relres = rel;
+        info[c].status = !std::isfinite(rel) ? LS_NAN : (rel <= tol ? LS_CONVERGED : LS_MAXIT);
+        info[c].n_refine = steps;
+        info[c].t_solve_ms = t1 - t0;
+        info[c].relres0 = 1.0;
+      }
     return LS_OK;
   } catch (const LsError& e) {
     return fail(e);

@@ -33,7 +33,8 @@ class _Options(C.Structure):
                 ("eps_inner", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("prec", C.c_int),
                 ("inner_tol", C.c_double), ("max_refine", C.c_int), ("build_fp32", C.c_int),
                 ("hodlr_rank_div", C.c_int), ("graph_iters", C.c_int),
-                ("stencil_mfma", C.c_int), ("pc_bf16", C.c_int), ("dcgs2", C.c_int), ("pc_lowp_solves", C.c_int)]
+                ("stencil_mfma", C.c_int), ("pc_bf16", C.c_int), ("dcgs2", C.c_int), ("pc_lowp_solves", C.c_int),
+                ("hodlr_tol", C.c_double)]
 
 
 class _Info(C.Structure):
@@ -49,7 +50,8 @@ class _Stats(C.Structure):
                 ("m2l_pairs", C.c_int64), ("stored_bytes64", C.c_int64), ("stored_bytes32", C.c_int64),
                 ("hodlr_bytes", C.c_int64), ("hodlr_levels", C.c_int), ("hodlr_rank_sum", C.c_int),
                 ("hodlr_dense_leaves", C.c_int64), ("t_plan_ms", C.c_double), ("t_nca_ms", C.c_double),
-                ("t_hodlr_ms", C.c_double), ("t_setup_ms", C.c_double)]
+                ("t_hodlr_ms", C.c_double), ("t_setup_ms", C.c_double),
+                ("hodlr_rank_used_sum", C.c_int64), ("hodlr_blocks", C.c_int64), ("hodlr_rank_used_max", C.c_int)]
 
 
 class _PlanInfo(C.Structure):
@@ -87,6 +89,7 @@ def lib():
         getattr(L, name).argtypes = [vp, vp, vp, ci, i64, ci, vp]
     L.ls_rhs_planewave.argtypes = [vp, vp, ci, vp, i64, vp]
     L.ls_solve.argtypes = [vp, vp, vp, ci, i64, cd, ci, ci, C.POINTER(_Info), vp]
+    L.ls_direct_solve.argtypes = [vp, vp, vp, ci, i64, cd, ci, C.POINTER(_Info), vp]
     L.ls_stats.argtypes = [vp, C.POINTER(_Stats)]
     L.ls_solve_queue.argtypes = [vp, ci, vp, vp, cd, ci, ci, ci, C.POINTER(_Info)]
     L.ls_autotune.argtypes = [vp, C.POINTER(_TuneInfo), vp]
@@ -154,6 +157,7 @@ class Options:
     pc_bf16: int = 1
     dcgs2: int = 1
     pc_lowp_solves: int = 0
+    hodlr_tol: float = 0.0
 
     def _c(self) -> _Options:
         o = _Options()
@@ -300,6 +304,19 @@ class Problem:
         out = [{"iters": i.iters, "relres": i.relres, "status": STATUS.get(i.status, str(i.status)),
                 "n_refine": i.n_refine, "t_solve_ms": i.t_solve_ms,
                 "relres0": i.relres0} for i in infos]
+        return psi, out
+
+    def direct_solve(self, f, psi=None, tol: float = 1e-8, max_refine: int = 10, stream=None):
+        """HODLR direct solve with FP64 iterative refinement (ls_direct_solve)."""
+        import torch
+        nrhs = _vec(f, self.N)
+        if psi is None:
+            psi = torch.zeros_like(f)
+        infos = (_Info * nrhs)()
+        _check(lib().ls_direct_solve(self._h, f.data_ptr(), psi.data_ptr(), nrhs, self.N, float(tol),
+                                     int(max_refine), infos, _stream(stream)))
+        out = [{"iters": i.iters, "relres": i.relres, "status": STATUS.get(i.status, str(i.status)),
+                "n_refine": i.n_refine, "t_solve_ms": i.t_solve_ms} for i in infos]
         return psi, out
 
     def autotune(self, stream=None) -> dict:
