@@ -18,6 +18,7 @@
 #include "../../include/ls.h"
 #include "h0.h"
 #include "field.h"
+#include "hodlr_setup.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -888,44 +889,121 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
   if (P->opt.hodlr_rank_div > 0)
     for (int l = 0; l < H.Lb; ++l)
       H.rank[l] = (int)std::max<long long>(1, std::min<long long>(r, (N >> (l + 1)) / P->opt.hodlr_rank_div));
-  std::vector<std::vector<zd>> Uh(H.Lb), Wh(H.Lb);
-  for (int l = 0; l < H.Lb; ++l) {
-    Uh[l].assign((size_t)N * H.rank[l], zd(0));
-    Wh[l].assign((size_t)N * H.rank[l], zd(0));
-  }
-  std::vector<std::pair<int, int>> work;  // (level, node)
-  for (int l = 0; l < H.Lb; ++l)
-    for (int nd = 0; nd < (1 << l); ++nd) work.push_back({l, nd});
-  // ranks the ACA reached per block (below the cap when hodlr_tol > 0 stops it early; the
-  // factor columns past a block's rank stay zero, which leaves identity rows in its core)
-  std::vector<int> used_rank(work.size() * 2, 0);
-  parallel_for((int)work.size() * 2, [&](int wi) {
-    int l = work[wi / 2].first, nd = work[wi / 2].second, which = wi % 2;
-    long long ns = N >> l, lo = (long long)nd * ns, mid = lo + ns / 2;
-    // which = 0: A[I1, I2] ~ P Q^T ; which = 1: A[I2, I1] ~ R S^T
-    long long r0 = which ? mid : lo, c0 = which ? lo : mid;
-    int m = (int)(ns / 2), n = (int)(ns / 2);
-    std::vector<char> rz(m);
-    for (int i = 0; i < m; ++i) rz[i] = qm[r0 + i] == 0.0;
-    auto rowfn = [&](int i, zd* out) {
-      long long gi = r0 + i;
-      double cq = coef * qm[gi];
-      int ai = mort_a[gi], bi = mort_b[gi];
-      for (int j = 0; j < n; ++j) out[j] = cq * W(ai - mort_a[c0 + j], bi - mort_b[c0 + j]);
-    };
-    auto colfn = [&](int j, zd* out) {
-      long long gj = c0 + j;
-      int aj = mort_a[gj], bj = mort_b[gj];
-      for (int i = 0; i < m; ++i) out[i] = coef * qm[r0 + i] * W(mort_a[r0 + i] - aj, mort_b[r0 + i] - bj);
-    };
-    ls::ACAResult R = ls::aca(m, n, H.rank[l], P->opt.hodlr_tol, &rz, rowfn, colfn);
-    int k = (int)R.u.size();
-    used_rank[wi] = k;
-    for (int c = 0; c < k; ++c) {
-      for (int i = 0; i < m; ++i) Uh[l][(size_t)c * N + r0 + i] = R.u[c][i];
-      for (int j = 0; j < n; ++j) Wh[l][(size_t)c * N + c0 + j] = R.v[c][j];
+  H.Y64.resize(H.Lb);
+  H.W64.resize(H.Lb);
+  H.coreinv.resize(H.Lb);
+  std::vector<int> used_rank;  // ranks the ACA reached, per block
+  if (P->opt.hodlr_tol <= 0.0) {
+    // fixed rank: batched ACA on the device, the factors written in place
+    DevBuf wdev, mad, mbd, rowu, colu, rbuf, ib, jb, state, kcur, retry;
+    wdev.upload(W.w);
+    mad.upload(mort_a);
+    mbd.upload(mort_b);
+    std::vector<unsigned char> rz((size_t)N);
+    for (long long i = 0; i < N; ++i) rz[i] = qm[i] == 0.0 ? 1 : 0;
+    rowu.alloc((size_t)N);
+    colu.alloc((size_t)N);
+    rbuf.alloc((size_t)N * 16);
+    const int nbmax = 1 << H.Lb;
+    for (DevBuf* d : {&ib, &jb, &state, &kcur, &retry}) d->alloc((size_t)nbmax * 4);
+    std::vector<int> hbuf(nbmax);
+    hipStream_t s0 = nullptr;
+    for (int l = 0; l < H.Lb; ++l) {
+      const int rl = H.rank[l];
+      H.Y64[l].alloc((size_t)N * rl * 16);
+      H.W64[l].alloc((size_t)N * rl * 16);
+      hip_check(hipMemsetAsync(H.Y64[l].p, 0, (size_t)N * rl * 16, s0), "memset");
+      hip_check(hipMemsetAsync(H.W64[l].p, 0, (size_t)N * rl * 16, s0), "memset");
+      hip_check(hipMemcpyAsync(rowu.p, rz.data(), (size_t)N, hipMemcpyHostToDevice, s0), "rows h2d");
+      hip_check(hipMemsetAsync(colu.p, 0, (size_t)N, s0), "memset");
+      lsk::AcaLevel L{};
+      L.W = wdev.as<double2>();
+      L.ma = mad.as<int>();
+      L.mb = mbd.as<int>();
+      L.q = P->q_m.as<double>();
+      L.coef = coef;
+      L.n = P->n;
+      L.N = N;
+      L.S = N >> (l + 1);
+      L.nb = 1 << (l + 1);
+      L.U = H.Y64[l].as<double2>();
+      L.V = H.W64[l].as<double2>();
+      L.row_used = rowu.as<unsigned char>();
+      L.col_used = colu.as<unsigned char>();
+      L.rbuf = rbuf.as<double2>();
+      L.ib = ib.as<int>();
+      L.jb = jb.as<int>();
+      L.state = state.as<int>();
+      L.kcur = kcur.as<int>();
+      L.retry = retry.as<int>();
+      lsk::launch_aca_start(L, s0);
+      const int kmax = (int)std::min<long long>(rl, L.S);
+      for (int k = 0; k < kmax; ++k) {
+        lsk::launch_aca_row(L, false, s0);
+        for (;;) {  // an exactly zero residual row: try the next unused one
+          hip_check(hipMemcpyAsync(hbuf.data(), retry.p, (size_t)L.nb * 4, hipMemcpyDeviceToHost, s0), "retry d2h");
+          hip_check(hipStreamSynchronize(s0), "aca");
+          bool any = false;
+          for (int b = 0; b < L.nb; ++b) any |= hbuf[b] != 0;
+          if (!any) break;
+          lsk::launch_aca_row(L, true, s0);
+        }
+        lsk::launch_aca_col(L, kmax, s0);
+      }
+      hip_check(hipMemcpyAsync(hbuf.data(), kcur.p, (size_t)L.nb * 4, hipMemcpyDeviceToHost, s0), "ranks d2h");
+      hip_check(hipStreamSynchronize(s0), "aca");
+      used_rank.insert(used_rank.end(), hbuf.begin(), hbuf.begin() + L.nb);
+      H.bytes += (int64_t)2 * N * rl * 16;
     }
-  });
+    hip_check(hipGetLastError(), "aca kernels");
+  } else {
+    // blocks to a tolerance (rank capped): the host ACA with Rjasanow's stopping test
+    std::vector<std::vector<zd>> Uh(H.Lb), Wh(H.Lb);
+    for (int l = 0; l < H.Lb; ++l) {
+      Uh[l].assign((size_t)N * H.rank[l], zd(0));
+      Wh[l].assign((size_t)N * H.rank[l], zd(0));
+    }
+    std::vector<std::pair<int, int>> work;  // (level, node)
+    for (int l = 0; l < H.Lb; ++l)
+      for (int nd = 0; nd < (1 << l); ++nd) work.push_back({l, nd});
+    used_rank.assign(work.size() * 2, 0);
+    parallel_for((int)work.size() * 2, [&](int wi) {
+      int l = work[wi / 2].first, nd = work[wi / 2].second, which = wi % 2;
+      long long ns = N >> l, lo = (long long)nd * ns, mid = lo + ns / 2;
+      // which = 0: A[I1, I2] ~ P Q^T ; which = 1: A[I2, I1] ~ R S^T
+      long long r0 = which ? mid : lo, c0 = which ? lo : mid;
+      int m = (int)(ns / 2), n = (int)(ns / 2);
+      std::vector<char> rz(m);
+      for (int i = 0; i < m; ++i) rz[i] = qm[r0 + i] == 0.0;
+      auto rowfn = [&](int i, zd* out) {
+        long long gi = r0 + i;
+        double cq = coef * qm[gi];
+        int ai = mort_a[gi], bi = mort_b[gi];
+        for (int j = 0; j < n; ++j) out[j] = cq * W(ai - mort_a[c0 + j], bi - mort_b[c0 + j]);
+      };
+      auto colfn = [&](int j, zd* out) {
+        long long gj = c0 + j;
+        int aj = mort_a[gj], bj = mort_b[gj];
+        for (int i = 0; i < m; ++i) out[i] = coef * qm[r0 + i] * W(mort_a[r0 + i] - aj, mort_b[r0 + i] - bj);
+      };
+      ls::ACAResult R = ls::aca(m, n, H.rank[l], P->opt.hodlr_tol, &rz, rowfn, colfn);
+      int k = (int)R.u.size();
+      used_rank[wi] = k;
+      for (int c = 0; c < k; ++c) {
+        for (int i = 0; i < m; ++i) Uh[l][(size_t)c * N + r0 + i] = R.u[c][i];
+        for (int j = 0; j < n; ++j) Wh[l][(size_t)c * N + c0 + j] = R.v[c][j];
+      }
+    });
+    for (int l = 0; l < H.Lb; ++l) {
+      H.Y64[l].upload(Uh[l]);
+      H.W64[l].upload(Wh[l]);
+      H.bytes += (int64_t)2 * N * H.rank[l] * 16;
+      Uh[l].clear();
+      Uh[l].shrink_to_fit();
+      Wh[l].clear();
+      Wh[l].shrink_to_fit();
+    }
+  }
   H.used_rank_sum = 0;
   H.used_rank_max = 0;
   for (int k : used_rank) {
@@ -933,19 +1011,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     H.used_rank_max = std::max(H.used_rank_max, k);
   }
   H.blocks = (int64_t)used_rank.size();
-  // upload U (becomes Y in place) and W; compute Y_l = D_l^{-1} U_l and the SMW cores
-  H.Y64.resize(H.Lb);
-  H.W64.resize(H.Lb);
-  H.coreinv.resize(H.Lb);
-  for (int l = 0; l < H.Lb; ++l) {
-    H.Y64[l].upload(Uh[l]);
-    H.W64[l].upload(Wh[l]);
-    H.bytes += (int64_t)2 * N * H.rank[l] * 16;
-    Uh[l].clear();
-    Uh[l].shrink_to_fit();
-    Wh[l].clear();
-    Wh[l].shrink_to_fit();
-  }
+  // Y_l = D_l^{-1} U_l (U becomes Y in place) and the SMW cores
   hipStream_t s = nullptr;
   int rmax = 0;
   for (int l = 0; l < H.Lb; ++l) rmax = std::max(rmax, H.rank[l]);

@@ -1,0 +1,30 @@
+// Batched ACA of the HODLR off-diagonal blocks on the device (see hodlr_setup.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace lsk {
+
+// One binary level: nb = 2^(l+1) blocks of S x S (block b: node b/2; b even = rows of the first
+// child against columns of the second, b odd = the transpose pair).  All arrays are device
+// arrays; U, V are the level's factors (column k of block b at k*N + its row / column offset).
+struct AcaLevel {
+  const double2* W;                // table of V entries, (2n-1)^2, offset (da, db) at (da+n-1)(2n-1)+db+n-1
+  const int *ma, *mb;              // grid coordinates of the Morton-ordered points
+  const double* q;                 // contrast, Morton order
+  double coef;                     // s kappa^2
+  int n;                           // grid side
+  long long N, S;
+  int nb;
+  double2 *U, *V;
+  unsigned char *row_used, *col_used;  // N each; rows with q = 0 start used
+  double2* rbuf;                   // N: residual pivot rows at their blocks' column ranges
+  int *ib, *jb, *state, *kcur, *retry;  // nb each
+};
+
+void launch_aca_start(const AcaLevel& L, hipStream_t s);
+// residual pivot rows and their column pivots (only_retry: blocks whose last row was zero)
+void launch_aca_row(const AcaLevel& L, bool only_retry, hipStream_t s);
+// v_k, u_k and the next pivot rows; blocks stop at kmax or when no row is left
+void launch_aca_col(const AcaLevel& L, int kmax, hipStream_t s);
+
+}  // namespace lsk
