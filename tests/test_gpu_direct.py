@@ -78,6 +78,21 @@ def test_block_of_right_hand_sides_equals_single_columns():
         assert rel(X[c].cpu().numpy(), x1.cpu().numpy()[0] if x1.dim() > 1 else x1.cpu().numpy()) < 1e-10
 
 
+def test_device_aca_matches_host_aca():
+    # the batched device ACA (fixed rank) and the host routine (a tolerance too small to stop
+    # it, so it also runs to the rank cap) choose the same pivots: the preconditioners agree
+    n, kappa = 64, 25.0
+    pb = inputs.problem_bumps(n, kappa, seed=6, count=5)
+    Pd = ls.Problem(pb.points(), pb.q, kappa, 1e-10, ls.Options(hodlr_rank=12))
+    Ph = ls.Problem(pb.points(), pb.q, kappa, 1e-10, ls.Options(hodlr_rank=12, hodlr_tol=1e-300))
+    assert Pd.stats()["hodlr_rank_used_sum"] == Ph.stats()["hodlr_rank_used_sum"]
+    b = torch.from_numpy(inputs.random_vector(n * n, seed=3)).cuda()
+    zd = Pd.precond_apply(b).cpu().numpy()
+    zh = Ph.precond_apply(b).cpu().numpy()
+    say("device vs host ACA", rel(zd, zh))
+    assert rel(zd, zh) < 1e-10
+
+
 def test_direct_solve_needs_a_factorisation():
     pb, A = gauss32()
     P = ls.Problem(pb.points(), pb.q, pb.kappa, 1e-12, ls.Options(hodlr_rank=0))
