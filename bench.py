@@ -2,9 +2,12 @@
 
 Workload (one step = the whole hot path once): the constant-contrast disc (R = 0.6, q = 1)
 on a 512 x 512 cell-centred grid of [-1, 1]^2, kappa = 80, NCA tolerance 1e-10, HODLR
-preconditioner of rank 15, plane wave at angle 0; one step is one mixed-precision
-(complex64 operator, complex128 Krylov/refinement) right-preconditioned GMRES solve from
-zero to a true relative residual of 1e-8.  `value` = solves/s over the timed steps.
+preconditioner of rank 128 (capped at child size / 4 on the deepest levels), plane wave at
+angle 0; one step is one mixed-precision (complex64 operator, complex-bfloat16 HODLR factors,
+complex128 Krylov/refinement and leaf/core solves) flexible GMRES solve from zero to a true
+relative residual of 1e-8.  `value` = solves/s over the timed steps; the setup (tree, NCA,
+HODLR factorisation) is reported separately, and the same solve with a rank-64 preconditioner
+beside it (`rank_tradeoff`: shorter setup, more iterations).
 
 Also reported (outside the timed region): the same solve in FP64, DAFMM matvec/s for the
 FP64 and FP32 operators (median of 30 applies), the error of the mixed solution against
@@ -126,7 +129,7 @@ def _read_counters(path, counter):
     return out
 
 
-def pmc_summary(fetch_csv, write_csv, cmd_fetch, cmd_write):
+def pmc_summary(fetch_csv, write_csv, cmd_fetch, cmd_write, workload):
     """Turn two rocprofv3 --pmc runs of this bench (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch)
     into HBM bytes per launch of the roofline kernels, each counter scaled by what it reads for
     the calibration copy of COPY_BYTES (the largest copyBuffer dispatch)."""
@@ -136,7 +139,7 @@ def pmc_summary(fetch_csv, write_csv, cmd_fetch, cmd_write):
         return max(vals)
     f_fetch = COPY_BYTES / 1024.0 / copy_val(fetch)
     f_write = COPY_BYTES / 1024.0 / copy_val(write)
-    res = {"source_sha256": _sha256(KERNELS_SRC), "copy_bytes": COPY_BYTES,
+    res = {"source_sha256": _sha256(KERNELS_SRC), "workload": workload, "copy_bytes": COPY_BYTES,
            "scale": {"FETCH_SIZE": f_fetch, "WRITE_SIZE": f_write}, "commands": [cmd_fetch, cmd_write], "kernels": {}}
     for cls, prefix in COUNTED.items():
         hit = lambda name: (prefix in name) if prefix.endswith("<") else (prefix + "(" in name)
@@ -162,17 +165,18 @@ def pmc_summary(fetch_csv, write_csv, cmd_fetch, cmd_write):
         for cls, v in res["kernels"].items():
             fh.write(f"| {cls} | `{v['kernel']}` | {v['dispatches']} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | "
                      f"{v['hbm_bytes_per_launch'] / 1e6:.2f} |\n")
-        fh.write(f"\nkernels.hip sha256 {res['source_sha256']} (bench.py reports traffic only for this source).\n")
+        fh.write(f"\nWorkload {workload}; kernels.hip sha256 {res['source_sha256']} (bench.py reports traffic only for "
+                 "this source and workload).\n")
     print(json.dumps(res, indent=1))
 
 
-def measured_traffic(cls):
+def measured_traffic(cls, workload):
     """HBM bytes per launch of a class from the committed counter summary, or None when absent or
-    taken on a different kernel source"""
+    taken on a different kernel source or workload"""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
-        if t["source_sha256"] != _sha256(KERNELS_SRC) or cls not in t["kernels"]:
+        if t["source_sha256"] != _sha256(KERNELS_SRC) or t.get("workload") != workload or cls not in t["kernels"]:
             return None
         return t["kernels"][cls]["hbm_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
@@ -186,7 +190,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--kappa", type=float, default=80.0)
-    ap.add_argument("--rank", type=int, default=64)
+    ap.add_argument("--rank", type=int, default=128, help="HODLR rank (levels capped at child size / rank-div)")
     ap.add_argument("--restart", type=int, default=500)
     ap.add_argument("--rank-div", type=int, default=4)
     ap.add_argument("--delta32", type=float, default=1e-4)
@@ -195,14 +199,15 @@ def main():
     ap.add_argument("--sample-every", type=int, default=7, help="time every k-th launch of a kernel class")
     ap.add_argument("--pc-bf16", type=int, default=1, help="bfloat16 HODLR factors in mixed solves (0: complex64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tradeoff-rank", type=int, default=128,
+    ap.add_argument("--tradeoff-rank", type=int, default=64,
                     help="also time the mixed solve with this HODLR rank (setup against solve time); 0: skip")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"),
                     help="summarise two rocprofv3 --pmc runs of this bench into the traffic file and exit")
     args = ap.parse_args()
+    workload = f"disc{args.n}_k{args.kappa:g}_mixed_hodlr{args.rank}"
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary)
+        pmc_summary(*args.pmc_summary, workload)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the batch axes shard without exchange; "
@@ -351,7 +356,7 @@ def main():
         bound, dt, amount = per_launch[c]
         achieved = amount / (tot_ms / timed / 1e3)
         if bound == "hbm":
-            tb = measured_traffic(c) if pc_fmt == "bf16" else None
+            tb = measured_traffic(c, workload) if pc_fmt == "bf16" else None
             return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     # measured HBM bytes per launch (counters, copy-calibrated) vs the algorithmic bytes
@@ -392,7 +397,7 @@ def main():
         "vs_baseline": None,
         "dtype": "c64 operator + bf16/c64 HODLR factors + c128 Krylov/refinement (mixed)",
         "data": "synthetic",
-        "config": {"workload": f"disc{n}_k{kappa:g}_mixed_hodlr{r}", "n": n, "N": N, "kappa": kappa,
+        "config": {"workload": workload, "n": n, "N": N, "kappa": kappa,
                    "contrast": "disc R=0.6 q=1", "eps_nca": 1e-10, "eps_inner": 1e-7, "hodlr_rank": r,
                    "tol": 1e-8, "nrhs": 1, "gmres_restart": args.restart, "hodlr_rank_div": args.rank_div,
                    "fp32_relax_delta": args.delta32, "hodlr_factors_mixed": pc_fmt,
@@ -411,8 +416,8 @@ def main():
         "error_function": err_fn,
     }
     if args.tradeoff_rank > 0:
-        # the same problem with a higher-rank preconditioner: longer setup (host-side HODLR
-        # factorisation), fewer iterations; reported beside the headline, not in it
+        # the same problem with another preconditioner rank (setup against iterations);
+        # reported beside the headline, not in it
         P.close()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
