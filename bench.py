@@ -104,6 +104,10 @@ def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok):
             cls["hodlr_dot"].append(N * ranks[l] * fsz + N * 16)
         pend = l
     cls["hodlr_update"].append(N * ranks[pend] * fsz + 2 * N * 16)
+    # SMW core products: the complex128 core inverses (2^l nodes of (2 r_l)^2), the chunk
+    # partials of W^T z read once, s written
+    cls["hodlr_core"] = [(1 << l) * (2 * ranks[l]) ** 2 * 16 + (N // chunk(l)) * ranks[l] * 16
+                         + (1 << l) * 2 * ranks[l] * 16 for l in range(levels)]
     return {c: sum(v) / len(v) / 1e9 for c, v in cls.items() if v}
 
 

@@ -283,7 +283,7 @@ ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt,
  * field + M2L launch (FP64 operator), 1 = HODLR level update, 2 = HODLR leaf solve,
  * 3 = Arnoldi dot products, 4 = near field + M2L launch (FP32 operator), 5 = HODLR level dot
  * products (W^T z), 6 = HODLR level update fused with the next level's dot products (complex
- * bfloat16 factors, one right-hand side).  every > 0 starts (and clears) the counters and times every every-th
+ * bfloat16 factors, one right-hand side), 7 = HODLR SMW core products s = K^-1 t.  every > 0 starts (and clears) the counters and times every every-th
  * launch of the class (timed dispatches run one at a time, so sparse sampling keeps the
  * timed run close to an untimed one); 0 stops.  ls_profile_read synchronises and returns the
  * summed time and number of the timed launches, and (all_launches, may be NULL) the number

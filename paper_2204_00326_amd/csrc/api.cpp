@@ -170,7 +170,7 @@ struct HodlrDev {
   DevBuf Dinv, ident;
   DevBuf Dinv32, Dinv16;  // leaf inverses in complex64 / complex bfloat16
   std::vector<DevBuf> Y64, W64, Y32, W32, Y16, W16;  // 16: complex bfloat16
-  std::vector<DevBuf> coreinv, core32, core16;      // SMW core inverses, column-major per node
+  std::vector<DevBuf> coreinv, core32, core16;      // SMW core inverses per node, 16-row blocks
   bool have16 = false;
   int64_t used_rank_sum = 0, blocks = 0;  // ACA ranks reached, over all off-diagonal blocks
   int used_rank_max = 0;
@@ -238,7 +238,7 @@ struct ls_problem {
   DevBuf w_x, w_y, w_t;  // Morton-order vectors (nrhs_cap)
   int ws_cap = 0;
   ls_stats_t stats{};
-  ProfileClass prof[7];
+  ProfileClass prof[8];
   // Krylov workspace
   DevBuf kQ, kZ, kw, kz, kr, kh, kpart, knp, kno, kalpha, ky, kx, kf, kdx;
   size_t kcap_key = 0;
@@ -813,8 +813,11 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
     // core inverses in complex128, or in the factors' precision on request
     const int cf = P->opt.pc_lowp_solves ? fmt : 0;
     const void* C = cf == 2 ? H.core16[l].p : (cf == 1 ? H.core32[l].p : H.coreinv[l].p);
-    lsk::launch_hodlr_core(cf, C, H.partial.as<double2>(), H.svec.as<double2>(), rl, nodes, H.cpc[l], H.nchunks[l],
-                           true, nrhs, s);
+    {
+      ProfScope pc(P, 7, s);
+      lsk::launch_hodlr_core(cf, C, H.partial.as<double2>(), H.svec.as<double2>(), rl, nodes, H.cpc[l], H.nchunks[l],
+                             true, nrhs, s);
+    }
     pend = l;
   }
   if (pend >= 0) update(pend, true);
@@ -1027,9 +1030,11 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     std::vector<zd> t((size_t)r * nodes * 2 * r);
     hip_check(hipMemcpy(t.data(), H.svec.p, t.size() * 16, hipMemcpyDeviceToHost), "core download");
     const int r2 = 2 * r;
-    std::vector<zd> cores((size_t)nodes * r2 * r2);
+    const long long ce = lsk::hodlr_core_elems(r);
+    std::vector<zd> cores((size_t)nodes * ce);
     parallel_for(nodes, [&](int nd) {
-      zd* C = &cores[(size_t)nd * r2 * r2];
+      std::vector<zd> Cv((size_t)r2 * r2);
+      zd* C = Cv.data();
       for (int i = 0; i < r2; ++i) C[(size_t)i * r2 + i] = 1.0;
       for (int c = 0; c < r; ++c) {
         const zd* tc = &t[((size_t)c * nodes + nd) * r2];
@@ -1039,8 +1044,10 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
         }
       }
       if (!ls::invert_inplace(C, r2)) throw LsError(LS_EINVAL, "singular HODLR core");
-      for (int i = 0; i < r2; ++i)  // to column-major for the device apply
-        for (int j = i + 1; j < r2; ++j) std::swap(C[(size_t)i * r2 + j], C[(size_t)j * r2 + i]);
+      // to the device layout: 16-row blocks, each column after column, rows past 2r zero
+      zd* D = &cores[(size_t)nd * ce];
+      for (int i = 0; i < r2; ++i)
+        for (int j = 0; j < r2; ++j) D[((size_t)(i / 16) * r2 + j) * 16 + (i % 16)] = C[(size_t)i * r2 + j];
     });
     H.coreinv[l].upload(cores);
     H.bytes += (int64_t)cores.size() * 16;
@@ -1056,7 +1063,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
   H.core32.resize(H.Lb);
   for (int l = 0; l < H.Lb; ++l) {
     const int r = H.rank[l];
-    const long long nc = (1LL << l) * 4LL * r * r;
+    const long long nc = (1LL << l) * lsk::hodlr_core_elems(r);
     H.Y32[l].alloc((size_t)N * r * 8);
     H.W32[l].alloc((size_t)N * r * 8);
     H.core32[l].alloc((size_t)nc * 8);
@@ -1074,7 +1081,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     H.core16.resize(H.Lb);
     for (int l = 0; l < H.Lb; ++l) {
       const int r = H.rank[l];
-      const long long nc = (1LL << l) * 4LL * r * r;
+      const long long nc = (1LL << l) * lsk::hodlr_core_elems(r);
       H.Y16[l].alloc((size_t)N * r * 4);
       H.W16[l].alloc((size_t)N * r * 4);
       H.core16[l].alloc((size_t)nc * 4);
@@ -2592,7 +2599,7 @@ void ls_destroy(ls_problem* P) {
 }
 
 ls_status ls_profile_enable(ls_problem* P, int cls, int every) {
-  if (!P || cls < 0 || cls > 6 || every < 0) {
+  if (!P || cls < 0 || cls > 7 || every < 0) {
     g_last_error = "bad arguments";
     return LS_EINVAL;
   }
@@ -2608,7 +2615,7 @@ ls_status ls_profile_enable(ls_problem* P, int cls, int every) {
 
 ls_status ls_profile_read(ls_problem* P, int cls, double* total_ms, int64_t* launches, int64_t* all_launches) {
   try {
-    if (!P || cls < 0 || cls > 6 || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
+    if (!P || cls < 0 || cls > 7 || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
     ProfileClass& pc = P->prof[cls];
     double tot = 0;
     for (size_t i = 0; i < pc.used; ++i) {

@@ -85,8 +85,10 @@ void launch_hodlr_upd_dot(const void* Y, int ra, const double2* sv, long long no
                           int rb, double2* z, long long N, double2* partial, long long chunk, hipStream_t s);
 void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
                       long long chunk, int nchunks, int nrhs, hipStream_t s);
-// cfmt: storage of the core inverses, 0 complex128, 1 complex64, 2 complex bfloat16 (r <= 128);
-// coreinv unused when !apply
+// cfmt: storage of the core inverses, 0 complex128, 1 complex64, 2 complex bfloat16 (r <= 128),
+// hodlr_core_elems(r) entries per node in 16-row blocks (rows 16b..16b+15 of every column,
+// column after column, rows past 2r zero); coreinv unused when !apply (s = t)
+long long hodlr_core_elems(int r);
 void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, double2* sout, int r, int nodes,
                        int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s);
 // z -= Y s per level.  z2 != NULL asks for a copy of the result in column *jdev of a basis

@@ -904,12 +904,11 @@ void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, d
 }
 
 // t = [t_A; t_B]: t_A from the chunks of the second child (rows paired with Q), t_B from
-// the first child (rows paired with S).  apply: s = coreinv * t, else s = t.  256 threads per
-// node (2r <= 256): nks = 256 / 2r threads per entry take every nks-th chunk, then a fixed-order
-// sum in LDS.
-__global__ __launch_bounds__(256) void k_hodlr_core(const double2* __restrict__ partial,
-                                                    const double2* __restrict__ coreinv, double2* __restrict__ sout,
-                                                    int r, int nodes, int cpc, int nchunks, int apply) {
+// the first child (rows paired with S), written out as it is (the setup forms the cores from
+// it; the apply form is k_hodlr_core_rows).  256 threads per node (2r <= 256): nks = 256 / 2r
+// threads per entry take every nks-th chunk, then a fixed-order sum in LDS.
+__global__ __launch_bounds__(256) void k_hodlr_core(const double2* __restrict__ partial, double2* __restrict__ sout,
+                                                    int r, int nodes, int cpc, int nchunks) {
   __shared__ double2 t[256];
   __shared__ double2 tp[256];
   const int node = blockIdx.x, rhs = blockIdx.y;
@@ -941,46 +940,50 @@ __global__ __launch_bounds__(256) void k_hodlr_core(const double2* __restrict__ 
   double2* so = sout + ((long long)rhs * nodes + node) * r2;
   const int i = threadIdx.x;
   if (i >= r2) return;
-  if (!apply) {
-    so[i] = t[i];
-    return;
-  }
-  const double2* Ci = coreinv + (long long)node * r2 * r2;  // column-major: entry (i, j) at j * r2 + i
-  double re = 0, im = 0;
-  for (int j = 0; j < r2; ++j) {
-    const double2 a = Ci[(long long)j * r2 + i];
-    const double2 x = t[j];
-    re = fma(a.x, x.x, re);
-    re = fma(-a.y, x.y, re);
-    im = fma(a.x, x.y, im);
-    im = fma(a.y, x.x, im);
-  }
-  so[i] = make_double2(re, im);
+  so[i] = t[i];
 }
 
-// Apply form split by rows: workgroup (node, slice) sums t from the partials (every slice of a
-// node recomputes the same 2r sums, in the same order) and computes 32 rows of s = coreinv t,
-// each row's dot product split over 8 column ranges and summed through LDS in a fixed order.
-template <typename TC>
-__global__ __launch_bounds__(256) void k_hodlr_core_rows(const double2* __restrict__ partial,
-                                                         const typename V2<TC>::type* __restrict__ coreinv,
-                                                         double2* __restrict__ sout, int r, int nodes, int cpc,
-                                                         int nchunks, int nrf) {
+// Apply form split by rows.  The core inverses are stored in 16-row blocks: block b of a node
+// holds rows 16b .. 16b+15 of every column, column after column (rows past 2r are zero), so a
+// block is one contiguous run of 16 * 2r entries.  Workgroup (node, block) sums t from the
+// chunk partials (every block of a node recomputes the same 2r sums, in the same order), then
+// its NT threads form 16 rows of s = K^-1 t: thread (li, jp) takes row li over the columns
+// jp, jp + NT/16, ..., so the lanes of a wave read one contiguous kilobyte per load and a
+// thread issues all its loads before using them; the NT/16 partial sums of a row are added
+// through LDS in a fixed order.  NT = 1024 for levels with many chunk partials per node.
+template <typename TC, int NT>
+__global__ __launch_bounds__(NT) void k_hodlr_core_rows(const double2* __restrict__ partial,
+                                                        const typename V2<TC>::type* __restrict__ coreinv,
+                                                        double2* __restrict__ sout, int r, int nodes, int cpc,
+                                                        int nchunks, int nrf) {
+  constexpr int CG = NT / 16;
+  constexpr int MAXU = 256 / CG;  // columns per thread at 2r = 256
+  using VT = typename V2<TC>::type;
   __shared__ double2 t[256];
-  __shared__ double2 tp[256];
-  __shared__ double2 part[8][32];
-  const int node = nrf ? blockIdx.x / nrf : blockIdx.x, slice = blockIdx.y;
+  __shared__ double2 tp[NT];
+  __shared__ double2 part[CG][16];
+  const int node = nrf ? blockIdx.x / nrf : blockIdx.x, blk = blockIdx.y;
   const int rhs = nrf ? blockIdx.x % nrf : blockIdx.z;
   const int r2 = 2 * r;
+  // the block of K^-1 does not depend on t: its loads go out first and overlap the sums of t
+  const int li = threadIdx.x & 15, jp = threadIdx.x >> 4;
+  const long long nb = (r2 + 15) / 16;
+  const VT* Cb = coreinv + ((long long)node * nb + blk) * 16 * r2;  // (16 blk + li, j) at j * 16 + li
+  VT a[MAXU];
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int j = jp + u * CG;
+    if (j < r2) a[u] = Cb[j * 16 + li];
+  }
   // t from the chunk partials: nks threads per value take every nks-th chunk, then a fixed-order sum
-  const int nks = 256 / r2;
+  const int nks = NT / r2;
   if ((int)threadIdx.x < r2 * nks) {
     const int v = threadIdx.x % r2, ks = threadIdx.x / r2;
     const int half = v < r ? 1 : 0;  // t_A sums the second child
     const int c = v < r ? v : v - r;
     const long long ch0 = (long long)node * 2 * cpc + (long long)half * cpc;
     double re = 0, im = 0;
-#pragma unroll 16
+#pragma unroll(NT == 1024 ? 16 : 4)
     for (int k = ks; k < cpc; k += nks) {
       const double2 p = partial[((long long)rhs * nchunks + ch0 + k) * r + c];
       re += p.x;
@@ -998,53 +1001,59 @@ __global__ __launch_bounds__(256) void k_hodlr_core_rows(const double2* __restri
     t[threadIdx.x] = make_double2(re, im);
   }
   __syncthreads();
-  const int li = threadIdx.x & 31, jp = threadIdx.x >> 5;
-  const int i = slice * 32 + li;
-  const int per = (r2 + 7) / 8;
-  const int j0 = jp * per, j1 = j0 + per < r2 ? j0 + per : r2;
-  const typename V2<TC>::type* Ci = coreinv + (long long)node * r2 * r2;  // column-major: (i, j) at j * r2 + i
   double re = 0, im = 0;
-  if (i < r2) {
-#pragma unroll 4
-    for (int j = j0; j < j1; ++j) {
-      const double2 a = to_d2(Ci[(long long)j * r2 + i]);
+#pragma unroll
+  for (int u = 0; u < MAXU; ++u) {
+    const int j = jp + u * CG;
+    if (j < r2) {
+      const double2 av = to_d2(a[u]);
       const double2 x = t[j];
-      re = fma(a.x, x.x, re);
-      re = fma(-a.y, x.y, re);
-      im = fma(a.x, x.y, im);
-      im = fma(a.y, x.x, im);
+      re = fma(av.x, x.x, re);
+      re = fma(-av.y, x.y, re);
+      im = fma(av.x, x.y, im);
+      im = fma(av.y, x.x, im);
     }
   }
   part[jp][li] = make_double2(re, im);
   __syncthreads();
+  const int i = blk * 16 + li;
   if (jp != 0 || i >= r2) return;
-  for (int q = 1; q < 8; ++q) {
+  for (int q = 1; q < CG; ++q) {
     re += part[q][li].x;
     im += part[q][li].y;
   }
   sout[((long long)rhs * nodes + node) * r2 + i] = make_double2(re, im);
 }
 
+long long hodlr_core_elems(int r) { return (long long)((2 * r + 15) / 16) * 16 * (2 * r); }
+
+template <typename TC>
+static void core_rows_pick(const void* coreinv, const double2* partial, double2* sout, int r, int nodes, int cpc,
+                           int nchunks, int nrhs, hipStream_t s) {
+  const int nrf = nrhs > 1 ? nrhs : 0;
+  dim3 grid(nrf ? nodes * nrhs : nodes, (2 * r + 15) / 16, nrf ? 1 : nrhs);
+  const auto* C = (const typename V2<TC>::type*)coreinv;
+  // many partials per node (the coarse levels): 1024 threads share the sums of t
+  if (cpc >= 16)
+    k_hodlr_core_rows<TC, 1024><<<grid, 1024, 0, s>>>(partial, C, sout, r, nodes, cpc, nchunks, nrf);
+  else
+    k_hodlr_core_rows<TC, 256><<<grid, 256, 0, s>>>(partial, C, sout, r, nodes, cpc, nchunks, nrf);
+}
+
 void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, double2* sout, int r, int nodes,
                        int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s) {
   if (apply && 2 * r <= 256) {
-    const int nrf = nrhs > 1 ? nrhs : 0;
-    dim3 grid(nrf ? nodes * nrhs : nodes, (2 * r + 31) / 32, nrf ? 1 : nrhs);
     if (cfmt == 2)
-      k_hodlr_core_rows<bf16><<<grid, 256, 0, s>>>(partial, (const BF2*)coreinv, sout, r, nodes, chunks_per_child,
-                                                   nchunks, nrf);
+      core_rows_pick<bf16>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s);
     else if (cfmt == 1)
-      k_hodlr_core_rows<float><<<grid, 256, 0, s>>>(partial, (const float2*)coreinv, sout, r, nodes, chunks_per_child,
-                                                    nchunks, nrf);
+      core_rows_pick<float>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s);
     else
-      k_hodlr_core_rows<double><<<grid, 256, 0, s>>>(partial, (const double2*)coreinv, sout, r, nodes,
-                                                     chunks_per_child, nchunks, nrf);
+      core_rows_pick<double>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s);
     return;
   }
   if (2 * r > 256) throw std::runtime_error("HODLR cores need rank <= 128");
   dim3 grid(nodes, nrhs);
-  k_hodlr_core<<<grid, 256, 0, s>>>(partial, (const double2*)coreinv, sout, r, nodes, chunks_per_child, nchunks,
-                                    apply ? 1 : 0);
+  k_hodlr_core<<<grid, 256, 0, s>>>(partial, sout, r, nodes, chunks_per_child, nchunks);
 }
 
 // z[i] -= sum_c Y[c*N + i] * s[node][half*r + c]

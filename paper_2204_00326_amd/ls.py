@@ -19,7 +19,7 @@ LS_OK, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_ENOTSUP = 0, -1, -2, -3, -4
 LS_FP64, LS_FP32, LS_MIXED = 0, 1, 2
 STATUS = {0: "CONVERGED", 1: "MAXIT", 2: "BREAKDOWN", 3: "NAN", 4: "REFINE_STAGNATED", 5: "WARMSTART_REJECTED"}
 PROFILE_CLASSES = {"near_m2l64": 0, "hodlr_update": 1, "leaf_solve": 2, "gs_dot": 3, "near_m2l32": 4,
-                   "hodlr_dot": 5, "hodlr_upd_dot": 6}
+                   "hodlr_dot": 5, "hodlr_upd_dot": 6, "hodlr_core": 7}
 
 
 class LsError(RuntimeError):
