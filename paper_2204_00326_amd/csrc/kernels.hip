@@ -1034,10 +1034,13 @@ static void core_rows_pick(const void* coreinv, const double2* partial, double2*
   dim3 grid(nrf ? nodes * nrhs : nodes, (2 * r + 15) / 16, nrf ? 1 : nrhs);
   const auto* C = (const typename V2<TC>::type*)coreinv;
   // many partials per node (the coarse levels): 1024 threads share the sums of t
-  if (cpc >= 16)
-    k_hodlr_core_rows<TC, 1024><<<grid, 1024, 0, s>>>(partial, C, sout, r, nodes, cpc, nchunks, nrf);
-  else
-    k_hodlr_core_rows<TC, 256><<<grid, 256, 0, s>>>(partial, C, sout, r, nodes, cpc, nchunks, nrf);
+  if (cpc >= 16) {
+    auto kern = k_hodlr_core_rows<TC, 1024>;
+    LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf);
+  } else {
+    auto kern = k_hodlr_core_rows<TC, 256>;
+    LSK_LAUNCH(kern, grid, 256, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf);
+  }
 }
 
 void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, double2* sout, int r, int nodes,
@@ -1095,6 +1098,53 @@ __global__ __launch_bounds__(256) void k_hodlr_update(const typename V2<T>::type
   o.x -= re;
   o.y -= im;
   z[rhs * ldz + i] = o;
+}
+
+// Many right-hand sides with complex128 factors (the r-column applies that form the factors):
+// a thread owns one row and RB right-hand sides, so each factor entry is read once per RB
+// right-hand sides instead of once per right-hand side.  A wave's 64 rows lie in one node half
+// (halves hold at least 64 rows), so the s entries a wave reads are the same for all its lanes.
+// Per (row, right-hand side) the sums run over c in the order of k_hodlr_update: same results.
+template <int RB>
+__global__ __launch_bounds__(256) void k_hodlr_update_rb(const double2* __restrict__ Y, const double2* __restrict__ sv,
+                                                         double2* __restrict__ z, long long ldz, long long N, int r,
+                                                         long long nodesize, int nodes, int nrhs) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int rhs0 = blockIdx.y * RB;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const long long i0 = (long long)blockIdx.x * 256 + wv * 64;
+  if (i0 >= N) return;
+  const long long node = i0 / nodesize;
+  const int half = (i0 - node * nodesize) >= (nodesize >> 1) ? 1 : 0;
+  const long long sstride = (long long)nodes * 2 * r;
+  const double2* s = sv + node * 2 * r + half * r + (long long)rhs0 * sstride;
+  const int nb = nrhs - rhs0 < RB ? nrhs - rhs0 : RB;
+  const long long ic = i < N ? i : N - 1;
+  double re[RB], im[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) re[b] = im[b] = 0;
+#pragma unroll 4
+  for (int c = 0; c < r; ++c) {
+    const double2 y = Y[(long long)c * N + ic];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const double2 x = b < nb ? s[b * sstride + c] : make_double2(0.0, 0.0);
+      re[b] = fma(y.x, x.x, re[b]);
+      re[b] = fma(-y.y, x.y, re[b]);
+      im[b] = fma(y.x, x.y, im[b]);
+      im[b] = fma(y.y, x.x, im[b]);
+    }
+  }
+  if (i >= N) return;
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    if (b >= nb) break;
+    double2* zp = z + (long long)(rhs0 + b) * ldz + i;
+    double2 o = *zp;
+    o.x -= re[b];
+    o.y -= im[b];
+    *zp = o;
+  }
 }
 
 // 16-byte-pack form: a thread owns R consecutive rows (one node half, as halves are multiples
@@ -1309,6 +1359,11 @@ bool launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, 
   } else if (fmt == 1) {
     auto kern = k_hodlr_update<float>;
     LSK_LAUNCH(kern, grid, 256, 0, s, (const float2*)Y, sv, z, ldz, N, r, nodesize, nodes);
+  } else if (nrhs >= 16 && nodesize % 128 == 0) {
+    constexpr int RB = 16;
+    dim3 gridb((unsigned)((N + 255) / 256), (unsigned)((nrhs + RB - 1) / RB));
+    auto kern = k_hodlr_update_rb<RB>;
+    LSK_LAUNCH(kern, gridb, 256, 0, s, (const double2*)Y, sv, z, ldz, N, r, nodesize, nodes, nrhs);
   } else {
     auto kern = k_hodlr_update<double>;
     LSK_LAUNCH(kern, grid, 256, 0, s, (const double2*)Y, sv, z, ldz, N, r, nodesize, nodes);
