@@ -415,6 +415,8 @@ def main():
         "mixed_vs_fp64_rel_diff": err_mixed,
         "matvec_per_s": {k: round(v, 1) for k, v in rates.items()},
         "setup_s": round(t_setup, 3),
+        "setup_ms": {k: round(st[f"t_{k}_ms"], 1) for k in ("plan", "nca", "hodlr", "hodlr_aca", "hodlr_apply",
+                                                             "hodlr_cores")},
         "ranks": {"fp64": st["rank_max64"], "fp32": st["rank_max32"]},
         "roofline": roof,
         "error_function": err_fn,

@@ -143,6 +143,9 @@ typedef struct {
   int64_t hodlr_rank_used_sum;  /* sum of the ranks the ACA reached over the off-diagonal blocks */
   int64_t hodlr_blocks;         /* number of off-diagonal blocks */
   int hodlr_rank_used_max;      /* largest of them */
+  /* parts of t_hodlr_ms: off-diagonal ACA; the applies of the finer levels that form
+   * Y = D^-1 U (device); forming, inverting (host) and uploading the SMW cores */
+  double t_hodlr_aca_ms, t_hodlr_apply_ms, t_hodlr_cores_ms;
 } ls_stats_t;
 
 /* Plan description for a uniform n x n grid on [-L, L]^2 (host only, no device use).

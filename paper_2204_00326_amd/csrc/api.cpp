@@ -174,6 +174,7 @@ struct HodlrDev {
   bool have16 = false;
   int64_t used_rank_sum = 0, blocks = 0;  // ACA ranks reached, over all off-diagonal blocks
   int used_rank_max = 0;
+  double t_aca_ms = 0, t_apply_ms = 0, t_cores_ms = 0;  // setup phases
   DevBuf partial, svec;
   std::vector<long long> chunk;  // per level
   std::vector<int> nchunks, cpc;
@@ -896,9 +897,10 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
   H.W64.resize(H.Lb);
   H.coreinv.resize(H.Lb);
   std::vector<int> used_rank;  // ranks the ACA reached, per block
+  const double t_aca0 = now_ms();
   if (P->opt.hodlr_tol <= 0.0) {
     // fixed rank: batched ACA on the device, the factors written in place
-    DevBuf wdev, mad, mbd, rowu, colu, rbuf, ib, jb, state, kcur, retry;
+    DevBuf wdev, mad, mbd, rowu, colu, rbuf, pmax, ib, jb, state, kcur, retry;
     wdev.upload(W.w);
     mad.upload(mort_a);
     mbd.upload(mort_b);
@@ -907,6 +909,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     rowu.alloc((size_t)N);
     colu.alloc((size_t)N);
     rbuf.alloc((size_t)N * 16);
+    pmax.alloc((size_t)(N / 256 + (1LL << H.Lb) + 1) * 8);  // >= nb * ceil(S / 256) on every level
     const int nbmax = 1 << H.Lb;
     for (DevBuf* d : {&ib, &jb, &state, &kcur, &retry}) d->alloc((size_t)nbmax * 4);
     std::vector<int> hbuf(nbmax);
@@ -934,6 +937,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
       L.row_used = rowu.as<unsigned char>();
       L.col_used = colu.as<unsigned char>();
       L.rbuf = rbuf.as<double2>();
+      L.pmax = pmax.as<double>();
       L.ib = ib.as<int>();
       L.jb = jb.as<int>();
       L.state = state.as<int>();
@@ -1007,6 +1011,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
       Wh[l].shrink_to_fit();
     }
   }
+  H.t_aca_ms = now_ms() - t_aca0;
   H.used_rank_sum = 0;
   H.used_rank_max = 0;
   for (int k : used_rank) {
@@ -1022,6 +1027,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
   for (int l = H.Lb - 1; l >= 0; --l) {
     const int r = H.rank[l];
     double2* Y = H.Y64[l].as<double2>();
+    const double ta = now_ms();
     hodlr_apply(P, 0, Y, N, Y, N, r, l + 1, s);
     int nodes = 1 << l;
     lsk::launch_hodlr_dot(0, H.W64[l].p, Y, N, H.partial.as<double2>(), N, r, H.chunk[l], H.nchunks[l], r, s);
@@ -1029,6 +1035,8 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
                            H.nchunks[l], false, r, s);
     std::vector<zd> t((size_t)r * nodes * 2 * r);
     hip_check(hipMemcpy(t.data(), H.svec.p, t.size() * 16, hipMemcpyDeviceToHost), "core download");
+    const double tc = now_ms();
+    H.t_apply_ms += tc - ta;
     const int r2 = 2 * r;
     const long long ce = lsk::hodlr_core_elems(r);
     std::vector<zd> cores((size_t)nodes * ce);
@@ -1051,6 +1059,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     });
     H.coreinv[l].upload(cores);
     H.bytes += (int64_t)cores.size() * 16;
+    H.t_cores_ms += now_ms() - tc;
   }
   hip_check(hipDeviceSynchronize(), "hodlr setup");
   // FP32 copies of the leaf inverses, the off-diagonal factors and the core inverses
@@ -2032,6 +2041,9 @@ ls_status ls_setup(const double* points, int64_t N, const double* q, double kapp
     S.hodlr_rank_used_sum = P->have_hodlr ? P->hod.used_rank_sum : 0;
     S.hodlr_blocks = P->have_hodlr ? P->hod.blocks : 0;
     S.hodlr_rank_used_max = P->have_hodlr ? P->hod.used_rank_max : 0;
+    S.t_hodlr_aca_ms = P->hod.t_aca_ms;
+    S.t_hodlr_apply_ms = P->hod.t_apply_ms;
+    S.t_hodlr_cores_ms = P->hod.t_cores_ms;
     S.t_plan_ms = t_plan - t0;
     S.t_nca_ms = t_nca - t_w;
     S.t_hodlr_ms = t_h - t_nca;

@@ -18,6 +18,8 @@ struct AcaLevel {
   double2 *U, *V;
   unsigned char *row_used, *col_used;  // N each; rows with q = 0 start used
   double2* rbuf;                   // N: residual pivot rows at their blocks' column ranges
+  double* pmax;                    // nb * ceil(S / 256): per 256-entry tile, the largest magnitude
+                                   // over its unused entries (-1 when it has none)
   int *ib, *jb, *state, *kcur, *retry;  // nb each
 };
 
