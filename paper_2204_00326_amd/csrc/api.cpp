@@ -1019,11 +1019,20 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     H.used_rank_max = std::max(H.used_rank_max, k);
   }
   H.blocks = (int64_t)used_rank.size();
-  // Y_l = D_l^{-1} U_l (U becomes Y in place) and the SMW cores
+  // Y_l = D_l^{-1} U_l (U becomes Y in place) and the SMW cores, inverted on the device
   hipStream_t s = nullptr;
   int rmax = 0;
-  for (int l = 0; l < H.Lb; ++l) rmax = std::max(rmax, H.rank[l]);
+  size_t kmax_elems = 1;
+  for (int l = 0; l < H.Lb; ++l) {
+    rmax = std::max(rmax, H.rank[l]);
+    kmax_elems = std::max(kmax_elems, (size_t)(1LL << l) * 4 * H.rank[l] * H.rank[l]);
+  }
   hodlr_ensure_ws(P, std::max(rmax, 1));
+  DevBuf kA, kB, kbad;
+  kA.alloc(kmax_elems * 16);
+  kB.alloc(kmax_elems * 16);
+  kbad.alloc((size_t)(1LL << H.Lb) * 4);
+  std::vector<int> bad((size_t)1 << H.Lb);
   for (int l = H.Lb - 1; l >= 0; --l) {
     const int r = H.rank[l];
     double2* Y = H.Y64[l].as<double2>();
@@ -1033,32 +1042,20 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     lsk::launch_hodlr_dot(0, H.W64[l].p, Y, N, H.partial.as<double2>(), N, r, H.chunk[l], H.nchunks[l], r, s);
     lsk::launch_hodlr_core(0, nullptr, H.partial.as<double2>(), H.svec.as<double2>(), r, nodes, H.cpc[l],
                            H.nchunks[l], false, r, s);
-    std::vector<zd> t((size_t)r * nodes * 2 * r);
-    hip_check(hipMemcpy(t.data(), H.svec.p, t.size() * 16, hipMemcpyDeviceToHost), "core download");
+    hip_check(hipStreamSynchronize(s), "hodlr factors");
     const double tc = now_ms();
     H.t_apply_ms += tc - ta;
-    const int r2 = 2 * r;
     const long long ce = lsk::hodlr_core_elems(r);
-    std::vector<zd> cores((size_t)nodes * ce);
-    parallel_for(nodes, [&](int nd) {
-      std::vector<zd> Cv((size_t)r2 * r2);
-      zd* C = Cv.data();
-      for (int i = 0; i < r2; ++i) C[(size_t)i * r2 + i] = 1.0;
-      for (int c = 0; c < r; ++c) {
-        const zd* tc = &t[((size_t)c * nodes + nd) * r2];
-        for (int i = 0; i < r; ++i) {
-          C[(size_t)i * r2 + (r + c)] += tc[i];       // Q^T Y2
-          C[(size_t)(r + i) * r2 + c] += tc[r + i];   // S^T Y1
-        }
-      }
-      if (!ls::invert_inplace(C, r2)) throw LsError(LS_EINVAL, "singular HODLR core");
-      // to the device layout: 16-row blocks, each column after column, rows past 2r zero
-      zd* D = &cores[(size_t)nd * ce];
-      for (int i = 0; i < r2; ++i)
-        for (int j = 0; j < r2; ++j) D[((size_t)(i / 16) * r2 + j) * 16 + (i % 16)] = C[(size_t)i * r2 + j];
-    });
-    H.coreinv[l].upload(cores);
-    H.bytes += (int64_t)cores.size() * 16;
+    H.coreinv[l].alloc((size_t)nodes * ce * 16);
+    hip_check(hipMemsetAsync(kbad.p, 0, (size_t)nodes * 4, s), "memset");
+    lsk::launch_core_invert(H.svec.as<double2>(), r, nodes, kA.as<double2>(), kB.as<double2>(),
+                            H.coreinv[l].as<double2>(), kbad.as<int>(), s);
+    hip_check(hipGetLastError(), "core inversion");
+    hip_check(hipMemcpyAsync(bad.data(), kbad.p, (size_t)nodes * 4, hipMemcpyDeviceToHost, s), "core status");
+    hip_check(hipStreamSynchronize(s), "core inversion");
+    for (int nd = 0; nd < nodes; ++nd)
+      if (bad[nd]) throw LsError(LS_EINVAL, "singular HODLR core");
+    H.bytes += (int64_t)nodes * ce * 16;
     H.t_cores_ms += now_ms() - tc;
   }
   hip_check(hipDeviceSynchronize(), "hodlr setup");

@@ -28,5 +28,10 @@ void launch_aca_start(const AcaLevel& L, hipStream_t s);
 void launch_aca_row(const AcaLevel& L, bool only_retry, hipStream_t s);
 // v_k, u_k and the next pivot rows; blocks stop at kmax or when no row is left
 void launch_aca_col(const AcaLevel& L, int kmax, hipStream_t s);
+// SMW core inverses of one level (2r <= 256) from t (svec layout: [c][node][2r], the r-column
+// W^T Y products) into out (hodlr_core_elems(r) entries per node, 16-row blocks); A, B: nodes x
+// (2r)^2 workspaces; bad[node] set to 1 where a pivot is exactly zero
+void launch_core_invert(const double2* t, int r, int nodes, double2* A, double2* B, double2* out, int* bad,
+                        hipStream_t s);
 
 }  // namespace lsk

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <stdexcept>
 
 #include "hodlr_setup.h"
 
@@ -235,6 +236,137 @@ __global__ __launch_bounds__(256) void k_aca_rowpivot(AcaLevel L, int kmax) {
   } else {
     L.ib[b] = (int)first;
   }
+}
+
+// SMW cores of one level, one workgroup per node: K = I + [0, X; Z, 0] with X[i][c] = t[c][node][i]
+// and Z[i][c] = t[c][node][r + i] (the r-column products W^T Y), inverted by Gauss-Jordan with
+// partial pivoting in the host routine's steps (pivot: largest magnitude in the column at or
+// below the diagonal, the lowest row among equals; scale the pivot row; subtract multiples of
+// it from every other row; columns left of the pivot are already unit columns and are skipped),
+// then written in the 16-row-block layout of the apply.  A, B: per-node n x n workspaces
+// (row-major); bad[node] = 1 for an exactly zero pivot.
+__global__ __launch_bounds__(1024) void k_core_invert(const double2* __restrict__ t, int r, int nodes,
+                                                      double2* __restrict__ Aw, double2* __restrict__ Bw,
+                                                      double2* __restrict__ out, int* __restrict__ bad) {
+  constexpr int NT = 1024;
+  __shared__ double rv[256];
+  __shared__ int rix[256];
+  __shared__ double2 f[256], arow[256], brow[256];
+  __shared__ int pivr;
+  __shared__ double2 pinv;
+  const int node = blockIdx.x, tid = threadIdx.x;
+  const int n = 2 * r;
+  double2* A = Aw + (long long)node * n * n;
+  double2* B = Bw + (long long)node * n * n;
+  for (int idx = tid; idx < n * n; idx += NT) {
+    const int i = idx / n, j = idx - i * n;
+    double2 a = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    if (i < r && j >= r) {
+      const double2 x = t[((long long)(j - r) * nodes + node) * n + i];
+      a.x += x.x;
+      a.y += x.y;
+    } else if (i >= r && j < r) {
+      const double2 x = t[((long long)j * nodes + node) * n + i];
+      a.x += x.x;
+      a.y += x.y;
+    }
+    A[idx] = a;
+    B[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  const int tr = tid >> 6, tj = tid & 63;  // 16 row groups x 64 columns
+  for (int col = 0; col < n; ++col) {
+    // pivot row
+    if (tid < 256) {
+      rv[tid] = (tid >= col && tid < n) ? cabs_(A[(long long)tid * n + col]) : -1.0;
+      rix[tid] = tid;
+    }
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) {
+        const double v2 = rv[tid + st];
+        const int i2 = rix[tid + st];
+        if (v2 > rv[tid] || (v2 == rv[tid] && i2 < rix[tid])) {
+          rv[tid] = v2;
+          rix[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    if (rv[0] <= 0.0) {  // the same value for every thread: all leave together
+      if (tid == 0) bad[node] = 1;
+      return;
+    }
+    if (tid == 0) pivr = rix[0];
+    __syncthreads();
+    const int pr = pivr;
+    // swap rows pr and col (A: columns >= col; B: all), keep the pivot row in LDS
+    for (int j = tid; j < n; j += NT) {
+      if (pr != col) {
+        if (j >= col) {
+          const double2 a1 = A[(long long)pr * n + j], a2 = A[(long long)col * n + j];
+          A[(long long)pr * n + j] = a2;
+          A[(long long)col * n + j] = a1;
+        }
+        const double2 b1 = B[(long long)pr * n + j], b2 = B[(long long)col * n + j];
+        B[(long long)pr * n + j] = b2;
+        B[(long long)col * n + j] = b1;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) pinv = cdiv(make_double2(1.0, 0.0), A[(long long)col * n + col]);
+    // multipliers of every other row (before the pivot row changes)
+    for (int i = tid; i < n; i += NT) f[i] = A[(long long)i * n + col];
+    __syncthreads();
+    const double2 iv = pinv;
+    for (int j = tid; j < n; j += NT) {
+      double2 b = B[(long long)col * n + j];
+      b = make_double2(b.x * iv.x - b.y * iv.y, b.x * iv.y + b.y * iv.x);
+      B[(long long)col * n + j] = b;
+      brow[j] = b;
+      if (j >= col) {
+        double2 a = A[(long long)col * n + j];
+        a = make_double2(a.x * iv.x - a.y * iv.y, a.x * iv.y + a.y * iv.x);
+        A[(long long)col * n + j] = a;
+        arow[j] = a;
+      }
+    }
+    __syncthreads();
+    for (int i = tr; i < n; i += NT / 64) {
+      if (i == col) continue;
+      const double2 fi = f[i];
+      if (fi.x == 0.0 && fi.y == 0.0) continue;
+      for (int j = col + tj; j < n; j += 64) {
+        const double2 p = arow[j];
+        double2 a = A[(long long)i * n + j];
+        a.x -= fi.x * p.x - fi.y * p.y;
+        a.y -= fi.x * p.y + fi.y * p.x;
+        A[(long long)i * n + j] = a;
+      }
+      for (int j = tj; j < n; j += 64) {
+        const double2 p = brow[j];
+        double2 b = B[(long long)i * n + j];
+        b.x -= fi.x * p.x - fi.y * p.y;
+        b.y -= fi.x * p.y + fi.y * p.x;
+        B[(long long)i * n + j] = b;
+      }
+    }
+    __syncthreads();
+  }
+  // K^-1 = B to the apply layout: 16-row blocks, each column after column, rows past n zero
+  const int nb = (n + 15) / 16;
+  double2* D = out + (long long)node * nb * 16 * n;
+  for (int idx = tid; idx < nb * 16 * n; idx += NT) {
+    const int blk = idx / (16 * n), rem = idx - blk * 16 * n;
+    const int j = rem >> 4, i = blk * 16 + (rem & 15);
+    D[idx] = i < n ? B[(long long)i * n + j] : make_double2(0.0, 0.0);
+  }
+}
+
+void launch_core_invert(const double2* t, int r, int nodes, double2* A, double2* B, double2* out, int* bad,
+                        hipStream_t s) {
+  if (2 * r > 256) throw std::runtime_error("HODLR cores need rank <= 128");
+  k_core_invert<<<nodes, 1024, 0, s>>>(t, r, nodes, A, B, out, bad);
 }
 
 void launch_aca_start(const AcaLevel& L, hipStream_t s) { k_aca_start<<<L.nb, 256, 0, s>>>(L); }
