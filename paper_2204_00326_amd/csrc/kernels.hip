@@ -860,6 +860,71 @@ __global__ __launch_bounds__(256) void k_hodlr_dot_seg(const typename V2<T>::typ
   partial[((long long)rhs * nchunks + ch) * r + c0 + sl] = make_double2(re, im);
 }
 
+// Many right-hand sides with complex128 factors: a segment owns one chunk, G columns and RB
+// right-hand sides, so each factor entry is read once per RB right-hand sides and each z entry
+// once per G columns.  Per (column, right-hand side) the lane and row order and the butterfly
+// are those of k_hodlr_dot_seg<double, 1, G>: the same sums, bit for bit.
+template <int G, int RB>
+__global__ __launch_bounds__(256) void k_hodlr_dot_rb(const double2* __restrict__ W, long long N, int r,
+                                                      const double2* __restrict__ z, long long ldz,
+                                                      double2* __restrict__ partial, long long chunk, int nchunks,
+                                                      int lc, int nrhs, int ngrp) {
+  const int grp = blockIdx.x % ngrp, rb0 = (blockIdx.x / ngrp) * RB;
+  const long long bx = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int spw = 64 / lc;
+  const int seg = lane / lc, sl = lane - seg * lc;
+  const long long ch = (bx * 4 + wave) * spw + seg;
+  const bool valid = ch < nchunks;
+  const int c0 = grp * G;
+  const int nb = nrhs - rb0 < RB ? nrhs - rb0 : RB;
+  double acc[G][RB][2];
+#pragma unroll
+  for (int c = 0; c < G; ++c)
+#pragma unroll
+    for (int b = 0; b < RB; ++b) acc[c][b][0] = acc[c][b][1] = 0;
+  if (valid) {
+    long long coff[G], zoff[RB];
+#pragma unroll
+    for (int c = 0; c < G; ++c) coff[c] = (long long)(c0 + c < r ? c0 + c : r - 1) * N;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) zoff[b] = (long long)(rb0 + (b < nb ? b : nb - 1)) * ldz;
+    const long long i0 = ch * chunk, i1 = i0 + chunk;
+    for (long long i = i0 + sl; i < i1; i += lc) {
+      double2 a[G], x[RB];
+#pragma unroll
+      for (int c = 0; c < G; ++c) a[c] = W[coff[c] + i];
+#pragma unroll
+      for (int b = 0; b < RB; ++b) x[b] = z[zoff[b] + i];
+#pragma unroll
+      for (int c = 0; c < G; ++c)
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          acc[c][b][0] = fma(a[c].x, x[b].x, acc[c][b][0]);
+          acc[c][b][0] = fma(-a[c].y, x[b].y, acc[c][b][0]);
+          acc[c][b][1] = fma(a[c].x, x[b].y, acc[c][b][1]);
+          acc[c][b][1] = fma(a[c].y, x[b].x, acc[c][b][1]);
+        }
+    }
+  }
+  for (int off = lc >> 1; off > 0; off >>= 1)
+#pragma unroll
+    for (int c = 0; c < G; ++c)
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        acc[c][b][0] += __shfl_xor(acc[c][b][0], off, 64);
+        acc[c][b][1] += __shfl_xor(acc[c][b][1], off, 64);
+      }
+  if (!valid) return;
+  // output k = c * RB + b goes out from lane k mod lc of the segment
+#pragma unroll
+  for (int c = 0; c < G; ++c)
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+      if ((c * RB + b) % lc == sl && c0 + c < r && b < nb)
+        partial[((long long)(rb0 + b) * nchunks + ch) * r + c0 + c] = make_double2(acc[c][b][0], acc[c][b][1]);
+}
+
 constexpr int kDotCols = 4;  // columns per segment (4 measured fastest of 4 / 8 / 16)
 template <typename T, int R>
 static void hodlr_dot_seg(const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
@@ -883,6 +948,17 @@ template <typename T>
 static void hodlr_dot_fmt(const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
                           long long chunk, int nchunks, int nrhs, hipStream_t s) {
   constexpr int RW = 16 / (int)sizeof(typename V2<T>::type);
+  if (RW == 1 && nrhs >= 8) {  // complex128 factors, many right-hand sides
+    constexpr int G = kDotCols, RB = 8;
+    int lc = 64;
+    while (lc > chunk) lc >>= 1;
+    const int per_wg = 4 * (64 / lc);
+    const int ngrp = (r + G - 1) / G;
+    dim3 grid((unsigned)(ngrp * ((nrhs + RB - 1) / RB)), (unsigned)((nchunks + per_wg - 1) / per_wg));
+    auto kern = k_hodlr_dot_rb<G, RB>;
+    LSK_LAUNCH(kern, grid, 256, 0, s, (const double2*)W, N, r, z, ldz, partial, chunk, nchunks, lc, nrhs, ngrp);
+    return;
+  }
   if (RW > 1 && chunk % RW == 0 && N % RW == 0 && chunk / RW >= 16)
     hodlr_dot_seg<T, RW>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s);
   else
