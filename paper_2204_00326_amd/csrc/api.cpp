@@ -855,38 +855,48 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
   H.Lb = 2 * p.leaf;
   H.N = N;
   const double coef = P->coef;
-  // leaf inverses (column-major per leaf)
+  // leaf inverses (column-major per leaf), on the device: dense leaves by Gauss-Jordan, leaves
+  // without contrast the identity
   const int lp = H.lp;
-  std::vector<zd> Vleaf((size_t)lp * lp);
-  for (int m = 0; m < lp; ++m)
-    for (int k = 0; k < lp; ++k) Vleaf[(size_t)m * lp + k] = W(mort_a[m] - mort_a[k], mort_b[m] - mort_b[k]);
-  std::vector<zd> Dinv((size_t)H.nleaves * lp * lp);
-  std::vector<unsigned char> ident(H.nleaves, 0);
-  parallel_for(H.nleaves, [&](int leafi) {
-    long long base = (long long)leafi * lp;
-    bool allzero = true;
-    for (int m = 0; m < lp; ++m)
-      if (qm[base + m] != 0.0) allzero = false;
-    zd* out = &Dinv[(size_t)leafi * lp * lp];
-    if (allzero) {
-      ident[leafi] = 1;
-      for (int k = 0; k < lp; ++k) out[(size_t)k * lp + k] = 1.0;
-      return;
+  DevBuf wdev, mad, mbd;
+  wdev.upload(W.w);
+  mad.upload(mort_a);
+  mbd.upload(mort_b);
+  {
+    std::vector<int> dense, idl;
+    for (int leafi = 0; leafi < H.nleaves; ++leafi) {
+      bool allzero = true;
+      for (int m = 0; m < lp; ++m)
+        if (qm[(size_t)leafi * lp + m] != 0.0) allzero = false;
+      (allzero ? idl : dense).push_back(leafi);
     }
-    std::vector<zd> A((size_t)lp * lp);
-    for (int m = 0; m < lp; ++m)
-      for (int k = 0; k < lp; ++k)
-        A[(size_t)m * lp + k] = (m == k ? zd(1.0) : zd(0.0)) + coef * qm[base + m] * Vleaf[(size_t)m * lp + k];
-    if (!ls::invert_inplace(A.data(), lp)) throw LsError(LS_EINVAL, "singular HODLR leaf block");
-    for (int m = 0; m < lp; ++m)
-      for (int k = 0; k < lp; ++k) out[(size_t)k * lp + m] = A[(size_t)m * lp + k];
-  });
-  H.Dinv.upload(Dinv);
-  H.ident.upload(ident);
-  for (unsigned char v : ident) H.dense_leaves += v ? 0 : 1;
-  H.bytes = (int64_t)Dinv.size() * 16;
-  Dinv.clear();
-  Dinv.shrink_to_fit();
+    std::vector<unsigned char> ident(H.nleaves, 0);
+    for (int leafi : idl) ident[leafi] = 1;
+    H.Dinv.alloc((size_t)H.nleaves * lp * lp * 16);
+    DevBuf dl, il, lA, lB, lbad;
+    dl.upload(dense);
+    il.upload(idl);
+    lsk::launch_leaf_identity(il.as<int>(), (int)idl.size(), lp, H.Dinv.as<double2>(), nullptr);
+    const int batch = (int)std::min<size_t>(std::max<size_t>(dense.size(), 1), 1024);
+    lA.alloc((size_t)batch * lp * lp * 16);
+    lB.alloc((size_t)batch * lp * lp * 16);
+    lbad.alloc((size_t)batch * 4);
+    std::vector<int> bad(batch);
+    for (size_t k0 = 0; k0 < dense.size(); k0 += batch) {
+      const int nk = (int)std::min<size_t>(batch, dense.size() - k0);
+      hip_check(hipMemsetAsync(lbad.p, 0, (size_t)nk * 4, nullptr), "memset");
+      lsk::launch_leaf_invert(wdev.as<double2>(), P->n, mad.as<int>(), mbd.as<int>(), P->q_m.as<double>(), coef, lp,
+                              dl.as<int>() + k0, nk, lA.as<double2>(), lB.as<double2>(), H.Dinv.as<double2>(),
+                              lbad.as<int>(), nullptr);
+      hip_check(hipGetLastError(), "leaf inversion");
+      hip_check(hipMemcpy(bad.data(), lbad.p, (size_t)nk * 4, hipMemcpyDeviceToHost), "leaf status");
+      for (int k = 0; k < nk; ++k)
+        if (bad[k]) throw LsError(LS_EINVAL, "singular HODLR leaf block");
+    }
+    H.ident.upload(ident);
+    H.dense_leaves = (int64_t)dense.size();
+    H.bytes = (int64_t)H.nleaves * lp * lp * 16;
+  }
   hodlr_chunks(H, P->tune.hodlr_rows);
   // off-diagonal ACA at fixed rank (rows with q = 0 are known zero)
   H.rank.assign(H.Lb, r);
@@ -900,10 +910,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
   const double t_aca0 = now_ms();
   if (P->opt.hodlr_tol <= 0.0) {
     // fixed rank: batched ACA on the device, the factors written in place
-    DevBuf wdev, mad, mbd, rowu, colu, rbuf, pmax, ib, jb, state, kcur, retry;
-    wdev.upload(W.w);
-    mad.upload(mort_a);
-    mbd.upload(mort_b);
+    DevBuf rowu, colu, rbuf, pmax, ib, jb, state, kcur, retry;
     std::vector<unsigned char> rz((size_t)N);
     for (long long i = 0; i < N; ++i) rz[i] = qm[i] == 0.0 ? 1 : 0;
     rowu.alloc((size_t)N);

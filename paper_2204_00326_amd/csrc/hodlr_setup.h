@@ -33,5 +33,13 @@ void launch_aca_col(const AcaLevel& L, int kmax, hipStream_t s);
 // (2r)^2 workspaces; bad[node] set to 1 where a pivot is exactly zero
 void launch_core_invert(const double2* t, int r, int nodes, double2* A, double2* B, double2* out, int* bad,
                         hipStream_t s);
+// inverses of the listed dense leaves (diagonal blocks I + coef diag(q) V of lp <= 256 points,
+// V from the table W of an n_grid x n_grid grid) into Dinv (column-major lp x lp at each leaf's
+// index); A, B: nleaves x lp^2 workspaces; bad[k] set to 1 where a pivot is exactly zero
+void launch_leaf_invert(const double2* W, int n_grid, const int* ma, const int* mb, const double* q, double coef,
+                        int lp, const int* leaves, int nleaves, double2* A, double2* B, double2* Dinv, int* bad,
+                        hipStream_t s);
+// identity blocks at the listed leaves of Dinv
+void launch_leaf_identity(const int* leaves, int nleaves, int lp, double2* Dinv, hipStream_t s);
 
 }  // namespace lsk

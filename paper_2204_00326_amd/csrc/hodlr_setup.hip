@@ -238,45 +238,22 @@ __global__ __launch_bounds__(256) void k_aca_rowpivot(AcaLevel L, int kmax) {
   }
 }
 
-// SMW cores of one level, one workgroup per node: K = I + [0, X; Z, 0] with X[i][c] = t[c][node][i]
-// and Z[i][c] = t[c][node][r + i] (the r-column products W^T Y), inverted by Gauss-Jordan with
-// partial pivoting in the host routine's steps (pivot: largest magnitude in the column at or
-// below the diagonal, the lowest row among equals; scale the pivot row; subtract multiples of
-// it from every other row; columns left of the pivot are already unit columns and are skipped),
-// then written in the 16-row-block layout of the apply.  A, B: per-node n x n workspaces
-// (row-major); bad[node] = 1 for an exactly zero pivot.
-__global__ __launch_bounds__(1024) void k_core_invert(const double2* __restrict__ t, int r, int nodes,
-                                                      double2* __restrict__ Aw, double2* __restrict__ Bw,
-                                                      double2* __restrict__ out, int* __restrict__ bad) {
+// Gauss-Jordan inversion of the n x n matrix A (row-major, n <= 256) by one workgroup of 1024
+// threads, B = A^-1 on return (B must hold the identity on entry), in the host routine's steps:
+// pivot = largest magnitude in the column at or below the diagonal, the lowest row among
+// equals; scale the pivot row; subtract multiples of it from every other row.  Columns left of
+// the pivot are already unit columns and are skipped.  Returns false (for every thread) on an
+// exactly zero pivot.
+__device__ bool gj_invert(double2* A, double2* B, int n) {
   constexpr int NT = 1024;
   __shared__ double rv[256];
   __shared__ int rix[256];
   __shared__ double2 f[256], arow[256], brow[256];
   __shared__ int pivr;
   __shared__ double2 pinv;
-  const int node = blockIdx.x, tid = threadIdx.x;
-  const int n = 2 * r;
-  double2* A = Aw + (long long)node * n * n;
-  double2* B = Bw + (long long)node * n * n;
-  for (int idx = tid; idx < n * n; idx += NT) {
-    const int i = idx / n, j = idx - i * n;
-    double2 a = make_double2(i == j ? 1.0 : 0.0, 0.0);
-    if (i < r && j >= r) {
-      const double2 x = t[((long long)(j - r) * nodes + node) * n + i];
-      a.x += x.x;
-      a.y += x.y;
-    } else if (i >= r && j < r) {
-      const double2 x = t[((long long)j * nodes + node) * n + i];
-      a.x += x.x;
-      a.y += x.y;
-    }
-    A[idx] = a;
-    B[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
+  const int tid = threadIdx.x;
   const int tr = tid >> 6, tj = tid & 63;  // 16 row groups x 64 columns
   for (int col = 0; col < n; ++col) {
-    // pivot row
     if (tid < 256) {
       rv[tid] = (tid >= col && tid < n) ? cabs_(A[(long long)tid * n + col]) : -1.0;
       rix[tid] = tid;
@@ -293,14 +270,11 @@ __global__ __launch_bounds__(1024) void k_core_invert(const double2* __restrict_
       }
       __syncthreads();
     }
-    if (rv[0] <= 0.0) {  // the same value for every thread: all leave together
-      if (tid == 0) bad[node] = 1;
-      return;
-    }
+    if (rv[0] <= 0.0) return false;  // the same value for every thread: all leave together
     if (tid == 0) pivr = rix[0];
     __syncthreads();
     const int pr = pivr;
-    // swap rows pr and col (A: columns >= col; B: all), keep the pivot row in LDS
+    // swap rows pr and col (A: columns >= col; B: all)
     for (int j = tid; j < n; j += NT) {
       if (pr != col) {
         if (j >= col) {
@@ -320,10 +294,10 @@ __global__ __launch_bounds__(1024) void k_core_invert(const double2* __restrict_
     __syncthreads();
     const double2 iv = pinv;
     for (int j = tid; j < n; j += NT) {
-      double2 b = B[(long long)col * n + j];
-      b = make_double2(b.x * iv.x - b.y * iv.y, b.x * iv.y + b.y * iv.x);
-      B[(long long)col * n + j] = b;
-      brow[j] = b;
+      double2 bb = B[(long long)col * n + j];
+      bb = make_double2(bb.x * iv.x - bb.y * iv.y, bb.x * iv.y + bb.y * iv.x);
+      B[(long long)col * n + j] = bb;
+      brow[j] = bb;
       if (j >= col) {
         double2 a = A[(long long)col * n + j];
         a = make_double2(a.x * iv.x - a.y * iv.y, a.x * iv.y + a.y * iv.x);
@@ -345,22 +319,106 @@ __global__ __launch_bounds__(1024) void k_core_invert(const double2* __restrict_
       }
       for (int j = tj; j < n; j += 64) {
         const double2 p = brow[j];
-        double2 b = B[(long long)i * n + j];
-        b.x -= fi.x * p.x - fi.y * p.y;
-        b.y -= fi.x * p.y + fi.y * p.x;
-        B[(long long)i * n + j] = b;
+        double2 bb = B[(long long)i * n + j];
+        bb.x -= fi.x * p.x - fi.y * p.y;
+        bb.y -= fi.x * p.y + fi.y * p.x;
+        B[(long long)i * n + j] = bb;
       }
     }
     __syncthreads();
   }
+  return true;
+}
+
+// SMW cores of one level, one workgroup per node: K = I + [0, X; Z, 0] with X[i][c] = t[c][node][i]
+// and Z[i][c] = t[c][node][r + i] (the r-column products W^T Y), inverted by gj_invert, then
+// written in the 16-row-block layout of the apply.  A, B: per-node n x n workspaces (row-major);
+// bad[node] = 1 for an exactly zero pivot.
+__global__ __launch_bounds__(1024) void k_core_invert(const double2* __restrict__ t, int r, int nodes,
+                                                      double2* __restrict__ Aw, double2* __restrict__ Bw,
+                                                      double2* __restrict__ out, int* __restrict__ bad) {
+  const int node = blockIdx.x, tid = threadIdx.x;
+  const int n = 2 * r;
+  double2* A = Aw + (long long)node * n * n;
+  double2* B = Bw + (long long)node * n * n;
+  for (int idx = tid; idx < n * n; idx += 1024) {
+    const int i = idx / n, j = idx - i * n;
+    double2 a = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    if (i < r && j >= r) {
+      const double2 x = t[((long long)(j - r) * nodes + node) * n + i];
+      a.x += x.x;
+      a.y += x.y;
+    } else if (i >= r && j < r) {
+      const double2 x = t[((long long)j * nodes + node) * n + i];
+      a.x += x.x;
+      a.y += x.y;
+    }
+    A[idx] = a;
+    B[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  if (!gj_invert(A, B, n)) {
+    if (tid == 0) bad[node] = 1;
+    return;
+  }
   // K^-1 = B to the apply layout: 16-row blocks, each column after column, rows past n zero
   const int nb = (n + 15) / 16;
   double2* D = out + (long long)node * nb * 16 * n;
-  for (int idx = tid; idx < nb * 16 * n; idx += NT) {
+  for (int idx = tid; idx < nb * 16 * n; idx += 1024) {
     const int blk = idx / (16 * n), rem = idx - blk * 16 * n;
     const int j = rem >> 4, i = blk * 16 + (rem & 15);
     D[idx] = i < n ? B[(long long)i * n + j] : make_double2(0.0, 0.0);
   }
+}
+
+// Dense HODLR leaves (diagonal blocks I + s kappa^2 diag(q) V of lp points), one workgroup per
+// listed leaf: formed from the table of V entries, inverted by gj_invert, written column-major to
+// Dinv at the leaf's index.  A, B: per-listed-leaf workspaces; bad[k] = 1 for a zero pivot.
+__global__ __launch_bounds__(1024) void k_leaf_invert(const double2* __restrict__ Wt, int n_grid,
+                                                      const int* __restrict__ ma, const int* __restrict__ mb,
+                                                      const double* __restrict__ q, double coef, int lp,
+                                                      const int* __restrict__ leaves, double2* __restrict__ Aw,
+                                                      double2* __restrict__ Bw, double2* __restrict__ Dinv,
+                                                      int* __restrict__ bad) {
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const long long leaf = leaves[k], base = leaf * lp;
+  double2* A = Aw + (long long)k * lp * lp;
+  double2* B = Bw + (long long)k * lp * lp;
+  for (int idx = tid; idx < lp * lp; idx += 1024) {
+    const int m = idx / lp, c = idx - m * lp;
+    const double2 w = Wt[(long long)(ma[base + m] - ma[base + c] + n_grid - 1) * (2 * n_grid - 1) +
+                         (mb[base + m] - mb[base + c] + n_grid - 1)];
+    const double cq = coef * q[base + m];
+    A[idx] = make_double2((m == c ? 1.0 : 0.0) + cq * w.x, cq * w.y);
+    B[idx] = make_double2(m == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  if (!gj_invert(A, B, lp)) {
+    if (tid == 0) bad[k] = 1;
+    return;
+  }
+  double2* D = Dinv + leaf * lp * lp;  // column-major: (m, c) at c * lp + m
+  for (int idx = tid; idx < lp * lp; idx += 1024) {
+    const int c = idx / lp, m = idx - c * lp;
+    D[idx] = B[(long long)m * lp + c];
+  }
+}
+
+// identity blocks (leaves without contrast)
+__global__ __launch_bounds__(256) void k_leaf_identity(const int* __restrict__ leaves, int lp, double2* __restrict__ Dinv) {
+  double2* D = Dinv + (long long)leaves[blockIdx.x] * lp * lp;
+  for (int idx = threadIdx.x; idx < lp * lp; idx += 256) D[idx] = make_double2(idx % (lp + 1) == 0 ? 1.0 : 0.0, 0.0);
+}
+
+void launch_leaf_identity(const int* leaves, int nleaves, int lp, double2* Dinv, hipStream_t s) {
+  if (nleaves > 0) k_leaf_identity<<<nleaves, 256, 0, s>>>(leaves, lp, Dinv);
+}
+
+void launch_leaf_invert(const double2* W, int n_grid, const int* ma, const int* mb, const double* q, double coef,
+                        int lp, const int* leaves, int nleaves, double2* A, double2* B, double2* Dinv, int* bad,
+                        hipStream_t s) {
+  if (lp > 256) throw std::runtime_error("HODLR leaves need at most 256 points");
+  if (nleaves > 0) k_leaf_invert<<<nleaves, 1024, 0, s>>>(W, n_grid, ma, mb, q, coef, lp, leaves, A, B, Dinv, bad);
 }
 
 void launch_core_invert(const double2* t, int r, int nodes, double2* A, double2* B, double2* out, int* bad,
