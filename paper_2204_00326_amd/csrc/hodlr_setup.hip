@@ -239,11 +239,11 @@ __global__ __launch_bounds__(256) void k_aca_rowpivot(AcaLevel L, int kmax) {
 }
 
 // Gauss-Jordan inversion of the n x n matrix A (row-major, n <= 256) by one workgroup of 1024
-// threads, B = A^-1 on return (B must hold the identity on entry), in the host routine's steps:
-// pivot = largest magnitude in the column at or below the diagonal, the lowest row among
-// equals; scale the pivot row; subtract multiples of it from every other row.  Columns left of
-// the pivot are already unit columns and are skipped.  Returns false (for every thread) on an
-// exactly zero pivot.
+// threads, B = A^-1 on return (B must hold the identity on entry).  Per column: the pivot is the
+// largest magnitude at or below the diagonal (the lowest row among equals), the pivot row is
+// swapped up and scaled, and multiples of it are subtracted from every other row.  Columns left
+// of the pivot are already unit columns and are skipped.  Returns false (for every thread) on
+// an exactly zero pivot.
 __device__ bool gj_invert(double2* A, double2* B, int n) {
   constexpr int NT = 1024;
   __shared__ double rv[256];

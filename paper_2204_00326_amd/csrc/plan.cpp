@@ -258,46 +258,6 @@ void plan_coverage(const Plan& p, int& cmin, int& cmax) {
 
 // ---- dense helpers --------------------------------------------------------------------
 
-bool invert_inplace(zd* A, int n) {
-  std::vector<int> piv(n);
-  std::vector<zd> I((size_t)n * n, zd(0));
-  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
-  for (int col = 0; col < n; ++col) {
-    int pr = col;
-    double best = std::abs(A[(size_t)col * n + col]);
-    for (int r = col + 1; r < n; ++r) {
-      double v = std::abs(A[(size_t)r * n + col]);
-      if (v > best) {
-        best = v;
-        pr = r;
-      }
-    }
-    if (best == 0.0) return false;
-    if (pr != col) {
-      for (int j = 0; j < n; ++j) {
-        std::swap(A[(size_t)pr * n + j], A[(size_t)col * n + j]);
-        std::swap(I[(size_t)pr * n + j], I[(size_t)col * n + j]);
-      }
-    }
-    zd inv = 1.0 / A[(size_t)col * n + col];
-    for (int j = 0; j < n; ++j) {
-      A[(size_t)col * n + j] *= inv;
-      I[(size_t)col * n + j] *= inv;
-    }
-    for (int r = 0; r < n; ++r) {
-      if (r == col) continue;
-      zd f = A[(size_t)r * n + col];
-      if (f == zd(0)) continue;
-      for (int j = 0; j < n; ++j) {
-        A[(size_t)r * n + j] -= f * A[(size_t)col * n + j];
-        I[(size_t)r * n + j] -= f * I[(size_t)col * n + j];
-      }
-    }
-  }
-  std::copy(I.begin(), I.end(), A);
-  return true;
-}
-
 // X (r x k, row-major) := X * B^{-1}, B (k x k row-major), by LU with partial pivoting of
 // B^T applied to the columns of X^T.
 void lu_solve_transposed(const std::vector<zd>& B, int k, std::vector<zd>& X, int r) {

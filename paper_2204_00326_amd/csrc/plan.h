@@ -105,7 +105,6 @@ ACAResult aca(int m, int n, int max_rank, double eps, const std::vector<char>* r
 
 // Dense complex helpers
 void lu_solve_transposed(const std::vector<zd>& B, int k, std::vector<zd>& X, int r);  // X (r x k) := X B^{-1}
-bool invert_inplace(zd* A, int n);  // Gauss-Jordan with partial pivoting; false if singular
 
 }  // namespace ls
 
