@@ -64,7 +64,8 @@ enum {
 };
 
 typedef struct {
-  int leaf_max;       /* max points per quadtree leaf (default 64) */
+  int leaf_max;       /* max points per quadtree leaf (default 64; at most 64 points per leaf
+                         when hodlr_rank > 0, else ls_setup returns LS_ENOTSUP) */
   double T;           /* a box of half-width w is high-frequency iff (kappa w)^2 > T (default 16) */
   int sign;           /* s in A = I + s kappa^2 diag(q) V; -1 (default) or +1 */
   int hodlr_rank;     /* fixed off-diagonal rank r of the HODLR preconditioner, 0..128; 0 = none

@@ -1917,6 +1917,8 @@ ls_status ls_setup(const double* points, int64_t N, const double* q, double kapp
     po.T = P->opt.T;
     P->plan = ls::make_plan(n, L, kappa, po);
     const ls::Plan& p = P->plan;
+    if (P->opt.hodlr_rank > 0 && p.leaf_side * p.leaf_side > 64)
+      throw LsError(LS_ENOTSUP, "the HODLR preconditioner needs quadtree leaves of at most 64 points (leaf_max)");
     double t_plan = now_ms();
     // ---- orders: Morton (solver) and S (DAFMM leaf arrays) ----
     const int side = p.leaf_side, nbL = p.lv[p.leaf].nb, nhL = nbL / 2;

@@ -99,3 +99,10 @@ def test_direct_solve_needs_a_factorisation():
     f = P.rhs_planewave([0.0])
     with pytest.raises(ls.LsError):
         P.direct_solve(f)
+
+
+def test_hodlr_needs_leaves_of_at_most_64_points():
+    pb = inputs.problem_bumps(64, 10.0, seed=1, count=2)
+    with pytest.raises(ls.LsError) as e:
+        ls.Problem(pb.points(), pb.q, 10.0, 1e-8, ls.Options(hodlr_rank=8, leaf_max=256))
+    assert e.value.code == ls.LS_ENOTSUP
