@@ -2,11 +2,11 @@
 
 Workload (one step = the whole hot path once): the constant-contrast disc (R = 0.6, q = 1)
 on a 512 x 512 cell-centred grid of [-1, 1]^2, kappa = 80, NCA tolerance 1e-10, HODLR
-preconditioner of rank 128 (capped at child size / 4 on the deepest levels), plane wave at
+preconditioner of rank 256 (capped at child size / 4 on the deepest levels), plane wave at
 angle 0; one step is one mixed-precision (complex64 operator, complex-bfloat16 HODLR factors,
 complex128 Krylov/refinement and leaf/core solves) flexible GMRES solve from zero to a true
 relative residual of 1e-8.  `value` = solves/s over the timed steps; the setup (tree, NCA,
-HODLR factorisation) is reported separately, and the same solve with a rank-64 preconditioner
+HODLR factorisation) is reported separately, and the same solve with a rank-128 preconditioner
 beside it (`rank_tradeoff`: shorter setup, more iterations).
 
 Also reported (outside the timed region): the same solve in FP64, DAFMM matvec/s for the
@@ -194,7 +194,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--kappa", type=float, default=80.0)
-    ap.add_argument("--rank", type=int, default=128, help="HODLR rank (levels capped at child size / rank-div)")
+    ap.add_argument("--rank", type=int, default=256, help="HODLR rank (levels capped at child size / rank-div)")
     ap.add_argument("--restart", type=int, default=500)
     ap.add_argument("--rank-div", type=int, default=4)
     ap.add_argument("--delta32", type=float, default=1e-4)
@@ -203,7 +203,7 @@ def main():
     ap.add_argument("--sample-every", type=int, default=7, help="time every k-th launch of a kernel class")
     ap.add_argument("--pc-bf16", type=int, default=1, help="bfloat16 HODLR factors in mixed solves (0: complex64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tradeoff-rank", type=int, default=64,
+    ap.add_argument("--tradeoff-rank", type=int, default=128,
                     help="also time the mixed solve with this HODLR rank (setup against solve time); 0: skip")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"),

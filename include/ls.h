@@ -68,7 +68,7 @@ typedef struct {
                          when hodlr_rank > 0, else ls_setup returns LS_ENOTSUP) */
   double T;           /* a box of half-width w is high-frequency iff (kappa w)^2 > T (default 16) */
   int sign;           /* s in A = I + s kappa^2 diag(q) V; -1 (default) or +1 */
-  int hodlr_rank;     /* fixed off-diagonal rank r of the HODLR preconditioner, 0..128; 0 = none
+  int hodlr_rank;     /* fixed off-diagonal rank r of the HODLR preconditioner, 0..256; 0 = none
                          (default 15) */
   double eps_inner;   /* NCA tolerance of the FP32 operator; <= 0: cast of the FP64 operator (default 1e-7) */
   int restart;        /* GMRES restart length m (default 200) */

@@ -952,17 +952,19 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
       L.retry = retry.as<int>();
       lsk::launch_aca_start(L, s0);
       const int kmax = (int)std::min<long long>(rl, L.S);
-      for (int k = 0; k < kmax; ++k) {
-        lsk::launch_aca_row(L, false, s0);
-        for (;;) {  // an exactly zero residual row: try the next unused one
-          hip_check(hipMemcpyAsync(hbuf.data(), retry.p, (size_t)L.nb * 4, hipMemcpyDeviceToHost, s0), "retry d2h");
-          hip_check(hipStreamSynchronize(s0), "aca");
-          bool any = false;
-          for (int b = 0; b < L.nb; ++b) any |= hbuf[b] != 0;
-          if (!any) break;
-          lsk::launch_aca_row(L, true, s0);
+      // kmax steps without a host round trip; blocks that met exactly zero rows (a step that
+      // only moved them to their next row) need more, until every block has stopped
+      for (int steps = kmax;;) {
+        for (int k = 0; k < steps; ++k) {
+          lsk::launch_aca_row(L, s0);
+          lsk::launch_aca_col(L, kmax, s0);
         }
-        lsk::launch_aca_col(L, kmax, s0);
+        hip_check(hipMemcpyAsync(hbuf.data(), state.p, (size_t)L.nb * 4, hipMemcpyDeviceToHost, s0), "state d2h");
+        hip_check(hipStreamSynchronize(s0), "aca");
+        bool any = false;
+        for (int b = 0; b < L.nb; ++b) any |= hbuf[b] == 0;
+        if (!any) break;
+        steps = 16;
       }
       hip_check(hipMemcpyAsync(hbuf.data(), kcur.p, (size_t)L.nb * 4, hipMemcpyDeviceToHost, s0), "ranks d2h");
       hip_check(hipStreamSynchronize(s0), "aca");
@@ -1808,7 +1810,7 @@ static void validate_options(const ls_options& o) {
   if (o.leaf_max < 1) throw LsError(LS_EINVAL, "leaf_max must be >= 1");
   if (!(o.T > 0) || !std::isfinite(o.T)) throw LsError(LS_EINVAL, "T must be positive");
   if (o.sign != -1 && o.sign != 1) throw LsError(LS_EINVAL, "sign must be -1 or +1");
-  if (o.hodlr_rank < 0 || o.hodlr_rank > 128) throw LsError(LS_EINVAL, "hodlr_rank must be in [0, 128]");
+  if (o.hodlr_rank < 0 || o.hodlr_rank > 256) throw LsError(LS_EINVAL, "hodlr_rank must be in [0, 256]");
   if (o.restart < 1) throw LsError(LS_EINVAL, "restart must be >= 1");
   if (o.maxit < 0) throw LsError(LS_EINVAL, "maxit must be >= 0");
   if (o.prec < 0 || o.prec > 2) throw LsError(LS_EINVAL, "prec must be LS_FP64, LS_FP32 or LS_MIXED");

@@ -24,16 +24,17 @@ struct AcaLevel {
 };
 
 void launch_aca_start(const AcaLevel& L, hipStream_t s);
-// residual pivot rows and their column pivots (only_retry: blocks whose last row was zero)
-void launch_aca_row(const AcaLevel& L, bool only_retry, hipStream_t s);
+// residual pivot rows and their column pivots (a block whose row is exactly zero marks it used,
+// moves to its next unused row and sets retry: the column kernels skip it in this step)
+void launch_aca_row(const AcaLevel& L, hipStream_t s);
 // v_k, u_k and the next pivot rows; blocks stop at kmax or when no row is left
 void launch_aca_col(const AcaLevel& L, int kmax, hipStream_t s);
-// SMW core inverses of one level (2r <= 256) from t (svec layout: [c][node][2r], the r-column
+// SMW core inverses of one level (2r <= 512) from t (svec layout: [c][node][2r], the r-column
 // W^T Y products) into out (hodlr_core_elems(r) entries per node, 16-row blocks); A, B: nodes x
 // (2r)^2 workspaces; bad[node] set to 1 where a pivot is exactly zero
 void launch_core_invert(const double2* t, int r, int nodes, double2* A, double2* B, double2* out, int* bad,
                         hipStream_t s);
-// inverses of the listed dense leaves (diagonal blocks I + coef diag(q) V of lp <= 256 points,
+// inverses of the listed dense leaves (diagonal blocks I + coef diag(q) V of lp <= 512 points,
 // V from the table W of an n_grid x n_grid grid) into Dinv (column-major lp x lp at each leaf's
 // index); A, B: nleaves x lp^2 workspaces; bad[k] set to 1 where a pivot is exactly zero
 void launch_leaf_invert(const double2* W, int n_grid, const int* ma, const int* mb, const double* q, double coef,

@@ -4,7 +4,9 @@
 // the largest residual entry of the pivot row over unused columns, the next row pivot the largest
 // entry of the new residual column over unused rows, an exactly zero residual row moves on to the
 // first unused row, magnitudes within a relative 1e-9 of the maximum are ties won by the lowest
-// index).  Every step runs for all blocks of the level at once; the residual row and column are
+// index).  Every step runs for all blocks of the level at once (a block whose pivot row was exactly
+// zero only moves to its next row in that step, and adds its term in a later one); the residual
+// row and column are
 // formed from the table of V entries, the contrast and the factors found so far, in the host
 // routine's order of operations, and the factors land directly in the device arrays U, V.
 // The pivot searches are two-stage: the kernels that form a residual row or column also write
@@ -131,10 +133,10 @@ __device__ long long pick_pivot(const AcaLevel& L, int b, long long ntiles, cons
 }
 
 // residual of the pivot row: r[j] = entry(i, j) - sum_{l < k} U_l[i] V_l[j]
-__global__ __launch_bounds__(256) void k_aca_row(AcaLevel L, int only_retry) {
+__global__ __launch_bounds__(256) void k_aca_row(AcaLevel L) {
   __shared__ double rd[256];
   const int b = blockIdx.y;
-  if (L.state[b] != 0 || (only_retry && !L.retry[b])) return;
+  if (L.state[b] != 0) return;
   const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
   const BlockGeom g = geom(L, b);
   double2 r = make_double2(0.0, 0.0);
@@ -156,11 +158,11 @@ __global__ __launch_bounds__(256) void k_aca_row(AcaLevel L, int only_retry) {
 }
 
 // column pivot of the residual row (or, for an exactly zero row, the next unused row to try)
-__global__ __launch_bounds__(256) void k_aca_colpivot(AcaLevel L, int only_retry) {
+__global__ __launch_bounds__(256) void k_aca_colpivot(AcaLevel L) {
   __shared__ double rd[256];
   __shared__ long long ri[256];
   const int b = blockIdx.x;
-  if (L.state[b] != 0 || (only_retry && !L.retry[b])) return;
+  if (L.state[b] != 0) return;
   const BlockGeom g = geom(L, b);
   double mx;
   const long long first = pick_pivot(L, b, (L.S + 255) / 256, L.rbuf + g.c0, L.col_used + g.c0, false, &mx, rd, ri);
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(256) void k_aca_colpivot(AcaLevel L, int only_retry
 __global__ __launch_bounds__(256) void k_aca_col(AcaLevel L) {
   __shared__ double rd[256];
   const int b = blockIdx.y;
-  if (L.state[b] != 0) return;
+  if (L.state[b] != 0 || L.retry[b]) return;  // retry: the row was zero, the next step tries another
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   const BlockGeom g = geom(L, b);
   const bool in = i < L.S;
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(256) void k_aca_rowpivot(AcaLevel L, int kmax) {
   __shared__ double rd[256];
   __shared__ long long ri[256];
   const int b = blockIdx.x;
-  if (L.state[b] != 0) return;
+  if (L.state[b] != 0 || L.retry[b]) return;
   const BlockGeom g = geom(L, b);
   const int k = L.kcur[b];
   double mx;
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(256) void k_aca_rowpivot(AcaLevel L, int kmax) {
   }
 }
 
-// Gauss-Jordan inversion of the n x n matrix A (row-major, n <= 256) by one workgroup of 1024
+// Gauss-Jordan inversion of the n x n matrix A (row-major, n <= 512) by one workgroup of 1024
 // threads, B = A^-1 on return (B must hold the identity on entry).  Per column: the pivot is the
 // largest magnitude at or below the diagonal (the lowest row among equals), the pivot row is
 // swapped up and scaled, and multiples of it are subtracted from every other row.  Columns left
@@ -246,20 +248,20 @@ __global__ __launch_bounds__(256) void k_aca_rowpivot(AcaLevel L, int kmax) {
 // an exactly zero pivot.
 __device__ bool gj_invert(double2* A, double2* B, int n) {
   constexpr int NT = 1024;
-  __shared__ double rv[256];
-  __shared__ int rix[256];
-  __shared__ double2 f[256], arow[256], brow[256];
+  __shared__ double rv[512];
+  __shared__ int rix[512];
+  __shared__ double2 f[512], arow[512], brow[512];
   __shared__ int pivr;
   __shared__ double2 pinv;
   const int tid = threadIdx.x;
   const int tr = tid >> 6, tj = tid & 63;  // 16 row groups x 64 columns
   for (int col = 0; col < n; ++col) {
-    if (tid < 256) {
+    if (tid < 512) {
       rv[tid] = (tid >= col && tid < n) ? cabs_(A[(long long)tid * n + col]) : -1.0;
       rix[tid] = tid;
     }
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
+    for (int st = 256; st > 0; st >>= 1) {
       if (tid < st) {
         const double v2 = rv[tid + st];
         const int i2 = rix[tid + st];
@@ -417,22 +419,22 @@ void launch_leaf_identity(const int* leaves, int nleaves, int lp, double2* Dinv,
 void launch_leaf_invert(const double2* W, int n_grid, const int* ma, const int* mb, const double* q, double coef,
                         int lp, const int* leaves, int nleaves, double2* A, double2* B, double2* Dinv, int* bad,
                         hipStream_t s) {
-  if (lp > 256) throw std::runtime_error("HODLR leaves need at most 256 points");
+  if (lp > 512) throw std::runtime_error("HODLR leaves need at most 512 points");
   if (nleaves > 0) k_leaf_invert<<<nleaves, 1024, 0, s>>>(W, n_grid, ma, mb, q, coef, lp, leaves, A, B, Dinv, bad);
 }
 
 void launch_core_invert(const double2* t, int r, int nodes, double2* A, double2* B, double2* out, int* bad,
                         hipStream_t s) {
-  if (2 * r > 256) throw std::runtime_error("HODLR cores need rank <= 128");
+  if (2 * r > 512) throw std::runtime_error("HODLR cores need rank <= 256");
   k_core_invert<<<nodes, 1024, 0, s>>>(t, r, nodes, A, B, out, bad);
 }
 
 void launch_aca_start(const AcaLevel& L, hipStream_t s) { k_aca_start<<<L.nb, 256, 0, s>>>(L); }
 
-void launch_aca_row(const AcaLevel& L, bool only_retry, hipStream_t s) {
+void launch_aca_row(const AcaLevel& L, hipStream_t s) {
   dim3 grid((unsigned)((L.S + 255) / 256), L.nb);
-  k_aca_row<<<grid, 256, 0, s>>>(L, only_retry ? 1 : 0);
-  k_aca_colpivot<<<L.nb, 256, 0, s>>>(L, only_retry ? 1 : 0);
+  k_aca_row<<<grid, 256, 0, s>>>(L);
+  k_aca_colpivot<<<L.nb, 256, 0, s>>>(L);
 }
 
 void launch_aca_col(const AcaLevel& L, int kmax, hipStream_t s) {

@@ -85,7 +85,7 @@ void launch_hodlr_upd_dot(const void* Y, int ra, const double2* sv, long long no
                           int rb, double2* z, long long N, double2* partial, long long chunk, hipStream_t s);
 void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
                       long long chunk, int nchunks, int nrhs, hipStream_t s);
-// cfmt: storage of the core inverses, 0 complex128, 1 complex64, 2 complex bfloat16 (r <= 128),
+// cfmt: storage of the core inverses, 0 complex128, 1 complex64, 2 complex bfloat16 (r <= 256),
 // hodlr_core_elems(r) entries per node in 16-row blocks (rows 16b..16b+15 of every column,
 // column after column, rows past 2r zero); coreinv unused when !apply (s = t)
 long long hodlr_core_elems(int r);

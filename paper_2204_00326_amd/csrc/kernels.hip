@@ -989,6 +989,21 @@ __global__ __launch_bounds__(256) void k_hodlr_core(const double2* __restrict__ 
   __shared__ double2 tp[256];
   const int node = blockIdx.x, rhs = blockIdx.y;
   const int r2 = 2 * r;
+  if (r2 > 256) {  // one thread per value and chunk order, several values per thread
+    for (int v = threadIdx.x; v < r2; v += 256) {
+      const int half = v < r ? 1 : 0;
+      const int c = v < r ? v : v - r;
+      const long long ch0 = (long long)node * 2 * cpc + (long long)half * cpc;
+      double re = 0, im = 0;
+      for (int k = 0; k < cpc; ++k) {
+        const double2 p = partial[((long long)rhs * nchunks + ch0 + k) * r + c];
+        re += p.x;
+        im += p.y;
+      }
+      sout[((long long)rhs * nodes + node) * r2 + v] = make_double2(re, im);
+    }
+    return;
+  }
   const int nks = 256 / r2;
   if ((int)threadIdx.x < r2 * nks) {
     const int v = threadIdx.x % r2, ks = threadIdx.x / r2;
@@ -1027,15 +1042,15 @@ __global__ __launch_bounds__(256) void k_hodlr_core(const double2* __restrict__ 
 // jp, jp + NT/16, ..., so the lanes of a wave read one contiguous kilobyte per load and a
 // thread issues all its loads before using them; the NT/16 partial sums of a row are added
 // through LDS in a fixed order.  NT = 1024 for levels with many chunk partials per node.
-template <typename TC, int NT>
+template <typename TC, int NT, int R2MAX = 256>
 __global__ __launch_bounds__(NT) void k_hodlr_core_rows(const double2* __restrict__ partial,
                                                         const typename V2<TC>::type* __restrict__ coreinv,
                                                         double2* __restrict__ sout, int r, int nodes, int cpc,
                                                         int nchunks, int nrf) {
   constexpr int CG = NT / 16;
-  constexpr int MAXU = 256 / CG;  // columns per thread at 2r = 256
+  constexpr int MAXU = R2MAX / CG;  // columns per thread at 2r = R2MAX
   using VT = typename V2<TC>::type;
-  __shared__ double2 t[256];
+  __shared__ double2 t[R2MAX];
   __shared__ double2 tp[NT];
   __shared__ double2 part[CG][16];
   const int node = nrf ? blockIdx.x / nrf : blockIdx.x, blk = blockIdx.y;
@@ -1109,6 +1124,12 @@ static void core_rows_pick(const void* coreinv, const double2* partial, double2*
   const int nrf = nrhs > 1 ? nrhs : 0;
   dim3 grid(nrf ? nodes * nrhs : nodes, (2 * r + 15) / 16, nrf ? 1 : nrhs);
   const auto* C = (const typename V2<TC>::type*)coreinv;
+  // ranks above 128: 1024 threads, up to 512 columns
+  if (2 * r > 256) {
+    auto kern = k_hodlr_core_rows<TC, 1024, 512>;
+    LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf);
+    return;
+  }
   // many partials per node (the coarse levels): 1024 threads share the sums of t
   if (cpc >= 16) {
     auto kern = k_hodlr_core_rows<TC, 1024>;
@@ -1121,7 +1142,8 @@ static void core_rows_pick(const void* coreinv, const double2* partial, double2*
 
 void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, double2* sout, int r, int nodes,
                        int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s) {
-  if (apply && 2 * r <= 256) {
+  if (2 * r > 512) throw std::runtime_error("HODLR cores need rank <= 256");
+  if (apply) {
     if (cfmt == 2)
       core_rows_pick<bf16>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s);
     else if (cfmt == 1)
@@ -1130,7 +1152,6 @@ void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, do
       core_rows_pick<double>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s);
     return;
   }
-  if (2 * r > 256) throw std::runtime_error("HODLR cores need rank <= 128");
   dim3 grid(nodes, nrhs);
   k_hodlr_core<<<grid, 256, 0, s>>>(partial, sout, r, nodes, chunks_per_child, nchunks);
 }

@@ -134,7 +134,7 @@ def test_rhs_planewave():
 
 
 @pytest.mark.parametrize("n,kappa,rank,kind", [(32, 10.0, 5, "gauss"), (32, 10.0, 15, "gauss"),
-                                               (64, 40.0, 10, "disc")])
+                                               (64, 40.0, 10, "disc"), (64, 40.0, 160, "disc")])
 def test_precond_matches_oracle_hodlr(n, kappa, rank, kind):
     if kind == "gauss":
         _, _, q = gauss32()
