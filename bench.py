@@ -378,7 +378,9 @@ def main():
                       "near_m2l32": "k_stencil_mfma<float> (near field + M2L launch)",
                       "hodlr_update": f"k_hodlr_update_wide<{'bf16' if args.pc_bf16 else 'float'}>",
                       "hodlr_dot": f"k_hodlr_dot_seg<{'bf16, 4' if args.pc_bf16 else 'float, 2'}> (HODLR W^T z)",
-                      "hodlr_upd_dot": "k_hodlr_upd_dot<1024> (HODLR z -= Y s fused with the next level's W^T z)"}[dom]
+                      "hodlr_upd_dot": "k_hodlr_upd_dot<CH> (HODLR z -= Y s fused with the next level's W^T z; "
+                                       "CH = 1024, 512, 256-row chunks, averaged over all three)",
+                      "hodlr_core": "k_hodlr_core_rows (HODLR SMW core products s = K^-1 t)"}[dom]
     roof["avg_launch_us"] = round(tot_ms / launches * 1e3, 2)
     roof["launches_timed"] = launches
     roof["launches"] = all_launches
@@ -399,7 +401,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 operator + bf16/c64 HODLR factors + c128 Krylov/refinement (mixed)",
+        "dtype": "c128 operator (c64 once the residual is below tol / 1e-4) + bf16/c64 HODLR factors + c128 "
+                 "Krylov/refinement/leaf/core solves (mixed)",
+        # near-field + M2L launches (one per operator application) of each precision per timed solve
+        "operator_applies_per_solve": {"c128": round(prof["near_m2l64"][2] / args.steps, 2),
+                                       "c64": round(prof["near_m2l32"][2] / args.steps, 2)},
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "N": N, "kappa": kappa,
                    "contrast": "disc R=0.6 q=1", "eps_nca": 1e-10, "eps_inner": 1e-7, "hodlr_rank": r,
