@@ -1042,7 +1042,7 @@ __global__ __launch_bounds__(256) void k_hodlr_core(const double2* __restrict__ 
 // jp, jp + NT/16, ..., so the lanes of a wave read one contiguous kilobyte per load and a
 // thread issues all its loads before using them; the NT/16 partial sums of a row are added
 // through LDS in a fixed order.  NT = 1024 for levels with many chunk partials per node.
-template <typename TC, int NT, int R2MAX = 256>
+template <typename TC, int NT, int R2MAX = 256, int RB = 1>
 __global__ __launch_bounds__(NT) void k_hodlr_core_rows(const double2* __restrict__ partial,
                                                         const typename V2<TC>::type* __restrict__ coreinv,
                                                         double2* __restrict__ sout, int r, int nodes, int cpc,
@@ -1050,11 +1050,15 @@ __global__ __launch_bounds__(NT) void k_hodlr_core_rows(const double2* __restric
   constexpr int CG = NT / 16;
   constexpr int MAXU = R2MAX / CG;  // columns per thread at 2r = R2MAX
   using VT = typename V2<TC>::type;
-  __shared__ double2 t[R2MAX];
+  __shared__ double2 t[RB][R2MAX];
   __shared__ double2 tp[NT];
   __shared__ double2 part[CG][16];
-  const int node = nrf ? blockIdx.x / nrf : blockIdx.x, blk = blockIdx.y;
-  const int rhs = nrf ? blockIdx.x % nrf : blockIdx.z;
+  // nrf > 0: nrf right-hand sides in blocks of RB (each block of K^-1 is read once per RB of
+  // them), the right-hand-side block fastest in grid.x; nrf = 0: the right-hand side is grid.z
+  const int nrb = nrf ? (nrf + RB - 1) / RB : 1;
+  const int node = nrf ? blockIdx.x / nrb : blockIdx.x, blk = blockIdx.y;
+  const int rhs0 = nrf ? (blockIdx.x % nrb) * RB : blockIdx.z;
+  const int nbr = nrf ? (nrf - rhs0 < RB ? nrf - rhs0 : RB) : 1;
   const int r2 = 2 * r;
   // the block of K^-1 does not depend on t: its loads go out first and overlap the sums of t
   const int li = threadIdx.x & 15, jp = threadIdx.x >> 4;
@@ -1068,76 +1072,94 @@ __global__ __launch_bounds__(NT) void k_hodlr_core_rows(const double2* __restric
   }
   // t from the chunk partials: nks threads per value take every nks-th chunk, then a fixed-order sum
   const int nks = NT / r2;
-  if ((int)threadIdx.x < r2 * nks) {
-    const int v = threadIdx.x % r2, ks = threadIdx.x / r2;
-    const int half = v < r ? 1 : 0;  // t_A sums the second child
-    const int c = v < r ? v : v - r;
-    const long long ch0 = (long long)node * 2 * cpc + (long long)half * cpc;
-    double re = 0, im = 0;
+  for (int b = 0; b < nbr; ++b) {
+    const long long rhs = rhs0 + b;
+    if ((int)threadIdx.x < r2 * nks) {
+      const int v = threadIdx.x % r2, ks = threadIdx.x / r2;
+      const int half = v < r ? 1 : 0;  // t_A sums the second child
+      const int c = v < r ? v : v - r;
+      const long long ch0 = (long long)node * 2 * cpc + (long long)half * cpc;
+      double re = 0, im = 0;
 #pragma unroll(NT == 1024 ? 16 : 4)
-    for (int k = ks; k < cpc; k += nks) {
-      const double2 p = partial[((long long)rhs * nchunks + ch0 + k) * r + c];
-      re += p.x;
-      im += p.y;
+      for (int k = ks; k < cpc; k += nks) {
+        const double2 p = partial[(rhs * nchunks + ch0 + k) * r + c];
+        re += p.x;
+        im += p.y;
+      }
+      tp[ks * r2 + v] = make_double2(re, im);
     }
-    tp[ks * r2 + v] = make_double2(re, im);
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < r2) {
-    double re = 0, im = 0;
-    for (int ks = 0; ks < nks; ++ks) {
-      re += tp[ks * r2 + threadIdx.x].x;
-      im += tp[ks * r2 + threadIdx.x].y;
+    __syncthreads();
+    if ((int)threadIdx.x < r2) {
+      double re = 0, im = 0;
+      for (int ks = 0; ks < nks; ++ks) {
+        re += tp[ks * r2 + threadIdx.x].x;
+        im += tp[ks * r2 + threadIdx.x].y;
+      }
+      t[b][threadIdx.x] = make_double2(re, im);
     }
-    t[threadIdx.x] = make_double2(re, im);
+    __syncthreads();
   }
-  __syncthreads();
-  double re = 0, im = 0;
-#pragma unroll
-  for (int u = 0; u < MAXU; ++u) {
-    const int j = jp + u * CG;
-    if (j < r2) {
-      const double2 av = to_d2(a[u]);
-      const double2 x = t[j];
-      re = fma(av.x, x.x, re);
-      re = fma(-av.y, x.y, re);
-      im = fma(av.x, x.y, im);
-      im = fma(av.y, x.x, im);
-    }
-  }
-  part[jp][li] = make_double2(re, im);
-  __syncthreads();
   const int i = blk * 16 + li;
-  if (jp != 0 || i >= r2) return;
-  for (int q = 1; q < CG; ++q) {
-    re += part[q][li].x;
-    im += part[q][li].y;
+  for (int b = 0; b < nbr; ++b) {
+    double re = 0, im = 0;
+#pragma unroll
+    for (int u = 0; u < MAXU; ++u) {
+      const int j = jp + u * CG;
+      if (j < r2) {
+        const double2 av = to_d2(a[u]);
+        const double2 x = t[b][j];
+        re = fma(av.x, x.x, re);
+        re = fma(-av.y, x.y, re);
+        im = fma(av.x, x.y, im);
+        im = fma(av.y, x.x, im);
+      }
+    }
+    part[jp][li] = make_double2(re, im);
+    __syncthreads();
+    if (jp == 0 && i < r2) {
+      for (int q = 1; q < CG; ++q) {
+        re += part[q][li].x;
+        im += part[q][li].y;
+      }
+      sout[((long long)(rhs0 + b) * nodes + node) * r2 + i] = make_double2(re, im);
+    }
+    __syncthreads();
   }
-  sout[((long long)rhs * nodes + node) * r2 + i] = make_double2(re, im);
 }
 
 long long hodlr_core_elems(int r) { return (long long)((2 * r + 15) / 16) * 16 * (2 * r); }
 
-template <typename TC>
-static void core_rows_pick(const void* coreinv, const double2* partial, double2* sout, int r, int nodes, int cpc,
-                           int nchunks, int nrhs, hipStream_t s) {
+template <typename TC, int RB>
+static void core_rows_shape(const void* coreinv, const double2* partial, double2* sout, int r, int nodes, int cpc,
+                            int nchunks, int nrhs, hipStream_t s) {
   const int nrf = nrhs > 1 ? nrhs : 0;
-  dim3 grid(nrf ? nodes * nrhs : nodes, (2 * r + 15) / 16, nrf ? 1 : nrhs);
+  const int nrb = (nrhs + RB - 1) / RB;
+  dim3 grid(nrf ? nodes * nrb : nodes, (2 * r + 15) / 16, nrf ? 1 : nrhs);
   const auto* C = (const typename V2<TC>::type*)coreinv;
   // ranks above 128: 1024 threads, up to 512 columns
   if (2 * r > 256) {
-    auto kern = k_hodlr_core_rows<TC, 1024, 512>;
+    auto kern = k_hodlr_core_rows<TC, 1024, 512, RB>;
     LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf);
     return;
   }
   // many partials per node (the coarse levels): 1024 threads share the sums of t
   if (cpc >= 16) {
-    auto kern = k_hodlr_core_rows<TC, 1024>;
+    auto kern = k_hodlr_core_rows<TC, 1024, 256, RB>;
     LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf);
   } else {
-    auto kern = k_hodlr_core_rows<TC, 256>;
+    auto kern = k_hodlr_core_rows<TC, 256, 256, RB>;
     LSK_LAUNCH(kern, grid, 256, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf);
   }
+}
+
+template <typename TC>
+static void core_rows_pick(const void* coreinv, const double2* partial, double2* sout, int r, int nodes, int cpc,
+                           int nchunks, int nrhs, hipStream_t s) {
+  // many right-hand sides: 8 per workgroup share each block of K^-1 (same sums per column)
+  if (nrhs >= 8)
+    core_rows_shape<TC, 8>(coreinv, partial, sout, r, nodes, cpc, nchunks, nrhs, s);
+  else
+    core_rows_shape<TC, 1>(coreinv, partial, sout, r, nodes, cpc, nchunks, nrhs, s);
 }
 
 void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, double2* sout, int r, int nodes,
