@@ -30,8 +30,9 @@ void launch_aca_row(const AcaLevel& L, hipStream_t s);
 // v_k, u_k and the next pivot rows; blocks stop at kmax or when no row is left
 void launch_aca_col(const AcaLevel& L, int kmax, hipStream_t s);
 // SMW core inverses of one level (2r <= 512) from t (svec layout: [c][node][2r], the r-column
-// W^T Y products) into out (hodlr_core_elems(r) entries per node, 16-row blocks); A, B: nodes x
-// (2r)^2 workspaces; bad[node] set to 1 where a pivot is exactly zero
+// W^T Y products) into out (hodlr_core_elems(r) entries per node, 16-row blocks), by the Schur
+// complement of the identity block; A: nodes x 4r^2 and B: nodes x r^2 workspaces (at least);
+// bad[node] set to 1 where a pivot of the Schur complement is exactly zero
 void launch_core_invert(const double2* t, int r, int nodes, double2* A, double2* B, double2* out, int* bad,
                         hipStream_t s);
 // inverses of the listed dense leaves (diagonal blocks I + coef diag(q) V of lp <= 512 points,

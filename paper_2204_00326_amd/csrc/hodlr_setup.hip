@@ -332,44 +332,84 @@ __device__ bool gj_invert(double2* A, double2* B, int n) {
   return true;
 }
 
-// SMW cores of one level, one workgroup per node: K = I + [0, X; Z, 0] with X[i][c] = t[c][node][i]
-// and Z[i][c] = t[c][node][r + i] (the r-column products W^T Y), inverted by gj_invert, then
-// written in the 16-row-block layout of the apply.  A, B: per-node n x n workspaces (row-major);
-// bad[node] = 1 for an exactly zero pivot.
-__global__ __launch_bounds__(1024) void k_core_invert(const double2* __restrict__ t, int r, int nodes,
-                                                      double2* __restrict__ Aw, double2* __restrict__ Bw,
-                                                      double2* __restrict__ out, int* __restrict__ bad) {
-  const int node = blockIdx.x, tid = threadIdx.x;
-  const int n = 2 * r;
-  double2* A = Aw + (long long)node * n * n;
-  double2* B = Bw + (long long)node * n * n;
-  for (int idx = tid; idx < n * n; idx += 1024) {
-    const int i = idx / n, j = idx - i * n;
-    double2 a = make_double2(i == j ? 1.0 : 0.0, 0.0);
-    if (i < r && j >= r) {
-      const double2 x = t[((long long)(j - r) * nodes + node) * n + i];
-      a.x += x.x;
-      a.y += x.y;
-    } else if (i >= r && j < r) {
-      const double2 x = t[((long long)j * nodes + node) * n + i];
-      a.x += x.x;
-      a.y += x.y;
+// Batched complex n x n products C = alpha A B (+ I), one 16 x 16 tile of C per workgroup and
+// node (grid: tiles x nodes).  Element (i, k) of A is at A[node aN + i aI + k aK], likewise B and
+// C, so the operands can be read in place from the t layout; a tile is loaded along whichever
+// index has unit stride.
+__global__ __launch_bounds__(256) void k_bgemm(const double2* __restrict__ A, long long aI, long long aK, long long aN,
+                                               const double2* __restrict__ B, long long bK, long long bJ,
+                                               long long bN, double2* __restrict__ C, long long cI, long long cJ,
+                                               long long cN, int n, double alpha, int add_identity) {
+  __shared__ double2 As[16][17], Bs[16][17];
+  const int nt = (n + 15) / 16;
+  const int ti = blockIdx.x / nt, tj = blockIdx.x - ti * nt;
+  const long long node = blockIdx.y;
+  const int li = threadIdx.x >> 4, lj = threadIdx.x & 15;
+  double re = 0, im = 0;
+  for (int k0 = 0; k0 < n; k0 += 16) {
+    {
+      const int x = aI == 1 ? lj : li, y = aI == 1 ? li : lj;  // As[x][y] = A(16 ti + x, k0 + y)
+      const int ai = ti * 16 + x, ak = k0 + y;
+      As[x][y] = (ai < n && ak < n) ? A[node * aN + ai * aI + ak * aK] : make_double2(0.0, 0.0);
     }
-    A[idx] = a;
-    B[idx] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    {
+      const int x = bK == 1 ? lj : li, y = bK == 1 ? li : lj;  // Bs[x][y] = B(k0 + x, 16 tj + y)
+      const int bk = k0 + x, bj = tj * 16 + y;
+      Bs[x][y] = (bk < n && bj < n) ? B[node * bN + bk * bK + bj * bJ] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const double2 u = As[li][kk], v = Bs[kk][lj];
+      re = fma(u.x, v.x, re);
+      re = fma(-u.y, v.y, re);
+      im = fma(u.x, v.y, im);
+      im = fma(u.y, v.x, im);
+    }
+    __syncthreads();
   }
+  const int i = ti * 16 + li, j = tj * 16 + lj;
+  if (i < n && j < n)
+    C[node * cN + i * cI + j * cJ] = make_double2(alpha * re + (add_identity && i == j ? 1.0 : 0.0), alpha * im);
+}
+
+// S^-1 for every node (S row-major n x n, destroyed), one workgroup per node
+__global__ __launch_bounds__(1024) void k_gj_batch(double2* __restrict__ Sw, double2* __restrict__ Siw, int n,
+                                                   int* __restrict__ bad) {
+  const long long node = blockIdx.x;
+  double2* S = Sw + node * n * n;
+  double2* Si = Siw + node * n * n;
+  for (int idx = threadIdx.x; idx < n * n; idx += 1024)
+    Si[idx] = make_double2(idx % (n + 1) == 0 ? 1.0 : 0.0, 0.0);
   __syncthreads();
-  if (!gj_invert(A, B, n)) {
-    if (tid == 0) bad[node] = 1;
-    return;
-  }
-  // K^-1 = B to the apply layout: 16-row blocks, each column after column, rows past n zero
-  const int nb = (n + 15) / 16;
-  double2* D = out + (long long)node * nb * 16 * n;
-  for (int idx = tid; idx < nb * 16 * n; idx += 1024) {
+  if (!gj_invert(S, Si, n) && threadIdx.x == 0) bad[node] = 1;
+}
+
+// K^-1 from its blocks, in the 16-row-block layout of the apply:
+// [[TL, -P], [-Q, S^-1]] with P = X S^-1, Q = S^-1 Z, TL = I + P Z (all r x r row-major per node)
+__global__ __launch_bounds__(256) void k_core_assemble(const double2* __restrict__ Si, const double2* __restrict__ P,
+                                                       const double2* __restrict__ Q, const double2* __restrict__ TL,
+                                                       int r, double2* __restrict__ out) {
+  const long long node = blockIdx.x;
+  const int n = 2 * r, nb = (n + 15) / 16;
+  const long long rr = (long long)r * r;
+  double2* D = out + node * nb * 16 * n;
+  for (int idx = threadIdx.x; idx < nb * 16 * n; idx += 256) {
     const int blk = idx / (16 * n), rem = idx - blk * 16 * n;
     const int j = rem >> 4, i = blk * 16 + (rem & 15);
-    D[idx] = i < n ? B[(long long)i * n + j] : make_double2(0.0, 0.0);
+    double2 v = make_double2(0.0, 0.0);
+    if (i < r && j < r) {
+      v = TL[node * rr + (long long)i * r + j];
+    } else if (i < r && j < n) {
+      const double2 p = P[node * rr + (long long)i * r + (j - r)];
+      v = make_double2(-p.x, -p.y);
+    } else if (i < n && j < r) {
+      const double2 q = Q[node * rr + (long long)(i - r) * r + j];
+      v = make_double2(-q.x, -q.y);
+    } else if (i < n) {
+      v = Si[node * rr + (long long)(i - r) * r + (j - r)];
+    }
+    D[idx] = v;
   }
 }
 
@@ -423,10 +463,28 @@ void launch_leaf_invert(const double2* W, int n_grid, const int* ma, const int* 
   if (nleaves > 0) k_leaf_invert<<<nleaves, 1024, 0, s>>>(W, n_grid, ma, mb, q, coef, lp, leaves, A, B, Dinv, bad);
 }
 
+// K = I + [0, X; Z, 0], X[i][c] = t[c][node][i], Z[i][c] = t[c][node][r + i] (t: [c][node][2r]).
+// By the Schur complement of the identity block, S = I - Z X and
+//   K^-1 = [[I + X S^-1 Z, -X S^-1], [-S^-1 Z, S^-1]]:
+// four batched r x r products and one batched Gauss-Jordan of order r instead of order 2r.
 void launch_core_invert(const double2* t, int r, int nodes, double2* A, double2* B, double2* out, int* bad,
                         hipStream_t s) {
   if (2 * r > 512) throw std::runtime_error("HODLR cores need rank <= 256");
-  k_core_invert<<<nodes, 1024, 0, s>>>(t, r, nodes, A, B, out, bad);
+  if (r <= 0 || nodes <= 0) return;
+  const long long rr = (long long)r * r, r2 = 2 * r, tn = (long long)nodes * r2;
+  double2 *S = A, *P = A + nodes * rr, *Q = A + 2 * nodes * rr, *TL = A + 3 * nodes * rr, *Si = B;
+  const int nt = (r + 15) / 16;
+  const dim3 grid((unsigned)(nt * nt), (unsigned)nodes);
+  const double2 *X = t, *Z = t + r;  // X(i, k) at X[node r2 + i + k tn], Z likewise
+  // S = I - Z X
+  k_bgemm<<<grid, 256, 0, s>>>(Z, 1, tn, r2, X, 1, tn, r2, S, r, 1, rr, r, -1.0, 1);
+  // S^-1 (S destroyed)
+  k_gj_batch<<<nodes, 1024, 0, s>>>(S, Si, r, bad);
+  // P = X S^-1, Q = S^-1 Z, TL = I + P Z
+  k_bgemm<<<grid, 256, 0, s>>>(X, 1, tn, r2, Si, r, 1, rr, P, r, 1, rr, r, 1.0, 0);
+  k_bgemm<<<grid, 256, 0, s>>>(Si, r, 1, rr, Z, 1, tn, r2, Q, r, 1, rr, r, 1.0, 0);
+  k_bgemm<<<grid, 256, 0, s>>>(P, r, 1, rr, Z, 1, tn, r2, TL, r, 1, rr, r, 1.0, 1);
+  k_core_assemble<<<nodes, 256, 0, s>>>(Si, P, Q, TL, r, out);
 }
 
 void launch_aca_start(const AcaLevel& L, hipStream_t s) { k_aca_start<<<L.nb, 256, 0, s>>>(L); }
