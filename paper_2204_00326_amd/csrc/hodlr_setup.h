@@ -1,4 +1,4 @@
-// Batched ACA of the HODLR off-diagonal blocks on the device (see hodlr_setup.hip).
+// HODLR factorisation on the device: batched ACA of the off-diagonal blocks, leaf and SMW core inverses.
 #pragma once
 #include <hip/hip_runtime.h>
 

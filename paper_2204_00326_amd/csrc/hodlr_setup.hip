@@ -1,19 +1,23 @@
-// Batched partially pivoted ACA for the off-diagonal blocks of one HODLR level on the device
-// (Section 5: fixed-rank compression of the off-diagonal blocks; the pivoting rules of the
-// host routine in aca_impl.h: start at the first row not known to be zero, the column pivot is
-// the largest residual entry of the pivot row over unused columns, the next row pivot the largest
-// entry of the new residual column over unused rows, an exactly zero residual row moves on to the
-// first unused row, magnitudes within a relative 1e-9 of the maximum are ties won by the lowest
-// index).  Every step runs for all blocks of the level at once (a block whose pivot row was exactly
-// zero only moves to its next row in that step, and adds its term in a later one); the residual
-// row and column are
-// formed from the table of V entries, the contrast and the factors found so far, in the host
-// routine's order of operations, and the factors land directly in the device arrays U, V.
-// The pivot searches are two-stage: the kernels that form a residual row or column also write
-// the largest magnitude over the unused entries of each 256-entry tile; the pivot kernel takes
-// the maximum over the tiles, finds the first tile that reaches the tie threshold and scans
-// only that tile for the first index that does (the first tile reaching it holds the first
-// such index), so a block of 131072 entries costs one workgroup a few hundred reads.
+// HODLR factorisation on the device (Section 5).
+//
+// Batched partially pivoted ACA for the off-diagonal blocks of one level (fixed-rank compression
+// of the off-diagonal blocks), with the pivoting rules of the host routine in aca_impl.h: start at
+// the first row not known to be zero, the column pivot is the largest residual entry of the pivot
+// row over unused columns, the next row pivot the largest entry of the new residual column over
+// unused rows, an exactly zero residual row moves on to the first unused row, magnitudes within a
+// relative 1e-9 of the maximum are ties won by the lowest index.  Every step runs for all blocks
+// of the level at once (a block whose pivot row was exactly zero only moves to its next row in
+// that step, and adds its term in a later one); the residual row and column are formed from the
+// table of V entries, the contrast and the factors found so far, in the host routine's order of
+// operations, and the factors land directly in the device arrays U, V.  The pivot searches are
+// two-stage: the kernels that form a residual row or column also write the largest magnitude over
+// the unused entries of each 256-entry tile; the pivot kernel takes the maximum over the tiles,
+// finds the first tile that reaches the tie threshold and scans only that tile for the first
+// index that does (the first tile reaching it holds the first such index), so a block of 131072
+// entries costs one workgroup a few hundred reads.
+//
+// Inverses of the dense leaf blocks (Gauss-Jordan) and of the SMW cores (through the Schur
+// complement of their identity block), written in the layouts the apply kernels read.
 #include <hip/hip_runtime.h>
 
 #include <climits>
