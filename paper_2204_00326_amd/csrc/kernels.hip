@@ -1222,17 +1222,20 @@ __global__ __launch_bounds__(256) void k_hodlr_update(const typename V2<T>::type
 // Many right-hand sides with complex128 factors (the r-column applies that form the factors):
 // a thread owns one row and RB right-hand sides, so each factor entry is read once per RB
 // right-hand sides instead of once per right-hand side.  A wave's 64 rows lie in one node half
-// (halves hold at least 64 rows), so the s entries a wave reads are the same for all its lanes.
-// Per (row, right-hand side) the sums run over c in the order of k_hodlr_update: same results.
+// (halves hold at least 64 rows), so the s entries a wave reads are the same for all its lanes:
+// the wave stages them in LDS, 32 columns at a time, and reads them back as broadcasts.  Per
+// (row, right-hand side) the sums run over c in the order of k_hodlr_update: same results.
 template <int RB>
 __global__ __launch_bounds__(256) void k_hodlr_update_rb(const double2* __restrict__ Y, const double2* __restrict__ sv,
                                                          double2* __restrict__ z, long long ldz, long long N, int r,
                                                          long long nodesize, int nodes, int nrhs) {
+  constexpr int CC = 32;  // columns of s staged at a time
+  __shared__ double2 sl[4][RB][CC];
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   const int rhs0 = blockIdx.y * RB;
-  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const long long i0 = (long long)blockIdx.x * 256 + wv * 64;
-  if (i0 >= N) return;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  long long i0 = (long long)blockIdx.x * 256 + wv * 64;
+  if (i0 > N - 1) i0 = N - 1;  // a wave past the end still takes part in the barriers
   const long long node = i0 / nodesize;
   const int half = (i0 - node * nodesize) >= (nodesize >> 1) ? 1 : 0;
   const long long sstride = (long long)nodes * 2 * r;
@@ -1242,17 +1245,27 @@ __global__ __launch_bounds__(256) void k_hodlr_update_rb(const double2* __restri
   double re[RB], im[RB];
 #pragma unroll
   for (int b = 0; b < RB; ++b) re[b] = im[b] = 0;
-#pragma unroll 4
-  for (int c = 0; c < r; ++c) {
-    const double2 y = Y[(long long)c * N + ic];
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      const double2 x = b < nb ? s[b * sstride + c] : make_double2(0.0, 0.0);
-      re[b] = fma(y.x, x.x, re[b]);
-      re[b] = fma(-y.y, x.y, re[b]);
-      im[b] = fma(y.x, x.y, im[b]);
-      im[b] = fma(y.y, x.x, im[b]);
+  for (int c0 = 0; c0 < r; c0 += CC) {
+    const int cw = r - c0 < CC ? r - c0 : CC;
+    // each wave stages the s entries of its own node half (waves of one workgroup may differ)
+    for (int e = lane; e < RB * CC; e += 64) {
+      const int b = e / CC, c = e - b * CC;
+      sl[wv][b][c] = (b < nb && c < cw) ? s[b * sstride + c0 + c] : make_double2(0.0, 0.0);
     }
+    __syncthreads();
+#pragma unroll 4
+    for (int c = 0; c < cw; ++c) {
+      const double2 y = Y[(long long)(c0 + c) * N + ic];
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        const double2 x = sl[wv][b][c];
+        re[b] = fma(y.x, x.x, re[b]);
+        re[b] = fma(-y.y, x.y, re[b]);
+        im[b] = fma(y.x, x.y, im[b]);
+        im[b] = fma(y.y, x.x, im[b]);
+      }
+    }
+    __syncthreads();
   }
   if (i >= N) return;
 #pragma unroll
