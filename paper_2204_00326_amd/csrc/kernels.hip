@@ -1136,10 +1136,15 @@ static void core_rows_shape(const void* coreinv, const double2* partial, double2
   const int nrb = (nrhs + RB - 1) / RB;
   dim3 grid(nrf ? nodes * nrb : nodes, (2 * r + 15) / 16, nrf ? 1 : nrhs);
   const auto* C = (const typename V2<TC>::type*)coreinv;
-  // ranks above 128: 1024 threads, up to 512 columns
+  // ranks above 128 (up to 512 columns): 1024 threads where many chunk partials make up t, else 512
   if (2 * r > 256) {
-    auto kern = k_hodlr_core_rows<TC, 1024, 512, RB>;
-    LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf);
+    if (cpc >= 16) {
+      auto kern = k_hodlr_core_rows<TC, 1024, 512, RB>;
+      LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf);
+    } else {
+      auto kern = k_hodlr_core_rows<TC, 512, 512, RB>;
+      LSK_LAUNCH(kern, grid, 512, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf);
+    }
     return;
   }
   // many partials per node (the coarse levels): 1024 threads share the sums of t
