@@ -78,7 +78,7 @@ KERNELS_SRC = os.path.join(ROOT, "paper_2204_00326_amd", "csrc", "kernels.hip")
 # kernel names (before the argument list) of the classes the roofline may report
 # (the HBM-bound ones; the matrix-core stencil kernel serves every DAFMM pass under one name)
 COUNTED = {"hodlr_dot": "lsk::k_hodlr_dot_seg<lsk::bf16, 4, 4>", "hodlr_update": "lsk::k_hodlr_update_wide<lsk::bf16>",
-           "hodlr_upd_dot": "lsk::k_hodlr_upd_dot<"}   # any chunk instantiation: same bytes per launch
+           "hodlr_upd_dot": "lsk::k_hodlr_upd_dot<"}
 
 
 def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok):
@@ -86,7 +86,7 @@ def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok):
     side), averaged over the launches of each class: a level's factor (N x r_l entries of fsz
     bytes) plus z (complex128) read, and z written by an update.  Mirrors the library's level
     plan: rank min(rank, child size / rank_div), chunks of at most max_rows rows, and an update
-    fused with the next level's dot where that level's chunks are 256, 512 or 1024 rows."""
+    fused with the next level's dot where that level's chunks are 1024 rows."""
     ranks = [max(1, min(rank, (N >> (l + 1)) // rank_div)) if rank_div > 0 else rank for l in range(levels)]
     def chunk(l):
         ch = N >> (l + 1)
@@ -96,7 +96,7 @@ def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok):
     cls = {"hodlr_dot": [], "hodlr_update": [], "hodlr_upd_dot": []}
     pend = -1
     for l in range(levels - 1, -1, -1):
-        if pend >= 0 and fused_ok and N % 1024 == 0 and (N >> pend) % 128 == 0 and chunk(l) in (256, 512, 1024):
+        if pend >= 0 and fused_ok and N % 1024 == 0 and (N >> pend) % 128 == 0 and chunk(l) == 1024:
             cls["hodlr_upd_dot"].append(N * (ranks[pend] + ranks[l]) * fsz + 2 * N * 16)
         else:
             if pend >= 0:
@@ -378,8 +378,7 @@ def main():
                       "near_m2l32": "k_stencil_mfma<float> (near field + M2L launch)",
                       "hodlr_update": f"k_hodlr_update_wide<{'bf16' if args.pc_bf16 else 'float'}>",
                       "hodlr_dot": f"k_hodlr_dot_seg<{'bf16, 4' if args.pc_bf16 else 'float, 2'}> (HODLR W^T z)",
-                      "hodlr_upd_dot": "k_hodlr_upd_dot<CH> (HODLR z -= Y s fused with the next level's W^T z; "
-                                       "CH = 1024, 512, 256-row chunks, averaged over all three)",
+                      "hodlr_upd_dot": "k_hodlr_upd_dot<1024> (HODLR z -= Y s fused with the next level's W^T z)",
                       "hodlr_core": "k_hodlr_core_rows (HODLR SMW core products s = K^-1 t)"}[dom]
     roof["avg_launch_us"] = round(tot_ms / launches * 1e3, 2)
     roof["launches_timed"] = launches

@@ -78,8 +78,8 @@ void launch_leaf_apply(int dfmt, const void* Dinv, const unsigned char* ident, c
                        double2* z, long long ldz, int lp, int nleaves, int nrhs, hipStream_t s,
                        const int* jdev = nullptr, long long bldj = 0);
 // complex bfloat16 factors, one right-hand side: z -= Y_a s_a (update of level a, node size
-// nodesize_a) and the chunk partials of W_b^T z (dot of level b, chunks of 256, 512 or 1024
-// rows) in one launch; the same sums as launch_hodlr_update followed by launch_hodlr_dot
+// nodesize_a) and the chunk partials of W_b^T z (dot of level b, chunks of 1024 rows) in one
+// launch; the same sums as launch_hodlr_update followed by launch_hodlr_dot
 bool hodlr_upd_dot_ok(long long N, long long nodesize_a, long long chunk_b);
 void launch_hodlr_upd_dot(const void* Y, int ra, const double2* sv, long long nodesize, int nodes, const void* W,
                           int rb, double2* z, long long N, double2* partial, long long chunk, hipStream_t s);

@@ -1343,8 +1343,9 @@ __global__ __launch_bounds__(256) void k_hodlr_update_wide(const typename V2<T>:
 // [1024 bx, 1024 bx + 1024).  Its threads first apply z -= Y s of level "a" to 4 rows each (the
 // arithmetic of k_hodlr_update_wide), keep the new rows in LDS and store them, then its waves
 // form the partial sums of W^T z over the 1024 / chunk chunks of those rows for the 4-column
-// groups of level "b" with the lane and row order of k_hodlr_dot_seg (chunk 256, 512 or 1024,
-// 64-lane segments): the same sums, bit for bit, without a second launch or a second read of z.
+// groups of level "b" with the lane and row order of k_hodlr_dot_seg (64-lane segments; the
+// library launches it for 1024-row chunks): the same sums, bit for bit, without a second launch
+// or a second read of z.
 template <int CH>
 __global__ __launch_bounds__(256) void k_hodlr_upd_dot(const BF2* __restrict__ Y, int ra,
                                                        const double2* __restrict__ sv, long long nodesize, int nodes,
@@ -1448,26 +1449,20 @@ __global__ __launch_bounds__(256) void k_hodlr_upd_dot(const BF2* __restrict__ Y
   }
 }
 
+// Fused only where the next level's chunks are 1024 rows: with shorter chunks the reduction phase
+// of one workgroup per 1024 rows has too few independent items per wave, and the two separate
+// launches (many workgroups each) are faster.
 bool hodlr_upd_dot_ok(long long N, long long nodesize_a, long long chunk_b) {
-  return N % 1024 == 0 && nodesize_a % 128 == 0 && (chunk_b == 256 || chunk_b == 512 || chunk_b == 1024);
+  return N % 1024 == 0 && nodesize_a % 128 == 0 && chunk_b == 1024;
 }
 
 void launch_hodlr_upd_dot(const void* Y, int ra, const double2* sv, long long nodesize, int nodes, const void* W,
                           int rb, double2* z, long long N, double2* partial, long long chunk, hipStream_t s) {
   const dim3 grid((unsigned)(N / 1024));
   const BF2 *Yb = (const BF2*)Y, *Wb = (const BF2*)W;
-  if (chunk == 1024) {
-    auto kern = k_hodlr_upd_dot<1024>;
-    LSK_LAUNCH(kern, grid, 256, 0, s, Yb, ra, sv, nodesize, nodes, Wb, rb, z, N, partial);
-  } else if (chunk == 512) {
-    auto kern = k_hodlr_upd_dot<512>;
-    LSK_LAUNCH(kern, grid, 256, 0, s, Yb, ra, sv, nodesize, nodes, Wb, rb, z, N, partial);
-  } else if (chunk == 256) {
-    auto kern = k_hodlr_upd_dot<256>;
-    LSK_LAUNCH(kern, grid, 256, 0, s, Yb, ra, sv, nodesize, nodes, Wb, rb, z, N, partial);
-  } else {
-    throw std::runtime_error("fused HODLR update/dot needs chunks of 256, 512 or 1024 rows");
-  }
+  if (chunk != 1024) throw std::runtime_error("fused HODLR update/dot needs chunks of 1024 rows");
+  auto kern = k_hodlr_upd_dot<1024>;
+  LSK_LAUNCH(kern, grid, 256, 0, s, Yb, ra, sv, nodesize, nodes, Wb, rb, z, N, partial);
 }
 
 bool launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
