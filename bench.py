@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--restart", type=int, default=500)
     ap.add_argument("--rank-div", type=int, default=4)
     ap.add_argument("--delta32", type=float, default=1e-4)
-    ap.add_argument("--graph-iters", type=int, default=8, help="Arnoldi steps per captured graph (0: host-driven)")
+    ap.add_argument("--graph-iters", type=int, default=2, help="Arnoldi steps per captured graph (0: host-driven)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false")
     ap.add_argument("--sample-every", type=int, default=7, help="time every k-th launch of a kernel class")
     ap.add_argument("--pc-bf16", type=int, default=1, help="bfloat16 HODLR factors in mixed solves (0: complex64)")
