@@ -198,7 +198,9 @@ def main():
     ap.add_argument("--restart", type=int, default=500)
     ap.add_argument("--rank-div", type=int, default=4)
     ap.add_argument("--delta32", type=float, default=1e-4)
-    ap.add_argument("--graph-iters", type=int, default=2, help="Arnoldi steps per captured graph (0: host-driven)")
+    ap.add_argument("--graph-iters", type=int, default=1, help="Arnoldi steps per captured graph (0: host-driven)")
+    ap.add_argument("--dcgs2", type=int, default=0,
+                    help="device-driven steps: 1 delayed CGS2 (one basis pass, stop test one step late), 0 CGS2")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false")
     ap.add_argument("--sample-every", type=int, default=7, help="time every k-th launch of a kernel class")
     ap.add_argument("--pc-bf16", type=int, default=1, help="bfloat16 HODLR factors in mixed solves (0: complex64)")
@@ -230,7 +232,7 @@ def main():
     P = ls.Problem(pb.points(), pb.q, kappa, 1e-10,
                    ls.Options(hodlr_rank=args.rank, hodlr_rank_div=args.rank_div, prec=ls.LS_MIXED,
                               eps_inner=1e-7, inner_tol=args.delta32, restart=args.restart, maxit=2000,
-                              graph_iters=args.graph_iters, pc_bf16=args.pc_bf16))
+                              graph_iters=args.graph_iters, pc_bf16=args.pc_bf16, dcgs2=args.dcgs2))
     tune = P.autotune() if args.autotune else None
     pc_fmt = "bf16" if args.pc_bf16 else "c64"
     t_setup = time.perf_counter() - t0
@@ -410,8 +412,9 @@ def main():
                    "contrast": "disc R=0.6 q=1", "eps_nca": 1e-10, "eps_inner": 1e-7, "hodlr_rank": r,
                    "tol": 1e-8, "nrhs": 1, "gmres_restart": args.restart, "hodlr_rank_div": args.rank_div,
                    "fp32_relax_delta": args.delta32, "hodlr_factors_mixed": pc_fmt,
-                   "gmres_driver": f"device-driven, {args.graph_iters} steps per graph" if args.graph_iters
-                   else "host-driven"},
+                   "gmres_driver": (f"device-driven {'delayed CGS2' if args.dcgs2 else 'CGS2'}, "
+                                    f"{args.graph_iters} step(s) per graph") if args.graph_iters
+                   else "host-driven CGS2"},
         "time_to_1e8_ms": {"mixed": round(ms_step, 3), "fp64": round(t_fp64 * 1e3, 3),
                            "mixed_graph_replay": None if ms_graph is None else round(ms_graph, 3)},
         "mixed_speedup_vs_fp64": round(t_fp64 * 1e3 / ms_step, 3),
@@ -435,7 +438,7 @@ def main():
         P2 = ls.Problem(pb.points(), pb.q, kappa, 1e-10,
                         ls.Options(hodlr_rank=args.tradeoff_rank, hodlr_rank_div=args.rank_div, prec=ls.LS_MIXED,
                                    eps_inner=1e-7, inner_tol=args.delta32, restart=args.restart, maxit=2000,
-                                   graph_iters=args.graph_iters, pc_bf16=args.pc_bf16))
+                                   graph_iters=args.graph_iters, pc_bf16=args.pc_bf16, dcgs2=args.dcgs2))
         if args.autotune:
             P2.autotune()
         t_setup2 = time.perf_counter() - t0
