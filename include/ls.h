@@ -82,8 +82,10 @@ typedef struct {
                          d > 0: rank min(hodlr_rank, child block size / d) per level */
   int graph_iters;    /* > 0: GMRES iterations run as device-driven Arnoldi steps (Arnoldi index,
                          Givens rotations and stop test on the device), captured into a HIP graph of
-                         this many iterations and replayed, one host synchronisation per replay;
-                         0: one host round trip per iteration (default 0) */
+                         this many iterations and replayed, one host synchronisation per replay
+                         (steps of the last replay after the stop test still run the operator and
+                         preconditioner launches, so solves of few, expensive iterations want small
+                         graphs); 0: one host round trip per iteration (default 0) */
   int stencil_mfma;   /* 1 (default): every DAFMM pass (near field, P2M, M2M, M2L, L2L, L2P) on the
                          matrix cores (16x16x4 MFMA); 0: the same sums on the vector ALUs */
   int pc_bf16;        /* 1 (default): also keep the HODLR off-diagonal factors in complex bfloat16 and
