@@ -101,6 +101,23 @@ def test_graph_driver_mixed_precision():
     assert abs(im[0]["iters"] - ih[0]["iters"]) <= 3
 
 
+def test_one_step_graphs_cgs2_high_rank_mixed():
+    # the bench's driver (device-driven CGS2, one Arnoldi step per captured graph) with a HODLR
+    # rank above 128 (SMW cores above 256 x 256): the mixed solve reaches the tolerance, equals the
+    # FP64 host-driven solve to 1e-6 and takes its iterations within one
+    n, kappa = 256, 80.0
+    pb = inputs.problem_bumps(n, kappa, seed=5, count=6)
+    A, B = pair(n, kappa, pb.q, hodlr_rank=160, hodlr_rank_div=4, restart=300, graph_iters_b=1, dcgs2=0)
+    f = A.rhs_planewave([0.3])
+    x64, i64 = A.solve(f, tol=1e-8, prec=ls.LS_FP64)
+    xm, im = B.solve(f, tol=1e-8, prec=ls.LS_MIXED)
+    xd, idd = B.solve(f, tol=1e-8, prec=ls.LS_FP64)
+    say("fp64 host", i64, "mixed one-step graphs", im, "fp64 one-step graphs", idd)
+    assert im[0]["status"] in ("CONVERGED", "REFINE_STAGNATED") and im[0]["relres"] <= 1e-8
+    assert rel(host(xm), host(x64)) < 1e-6
+    assert abs(idd[0]["iters"] - i64[0]["iters"]) <= 1 and rel(host(xd), host(x64)) < 1e-9
+
+
 @pytest.mark.parametrize("prec", [ls.LS_FP64, ls.LS_MIXED])
 def test_delayed_cgs2_matches_cgs2(prec):
     # delayed CGS2 (one reduction and one update pass per step) against two-pass CGS2 in the
