@@ -77,16 +77,21 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_disc512_k80.txt")  # 
 KERNELS_SRC = os.path.join(ROOT, "paper_2204_00326_amd", "csrc", "kernels.hip")
 # kernel names (before the argument list) of the classes the roofline may report
 # (the HBM-bound ones; the matrix-core stencil kernel serves every DAFMM pass under one name)
-COUNTED = {"hodlr_dot": "lsk::k_hodlr_dot_seg<lsk::bf16, 4, 4>", "hodlr_update": "lsk::k_hodlr_update_wide<lsk::bf16>",
-           "hodlr_upd_dot": "lsk::k_hodlr_upd_dot<"}
+COUNTED = {"hodlr_dot": ("lsk::k_hodlr_dot_seg<lsk::bf16, 4, 4>",),
+           "hodlr_update": ("lsk::k_hodlr_update_wide<lsk::bf16>", "lsk::k_hodlr_update_list<lsk::bf16>"),
+           "hodlr_upd_dot": ("lsk::k_hodlr_upd_dot<",)}
 
 
-def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok):
+def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok, act=1.0, listed=False):
     """Algorithmic HBM bytes per launch of the HODLR level kernels of one apply (one right-hand
     side), averaged over the launches of each class: a level's factor (N x r_l entries of fsz
     bytes) plus z (complex128) read, and z written by an update.  Mirrors the library's level
     plan: rank min(rank, child size / rank_div), chunks of at most max_rows rows, and an update
-    fused with the next level's dot where that level's chunks are 1024 rows."""
+    fused with the next level's dot where that level's chunks are 1024 rows.  act: the fraction
+    of rows in 256-row blocks with contrast; an update reads Y and writes z only there (the
+    other rows of Y are zero).  listed: the library runs the updates over the listed blocks only
+    (z read there too) and fuses none; the last update, which also stores z~ for flexible GMRES,
+    reads all of z and writes the copy."""
     ranks = [max(1, min(rank, (N >> (l + 1)) // rank_div)) if rank_div > 0 else rank for l in range(levels)]
     def chunk(l):
         ch = N >> (l + 1)
@@ -94,16 +99,18 @@ def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok):
             ch //= 2
         return ch
     cls = {"hodlr_dot": [], "hodlr_update": [], "hodlr_upd_dot": []}
+    upd = (lambda ra: act * N * ra * fsz + 2 * act * N * 16) if listed else \
+          (lambda ra: act * N * ra * fsz + (1 + act) * N * 16)
     pend = -1
     for l in range(levels - 1, -1, -1):
-        if pend >= 0 and fused_ok and N % 1024 == 0 and (N >> pend) % 128 == 0 and chunk(l) == 1024:
-            cls["hodlr_upd_dot"].append(N * (ranks[pend] + ranks[l]) * fsz + 2 * N * 16)
+        if pend >= 0 and fused_ok and not listed and N % 1024 == 0 and (N >> pend) % 128 == 0 and chunk(l) == 1024:
+            cls["hodlr_upd_dot"].append(N * (act * ranks[pend] + ranks[l]) * fsz + (1 + act) * N * 16)
         else:
             if pend >= 0:
-                cls["hodlr_update"].append(N * ranks[pend] * fsz + 2 * N * 16)
+                cls["hodlr_update"].append(upd(ranks[pend]))
             cls["hodlr_dot"].append(N * ranks[l] * fsz + N * 16)
         pend = l
-    cls["hodlr_update"].append(N * ranks[pend] * fsz + 2 * N * 16)
+    cls["hodlr_update"].append(act * N * ranks[pend] * fsz + (2 + act) * N * 16)
     # SMW core products: the complex128 core inverses (2^l nodes of (2 r_l)^2), the chunk
     # partials of W^T z read once, s written
     cls["hodlr_core"] = [(1 << l) * (2 * ranks[l]) ** 2 * 16 + (N // chunk(l)) * ranks[l] * 16
@@ -145,17 +152,16 @@ def pmc_summary(fetch_csv, write_csv, cmd_fetch, cmd_write, workload):
     f_write = COPY_BYTES / 1024.0 / copy_val(write)
     res = {"source_sha256": _sha256(KERNELS_SRC), "workload": workload, "copy_bytes": COPY_BYTES,
            "scale": {"FETCH_SIZE": f_fetch, "WRITE_SIZE": f_write}, "commands": [cmd_fetch, cmd_write], "kernels": {}}
-    for cls, prefix in COUNTED.items():
-        hit = lambda name: (prefix in name) if prefix.endswith("<") else (prefix + "(" in name)
-        fv = [v for name, vs in fetch.items() if hit(name) for v in vs]
-        wv = [v for name, vs in write.items() if hit(name) for v in vs]
+    for cls, prefixes in COUNTED.items():
+        hit = lambda name: any((p in name) if p.endswith("<") else (p + "(" in name) for p in prefixes)
+        # per kernel, the last 80 % of its dispatches: the timed solves, past the autotuner's trials
+        fv = [v for name, vs in fetch.items() if hit(name) for v in vs[len(vs) // 5:]]
+        wv = [v for name, vs in write.items() if hit(name) for v in vs[len(vs) // 5:]]
         if not fv or not wv:
             continue
-        # the last 80 % of the dispatches: the timed solves, past the autotuner's trial shapes
-        fv, wv = fv[len(fv) // 5:], wv[len(wv) // 5:]
         fk, wk = sum(fv) / len(fv), sum(wv) / len(wv)
-        res["kernels"][cls] = {"kernel": prefix, "dispatches": len(fv), "fetch_kib": fk, "write_kib": wk,
-                               "hbm_bytes_per_launch": (fk * f_fetch + wk * f_write) * 1024.0}
+        res["kernels"][cls] = {"kernel": " + ".join(prefixes), "dispatches": len(fv), "fetch_kib": fk,
+                               "write_kib": wk, "hbm_bytes_per_launch": (fk * f_fetch + wk * f_write) * 1024.0}
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(res, fh, indent=1)
@@ -346,8 +352,10 @@ def main():
     r = args.rank
     lb = st["hodlr_levels"]
     fsz = {"bf16": 4, "c64": 8}[pc_fmt]   # bytes per stored HODLR factor entry in mixed solves
+    act = st["hodlr_rows_active"] / N
+    listed = N % 256 == 0 and st["hodlr_rows_active"] * 4 < 3 * N   # the library's rule
     hb = hodlr_launch_bytes(N, lb, args.rank, args.rank_div, tune["hodlr_rows"] if tune else 1024, fsz,
-                            pc_fmt == "bf16")
+                            pc_fmt == "bf16", act, listed)
     per_launch = {
         # flops of one near-field + M2L launch (8 real flops per complex multiply-add), matrix cores
         "near_m2l64": ("mfma", "f64", 8.0 * (st["entries_near"] + st["entries_m2l64"]) / 1e12),
@@ -378,7 +386,8 @@ def main():
     tot_ms, launches, all_launches = cand[dom]
     roof["kernel"] = {"near_m2l64": "k_stencil_mfma<double> (near field + M2L launch)",
                       "near_m2l32": "k_stencil_mfma<float> (near field + M2L launch)",
-                      "hodlr_update": f"k_hodlr_update_wide<{'bf16' if args.pc_bf16 else 'float'}>",
+                      "hodlr_update": f"k_hodlr_update_list / k_hodlr_update_wide<{'bf16' if args.pc_bf16 else 'float'}> "
+                                      "(HODLR z -= Y s)",
                       "hodlr_dot": f"k_hodlr_dot_seg<{'bf16, 4' if args.pc_bf16 else 'float, 2'}> (HODLR W^T z)",
                       "hodlr_upd_dot": "k_hodlr_upd_dot<1024> (HODLR z -= Y s fused with the next level's W^T z)",
                       "hodlr_core": "k_hodlr_core_rows (HODLR SMW core products s = K^-1 t)"}[dom]
@@ -412,6 +421,7 @@ def main():
                    "contrast": "disc R=0.6 q=1", "eps_nca": 1e-10, "eps_inner": 1e-7, "hodlr_rank": r,
                    "tol": 1e-8, "nrhs": 1, "gmres_restart": args.restart, "hodlr_rank_div": args.rank_div,
                    "fp32_relax_delta": args.delta32, "hodlr_factors_mixed": pc_fmt,
+                   "hodlr_update_rows_active": round(act, 4),
                    "gmres_driver": (f"device-driven {'delayed CGS2' if args.dcgs2 else 'CGS2'}, "
                                     f"{args.graph_iters} step(s) per graph") if args.graph_iters
                    else "host-driven CGS2"},

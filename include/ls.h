@@ -149,6 +149,10 @@ typedef struct {
   /* parts of t_hodlr_ms: off-diagonal ACA; the applies of the finer levels that form
    * Y = D^-1 U (device); forming, inverting (host) and uploading the SMW cores */
   double t_hodlr_aca_ms, t_hodlr_apply_ms, t_hodlr_cores_ms;
+  /* rows in 256-row blocks (solver order) that hold a point with contrast; the HODLR level
+   * updates skip the other blocks (points without contrast are identity rows of A, so the
+   * matching rows of the preconditioner factors Y = D^-1 U are zero) */
+  int64_t hodlr_rows_active;
 } ls_stats_t;
 
 /* Plan description for a uniform n x n grid on [-L, L]^2 (host only, no device use).

@@ -175,6 +175,12 @@ struct HodlrDev {
   int64_t used_rank_sum = 0, blocks = 0;  // ACA ranks reached, over all off-diagonal blocks
   int used_rank_max = 0;
   double t_aca_ms = 0, t_apply_ms = 0, t_cores_ms = 0;  // setup phases
+  // one byte per 256 Morton rows: 0 where no point of the block has contrast (Y's rows are zero)
+  DevBuf ract;
+  int64_t rows_active = 0;
+  DevBuf alist;          // indices of the 256-row blocks with contrast
+  int nact = 0;
+  bool sparse = false;   // few enough such blocks that updates run over the list alone
   DevBuf partial, svec;
   std::vector<long long> chunk;  // per level
   std::vector<int> nchunks, cpc;
@@ -793,18 +799,24 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
   auto update = [&](int a, bool last) {
     const void* Y = fmt == 2 ? H.Y16[a].p : (fmt == 1 ? H.Y32[a].p : H.Y64[a].p);
     ProfScope ps(P, 1, s);
+    if (H.sparse && nrhs == 1 && fmt >= 1 && !(last && zcopy)) {
+      lsk::launch_hodlr_update_list(fmt, Y, H.svec.as<double2>(), z, H.N, H.rank[a], H.N >> a, H.alist.as<int>(),
+                                    H.nact, s);
+      copied = false;
+      return;
+    }
     copied = lsk::launch_hodlr_update(fmt, Y, H.svec.as<double2>(), z, ldz, H.N, H.rank[a], H.N >> a, 1 << a, nrhs,
-                                      s, last ? zcopy : nullptr, zldr, jdev, zldj);
+                                      s, last ? zcopy : nullptr, zldr, jdev, zldj, H.ract.as<unsigned char>());
   };
   for (int l = H.Lb - 1; l >= lstop; --l) {
     const void* W = fmt == 2 ? H.W16[l].p : (fmt == 1 ? H.W32[l].p : H.W64[l].p);
     int nodes = 1 << l;
     const int rl = H.rank[l];
     if (rl == 0) continue;
-    if (pend >= 0 && fmt == 2 && nrhs == 1 && lsk::hodlr_upd_dot_ok(H.N, H.N >> pend, H.chunk[l])) {
+    if (pend >= 0 && fmt == 2 && nrhs == 1 && !H.sparse && lsk::hodlr_upd_dot_ok(H.N, H.N >> pend, H.chunk[l])) {
       ProfScope pf(P, 6, s);
       lsk::launch_hodlr_upd_dot(H.Y16[pend].p, H.rank[pend], H.svec.as<double2>(), H.N >> pend, 1 << pend, W, rl, z,
-                                H.N, H.partial.as<double2>(), H.chunk[l], s);
+                                H.N, H.partial.as<double2>(), H.chunk[l], s, H.ract.as<unsigned char>());
     } else {
       if (pend >= 0) update(pend, false);
       ProfScope pd(P, 5, s);
@@ -895,6 +907,23 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     }
     H.ident.upload(ident);
     H.dense_leaves = (int64_t)dense.size();
+    // rows without contrast are identity rows of A, so the same rows of every Y = D^-1 U are zero
+    std::vector<unsigned char> ract((size_t)((N + 255) / 256), 0);
+    for (long long i = 0; i < N; ++i)
+      if (qm[i] != 0.0) ract[(size_t)(i >> 8)] = 1;
+    H.rows_active = 0;
+    std::vector<int> alist;
+    for (size_t b = 0; b < ract.size(); ++b)
+      if (ract[b]) {
+        H.rows_active += std::min<long long>(256, N - (long long)b * 256);
+        alist.push_back((int)b);
+      }
+    H.ract.upload(ract);
+    H.alist.upload(alist);
+    H.nact = (int)alist.size();
+    // below three quarters of the rows, single-column updates run over the listed blocks (all
+    // threads on rows that change) instead of inside the fused update + W^T z launch
+    H.sparse = N % 256 == 0 && H.rows_active * 4 < N * 3;
     H.bytes = (int64_t)H.nleaves * lp * lp * 16;
   }
   hodlr_chunks(H, P->tune.hodlr_rows);
@@ -1047,6 +1076,8 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     double2* Y = H.Y64[l].as<double2>();
     const double ta = now_ms();
     hodlr_apply(P, 0, Y, N, Y, N, r, l + 1, s);
+    // exact zeros where the point has no contrast (the apply kernels skip those rows)
+    lsk::launch_zero_rows(Y, N, r, P->q_m.as<double>(), s);
     int nodes = 1 << l;
     lsk::launch_hodlr_dot(0, H.W64[l].p, Y, N, H.partial.as<double2>(), N, r, H.chunk[l], H.nchunks[l], r, s);
     lsk::launch_hodlr_core(0, nullptr, H.partial.as<double2>(), H.svec.as<double2>(), r, nodes, H.cpc[l],
@@ -2049,6 +2080,7 @@ ls_status ls_setup(const double* points, int64_t N, const double* q, double kapp
     S.hodlr_rank_used_sum = P->have_hodlr ? P->hod.used_rank_sum : 0;
     S.hodlr_blocks = P->have_hodlr ? P->hod.blocks : 0;
     S.hodlr_rank_used_max = P->have_hodlr ? P->hod.used_rank_max : 0;
+    S.hodlr_rows_active = P->have_hodlr ? P->hod.rows_active : 0;
     S.t_hodlr_aca_ms = P->hod.t_aca_ms;
     S.t_hodlr_apply_ms = P->hod.t_apply_ms;
     S.t_hodlr_cores_ms = P->hod.t_cores_ms;

@@ -41,6 +41,8 @@ void launch_core_invert(const double2* t, int r, int nodes, double2* A, double2*
 void launch_leaf_invert(const double2* W, int n_grid, const int* ma, const int* mb, const double* q, double coef,
                         int lp, const int* leaves, int nleaves, double2* A, double2* B, double2* Dinv, int* bad,
                         hipStream_t s);
+// Y[c][i] = 0 for every column c where q[i] == 0 (Y: N x r column-major)
+void launch_zero_rows(double2* Y, long long N, int r, const double* q, hipStream_t s);
 // identity blocks at the listed leaves of Dinv
 void launch_leaf_identity(const int* leaves, int nleaves, int lp, double2* Dinv, hipStream_t s);
 

@@ -491,6 +491,18 @@ void launch_core_invert(const double2* t, int r, int nodes, double2* A, double2*
   k_core_assemble<<<nodes, 256, 0, s>>>(Si, P, Q, TL, r, out);
 }
 
+// rows of a factor (N x r, column-major) that belong to points without contrast set to zero
+__global__ __launch_bounds__(256) void k_zero_rows(double2* __restrict__ Y, long long N, int r,
+                                                   const double* __restrict__ q) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= N || q[i] != 0.0) return;
+  for (int c = 0; c < r; ++c) Y[(long long)c * N + i] = make_double2(0.0, 0.0);
+}
+
+void launch_zero_rows(double2* Y, long long N, int r, const double* q, hipStream_t s) {
+  if (N > 0 && r > 0) k_zero_rows<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(Y, N, r, q);
+}
+
 void launch_aca_start(const AcaLevel& L, hipStream_t s) { k_aca_start<<<L.nb, 256, 0, s>>>(L); }
 
 void launch_aca_row(const AcaLevel& L, hipStream_t s) {

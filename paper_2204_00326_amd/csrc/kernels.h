@@ -82,7 +82,8 @@ void launch_leaf_apply(int dfmt, const void* Dinv, const unsigned char* ident, c
 // launch; the same sums as launch_hodlr_update followed by launch_hodlr_dot
 bool hodlr_upd_dot_ok(long long N, long long nodesize_a, long long chunk_b);
 void launch_hodlr_upd_dot(const void* Y, int ra, const double2* sv, long long nodesize, int nodes, const void* W,
-                          int rb, double2* z, long long N, double2* partial, long long chunk, hipStream_t s);
+                          int rb, double2* z, long long N, double2* partial, long long chunk, hipStream_t s,
+                          const unsigned char* ract = nullptr);
 void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
                       long long chunk, int nchunks, int nrhs, hipStream_t s);
 // cfmt: storage of the core inverses, 0 complex128, 1 complex64, 2 complex bfloat16 (r <= 256),
@@ -93,9 +94,16 @@ void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, do
                        int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s);
 // z -= Y s per level.  z2 != NULL asks for a copy of the result in column *jdev of a basis
 // (z2 + rhs*z2ldr + *jdev*z2ldj); returns whether the launch made it (the caller copies otherwise)
+// z -= Y s, one right-hand side, complex64 (fmt 1) or complex bfloat16 (fmt 2) factors, only on the
+// nact listed 256-row blocks (blist: block indices; the rows of Y outside them are zero)
+void launch_hodlr_update_list(int fmt, const void* Y, const double2* sv, double2* z, long long N, int r,
+                              long long nodesize, const int* blist, int nact, hipStream_t s);
+// ract (may be NULL): one byte per 256 rows, 0 where no row of the block has contrast (Y's rows are
+// zero there; the wide kernels then leave those rows of z untouched and read no Y)
 bool launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
                          long long nodesize, int nodes, int nrhs, hipStream_t s, double2* z2 = nullptr,
-                         long long z2ldr = 0, const int* jdev = nullptr, long long z2ldj = 0);
+                         long long z2ldr = 0, const int* jdev = nullptr, long long z2ldj = 0,
+                         const unsigned char* ract = nullptr);
 
 // ---- Krylov vector kernels (complex128) ----
 void launch_gs_dot(const double2* Q, long long ldq_vec, long long ldq_rhs, int nv, const double2* w, long long ldw,

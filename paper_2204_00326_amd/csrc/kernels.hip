@@ -1292,19 +1292,22 @@ __global__ __launch_bounds__(256) void k_hodlr_update_wide(const typename V2<T>:
                                                            long long ldz, long long N, int r, long long nodesize,
                                                            int nodes, int nrf, double2* __restrict__ z2,
                                                            long long z2ldr, const int* __restrict__ jdev,
-                                                           long long z2ldj) {
+                                                           long long z2ldj, const unsigned char* __restrict__ ract) {
   constexpr int R = 16 / (int)sizeof(typename V2<T>::type);
   const long long bx = nrf ? blockIdx.x / nrf : blockIdx.x;
   const int rhs = nrf ? blockIdx.x % nrf : blockIdx.y;
   const long long i = (bx * blockDim.x + threadIdx.x) * R;
   if (i >= N) return;
+  // a wave's 64 R rows lie in one 256-row block (N is a multiple of 128): rows without contrast
+  // have zero rows of Y, so such a wave leaves z as it is and reads no Y
+  const bool act = !ract || ract[__builtin_amdgcn_readfirstlane((int)(i >> 8))] != 0;
   const long long node = i / nodesize;
   const int half = (i - node * nodesize) >= (nodesize >> 1) ? 1 : 0;
   const double2* s = sv + ((long long)rhs * nodes + node) * 2 * r + half * r;
   double re[R], im[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) re[q] = im[q] = 0;
-  for (int c0 = 0; c0 < r; c0 += 8) {
+  for (int c0 = 0; act && c0 < r; c0 += 8) {
     Pack<T, R> y[8];
     double2 x[8];
 #pragma unroll
@@ -1332,9 +1335,11 @@ __global__ __launch_bounds__(256) void k_hodlr_update_wide(const typename V2<T>:
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     double2 o = z[rhs * ldz + i + q];
-    o.x -= re[q];
-    o.y -= im[q];
-    z[rhs * ldz + i + q] = o;
+    if (act) {
+      o.x -= re[q];
+      o.y -= im[q];
+      z[rhs * ldz + i + q] = o;
+    }
     if (zc) zc[i + q] = o;
   }
 }
@@ -1350,7 +1355,8 @@ template <int CH>
 __global__ __launch_bounds__(256) void k_hodlr_upd_dot(const BF2* __restrict__ Y, int ra,
                                                        const double2* __restrict__ sv, long long nodesize, int nodes,
                                                        const BF2* __restrict__ W, int rb, double2* __restrict__ z,
-                                                       long long N, double2* __restrict__ partial) {
+                                                       long long N, double2* __restrict__ partial,
+                                                       const unsigned char* __restrict__ ract) {
   constexpr int chunk = CH, NS = CH / 256;  // rows per chunk, steps per lane
   constexpr int R = 4, G = 4;
   __shared__ double2 zs[1024];
@@ -1358,13 +1364,16 @@ __global__ __launch_bounds__(256) void k_hodlr_upd_dot(const BF2* __restrict__ Y
   const int t = threadIdx.x;
   {
     const long long i = bx * 1024 + (long long)t * R;
+    // a wave's 256 rows: rows without contrast have zero rows of Y, so a wave whose rows all
+    // lack contrast leaves z as it is and reads no Y
+    const bool act = !ract || ract[__builtin_amdgcn_readfirstlane((int)(i >> 8))] != 0;
     const long long node = i / nodesize;
     const int half = (i - node * nodesize) >= (nodesize >> 1) ? 1 : 0;
     const double2* s = sv + node * 2 * ra + half * ra;
     double re[R], im[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) re[q] = im[q] = 0;
-    for (int c0 = 0; c0 < ra; c0 += 8) {
+    for (int c0 = 0; act && c0 < ra; c0 += 8) {
       Pack<bf16, R> y[8];
       double2 x[8];
 #pragma unroll
@@ -1390,9 +1399,11 @@ __global__ __launch_bounds__(256) void k_hodlr_upd_dot(const BF2* __restrict__ Y
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       double2 o = z[i + q];
-      o.x -= re[q];
-      o.y -= im[q];
-      z[i + q] = o;
+      if (act) {
+        o.x -= re[q];
+        o.y -= im[q];
+        z[i + q] = o;
+      }
       zs[t * R + q] = o;
     }
   }
@@ -1457,17 +1468,96 @@ bool hodlr_upd_dot_ok(long long N, long long nodesize_a, long long chunk_b) {
 }
 
 void launch_hodlr_upd_dot(const void* Y, int ra, const double2* sv, long long nodesize, int nodes, const void* W,
-                          int rb, double2* z, long long N, double2* partial, long long chunk, hipStream_t s) {
+                          int rb, double2* z, long long N, double2* partial, long long chunk, hipStream_t s,
+                          const unsigned char* ract) {
   const dim3 grid((unsigned)(N / 1024));
   const BF2 *Yb = (const BF2*)Y, *Wb = (const BF2*)W;
   if (chunk != 1024) throw std::runtime_error("fused HODLR update/dot needs chunks of 1024 rows");
   auto kern = k_hodlr_upd_dot<1024>;
-  LSK_LAUNCH(kern, grid, 256, 0, s, Yb, ra, sv, nodesize, nodes, Wb, rb, z, N, partial);
+  LSK_LAUNCH(kern, grid, 256, 0, s, Yb, ra, sv, nodesize, nodes, Wb, rb, z, N, partial, ract);
+}
+
+// One right-hand side, only the listed 256-row blocks (those with contrast; the other rows of Y
+// are zero), one block per workgroup: its four waves take a quarter of the columns each over all
+// 256 rows (R rows per lane, 16-byte loads), and the four partial sums of a row are added in
+// wave order through LDS before z is updated.  All threads of the launch work on rows that
+// change, and a wave's chain of loads is a quarter as long as in the row-per-thread kernels.
+template <typename T>
+__global__ __launch_bounds__(256) void k_hodlr_update_list(const typename V2<T>::type* __restrict__ Y,
+                                                           const double2* __restrict__ sv, double2* __restrict__ z,
+                                                           long long N, int r, long long nodesize,
+                                                           const int* __restrict__ blist, int nact) {
+  constexpr int R = 16 / (int)sizeof(typename V2<T>::type);
+  constexpr int LR = 64 * R;  // rows of one pass of a wave
+  __shared__ double2 part[4][256];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long b0 = (long long)blist[blockIdx.x] * 256;
+  const int cw = (r + 3) / 4, c_lo = w * cw, c_hi = c_lo + cw < r ? c_lo + cw : r;
+  for (int pass = 0; pass < 256 / LR; ++pass) {
+    const int lr = pass * LR + lane * R;  // row in the block
+    long long i = b0 + lr;
+    if (i > N - R) i = N - R;            // a clipped last block: in-bounds loads, rows not written
+    const long long node = i / nodesize;
+    const int half = (i - node * nodesize) >= (nodesize >> 1) ? 1 : 0;
+    const double2* s = sv + node * 2 * r + half * r;
+    double re[R], im[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) re[q] = im[q] = 0;
+    for (int c0 = c_lo; c0 < c_hi; c0 += 8) {
+      Pack<T, R> y[8];
+      double2 x[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int cc = c0 + c < c_hi ? c0 + c : c_hi - 1;
+        y[c] = *reinterpret_cast<const Pack<T, R>*>(Y + (long long)cc * N + i);
+        x[c] = s[cc];
+        if (c0 + c >= c_hi) x[c] = make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const double2 yv = to_d2(y[c].v[q]);
+          re[q] = fma(yv.x, x[c].x, re[q]);
+          re[q] = fma(-yv.y, x[c].y, re[q]);
+          im[q] = fma(yv.x, x[c].y, im[q]);
+          im[q] = fma(yv.y, x[c].x, im[q]);
+        }
+      __builtin_amdgcn_sched_group_barrier(0x0020, 16, 0);
+      __builtin_amdgcn_sched_group_barrier(0x0002, 32 * R, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) part[w][lr + q] = make_double2(re[q], im[q]);
+  }
+  __syncthreads();
+  const long long i = b0 + threadIdx.x;
+  if (i >= N) return;
+  const double2 p0 = part[0][threadIdx.x], p1 = part[1][threadIdx.x], p2 = part[2][threadIdx.x],
+                p3 = part[3][threadIdx.x];
+  double2 o = z[i];
+  o.x -= ((p0.x + p1.x) + p2.x) + p3.x;
+  o.y -= ((p0.y + p1.y) + p2.y) + p3.y;
+  z[i] = o;
+}
+
+void launch_hodlr_update_list(int fmt, const void* Y, const double2* sv, double2* z, long long N, int r,
+                              long long nodesize, const int* blist, int nact, hipStream_t s) {
+  if (nact <= 0) return;
+  if (N < 4) throw std::runtime_error("listed HODLR update needs N >= 4");
+  if (fmt == 2) {
+    auto kern = k_hodlr_update_list<bf16>;
+    LSK_LAUNCH(kern, dim3((unsigned)nact), 256, 0, s, (const BF2*)Y, sv, z, N, r, nodesize, blist, nact);
+  } else if (fmt == 1) {
+    auto kern = k_hodlr_update_list<float>;
+    LSK_LAUNCH(kern, dim3((unsigned)nact), 256, 0, s, (const float2*)Y, sv, z, N, r, nodesize, blist, nact);
+  } else {
+    throw std::runtime_error("listed HODLR update needs complex64 or complex bfloat16 factors");
+  }
 }
 
 bool launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
                          long long nodesize, int nodes, int nrhs, hipStream_t s, double2* z2, long long z2ldr,
-                         const int* jdev, long long z2ldj) {
+                         const int* jdev, long long z2ldj, const unsigned char* ract) {
   if (fmt != 0 && N % 64 == 0 && nodesize % 128 == 0) {
     const int R = fmt == 2 ? 4 : 2;
     const unsigned nbx = (unsigned)((N / R + 255) / 256);
@@ -1476,11 +1566,11 @@ bool launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, 
     if (fmt == 2) {
       auto kern = k_hodlr_update_wide<bf16>;
       LSK_LAUNCH(kern, gridw, 256, 0, s, (const BF2*)Y, sv, z, ldz, N, r, nodesize, nodes, nrf, z2, z2ldr, jdev,
-                 z2ldj);
+                 z2ldj, ract);
     } else {
       auto kern = k_hodlr_update_wide<float>;
       LSK_LAUNCH(kern, gridw, 256, 0, s, (const float2*)Y, sv, z, ldz, N, r, nodesize, nodes, nrf, z2, z2ldr, jdev,
-                 z2ldj);
+                 z2ldj, ract);
     }
     return z2 != nullptr;
   }

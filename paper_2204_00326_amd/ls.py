@@ -52,7 +52,8 @@ class _Stats(C.Structure):
                 ("hodlr_dense_leaves", C.c_int64), ("t_plan_ms", C.c_double), ("t_nca_ms", C.c_double),
                 ("t_hodlr_ms", C.c_double), ("t_setup_ms", C.c_double),
                 ("hodlr_rank_used_sum", C.c_int64), ("hodlr_blocks", C.c_int64), ("hodlr_rank_used_max", C.c_int),
-                ("t_hodlr_aca_ms", C.c_double), ("t_hodlr_apply_ms", C.c_double), ("t_hodlr_cores_ms", C.c_double)]
+                ("t_hodlr_aca_ms", C.c_double), ("t_hodlr_apply_ms", C.c_double), ("t_hodlr_cores_ms", C.c_double),
+                ("hodlr_rows_active", C.c_int64)]
 
 
 class _PlanInfo(C.Structure):

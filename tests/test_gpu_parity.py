@@ -155,6 +155,38 @@ def test_precond_matches_oracle_hodlr(n, kappa, rank, kind):
     assert rel(z32, zref) < 1e-4
 
 
+def test_sparse_contrast_updates_match_oracle():
+    # a disc of radius 0.3 leaves three quarters of the 256-row blocks without contrast: the level
+    # updates then run over the listed blocks only (complex64 and bfloat16 factors); the rows of Y
+    # they skip are zero, so the applies still match the oracle HODLR and the solve the FP64 one
+    n, kappa, rank = 64, 20.0, 12
+    x = inputs.grid_points(n)
+    q = (np.hypot(x[:, 0], x[:, 1]) < 0.3).astype(float)
+    P = problem("smalldisc64", n, kappa, q, hodlr_rank=rank)
+    st = P.stats()
+    assert st["hodlr_rows_active"] * 4 < 3 * n * n
+    side = st["leaf_side"]
+    A = lsop.dense_A(n, 1.0, kappa, q, -1)
+    perm = ohodlr.morton_permutation(n, side)
+    H = ohodlr.HODLR(A[np.ix_(perm, perm)], side * side, rank)
+    b = inputs.random_vector(n * n, seed=23)
+    zref = np.empty_like(b)
+    zref[perm] = H.solve(b[perm])
+    z64 = host(P.precond_apply(dev(b)))
+    z32 = host(P.precond_apply(dev(b), prec=ls.LS_FP32))
+    zm = host(P.precond_apply(dev(b), prec=ls.LS_MIXED))
+    say("sparse contrast: rows active", st["hodlr_rows_active"], rel(z64, zref), rel(z32, zref), rel(zm, zref))
+    assert rel(z64, zref) < 1e-9
+    assert rel(z32, zref) < 1e-5
+    assert rel(zm, zref) < 2e-2
+    f = P.rhs_planewave([0.7])
+    x64, i64 = P.solve(f, tol=1e-10, prec=ls.LS_FP64)
+    xm, im = P.solve(f, tol=1e-8, prec=ls.LS_MIXED)
+    assert i64[0]["status"] == "CONVERGED" and im[0]["relres"] <= 1e-8
+    assert rel(host(xm), host(x64)) < 1e-6
+    assert rel(host(x64), np.linalg.solve(A, host(f)[0] if host(f).ndim > 1 else host(f))) < 1e-6
+
+
 def test_precond_full_rank_is_inverse():
     n, kappa = 8, 6.0
     q = inputs.contrast_gaussian(inputs.grid_points(n), 1.5, 10.0)
