@@ -77,7 +77,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_disc512_k80.txt")  # 
 KERNELS_SRC = os.path.join(ROOT, "paper_2204_00326_amd", "csrc", "kernels.hip")
 # kernel names (before the argument list) of the classes the roofline may report
 # (the HBM-bound ones; the matrix-core stencil kernel serves every DAFMM pass under one name)
-COUNTED = {"hodlr_dot": ("lsk::k_hodlr_dot_seg<lsk::bf16, 4, 4>",),
+COUNTED = {"hodlr_dot": ("lsk::k_hodlr_dot_seg<lsk::bf16, 4, 8>",),
            "hodlr_update": ("lsk::k_hodlr_update_wide<lsk::bf16>", "lsk::k_hodlr_update_list<lsk::bf16>"),
            "hodlr_upd_dot": ("lsk::k_hodlr_upd_dot<",)}
 

@@ -925,7 +925,7 @@ __global__ __launch_bounds__(256) void k_hodlr_dot_rb(const double2* __restrict_
         partial[((long long)(rb0 + b) * nchunks + ch) * r + c0 + c] = make_double2(acc[c][b][0], acc[c][b][1]);
 }
 
-constexpr int kDotCols = 4;  // columns per segment (4 measured fastest of 4 / 8 / 16)
+constexpr int kDotCols = 8;  // columns per segment
 template <typename T, int R>
 static void hodlr_dot_seg(const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
                           long long chunk, int nchunks, int nrhs, hipStream_t s) {
@@ -949,7 +949,7 @@ static void hodlr_dot_fmt(const void* W, const double2* z, long long ldz, double
                           long long chunk, int nchunks, int nrhs, hipStream_t s) {
   constexpr int RW = 16 / (int)sizeof(typename V2<T>::type);
   if (RW == 1 && nrhs >= 8) {  // complex128 factors, many right-hand sides
-    constexpr int G = kDotCols, RB = 8;
+    constexpr int G = 4, RB = 8;
     int lc = 64;
     while (lc > chunk) lc >>= 1;
     const int per_wg = 4 * (64 / lc);
