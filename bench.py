@@ -82,7 +82,8 @@ COUNTED = {"hodlr_dot": ("lsk::k_hodlr_dot_seg<lsk::bf16, 4, 8>",),
            "hodlr_upd_dot": ("lsk::k_hodlr_upd_dot<",)}
 
 
-def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok, act=1.0, listed=False):
+def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok, act=1.0, listed=False, dot_rows=None,
+                       core_nodes=None):
     """Algorithmic HBM bytes per launch of the HODLR level kernels of one apply (one right-hand
     side), averaged over the launches of each class: a level's factor (N x r_l entries of fsz
     bytes) plus z (complex128) read, and z written by an update.  Mirrors the library's level
@@ -91,7 +92,9 @@ def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok, act=1
     of rows in 256-row blocks with contrast; an update reads Y and writes z only there (the
     other rows of Y are zero).  listed: the library runs the updates over the listed blocks only
     (z read there too) and fuses none; the last update, which also stores z~ for flexible GMRES,
-    reads all of z and writes the copy."""
+    reads all of z and writes the copy.  dot_rows / core_nodes (per level, from the library's
+    statistics): the rows whose W^T z an unfused dot forms and the nodes whose K^-1 block is read
+    (the others meet a zero Y: a child without contrast)."""
     ranks = [max(1, min(rank, (N >> (l + 1)) // rank_div)) if rank_div > 0 else rank for l in range(levels)]
     def chunk(l):
         ch = N >> (l + 1)
@@ -108,12 +111,14 @@ def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok, act=1
         else:
             if pend >= 0:
                 cls["hodlr_update"].append(upd(ranks[pend]))
-            cls["hodlr_dot"].append(N * ranks[l] * fsz + N * 16)
+            rows = dot_rows[l] if dot_rows else N
+            cls["hodlr_dot"].append(rows * ranks[l] * fsz + rows * 16)
         pend = l
     cls["hodlr_update"].append(act * N * ranks[pend] * fsz + (2 + act) * N * 16)
     # SMW core products: the complex128 core inverses (2^l nodes of (2 r_l)^2), the chunk
     # partials of W^T z read once, s written
-    cls["hodlr_core"] = [(1 << l) * (2 * ranks[l]) ** 2 * 16 + (N // chunk(l)) * ranks[l] * 16
+    cls["hodlr_core"] = [(core_nodes[l] if core_nodes else 1 << l) * (2 * ranks[l]) ** 2 * 16
+                         + (N // chunk(l)) * ranks[l] * 16
                          + (1 << l) * 2 * ranks[l] * 16 for l in range(levels)]
     return {c: sum(v) / len(v) / 1e9 for c, v in cls.items() if v}
 
@@ -355,7 +360,7 @@ def main():
     act = st["hodlr_rows_active"] / N
     listed = N % 256 == 0 and st["hodlr_rows_active"] * 4 < 3 * N   # the library's rule
     hb = hodlr_launch_bytes(N, lb, args.rank, args.rank_div, tune["hodlr_rows"] if tune else 1024, fsz,
-                            pc_fmt == "bf16", act, listed)
+                            pc_fmt == "bf16", act, listed, st["hodlr_dot_rows"][:lb], st["hodlr_core_nodes"][:lb])
     per_launch = {
         # flops of one near-field + M2L launch (8 real flops per complex multiply-add), matrix cores
         "near_m2l64": ("mfma", "f64", 8.0 * (st["entries_near"] + st["entries_m2l64"]) / 1e12),
@@ -422,6 +427,9 @@ def main():
                    "tol": 1e-8, "nrhs": 1, "gmres_restart": args.restart, "hodlr_rank_div": args.rank_div,
                    "fp32_relax_delta": args.delta32, "hodlr_factors_mixed": pc_fmt,
                    "hodlr_update_rows_active": round(act, 4),
+                   # W^T z rows and K^-1 blocks the applies form (the rest meet a zero Y)
+                   "hodlr_dot_rows_frac": round(sum(st["hodlr_dot_rows"][:lb]) / (lb * N), 4),
+                   "hodlr_core_nodes_frac": round(sum(st["hodlr_core_nodes"][:lb]) / ((1 << lb) - 1), 4),
                    "gmres_driver": (f"device-driven {'delayed CGS2' if args.dcgs2 else 'CGS2'}, "
                                     f"{args.graph_iters} step(s) per graph") if args.graph_iters
                    else "host-driven CGS2"},

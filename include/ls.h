@@ -153,6 +153,12 @@ typedef struct {
    * updates skip the other blocks (points without contrast are identity rows of A, so the
    * matching rows of the preconditioner factors Y = D^-1 U are zero) */
   int64_t hodlr_rows_active;
+  /* per binary level l < hodlr_levels (at most 32): rows whose W^T z a preconditioner apply
+   * forms, and nodes whose core product K^-1 t it forms.  A child node without contrast has
+   * Y = 0: its sibling's rows feed nothing, and K^-1 is the identity on the half of s the
+   * other child uses, so those chunks and core rows are skipped. */
+  int64_t hodlr_dot_rows[32];
+  int hodlr_core_nodes[32];
 } ls_stats_t;
 
 /* Plan description for a uniform n x n grid on [-L, L]^2 (host only, no device use).

@@ -181,6 +181,15 @@ struct HodlrDev {
   DevBuf alist;          // indices of the 256-row blocks with contrast
   int nact = 0;
   bool sparse = false;   // few enough such blocks that updates run over the list alone
+  // one byte per tree node (node j of depth d at (1 << d) + j, depth Lb = the leaves): nonzero
+  // where the node holds a point with contrast.  Set after the factors are built; the applies
+  // then skip the W^T z chunks and K^-1 products that meet a zero Y.
+  DevBuf nodeact;
+  DevBuf dlist;                   // per level: the children whose sibling has contrast (W^T z chunks formed)
+  std::vector<long long> doff;    // offset of each level's list in dlist
+  std::vector<int> dcnt;          // its length
+  std::vector<int64_t> dot_rows;  // per level: rows whose W^T z the masked apply forms
+  std::vector<int> core_nodes;    // per level: nodes whose two children both hold contrast
   DevBuf partial, svec;
   std::vector<long long> chunk;  // per level
   std::vector<int> nchunks, cpc;
@@ -813,6 +822,8 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
     int nodes = 1 << l;
     const int rl = H.rank[l];
     if (rl == 0) continue;
+    // activity of the level's children (after setup): chunks and core rows that meet a zero Y are skipped
+    const unsigned char* cact = H.nodeact.p ? H.nodeact.as<unsigned char>() + (2LL << l) : nullptr;
     if (pend >= 0 && fmt == 2 && nrhs == 1 && !H.sparse && lsk::hodlr_upd_dot_ok(H.N, H.N >> pend, H.chunk[l])) {
       ProfScope pf(P, 6, s);
       lsk::launch_hodlr_upd_dot(H.Y16[pend].p, H.rank[pend], H.svec.as<double2>(), H.N >> pend, 1 << pend, W, rl, z,
@@ -820,7 +831,8 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
     } else {
       if (pend >= 0) update(pend, false);
       ProfScope pd(P, 5, s);
-      lsk::launch_hodlr_dot(fmt, W, z, ldz, H.partial.as<double2>(), H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s);
+      lsk::launch_hodlr_dot(fmt, W, z, ldz, H.partial.as<double2>(), H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s,
+                            cact ? H.dlist.as<int>() + H.doff[l] : nullptr, cact ? H.dcnt[l] : 0, H.cpc[l]);
     }
     pend = -1;
     // core inverses in complex128, or in the factors' precision on request
@@ -829,7 +841,7 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
     {
       ProfScope pc(P, 7, s);
       lsk::launch_hodlr_core(cf, C, H.partial.as<double2>(), H.svec.as<double2>(), rl, nodes, H.cpc[l], H.nchunks[l],
-                             true, nrhs, s);
+                             true, nrhs, s, cact);
     }
     pend = l;
   }
@@ -1099,6 +1111,38 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     H.t_cores_ms += now_ms() - tc;
   }
   hip_check(hipDeviceSynchronize(), "hodlr setup");
+  // node activity for the applies (the factor construction above ran unmasked)
+  if (N % (1LL << H.Lb) == 0) {
+    std::vector<unsigned char> act((size_t)2 << H.Lb, 0);
+    const long long leaf = N >> H.Lb;
+    for (long long i = 0; i < N; ++i)
+      if (qm[i] != 0.0) act[(size_t)((1LL << H.Lb) + i / leaf)] = 1;
+    for (int d = H.Lb - 1; d >= 0; --d)
+      for (long long j = 0; j < (1LL << d); ++j)
+        act[(size_t)((1LL << d) + j)] = act[(size_t)((2LL << d) + 2 * j)] | act[(size_t)((2LL << d) + 2 * j + 1)];
+    H.dot_rows.assign(H.Lb, 0);
+    H.core_nodes.assign(H.Lb, 0);
+    H.doff.assign(H.Lb, 0);
+    H.dcnt.assign(H.Lb, 0);
+    std::vector<int> dl;
+    for (int l = 0; l < H.Lb; ++l) {
+      const unsigned char* c = act.data() + (2LL << l);
+      H.doff[l] = (long long)dl.size();
+      for (long long j = 0; j < (2LL << l); ++j)
+        if (c[j ^ 1]) dl.push_back((int)j);
+      H.dcnt[l] = (int)((long long)dl.size() - H.doff[l]);
+      for (long long j = 0; j < (1LL << l); ++j) {
+        if (c[2 * j] && c[2 * j + 1]) H.core_nodes[l] += 1;
+        if (H.chunk[l] < 16)
+          H.dot_rows[l] += N >> l;  // the tall-skinny reduction forms every chunk
+        else
+          H.dot_rows[l] += ((c[2 * j] ? 1 : 0) + (c[2 * j + 1] ? 1 : 0)) * (N >> (l + 1));
+      }
+    }
+    H.nodeact.upload(act);
+    if (dl.empty()) dl.push_back(0);
+    H.dlist.upload(dl);
+  }
   // FP32 copies of the leaf inverses, the off-diagonal factors and the core inverses
   const long long nd = (long long)H.nleaves * H.lp * H.lp;
   H.Dinv32.alloc((size_t)nd * 8);
@@ -2081,6 +2125,10 @@ ls_status ls_setup(const double* points, int64_t N, const double* q, double kapp
     S.hodlr_blocks = P->have_hodlr ? P->hod.blocks : 0;
     S.hodlr_rank_used_max = P->have_hodlr ? P->hod.used_rank_max : 0;
     S.hodlr_rows_active = P->have_hodlr ? P->hod.rows_active : 0;
+    for (int l = 0; P->have_hodlr && l < P->hod.Lb && l < 32; ++l) {
+      S.hodlr_dot_rows[l] = l < (int)P->hod.dot_rows.size() ? P->hod.dot_rows[l] : P->N;
+      S.hodlr_core_nodes[l] = l < (int)P->hod.core_nodes.size() ? P->hod.core_nodes[l] : (1 << l);
+    }
     S.t_hodlr_aca_ms = P->hod.t_aca_ms;
     S.t_hodlr_apply_ms = P->hod.t_apply_ms;
     S.t_hodlr_cores_ms = P->hod.t_cores_ms;

@@ -84,14 +84,25 @@ bool hodlr_upd_dot_ok(long long N, long long nodesize_a, long long chunk_b);
 void launch_hodlr_upd_dot(const void* Y, int ra, const double2* sv, long long nodesize, int nodes, const void* W,
                           int rb, double2* z, long long N, double2* partial, long long chunk, hipStream_t s,
                           const unsigned char* ract = nullptr);
+// clist (optional): the nlist children of the level (cpc chunks each) whose chunk partials are
+// formed; the segmented kernel (chunks of at least 16 rows, fewer than 8 right-hand sides or
+// low-precision factors) leaves the others unwritten.  A child without contrast has Y = 0, so
+// the partials of its sibling's chunks feed nothing: the list holds the children whose sibling
+// has contrast.
 void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
-                      long long chunk, int nchunks, int nrhs, hipStream_t s);
+                      long long chunk, int nchunks, int nrhs, hipStream_t s, const int* clist = nullptr,
+                      int nlist = 0, int cpc = 0);
 // cfmt: storage of the core inverses, 0 complex128, 1 complex64, 2 complex bfloat16 (r <= 256),
 // hodlr_core_elems(r) entries per node in 16-row blocks (rows 16b..16b+15 of every column,
 // column after column, rows past 2r zero); coreinv unused when !apply (s = t)
 long long hodlr_core_elems(int r);
+// cact (apply only, optional, as for launch_hodlr_dot): where a child has no contrast its Y is
+// zero and K^-1 reduces to the identity on the half of s the other child uses (s_A = t_A when
+// only the first child holds contrast, s_B = t_B when only the second does); that half is
+// written as t, the unused half as zeros, without reading K^-1; nodes without contrast get s = 0.
 void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, double2* sout, int r, int nodes,
-                       int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s);
+                       int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s,
+                       const unsigned char* cact = nullptr);
 // z -= Y s per level.  z2 != NULL asks for a copy of the result in column *jdev of a basis
 // (z2 + rhs*z2ldr + *jdev*z2ldj); returns whether the launch made it (the caller copies otherwise)
 // z -= Y s, one right-hand side, complex64 (fmt 1) or complex bfloat16 (fmt 2) factors, only on the

@@ -805,15 +805,18 @@ template <typename T, int R, int G>
 __global__ __launch_bounds__(256) void k_hodlr_dot_seg(const typename V2<T>::type* __restrict__ W, long long N, int r,
                                                        const double2* __restrict__ z, long long ldz,
                                                        double2* __restrict__ partial, long long chunk, int nchunks,
-                                                       int lc, int nrf) {
+                                                       int lc, int nrf, const int* __restrict__ clist, int nk,
+                                                       int cpc) {
   // nrf > 0: right-hand sides fastest in grid.x (factor tiles reused from L2 across them)
   const int rhs = nrf ? blockIdx.x % nrf : blockIdx.z, grp = blockIdx.y;
   const long long bx = nrf ? blockIdx.x / nrf : blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int spw = 64 / lc;
   const int seg = lane / lc, sl = lane - seg * lc;
-  const long long ch = (bx * 4 + wave) * spw + seg;
-  const bool valid = ch < nchunks;
+  // clist: the children whose chunks are formed (cpc chunks each, nk chunks in all); else every chunk
+  const long long k = (bx * 4 + wave) * spw + seg;
+  const bool valid = k < nk;
+  const long long ch = clist && valid ? (long long)clist[k / cpc] * cpc + k % cpc : k;
   const int c0 = grp * G;
   const double2* zb = z + rhs * ldz;
   double acc[2 * G];
@@ -928,25 +931,26 @@ __global__ __launch_bounds__(256) void k_hodlr_dot_rb(const double2* __restrict_
 constexpr int kDotCols = 8;  // columns per segment
 template <typename T, int R>
 static void hodlr_dot_seg(const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
-                          long long chunk, int nchunks, int nrhs, hipStream_t s) {
+                          long long chunk, int nchunks, int nrhs, hipStream_t s, const int* clist, int nlist, int cpc) {
   int lc = 64;
   while (lc > chunk / R) lc >>= 1;
   constexpr int G = kDotCols;
   const int per_wg = 4 * (64 / lc);
-  const unsigned nbx = (unsigned)((nchunks + per_wg - 1) / per_wg);
+  const int nk = clist ? nlist * cpc : nchunks;
+  const unsigned nbx = (unsigned)((nk + per_wg - 1) / per_wg);
   const int nrf = nrhs > 1 ? nrhs : 0;
   dim3 grid(nrf ? nbx * nrhs : nbx, (r + G - 1) / G, nrf ? 1 : nrhs);
   using S = typename V2<T>::type;
   const S* Ws = (const S*)W;
   auto kern = k_hodlr_dot_seg<T, R, G>;
-  LSK_LAUNCH(kern, grid, 256, 0, s, Ws, N, r, z, ldz, partial, chunk, nchunks, lc, nrf);
+  LSK_LAUNCH(kern, grid, 256, 0, s, Ws, N, r, z, ldz, partial, chunk, nchunks, lc, nrf, clist, nk, cpc);
 }
 
 // 16-byte packs when the chunk and N allow them (chunk a multiple of R holding at least 16
 // packs), single entries otherwise
 template <typename T>
 static void hodlr_dot_fmt(const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
-                          long long chunk, int nchunks, int nrhs, hipStream_t s) {
+                          long long chunk, int nchunks, int nrhs, hipStream_t s, const int* clist, int nlist, int cpc) {
   constexpr int RW = 16 / (int)sizeof(typename V2<T>::type);
   if (RW == 1 && nrhs >= 8) {  // complex128 factors, many right-hand sides
     constexpr int G = 4, RB = 8;
@@ -960,23 +964,26 @@ static void hodlr_dot_fmt(const void* W, const double2* z, long long ldz, double
     return;
   }
   if (RW > 1 && chunk % RW == 0 && N % RW == 0 && chunk / RW >= 16)
-    hodlr_dot_seg<T, RW>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s);
+    hodlr_dot_seg<T, RW>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s, clist, nlist, cpc);
   else
-    hodlr_dot_seg<T, 1>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s);
+    hodlr_dot_seg<T, 1>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s, clist, nlist, cpc);
 }
 
 void launch_hodlr_dot(int fmt, const void* W, const double2* z, long long ldz, double2* partial, long long N, int r,
-                      long long chunk, int nchunks, int nrhs, hipStream_t s) {
+                      long long chunk, int nchunks, int nrhs, hipStream_t s, const int* clist, int nlist, int cpc) {
+  if (clist && (cpc <= 0 || nchunks % cpc != 0 || nlist < 0 || (long long)nlist * cpc > nchunks))
+    throw std::runtime_error("hodlr dot: the child list needs whole children of cpc chunks");
   if (chunk < 16) {  // tiny leaves: plain tall-skinny reduction
     tsdot(fmt, false, W, N, 0, r, z, ldz, partial, r, chunk, nchunks, N, nrhs, s);
     return;
   }
+  if (clist && nlist == 0) return;  // no chunk is needed on this level
   if (fmt == 2)
-    hodlr_dot_fmt<bf16>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s);
+    hodlr_dot_fmt<bf16>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s, clist, nlist, cpc);
   else if (fmt == 1)
-    hodlr_dot_fmt<float>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s);
+    hodlr_dot_fmt<float>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s, clist, nlist, cpc);
   else
-    hodlr_dot_fmt<double>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s);
+    hodlr_dot_fmt<double>(W, z, ldz, partial, N, r, chunk, nchunks, nrhs, s, clist, nlist, cpc);
 }
 
 // t = [t_A; t_B]: t_A from the chunks of the second child (rows paired with Q), t_B from
@@ -1046,7 +1053,7 @@ template <typename TC, int NT, int R2MAX = 256, int RB = 1>
 __global__ __launch_bounds__(NT) void k_hodlr_core_rows(const double2* __restrict__ partial,
                                                         const typename V2<TC>::type* __restrict__ coreinv,
                                                         double2* __restrict__ sout, int r, int nodes, int cpc,
-                                                        int nchunks, int nrf) {
+                                                        int nchunks, int nrf, const unsigned char* __restrict__ cact) {
   constexpr int CG = NT / 16;
   constexpr int MAXU = R2MAX / CG;  // columns per thread at 2r = R2MAX
   using VT = typename V2<TC>::type;
@@ -1060,15 +1067,26 @@ __global__ __launch_bounds__(NT) void k_hodlr_core_rows(const double2* __restric
   const int rhs0 = nrf ? (blockIdx.x % nrb) * RB : blockIdx.z;
   const int nbr = nrf ? (nrf - rhs0 < RB ? nrf - rhs0 : RB) : 1;
   const int r2 = 2 * r;
-  // the block of K^-1 does not depend on t: its loads go out first and overlap the sums of t
   const int li = threadIdx.x & 15, jp = threadIdx.x >> 4;
+  const int i = blk * 16 + li;
+  // children with contrast (bit 0 first child, bit 1 second); the same for the whole workgroup
+  const int m = cact ? (cact[2 * node] ? 1 : 0) | (cact[2 * node + 1] ? 2 : 0) : 3;
+  // both Y zero, or this block's 16 rows all in the half of s that a child without contrast uses
+  if (m == 0 || (m != 3 && (blk * 16 + 16 <= r ? !(m & 1) : (blk * 16 >= r && !(m & 2))))) {
+    if (jp == 0 && i < r2)
+      for (int b = 0; b < nbr; ++b) sout[((long long)(rhs0 + b) * nodes + node) * r2 + i] = make_double2(0.0, 0.0);
+    return;
+  }
+  // the block of K^-1 does not depend on t: its loads go out first and overlap the sums of t
   const long long nb = (r2 + 15) / 16;
   const VT* Cb = coreinv + ((long long)node * nb + blk) * 16 * r2;  // (16 blk + li, j) at j * 16 + li
   VT a[MAXU];
+  if (m == 3) {
 #pragma unroll
-  for (int u = 0; u < MAXU; ++u) {
-    const int j = jp + u * CG;
-    if (j < r2) a[u] = Cb[j * 16 + li];
+    for (int u = 0; u < MAXU; ++u) {
+      const int j = jp + u * CG;
+      if (j < r2) a[u] = Cb[j * 16 + li];
+    }
   }
   // t from the chunk partials: nks threads per value take every nks-th chunk, then a fixed-order sum
   const int nks = NT / r2;
@@ -1099,7 +1117,13 @@ __global__ __launch_bounds__(NT) void k_hodlr_core_rows(const double2* __restric
     }
     __syncthreads();
   }
-  const int i = blk * 16 + li;
+  if (m != 3) {  // one child with contrast: K^-1 is the identity on the half that child uses
+    if (jp == 0 && i < r2)
+      for (int b = 0; b < nbr; ++b)
+        sout[((long long)(rhs0 + b) * nodes + node) * r2 + i] =
+            (m & (i < r ? 1 : 2)) ? t[b][i] : make_double2(0.0, 0.0);
+    return;
+  }
   for (int b = 0; b < nbr; ++b) {
     double re = 0, im = 0;
 #pragma unroll
@@ -1131,7 +1155,7 @@ long long hodlr_core_elems(int r) { return (long long)((2 * r + 15) / 16) * 16 *
 
 template <typename TC, int RB>
 static void core_rows_shape(const void* coreinv, const double2* partial, double2* sout, int r, int nodes, int cpc,
-                            int nchunks, int nrhs, hipStream_t s) {
+                            int nchunks, int nrhs, hipStream_t s, const unsigned char* cact) {
   const int nrf = nrhs > 1 ? nrhs : 0;
   const int nrb = (nrhs + RB - 1) / RB;
   dim3 grid(nrf ? nodes * nrb : nodes, (2 * r + 15) / 16, nrf ? 1 : nrhs);
@@ -1140,43 +1164,44 @@ static void core_rows_shape(const void* coreinv, const double2* partial, double2
   if (2 * r > 256) {
     if (cpc >= 16) {
       auto kern = k_hodlr_core_rows<TC, 1024, 512, RB>;
-      LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf);
+      LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf, cact);
     } else {
       auto kern = k_hodlr_core_rows<TC, 512, 512, RB>;
-      LSK_LAUNCH(kern, grid, 512, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf);
+      LSK_LAUNCH(kern, grid, 512, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf, cact);
     }
     return;
   }
   // many partials per node (the coarse levels): 1024 threads share the sums of t
   if (cpc >= 16) {
     auto kern = k_hodlr_core_rows<TC, 1024, 256, RB>;
-    LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf);
+    LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf, cact);
   } else {
     auto kern = k_hodlr_core_rows<TC, 256, 256, RB>;
-    LSK_LAUNCH(kern, grid, 256, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf);
+    LSK_LAUNCH(kern, grid, 256, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf, cact);
   }
 }
 
 template <typename TC>
 static void core_rows_pick(const void* coreinv, const double2* partial, double2* sout, int r, int nodes, int cpc,
-                           int nchunks, int nrhs, hipStream_t s) {
+                           int nchunks, int nrhs, hipStream_t s, const unsigned char* cact) {
   // many right-hand sides: 8 per workgroup share each block of K^-1 (same sums per column)
   if (nrhs >= 8)
-    core_rows_shape<TC, 8>(coreinv, partial, sout, r, nodes, cpc, nchunks, nrhs, s);
+    core_rows_shape<TC, 8>(coreinv, partial, sout, r, nodes, cpc, nchunks, nrhs, s, cact);
   else
-    core_rows_shape<TC, 1>(coreinv, partial, sout, r, nodes, cpc, nchunks, nrhs, s);
+    core_rows_shape<TC, 1>(coreinv, partial, sout, r, nodes, cpc, nchunks, nrhs, s, cact);
 }
 
 void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, double2* sout, int r, int nodes,
-                       int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s) {
+                       int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s,
+                       const unsigned char* cact) {
   if (2 * r > 512) throw std::runtime_error("HODLR cores need rank <= 256");
   if (apply) {
     if (cfmt == 2)
-      core_rows_pick<bf16>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s);
+      core_rows_pick<bf16>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s, cact);
     else if (cfmt == 1)
-      core_rows_pick<float>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s);
+      core_rows_pick<float>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s, cact);
     else
-      core_rows_pick<double>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s);
+      core_rows_pick<double>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s, cact);
     return;
   }
   dim3 grid(nodes, nrhs);

@@ -53,7 +53,8 @@ class _Stats(C.Structure):
                 ("t_hodlr_ms", C.c_double), ("t_setup_ms", C.c_double),
                 ("hodlr_rank_used_sum", C.c_int64), ("hodlr_blocks", C.c_int64), ("hodlr_rank_used_max", C.c_int),
                 ("t_hodlr_aca_ms", C.c_double), ("t_hodlr_apply_ms", C.c_double), ("t_hodlr_cores_ms", C.c_double),
-                ("hodlr_rows_active", C.c_int64)]
+                ("hodlr_rows_active", C.c_int64), ("hodlr_dot_rows", C.c_int64 * 32),
+                ("hodlr_core_nodes", C.c_int * 32)]
 
 
 class _PlanInfo(C.Structure):
@@ -329,7 +330,8 @@ class Problem:
     def stats(self) -> dict:
         s = _Stats()
         _check(lib().ls_stats(self._h, C.byref(s)))
-        return {f[0]: getattr(s, f[0]) for f in _Stats._fields_}
+        return {f[0]: (list(getattr(s, f[0])) if isinstance(getattr(s, f[0]), C.Array) else getattr(s, f[0]))
+                for f in _Stats._fields_}
 
     def profile_enable(self, cls: str, every: int = 1):
         """Time every `every`-th launch of a kernel class (0 or False: stop)."""

@@ -187,6 +187,44 @@ def test_sparse_contrast_updates_match_oracle():
     assert rel(host(x64), np.linalg.solve(A, host(f)[0] if host(f).ndim > 1 else host(f))) < 1e-6
 
 
+def test_one_sided_nodes_skip_dot_and_core_and_match_oracle():
+    # contrast in one quadrant only: from the root down, many nodes have one child without
+    # contrast (its Y is zero, so the sibling's W^T z chunks feed nothing and K^-1 is the
+    # identity on the half of s the other child uses) and many have none; the masked applies
+    # skip that work and still match the oracle HODLR, and the solves the dense solve
+    n, kappa, rank = 64, 20.0, 12
+    x = inputs.grid_points(n)
+    q = (np.hypot(x[:, 0] - 0.5, x[:, 1] - 0.5) < 0.3).astype(float)
+    P = problem("quadrantdisc64", n, kappa, q, hodlr_rank=rank)
+    st = P.stats()
+    N, lb = n * n, st["hodlr_levels"]
+    say("dot rows", st["hodlr_dot_rows"][:lb], "core nodes", st["hodlr_core_nodes"][:lb])
+    assert st["hodlr_core_nodes"][0] == 0 and st["hodlr_dot_rows"][0] == N // 2
+    assert all(0 <= st["hodlr_core_nodes"][l] < (1 << l) for l in range(lb))
+    assert all(0 < st["hodlr_dot_rows"][l] <= N for l in range(lb))
+    side = st["leaf_side"]
+    A = lsop.dense_A(n, 1.0, kappa, q, -1)
+    perm = ohodlr.morton_permutation(n, side)
+    H = ohodlr.HODLR(A[np.ix_(perm, perm)], side * side, rank)
+    for seed in (29, 31):
+        b = inputs.random_vector(n * n, seed=seed)
+        zref = np.empty_like(b)
+        zref[perm] = H.solve(b[perm])
+        z64 = host(P.precond_apply(dev(b)))
+        z32 = host(P.precond_apply(dev(b), prec=ls.LS_FP32))
+        zm = host(P.precond_apply(dev(b), prec=ls.LS_MIXED))
+        say("one-sided nodes: seed", seed, rel(z64, zref), rel(z32, zref), rel(zm, zref))
+        assert rel(z64, zref) < 1e-9
+        assert rel(z32, zref) < 1e-5
+        assert rel(zm, zref) < 2e-2
+    f = P.rhs_planewave([0.4])
+    x64, i64 = P.solve(f, tol=1e-10, prec=ls.LS_FP64)
+    xm, im = P.solve(f, tol=1e-8, prec=ls.LS_MIXED)
+    assert i64[0]["status"] == "CONVERGED" and im[0]["relres"] <= 1e-8
+    assert rel(host(xm), host(x64)) < 1e-6
+    assert rel(host(x64), np.linalg.solve(A, host(f)[0] if host(f).ndim > 1 else host(f))) < 1e-6
+
+
 def test_precond_full_rank_is_inverse():
     n, kappa = 8, 6.0
     q = inputs.contrast_gaussian(inputs.grid_points(n), 1.5, 10.0)
