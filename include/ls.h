@@ -11,9 +11,9 @@
  * for i != j and the exact integral of G over the cell for i = j.  The physical sign is
  * s = -1 (so psi = kappa^2 q u); s = +1 reproduces Eq. (eq:6) as printed.
  *
- * Products with V use the Directional Algebraic FMM of Section 4 with Nested Cross
- * Approximation factors (Section 3); solves use GMRES (Section 5), optionally right-
- * preconditioned by a fixed-rank HODLR approximation of A (Section 5, Eq. (eq:hybrid)).
+ * Products with V use the Directional Algebraic FMM of Section 5 with Nested Cross
+ * Approximation factors (Section 4); solves use GMRES (Section 6), optionally right-
+ * preconditioned by a fixed-rank HODLR approximation of A (Section 6, Eq. (eq:hybrid)).
  *
  * Conventions for every call below
  *   - Setup inputs are HOST arrays and are copied.  Vectors passed to vector calls are
@@ -76,7 +76,9 @@ typedef struct {
   int prec;           /* ls_prec used by ls_solve (default LS_FP64) */
   double inner_tol;   /* LS_MIXED: relative accuracy delta of the FP32 operator; products switch to FP32
                          once every residual estimate is below tol / delta (default 1e-5) */
-  int max_refine;     /* LS_MIXED: max outer refinement steps (default 10) */
+  int max_refine;     /* LS_MIXED: Krylov cycles (each started from an FP64 residual f - A x) that may
+                         use FP32 products; a column still unconverged after them is finished with
+                         FP64 products and reports LS_REFINE_STAGNATED (default 10) */
   int build_fp32;     /* build the FP32 operator at setup (default 1) */
   int hodlr_rank_div; /* 0 (default): rank hodlr_rank at every HODLR level, as in the paper;
                          d > 0: rank min(hodlr_rank, child block size / d) per level */
@@ -103,9 +105,9 @@ typedef struct {
                          leaf and core inverses in the off-diagonal factors' precision (complex
                          bfloat16 or complex64: less traffic, a less exact preconditioner) */
   double hodlr_tol;   /* 0 (default): every off-diagonal HODLR block at the fixed rank (the
-                         preconditioner of Section 5); eps > 0: each block's ACA stops at
+                         preconditioner of Section 6); eps > 0: each block's ACA stops at
                          ||u_k|| ||v_k|| <= eps ||S_k||_F (the HODLR factorisation at a fixed
-                         tolerance, Section 5), its rank still capped by hodlr_rank; for
+                         tolerance, Section 6), its rank still capped by hodlr_rank; for
                          ls_direct_solve */
 } ls_options;
 
@@ -115,7 +117,8 @@ typedef struct {
   int status;         /* LS_CONVERGED; LS_MAXIT (maxit reached); LS_NAN (non-finite residual);
                          LS_WARMSTART_REJECTED (converged, but the given x0 was replaced by zero);
                          LS_REFINE_STAGNATED (LS_MIXED: FP32 products stopped reducing the FP64
-                         residual, the column was finished with FP64 products and converged) */
+                         residual, or max_refine cycles were spent; the column was finished with
+                         FP64 products and converged) */
   int n_refine;       /* LS_MIXED: Krylov cycles, each started from an FP64 residual f - A x */
   double t_solve_ms;  /* wall time of the call */
   double relres0;     /* ||f - A x0|| / ||f|| of the start GMRES used (1 for a zero start) */
@@ -165,7 +168,7 @@ typedef struct {
  * Per level nu (0..levels): hf[nu], ndir[nu] (cones), il_pairs[nu] (in-domain M2L pairs
  * over (box, direction)), max_il[nu]; near_pairs = ordered neighbouring leaf pairs.
  * coverage_min/max: over all ordered leaf pairs, the number of times each pair is
- * handled (near field or exactly one M2L); both must be 1 (Section 4: every
+ * handled (near field or exactly one M2L); both must be 1 (Section 5: every
  * interaction is either near field or transferred by one M2L).  Arrays hold 32 levels. */
 typedef struct {
   int levels, leaf_side, top_level;
@@ -180,7 +183,7 @@ void ls_default_options(ls_options* opt);
 /* Build the solver for the points of a uniform cell-centred n x n grid (any order).
  *   points : host, N x 2 row-major (x1, x2); must form a uniform cell-centred square grid.
  *   q      : host, N real contrast values q(x_i) in the same order.
- *   kappa  : wavenumber > 0.   tol : NCA tolerance eps_NCA in (0, 1) (Section 3.2.2).
+ *   kappa  : wavenumber > 0.   tol : NCA tolerance eps_NCA in (0, 1) (Section 4.2.2).
  *   opt    : NULL for defaults.  *out receives the handle (NULL on error).
  * Synchronous.  Uses the current HIP device.  Errors: LS_EINVAL (N <= 0, kappa <= 0,
  * tol outside (0,1), non-finite or duplicate points, non-finite q, bad options);
@@ -189,16 +192,16 @@ void ls_default_options(ls_options* opt);
 ls_status ls_setup(const double* points, int64_t N, const double* q, double kappa, double tol,
                    const ls_options* opt, ls_problem** out);
 
-/* y = A x (Eq. (eq:12a)) with the DAFMM product (Section 4) for V.
+/* y = A x (Eq. (eq:12a)) with the DAFMM product (Section 5) for V.
  * x, y: device, N x nrhs complex128, leading dimension ld.  prec: LS_FP64 or LS_FP32
  * (FP32 converts x to complex64 for the operator and accumulates the result in
  * complex128).  x and y must not overlap. */
 ls_status ls_matvec(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld, int prec, void* stream);
 
-/* u = V psi: the scattered field on the grid (Section 5, last paragraph before 5.1). */
+/* u = V psi: the scattered field on the grid (Section 6, last paragraph before 6.1). */
 ls_status ls_apply_V(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld, int prec, void* stream);
 
-/* HODLR direct solver (Section 5: the factorisation used as the solver, the paper's choice for
+/* HODLR direct solver (Section 6: the factorisation used as the solver, the paper's choice for
  * many right-hand sides): psi = A~^{-1} f, then iterative refinement psi += A~^{-1} (f - A psi)
  * with FP64 DAFMM products until ||f - A psi|| <= tol ||f|| for every column or max_refine steps
  * (tol = 0: exactly max_refine steps).  A~ is the factorisation built at setup; with hodlr_tol > 0
@@ -208,14 +211,14 @@ ls_status ls_apply_V(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld
 ls_status ls_direct_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld, double tol, int max_refine,
                           ls_solve_info* info, void* stream);
 
-/* z = A~^{-1} r with the fixed-rank HODLR approximation A~ of A (Section 5, Eq. (eq:hybrid)).
+/* z = A~^{-1} r with the fixed-rank HODLR approximation A~ of A (Section 6, Eq. (eq:hybrid)).
  * prec LS_FP64: all factors complex128; LS_FP32: off-diagonal factors stored complex64;
  * LS_MIXED: off-diagonal factors complex bfloat16 when pc_bf16 = 1 (else complex64); leaf
  * and SMW core solves complex128 (unless pc_lowp_solves = 1) and all sums in FP64 in every
  * case.  LS_ENOTSUP when hodlr_rank = 0. */
 ls_status ls_precond_apply(ls_problem* P, const void* r, void* z, int nrhs, int64_t ld, int prec, void* stream);
 
-/* f_j = -s kappa^2 q u_inc(theta_j), u_inc = exp(i kappa (cos t x1 + sin t x2)) (Section 5.2).
+/* f_j = -s kappa^2 q u_inc(theta_j), u_inc = exp(i kappa (cos t x1 + sin t x2)) (Section 6.2).
  * angles: host, nrhs values.  f: device, N x nrhs complex128. */
 ls_status ls_rhs_planewave(ls_problem* P, const double* angles, int nrhs, void* f, int64_t ld, void* stream);
 
@@ -232,7 +235,7 @@ ls_status ls_rhs_planewave(ls_problem* P, const double* angles, int nrhs, void* 
 ls_status ls_solve(ls_problem* P, const void* f, void* psi, int nrhs, int64_t ld, double tol,
                    int x0_given, int prec, ls_solve_info* info, void* stream);
 
-/* Queue of independent problems (Section 5's solver applied to each): solves
+/* Queue of independent problems (Section 6's solver applied to each): solves
  * A_p psi_p = f_p for p < nprob, one right-hand side each, from a zero start, to
  * ||f_p - A_p psi_p|| / ||f_p|| <= tol.  Problems are taken largest first by `nworkers` host
  * threads (0 = 4), each driving its own HIP stream (default priority); every solve uses the
@@ -264,7 +267,7 @@ ls_status ls_autotune(ls_problem* P, ls_tune_info* out, void* stream);
  * complex128, owned by the caller.  Synchronous on `stream`.  LS_ENOTSUP if kappa h >= 4/0.7072. */
 ls_status ls_green_table(int n, double h, double kappa, void* out, void* stream);
 
-/* Off-grid volume potential (Section 5, the paragraph before Section 5.1: u_scat = V[psi] from
+/* Off-grid volume potential (Section 6, the paragraph before Section 6.1: u_scat = V[psi] from
  * the discrete density).  At p = 1 the density is constant on each cell, so
  *   u[t] = sum_j psi_j int_{cell j} G(|x_t - y|) dy,   G = (i/4) H0^(1)(kappa r),
  * for any points x_t, inside or outside the grid.  Cells two or more cells away from the one

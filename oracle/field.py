@@ -2,8 +2,8 @@
 
 Test infrastructure: only tests/ and the bench's CPU leg use this module.
 
-Paper, Section 5 (the paragraph before Section 5.1): the scattered field is u_scat = V[psi],
-computed from the discrete density on the same grid; Section 5.2, Eq. (eq:error): the error
+Paper, Section 6 (the paragraph before Section 6.1): the scattered field is u_scat = V[psi],
+computed from the discrete density on the same grid; Section 6.2, Eq. (eq:error): the error
 function E(x) is the residual of the continuous equation at any x in the domain, with the
 density interpolated by the leaf basis (Eq. (eq:7)).  At p = 1 that basis is the constant 1 on
 each cell, so for any point x

@@ -1,6 +1,6 @@
 """Restarted GMRES (oracle).
 
-Paper, Section 5 ("GMRES solver" and the Hybrid solver, Eq. (eq:hybrid)): GMRES
+Paper, Section 6 ("GMRES solver" and the Hybrid solver, Eq. (eq:hybrid)): GMRES
 (Saad & Schultz) with every product computed by the operator, stopped on the
 relative residual ||A psi - f|| / ||f|| <= eps_GMRES.
 

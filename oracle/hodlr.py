@@ -1,6 +1,6 @@
 """Fixed-rank HODLR approximation of A and its inverse (oracle).
 
-Paper, Section 5 (Hybrid solver, Eq. (eq:hybrid)) and Section 5.1: the HODLR
+Paper, Section 6 (Hybrid solver, Eq. (eq:hybrid)) and Section 6.1: the HODLR
 preconditioner A~ is built by fixing a priori the rank r of its off-diagonal
 blocks; GMRES then solves A~^{-1} A psi = A~^{-1} f.  The paper does not spell the
 construction out.  The reading used here:
@@ -124,26 +124,38 @@ def morton_permutation(n: int, side: int) -> np.ndarray:
 
 
 class HODLR:
-    """A~ for a dense matrix A given in HODLR (Morton) order, leaves of ``leaf`` indices."""
+    """A~ for a dense matrix A given in HODLR (Morton) order, leaves of ``leaf`` indices.
 
-    def __init__(self, A: np.ndarray, leaf: int, rank: int):
+    ``rank`` is the off-diagonal rank of every node, as in the paper.  ``level_ranks``, if
+    given, overrides it per depth of the binary tree (root = depth 0): the blocks of a node at
+    depth d are compressed at rank level_ranks[d].
+    """
+
+    def __init__(self, A: np.ndarray, leaf: int, rank: int, level_ranks=None):
         self.A = A
         self.leaf = leaf
         self.rank = rank
-        self.root = self._build(0, A.shape[0])
+        self.level_ranks = None if level_ranks is None else [int(k) for k in level_ranks]
+        self.root = self._build(0, A.shape[0], 0)
 
-    def _build(self, lo, hi):
-        node = {"lo": lo, "hi": hi}
+    def rank_at(self, depth: int) -> int:
+        if self.level_ranks is None:
+            return self.rank
+        return self.level_ranks[depth]
+
+    def _build(self, lo, hi, depth):
+        node = {"lo": lo, "hi": hi, "depth": depth}
         if hi - lo <= self.leaf:
             node["leaf"] = True
             node["D"] = self.A[lo:hi, lo:hi].copy()
             return node
         mid = (lo + hi) // 2
         node["leaf"] = False
-        node["c1"] = self._build(lo, mid)
-        node["c2"] = self._build(mid, hi)
-        P, Q, _, _ = aca(self.A[lo:mid, mid:hi], self.rank)
-        R, S, _, _ = aca(self.A[mid:hi, lo:mid], self.rank)
+        node["c1"] = self._build(lo, mid, depth + 1)
+        node["c2"] = self._build(mid, hi, depth + 1)
+        k = self.rank_at(depth)
+        P, Q, _, _ = aca(self.A[lo:mid, mid:hi], k)
+        R, S, _, _ = aca(self.A[mid:hi, lo:mid], k)
         node["P"], node["Q"], node["R"], node["S"] = P, Q, R, S
         # Y = blockdiag(A~1^{-1} P, A~2^{-1} R);  core = I + W^T Y
         Y1 = self._solve(node["c1"], P) if P.shape[1] else P

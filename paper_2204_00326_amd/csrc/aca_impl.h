@@ -1,9 +1,9 @@
 // Partially pivoted adaptive cross approximation (ACA).
 //
 // The paper chooses NCA pivots with partially pivoted ACA stopped by Rjasanow's
-// criterion at accuracy eps_NCA (Section 3.2.2, step 2, and the notation table of
-// Section 5.2); the same routine, capped at a fixed rank, compresses the off-diagonal
-// blocks of the HODLR preconditioner (Section 5).  Rules: start at the first row
+// criterion at accuracy eps_NCA (Section 4.2.2, step 2, and the notation table of
+// Section 6.2); the same routine, capped at a fixed rank, compresses the off-diagonal
+// blocks of the HODLR preconditioner (Section 6).  Rules: start at the first row
 // that is not known to be zero; the column pivot is the largest residual entry of the
 // pivot row over unused columns; the next row pivot is the largest entry of the new
 // residual column over unused rows; an exactly zero residual row is skipped in favour

@@ -935,7 +935,13 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     H.nact = (int)alist.size();
     // below three quarters of the rows, single-column updates run over the listed blocks (all
     // threads on rows that change) instead of inside the fused update + W^T z launch
-    H.sparse = N % 256 == 0 && H.rows_active * 4 < N * 3;
+    // the listed kernel takes 4 (bf16) or 2 (complex64) consecutive rows per lane with one s,
+    // so every node half must hold a multiple of 4 rows (not so for odd leaf sides, e.g. 25- or
+    // 49-point leaves)
+    bool halves4 = true;
+    for (int l = 0; l < H.Lb; ++l)
+      if (N % (2LL << l) != 0 || (N >> (l + 1)) % 4 != 0) halves4 = false;
+    H.sparse = N % 256 == 0 && halves4 && H.rows_active * 4 < N * 3;
     H.bytes = (int64_t)H.nleaves * lp * lp * 16;
   }
   hodlr_chunks(H, P->tune.hodlr_rows);
@@ -1186,7 +1192,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
 }
 
 // ---------------------------------------------------------------------------------------
-// GMRES (Section 5): restarted, right-preconditioned, classical Gram-Schmidt with one
+// GMRES (Section 6): restarted, right-preconditioned, classical Gram-Schmidt with one
 // reorthogonalisation, Givens rotations on the host.  All vectors in Morton order.
 // ---------------------------------------------------------------------------------------
 struct GmresCfg {
@@ -1200,6 +1206,7 @@ struct GmresCfg {
   bool dcgs2 = false;    // device-driven steps: delayed CGS2 (one reduction, one update pass)
   int restart = 200;
   int maxit = 2000;
+  int max_refine = 1 << 30;  // relax > 0: Krylov cycles that may use FP32 products
 };
 
 struct ColState {
@@ -1307,8 +1314,10 @@ void gmres(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* x, int
       } else {
         any = true;
         st[c].cycles++;
-        if (relax_enabled && st[c].cycles > 1 && beta[c] > 0.9 * st[c].prev_true) {
-          relax_enabled = false;  // FP32 products stopped reducing the true residual
+        // FP32 products stopped reducing the true residual, or the refinement budget is spent
+        if (relax_enabled && st[c].cycles > 1 &&
+            (beta[c] > 0.9 * st[c].prev_true || st[c].cycles > cfg.max_refine)) {
+          relax_enabled = false;
           st[c].fell_back = true;
         }
         st[c].prev_true = beta[c];
@@ -1691,7 +1700,9 @@ void gmres_graph(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* 
       } else {
         any = true;
         st[c].cycles++;
-        if (relax_enabled && st[c].cycles > 1 && beta[c] > 0.9 * st[c].prev_true) {
+        // FP32 products stopped reducing the true residual, or the refinement budget is spent
+        if (relax_enabled && st[c].cycles > 1 &&
+            (beta[c] > 0.9 * st[c].prev_true || st[c].cycles > cfg.max_refine)) {
           relax_enabled = false;
           st[c].fell_back = true;
         }
@@ -2395,11 +2406,13 @@ static void solve_impl(ls_problem* P, const void* f, void* psi, int nrhs, int64_
       // mixed: flexible GMRES whose products switch from the FP64 to the FP32 operator once
       // every residual estimate is below tol / delta32 (relaxation of inexact Krylov methods),
       // FP32 off-diagonal HODLR factors throughout; each restart recomputes the true FP64
-      // residual f - A x (iterative refinement), at most max_refine restarts.
+      // residual f - A x (iterative refinement); after max_refine such cycles, or once a
+      // cycle fails to lower the true residual by 10%, the products stay FP64.
       cfg.op32 = false;
       cfg.pcf = P->hod.have16 ? 2 : 1;
       cfg.flexible = true;
       cfg.relax = std::min(0.5, tol / P->opt.inner_tol);
+      cfg.max_refine = P->opt.max_refine;
       if (graph_iters > 0)
         gmres_graph(P, cfg, fm, xm, nrhs, st, graph_iters, s);
       else

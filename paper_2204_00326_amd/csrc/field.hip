@@ -1,5 +1,5 @@
-// Off-grid volume potential and the error function E(x) (paper, Section 5: u_scat = V[psi]
-// from the discrete density; Section 5.2, Eq. (eq:error)).  At p = 1 the density is constant
+// Off-grid volume potential and the error function E(x) (paper, Section 6: u_scat = V[psi]
+// from the discrete density; Section 6.2, Eq. (eq:error)).  At p = 1 the density is constant
 // on each cell, so (V psi)(x) = sum_j psi_j int_{cell j} G(|x - y|) dy for any point x.
 //
 // One workgroup per target.  Cells at Chebyshev distance d >= 2 (in cells) from the cell that

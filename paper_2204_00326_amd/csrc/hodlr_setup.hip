@@ -1,4 +1,4 @@
-// HODLR factorisation on the device (Section 5).
+// HODLR factorisation on the device (Section 6).
 //
 // Batched partially pivoted ACA for the off-diagonal blocks of one level (fixed-rank compression
 // of the off-diagonal blocks), with the pivoting rules of the host routine in aca_impl.h: start at

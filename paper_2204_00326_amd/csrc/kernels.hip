@@ -1097,9 +1097,12 @@ __global__ __launch_bounds__(NT) void k_hodlr_core_rows(const double2* __restric
       const int half = v < r ? 1 : 0;  // t_A sums the second child
       const int c = v < r ? v : v - r;
       const long long ch0 = (long long)node * 2 * cpc + (long long)half * cpc;
+      // a one-sided node uses only the half of t that its child with contrast multiplies; the
+      // chunk partials of the other half were not formed by the masked W^T z (stale) and are not read
+      const int kend = (m == 3 || (m & (v < r ? 1 : 2))) ? cpc : 0;
       double re = 0, im = 0;
 #pragma unroll(NT == 1024 ? 16 : 4)
-      for (int k = ks; k < cpc; k += nks) {
+      for (int k = ks; k < kend; k += nks) {
         const double2 p = partial[(rhs * nchunks + ch0 + k) * r + c];
         re += p.x;
         im += p.y;
@@ -1569,6 +1572,8 @@ void launch_hodlr_update_list(int fmt, const void* Y, const double2* sv, double2
                               long long nodesize, const int* blist, int nact, hipStream_t s) {
   if (nact <= 0) return;
   if (N < 4) throw std::runtime_error("listed HODLR update needs N >= 4");
+  if (N % 256 != 0 || nodesize % 8 != 0 || N % nodesize != 0)
+    throw std::runtime_error("listed HODLR update needs N % 256 == 0 and node halves of a multiple of 4 rows");
   if (fmt == 2) {
     auto kern = k_hodlr_update_list<bf16>;
     LSK_LAUNCH(kern, dim3((unsigned)nact), 256, 0, s, (const BF2*)Y, sv, z, N, r, nodesize, blist, nact);

@@ -3,8 +3,8 @@
 // Section 2.1 builds a quadtree; Section 3 classifies a box of half-width w as
 // high-frequency when (kappa w)^2 > T and defines the low-frequency (LF) and
 // directional high-frequency (HF) admissibility conditions; Section 3.2.1 builds the
-// cone hierarchy; Table "notations" of Section 3.1 defines N(B), IL(B) and IL(B, l);
-// Section 3.2 builds nested bases and pivots with NCA.
+// cone hierarchy; Table "notations" of Section 4.1 defines N(B), IL(B) and IL(B, l);
+// Section 4 builds nested bases and pivots with NCA.
 //
 // On a uniform grid with the translation-invariant p = 1 kernel, the interaction list
 // of a box depends only on its position inside its parent (its class) and on clipping
@@ -301,7 +301,7 @@ void lu_solve_transposed(const std::vector<zd>& B, int k, std::vector<zd>& X, in
   }
 }
 
-// ---- NCA (Section 3.2) -------------------------------------------------------------------
+// ---- NCA (Section 4) -------------------------------------------------------------------
 
 NCA build_nca(const Plan& p, const WTable& W, double tol) {
   NCA out;
@@ -342,7 +342,7 @@ NCA build_nca(const Plan& p, const WTable& W, double tol) {
     std::vector<std::string> errs(nd);
     auto work = [&](int dir) {
       try {
-        // candidate sets (Section 3.2.2, step 1)
+        // candidate sets (Section 4.2.2, step 1)
         std::vector<Off> tcand, scand;
         std::vector<Off> selfchild;  // for L2L: which child/pivot each candidate came from
         if (is_leaf) {
@@ -422,7 +422,7 @@ NCA build_nca(const Plan& p, const WTable& W, double tol) {
     for (int dir = 0; dir < nd; ++dir) L.kmax = std::max(L.kmax, L.rank[dir]);
     if (is_leaf) out.kleaf = L.rank[0];
   }
-  // M2L operators (Section 4, transverse pass): K = V(self pivots of B, self pivots of B + d)
+  // M2L operators (Section 5, transverse pass): K = V(self pivots of B, self pivots of B + d)
   for (int nu = p.top; nu <= leaf; ++nu) {
     const Level& l = p.lv[nu];
     LevelNCA& L = out.lv[nu];

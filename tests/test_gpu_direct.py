@@ -1,4 +1,4 @@
-"""HODLR direct solver (ls_direct_solve; Section 5, the factorisation used as the solver) with
+"""HODLR direct solver (ls_direct_solve; Section 6, the factorisation used as the solver) with
 tolerance-controlled off-diagonal ranks (hodlr_tol) and FP64 iterative refinement, against the
 dense solve of the oracle operator."""
 import sys

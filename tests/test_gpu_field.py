@@ -1,5 +1,5 @@
 """GPU parity of the off-grid volume potential and the error function E(x) (ls_field_eval,
-ls_error_eval; Section 5 and Eq. (eq:error)) against the FP64 oracle, which integrates every
+ls_error_eval; Section 6 and Eq. (eq:error)) against the FP64 oracle, which integrates every
 cell by adaptive quadrature (near the target) or a 12 x 12 Gauss-Legendre rule: targets at cell
 centres, inside cells, next to edges and corners, just outside the grid and far away; points
 passed in a shuffled order so that the caller-order mapping is exercised."""

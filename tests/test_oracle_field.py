@@ -1,4 +1,4 @@
-"""Pins of the off-grid field / error-function oracle (Section 5, Eq. (eq:error)).
+"""Pins of the off-grid field / error-function oracle (Section 6, Eq. (eq:error)).
 
 * the cell integral at its own centre is the exact self-cell term W0 (closed form, and the
   value printed for (h, kappa) = (1/16, 10));

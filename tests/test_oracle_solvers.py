@@ -121,6 +121,57 @@ def test_hodlr_full_rank_is_exact():
     assert np.linalg.norm(H.solve(b) - np.linalg.solve(Ah, b)) <= 1e-10 * np.linalg.norm(np.linalg.solve(Ah, b))
 
 
+def _offdiag_blocks(H):
+    """(depth, upper block, lower block) of every non-leaf node of the assembled A~."""
+    D = H.dense()
+    out = []
+
+    def walk(node):
+        if node["leaf"]:
+            return
+        lo, hi, mid = node["lo"], node["hi"], node["c1"]["hi"]
+        out.append((node["depth"], D[lo:mid, mid:hi], D[mid:hi, lo:mid]))
+        walk(node["c1"])
+        walk(node["c2"])
+
+    walk(H.root)
+    return out
+
+
+def test_hodlr_level_ranks_full_rank_is_exact():
+    # full rank at every depth (the child block size): A~ = A and A~^{-1} b = A^{-1} b
+    p, A, f = _c1()
+    perm = hodlr.morton_permutation(p.n, 8)
+    Ah = A[np.ix_(perm, perm)]
+    full = [p.N >> (d + 1) for d in range(4)]
+    H = hodlr.HODLR(Ah, 64, 1, level_ranks=full)
+    assert np.linalg.norm(H.dense() - Ah) <= 1e-11 * np.linalg.norm(Ah)
+    b = inputs.random_vector(p.N, seed=6)
+    x = np.linalg.solve(Ah, b)
+    assert np.linalg.norm(H.solve(b) - x) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_hodlr_level_ranks_set_each_depth():
+    # every off-diagonal block at depth d has numerical rank exactly level_ranks[d] (the C1
+    # blocks have higher rank, so a rank taken from the wrong depth shows), and a constant list
+    # reproduces the single-rank construction
+    p, A, f = _c1()
+    perm = hodlr.morton_permutation(p.n, 8)
+    Ah = A[np.ix_(perm, perm)]
+    ranks = [7, 3, 5, 2]
+    H = hodlr.HODLR(Ah, 64, 99, level_ranks=ranks)
+    blocks = _offdiag_blocks(H)
+    assert sorted({d for d, _, _ in blocks}) == [0, 1, 2, 3]
+    for d, U, L in blocks:
+        for B in (U, L):
+            sv = np.linalg.svd(B, compute_uv=False)
+            k = ranks[d]
+            assert sv[k - 1] > 1e-6 * sv[0] and sv[k] <= 1e-10 * sv[0], (d, k, sv[: k + 2])
+    H1 = hodlr.HODLR(Ah, 64, 4)
+    H2 = hodlr.HODLR(Ah, 64, 99, level_ranks=[4, 4, 4, 4])
+    assert np.array_equal(H1.dense(), H2.dense())
+
+
 def test_hodlr_preconditioner_reduces_iterations():
     p = inputs.problem_disc(32, 20.0)
     A = lsop.dense_A(p.n, p.L, p.kappa, p.q, -1)
