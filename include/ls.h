@@ -218,6 +218,23 @@ ls_status ls_direct_solve(ls_problem* P, const void* f, void* psi, int nrhs, int
  * case.  LS_ENOTSUP when hodlr_rank = 0. */
 ls_status ls_precond_apply(ls_problem* P, const void* r, void* z, int nrhs, int64_t ld, int prec, void* stream);
 
+/* ls_precond_apply for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and the same
+ * result, with every workspace (the Morton-order copy of r, the W^T z chunk partials and the
+ * SMW s vectors) placed in one fixed 64 MiB array that the library's code object holds on each
+ * GPU it runs on, from the load of the library until the process ends; the call makes no
+ * hipMalloc, hipFree, event creation or other allocating call.  Arguments, layout and prec as
+ * ls_precond_apply; r and z are caller-owned device buffers and must not overlap.  The current
+ * device must be the one ls_setup ran on (else LS_EINVAL).  The workspace needs, rounded up to
+ * 256 bytes each, 16 N nrhs bytes + 16 nrhs max_l(chunks_l r_l) + 16 nrhs max_l(2^(l+1) r_l)
+ * bytes (about 6 MiB per right-hand side at N = 512^2, rank 256); a call that would need more
+ * than 64 MiB returns LS_EINVAL with the required size in ls_last_error().  Every call on a GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (other streams, other threads,
+ * other handles) race and give undefined results.  Nothing in the array needs to start at zero
+ * (every entry a call reads was written earlier in the same call). */
+ls_status ls_precond_apply_noalloc(ls_problem* P, const void* r, void* z, int nrhs, int64_t ld, int prec,
+                                   void* stream);
+
 /* f_j = -s kappa^2 q u_inc(theta_j), u_inc = exp(i kappa (cos t x1 + sin t x2)) (Section 6.2).
  * angles: host, nrhs values.  f: device, N x nrhs complex128. */
 ls_status ls_rhs_planewave(ls_problem* P, const double* angles, int nrhs, void* f, int64_t ld, void* stream);

@@ -236,6 +236,8 @@ struct ProfileClass {
 
 struct ls_problem {
   ls_options opt;
+  int device = 0;            // HIP device current at ls_setup (every vector call runs there)
+  void* scratch = nullptr;   // that device's address of the allocation-free entry point's array
   ls::Plan plan;
   ls::NCA nca64, nca32;
   long long N = 0;
@@ -276,8 +278,8 @@ namespace {
 struct ProfScope {
   ProfileClass* pc;
   hipStream_t s;
-  ProfScope(ls_problem* P, int cls, hipStream_t st) : pc(&P->prof[cls]), s(st) {
-    if (!pc->enabled || P->capturing || (pc->count++ % pc->every) != 0) {
+  ProfScope(ls_problem* P, int cls, hipStream_t st, bool on = true) : pc(&P->prof[cls]), s(st) {
+    if (!on || !pc->enabled || P->capturing || (pc->count++ % pc->every) != 0) {
       pc = nullptr;
       return;
     }
@@ -771,28 +773,48 @@ void fmm_apply(ls_problem* P, bool fp32, const double2* x, long long ldx, double
 // ---------------------------------------------------------------------------------------
 // HODLR
 // ---------------------------------------------------------------------------------------
+void hodlr_ws_elems(const HodlrDev& H, size_t* np, size_t* ns);
+
 void hodlr_ensure_ws(ls_problem* P, int nrhs) {
   HodlrDev& H = P->hod;
   size_t needp = 0, needs = 0;
-  for (int l = 0; l < H.Lb; ++l) {
-    needp = std::max(needp, (size_t)H.nchunks[l] * H.rank[l]);
-    needs = std::max(needs, (size_t)(1LL << l) * 2 * H.rank[l]);
-  }
-  H.partial.ensure(std::max<size_t>(needp, 1) * nrhs * 16);
-  H.svec.ensure(std::max<size_t>(needs, 1) * nrhs * 16);
+  hodlr_ws_elems(H, &needp, &needs);
+  H.partial.ensure(needp * nrhs * 16);
+  H.svec.ensure(needs * nrhs * 16);
 }
 
 // z = (partial) HODLR inverse applied to b (Morton order): leaf solves, then levels
 // Lb-1 .. lstop.  b and z may be the same buffer.
 // jdev != NULL: b is column *jdev of a basis (b + *jdev * bldj); zcopy != NULL: the result is
 // also stored in column *jdev of zcopy (ld per right-hand side zldr, per column zldj)
+// Workspaces of one apply: the chunk partials of W^T z and the s vectors of the SMW cores.
+struct HodlrWs {
+  double2* partial = nullptr;
+  double2* svec = nullptr;
+  bool timers = true;  // sampled kernel timers may create events
+};
+
+// complex entries of the chunk partials and of the s vectors one right-hand side needs
+void hodlr_ws_elems(const HodlrDev& H, size_t* np, size_t* ns) {
+  size_t needp = 0, needs = 0;
+  for (int l = 0; l < H.Lb; ++l) {
+    needp = std::max(needp, (size_t)H.nchunks[l] * H.rank[l]);
+    needs = std::max(needs, (size_t)(1LL << l) * 2 * H.rank[l]);
+  }
+  *np = std::max<size_t>(needp, 1);
+  *ns = std::max<size_t>(needs, 1);
+}
+
 void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double2* z, long long ldz, int nrhs,
                  int lstop, hipStream_t s, const int* jdev = nullptr, long long bldj = 0, double2* zcopy = nullptr,
-                 long long zldr = 0, long long zldj = 0) {
+                 long long zldr = 0, long long zldj = 0, const HodlrWs* ws = nullptr) {
   HodlrDev& H = P->hod;
-  hodlr_ensure_ws(P, nrhs);
+  if (!ws) hodlr_ensure_ws(P, nrhs);
+  double2* const partial = ws ? ws->partial : H.partial.as<double2>();
+  double2* const svec = ws ? ws->svec : H.svec.as<double2>();
+  const bool tm = ws ? ws->timers : true;
   {
-    ProfScope ps(P, 2, s);
+    ProfScope ps(P, 2, s, tm);
     // leaf inverses in complex128, or in the factors' precision on request
     const int lf = P->opt.pc_lowp_solves ? fmt : 0;
     const void* D = lf == 2 && H.Dinv16.p ? H.Dinv16.p : (lf >= 1 && H.Dinv32.p ? H.Dinv32.p : H.Dinv.p);
@@ -807,14 +829,14 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
   bool copied = false;
   auto update = [&](int a, bool last) {
     const void* Y = fmt == 2 ? H.Y16[a].p : (fmt == 1 ? H.Y32[a].p : H.Y64[a].p);
-    ProfScope ps(P, 1, s);
+    ProfScope ps(P, 1, s, tm);
     if (H.sparse && nrhs == 1 && fmt >= 1 && !(last && zcopy)) {
-      lsk::launch_hodlr_update_list(fmt, Y, H.svec.as<double2>(), z, H.N, H.rank[a], H.N >> a, H.alist.as<int>(),
+      lsk::launch_hodlr_update_list(fmt, Y, svec, z, H.N, H.rank[a], H.N >> a, H.alist.as<int>(),
                                     H.nact, s);
       copied = false;
       return;
     }
-    copied = lsk::launch_hodlr_update(fmt, Y, H.svec.as<double2>(), z, ldz, H.N, H.rank[a], H.N >> a, 1 << a, nrhs,
+    copied = lsk::launch_hodlr_update(fmt, Y, svec, z, ldz, H.N, H.rank[a], H.N >> a, 1 << a, nrhs,
                                       s, last ? zcopy : nullptr, zldr, jdev, zldj, H.ract.as<unsigned char>());
   };
   for (int l = H.Lb - 1; l >= lstop; --l) {
@@ -825,13 +847,13 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
     // activity of the level's children (after setup): chunks and core rows that meet a zero Y are skipped
     const unsigned char* cact = H.nodeact.p ? H.nodeact.as<unsigned char>() + (2LL << l) : nullptr;
     if (pend >= 0 && fmt == 2 && nrhs == 1 && !H.sparse && lsk::hodlr_upd_dot_ok(H.N, H.N >> pend, H.chunk[l])) {
-      ProfScope pf(P, 6, s);
-      lsk::launch_hodlr_upd_dot(H.Y16[pend].p, H.rank[pend], H.svec.as<double2>(), H.N >> pend, 1 << pend, W, rl, z,
-                                H.N, H.partial.as<double2>(), H.chunk[l], s, H.ract.as<unsigned char>());
+      ProfScope pf(P, 6, s, tm);
+      lsk::launch_hodlr_upd_dot(H.Y16[pend].p, H.rank[pend], svec, H.N >> pend, 1 << pend, W, rl, z,
+                                H.N, partial, H.chunk[l], s, H.ract.as<unsigned char>());
     } else {
       if (pend >= 0) update(pend, false);
-      ProfScope pd(P, 5, s);
-      lsk::launch_hodlr_dot(fmt, W, z, ldz, H.partial.as<double2>(), H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s,
+      ProfScope pd(P, 5, s, tm);
+      lsk::launch_hodlr_dot(fmt, W, z, ldz, partial, H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s,
                             cact ? H.dlist.as<int>() + H.doff[l] : nullptr, cact ? H.dcnt[l] : 0, H.cpc[l]);
     }
     pend = -1;
@@ -839,8 +861,8 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
     const int cf = P->opt.pc_lowp_solves ? fmt : 0;
     const void* C = cf == 2 ? H.core16[l].p : (cf == 1 ? H.core32[l].p : H.coreinv[l].p);
     {
-      ProfScope pc(P, 7, s);
-      lsk::launch_hodlr_core(cf, C, H.partial.as<double2>(), H.svec.as<double2>(), rl, nodes, H.cpc[l], H.nchunks[l],
+      ProfScope pc(P, 7, s, tm);
+      lsk::launch_hodlr_core(cf, C, partial, svec, rl, nodes, H.cpc[l], H.nchunks[l],
                              true, nrhs, s, cact);
     }
     pend = l;
@@ -1856,6 +1878,39 @@ zd self_cell(double h, double kappa) {
   return 8.0 * acc;
 }
 
+// ---------------------------------------------------------------------------------------
+// Device scratch of the allocation-free preconditioner apply: a fixed array in the code object
+// (one copy per GPU, allocated when the library's code is loaded there, kept until the process
+// ends).  Host code never passes the array's name to a kernel: its device address is looked up
+// once per device with hipGetSymbolAddress and only that address is used.
+// ---------------------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;  // per device ordinal: device address of `scratch`, or null
+
+// device address of the scratch array on the current device (looked up once per device)
+void* scratch_address(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize(device + 1, nullptr);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      throw LsError(LS_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[device] = ptr;
+  }
+  return g_scratch_dev[device];
+}
+
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
 ls_status fail(const LsError& e) {
   g_last_error = e.what();
   return (ls_status)e.code;
@@ -1995,6 +2050,9 @@ ls_status ls_setup(const double* points, int64_t N, const double* q, double kapp
     P->gx0 = xmin;
     P->gy0 = ymin;
     P->gh = h;
+    // the inputs are valid: from here on the setup works on the current device
+    hip_check(hipGetDevice(&P->device), "hipGetDevice");
+    P->scratch = scratch_address(P->device);
     P->g2c.upload(grid2caller);
     P->kappa = kappa;
     P->tol = tol;
@@ -2233,6 +2291,46 @@ ls_status ls_precond_apply(ls_problem* P, const void* r, void* z, int nrhs, int6
     hodlr_apply(P, fmt, a, N, a, N, nrhs, 0, s);
     lsk::launch_permute(a, N, (double2*)z, ld, P->m2c.as<int>(), N, nrhs, true, s);
     hip_check(hipGetLastError(), "precond");
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
+}
+
+ls_status ls_precond_apply_noalloc(ls_problem* P, const void* r, void* z, int nrhs, int64_t ld, int prec,
+                                   void* stream) {
+  try {
+    check_vec_args(P, r, z, nrhs, ld);
+    if (prec != LS_FP64 && prec != LS_FP32 && prec != LS_MIXED)
+      throw LsError(LS_EINVAL, "prec must be LS_FP64, LS_FP32 or LS_MIXED");
+    if (!P->have_hodlr) throw LsError(LS_ENOTSUP, "no HODLR preconditioner (hodlr_rank = 0)");
+    int dev = -1;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != P->device) throw LsError(LS_EINVAL, "the current device is not the problem's device");
+    const HodlrDev& H = P->hod;
+    const long long N = P->N;
+    size_t np = 0, ns = 0;
+    hodlr_ws_elems(H, &np, &ns);
+    // layout: Morton copy of r (N x nrhs), chunk partials, s vectors; each 256-byte aligned
+    const size_t b_vec = align256((size_t)N * nrhs * 16), b_part = align256(np * nrhs * 16),
+                 b_svec = align256(ns * nrhs * 16);
+    const size_t need = b_vec + b_part + b_svec;
+    if (need > kScratchBytes)
+      throw LsError(LS_EINVAL, "ls_precond_apply_noalloc: needs " + std::to_string(need) + " bytes of scratch for N = " +
+                                   std::to_string(N) + ", nrhs = " + std::to_string(nrhs) + "; the maximum is " +
+                                   std::to_string(kScratchBytes));
+    char* base = (char*)P->scratch;
+    double2* a = (double2*)base;
+    HodlrWs ws;
+    ws.partial = (double2*)(base + b_vec);
+    ws.svec = (double2*)(base + b_vec + b_part);
+    ws.timers = false;
+    hipStream_t s = (hipStream_t)stream;
+    lsk::launch_permute((const double2*)r, ld, a, N, P->m2c.as<int>(), N, nrhs, false, s);
+    const int fmt = prec == LS_FP64 ? 0 : (prec == LS_MIXED && H.have16 ? 2 : 1);
+    hodlr_apply(P, fmt, a, N, a, N, nrhs, 0, s, nullptr, 0, nullptr, 0, 0, &ws);
+    lsk::launch_permute(a, N, (double2*)z, ld, P->m2c.as<int>(), N, nrhs, true, s);
+    hip_check(hipGetLastError(), "precond (no allocation)");
     return LS_OK;
   } catch (const LsError& e) {
     return fail(e);

@@ -88,7 +88,7 @@ def lib():
     L.ls_default_options.restype = None
     L.ls_last_error.restype = C.c_char_p
     L.ls_setup.argtypes = [vp, i64, vp, cd, cd, C.POINTER(_Options), C.POINTER(vp)]
-    for name in ("ls_matvec", "ls_apply_V", "ls_precond_apply"):
+    for name in ("ls_matvec", "ls_apply_V", "ls_precond_apply", "ls_precond_apply_noalloc"):
         getattr(L, name).argtypes = [vp, vp, vp, ci, i64, ci, vp]
     L.ls_rhs_planewave.argtypes = [vp, vp, ci, vp, i64, vp]
     L.ls_solve.argtypes = [vp, vp, vp, ci, i64, cd, ci, ci, C.POINTER(_Info), vp]
@@ -121,7 +121,8 @@ def lib():
     for name in ("ls_nop_create", "ls_nop_forward", "ls_nop_backward", "ls_nop_loss", "ls_nop_adam_step",
                  "ls_nop_features", "ls_nop_warmstart"):
         getattr(L, name).restype = C.c_int
-    for name in ("ls_setup", "ls_matvec", "ls_apply_V", "ls_precond_apply", "ls_rhs_planewave", "ls_solve",
+    for name in ("ls_setup", "ls_matvec", "ls_apply_V", "ls_precond_apply", "ls_precond_apply_noalloc",
+                 "ls_rhs_planewave", "ls_solve",
                  "ls_stats", "ls_plan_describe", "ls_profile_enable", "ls_profile_read", "ls_green_table",
                  "ls_solve_queue", "ls_autotune"):
         getattr(L, name).restype = C.c_int
@@ -262,6 +263,15 @@ class Problem:
         nrhs = _vec(r, self.N)
         z = self._out(r, z)
         _check(lib().ls_precond_apply(self._h, r.data_ptr(), z.data_ptr(), nrhs, self.N, prec, _stream(stream)))
+        return z
+
+    def precond_apply_noalloc(self, r, z, prec: int = LS_FP64, stream=None):
+        """ls_precond_apply_noalloc: z must be given (the call allocates nothing)."""
+        nrhs = _vec(r, self.N)
+        if _vec(z, self.N) != nrhs:
+            raise ValueError("z must have the shape of r")
+        _check(lib().ls_precond_apply_noalloc(self._h, r.data_ptr(), z.data_ptr(), nrhs, self.N, prec,
+                                              _stream(stream)))
         return z
 
     def field_eval(self, targets, psi, stream=None):
