@@ -109,6 +109,11 @@ typedef struct {
                          ||u_k|| ||v_k|| <= eps ||S_k||_F (the HODLR factorisation at a fixed
                          tolerance, Section 6), its rank still capped by hodlr_rank; for
                          ls_direct_solve */
+  int fmm_fused;      /* with stencil_mfma = 1: 1 every DAFMM pass of a product runs in one persistent
+                         launch whose workgroups take the passes' blocks from a queue in dependency
+                         order (the near field fills the waits of the upward and downward chains;
+                         same sums per block, bit-identical results); 0 (default): one launch per
+                         pass, faster on this part (the chain blocks slow down under the filler) */
 } ls_options;
 
 typedef struct {
@@ -319,7 +324,9 @@ ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt,
  * field + M2L launch (FP64 operator), 1 = HODLR level update, 2 = HODLR leaf solve,
  * 3 = Arnoldi dot products, 4 = near field + M2L launch (FP32 operator), 5 = HODLR level dot
  * products (W^T z), 6 = HODLR level update fused with the next level's dot products (complex
- * bfloat16 factors, one right-hand side), 7 = HODLR SMW core products s = K^-1 t.  every > 0 starts (and clears) the counters and times every every-th
+ * bfloat16 factors, one right-hand side), 7 = HODLR SMW core products s = K^-1 t, 8 = the fused
+ * DAFMM launch (every pass, FP64 operator), 9 = the same with the FP32 operator.  every > 0
+ * starts (and clears) the counters and times every every-th
  * launch of the class (timed dispatches run one at a time, so sparse sampling keeps the
  * timed run close to an untimed one); 0 stops.  ls_profile_read synchronises and returns the
  * summed time and number of the timed launches, and (all_launches, may be NULL) the number

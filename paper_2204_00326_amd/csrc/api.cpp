@@ -8,7 +8,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <queue>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -147,6 +149,12 @@ struct FmmDev {
   Phase p2m, nearm2l, l2p;
   std::vector<Phase> up;    // M2M, deepest parent first
   std::vector<Phase> down;  // L2L, top parent first
+  // every pass in one persistent launch (matrix-core form): all tasks and terms, the queue of
+  // (task, block) pairs, stage sizes, and the counters (ticket, one per stage, error flag)
+  Phase fused;
+  DevBuf fneed, fctr;
+  int nstages = 0;
+  int fused_wg = 0;
   // host copies of per-level ranks
   std::vector<std::vector<int>> rank;
   std::vector<int> kmax;
@@ -256,7 +264,7 @@ struct ls_problem {
   DevBuf w_x, w_y, w_t;  // Morton-order vectors (nrhs_cap)
   int ws_cap = 0;
   ls_stats_t stats{};
-  ProfileClass prof[8];
+  ProfileClass prof[16];
   // Krylov workspace
   DevBuf kQ, kZ, kw, kz, kr, kh, kpart, knp, kno, kalpha, ky, kx, kf, kdx;
   size_t kcap_key = 0;
@@ -418,6 +426,28 @@ void build_phases(ls_problem* P, FmmDev& F) {
     return (void*)(base + (F.lvl_off[nu] + (long long)dir * F.kmax[nu] * 4 * nh * nh) * es);
   };
   const long long N = P->N;
+  // stages of the fused launch: P2M, near field, M2M per parent level, M2L per level, L2L per
+  // parent level, L2P; a task's stage and prerequisites are set where the task is made
+  const int nup = p.top <= leaf ? leaf - p.top : 0;
+  const int S_P2M = 0, S_NEAR = 1;
+  auto S_UP = [&](int nu) { return 2 + (nu - p.top); };
+  auto S_M2L = [&](int nu) { return 2 + nup + (nu - p.top); };
+  auto S_DOWN = [&](int nu) { return 2 + nup + (nup + 1) + (nu - p.top); };
+  const int S_L2P = 2 + 3 * nup + 1;
+  const int nst = p.top <= leaf ? S_L2P + 1 : 2;
+  auto set_stage = [](lsk::DTask& tk, int st, int d0, int d1, int d2, int coh_out) {
+    tk.stage = st;
+    tk.dep[0] = d0;
+    tk.dep[1] = d1;
+    tk.dep[2] = d2;
+    tk.coh_out = coh_out;
+  };
+  struct HostPhase {
+    std::vector<lsk::DTask> tasks;
+    std::vector<lsk::DTerm> terms;
+    std::vector<int> pairs;
+  };
+  std::vector<HostPhase> hps;
   auto make_phase = [&](Phase& ph, std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms) {
     std::vector<int> blk;
     for (size_t t = 0; t < tasks.size(); ++t) {
@@ -486,6 +516,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
     ph.nblocks = (int)blk.size();
     ph.ntasks = (int)tasks.size();
     ph.mfma = true;
+    hps.push_back({tasks, terms, pairs});
   };
   auto mk_phase = [&](Phase& ph, std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms) {
     if (P->opt.stencil_mfma)
@@ -517,6 +548,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
       tk.nh = nhL;
       tk.cout = c;
       tk.beta = 0;
+      set_stage(tk, S_NEAR, -1, -1, -1, p.top <= leaf ? 1 : 0);
       tk.t0 = (int)terms.size();
       for (int da = -1; da <= 1; ++da)
         for (int db = -1; db <= 1; ++db) {
@@ -545,6 +577,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
           tk.nh = nh;
           tk.cout = c;
           tk.beta = 0;
+          set_stage(tk, S_M2L(nu), nu == leaf ? S_P2M : S_UP(nu), -1, -1, 1);
           tk.t0 = (int)terms.size();
           if (F.rank[nu][ad] > 0)
             for (const Off& d : l.terms[c * l.ndir + dir]) {
@@ -556,6 +589,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
               tm.in = lvl_ptr(mult, nu, ad);
               tm.in_rhs = F.ml_rhs;
               tm.K = F.rank[nu][ad];
+              tm.coh = 1;
               terms.push_back(tm);
             }
           tk.t1 = (int)terms.size();
@@ -566,7 +600,133 @@ void build_phases(ls_problem* P, FmmDev& F) {
     mk_phase(F.nearm2l, tasks, terms);
     F.nearm2l.tag = 0;
   }
-  if (p.top > leaf) return;
+
+  // ---- the fused launch: every task and term of the phases above, and the queue ----
+  auto build_fused = [&]() {
+    F.fused = Phase();
+    F.nstages = 0;
+    // one flag bit per stage (bit 31 marks a wait that ran out): at most 31 stages
+    if (!P->opt.stencil_mfma || nst > 31) return;
+    std::vector<lsk::DTask> ft;
+    std::vector<lsk::DTerm> fm;
+    struct Item {
+      int task, local, stage;
+      double cost;
+    };
+    std::vector<Item> items;
+    for (auto& hp : hps) {
+      const int toff = (int)ft.size(), moff = (int)fm.size();
+      for (lsk::DTask tk : hp.tasks) {
+        tk.t0 += moff;
+        tk.t1 += moff;
+        ft.push_back(tk);
+      }
+      fm.insert(fm.end(), hp.terms.begin(), hp.terms.end());
+      for (size_t q = 0; q + 1 < hp.pairs.size(); q += 2) {
+        const lsk::DTask& tk = hp.tasks[hp.pairs[q]];
+        // cost in k-blocks per wave plus a fixed part (waits, term set-up, stores)
+        items.push_back({hp.pairs[q] + toff, hp.pairs[q + 1], tk.stage, (double)((tk.ktot + tk.kps - 1) / tk.kps) + 8.0});
+      }
+    }
+    if (items.empty()) return;
+    std::vector<std::vector<int>> sitems(nst);
+    std::vector<std::array<int, 3>> sdep(nst, std::array<int, 3>{-1, -1, -1});
+    for (size_t i = 0; i < items.size(); ++i) sitems[items[i].stage].push_back((int)i);
+    for (const lsk::DTask& tk : ft) sdep[tk.stage] = {tk.dep[0], tk.dep[1], tk.dep[2]};
+    // list scheduling on W resident workgroups: whenever a workgroup frees up, it takes the next
+    // block of the ready stage with the longest remaining chain (a stage is ready once every
+    // block of its prerequisites is placed and finished); with none ready, the stage that gets
+    // ready first.  Every block thus follows all blocks of its prerequisite stages in the queue.
+    const int W = std::max(1, lsk::dafmm_fused_workgroups(F.fp32));
+    std::vector<double> span(nst, 0.0), blev(nst, -1.0);
+    for (int st = 0; st < nst; ++st) {
+      double tot = 0, mx = 0;
+      for (int i : sitems[st]) {
+        tot += items[i].cost;
+        mx = std::max(mx, items[i].cost);
+      }
+      span[st] = tot / W + mx;
+    }
+    std::function<double(int)> bl = [&](int st) -> double {
+      if (blev[st] >= 0) return blev[st];
+      double best = 0;
+      for (int u = 0; u < nst; ++u)
+        for (int d : sdep[u])
+          if (d == st) best = std::max(best, bl(u));
+      return blev[st] = span[st] + best;
+    };
+    for (int st = 0; st < nst; ++st) bl(st);
+    std::priority_queue<double, std::vector<double>, std::greater<double>> slots;
+    for (int w = 0; w < W; ++w) slots.push(0.0);
+    std::vector<size_t> next(nst, 0);
+    std::vector<double> done(nst, 0.0);
+    auto full = [&](int st) { return next[st] == sitems[st].size(); };
+    std::vector<int> order;
+    order.reserve(2 * items.size());
+    for (size_t placed = 0; placed < items.size(); ++placed) {
+      const double t = slots.top();
+      slots.pop();
+      int pick = -1, wait = -1;
+      double wait_t = 0;
+      for (int st = 0; st < nst; ++st) {
+        if (full(st)) continue;
+        bool ok = true;
+        double rt = 0;
+        for (int d : sdep[st])
+          if (d >= 0) {
+            if (!full(d)) ok = false;
+            rt = std::max(rt, done[d]);
+          }
+        if (!ok) continue;
+        if (rt <= t) {
+          if (pick < 0 || blev[st] > blev[pick]) pick = st;
+        } else if (wait < 0 || rt < wait_t || (rt == wait_t && blev[st] > blev[wait])) {
+          wait = st;
+          wait_t = rt;
+        }
+      }
+      if (pick < 0) pick = wait;
+      if (pick < 0) throw LsError(LS_EINVAL, "internal: fused DAFMM schedule has no eligible stage");
+      double rt = 0;
+      for (int d : sdep[pick])
+        if (d >= 0) rt = std::max(rt, done[d]);
+      const Item& it = items[sitems[pick][next[pick]++]];
+      const double fin = std::max(t, rt) + it.cost;
+      done[pick] = std::max(done[pick], fin);
+      slots.push(fin);
+      order.push_back(it.task);
+      order.push_back(it.local);
+    }
+    std::vector<unsigned> need(nst, 0);
+    for (int st = 0; st < nst; ++st) need[st] = (unsigned)sitems[st].size();
+    // the property every wait relies on: all blocks of a block's prerequisite stages come earlier
+    {
+      std::vector<unsigned> seen(nst, 0);
+      for (size_t q = 0; q < order.size(); q += 2) {
+        const lsk::DTask& tk = ft[order[q]];
+        for (int d : tk.dep)
+          if (d >= 0 && (d >= nst || seen[d] != need[d]))
+            throw LsError(LS_EINVAL, "internal: fused DAFMM queue is not in dependency order");
+        seen[tk.stage]++;
+      }
+    }
+    F.fused.tasks.upload(ft);
+    F.fused.terms.upload(fm);
+    F.fused.blk.upload(order);
+    F.fused.nblocks = (int)items.size();
+    F.fused.ntasks = (int)ft.size();
+    F.fused.mfma = true;
+    F.fneed.upload(need);
+    const size_t cbytes = (size_t)lsk::dafmm_fused_counter_lines(nst) * 128;
+    F.fctr.alloc(cbytes);
+    hip_check(hipMemset(F.fctr.p, 0, cbytes), "memset");
+    F.nstages = nst;
+    F.fused_wg = W;
+  };
+  if (p.top > leaf) {
+    build_fused();
+    return;
+  }
   // ---- P2M ----
   {
     std::vector<lsk::DTask> tasks;
@@ -579,6 +739,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
       tk.nh = nhL;
       tk.cout = c;
       tk.beta = 0;
+      set_stage(tk, S_P2M, -1, -1, -1, 1);
       tk.t0 = (int)terms.size();
       lsk::DTerm tm{};
       tm.mode = lsk::MODE_SAME;
@@ -606,6 +767,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
       tk.nh = nhL;
       tk.cout = c;
       tk.beta = 1;
+      set_stage(tk, S_L2P, nup > 0 ? S_DOWN(leaf - 1) : -1, S_M2L(leaf), S_NEAR, 0);
       tk.t0 = (int)terms.size();
       lsk::DTerm tm{};
       tm.mode = lsk::MODE_SAME;
@@ -613,6 +775,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
       tm.in = lvl_ptr(loc, leaf, 0);
       tm.in_rhs = F.ml_rhs;
       tm.K = F.kleaf;
+      tm.coh = 1;
       tm.nh_in = nhL;
       terms.push_back(tm);
       tk.t1 = (int)terms.size();
@@ -640,6 +803,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
         tk.nh = nh;
         tk.cout = c;
         tk.beta = 0;
+        set_stage(tk, S_UP(nu), nu == leaf - 1 ? S_P2M : S_UP(nu + 1), -1, -1, 1);
         tk.t0 = (int)terms.size();
         for (int cc = 0; cc < 4; ++cc) {
           lsk::DTerm tm{};
@@ -648,6 +812,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
           tm.op = opp(F.off_C[nu][dir][cc]);
           tm.in = lvl_ptr(mult, nu + 1, cd);
           tm.in_rhs = F.ml_rhs;
+          tm.coh = 1;
           tm.K = F.rank[nu + 1][cd];
           tm.nh_in = cl.nb / 2;
           if (tm.K > 0) terms.push_back(tm);
@@ -677,6 +842,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
         tk.nh = nhc;
         tk.cout = c;
         tk.beta = 1;
+        set_stage(tk, S_DOWN(nu), S_M2L(nu), S_M2L(nu + 1), nu > p.top ? S_DOWN(nu - 1) : -1, 1);
         tk.t0 = (int)terms.size();
         for (int dir = 0; dir < l.ndir; ++dir) {
           int cd = cl.hf ? dir / 2 : 0;
@@ -686,6 +852,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
           tm.op = opp(F.off_Ct[nu][dir][c]);
           tm.in = lvl_ptr(loc, nu, dir);
           tm.in_rhs = F.ml_rhs;
+          tm.coh = 1;
           tm.K = F.rank[nu][dir];
           tm.nh_in = l.nb / 2;
           if (tm.K > 0) terms.push_back(tm);
@@ -697,6 +864,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
     mk_phase(F.down[nu - p.top], tasks, terms);
     F.down[nu - p.top].tag = 3;
   }
+  build_fused();
 }
 
 void ensure_fmm_capacity(ls_problem* P, FmmDev& F, int nrhs) {
@@ -746,15 +914,34 @@ void run_phase(ls_problem* P, FmmDev& F, Phase& ph, int nrhs, hipStream_t s, int
 }
 
 // y = alpha x + coef diag(q) (V x) in Morton (mode 0) or caller (mode 1) order.
+// y = alpha x + coef diag(q) (V x) in Morton (mode 0) or caller (mode 1) order; with_q = false:
+// y = alpha x + coef (V x).
 void fmm_apply(ls_problem* P, bool fp32, const double2* x, long long ldx, double2* y, long long ldy, int nrhs,
-               double alpha, double coef, bool caller_order, hipStream_t s) {
+               double alpha, double coef, bool caller_order, hipStream_t s, bool with_q = true) {
   FmmDev& F = fp32 ? P->f32 : P->f64;
   if (fp32 && !P->have32) throw LsError(LS_ENOTSUP, "FP32 operator was not built (build_fp32 = 0)");
   ensure_fmm_capacity(P, F, nrhs);
   const long long N = P->N;
   const int* gidx = caller_order ? P->s2c.as<int>() : P->s2m.as<int>();
   const int* eidx = caller_order ? P->c2s.as<int>() : P->m2s.as<int>();
-  const double* q = caller_order ? P->q_c.as<double>() : P->q_m.as<double>();
+  const double* q = !with_q ? nullptr : (caller_order ? P->q_c.as<double>() : P->q_m.as<double>());
+  if (P->opt.fmm_fused && F.fused.nblocks > 0) {
+    // every pass in one persistent launch between the gather (which also zeroes its counters)
+    // and the epilogue
+    unsigned* ctr = F.fctr.as<unsigned>();
+    const int lines = lsk::dafmm_fused_counter_lines(F.nstages);
+    const unsigned* err = ctr + 32 * (1 + F.nstages);  // first group flag word (bit 31: a wait ran out)
+    lsk::launch_gather_zero(fp32, x, ldx, F.xs.p, gidx, N, nrhs, ctr, lines, s);
+    {
+      ProfScope ps(P, fp32 ? 9 : 8, s);
+      lsk::launch_dafmm_fused(fp32, F.fused.tasks.as<lsk::DTask>(), F.fused.terms.as<lsk::DTerm>(),
+                              F.fused.blk.as<int>(), F.fused.nblocks, nrhs, F.nstages, ctr, F.fneed.as<unsigned>(),
+                              F.fused_wg, s);
+    }
+    lsk::launch_epilogue_checked(fp32, x, ldx, F.ys.p, eidx, q, alpha, coef, y, ldy, N, nrhs, err, s);
+    hip_check(hipGetLastError(), "fused fmm kernels");
+    return;
+  }
   lsk::launch_gather(fp32, x, ldx, F.xs.p, gidx, N, nrhs, s);
   const ls::Plan& p = P->plan;
   if (p.top <= p.leaf) {
@@ -1567,6 +1754,9 @@ void kd_key_fmm(std::vector<uintptr_t>& k, const FmmDev& F) {
   kd_key_phase(k, F.l2p);
   for (const Phase& ph : F.up) kd_key_phase(k, ph);
   for (const Phase& ph : F.down) kd_key_phase(k, ph);
+  kd_key_phase(k, F.fused);
+  for (const DevBuf* b : {&F.fneed, &F.fctr}) k.push_back((uintptr_t)b->p);
+  k.push_back((uintptr_t)F.fused_wg);
 }
 
 // everything a captured step depends on: sizes, modes and every device address it touches
@@ -1939,6 +2129,7 @@ void ls_default_options(ls_options* o) {
   o->hodlr_rank_div = 0;
   o->graph_iters = 0;
   o->stencil_mfma = 1;
+  o->fmm_fused = 0;
   o->pc_bf16 = 1;
   o->pc_lowp_solves = 0;
   o->hodlr_tol = 0.0;
@@ -1960,6 +2151,7 @@ static void validate_options(const ls_options& o) {
   if (o.hodlr_rank_div < 0) throw LsError(LS_EINVAL, "hodlr_rank_div must be >= 0");
   if (o.graph_iters < 0 || o.graph_iters > 64) throw LsError(LS_EINVAL, "graph_iters must be in [0, 64]");
   if (o.stencil_mfma != 0 && o.stencil_mfma != 1) throw LsError(LS_EINVAL, "stencil_mfma must be 0 or 1");
+  if (o.fmm_fused != 0 && o.fmm_fused != 1) throw LsError(LS_EINVAL, "fmm_fused must be 0 or 1");
   if (o.pc_bf16 != 0 && o.pc_bf16 != 1) throw LsError(LS_EINVAL, "pc_bf16 must be 0 or 1");
   if (o.pc_lowp_solves != 0 && o.pc_lowp_solves != 1) throw LsError(LS_EINVAL, "pc_lowp_solves must be 0 or 1");
   if (!(o.hodlr_tol >= 0 && o.hodlr_tol < 1)) throw LsError(LS_EINVAL, "hodlr_tol must be in [0, 1)");
@@ -2242,26 +2434,9 @@ ls_status ls_apply_V(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld
     if (prec != LS_FP64 && prec != LS_FP32 && prec != LS_MIXED)
       throw LsError(LS_EINVAL, "prec must be LS_FP64, LS_FP32 or LS_MIXED");
     if (x == y) throw LsError(LS_EINVAL, "x and y must not overlap");
-    hipStream_t s = (hipStream_t)stream;
-    // y = V x : epilogue with alpha = 0, coef = 1 and no contrast
-    FmmDev& F = prec == LS_FP32 ? P->f32 : P->f64;
-    if (prec == LS_FP32 && !P->have32) throw LsError(LS_ENOTSUP, "FP32 operator was not built");
-    ensure_fmm_capacity(P, F, nrhs);
-    const long long N = P->N;
-    lsk::launch_gather(F.fp32, (const double2*)x, ld, F.xs.p, P->s2c.as<int>(), N, nrhs, s);
-    const ls::Plan& p = P->plan;
-    if (p.top <= p.leaf) {
-      run_phase(P, F, F.p2m, nrhs, s);
-      for (auto& ph : F.up) run_phase(P, F, ph, nrhs, s);
-    }
-    run_phase(P, F, F.nearm2l, nrhs, s);
-    if (p.top <= p.leaf) {
-      for (auto& ph : F.down) run_phase(P, F, ph, nrhs, s);
-      run_phase(P, F, F.l2p, nrhs, s);
-    }
-    lsk::launch_epilogue(F.fp32, (const double2*)x, ld, F.ys.p, P->c2s.as<int>(), nullptr, 0.0, 1.0, (double2*)y, ld,
-                         N, nrhs, s);
-    hip_check(hipGetLastError(), "apply_V");
+    // y = V x: the epilogue with alpha = 0, coef = 1 and no contrast
+    fmm_apply(P, prec == LS_FP32, (const double2*)x, ld, (double2*)y, ld, nrhs, 0.0, 1.0, true, (hipStream_t)stream,
+              false);
     return LS_OK;
   } catch (const LsError& e) {
     return fail(e);
@@ -2810,7 +2985,7 @@ void ls_destroy(ls_problem* P) {
 }
 
 ls_status ls_profile_enable(ls_problem* P, int cls, int every) {
-  if (!P || cls < 0 || cls > 7 || every < 0) {
+  if (!P || cls < 0 || cls > 9 || every < 0) {
     g_last_error = "bad arguments";
     return LS_EINVAL;
   }
@@ -2826,7 +3001,7 @@ ls_status ls_profile_enable(ls_problem* P, int cls, int every) {
 
 ls_status ls_profile_read(ls_problem* P, int cls, double* total_ms, int64_t* launches, int64_t* all_launches) {
   try {
-    if (!P || cls < 0 || cls > 7 || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
+    if (!P || cls < 0 || cls > 9 || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
     ProfileClass& pc = P->prof[cls];
     double tot = 0;
     for (size_t i = 0; i < pc.used; ++i) {

@@ -27,6 +27,7 @@ struct DTerm {
   int sha, shb;     // SHIFT: shift in the class half-grid
   int nh_in;        // half-grid side of the input level
   int kbase;        // sum of K over the task's earlier terms
+  int coh;          // fused form: the input is written inside the same launch (read it coherently)
 };
 
 struct DTask {
@@ -41,6 +42,12 @@ struct DTask {
   int blk0;          // first workgroup of this task
   int ktot;          // sum of K over the task's terms (MFMA form: of the 4-deep k-blocks)
   int kps;           // MFMA form: waves of a workgroup that split the k-blocks (1, 2 or 4)
+  // fused form (one launch for every pass): the stage this task's blocks count into, up to three
+  // stages that must be complete before a block starts (-1: none), and whether the output is read
+  // inside the same launch (written coherently)
+  int stage;
+  int dep[3];
+  int coh_out;
 };
 
 constexpr int kRowBlock = 8;
@@ -54,6 +61,30 @@ void launch_stencil_mfma(bool fp32, const DTask* tasks, const DTerm* terms, cons
                          int nrhs, hipStream_t s);
 void launch_stencil(int tag, bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
                     int nrhs, hipStream_t s);
+
+// Every DAFMM pass in one persistent launch.  queue: (task, block within the task) pairs in
+// an order in which every block's prerequisite stages come earlier; workgroups take the pairs
+// (times nrhs right-hand sides, right-hand side fastest) by an atomic ticket, wait until the
+// stages their task depends on are complete, compute the block and count it into the task's
+// stage.  ctr: the counter block of dafmm_fused_counter_lines(nst) lines, zeroed (first word of
+// each line); need: blocks per stage for one right-hand side.  If a wait runs out of its bound,
+// bit 31 of the group flag words is set and the results are invalid (launch_epilogue_checked,
+// given the first flag word, writes NaN).
+void launch_dafmm_fused(bool fp32, const DTask* tasks, const DTerm* terms, const int* queue, int nitems, int nrhs,
+                        int nst, unsigned* ctr, const unsigned* need, int nwg, hipStream_t s);
+// 128-byte lines of the fused launch's counter block for nst stages (ticket, stage counts, 64
+// group flag words; the first unsigned of each line is used)
+int dafmm_fused_counter_lines(int nst);
+// workgroups the fused launch keeps resident (all CUs times its occupancy)
+int dafmm_fused_workgroups(bool fp32);
+// launch_gather, and zero the first unsigned of `nz` 128-byte lines at `zero` (the fused launch's
+// counter block)
+void launch_gather_zero(bool to_fp32, const double2* x, long long ldx, void* xs, const int* idx, long long N, int nrhs,
+                        unsigned* zero, int nz, hipStream_t s);
+// launch_epilogue; if bit 31 of *err is set, y is NaN
+void launch_epilogue_checked(bool from_fp32, const double2* x, long long ldx, const void* ys, const int* idx,
+                             const double* q, double alpha, double coef, double2* y, long long ldy, long long N,
+                             int nrhs, const unsigned* err, hipStream_t s);
 
 // ---- setup ----
 void launch_wtable(double2* W, int n, double h, double kappa, hipStream_t s);

@@ -327,21 +327,35 @@ struct MfmaAcc<float> {
   __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-template <typename T>
-__global__ __launch_bounds__(256, 6) void k_stencil_mfma(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms,
-                                                      const int* __restrict__ blk_task) {
+// coherent (device-scope) loads and stores for data written and read inside one launch by
+// different workgroups: relaxed agent-scope atomics, which neither hit nor leave stale copies
+// in the per-CU and per-XCD caches
+template <typename C2>
+__device__ inline C2 ld_coh(const C2* p) {
+  C2 v;
+  v.x = __hip_atomic_load(&p->x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  v.y = __hip_atomic_load(&p->y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return v;
+}
+template <typename C2>
+__device__ inline void st_coh(C2* p, const C2& v) {
+  __hip_atomic_store(&p->x, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&p->y, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One block of the stencil GEMM: task ti, block `local` within the task, right-hand side rhs.
+// COH: honour the coherence flags of the fused launch (inputs and outputs produced or consumed
+// by other workgroups of the same launch).  Called by all 256 threads; contains one barrier
+// when the task splits its k-blocks over waves (kps > 1).
+template <typename T, bool COH>
+__device__ __forceinline__ void mfma_block(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms, int ti,
+                                           int local, int rhs, T (*red)[8][64]) {
   using C2 = typename P2<T>::type;
   using MA = MfmaAcc<T>;
   using V4 = typename MA::type;
-  __shared__ T red[3][8][64];
-  const int blk = blockIdx.x;
-  const int rhs = blockIdx.y;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  // blk_task holds (task, block within the task) pairs in dispatch order, heaviest blocks first
-  const int ti = __builtin_amdgcn_readfirstlane(blk_task[2 * blk]);
   const DTask& tk = tasks[ti];
-  const int local = __builtin_amdgcn_readfirstlane(blk_task[2 * blk + 1]);
   const int rt = local % tk.nrb;
   const int bb = local / tk.nrb;
   const int kps = tk.kps;             // 1, 2 or 4
@@ -365,7 +379,7 @@ __global__ __launch_bounds__(256, 6) void k_stencil_mfma(const DTask* __restrict
   int t = tk.t0;
   while (t < tk.t1 && terms[t].kbase + ((terms[t].K + 3) >> 2) <= b0) ++t;  // skips empty terms too
   int pb = 0, pnb = 0, pK = 0;     // block inside the term, blocks and K of the term
-  bool pok = false;
+  bool pok = false, pcoh = false;
   const C2* pin = nullptr;
   const C2* pop = nullptr;
   long long pks = 0;
@@ -374,6 +388,7 @@ __global__ __launch_bounds__(256, 6) void k_stencil_mfma(const DTask* __restrict
     pK = tm.K;
     pnb = (tm.K + 3) >> 2;
     pb = first_block;
+    pcoh = COH && tm.coh;
     const int nhi = tm.nh_in;
     const long long plane = (long long)nhi * nhi;
     long long src = 0;
@@ -416,7 +431,10 @@ __global__ __launch_bounds__(256, 6) void k_stencil_mfma(const DTask* __restrict
     const int k = 4 * pb + lk;
     const bool vk = k < pK;
     a = pop[(long long)(vk ? k : 0) * Mp];
-    x = pin[(long long)(vk ? k : 0) * pks];
+    if (COH && pcoh)
+      x = ld_coh(pin + (long long)(vk ? k : 0) * pks);
+    else
+      x = pin[(long long)(vk ? k : 0) * pks];
     va = vk && arow;
     vx = vk && pok;
     ++g;
@@ -477,6 +495,7 @@ __global__ __launch_bounds__(256, 6) void k_stencil_mfma(const DTask* __restrict
   if (!bact) return;
   C2* out = reinterpret_cast<C2*>(tk.out) + rhs * tk.out_rhs + (long long)tk.cout * nbox + box;
   const long long kso = 4LL * nbox;
+  const bool coh = COH && tk.coh_out;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int m = rt * 16 + MA::row(lane, v);
@@ -484,14 +503,28 @@ __global__ __launch_bounds__(256, 6) void k_stencil_mfma(const DTask* __restrict
       C2 o;
       o.x = cre[v];
       o.y = cim[v];
+      C2* po = out + (long long)m * kso;
       if (tk.beta) {
-        const C2 p = out[(long long)m * kso];
+        const C2 p = coh ? ld_coh(po) : *po;
         o.x += p.x;
         o.y += p.y;
       }
-      out[(long long)m * kso] = o;
+      if (coh)
+        st_coh(po, o);
+      else
+        *po = o;
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 6) void k_stencil_mfma(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms,
+                                                      const int* __restrict__ blk_task) {
+  __shared__ T red[3][8][64];
+  // blk_task holds (task, block within the task) pairs in dispatch order, heaviest blocks first
+  const int ti = __builtin_amdgcn_readfirstlane(blk_task[2 * blockIdx.x]);
+  const int local = __builtin_amdgcn_readfirstlane(blk_task[2 * blockIdx.x + 1]);
+  mfma_block<T, false>(tasks, terms, ti, local, blockIdx.y, red);
 }
 
 void launch_stencil_mfma(bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
@@ -506,6 +539,115 @@ void launch_stencil_mfma(bool fp32, const DTask* tasks, const DTerm* terms, cons
     LSK_LAUNCH(kern, grid, 256, 0, s, tasks, terms, blk_task);
   }
 }
+
+// =====================================================================================
+// All DAFMM passes in one persistent launch.  Each workgroup loops: take a ticket (an atomic
+// counter), map it to (queue item, right-hand side), wait until every stage the item's task
+// depends on is complete, compute the block (mfma_block with coherent loads of in-launch
+// inputs and coherent stores of in-launch outputs), then count it into its stage.  The
+// workgroup whose count completes a stage sets the stage's bit in 64 flag words, one per group
+// of workgroups (blockIdx % 64, so each group sits on one XCD), and waiting workgroups poll
+// their group's word: the polls spread over 64 cache lines instead of hammering one.
+// The queue is in dependency order, so the earliest unfinished ticket never waits on a later
+// one: every wait ends.  A wait is still bounded: past kSpinLimit polls bit 31 is set in every
+// flag word, every later wait returns at once, and the epilogue turns the result into NaN.
+// Counter block (unsigned, one 128-byte line each): line 0 the ticket, lines 1..nst the stage
+// counts, lines nst+1..nst+64 the group flags.
+// =====================================================================================
+constexpr unsigned kSpinLimit = 1u << 20;
+constexpr int kFlagGroups = 64;
+constexpr int kLine = 32;  // unsigned per 128-byte line
+
+template <typename T>
+__global__ __launch_bounds__(256, 6) void k_dafmm_fused(const DTask* __restrict__ tasks,
+                                                     const DTerm* __restrict__ terms, const int* __restrict__ queue,
+                                                     int nitems, int nrhs, int nst, unsigned* __restrict__ ctr,
+                                                     const unsigned* __restrict__ need) {
+  __shared__ T red[3][8][64];
+  __shared__ int s_ticket;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const unsigned one = lane == 0 ? 1u : 0u;  // a whole-wave atomic adds 1 in total
+  const int total = nitems * nrhs;
+  unsigned* const flags = ctr + kLine * (1 + nst);
+  unsigned* const myflag = flags + kLine * (blockIdx.x % kFlagGroups);
+  // Every branch below that encloses a barrier, an atomic or a loop is uniform per wave (wave 0
+  // alone takes tickets, waits and counts, with all of its lanes), so all lanes of a wave stay
+  // in the same iteration.  Each iteration takes a new ticket, so at most total + 1 iterations.
+  for (int iter = 0; iter <= total; ++iter) {
+    if (wave == 0) {
+      const unsigned old = atomicAdd(&ctr[0], one);
+      s_ticket = (int)__builtin_amdgcn_readfirstlane(old);
+    }
+    __syncthreads();
+    const int tkt = __builtin_amdgcn_readfirstlane(s_ticket);
+    if (tkt >= total) break;
+    const int item = tkt / nrhs, rhs = tkt - item * nrhs;
+    const int ti = __builtin_amdgcn_readfirstlane(queue[2 * item]);
+    const int local = __builtin_amdgcn_readfirstlane(queue[2 * item + 1]);
+    const DTask& tk = tasks[ti];
+    if (wave == 0) {
+      unsigned mask = 0;
+      for (int q = 0; q < 3; ++q)
+        if (tk.dep[q] >= 0) mask |= 1u << tk.dep[q];
+      if (mask != 0u) {
+        for (unsigned spins = 0;; ++spins) {
+          const unsigned f = __builtin_amdgcn_readfirstlane(
+              __hip_atomic_load(myflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          if ((f & mask) == mask || (f >> 31) != 0u) break;
+          if (spins >= kSpinLimit) {
+            __hip_atomic_fetch_or(flags + kLine * lane, 1u << 31, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(16);
+        }
+      }
+    }
+    __syncthreads();
+    mfma_block<T, true>(tasks, terms, ti, local, rhs, red);
+    // this wave's stores (coherent at device scope) are complete before the workgroup counts
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (wave == 0) {
+      const int st = tk.stage;
+      const unsigned old = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_fetch_add(&ctr[kLine * (1 + st)], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (old + 1u == need[st] * (unsigned)nrhs)  // the stage's last block: publish it
+        __hip_atomic_fetch_or(flags + kLine * lane, 1u << st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+int dafmm_fused_workgroups(bool fp32) {
+  static int cached[2] = {0, 0};
+  int& c = cached[fp32 ? 1 : 0];
+  if (c > 0) return c;
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) throw std::runtime_error("hipGetDevice failed");
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    throw std::runtime_error("hipDeviceGetAttribute failed");
+  hipError_t e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_dafmm_fused<float>, 256, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_dafmm_fused<double>, 256, 0);
+  if (e != hipSuccess || per <= 0) throw std::runtime_error("occupancy query failed");
+  c = cus * per;
+  return c;
+}
+
+void launch_dafmm_fused(bool fp32, const DTask* tasks, const DTerm* terms, const int* queue, int nitems, int nrhs,
+                        int nst, unsigned* ctr, const unsigned* need, int nwg, hipStream_t s) {
+  if (nitems <= 0) return;
+  if (nwg <= 0) throw std::runtime_error("fused DAFMM launch needs workgroups");
+  if (nst < 1 || nst > 31) throw std::runtime_error("fused DAFMM launch takes 1 to 31 stages");
+  if (fp32) {
+    auto kern = k_dafmm_fused<float>;
+    LSK_LAUNCH(kern, dim3(nwg), 256, 0, s, tasks, terms, queue, nitems, nrhs, nst, ctr, need);
+  } else {
+    auto kern = k_dafmm_fused<double>;
+    LSK_LAUNCH(kern, dim3(nwg), 256, 0, s, tasks, terms, queue, nitems, nrhs, nst, ctr, need);
+  }
+}
+
+int dafmm_fused_counter_lines(int nst) { return 1 + nst + kFlagGroups; }
 
 // =====================================================================================
 // Offset table W(da, db) = h^2 (i/4) H0(kappa h |(da, db)|); the (0,0) entry is set on
@@ -582,6 +724,64 @@ void launch_epilogue(bool from_fp32, const double2* x, long long ldx, const void
     k_epilogue<float><<<grid, 256, 0, s>>>(x, ldx, (const float2*)ys, idx, q, alpha, coef, y, ldy, N);
   else
     k_epilogue<double><<<grid, 256, 0, s>>>(x, ldx, (const double2*)ys, idx, q, alpha, coef, y, ldy, N);
+}
+
+template <typename T>
+__global__ void k_gather_zero(const double2* __restrict__ x, long long ldx, typename V2<T>::type* __restrict__ xs,
+                              const int* __restrict__ idx, long long N, unsigned* __restrict__ zero, int nz) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (rhs == 0 && t < nz) zero[t * kLine] = 0u;
+  if (t >= N) return;
+  const double2 v = x[rhs * ldx + idx[t]];
+  typename V2<T>::type o;
+  o.x = (T)v.x;
+  o.y = (T)v.y;
+  xs[rhs * N + t] = o;
+}
+
+void launch_gather_zero(bool to_fp32, const double2* x, long long ldx, void* xs, const int* idx, long long N, int nrhs,
+                        unsigned* zero, int nz, hipStream_t s) {
+  if (nz < 0 || nz > 1024) throw std::runtime_error("gather: at most 1024 counter lines to zero");
+  const long long nt = N > nz ? N : nz;
+  dim3 grid((unsigned)((nt + 255) / 256), nrhs);
+  if (to_fp32)
+    k_gather_zero<float><<<grid, 256, 0, s>>>(x, ldx, (float2*)xs, idx, N, zero, nz);
+  else
+    k_gather_zero<double><<<grid, 256, 0, s>>>(x, ldx, (double2*)xs, idx, N, zero, nz);
+}
+
+template <typename T>
+__global__ void k_epilogue_checked(const double2* __restrict__ x, long long ldx,
+                                   const typename V2<T>::type* __restrict__ ys, const int* __restrict__ idx,
+                                   const double* __restrict__ q, double alpha, double coef, double2* __restrict__ y,
+                                   long long ldy, long long N, const unsigned* __restrict__ err) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (i >= N) return;
+  if ((*err >> 31) != 0u) {
+    y[rhs * ldy + i] = make_double2(__builtin_nan(""), __builtin_nan(""));
+    return;
+  }
+  const typename V2<T>::type v = ys[rhs * N + idx[i]];
+  const double c = q ? coef * q[i] : coef;
+  double2 o = make_double2(c * (double)v.x, c * (double)v.y);
+  if (alpha != 0.0) {
+    const double2 xv = x[rhs * ldx + i];
+    o.x += alpha * xv.x;
+    o.y += alpha * xv.y;
+  }
+  y[rhs * ldy + i] = o;
+}
+
+void launch_epilogue_checked(bool from_fp32, const double2* x, long long ldx, const void* ys, const int* idx,
+                             const double* q, double alpha, double coef, double2* y, long long ldy, long long N,
+                             int nrhs, const unsigned* err, hipStream_t s) {
+  dim3 grid((unsigned)((N + 255) / 256), nrhs);
+  if (from_fp32)
+    k_epilogue_checked<float><<<grid, 256, 0, s>>>(x, ldx, (const float2*)ys, idx, q, alpha, coef, y, ldy, N, err);
+  else
+    k_epilogue_checked<double><<<grid, 256, 0, s>>>(x, ldx, (const double2*)ys, idx, q, alpha, coef, y, ldy, N, err);
 }
 
 __global__ void k_permute(const double2* __restrict__ x, long long ldx, double2* __restrict__ y, long long ldy,

@@ -19,7 +19,7 @@ LS_OK, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_ENOTSUP = 0, -1, -2, -3, -4
 LS_FP64, LS_FP32, LS_MIXED = 0, 1, 2
 STATUS = {0: "CONVERGED", 1: "MAXIT", 2: "BREAKDOWN", 3: "NAN", 4: "REFINE_STAGNATED", 5: "WARMSTART_REJECTED"}
 PROFILE_CLASSES = {"near_m2l64": 0, "hodlr_update": 1, "leaf_solve": 2, "gs_dot": 3, "near_m2l32": 4,
-                   "hodlr_dot": 5, "hodlr_upd_dot": 6, "hodlr_core": 7}
+                   "hodlr_dot": 5, "hodlr_upd_dot": 6, "hodlr_core": 7, "dafmm64": 8, "dafmm32": 9}
 
 
 class LsError(RuntimeError):
@@ -34,7 +34,7 @@ class _Options(C.Structure):
                 ("inner_tol", C.c_double), ("max_refine", C.c_int), ("build_fp32", C.c_int),
                 ("hodlr_rank_div", C.c_int), ("graph_iters", C.c_int),
                 ("stencil_mfma", C.c_int), ("pc_bf16", C.c_int), ("dcgs2", C.c_int), ("pc_lowp_solves", C.c_int),
-                ("hodlr_tol", C.c_double)]
+                ("hodlr_tol", C.c_double), ("fmm_fused", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -162,6 +162,7 @@ class Options:
     dcgs2: int = 1
     pc_lowp_solves: int = 0
     hodlr_tol: float = 0.0
+    fmm_fused: int = 0
 
     def _c(self) -> _Options:
         o = _Options()
