@@ -130,6 +130,10 @@ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 // ---------------------------------------------------------------------------------------
 struct Phase {
   DevBuf tasks, terms, blk;
+  DevBuf part, sk;    // split-K partial planes and the tasks' reduction descriptors
+  int nsk = 0;
+  long long sk_elems = 0;
+  DevBuf kbl;         // matrix-core form: k-block descriptors of every task
   int nblocks = 0;
   int ntasks = 0;
   int tag = 0;        // 0 near+M2L, 1 P2M, 2 M2M, 3 L2L, 4 L2P
@@ -245,6 +249,7 @@ struct ProfileClass {
 struct ls_problem {
   ls_options opt;
   int device = 0;            // HIP device current at ls_setup (every vector call runs there)
+
   void* scratch = nullptr;   // that device's address of the allocation-free entry point's array
   ls::Plan plan;
   ls::NCA nca64, nca32;
@@ -426,6 +431,9 @@ void build_phases(ls_problem* P, FmmDev& F) {
     return (void*)(base + (F.lvl_off[nu] + (long long)dir * F.kmax[nu] * 4 * nh * nh) * es);
   };
   const long long N = P->N;
+  // longest chain of k-blocks one wave of the matrix-core form should carry (longer tasks split
+  // over more waves, then over more workgroups), so that no block forms a long tail
+  constexpr int kMaxChain = 72;
   // stages of the fused launch: P2M, near field, M2M per parent level, M2L per level, L2L per
   // parent level, L2P; a task's stage and prerequisites are set where the task is made
   const int nup = p.top <= leaf ? leaf - p.top : 0;
@@ -472,7 +480,9 @@ void build_phases(ls_problem* P, FmmDev& F) {
   };
   // matrix-core form: 16-row tiles, k in 4-deep blocks, kps waves per box sub-tile split the
   // blocks (more splitting for long tasks and for levels with at most 16 boxes per class)
-  auto make_phase_mfma = [&](Phase& ph, std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms) {
+  // rpg: row tiles a wave multiplies each input tile into (more reuse of the inputs, fewer and
+  // longer blocks: 4 for the big near-field + M2L launch, 1 for the short dependent passes)
+  auto make_phase_mfma = [&](Phase& ph, std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms, int rpg) {
     std::vector<int> blk;
     // a pass that would fill fewer than two workgroups per CU splits every task's k-range over
     // all 4 waves (4x the workgroups, shorter dependent chains)
@@ -487,22 +497,99 @@ void build_phases(ls_problem* P, FmmDev& F) {
         }
         tk.ktot = kb;
         tk.Mpad = round_up(std::max(tk.M, 1), lsk::kRowBlock);
-        tk.nrb = (tk.M + 15) / 16;
+        const int mt = std::min(rpg, (tk.M + 15) / 16);
+        tk.rpg = std::max(mt, 1);
+        tk.nrb = ((tk.M + 15) / 16 + tk.rpg - 1) / tk.rpg;  // row groups of rpg tiles
         const int nbox = tk.nh * tk.nh;
-        tk.kps = (pass == 1 || nbox <= 16 || kb > 160) ? 4 : (kb > 48 ? 2 : 1);
+        // waves that split the k-blocks of a tile: enough that one wave chains at most kMaxChain
+        // tile-k-blocks (k-blocks times row tiles)
+        const long long chain = (long long)kb * mt;
+        tk.kps = (pass == 1 || nbox <= 16 || chain > 2 * kMaxChain) ? 4 : (chain > kMaxChain ? 2 : 1);
         const int per = 16 * (4 / tk.kps);
-        const int nbb = (nbox + per - 1) / per;
+        tk.nbb = (nbox + per - 1) / per;
+        // beyond that, workgroups split K (one launch per pass only; the fused launch keeps 1)
+        tk.kgroups = 1;
+        if (!P->opt.fmm_fused && chain > 4 * kMaxChain)
+          tk.kgroups = (int)std::min<long long>(kb, (chain + 4 * kMaxChain - 1) / (4 * kMaxChain));
         tk.blk0 = (int)blk.size();
-        for (int i = 0; i < nbb * tk.nrb; ++i) blk.push_back((int)t);
+        for (int i = 0; i < tk.nbb * tk.nrb * tk.kgroups; ++i) blk.push_back((int)t);
       }
       if (blk.size() >= 512) break;
+    }
+    // k-block descriptors: per task, its terms' 4-deep k-blocks in term order, each with the
+    // address of its operator rows and of its inputs (class plane of the term included), the
+    // term's box shift and its real depth
+    {
+      std::vector<lsk::KBlk> kbl;
+      std::vector<long long> kb0(tasks.size(), 0);
+      for (size_t t = 0; t < tasks.size(); ++t) {
+        lsk::DTask& tk = tasks[t];
+        kb0[t] = (long long)kbl.size();
+        tk.mode = tk.t1 > tk.t0 ? terms[tk.t0].mode : lsk::MODE_SAME;
+        tk.nh_in = tk.t1 > tk.t0 ? terms[tk.t0].nh_in : tk.nh;
+        tk.in_rhs = tk.t1 > tk.t0 ? terms[tk.t0].in_rhs : 0;
+        tk.pks = 4LL * tk.nh_in * tk.nh_in;
+        tk.coh_in = tk.t1 > tk.t0 ? terms[tk.t0].coh : 0;
+        for (int q = tk.t0; q < tk.t1; ++q) {
+          const lsk::DTerm& tm = terms[q];
+          if (tm.mode != tk.mode || tm.nh_in != tk.nh_in || tm.in_rhs != tk.in_rhs || tm.coh != tk.coh_in)
+            throw LsError(LS_EINVAL, "internal: the terms of a task differ in mode or input level");
+          const long long plane = (long long)tm.nh_in * tm.nh_in;
+          const long long cin = (tm.mode == lsk::MODE_SHIFT || tm.mode == lsk::MODE_CHILD) ? tm.cin : 0;
+          for (int kk = 0; kk < (tm.K + 3) / 4; ++kk) {
+            lsk::KBlk d{};
+            d.op = (unsigned long long)((const char*)tm.op + (long long)4 * kk * tk.Mpad * F.esz);
+            d.in = (unsigned long long)((const char*)tm.in + (4LL * kk * tk.pks + cin * plane) * F.esz);
+            d.sha = tm.sha;
+            d.shb = tm.shb;
+            d.klim = std::min(4, tm.K - 4 * kk);
+            kbl.push_back(d);
+          }
+        }
+        if ((long long)kbl.size() - kb0[t] != tk.ktot) throw LsError(LS_EINVAL, "internal: k-block count");
+      }
+      ph.kbl.upload(kbl);
+      for (size_t t = 0; t < tasks.size(); ++t) tasks[t].kb = ph.kbl.as<lsk::KBlk>() + kb0[t];
+    }
+    // split-K partial planes [rhs][g][m][box] per task, and the descriptors of their reduction
+    {
+      long long pe = 0;
+      for (auto& tk : tasks)
+        if (tk.kgroups > 1) {
+          tk.part_rhs = (long long)tk.kgroups * tk.M * tk.nh * tk.nh;
+          pe += tk.part_rhs * F.nrhs_cap;
+        }
+      ph.part.alloc((size_t)std::max(pe, 1LL) * F.esz);
+      long long po = 0;
+      std::vector<lsk::SplitK> sk;
+      ph.sk_elems = 0;
+      for (auto& tk : tasks)
+        if (tk.kgroups > 1) {
+          tk.part = ph.part.as<char>() + po * F.esz;
+          po += tk.part_rhs * F.nrhs_cap;
+          lsk::SplitK d{};
+          d.part = tk.part;
+          d.out = tk.out;
+          d.part_rhs = tk.part_rhs;
+          d.out_rhs = tk.out_rhs;
+          d.M = tk.M;
+          d.nbox = tk.nh * tk.nh;
+          d.cout = tk.cout;
+          d.G = tk.kgroups;
+          d.beta = tk.beta;
+          sk.push_back(d);
+          ph.sk_elems = std::max(ph.sk_elems, (long long)tk.M * tk.nh * tk.nh);
+        }
+      ph.sk.upload(sk);
+      ph.nsk = (int)sk.size();
     }
     // dispatch order: blocks with the most k-blocks per wave first (the long ones start early
     // instead of forming the tail); entries are (task, block within the task) pairs
     std::vector<std::array<int, 3>> order;  // work, task, local
     for (size_t q = 0; q < blk.size(); ++q) {
       const lsk::DTask& tk = tasks[blk[q]];
-      order.push_back({(tk.ktot + tk.kps - 1) / tk.kps, blk[q], (int)q - tk.blk0});
+      const int per_wave = (tk.ktot * tk.rpg + tk.kgroups * tk.kps - 1) / (tk.kgroups * tk.kps);
+      order.push_back({per_wave, blk[q], (int)q - tk.blk0});
     }
     std::stable_sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a[0] > b[0]; });
     std::vector<int> pairs;
@@ -518,9 +605,9 @@ void build_phases(ls_problem* P, FmmDev& F) {
     ph.mfma = true;
     hps.push_back({tasks, terms, pairs});
   };
-  auto mk_phase = [&](Phase& ph, std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms) {
+  auto mk_phase = [&](Phase& ph, std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms, int rpg = 1) {
     if (P->opt.stencil_mfma)
-      make_phase_mfma(ph, tasks, terms);
+      make_phase_mfma(ph, tasks, terms, rpg);
     else
       make_phase(ph, tasks, terms);
   };
@@ -597,7 +684,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
         }
       }
     }
-    mk_phase(F.nearm2l, tasks, terms);
+    mk_phase(F.nearm2l, tasks, terms, 4);
     F.nearm2l.tag = 0;
   }
 
@@ -901,6 +988,7 @@ void run_phase(ls_problem* P, FmmDev& F, Phase& ph, int nrhs, hipStream_t s, int
       lsk::launch_stencil_mfma(F.fp32, ph.tasks.as<lsk::DTask>(), ph.terms.as<lsk::DTerm>(), ph.blk.as<int>(),
                                ph.nblocks, nrhs, s);
     }
+    lsk::launch_splitk_reduce(F.fp32, ph.sk.as<lsk::SplitK>(), ph.nsk, ph.sk_elems, nrhs, s);
     return;
   }
   if (prof_cls >= 0) {
@@ -1744,6 +1832,8 @@ void kd_key_phase(std::vector<uintptr_t>& k, const Phase& ph) {
   k.push_back((uintptr_t)ph.tasks.p);
   k.push_back((uintptr_t)ph.terms.p);
   k.push_back((uintptr_t)ph.blk.p);
+  k.push_back((uintptr_t)ph.sk.p);
+  k.push_back((uintptr_t)ph.nsk);
 }
 
 void kd_key_fmm(std::vector<uintptr_t>& k, const FmmDev& F) {

@@ -30,6 +30,18 @@ struct DTerm {
   int coh;          // fused form: the input is written inside the same launch (read it coherently)
 };
 
+// One 4-deep k-block of a matrix-core task: where the operator rows of this block start
+// (op: address of op[4 kk][0] of its term), where its inputs start for right-hand side 0 and
+// box 0 (in: address of in[4 kk][class plane of the term]), the term's box shift (SHIFT
+// mode) and how many of the 4 k are real (the last block of a term may be partial).
+struct alignas(32) KBlk {
+  unsigned long long op;
+  unsigned long long in;
+  int sha, shb;
+  int klim;
+  int pad;
+};
+
 struct DTask {
   void* out;         // output base of (level, direction) for rhs 0
   long long out_rhs; // rhs stride of the output
@@ -48,6 +60,23 @@ struct DTask {
   int stage;
   int dep[3];
   int coh_out;
+  int coh_in;        // fused form: the inputs are written inside the same launch
+  // split K (MFMA form, one launch per pass): kgroups > 1 workgroups share each output tile, each
+  // summing a contiguous share of the k-blocks into its own partial plane part[rhs][g][m][box]
+  // (part_rhs complex per right-hand side); launch_splitk_reduce then adds the planes in the
+  // order g = 0, 1, ... into the output
+  int kgroups;
+  int nbb;           // box blocks of the task
+  int rpg;           // matrix-core form: 16-row tiles per row group (1..4; nrb = row groups)
+  // matrix-core form: the task's k-blocks (ktot of them, in term order), the mode shared by all
+  // its terms, the input half-grid side and the input stride between k
+  const KBlk* kb;
+  int mode;
+  int nh_in;
+  long long in_rhs;
+  long long pks;
+  void* part;
+  long long part_rhs;
 };
 
 constexpr int kRowBlock = 8;
@@ -61,6 +90,17 @@ void launch_stencil_mfma(bool fp32, const DTask* tasks, const DTerm* terms, cons
                          int nrhs, hipStream_t s);
 void launch_stencil(int tag, bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
                     int nrhs, hipStream_t s);
+
+// the output of one split-K task: out[rhs][m][cout][box] (+)= sum_g part[rhs][g][m][box]
+struct SplitK {
+  const void* part;
+  void* out;
+  long long part_rhs, out_rhs;
+  int M, nbox, cout, G, beta;
+};
+// after a matrix-core pass with split-K tasks: add their partial planes into their outputs
+// (max_elems: the largest M * nbox over the tasks)
+void launch_splitk_reduce(bool fp32, const SplitK* sk, int ntask, long long max_elems, int nrhs, hipStream_t s);
 
 // Every DAFMM pass in one persistent launch.  queue: (task, block within the task) pairs in
 // an order in which every block's prerequisite stages come earlier; workgroups take the pairs

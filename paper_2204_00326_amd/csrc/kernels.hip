@@ -294,16 +294,20 @@ void launch_stencil(int tag, bool fp32, const DTask* tasks, const DTerm* terms, 
 }
 
 // =====================================================================================
-// Stencil GEMM on the matrix cores.  For one task (output level/direction/class) and one
-// 16-row tile of the output, out[m][box] = sum_terms sum_k op_t[k][m] in_t[k][src_t(box)] is a
-// sum of 16 x 4 by 4 x 16 products, one per 4-deep k-block of a term (a term's K is padded to
-// the block by zeros).  Complex entries: Re += Ar Xr - Ai Xi, Im += Ar Xi + Ai Xr, four real
-// 16x16x4 MFMAs.  A workgroup's 4 waves cover 64 / kps boxes in sub-tiles of 16 boxes, and
-// kps waves per sub-tile split the task's k-blocks; the parts are summed through LDS in a fixed
-// order (deterministic).  Lane l: A element (row l % 16, k l / 16), B element (k l / 16,
+// Stencil GEMM on the matrix cores.  For one task (output level/direction/class) and a group of
+// rpg 16-row tiles of the output, out[m][box] = sum_terms sum_k op_t[k][m] in_t[k][src_t(box)]
+// is a sum of 16 x 4 by 4 x 16 products, one per 4-deep k-block of a term (a term's K is padded
+// to the block by zeros); each input tile a wave loads is multiplied into all rpg row tiles.
+// Complex entries: Re += Ar Xr - Ai Xi, Im += Ar Xi + Ai Xr, four real 16x16x4 MFMAs.  A
+// workgroup's 4 waves cover 64 / kps boxes in sub-tiles of 16 boxes, and kps waves per sub-tile
+// split the task's k-blocks; the parts are summed through LDS in a fixed order (deterministic).
+// Long tasks also split their k-blocks over kgroups workgroups, each writing a partial plane that
+// a separate launch adds in group order.  The host lists every k-block of a task (operator and
+// input addresses, box shift, real depth), so the inner loop is a counted loop over descriptors
+// read through the scalar cache, with a ring of in-flight loads (branch-free: clamped addresses,
+// empty slots zeroed at use).  Lane l: A element (row l % 16, k l / 16), B element (k l / 16,
 // box l % 16); the accumulator element v of lane l is (row l/16 + 4v) for FP64 and
-// (row 4(l/16) + v) for FP32, box l % 16.  Loads use clamped in-range addresses and are
-// zeroed by selects, so all of a block's loads can be in flight together.
+// (row 4(l/16) + v) for FP32, box l % 16.
 // =====================================================================================
 typedef double mf64x4 __attribute__((ext_vector_type(4)));
 typedef float mf32x4 __attribute__((ext_vector_type(4)));
@@ -344,20 +348,22 @@ __device__ inline void st_coh(C2* p, const C2& v) {
 }
 
 // One block of the stencil GEMM: task ti, block `local` within the task, right-hand side rhs.
-// COH: honour the coherence flags of the fused launch (inputs and outputs produced or consumed
-// by other workgroups of the same launch).  Called by all 256 threads; contains one barrier
-// when the task splits its k-blocks over waves (kps > 1).
-template <typename T, bool COH>
-__device__ __forceinline__ void mfma_block(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms, int ti,
-                                           int local, int rhs, T (*red)[8][64]) {
+// A block covers one row group (up to four 16-row tiles: every wave multiplies each input tile it
+// loads into all of them), 64 / kps boxes in sub-tiles of 16, and the k-blocks of split-K group
+// grp.  COH: honour the coherence flags of the fused launch (inputs and outputs produced or
+// consumed by other workgroups of the same launch).  Called by all 256 threads; contains
+// barriers when the task splits its k-blocks over waves (kps > 1) or workgroups (kgroups > 1).
+template <typename T, bool COH, int MT>
+__device__ __forceinline__ void mfma_rows(const DTask& tk, const DTerm* __restrict__ terms, int rg, int bb, int grp,
+                                          int rhs, T (*red)[32][64]) {
   using C2 = typename P2<T>::type;
+  using GC = __attribute__((address_space(1))) const C2*;
   using MA = MfmaAcc<T>;
   using V4 = typename MA::type;
+  constexpr int D = MT >= 3 ? 2 : 3;  // k-blocks in flight per wave
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const DTask& tk = tasks[ti];
-  const int rt = local % tk.nrb;
-  const int bb = local / tk.nrb;
+  const int G = tk.kgroups;           // workgroups sharing the tile (split K)
   const int kps = tk.kps;             // 1, 2 or 4
   const int nsub = 4 / kps;           // box sub-tiles per workgroup
   const int sub = wave % nsub, kpart = wave / nsub;
@@ -367,108 +373,99 @@ __device__ __forceinline__ void mfma_block(const DTask* __restrict__ tasks, cons
   const bool bact = box < nbox;
   const int ha = bact ? box / nh : 0;
   const int hb = bact ? box - ha * nh : 0;
-  const int mrow = rt * 16 + li;
-  const bool arow = mrow < tk.M;
-  const long long mcl = arow ? mrow : 0;
-  V4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
-  const int nblk = tk.ktot;
-  const int b0 = (int)(((long long)nblk * kpart) / kps);
-  const int b1 = (int)(((long long)nblk * (kpart + 1)) / kps);
-  // Prefetch cursor over (term, block) pairs, running 4 blocks ahead of the products so that
-  // a block's loads are in flight while the three blocks before it are multiplied.
-  int t = tk.t0;
-  while (t < tk.t1 && terms[t].kbase + ((terms[t].K + 3) >> 2) <= b0) ++t;  // skips empty terms too
-  int pb = 0, pnb = 0, pK = 0;     // block inside the term, blocks and K of the term
-  bool pok = false, pcoh = false;
-  const C2* pin = nullptr;
-  const C2* pop = nullptr;
-  long long pks = 0;
-  auto open_term = [&](int tt, int first_block) {
-    const DTerm& tm = terms[tt];
-    pK = tm.K;
-    pnb = (tm.K + 3) >> 2;
-    pb = first_block;
-    pcoh = COH && tm.coh;
-    const int nhi = tm.nh_in;
-    const long long plane = (long long)nhi * nhi;
-    long long src = 0;
-    bool ok = bact;
-    switch (tm.mode) {
-      case MODE_SAME:
-        src = (long long)tk.cout * plane + box;
-        break;
-      case MODE_SHIFT: {
-        const int sa = ha + tm.sha, sb = hb + tm.shb;
-        ok = ok && sa >= 0 && sa < nhi && sb >= 0 && sb < nhi;
-        src = (long long)tm.cin * plane + (long long)sa * nhi + sb;
-      } break;
-      case MODE_CHILD: {
-        const int pa = 2 * ha + (tk.cout >> 1), pc = 2 * hb + (tk.cout & 1);
-        src = (long long)tm.cin * plane + (long long)pa * nhi + pc;
-      } break;
-      default: {
-        const int pc = ((ha & 1) << 1) | (hb & 1);
-        src = (long long)pc * plane + (long long)(ha >> 1) * nhi + (hb >> 1);
-      } break;
-    }
-    pok = ok;
-    if (!ok) src = 0;
-    pin = reinterpret_cast<const C2*>(tm.in) + rhs * tm.in_rhs + src;
-    pop = reinterpret_cast<const C2*>(tm.op) + mcl;
-    pks = 4 * plane;
-  };
-  if (b0 < b1) open_term(t, b0 - terms[t].kbase);
+  // operator rows of this lane in each tile (rows past M read row 0: finite, and never stored)
+  int arow[MT];
+#pragma unroll
+  for (int r = 0; r < MT; ++r) {
+    const int m = (rg * tk.rpg + r) * 16 + li;
+    arow[r] = m < tk.M ? m : 0;
+  }
+  V4 cre[MT], cim[MT];
+#pragma unroll
+  for (int r = 0; r < MT; ++r) {
+    cre[r] = V4{0, 0, 0, 0};
+    cim[r] = V4{0, 0, 0, 0};
+  }
+  // this workgroup's share of the task's k-blocks, split again over its kps waves
+  const int g0 = (int)(((long long)tk.ktot * grp) / G), g1 = (int)(((long long)tk.ktot * (grp + 1)) / G);
+  const int nblk = g1 - g0;
+  const int b0 = g0 + (int)(((long long)nblk * kpart) / kps);
+  const int b1 = g0 + (int)(((long long)nblk * (kpart + 1)) / kps);
+  // the lane's input box inside a plane of the input level (SHIFT adds each block's shift)
+  const int nhi = tk.nh_in;
+  const long long plane = (long long)nhi * nhi;
+  long long lsrc = 0;
+  switch (tk.mode) {
+    case MODE_SAME: lsrc = (long long)tk.cout * plane + box; break;
+    case MODE_SHIFT: lsrc = (long long)ha * nhi + hb; break;
+    case MODE_CHILD: lsrc = (long long)(2 * ha + (tk.cout >> 1)) * nhi + 2 * hb + (tk.cout & 1); break;
+    default: lsrc = (long long)(((ha & 1) << 1) | (hb & 1)) * plane + (long long)(ha >> 1) * nhi + (hb >> 1); break;
+  }
+  const bool shift = tk.mode == MODE_SHIFT;
   const long long Mp = tk.Mpad;
-  // fetch the next block into (a, x) with its validity flags; past b1 the slot is empty
-  int g = b0;  // global index of the next block to fetch
-  auto fetch = [&](C2& a, C2& x, bool& va, bool& vx) {
-    if (g >= b1) {
-      va = vx = false;
-      a.x = a.y = 0;
-      x.x = x.y = 0;
-      return;
+  // the descriptors are constant for the launch: read them through the scalar cache (a generic
+  // pointer would be read with vector loads, whose completion the data loads would then share)
+  using KC = __attribute__((address_space(4))) const KBlk*;
+  const KC kbl = (KC)tk.kb;
+  // ring of D in-flight k-blocks: the operator entries of every tile and the input entry.  The
+  // loop is branch-free: past b1 the last block is fetched again and marked empty; an input past
+  // the block's real depth or outside the domain is zeroed at use.
+  C2 ra[D][MT], rx[D];
+  bool rv[D];
+  auto fetch = [&](int s, int j) {
+    const bool inr = j < b1;
+    const KC dp = kbl + (inr ? j : b1 - 1);
+    const unsigned long long d_op = dp->op, d_in = dp->in;
+    const int d_sha = dp->sha, d_shb = dp->shb, d_klim = dp->klim;
+    const int sa = ha + (shift ? d_sha : 0), sb = hb + (shift ? d_shb : 0);
+    const bool ok = bact && (!shift || (sa >= 0 && sa < nhi && sb >= 0 && sb < nhi));
+    const long long src = ok ? (shift ? (long long)d_shb + (long long)d_sha * nhi + lsrc : lsrc) : 0;
+    // a lane past the block's real depth reads row k = 0 of the block (inside the term's operator
+    // and input) and is zeroed at use
+    const bool kin = lk < d_klim;
+    const long long lkc = kin ? lk : 0;
+    const C2* pa = reinterpret_cast<const C2*>(d_op) + lkc * Mp;
+#pragma unroll
+    for (int r = 0; r < MT; ++r) {
+      const GC q = (GC)(pa + arow[r]);
+      ra[s][r].x = q->x;
+      ra[s][r].y = q->y;
     }
-    const int k = 4 * pb + lk;
-    const bool vk = k < pK;
-    a = pop[(long long)(vk ? k : 0) * Mp];
-    if (COH && pcoh)
-      x = ld_coh(pin + (long long)(vk ? k : 0) * pks);
-    else
-      x = pin[(long long)(vk ? k : 0) * pks];
-    va = vk && arow;
-    vx = vk && pok;
-    ++g;
-    if (++pb == pnb && g < b1) {
-      do ++t;
-      while (terms[t].K == 0);  // empty terms own no blocks
-      open_term(t, 0);
+    const C2* px = reinterpret_cast<const C2*>(d_in) + lkc * tk.pks + rhs * tk.in_rhs + src;
+    if (COH && tk.coh_in) {
+      rx[s] = ld_coh(px);
+    } else {
+      const GC q = (GC)px;
+      rx[s].x = q->x;
+      rx[s].y = q->y;
     }
+    rv[s] = inr && ok && kin;
   };
-  auto mac = [&](const C2& a, const C2& x, bool va, bool vx) {
+  auto mac = [&](int s) {
     const T zr = 0;
-    const T ar = va ? a.x : zr, ai = va ? a.y : zr;
-    const T xr = vx ? x.x : zr, xi = vx ? x.y : zr;
-    cre = MA::mma(ar, xr, cre);
-    cim = MA::mma(ar, xi, cim);
-    cre = MA::mma(-ai, xi, cre);
-    cim = MA::mma(ai, xr, cim);
+    const T xr = rv[s] ? rx[s].x : zr, xi = rv[s] ? rx[s].y : zr;
+    // the real parts of the operator first, then the imaginary parts: an accumulator is reused
+    // only 2 MT products later
+#pragma unroll
+    for (int r = 0; r < MT; ++r) {
+      cre[r] = MA::mma(ra[s][r].x, xr, cre[r]);
+      cim[r] = MA::mma(ra[s][r].x, xi, cim[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < MT; ++r) {
+      cre[r] = MA::mma(-ra[s][r].y, xi, cre[r]);
+      cim[r] = MA::mma(ra[s][r].y, xr, cim[r]);
+    }
   };
   if (b0 < b1) {
-    C2 a0, a1, a2, a3, x0, x1, x2, x3;
-    bool va0, va1, va2, va3, vx0, vx1, vx2, vx3;
-    fetch(a0, x0, va0, vx0);
-    fetch(a1, x1, va1, vx1);
-    fetch(a2, x2, va2, vx2);
-    fetch(a3, x3, va3, vx3);
-    for (int c = b0; c < b1; c += 4) {
-      mac(a0, x0, va0, vx0);
-      fetch(a0, x0, va0, vx0);
-      mac(a1, x1, va1, vx1);
-      fetch(a1, x1, va1, vx1);
-      mac(a2, x2, va2, vx2);
-      fetch(a2, x2, va2, vx2);
-      mac(a3, x3, va3, vx3);
-      fetch(a3, x3, va3, vx3);
+#pragma unroll
+    for (int s = 0; s < D; ++s) fetch(s, b0 + s);
+    for (int c = b0; c < b1; c += D) {
+#pragma unroll
+      for (int s = 0; s < D; ++s) {
+        mac(s);
+        fetch(s, c + D + s);
+      }
     }
   }
   // k-parts 1..kps-1 of each sub-tile hand their sums to part 0 through LDS; waves 1..3
@@ -476,55 +473,132 @@ __device__ __forceinline__ void mfma_block(const DTask* __restrict__ tasks, cons
   if (kps > 1) {
     if (wave > 0 && kpart > 0) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        red[wave - 1][v][lane] = cre[v];
-        red[wave - 1][4 + v][lane] = cim[v];
-      }
+      for (int r = 0; r < MT; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          red[wave - 1][8 * r + v][lane] = cre[r][v];
+          red[wave - 1][8 * r + 4 + v][lane] = cim[r][v];
+        }
     }
     __syncthreads();
-    if (kpart != 0) return;
-    for (int q = 1; q < kps; ++q) {
-      const int w = q * nsub + sub;
+    if (kpart == 0)
+      for (int q = 1; q < kps; ++q) {
+        const int w = q * nsub + sub;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        cre[v] += red[w - 1][v][lane];
-        cim[v] += red[w - 1][4 + v][lane];
+        for (int r = 0; r < MT; ++r)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            cre[r][v] += red[w - 1][8 * r + v][lane];
+            cim[r][v] += red[w - 1][8 * r + 4 + v][lane];
+          }
       }
-    }
   }
-  if (!bact) return;
   C2* out = reinterpret_cast<C2*>(tk.out) + rhs * tk.out_rhs + (long long)tk.cout * nbox + box;
   const long long kso = 4LL * nbox;
+  if (G > 1) {
+    // split K: this group's partial tile goes to its plane of part[rhs][g][m][box]; a separate
+    // launch (launch_splitk_reduce) adds the planes in group order into the output
+    if (kpart != 0 || !bact) return;
+    using GO = __attribute__((address_space(1))) C2*;
+    C2* pp = reinterpret_cast<C2*>(tk.part) + rhs * tk.part_rhs + (long long)grp * tk.M * nbox + box;
+#pragma unroll
+    for (int r = 0; r < MT; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = (rg * tk.rpg + r) * 16 + MA::row(lane, v);
+        if (m < tk.M) {
+          GO q = (GO)(pp + (long long)m * nbox);
+          q->x = cre[r][v];
+          q->y = cim[r][v];
+        }
+      }
+    return;
+  }
+  if (kpart != 0 || !bact) return;
   const bool coh = COH && tk.coh_out;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int m = rt * 16 + MA::row(lane, v);
-    if (m < tk.M) {
-      C2 o;
-      o.x = cre[v];
-      o.y = cim[v];
-      C2* po = out + (long long)m * kso;
-      if (tk.beta) {
-        const C2 p = coh ? ld_coh(po) : *po;
-        o.x += p.x;
-        o.y += p.y;
+  for (int r = 0; r < MT; ++r)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = (rg * tk.rpg + r) * 16 + MA::row(lane, v);
+      if (m < tk.M) {
+        C2 o;
+        o.x = cre[r][v];
+        o.y = cim[r][v];
+        C2* po = out + (long long)m * kso;
+        if (tk.beta) {
+          const C2 p = COH ? ld_coh(po) : *po;
+          o.x += p.x;
+          o.y += p.y;
+        }
+        if (coh)
+          st_coh(po, o);
+        else
+          *po = o;
       }
-      if (coh)
-        st_coh(po, o);
-      else
-        *po = o;
     }
+}
+
+template <typename T, bool COH>
+__device__ __forceinline__ void mfma_block(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms, int ti,
+                                           int local, int rhs, T (*red)[32][64]) {
+  const DTask& tk = tasks[ti];
+  const int rg = local % tk.nrb;               // row group (rpg 16-row tiles)
+  const int bb = (local / tk.nrb) % tk.nbb;    // box block
+  const int grp = local / (tk.nrb * tk.nbb);   // split-K group
+  const int ntile = (tk.M + 15) / 16 - tk.rpg * rg;
+  switch (ntile >= tk.rpg ? tk.rpg : ntile) {
+    case 1: mfma_rows<T, COH, 1>(tk, terms, rg, bb, grp, rhs, red); break;
+    case 2: mfma_rows<T, COH, 2>(tk, terms, rg, bb, grp, rhs, red); break;
+    case 3: mfma_rows<T, COH, 3>(tk, terms, rg, bb, grp, rhs, red); break;
+    default: mfma_rows<T, COH, 4>(tk, terms, rg, bb, grp, rhs, red); break;
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256, 6) void k_stencil_mfma(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms,
+__global__ __launch_bounds__(256, 2) void k_stencil_mfma(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms,
                                                       const int* __restrict__ blk_task) {
-  __shared__ T red[3][8][64];
+  __shared__ T red[3][32][64];
   // blk_task holds (task, block within the task) pairs in dispatch order, heaviest blocks first
   const int ti = __builtin_amdgcn_readfirstlane(blk_task[2 * blockIdx.x]);
   const int local = __builtin_amdgcn_readfirstlane(blk_task[2 * blockIdx.x + 1]);
   mfma_block<T, false>(tasks, terms, ti, local, blockIdx.y, red);
+}
+
+// out[m][box] (+)= sum_{g = 0..G-1} part[g][m][box] for every split-K task of a pass, the planes
+// added in group order (deterministic); one thread per output element, grid.y = task, grid.z = rhs
+template <typename T>
+__global__ __launch_bounds__(256) void k_splitk_reduce(const SplitK* __restrict__ sk) {
+  using C2 = typename P2<T>::type;
+  const SplitK& k = sk[blockIdx.y];
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long ne = (long long)k.M * k.nbox;
+  if (e >= ne) return;
+  const int rhs = blockIdx.z;
+  const long long m = e / k.nbox, box = e - m * k.nbox;
+  const C2* p = reinterpret_cast<const C2*>(k.part) + rhs * k.part_rhs + e;
+  C2 o = p[0];
+  for (int g = 1; g < k.G; ++g) {
+    const C2 q = p[(long long)g * ne];
+    o.x += q.x;
+    o.y += q.y;
+  }
+  C2* po = reinterpret_cast<C2*>(k.out) + rhs * k.out_rhs + (long long)k.cout * k.nbox + box + m * 4LL * k.nbox;
+  if (k.beta) {
+    const C2 q = *po;
+    o.x += q.x;
+    o.y += q.y;
+  }
+  *po = o;
+}
+
+void launch_splitk_reduce(bool fp32, const SplitK* sk, int ntask, long long max_elems, int nrhs, hipStream_t s) {
+  if (ntask <= 0) return;
+  dim3 grid((unsigned)((max_elems + 255) / 256), ntask, nrhs);
+  if (fp32)
+    k_splitk_reduce<float><<<grid, 256, 0, s>>>(sk);
+  else
+    k_splitk_reduce<double><<<grid, 256, 0, s>>>(sk);
 }
 
 void launch_stencil_mfma(bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
@@ -559,11 +633,11 @@ constexpr int kFlagGroups = 64;
 constexpr int kLine = 32;  // unsigned per 128-byte line
 
 template <typename T>
-__global__ __launch_bounds__(256, 6) void k_dafmm_fused(const DTask* __restrict__ tasks,
+__global__ __launch_bounds__(256, 2) void k_dafmm_fused(const DTask* __restrict__ tasks,
                                                      const DTerm* __restrict__ terms, const int* __restrict__ queue,
                                                      int nitems, int nrhs, int nst, unsigned* __restrict__ ctr,
                                                      const unsigned* __restrict__ need) {
-  __shared__ T red[3][8][64];
+  __shared__ T red[3][32][64];
   __shared__ int s_ticket;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;

@@ -302,19 +302,22 @@ def test_queue_failed_problem_leaves_the_others():
 @pytest.mark.parametrize("n,kappa,leaf_max", [(8, 6.0, 4), (64, 40.0, 64), (128, 80.0, 64)])
 def test_fused_dafmm_launch_equals_per_pass_launches(n, kappa, leaf_max):
     # fmm_fused = 1: every pass in one persistent launch (blocks taken from a queue in dependency
-    # order, per-stage completion counts); the blocks compute the same sums, so the products are
-    # bit-identical to one launch per pass, for A and V, both precisions, several right-hand sides
+    # order, per-stage completion counts) against one launch per pass (whose long tasks split K
+    # over workgroups, so the sums differ in order only): products of A and V agree to rounding,
+    # for both precisions and several right-hand sides, and each path repeats bit for bit
     pb = inputs.problem_bumps(n, kappa, seed=5, count=4)
     opt = dict(hodlr_rank=0, leaf_max=leaf_max)
     Pf = ls.Problem(pb.points(), pb.q, kappa, 1e-10, ls.Options(fmm_fused=1, **opt))
     Pu = ls.Problem(pb.points(), pb.q, kappa, 1e-10, ls.Options(fmm_fused=0, **opt))
     X = torch.stack([dev(inputs.random_vector(n * n, seed=300 + j)) for j in range(3)])
-    for prec in (ls.LS_FP64, ls.LS_FP32):
+    for prec, tol in ((ls.LS_FP64, 1e-13), (ls.LS_FP32, 2e-6)):
+        yf0, yu0 = Pf.matvec(X, prec=prec), Pu.matvec(X, prec=prec)
         for rep in range(3):
             yf, yu = Pf.matvec(X, prec=prec), Pu.matvec(X, prec=prec)
             vf, vu = Pf.apply_V(X[0].contiguous(), prec=prec), Pu.apply_V(X[0].contiguous(), prec=prec)
             torch.cuda.synchronize()
-            assert torch.equal(yf, yu) and torch.equal(vf, vu), (prec, rep)
+            assert torch.equal(yf, yf0) and torch.equal(yu, yu0), (prec, rep)
+            assert rel(host(yf), host(yu)) < tol and rel(host(vf), host(vu)) < tol, (prec, rep)
     ref = X[1].cpu().numpy() - kappa * kappa * pb.q * lsop.FFTApplyV(n, 1.0, kappa)(X[1].cpu().numpy())
     assert rel(host(Pf.matvec(X[1].contiguous())), ref) < 1e-8
     Pf.close()
