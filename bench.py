@@ -260,6 +260,60 @@ def rhs_block(args, torch, np, inputs, ls):
     return out
 
 
+def matvec_rates(P, st, n, torch, np, ls):
+    """Median time of the FP64 and FP32 products (30 event-timed products each after 3 warm-up
+    ones), their per-pass split and the whole product against the matrix-core roof."""
+    stream = torch.cuda.current_stream()
+    x = torch.randn(n * n, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    rates = {}
+    for name, prec in (("fp64", ls.LS_FP64), ("fp32", ls.LS_FP32)):
+        for _ in range(3):
+            P.matvec(x, y, prec=prec)
+        ts = []
+        for _ in range(30):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            P.matvec(x, y, prec=prec)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        rates[name] = 1e3 / float(np.median(ts))
+    log("matvec/s", rates)
+    # per-pass split of the product: each pass group timed between two events on the stream
+    # (launch gaps and split-K reductions included) over 30 products of each precision, in
+    # microseconds per product; outside the median-timed loop above, so its timers do not
+    # touch the rates
+    passes = {}
+    for name, prec, b in (("fp64", ls.LS_FP64, "64"), ("fp32", ls.LS_FP32, "32")):
+        keys = [k for k in ls.PROFILE_SPANS if k.startswith(f"mv{b}_")]
+        for k in keys:
+            P.profile_enable(k, 1)
+        for _ in range(30):
+            P.matvec(x, y, prec=prec)
+        torch.cuda.synchronize()
+        sp = {}
+        for k in keys:
+            ms, timed, _ = P.profile_read(k)
+            P.profile_enable(k, 0)
+            sp[k.split("_", 1)[1]] = round(1e3 * ms / timed, 2) if timed else 0.0
+        sp["sum"] = round(sum(sp.values()), 2)
+        passes[name] = sp
+    log("matvec passes (us)", passes)
+    # the whole DAFMM product against the matrix-core roof: 8 real flops per complex entry of
+    # every pass (near field, P2M, M2M, M2L, L2L, L2P) over the median product time
+    mv_flops = {"fp64": 8.0 * (st["entries_near"] + st["entries_far64"]),
+                "fp32": 8.0 * (st["entries_near"] + st["entries_far32"])}
+    roof_mv = {}
+    for name, dt in (("fp64", "f64"), ("fp32", "f32")):
+        ach = mv_flops[name] * rates[name] / 1e12
+        roof_mv[name] = {"bound": "mfma", "achieved": round(ach, 3), "peak": MFMA_PEAK_TFLOPS[dt],
+                         "unit": "TFLOP/s", "frac": round(ach / MFMA_PEAK_TFLOPS[dt], 4),
+                         "flops_per_matvec": mv_flops[name], "us_per_matvec": round(1e6 / rates[name], 2),
+                         "passes_us": passes[name]}
+    return rates, passes, roof_mv
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,6 +339,8 @@ def main():
                     help="also solve this many plane waves on Gaussian bumps as one block (0: skip)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"),
                     help="summarise two rocprofv3 --pmc runs of this bench into the traffic file and exit")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="time only the DAFMM products (no preconditioner, no solve) and print their line")
     args = ap.parse_args()
     workload = f"disc{args.n}_k{args.kappa:g}_mixed_hodlr{args.rank}"
     if args.pmc_summary:
@@ -303,6 +359,18 @@ def main():
     torch.cuda.set_device(0)
     n, kappa = args.n, args.kappa
     pb = inputs.problem_disc(n, kappa)
+    if args.matvec_only:
+        P = ls.Problem(pb.points(), pb.q, kappa, 1e-10, ls.Options(hodlr_rank=0, eps_inner=1e-7))
+        st = P.stats()
+        rates, _, roof_mv = matvec_rates(P, st, n, torch, np, ls)
+        print(json.dumps({"metric": "DAFMM matvec/s", "value": round(rates["fp64"], 1), "unit": "matvec/s",
+                          "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+                          "config": {"workload": f"disc{n}_k{kappa:g}_matvec", "n": n, "kappa": kappa,
+                                     "eps_nca": 1e-10, "eps_inner": 1e-7},
+                          "matvec_per_s": {k: round(v, 1) for k, v in rates.items()},
+                          "roofline_matvec": roof_mv}), flush=True)
+        P.close()
+        return
     t0 = time.perf_counter()
     P = ls.Problem(pb.points(), pb.q, kappa, 1e-10,
                    ls.Options(hodlr_rank=args.rank, hodlr_rank_div=args.rank_div, prec=ls.LS_MIXED,
@@ -395,33 +463,7 @@ def main():
               "note": "per target all n^2 cells are visited; cells with zero density are skipped"}
     log("error function", err_fn)
 
-    # matvec rates
-    x = torch.randn(n * n, dtype=torch.complex128, device="cuda")
-    y = torch.empty_like(x)
-    rates = {}
-    for name, prec in (("fp64", ls.LS_FP64), ("fp32", ls.LS_FP32)):
-        for _ in range(3):
-            P.matvec(x, y, prec=prec)
-        ts = []
-        for _ in range(30):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            P.matvec(x, y, prec=prec)
-            e1.record(stream)
-            e1.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        rates[name] = 1e3 / float(np.median(ts))
-    log("matvec/s", rates)
-    # the whole DAFMM product against the matrix-core roof: 8 real flops per complex entry of
-    # every pass (near field, P2M, M2M, M2L, L2L, L2P) over the median product time
-    mv_flops = {"fp64": 8.0 * (st["entries_near"] + st["entries_far64"]),
-                "fp32": 8.0 * (st["entries_near"] + st["entries_far32"])}
-    roof_mv = {}
-    for name, dt in (("fp64", "f64"), ("fp32", "f32")):
-        ach = mv_flops[name] * rates[name] / 1e12
-        roof_mv[name] = {"bound": "mfma", "achieved": round(ach, 3), "peak": MFMA_PEAK_TFLOPS[dt],
-                         "unit": "TFLOP/s", "frac": round(ach / MFMA_PEAK_TFLOPS[dt], 4),
-                         "flops_per_matvec": mv_flops[name], "us_per_matvec": round(1e6 / rates[name], 2)}
+    rates, passes, roof_mv = matvec_rates(P, st, n, torch, np, ls)
 
     # calibration copy of COPY_BYTES for the HBM counters (read and written once)
     src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")

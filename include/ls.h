@@ -200,10 +200,12 @@ ls_status ls_setup(const double* points, int64_t N, const double* q, double kapp
 /* y = A x (Eq. (eq:12a)) with the DAFMM product (Section 5) for V.
  * x, y: device, N x nrhs complex128, leading dimension ld.  prec: LS_FP64 or LS_FP32
  * (FP32 converts x to complex64 for the operator and accumulates the result in
- * complex128).  x and y must not overlap. */
+ * complex128).  x and y must not overlap.  Calls on one handle must not overlap in time (the
+ * product's workspaces belong to the handle). */
 ls_status ls_matvec(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld, int prec, void* stream);
 
-/* u = V psi: the scattered field on the grid (Section 6, last paragraph before 6.1). */
+/* u = V psi: the scattered field on the grid (Section 6, last paragraph before 6.1).  Arguments
+ * and overlap rules as for ls_matvec. */
 ls_status ls_apply_V(ls_problem* P, const void* x, void* y, int nrhs, int64_t ld, int prec, void* stream);
 
 /* HODLR direct solver (Section 6: the factorisation used as the solver, the paper's choice for
@@ -325,7 +327,11 @@ ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt,
  * 3 = Arnoldi dot products, 4 = near field + M2L launch (FP32 operator), 5 = HODLR level dot
  * products (W^T z), 6 = HODLR level update fused with the next level's dot products (complex
  * bfloat16 factors, one right-hand side), 7 = HODLR SMW core products s = K^-1 t, 8 = the fused
- * DAFMM launch (every pass, FP64 operator), 9 = the same with the FP32 operator.  every > 0
+ * DAFMM launch (every pass, FP64 operator), 9 = the same with the FP32 operator.  Classes
+ * 10..14 time spans of the per-pass DAFMM product with the FP64 operator between two events
+ * recorded on the stream (launch gaps included): 10 = gather into the tree order, 11 = upward
+ * pass (P2M, M2M), 12 = near field + M2L, 13 = downward pass (L2L, L2P), 14 = epilogue
+ * (y = alpha x + coef q V x); 15..19 the same with the FP32 operator.  every > 0
  * starts (and clears) the counters and times every every-th
  * launch of the class (timed dispatches run one at a time, so sparse sampling keeps the
  * timed run close to an untimed one); 0 stops.  ls_profile_read synchronises and returns the

@@ -236,6 +236,11 @@ struct KrylovDev {
   }
 };
 
+// kernel classes 0..9 time one launch each; 10..19 time a span of launches of the unfused DAFMM
+// product (gather, upward pass, near field + M2L, downward pass, epilogue; FP64 then FP32)
+constexpr int kProfClasses = 20;
+constexpr int kProfSpan = 10;
+
 struct ProfileClass {
   bool enabled = false;
   int every = 1;       // time every `every`-th launch
@@ -269,7 +274,7 @@ struct ls_problem {
   DevBuf w_x, w_y, w_t;  // Morton-order vectors (nrhs_cap)
   int ws_cap = 0;
   ls_stats_t stats{};
-  ProfileClass prof[16];
+  ProfileClass prof[kProfClasses];
   // Krylov workspace
   DevBuf kQ, kZ, kw, kz, kr, kh, kpart, knp, kno, kalpha, ky, kx, kf, kdx;
   size_t kcap_key = 0;
@@ -311,6 +316,27 @@ struct ProfScope {
       lsk::clear_next_launch_events();
       pc->used--;
     }
+  }
+};
+
+// a span of launches between two event records on the stream (launch gaps included)
+struct SpanScope {
+  std::pair<hipEvent_t, hipEvent_t>* pr = nullptr;
+  hipStream_t s;
+  SpanScope(ls_problem* P, int cls, hipStream_t st) : s(st) {
+    ProfileClass* pc = &P->prof[cls];
+    if (!pc->enabled || P->capturing || (pc->count++ % pc->every) != 0) return;
+    if (pc->used == pc->ev.size()) {
+      hipEvent_t a, b;
+      hip_check(hipEventCreate(&a), "hipEventCreate");
+      hip_check(hipEventCreate(&b), "hipEventCreate");
+      pc->ev.push_back({a, b});
+    }
+    pr = &pc->ev[pc->used++];
+    hip_check(hipEventRecord(pr->first, s), "hipEventRecord");
+  }
+  ~SpanScope() {
+    if (pr) (void)hipEventRecord(pr->second, s);
   }
 };
 
@@ -433,7 +459,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
   const long long N = P->N;
   // longest chain of k-blocks one wave of the matrix-core form should carry (longer tasks split
   // over more waves, then over more workgroups), so that no block forms a long tail
-  constexpr int kMaxChain = 72;
+  const int kMaxChain = F.fp32 ? 144 : 72;
   // stages of the fused launch: P2M, near field, M2M per parent level, M2L per level, L2L per
   // parent level, L2P; a task's stage and prerequisites are set where the task is made
   const int nup = p.top <= leaf ? leaf - p.top : 0;
@@ -540,8 +566,10 @@ void build_phases(ls_problem* P, FmmDev& F) {
             lsk::KBlk d{};
             d.op = (unsigned long long)((const char*)tm.op + (long long)4 * kk * tk.Mpad * F.esz);
             d.in = (unsigned long long)((const char*)tm.in + (4LL * kk * tk.pks + cin * plane) * F.esz);
-            d.sha = tm.sha;
-            d.shb = tm.shb;
+            // the box shift of a shifted term; zero for every other mode (the kernel adds it
+            // unconditionally)
+            d.sha = tm.mode == lsk::MODE_SHIFT ? tm.sha : 0;
+            d.shb = tm.mode == lsk::MODE_SHIFT ? tm.shb : 0;
             d.klim = std::min(4, tm.K - 4 * kk);
             kbl.push_back(d);
           }
@@ -1030,18 +1058,30 @@ void fmm_apply(ls_problem* P, bool fp32, const double2* x, long long ldx, double
     hip_check(hipGetLastError(), "fused fmm kernels");
     return;
   }
-  lsk::launch_gather(fp32, x, ldx, F.xs.p, gidx, N, nrhs, s);
+  const int span = kProfSpan + (fp32 ? 5 : 0);
+  {
+    SpanScope sp(P, span + 0, s);
+    lsk::launch_gather(fp32, x, ldx, F.xs.p, gidx, N, nrhs, s);
+  }
   const ls::Plan& p = P->plan;
   if (p.top <= p.leaf) {
+    SpanScope sp(P, span + 1, s);
     run_phase(P, F, F.p2m, nrhs, s);
     for (auto& ph : F.up) run_phase(P, F, ph, nrhs, s);
   }
-  run_phase(P, F, F.nearm2l, nrhs, s, fp32 ? 4 : 0);
+  {
+    SpanScope sp(P, span + 2, s);
+    run_phase(P, F, F.nearm2l, nrhs, s, fp32 ? 4 : 0);
+  }
   if (p.top <= p.leaf) {
+    SpanScope sp(P, span + 3, s);
     for (auto& ph : F.down) run_phase(P, F, ph, nrhs, s);
     run_phase(P, F, F.l2p, nrhs, s);
   }
-  lsk::launch_epilogue(fp32, x, ldx, F.ys.p, eidx, q, alpha, coef, y, ldy, N, nrhs, s);
+  {
+    SpanScope sp(P, span + 4, s);
+    lsk::launch_epilogue(fp32, x, ldx, F.ys.p, eidx, q, alpha, coef, y, ldy, N, nrhs, s);
+  }
   hip_check(hipGetLastError(), "fmm kernels");
 }
 
@@ -3075,7 +3115,7 @@ void ls_destroy(ls_problem* P) {
 }
 
 ls_status ls_profile_enable(ls_problem* P, int cls, int every) {
-  if (!P || cls < 0 || cls > 9 || every < 0) {
+  if (!P || cls < 0 || cls >= kProfClasses || every < 0) {
     g_last_error = "bad arguments";
     return LS_EINVAL;
   }
@@ -3091,7 +3131,7 @@ ls_status ls_profile_enable(ls_problem* P, int cls, int every) {
 
 ls_status ls_profile_read(ls_problem* P, int cls, double* total_ms, int64_t* launches, int64_t* all_launches) {
   try {
-    if (!P || cls < 0 || cls > 9 || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
+    if (!P || cls < 0 || cls >= kProfClasses || !total_ms || !launches) throw LsError(LS_EINVAL, "bad arguments");
     ProfileClass& pc = P->prof[cls];
     double tot = 0;
     for (size_t i = 0; i < pc.used; ++i) {

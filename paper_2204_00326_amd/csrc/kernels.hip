@@ -355,7 +355,7 @@ __device__ inline void st_coh(C2* p, const C2& v) {
 // barriers when the task splits its k-blocks over waves (kps > 1) or workgroups (kgroups > 1).
 template <typename T, bool COH, int MT>
 __device__ __forceinline__ void mfma_rows(const DTask& tk, const DTerm* __restrict__ terms, int rg, int bb, int grp,
-                                          int rhs, T (*red)[32][64]) {
+                                          int rhs, T (*red)[16][64]) {
   using C2 = typename P2<T>::type;
   using GC = __attribute__((address_space(1))) const C2*;
   using MA = MfmaAcc<T>;
@@ -412,14 +412,30 @@ __device__ __forceinline__ void mfma_rows(const DTask& tk, const DTerm* __restri
   // the block's real depth or outside the domain is zeroed at use.
   C2 ra[D][MT], rx[D];
   bool rv[D];
+  // descriptors of the next ring round, read one round ahead so that the scalar loads complete
+  // behind the matrix products instead of stalling the address computation
+  struct Dsc {
+    unsigned long long op, in;
+    int sha, shb, klim;
+  } dn[D];
+  auto desc = [&](int s, int j) {
+    const KC dp = kbl + (j < b1 ? j : b1 - 1);
+    dn[s].op = dp->op;
+    dn[s].in = dp->in;
+    dn[s].sha = dp->sha;
+    dn[s].shb = dp->shb;
+    dn[s].klim = dp->klim;
+  };
   auto fetch = [&](int s, int j) {
     const bool inr = j < b1;
-    const KC dp = kbl + (inr ? j : b1 - 1);
-    const unsigned long long d_op = dp->op, d_in = dp->in;
-    const int d_sha = dp->sha, d_shb = dp->shb, d_klim = dp->klim;
-    const int sa = ha + (shift ? d_sha : 0), sb = hb + (shift ? d_shb : 0);
-    const bool ok = bact && (!shift || (sa >= 0 && sa < nhi && sb >= 0 && sb < nhi));
-    const long long src = ok ? (shift ? (long long)d_shb + (long long)d_sha * nhi + lsrc : lsrc) : 0;
+    const unsigned long long d_op = dn[s].op, d_in = dn[s].in;
+    const int d_sha = dn[s].sha, d_shb = dn[s].shb, d_klim = dn[s].klim;
+    const int sa = ha + d_sha, sb = hb + d_shb;  // the shift is zero unless the term is shifted
+    // branch-free validity (bitwise, not short-circuit): the box exists and, for a shifted term,
+    // its neighbour lies inside the level
+    const bool inside = ((unsigned)sa < (unsigned)nhi) & ((unsigned)sb < (unsigned)nhi);
+    const bool ok = bact & (!shift | inside);
+    const long long src = ok ? (long long)d_shb + (long long)d_sha * nhi + lsrc : 0;
     // a lane past the block's real depth reads row k = 0 of the block (inside the term's operator
     // and input) and is zeroed at use
     const bool kin = lk < d_klim;
@@ -459,39 +475,48 @@ __device__ __forceinline__ void mfma_rows(const DTask& tk, const DTerm* __restri
   };
   if (b0 < b1) {
 #pragma unroll
-    for (int s = 0; s < D; ++s) fetch(s, b0 + s);
+    for (int s = 0; s < D; ++s) {
+      desc(s, b0 + s);
+      fetch(s, b0 + s);
+      desc(s, b0 + D + s);
+    }
     for (int c = b0; c < b1; c += D) {
 #pragma unroll
       for (int s = 0; s < D; ++s) {
         mac(s);
         fetch(s, c + D + s);
+        desc(s, c + 2 * D + s);
       }
     }
   }
   // k-parts 1..kps-1 of each sub-tile hand their sums to part 0 through LDS; waves 1..3
   // own slots 0..2 (wave w = kpart * nsub + sub, so part 0 waves are 0..nsub-1)
   if (kps > 1) {
-    if (wave > 0 && kpart > 0) {
+    // real parts, then imaginary parts, through one 16-value slot per wave
 #pragma unroll
-      for (int r = 0; r < MT; ++r)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          red[wave - 1][8 * r + v][lane] = cre[r][v];
-          red[wave - 1][8 * r + 4 + v][lane] = cim[r][v];
-        }
-    }
-    __syncthreads();
-    if (kpart == 0)
-      for (int q = 1; q < kps; ++q) {
-        const int w = q * nsub + sub;
+    for (int h = 0; h < 2; ++h) {
+      if (wave > 0 && kpart > 0) {
 #pragma unroll
         for (int r = 0; r < MT; ++r)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            cre[r][v] += red[w - 1][8 * r + v][lane];
-            cim[r][v] += red[w - 1][8 * r + 4 + v][lane];
-          }
+          for (int v = 0; v < 4; ++v) red[wave - 1][4 * r + v][lane] = h ? cim[r][v] : cre[r][v];
       }
+      __syncthreads();
+      if (kpart == 0)
+        for (int q = 1; q < kps; ++q) {
+          const int w = q * nsub + sub;
+#pragma unroll
+          for (int r = 0; r < MT; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              if (h)
+                cim[r][v] += red[w - 1][4 * r + v][lane];
+              else
+                cre[r][v] += red[w - 1][4 * r + v][lane];
+            }
+        }
+      if (h == 0) __syncthreads();
+    }
   }
   C2* out = reinterpret_cast<C2*>(tk.out) + rhs * tk.out_rhs + (long long)tk.cout * nbox + box;
   const long long kso = 4LL * nbox;
@@ -541,7 +566,7 @@ __device__ __forceinline__ void mfma_rows(const DTask& tk, const DTerm* __restri
 
 template <typename T, bool COH>
 __device__ __forceinline__ void mfma_block(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms, int ti,
-                                           int local, int rhs, T (*red)[32][64]) {
+                                           int local, int rhs, T (*red)[16][64]) {
   const DTask& tk = tasks[ti];
   const int rg = local % tk.nrb;               // row group (rpg 16-row tiles)
   const int bb = (local / tk.nrb) % tk.nbb;    // box block
@@ -558,7 +583,7 @@ __device__ __forceinline__ void mfma_block(const DTask* __restrict__ tasks, cons
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_stencil_mfma(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms,
                                                       const int* __restrict__ blk_task) {
-  __shared__ T red[3][32][64];
+  __shared__ T red[3][16][64];
   // blk_task holds (task, block within the task) pairs in dispatch order, heaviest blocks first
   const int ti = __builtin_amdgcn_readfirstlane(blk_task[2 * blockIdx.x]);
   const int local = __builtin_amdgcn_readfirstlane(blk_task[2 * blockIdx.x + 1]);
@@ -637,7 +662,7 @@ __global__ __launch_bounds__(256, 2) void k_dafmm_fused(const DTask* __restrict_
                                                      const DTerm* __restrict__ terms, const int* __restrict__ queue,
                                                      int nitems, int nrhs, int nst, unsigned* __restrict__ ctr,
                                                      const unsigned* __restrict__ need) {
-  __shared__ T red[3][32][64];
+  __shared__ T red[3][16][64];
   __shared__ int s_ticket;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;

@@ -20,6 +20,13 @@ LS_FP64, LS_FP32, LS_MIXED = 0, 1, 2
 STATUS = {0: "CONVERGED", 1: "MAXIT", 2: "BREAKDOWN", 3: "NAN", 4: "REFINE_STAGNATED", 5: "WARMSTART_REJECTED"}
 PROFILE_CLASSES = {"near_m2l64": 0, "hodlr_update": 1, "leaf_solve": 2, "gs_dot": 3, "near_m2l32": 4,
                    "hodlr_dot": 5, "hodlr_upd_dot": 6, "hodlr_core": 7, "dafmm64": 8, "dafmm32": 9}
+# spans of the per-pass DAFMM product (every launch between two stream events)
+PROFILE_SPANS = {f"mv{b}_{k}": o + i for b, o in (("64", 10), ("32", 15))
+                 for i, k in enumerate(("gather", "up", "near_m2l", "down", "epilogue"))}
+
+
+def _prof_index(cls: str) -> int:
+    return PROFILE_CLASSES[cls] if cls in PROFILE_CLASSES else PROFILE_SPANS[cls]
 
 
 class LsError(RuntimeError):
@@ -346,14 +353,14 @@ class Problem:
 
     def profile_enable(self, cls: str, every: int = 1):
         """Time every `every`-th launch of a kernel class (0 or False: stop)."""
-        _check(lib().ls_profile_enable(self._h, PROFILE_CLASSES[cls], int(every)))
+        _check(lib().ls_profile_enable(self._h, _prof_index(cls), int(every)))
 
     def profile_read(self, cls: str):
         """(summed ms of the timed launches, timed launches, all launches since enabling)"""
         ms = C.c_double()
         n = C.c_int64()
         a = C.c_int64()
-        _check(lib().ls_profile_read(self._h, PROFILE_CLASSES[cls], C.byref(ms), C.byref(n), C.byref(a)))
+        _check(lib().ls_profile_read(self._h, _prof_index(cls), C.byref(ms), C.byref(n), C.byref(a)))
         return ms.value, n.value, a.value
 
 

@@ -65,3 +65,31 @@ def test_setup_timers_are_parts_of_the_hodlr_setup():
                                       "t_hodlr_cores_ms", "t_setup_ms")})
     assert all(st[k] > 0.0 for k in ("t_hodlr_aca_ms", "t_hodlr_apply_ms", "t_hodlr_cores_ms"))
     assert parts <= st["t_hodlr_ms"] <= st["t_setup_ms"]
+
+
+def test_pass_spans_of_the_product_cover_every_pass_once():
+    # one span per pass group and product; the spans lie inside the product, so their sum is
+    # at most the time of the whole product between two events around it
+    P = problem()
+    x = torch.from_numpy(inputs.random_vector(P.N, seed=5)).cuda()
+    y0 = P.matvec(x, prec=ls.LS_FP64)
+    for b, prec in (("64", ls.LS_FP64), ("32", ls.LS_FP32)):
+        keys = [k for k in ls.PROFILE_SPANS if k.startswith(f"mv{b}_")]
+        for k in keys:
+            P.profile_enable(k, 1)
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(4):
+            y = P.matvec(x, prec=prec)
+        e1.record(s)
+        torch.cuda.synchronize()
+        got = {k: P.profile_read(k) for k in keys}
+        for k in keys:
+            P.profile_enable(k, 0)
+        say(b, {k: (round(v[0], 4), v[1], v[2]) for k, v in got.items()}, "whole", e0.elapsed_time(e1))
+        for k, (ms, timed, launches) in got.items():
+            assert timed == launches == 4 and ms > 0.0, k
+        assert sum(v[0] for v in got.values()) <= e0.elapsed_time(e1)
+        if prec == ls.LS_FP64:
+            assert torch.equal(y, y0)
