@@ -167,6 +167,11 @@ typedef struct {
    * other child uses, so those chunks and core rows are skipped. */
   int64_t hodlr_dot_rows[32];
   int hodlr_core_nodes[32];
+  /* complex multiply-adds per product and right-hand side of the middle launch of the product
+   * (kernel timing classes 0 and 4): the M2L of the top level and the near-field classes not
+   * packed into the upward-pass launches (all of the near field and M2L without the
+   * matrix-core form or in the fused launch) */
+  int64_t entries_mid64, entries_mid32;
 } ls_stats_t;
 
 /* Plan description for a uniform n x n grid on [-L, L]^2 (host only, no device use).

@@ -171,6 +171,7 @@ struct FmmDev {
   std::vector<std::vector<std::vector<long long>>> off_K;    // [nu][dir][term]: M2L op = K^T
   int64_t entries_far = 0;
   int64_t entries_m2l = 0;
+  double entries_mid = 0;  // complex multiply-adds of the middle launch (one right-hand side)
   int64_t stored_bytes = 0;
 };
 
@@ -508,12 +509,28 @@ void build_phases(ls_problem* P, FmmDev& F) {
   // blocks (more splitting for long tasks and for levels with at most 16 boxes per class)
   // rpg: row tiles a wave multiplies each input tile into (more reuse of the inputs, fewer and
   // longer blocks: 4 for the big near-field + M2L launch, 1 for the short dependent passes)
-  auto make_phase_mfma = [&](Phase& ph, std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms, int rpg) {
+  // prio (per task, may be empty): tasks of higher priority are dispatched first (the dependent
+  // chain of a launch ahead of the independent work packed into it); only their blocks decide
+  // whether the launch splits every k-range over all 4 waves.  acc (may be null): split-K
+  // reduction descriptors collected over several passes; with flush = false this pass adds its
+  // own to them (no reduction after it), with flush = true its reduction launch covers them all.
+  // A task's rpg set before the call overrides the phase's.
+  // chunk (may be empty): per task (index, count) — the task covers that share of its level's
+  // box blocks (count > 1: no split K, its partial planes would cover the whole level).
+  auto make_phase_mfma = [&](Phase& ph, std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms, int rpg,
+                             const std::vector<int>& prio = {}, std::vector<lsk::SplitK>* acc = nullptr,
+                             long long* acc_elems = nullptr, bool flush = false,
+                             const std::vector<std::array<int, 2>>& chunk = {}) {
     std::vector<int> blk;
-    // a pass that would fill fewer than two workgroups per CU splits every task's k-range over
-    // all 4 waves (4x the workgroups, shorter dependent chains)
+    std::vector<int> want(tasks.size());
+    const int top_prio = prio.empty() ? 0 : *std::max_element(prio.begin(), prio.end());
+    auto lead = [&](size_t t) { return prio.empty() || prio[t] == top_prio; };
+    for (size_t t = 0; t < tasks.size(); ++t) want[t] = tasks[t].rpg > 0 ? tasks[t].rpg : rpg;
+    // a pass whose leading tasks would fill fewer than two workgroups per CU splits their
+    // k-ranges over all 4 waves (4x the workgroups, shorter dependent chains)
     for (int pass = 0; pass < 2; ++pass) {
       blk.clear();
+      size_t nlead = 0;
       for (size_t t = 0; t < tasks.size(); ++t) {
         lsk::DTask& tk = tasks[t];
         int kb = 0;
@@ -523,24 +540,38 @@ void build_phases(ls_problem* P, FmmDev& F) {
         }
         tk.ktot = kb;
         tk.Mpad = round_up(std::max(tk.M, 1), lsk::kRowBlock);
-        const int mt = std::min(rpg, (tk.M + 15) / 16);
+        const int mt = std::min(want[t], (tk.M + 15) / 16);
         tk.rpg = std::max(mt, 1);
         tk.nrb = ((tk.M + 15) / 16 + tk.rpg - 1) / tk.rpg;  // row groups of rpg tiles
         const int nbox = tk.nh * tk.nh;
         // waves that split the k-blocks of a tile: enough that one wave chains at most kMaxChain
         // tile-k-blocks (k-blocks times row tiles)
         const long long chain = (long long)kb * mt;
-        tk.kps = (pass == 1 || nbox <= 16 || chain > 2 * kMaxChain) ? 4 : (chain > kMaxChain ? 2 : 1);
+        // a chunk is filler work next to a dependent chain: short blocks, every k-range split
+        // over the 4 waves
+        const bool chunked = !chunk.empty() && chunk[t][1] > 1;
+        tk.kps = ((pass == 1 && lead(t)) || chunked || nbox <= 16 || chain > 2 * kMaxChain)
+                     ? 4
+                     : (chain > kMaxChain ? 2 : 1);
         const int per = 16 * (4 / tk.kps);
         tk.nbb = (nbox + per - 1) / per;
-        // beyond that, workgroups split K (one launch per pass only; the fused launch keeps 1)
+        tk.bb0 = 0;
+        if (chunked) {
+          const int nb = tk.nbb, ci = chunk[t][0], nc = chunk[t][1];
+          tk.bb0 = (int)((long long)nb * ci / nc);
+          tk.nbb = (int)((long long)nb * (ci + 1) / nc) - tk.bb0;
+        }
+        // beyond that, workgroups split K (one launch per pass only; the fused launch keeps 1,
+        // and so does a chain task whose reduction would be deferred past the next pass)
         tk.kgroups = 1;
-        if (!P->opt.fmm_fused && chain > 4 * kMaxChain)
+        const bool deferred_chain = acc && !flush && !prio.empty() && prio[t] > 0;
+        if (!P->opt.fmm_fused && !deferred_chain && !chunked && chain > 4 * kMaxChain)
           tk.kgroups = (int)std::min<long long>(kb, (chain + 4 * kMaxChain - 1) / (4 * kMaxChain));
         tk.blk0 = (int)blk.size();
         for (int i = 0; i < tk.nbb * tk.nrb * tk.kgroups; ++i) blk.push_back((int)t);
+        if (lead(t)) nlead += (size_t)tk.nbb * tk.nrb * tk.kgroups;
       }
-      if (blk.size() >= 512) break;
+      if (nlead >= 512) break;
     }
     // k-block descriptors: per task, its terms' 4-deep k-blocks in term order, each with the
     // address of its operator rows and of its inputs (class plane of the term included), the
@@ -591,6 +622,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
       long long po = 0;
       std::vector<lsk::SplitK> sk;
       ph.sk_elems = 0;
+      long long elems = 0;
       for (auto& tk : tasks)
         if (tk.kgroups > 1) {
           tk.part = ph.part.as<char>() + po * F.esz;
@@ -606,24 +638,36 @@ void build_phases(ls_problem* P, FmmDev& F) {
           d.G = tk.kgroups;
           d.beta = tk.beta;
           sk.push_back(d);
-          ph.sk_elems = std::max(ph.sk_elems, (long long)tk.M * tk.nh * tk.nh);
+          elems = std::max(elems, (long long)tk.M * tk.nh * tk.nh);
         }
-      ph.sk.upload(sk);
-      ph.nsk = (int)sk.size();
+      if (acc) {
+        acc->insert(acc->end(), sk.begin(), sk.end());
+        *acc_elems = std::max(*acc_elems, elems);
+        if (flush) {
+          sk = *acc;
+          elems = *acc_elems;
+        }
+      }
+      if (!acc || flush) {
+        ph.sk_elems = elems;
+        ph.sk.upload(sk);
+        ph.nsk = (int)sk.size();
+      }
     }
     // dispatch order: blocks with the most k-blocks per wave first (the long ones start early
     // instead of forming the tail); entries are (task, block within the task) pairs
-    std::vector<std::array<int, 3>> order;  // work, task, local
+    std::vector<std::array<int, 4>> order;  // priority, work, task, local
     for (size_t q = 0; q < blk.size(); ++q) {
       const lsk::DTask& tk = tasks[blk[q]];
       const int per_wave = (tk.ktot * tk.rpg + tk.kgroups * tk.kps - 1) / (tk.kgroups * tk.kps);
-      order.push_back({per_wave, blk[q], (int)q - tk.blk0});
+      order.push_back({prio.empty() ? 0 : prio[blk[q]], per_wave, blk[q], (int)q - tk.blk0});
     }
-    std::stable_sort(order.begin(), order.end(), [](const auto& a, const auto& b) { return a[0] > b[0]; });
+    std::stable_sort(order.begin(), order.end(),
+                     [](const auto& a, const auto& b) { return a[0] != b[0] ? a[0] > b[0] : a[1] > b[1]; });
     std::vector<int> pairs;
     for (const auto& o : order) {
-      pairs.push_back(o[1]);
       pairs.push_back(o[2]);
+      pairs.push_back(o[3]);
     }
     ph.tasks.upload(tasks);
     ph.terms.upload(terms);
@@ -651,71 +695,113 @@ void build_phases(ls_problem* P, FmmDev& F) {
     return tm;
   };
   const int nhL = p.lv[leaf].nb / 2;
-  // ---- near field + M2L (one launch) ----
-  {
+  // A group of tasks of one kind (near field of one class, M2L of one level, P2M, M2M of one
+  // level) and the complex multiply-adds it applies per product and right-hand side.
+  struct Group {
     std::vector<lsk::DTask> tasks;
     std::vector<lsk::DTerm> terms;
-    for (int c = 0; c < 4; ++c) {
-      lsk::DTask tk{};
-      tk.out = F.ys.p;
-      tk.out_rhs = N;
-      tk.M = s2;
-      tk.nh = nhL;
-      tk.cout = c;
-      tk.beta = 0;
-      set_stage(tk, S_NEAR, -1, -1, -1, p.top <= leaf ? 1 : 0);
-      tk.t0 = (int)terms.size();
-      for (int da = -1; da <= 1; ++da)
-        for (int db = -1; db <= 1; ++db) {
-          lsk::DTerm tm = shift_term(c, {da, db}, nhL);
-          tm.op = opp(F.off_near[(da + 1) * 3 + (db + 1)]);
-          tm.in = F.xs.p;
-          tm.in_rhs = N;
-          tm.K = s2;
-          terms.push_back(tm);
-        }
-      tk.t1 = (int)terms.size();
-      tasks.push_back(tk);
-    }
-    for (int nu = p.top; nu <= leaf; ++nu) {
-      const ls::Level& l = p.lv[nu];
-      int nh = l.nb / 2;
-      for (int dir = 0; dir < l.ndir; ++dir) {
-        int ad = ls::antipodal(dir, l.ndir);
-        // term index lookup for this direction's operator list
-        const auto& kofs = (F.fp32 ? P->nca32 : P->nca64).lv[nu].kofs[dir];
-        for (int c = 0; c < 4; ++c) {
-          lsk::DTask tk{};
-          tk.out = lvl_ptr(loc, nu, dir);
-          tk.out_rhs = F.ml_rhs;
-          tk.M = F.rank[nu][dir];
-          tk.nh = nh;
-          tk.cout = c;
-          tk.beta = 0;
-          set_stage(tk, S_M2L(nu), nu == leaf ? S_P2M : S_UP(nu), -1, -1, 1);
-          tk.t0 = (int)terms.size();
-          if (F.rank[nu][ad] > 0)
-            for (const Off& d : l.terms[c * l.ndir + dir]) {
-              size_t ti = 0;
-              while (ti < kofs.size() && !(kofs[ti].a == d.a && kofs[ti].b == d.b)) ++ti;
-              if (ti == kofs.size()) throw LsError(LS_EINVAL, "internal: M2L offset missing");
-              lsk::DTerm tm = shift_term(c, d, nh);
-              tm.op = opp(F.off_K[nu][dir][ti]);
-              tm.in = lvl_ptr(mult, nu, ad);
-              tm.in_rhs = F.ml_rhs;
-              tm.K = F.rank[nu][ad];
-              tm.coh = 1;
-              terms.push_back(tm);
-            }
-          tk.t1 = (int)terms.size();
-          if (tk.M > 0) tasks.push_back(tk);
-        }
+    double work = 0;
+  };
+  // in-domain (box, term) pairs of a term times its operator size
+  auto term_work = [](const lsk::DTask& tk, const lsk::DTerm& tm) {
+    long long ca = tk.nh, cb = tk.nh;
+    if (tm.mode == lsk::MODE_SHIFT) {
+      ca = cb = 0;
+      for (int h = 0; h < tk.nh; ++h) {
+        ca += (h + tm.sha >= 0 && h + tm.sha < tm.nh_in);
+        cb += (h + tm.shb >= 0 && h + tm.shb < tm.nh_in);
       }
     }
-    mk_phase(F.nearm2l, tasks, terms, 4);
-    F.nearm2l.tag = 0;
+    return (double)ca * cb * tk.M * tm.K;
+  };
+  auto finish = [&](Group& g) {
+    g.work = 0;
+    for (const lsk::DTask& tk : g.tasks)
+      for (int q = tk.t0; q < tk.t1; ++q) g.work += term_work(tk, g.terms[q]);
+  };
+  // appends a group's tasks (term ranges shifted) with dispatch priority pr, as chunk ci of nc
+  // of their box blocks (rpg > 0: row tiles per row group)
+  auto append = [](std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms, std::vector<int>& prio,
+                   std::vector<std::array<int, 2>>& chunk, const Group& g, int pr, int ci = 0, int nc = 1,
+                   int rpg = 0) {
+    const int off = (int)terms.size();
+    for (lsk::DTask tk : g.tasks) {
+      tk.t0 += off;
+      tk.t1 += off;
+      if (rpg > 0) tk.rpg = rpg;
+      tasks.push_back(tk);
+      prio.push_back(pr);
+      chunk.push_back({ci, nc});
+    }
+    terms.insert(terms.end(), g.terms.begin(), g.terms.end());
+  };
+  // ---- near field: one group per class (depends only on the gathered input) ----
+  std::vector<Group> near_g(4);
+  for (int c = 0; c < 4; ++c) {
+    Group& g = near_g[c];
+    lsk::DTask tk{};
+    tk.out = F.ys.p;
+    tk.out_rhs = N;
+    tk.M = s2;
+    tk.nh = nhL;
+    tk.cout = c;
+    tk.beta = 0;
+    tk.rpg = 4;
+    set_stage(tk, S_NEAR, -1, -1, -1, p.top <= leaf ? 1 : 0);
+    tk.t0 = 0;
+    for (int da = -1; da <= 1; ++da)
+      for (int db = -1; db <= 1; ++db) {
+        lsk::DTerm tm = shift_term(c, {da, db}, nhL);
+        tm.op = opp(F.off_near[(da + 1) * 3 + (db + 1)]);
+        tm.in = F.xs.p;
+        tm.in_rhs = N;
+        tm.K = s2;
+        g.terms.push_back(tm);
+      }
+    tk.t1 = (int)g.terms.size();
+    g.tasks.push_back(tk);
+    finish(g);
   }
-
+  // ---- M2L: one group per level (depends on the multipoles of that level) ----
+  std::vector<Group> m2l_g(leaf + 1);
+  for (int nu = p.top; nu <= leaf; ++nu) {
+    Group& g = m2l_g[nu];
+    const ls::Level& l = p.lv[nu];
+    int nh = l.nb / 2;
+    for (int dir = 0; dir < l.ndir; ++dir) {
+      int ad = ls::antipodal(dir, l.ndir);
+      // term index lookup for this direction's operator list
+      const auto& kofs = (F.fp32 ? P->nca32 : P->nca64).lv[nu].kofs[dir];
+      for (int c = 0; c < 4; ++c) {
+        lsk::DTask tk{};
+        tk.out = lvl_ptr(loc, nu, dir);
+        tk.out_rhs = F.ml_rhs;
+        tk.M = F.rank[nu][dir];
+        tk.nh = nh;
+        tk.cout = c;
+        tk.beta = 0;
+        tk.rpg = 4;
+        set_stage(tk, S_M2L(nu), nu == leaf ? S_P2M : S_UP(nu), -1, -1, 1);
+        tk.t0 = (int)g.terms.size();
+        if (F.rank[nu][ad] > 0)
+          for (const Off& d : l.terms[c * l.ndir + dir]) {
+            size_t ti = 0;
+            while (ti < kofs.size() && !(kofs[ti].a == d.a && kofs[ti].b == d.b)) ++ti;
+            if (ti == kofs.size()) throw LsError(LS_EINVAL, "internal: M2L offset missing");
+            lsk::DTerm tm = shift_term(c, d, nh);
+            tm.op = opp(F.off_K[nu][dir][ti]);
+            tm.in = lvl_ptr(mult, nu, ad);
+            tm.in_rhs = F.ml_rhs;
+            tm.K = F.rank[nu][ad];
+            tm.coh = 1;
+            g.terms.push_back(tm);
+          }
+        tk.t1 = (int)g.terms.size();
+        if (tk.M > 0) g.tasks.push_back(tk);
+      }
+    }
+    finish(g);
+  }
   // ---- the fused launch: every task and term of the phases above, and the queue ----
   auto build_fused = [&]() {
     F.fused = Phase();
@@ -839,36 +925,142 @@ void build_phases(ls_problem* P, FmmDev& F) {
     F.fused_wg = W;
   };
   if (p.top > leaf) {
+    // no far field: the near field is the whole product
+    std::vector<lsk::DTask> tasks;
+    std::vector<lsk::DTerm> terms;
+    std::vector<int> prio;
+    std::vector<std::array<int, 2>> chunk;
+    for (const Group& g : near_g) append(tasks, terms, prio, chunk, g, 0);
+    mk_phase(F.nearm2l, tasks, terms, 4);
+    F.nearm2l.tag = 0;
+    F.entries_mid = 0;
+    for (const Group& g : near_g) F.entries_mid += g.work;
     build_fused();
     return;
   }
   // ---- P2M ----
-  {
-    std::vector<lsk::DTask> tasks;
-    std::vector<lsk::DTerm> terms;
-    for (int c = 0; c < 4; ++c) {
-      lsk::DTask tk{};
-      tk.out = lvl_ptr(mult, leaf, 0);
-      tk.out_rhs = F.ml_rhs;
-      tk.M = F.kleaf;
-      tk.nh = nhL;
-      tk.cout = c;
-      tk.beta = 0;
-      set_stage(tk, S_P2M, -1, -1, -1, 1);
-      tk.t0 = (int)terms.size();
-      lsk::DTerm tm{};
-      tm.mode = lsk::MODE_SAME;
-      tm.op = opp(F.off_U);
-      tm.in = F.xs.p;
-      tm.in_rhs = N;
-      tm.K = s2;
-      tm.nh_in = nhL;
-      terms.push_back(tm);
-      tk.t1 = (int)terms.size();
-      tasks.push_back(tk);
+  Group p2m_g;
+  for (int c = 0; c < 4; ++c) {
+    lsk::DTask tk{};
+    tk.out = lvl_ptr(mult, leaf, 0);
+    tk.out_rhs = F.ml_rhs;
+    tk.M = F.kleaf;
+    tk.nh = nhL;
+    tk.cout = c;
+    tk.beta = 0;
+    set_stage(tk, S_P2M, -1, -1, -1, 1);
+    tk.t0 = (int)p2m_g.terms.size();
+    lsk::DTerm tm{};
+    tm.mode = lsk::MODE_SAME;
+    tm.op = opp(F.off_U);
+    tm.in = F.xs.p;
+    tm.in_rhs = N;
+    tm.K = s2;
+    tm.nh_in = nhL;
+    p2m_g.terms.push_back(tm);
+    tk.t1 = (int)p2m_g.terms.size();
+    p2m_g.tasks.push_back(tk);
+  }
+  // ---- M2M (parent nu from children nu+1) ----
+  std::vector<Group> m2m_g(leaf + 1);
+  for (int nu = leaf - 1; nu >= p.top; --nu) {
+    Group& g = m2m_g[nu];
+    const ls::Level& l = p.lv[nu];
+    const ls::Level& cl = p.lv[nu + 1];
+    int nh = l.nb / 2;
+    for (int dir = 0; dir < l.ndir; ++dir) {
+      int cd = cl.hf ? dir / 2 : 0;
+      for (int c = 0; c < 4; ++c) {
+        lsk::DTask tk{};
+        tk.out = lvl_ptr(mult, nu, dir);
+        tk.out_rhs = F.ml_rhs;
+        tk.M = F.rank[nu][dir];
+        tk.nh = nh;
+        tk.cout = c;
+        tk.beta = 0;
+        set_stage(tk, S_UP(nu), nu == leaf - 1 ? S_P2M : S_UP(nu + 1), -1, -1, 1);
+        tk.t0 = (int)g.terms.size();
+        for (int cc = 0; cc < 4; ++cc) {
+          lsk::DTerm tm{};
+          tm.mode = lsk::MODE_CHILD;
+          tm.cin = cc;
+          tm.op = opp(F.off_C[nu][dir][cc]);
+          tm.in = lvl_ptr(mult, nu + 1, cd);
+          tm.in_rhs = F.ml_rhs;
+          tm.coh = 1;
+          tm.K = F.rank[nu + 1][cd];
+          tm.nh_in = cl.nb / 2;
+          if (tm.K > 0) g.terms.push_back(tm);
+        }
+        tk.t1 = (int)g.terms.size();
+        if (tk.M > 0) g.tasks.push_back(tk);
+      }
     }
-    mk_phase(F.p2m, tasks, terms);
-    F.p2m.tag = 1;
+  }
+  // ---- launches up to the middle one: U_0 = P2M, U_j = M2M of level leaf - j (j = 1..nup),
+  // U_{nup+1} = the middle launch.  Independent work is packed into the upward launches, whose
+  // own dependent chain leaves most of the chip idle: the near field (it needs only the
+  // gathered input) in kNearChunks chunks of box blocks per class, spread over U_0..U_nup, in
+  // short blocks (one row tile each, no split K); with kPackM2L also the M2L of level nu, which
+  // needs the multipoles of nu, in the launch after the one that completes them.  What is not
+  // packed forms the middle launch (M2L of the top level at least).  The chain's blocks are
+  // dispatched first, and the split-K reductions of all packed work run once, after the middle
+  // launch (nothing reads those outputs before the downward pass).  Without the matrix-core form
+  // (or in the fused launch) the near field and every M2L form the middle launch.
+  F.up.clear();
+  F.up.resize(leaf - p.top);
+  {
+    // measured on the 512^2 disc at kappa 80: packing the near field (4, 8 or 16 chunks per
+    // class, one or four row tiles per block) or also the M2L made the FP64 product 7-40% and
+    // the FP32 one 15-50% slower than one middle launch with all of it, so both are off
+    constexpr int kNearChunks = 0;
+    constexpr bool kPackM2L = false;
+    constexpr int kFillRpg = 1;
+    const bool pack = P->opt.stencil_mfma && !P->opt.fmm_fused;
+    const int nU = nup + 1;
+    struct Fill {
+      const Group* g;
+      int ci, nc, rpg;
+    };
+    std::vector<std::vector<Fill>> fill(nU + 1);
+    std::vector<double> load(nU + 1, 0.0);
+    for (int nu = p.top; nu <= leaf; ++nu) {
+      const int u = (pack && kPackM2L) ? leaf - nu + 1 : nU;
+      fill[u].push_back({&m2l_g[nu], 0, 1, 0});
+      load[u] += m2l_g[nu].work;
+    }
+    for (int c = 0; c < 4; ++c) {
+      if (pack && kNearChunks > 0) {
+        for (int k = 0; k < kNearChunks; ++k) {
+          const int u = (int)((long long)k * nU / kNearChunks);
+          fill[u].push_back({&near_g[c], k, kNearChunks, kFillRpg});
+          load[u] += near_g[c].work / kNearChunks;
+        }
+      } else {
+        fill[nU].push_back({&near_g[c], 0, 1, 0});
+        load[nU] += near_g[c].work;
+      }
+    }
+    std::vector<lsk::SplitK> acc;
+    long long acc_elems = 0;
+    for (int u = 0; u <= nU; ++u) {
+      std::vector<lsk::DTask> tasks;
+      std::vector<lsk::DTerm> terms;
+      std::vector<int> prio;
+      std::vector<std::array<int, 2>> chunk;
+      if (u == 0) append(tasks, terms, prio, chunk, p2m_g, 1);
+      if (u >= 1 && u < nU) append(tasks, terms, prio, chunk, m2m_g[leaf - u], 1);
+      for (const Fill& f : fill[u]) append(tasks, terms, prio, chunk, *f.g, 0, f.ci, f.nc, f.rpg);
+      Phase& ph = u == 0 ? F.p2m : (u < nU ? F.up[u - 1] : F.nearm2l);
+      if (P->opt.stencil_mfma)
+        make_phase_mfma(ph, tasks, terms, u == nU ? 4 : 1, prio, &acc, &acc_elems, u == nU, chunk);
+      else
+        make_phase(ph, tasks, terms);
+      ph.tag = u == 0 ? 1 : (u < nU ? 2 : 0);
+    }
+    // middle-launch work: chunk shares of a class are counted by box blocks, near enough for a
+    // rate (the classes have equal box counts up to the domain edge)
+    F.entries_mid = load[nU];
   }
   // ---- L2P (accumulates onto the near field) ----
   {
@@ -898,46 +1090,6 @@ void build_phases(ls_problem* P, FmmDev& F) {
     }
     mk_phase(F.l2p, tasks, terms);
     F.l2p.tag = 4;
-  }
-  // ---- M2M (parent nu from children nu+1), deepest first ----
-  F.up.clear();
-  F.up.resize(leaf - p.top);
-  for (int nu = leaf - 1; nu >= p.top; --nu) {
-    const ls::Level& l = p.lv[nu];
-    const ls::Level& cl = p.lv[nu + 1];
-    std::vector<lsk::DTask> tasks;
-    std::vector<lsk::DTerm> terms;
-    int nh = l.nb / 2;
-    for (int dir = 0; dir < l.ndir; ++dir) {
-      int cd = cl.hf ? dir / 2 : 0;
-      for (int c = 0; c < 4; ++c) {
-        lsk::DTask tk{};
-        tk.out = lvl_ptr(mult, nu, dir);
-        tk.out_rhs = F.ml_rhs;
-        tk.M = F.rank[nu][dir];
-        tk.nh = nh;
-        tk.cout = c;
-        tk.beta = 0;
-        set_stage(tk, S_UP(nu), nu == leaf - 1 ? S_P2M : S_UP(nu + 1), -1, -1, 1);
-        tk.t0 = (int)terms.size();
-        for (int cc = 0; cc < 4; ++cc) {
-          lsk::DTerm tm{};
-          tm.mode = lsk::MODE_CHILD;
-          tm.cin = cc;
-          tm.op = opp(F.off_C[nu][dir][cc]);
-          tm.in = lvl_ptr(mult, nu + 1, cd);
-          tm.in_rhs = F.ml_rhs;
-          tm.coh = 1;
-          tm.K = F.rank[nu + 1][cd];
-          tm.nh_in = cl.nb / 2;
-          if (tm.K > 0) terms.push_back(tm);
-        }
-        tk.t1 = (int)terms.size();
-        if (tk.M > 0) tasks.push_back(tk);
-      }
-    }
-    mk_phase(F.up[leaf - 1 - nu], tasks, terms);
-    F.up[leaf - 1 - nu].tag = 2;
   }
   // ---- L2L (parent nu -> children nu+1), top first ----
   F.down.clear();
@@ -1006,7 +1158,7 @@ void ensure_fmm_capacity(ls_problem* P, FmmDev& F, int nrhs) {
 }
 
 void run_phase(ls_problem* P, FmmDev& F, Phase& ph, int nrhs, hipStream_t s, int prof_cls = -1) {
-  if (ph.nblocks == 0) return;
+  if (ph.nblocks == 0 && ph.nsk == 0) return;
   if (ph.mfma) {
     if (prof_cls >= 0) {
       ProfScope ps(P, prof_cls, s);
@@ -2506,6 +2658,8 @@ ls_status ls_setup(const double* points, int64_t N, const double* q, double kapp
     S.entries_far32 = P->have32 ? P->f32.entries_far : 0;
     S.entries_m2l64 = P->f64.entries_m2l;
     S.entries_m2l32 = P->have32 ? P->f32.entries_m2l : 0;
+    S.entries_mid64 = (int64_t)P->f64.entries_mid;
+    S.entries_mid32 = P->have32 ? (int64_t)P->f32.entries_mid : 0;
     S.stored_bytes64 = P->f64.stored_bytes;
     S.stored_bytes32 = P->have32 ? P->f32.stored_bytes : 0;
     S.hodlr_bytes = P->hod.bytes;

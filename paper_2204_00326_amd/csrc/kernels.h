@@ -67,6 +67,7 @@ struct DTask {
   // order g = 0, 1, ... into the output
   int kgroups;
   int nbb;           // box blocks of the task
+  int bb0;           // matrix-core form: first box block (a task may cover a chunk of its level)
   int rpg;           // matrix-core form: 16-row tiles per row group (1..4; nrb = row groups)
   // matrix-core form: the task's k-blocks (ktot of them, in term order), the mode shared by all
   // its terms, the input half-grid side and the input stride between k

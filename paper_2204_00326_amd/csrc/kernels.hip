@@ -569,7 +569,7 @@ __device__ __forceinline__ void mfma_block(const DTask* __restrict__ tasks, cons
                                            int local, int rhs, T (*red)[16][64]) {
   const DTask& tk = tasks[ti];
   const int rg = local % tk.nrb;               // row group (rpg 16-row tiles)
-  const int bb = (local / tk.nrb) % tk.nbb;    // box block
+  const int bb = tk.bb0 + (local / tk.nrb) % tk.nbb;  // box block
   const int grp = local / (tk.nrb * tk.nbb);   // split-K group
   const int ntile = (tk.M + 15) / 16 - tk.rpg * rg;
   switch (ntile >= tk.rpg ? tk.rpg : ntile) {

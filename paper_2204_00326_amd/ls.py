@@ -61,7 +61,7 @@ class _Stats(C.Structure):
                 ("hodlr_rank_used_sum", C.c_int64), ("hodlr_blocks", C.c_int64), ("hodlr_rank_used_max", C.c_int),
                 ("t_hodlr_aca_ms", C.c_double), ("t_hodlr_apply_ms", C.c_double), ("t_hodlr_cores_ms", C.c_double),
                 ("hodlr_rows_active", C.c_int64), ("hodlr_dot_rows", C.c_int64 * 32),
-                ("hodlr_core_nodes", C.c_int * 32)]
+                ("hodlr_core_nodes", C.c_int * 32), ("entries_mid64", C.c_int64), ("entries_mid32", C.c_int64)]
 
 
 class _PlanInfo(C.Structure):
