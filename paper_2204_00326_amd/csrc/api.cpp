@@ -172,6 +172,9 @@ struct FmmDev {
   int64_t entries_far = 0;
   int64_t entries_m2l = 0;
   double entries_mid = 0;  // complex multiply-adds of the middle launch (one right-hand side)
+  // P2M reads the product's input through the tree-order map (and stores the tree-order copy
+  // for the near field) and L2P finishes the output: no separate gather and epilogue launches
+  bool io_fold = false;
   int64_t stored_bytes = 0;
 };
 
@@ -525,7 +528,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
     std::vector<int> want(tasks.size());
     const int top_prio = prio.empty() ? 0 : *std::max_element(prio.begin(), prio.end());
     auto lead = [&](size_t t) { return prio.empty() || prio[t] == top_prio; };
-    for (size_t t = 0; t < tasks.size(); ++t) want[t] = tasks[t].rpg > 0 ? tasks[t].rpg : rpg;
+    for (size_t t = 0; t < tasks.size(); ++t) want[t] = tasks[t].io ? 1 : (tasks[t].rpg > 0 ? tasks[t].rpg : rpg);
     // a pass whose leading tasks would fill fewer than two workgroups per CU splits their
     // k-ranges over all 4 waves (4x the workgroups, shorter dependent chains)
     for (int pass = 0; pass < 2; ++pass) {
@@ -565,7 +568,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
         // and so does a chain task whose reduction would be deferred past the next pass)
         tk.kgroups = 1;
         const bool deferred_chain = acc && !flush && !prio.empty() && prio[t] > 0;
-        if (!P->opt.fmm_fused && !deferred_chain && !chunked && chain > 4 * kMaxChain)
+        if (!P->opt.fmm_fused && !deferred_chain && !chunked && !tk.io && chain > 4 * kMaxChain)
           tk.kgroups = (int)std::min<long long>(kb, (chain + 4 * kMaxChain - 1) / (4 * kMaxChain));
         tk.blk0 = (int)blk.size();
         for (int i = 0; i < tk.nbb * tk.nrb * tk.kgroups; ++i) blk.push_back((int)t);
@@ -926,6 +929,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
   };
   if (p.top > leaf) {
     // no far field: the near field is the whole product
+    F.io_fold = false;
     std::vector<lsk::DTask> tasks;
     std::vector<lsk::DTerm> terms;
     std::vector<int> prio;
@@ -939,9 +943,11 @@ void build_phases(ls_problem* P, FmmDev& F) {
     return;
   }
   // ---- P2M ----
+  F.io_fold = P->opt.stencil_mfma && !P->opt.fmm_fused;
   Group p2m_g;
   for (int c = 0; c < 4; ++c) {
     lsk::DTask tk{};
+    tk.io = F.io_fold ? lsk::IO_GATHER : 0;
     tk.out = lvl_ptr(mult, leaf, 0);
     tk.out_rhs = F.ml_rhs;
     tk.M = F.kleaf;
@@ -1074,6 +1080,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
       tk.nh = nhL;
       tk.cout = c;
       tk.beta = 1;
+      tk.io = F.io_fold ? lsk::IO_EPILOGUE : 0;
       set_stage(tk, S_L2P, nup > 0 ? S_DOWN(leaf - 1) : -1, S_M2L(leaf), S_NEAR, 0);
       tk.t0 = (int)terms.size();
       lsk::DTerm tm{};
@@ -1157,16 +1164,17 @@ void ensure_fmm_capacity(ls_problem* P, FmmDev& F, int nrhs) {
   build_phases(P, F);
 }
 
-void run_phase(ls_problem* P, FmmDev& F, Phase& ph, int nrhs, hipStream_t s, int prof_cls = -1) {
+void run_phase(ls_problem* P, FmmDev& F, Phase& ph, int nrhs, hipStream_t s, int prof_cls = -1,
+               const lsk::IoArgs* io = nullptr) {
   if (ph.nblocks == 0 && ph.nsk == 0) return;
   if (ph.mfma) {
     if (prof_cls >= 0) {
       ProfScope ps(P, prof_cls, s);
       lsk::launch_stencil_mfma(F.fp32, ph.tasks.as<lsk::DTask>(), ph.terms.as<lsk::DTerm>(), ph.blk.as<int>(),
-                               ph.nblocks, nrhs, s);
+                               ph.nblocks, nrhs, s, io);
     } else {
       lsk::launch_stencil_mfma(F.fp32, ph.tasks.as<lsk::DTask>(), ph.terms.as<lsk::DTerm>(), ph.blk.as<int>(),
-                               ph.nblocks, nrhs, s);
+                               ph.nblocks, nrhs, s, io);
     }
     lsk::launch_splitk_reduce(F.fp32, ph.sk.as<lsk::SplitK>(), ph.nsk, ph.sk_elems, nrhs, s);
     return;
@@ -1211,14 +1219,17 @@ void fmm_apply(ls_problem* P, bool fp32, const double2* x, long long ldx, double
     return;
   }
   const int span = kProfSpan + (fp32 ? 5 : 0);
+  const ls::Plan& p = P->plan;
+  // with io_fold the gather is P2M's and the epilogue L2P's (their spans stay empty)
+  const bool fold = F.io_fold && p.top <= p.leaf;
+  lsk::IoArgs io{x, ldx, y, ldy, gidx, q, alpha, coef, F.xs.p, F.ys.p};
   {
     SpanScope sp(P, span + 0, s);
-    lsk::launch_gather(fp32, x, ldx, F.xs.p, gidx, N, nrhs, s);
+    if (!fold) lsk::launch_gather(fp32, x, ldx, F.xs.p, gidx, N, nrhs, s);
   }
-  const ls::Plan& p = P->plan;
   if (p.top <= p.leaf) {
     SpanScope sp(P, span + 1, s);
-    run_phase(P, F, F.p2m, nrhs, s);
+    run_phase(P, F, F.p2m, nrhs, s, -1, fold ? &io : nullptr);
     for (auto& ph : F.up) run_phase(P, F, ph, nrhs, s);
   }
   {
@@ -1228,11 +1239,11 @@ void fmm_apply(ls_problem* P, bool fp32, const double2* x, long long ldx, double
   if (p.top <= p.leaf) {
     SpanScope sp(P, span + 3, s);
     for (auto& ph : F.down) run_phase(P, F, ph, nrhs, s);
-    run_phase(P, F, F.l2p, nrhs, s);
+    run_phase(P, F, F.l2p, nrhs, s, -1, fold ? &io : nullptr);
   }
   {
     SpanScope sp(P, span + 4, s);
-    lsk::launch_epilogue(fp32, x, ldx, F.ys.p, eidx, q, alpha, coef, y, ldy, N, nrhs, s);
+    if (!fold) lsk::launch_epilogue(fp32, x, ldx, F.ys.p, eidx, q, alpha, coef, y, ldy, N, nrhs, s);
   }
   hip_check(hipGetLastError(), "fmm kernels");
 }

@@ -68,6 +68,11 @@ struct DTask {
   int kgroups;
   int nbb;           // box blocks of the task
   int bb0;           // matrix-core form: first box block (a task may cover a chunk of its level)
+  // matrix-core form, one launch per pass: IO_GATHER = the input is the caller's vector read
+  // through the tree-order map (and row group 0 stores the tree-order copy for later passes);
+  // IO_EPILOGUE = the output, accumulated onto the tree-order result, is finished into the
+  // caller's vector (see IoArgs)
+  int io;
   int rpg;           // matrix-core form: 16-row tiles per row group (1..4; nrb = row groups)
   // matrix-core form: the task's k-blocks (ktot of them, in term order), the mode shared by all
   // its terms, the input half-grid side and the input stride between k
@@ -85,10 +90,29 @@ constexpr int kBoxBlock = 64;
 constexpr int kStencilWaves = 4;
 constexpr int kStencilThreads = 64 * kStencilWaves;
 
+constexpr int IO_GATHER = 1;
+constexpr int IO_EPILOGUE = 2;
+// The vectors of one product for tasks with io set: x (ldx per right-hand side) in the caller's
+// (or the solver's) order, the map tree index -> that order (gidx), the tree-order copies xs and
+// ys (N per right-hand side), and the epilogue y[e] = alpha x[e] + coef q[e] v[t] for e = gidx[t]
+// (q may be null: 1), v the accumulated tree-order result.
+struct IoArgs {
+  const double2* x;
+  long long ldx;
+  double2* y;
+  long long ldy;
+  const int* gidx;
+  const double* q;
+  double alpha, coef;
+  const void* xs;
+  const void* ys;
+};
+
 // MFMA form of the stencil (any term modes): a workgroup computes 16 rows x (64 / kps)
-// boxes; complex products as four real 16x16x4 matrix-core operations per k-block.
+// boxes; complex products as four real 16x16x4 matrix-core operations per k-block.  io: the
+// vectors of tasks with io set (may be null if none is).
 void launch_stencil_mfma(bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
-                         int nrhs, hipStream_t s);
+                         int nrhs, hipStream_t s, const IoArgs* io = nullptr);
 void launch_stencil(int tag, bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
                     int nrhs, hipStream_t s);
 

@@ -353,9 +353,12 @@ __device__ inline void st_coh(C2* p, const C2& v) {
 // grp.  COH: honour the coherence flags of the fused launch (inputs and outputs produced or
 // consumed by other workgroups of the same launch).  Called by all 256 threads; contains
 // barriers when the task splits its k-blocks over waves (kps > 1) or workgroups (kgroups > 1).
-template <typename T, bool COH, int MT>
+// IO: 0, IO_GATHER (the input is io.x read through io.gidx; the task has one same-box term, so
+// the tree index of k row k of a lane's box is k * pks + lsrc; row group 0 stores the values
+// into io.xs) or IO_EPILOGUE (the accumulated output is finished into io.y).
+template <typename T, bool COH, int MT, int IO>
 __device__ __forceinline__ void mfma_rows(const DTask& tk, const DTerm* __restrict__ terms, int rg, int bb, int grp,
-                                          int rhs, T (*red)[16][64]) {
+                                          int rhs, T (*red)[16][64], const IoArgs& io) {
   using C2 = typename P2<T>::type;
   using GC = __attribute__((address_space(1))) const C2*;
   using MA = MfmaAcc<T>;
@@ -412,6 +415,18 @@ __device__ __forceinline__ void mfma_rows(const DTask& tk, const DTerm* __restri
   // the block's real depth or outside the domain is zeroed at use.
   C2 ra[D][MT], rx[D];
   bool rv[D];
+  // IO_GATHER: the tree index of the lane's input for the next block of each slot and its index
+  // in io.x (loaded one ring round before the value; a k row past the term's depth takes the
+  // block's first row, inside the level), and the tree index of the value in the slot
+  long long gnx[D], gcur[D];
+  int enx[D];
+  const int kg = IO == IO_GATHER ? terms[tk.t0].K : 0;
+  auto gidx_load = [&](int s, int j) {
+    const int jj = j < b1 ? j : b1 - 1;
+    const int k = 4 * jj + lk < kg ? 4 * jj + lk : 4 * jj;
+    gnx[s] = (long long)k * tk.pks + lsrc;
+    enx[s] = bact ? io.gidx[gnx[s]] : 0;
+  };
   // descriptors of the next ring round, read one round ahead so that the scalar loads complete
   // behind the matrix products instead of stalling the address computation
   struct Dsc {
@@ -448,7 +463,12 @@ __device__ __forceinline__ void mfma_rows(const DTask& tk, const DTerm* __restri
       ra[s][r].y = q->y;
     }
     const C2* px = reinterpret_cast<const C2*>(d_in) + lkc * tk.pks + rhs * tk.in_rhs + src;
-    if (COH && tk.coh_in) {
+    if constexpr (IO == IO_GATHER) {
+      const double2 xv = io.x[rhs * io.ldx + enx[s]];
+      rx[s].x = (T)xv.x;
+      rx[s].y = (T)xv.y;
+      gcur[s] = gnx[s];
+    } else if (COH && tk.coh_in) {
       rx[s] = ld_coh(px);
     } else {
       const GC q = (GC)px;
@@ -460,6 +480,10 @@ __device__ __forceinline__ void mfma_rows(const DTask& tk, const DTerm* __restri
   auto mac = [&](int s) {
     const T zr = 0;
     const T xr = rv[s] ? rx[s].x : zr, xi = rv[s] ? rx[s].y : zr;
+    if constexpr (IO == IO_GATHER) {
+      // the tree-order copy of the input, for the passes that read it later
+      if (rg == 0 && rv[s]) reinterpret_cast<C2*>(const_cast<void*>(io.xs))[rhs * tk.in_rhs + gcur[s]] = rx[s];
+    }
     // the real parts of the operator first, then the imaginary parts: an accumulator is reused
     // only 2 MT products later
 #pragma unroll
@@ -476,9 +500,11 @@ __device__ __forceinline__ void mfma_rows(const DTask& tk, const DTerm* __restri
   if (b0 < b1) {
 #pragma unroll
     for (int s = 0; s < D; ++s) {
+      if constexpr (IO == IO_GATHER) gidx_load(s, b0 + s);
       desc(s, b0 + s);
       fetch(s, b0 + s);
       desc(s, b0 + D + s);
+      if constexpr (IO == IO_GATHER) gidx_load(s, b0 + D + s);
     }
     for (int c = b0; c < b1; c += D) {
 #pragma unroll
@@ -486,6 +512,7 @@ __device__ __forceinline__ void mfma_rows(const DTask& tk, const DTerm* __restri
         mac(s);
         fetch(s, c + D + s);
         desc(s, c + 2 * D + s);
+        if constexpr (IO == IO_GATHER) gidx_load(s, c + 2 * D + s);
       }
     }
   }
@@ -556,38 +583,62 @@ __device__ __forceinline__ void mfma_rows(const DTask& tk, const DTerm* __restri
           o.x += p.x;
           o.y += p.y;
         }
-        if (coh)
+        if constexpr (IO == IO_EPILOGUE) {
+          // finish into the caller's vector: y[e] = alpha x[e] + coef q[e] v, e = gidx[t]
+          const long long t = (po - reinterpret_cast<const C2*>(io.ys)) - rhs * tk.out_rhs;
+          const int e = io.gidx[t];
+          const double c = io.q ? io.coef * io.q[e] : io.coef;
+          double2 r = make_double2(c * (double)o.x, c * (double)o.y);
+          if (io.alpha != 0.0) {
+            const double2 xv = io.x[rhs * io.ldx + e];
+            r.x += io.alpha * xv.x;
+            r.y += io.alpha * xv.y;
+          }
+          io.y[rhs * io.ldy + e] = r;
+        } else if (coh) {
           st_coh(po, o);
-        else
+        } else {
           *po = o;
+        }
       }
     }
 }
 
+// tasks with io set have one row tile per row group (rpg = 1)
 template <typename T, bool COH>
 __device__ __forceinline__ void mfma_block(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms, int ti,
-                                           int local, int rhs, T (*red)[16][64]) {
+                                           int local, int rhs, T (*red)[16][64], const IoArgs& io) {
   const DTask& tk = tasks[ti];
   const int rg = local % tk.nrb;               // row group (rpg 16-row tiles)
   const int bb = tk.bb0 + (local / tk.nrb) % tk.nbb;  // box block
   const int grp = local / (tk.nrb * tk.nbb);   // split-K group
+  if constexpr (!COH) {
+    if (tk.io == IO_GATHER) {
+      mfma_rows<T, false, 1, IO_GATHER>(tk, terms, rg, bb, grp, rhs, red, io);
+      return;
+    }
+    if (tk.io == IO_EPILOGUE) {
+      mfma_rows<T, false, 1, IO_EPILOGUE>(tk, terms, rg, bb, grp, rhs, red, io);
+      return;
+    }
+  }
   const int ntile = (tk.M + 15) / 16 - tk.rpg * rg;
   switch (ntile >= tk.rpg ? tk.rpg : ntile) {
-    case 1: mfma_rows<T, COH, 1>(tk, terms, rg, bb, grp, rhs, red); break;
-    case 2: mfma_rows<T, COH, 2>(tk, terms, rg, bb, grp, rhs, red); break;
-    case 3: mfma_rows<T, COH, 3>(tk, terms, rg, bb, grp, rhs, red); break;
-    default: mfma_rows<T, COH, 4>(tk, terms, rg, bb, grp, rhs, red); break;
+    case 1: mfma_rows<T, COH, 1, 0>(tk, terms, rg, bb, grp, rhs, red, io); break;
+    case 2: mfma_rows<T, COH, 2, 0>(tk, terms, rg, bb, grp, rhs, red, io); break;
+    case 3: mfma_rows<T, COH, 3, 0>(tk, terms, rg, bb, grp, rhs, red, io); break;
+    default: mfma_rows<T, COH, 4, 0>(tk, terms, rg, bb, grp, rhs, red, io); break;
   }
 }
 
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_stencil_mfma(const DTask* __restrict__ tasks, const DTerm* __restrict__ terms,
-                                                      const int* __restrict__ blk_task) {
+                                                      const int* __restrict__ blk_task, IoArgs io) {
   __shared__ T red[3][16][64];
   // blk_task holds (task, block within the task) pairs in dispatch order, heaviest blocks first
   const int ti = __builtin_amdgcn_readfirstlane(blk_task[2 * blockIdx.x]);
   const int local = __builtin_amdgcn_readfirstlane(blk_task[2 * blockIdx.x + 1]);
-  mfma_block<T, false>(tasks, terms, ti, local, blockIdx.y, red);
+  mfma_block<T, false>(tasks, terms, ti, local, blockIdx.y, red, io);
 }
 
 // out[m][box] (+)= sum_{g = 0..G-1} part[g][m][box] for every split-K task of a pass, the planes
@@ -627,15 +678,16 @@ void launch_splitk_reduce(bool fp32, const SplitK* sk, int ntask, long long max_
 }
 
 void launch_stencil_mfma(bool fp32, const DTask* tasks, const DTerm* terms, const int* blk_task, int nblocks,
-                         int nrhs, hipStream_t s) {
+                         int nrhs, hipStream_t s, const IoArgs* io) {
   if (nblocks <= 0) return;
   dim3 grid(nblocks, nrhs);
+  const IoArgs a = io ? *io : IoArgs{};
   if (fp32) {
     auto kern = k_stencil_mfma<float>;
-    LSK_LAUNCH(kern, grid, 256, 0, s, tasks, terms, blk_task);
+    LSK_LAUNCH(kern, grid, 256, 0, s, tasks, terms, blk_task, a);
   } else {
     auto kern = k_stencil_mfma<double>;
-    LSK_LAUNCH(kern, grid, 256, 0, s, tasks, terms, blk_task);
+    LSK_LAUNCH(kern, grid, 256, 0, s, tasks, terms, blk_task, a);
   }
 }
 
@@ -703,7 +755,7 @@ __global__ __launch_bounds__(256, 2) void k_dafmm_fused(const DTask* __restrict_
       }
     }
     __syncthreads();
-    mfma_block<T, true>(tasks, terms, ti, local, rhs, red);
+    mfma_block<T, true>(tasks, terms, ti, local, rhs, red, IoArgs{});
     // this wave's stores (coherent at device scope) are complete before the workgroup counts
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
