@@ -105,7 +105,7 @@ COUNTED = {"hodlr_dot": ("lsk::k_hodlr_dot_seg<lsk::bf16, 4, 8>",),
 
 
 def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok, act=1.0, listed=False, dot_rows=None,
-                       core_nodes=None):
+                       core_nodes=None, per_level=False):
     """Algorithmic HBM bytes per launch of the HODLR level kernels of one apply (one right-hand
     side), averaged over the launches of each class: a level's factor (N x r_l entries of fsz
     bytes) plus z (complex128) read, and z written by an update.  Mirrors the library's level
@@ -116,33 +116,38 @@ def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok, act=1
     (z read there too) and fuses none; the last update, which also stores z~ for flexible GMRES,
     reads all of z and writes the copy.  dot_rows / core_nodes (per level, from the library's
     statistics): the rows whose W^T z an unfused dot forms and the nodes whose K^-1 block is read
-    (the others meet a zero Y: a child without contrast)."""
+    (the others meet a zero Y: a child without contrast).  per_level: ({class: {level: GB}},
+    ranks) instead of the averages."""
     ranks = [max(1, min(rank, (N >> (l + 1)) // rank_div)) if rank_div > 0 else rank for l in range(levels)]
     def chunk(l):
         ch = N >> (l + 1)
         while ch > max_rows and ch % 2 == 0:
             ch //= 2
         return ch
-    cls = {"hodlr_dot": [], "hodlr_update": [], "hodlr_upd_dot": []}
+    # per class: {level: bytes}, keyed like the library's launch tags (the level whose factors
+    # a launch reads; an update fused with the next level's dot is tagged with that level)
+    cls = {"hodlr_dot": {}, "hodlr_update": {}, "hodlr_upd_dot": {}}
     upd = (lambda ra: act * N * ra * fsz + 2 * act * N * 16) if listed else \
           (lambda ra: act * N * ra * fsz + (1 + act) * N * 16)
     pend = -1
     for l in range(levels - 1, -1, -1):
         if pend >= 0 and fused_ok and not listed and N % 1024 == 0 and (N >> pend) % 128 == 0 and chunk(l) == 1024:
-            cls["hodlr_upd_dot"].append(N * (act * ranks[pend] + ranks[l]) * fsz + (1 + act) * N * 16)
+            cls["hodlr_upd_dot"][l] = N * (act * ranks[pend] + ranks[l]) * fsz + (1 + act) * N * 16
         else:
             if pend >= 0:
-                cls["hodlr_update"].append(upd(ranks[pend]))
+                cls["hodlr_update"][pend] = upd(ranks[pend])
             rows = dot_rows[l] if dot_rows else N
-            cls["hodlr_dot"].append(rows * ranks[l] * fsz + rows * 16)
+            cls["hodlr_dot"][l] = rows * ranks[l] * fsz + rows * 16
         pend = l
-    cls["hodlr_update"].append(act * N * ranks[pend] * fsz + (2 + act) * N * 16)
+    cls["hodlr_update"][pend] = act * N * ranks[pend] * fsz + (2 + act) * N * 16
     # SMW core products: the complex128 core inverses (2^l nodes of (2 r_l)^2), the chunk
     # partials of W^T z read once, s written
-    cls["hodlr_core"] = [(core_nodes[l] if core_nodes else 1 << l) * (2 * ranks[l]) ** 2 * 16
+    cls["hodlr_core"] = {l: (core_nodes[l] if core_nodes else 1 << l) * (2 * ranks[l]) ** 2 * 16
                          + (N // chunk(l)) * ranks[l] * 16
-                         + (1 << l) * 2 * ranks[l] * 16 for l in range(levels)]
-    return {c: sum(v) / len(v) / 1e9 for c, v in cls.items() if v}
+                         + (1 << l) * 2 * ranks[l] * 16 for l in range(levels)}
+    if per_level:
+        return {c: {l: b / 1e9 for l, b in v.items()} for c, v in cls.items()}, ranks
+    return {c: sum(v.values()) / len(v) / 1e9 for c, v in cls.items() if v}
 
 
 def _sha256(path):
@@ -525,6 +530,31 @@ def main():
     roof["classes"] = {c: dict(roof_of(c), avg_launch_us=round(cand[c][0] / cand[c][1] * 1e3, 2),
                                launches_timed=cand[c][1], launches=cand[c][2],
                                est_total_ms=round(cand[c][0] / cand[c][1] * cand[c][2], 3)) for c in cand}
+    # per binary level: every HODLR launch of one more mixed solve timed (outside the timed
+    # region), averaged per (class, level), against the level's algorithmic bytes
+    lvl_bytes, lvl_ranks = hodlr_launch_bytes(N, lb, args.rank, args.rank_div, tune["hodlr_rows"] if tune else 1024,
+                                              fsz, pc_fmt == "bf16", act, listed, st["hodlr_dot_rows"][:lb],
+                                              st["hodlr_core_nodes"][:lb], per_level=True)
+    hcls = ("hodlr_dot", "hodlr_update", "hodlr_upd_dot", "hodlr_core")
+    for c in hcls:
+        P.profile_enable(c, 1)
+    solve(ls.LS_MIXED)
+    each = {c: P.profile_read_each(c) for c in hcls}
+    for c in hcls:
+        P.profile_enable(c, 0)
+    levels_tab = []
+    for l in range(lb):
+        row = {"level": l, "rank": lvl_ranks[l], "dot_rows": st["hodlr_dot_rows"][l],
+               "core_nodes": st["hodlr_core_nodes"][l]}
+        for c in hcls:
+            t = [ms for ms, tag in each[c] if tag == l]
+            if t and l in lvl_bytes[c]:
+                us = 1e3 * sum(t) / len(t)
+                gbs = lvl_bytes[c][l] / (us / 1e6)
+                row[c] = {"us": round(us, 2), "launches": len(t), "GB": round(lvl_bytes[c][l], 5),
+                          "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        levels_tab.append(row)
+    log("hodlr levels", levels_tab)
 
 
     line = {
@@ -576,6 +606,7 @@ def main():
                                                              "hodlr_cores")},
         "ranks": {"fp64": st["rank_max64"], "fp32": st["rank_max32"]},
         "roofline": roof,
+        "hodlr_levels": levels_tab,
         "error_function": err_fn,
     }
     if args.tradeoff_rank > 0:

@@ -347,6 +347,11 @@ ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt,
 ls_status ls_profile_enable(ls_problem* P, int kernel_class, int every);
 ls_status ls_profile_read(ls_problem* P, int kernel_class, double* total_ms, int64_t* launches,
                           int64_t* all_launches);
+/* The timed launches of a class one by one, in launch order: ms[i] and tags[i] (the binary
+ * level for the HODLR classes 1, 5, 6, 7 — the level whose factors the launch reads, for an
+ * update fused with the next level's dot products the next level; -1 for the others) for
+ * i < min(cap, *n); *n = the number of timed launches.  Synchronises like ls_profile_read. */
+ls_status ls_profile_read_each(ls_problem* P, int kernel_class, double* ms, int* tags, int64_t cap, int64_t* n);
 
 /* ---------------------------------------------------------------------------------------
  * Learned GMRES warm start (an extension; the paper has no learned component).

@@ -250,6 +250,7 @@ struct ProfileClass {
   int every = 1;       // time every `every`-th launch
   int64_t count = 0;   // launches of the class since enabling
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<int> tag;  // per timed launch: the caller's tag (a HODLR level; -1 none)
   size_t used = 0;     // timed launches
 };
 
@@ -300,7 +301,7 @@ namespace {
 struct ProfScope {
   ProfileClass* pc;
   hipStream_t s;
-  ProfScope(ls_problem* P, int cls, hipStream_t st, bool on = true) : pc(&P->prof[cls]), s(st) {
+  ProfScope(ls_problem* P, int cls, hipStream_t st, bool on = true, int tag = -1) : pc(&P->prof[cls]), s(st) {
     if (!on || !pc->enabled || P->capturing || (pc->count++ % pc->every) != 0) {
       pc = nullptr;
       return;
@@ -310,7 +311,9 @@ struct ProfScope {
       hip_check(hipEventCreate(&a), "hipEventCreate");
       hip_check(hipEventCreate(&b), "hipEventCreate");
       pc->ev.push_back({a, b});
+      pc->tag.push_back(-1);
     }
+    pc->tag[pc->used] = tag;
     auto& pr = pc->ev[pc->used++];
     lsk::set_next_launch_events(pr.first, pr.second);
   }
@@ -336,6 +339,8 @@ struct SpanScope {
       hip_check(hipEventCreate(&b), "hipEventCreate");
       pc->ev.push_back({a, b});
     }
+    if (pc->tag.size() < pc->ev.size()) pc->tag.resize(pc->ev.size(), -1);
+    pc->tag[pc->used] = -1;
     pr = &pc->ev[pc->used++];
     hip_check(hipEventRecord(pr->first, s), "hipEventRecord");
   }
@@ -1307,7 +1312,7 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
   bool copied = false;
   auto update = [&](int a, bool last) {
     const void* Y = fmt == 2 ? H.Y16[a].p : (fmt == 1 ? H.Y32[a].p : H.Y64[a].p);
-    ProfScope ps(P, 1, s, tm);
+    ProfScope ps(P, 1, s, tm, a);
     if (H.sparse && nrhs == 1 && fmt >= 1 && !(last && zcopy)) {
       lsk::launch_hodlr_update_list(fmt, Y, svec, z, H.N, H.rank[a], H.N >> a, H.alist.as<int>(),
                                     H.nact, s);
@@ -1325,12 +1330,12 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
     // activity of the level's children (after setup): chunks and core rows that meet a zero Y are skipped
     const unsigned char* cact = H.nodeact.p ? H.nodeact.as<unsigned char>() + (2LL << l) : nullptr;
     if (pend >= 0 && fmt == 2 && nrhs == 1 && !H.sparse && lsk::hodlr_upd_dot_ok(H.N, H.N >> pend, H.chunk[l])) {
-      ProfScope pf(P, 6, s, tm);
+      ProfScope pf(P, 6, s, tm, l);
       lsk::launch_hodlr_upd_dot(H.Y16[pend].p, H.rank[pend], svec, H.N >> pend, 1 << pend, W, rl, z,
                                 H.N, partial, H.chunk[l], s, H.ract.as<unsigned char>());
     } else {
       if (pend >= 0) update(pend, false);
-      ProfScope pd(P, 5, s, tm);
+      ProfScope pd(P, 5, s, tm, l);
       lsk::launch_hodlr_dot(fmt, W, z, ldz, partial, H.N, rl, H.chunk[l], H.nchunks[l], nrhs, s,
                             cact ? H.dlist.as<int>() + H.doff[l] : nullptr, cact ? H.dcnt[l] : 0, H.cpc[l]);
     }
@@ -1339,7 +1344,7 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
     const int cf = P->opt.pc_lowp_solves ? fmt : 0;
     const void* C = cf == 2 ? H.core16[l].p : (cf == 1 ? H.core32[l].p : H.coreinv[l].p);
     {
-      ProfScope pc(P, 7, s, tm);
+      ProfScope pc(P, 7, s, tm, l);
       lsk::launch_hodlr_core(cf, C, partial, svec, rl, nodes, H.cpc[l], H.nchunks[l],
                              true, nrhs, s, cact);
     }
@@ -3292,6 +3297,26 @@ ls_status ls_profile_enable(ls_problem* P, int cls, int every) {
     pc.count = 0;
   }
   return LS_OK;
+}
+
+ls_status ls_profile_read_each(ls_problem* P, int cls, double* ms, int* tags, int64_t cap, int64_t* n) {
+  try {
+    if (!P || cls < 0 || cls >= kProfClasses || cap < 0 || (cap > 0 && (!ms || !tags)) || !n)
+      throw LsError(LS_EINVAL, "bad arguments");
+    ProfileClass& pc = P->prof[cls];
+    const size_t m = std::min(pc.used, (size_t)cap);
+    for (size_t i = 0; i < m; ++i) {
+      hip_check(hipEventSynchronize(pc.ev[i].second), "event sync");
+      float t = 0;
+      hip_check(hipEventElapsedTime(&t, pc.ev[i].first, pc.ev[i].second), "elapsed");
+      ms[i] = t;
+      tags[i] = i < pc.tag.size() ? pc.tag[i] : -1;
+    }
+    *n = (int64_t)pc.used;
+    return LS_OK;
+  } catch (const LsError& e) {
+    return fail(e);
+  }
 }
 
 ls_status ls_profile_read(ls_problem* P, int cls, double* total_ms, int64_t* launches, int64_t* all_launches) {

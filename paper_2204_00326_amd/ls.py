@@ -111,6 +111,7 @@ def lib():
     L.ls_error_eval.argtypes = [vp, vp, i64, vp, cd, vp, vp, vp]
     L.ls_profile_enable.argtypes = [vp, ci, ci]
     L.ls_profile_read.argtypes = [vp, ci, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.ls_profile_read_each.argtypes = [vp, ci, vp, vp, i64, C.POINTER(C.c_int64)]
     L.ls_nop_create.argtypes = [C.POINTER(_NopConfig), C.POINTER(vp)]
     L.ls_nop_param_count.argtypes = [vp]
     L.ls_nop_param_count.restype = C.c_int64
@@ -130,7 +131,8 @@ def lib():
         getattr(L, name).restype = C.c_int
     for name in ("ls_setup", "ls_matvec", "ls_apply_V", "ls_precond_apply", "ls_precond_apply_noalloc",
                  "ls_rhs_planewave", "ls_solve",
-                 "ls_stats", "ls_plan_describe", "ls_profile_enable", "ls_profile_read", "ls_green_table",
+                 "ls_stats", "ls_plan_describe", "ls_profile_enable", "ls_profile_read", "ls_profile_read_each",
+                 "ls_green_table",
                  "ls_solve_queue", "ls_autotune"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -354,6 +356,15 @@ class Problem:
     def profile_enable(self, cls: str, every: int = 1):
         """Time every `every`-th launch of a kernel class (0 or False: stop)."""
         _check(lib().ls_profile_enable(self._h, _prof_index(cls), int(every)))
+
+    def profile_read_each(self, cls: str):
+        """[(ms, tag)] of the timed launches of a class in launch order (tag: HODLR level or -1)"""
+        n = C.c_int64()
+        _check(lib().ls_profile_read_each(self._h, _prof_index(cls), None, None, 0, C.byref(n)))
+        ms = (C.c_double * max(n.value, 1))()
+        tg = (C.c_int * max(n.value, 1))()
+        _check(lib().ls_profile_read_each(self._h, _prof_index(cls), ms, tg, n.value, C.byref(n)))
+        return [(ms[i], tg[i]) for i in range(n.value)]
 
     def profile_read(self, cls: str):
         """(summed ms of the timed launches, timed launches, all launches since enabling)"""

@@ -145,3 +145,12 @@ def test_plan_rejects_bad_options():
         ls.plan_describe(31, 1.0, 10.0)       # odd side: no quadtree split
     with pytest.raises(ls.LsError):
         ls.plan_describe(32, 1.0, -3.0)
+
+
+def test_profile_readers_reject_bad_arguments():
+    L = ls.lib()
+    n = C.c_int64()
+    ms = C.c_double()
+    assert L.ls_profile_read_each(None, 5, None, None, 0, C.byref(n)) == ls.LS_EINVAL
+    assert L.ls_profile_read(None, 0, C.byref(ms), C.byref(n), None) == ls.LS_EINVAL
+    assert L.ls_profile_enable(None, 0, 1) == ls.LS_EINVAL
