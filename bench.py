@@ -113,8 +113,9 @@ def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok, act=1
     fused with the next level's dot where that level's chunks are 1024 rows.  act: the fraction
     of rows in 256-row blocks with contrast; an update reads Y and writes z only there (the
     other rows of Y are zero).  listed: the library runs the updates over the listed blocks only
-    (z read there too) and fuses none; the last update, which also stores z~ for flexible GMRES,
-    reads all of z and writes the copy.  dot_rows / core_nodes (per level, from the library's
+    (z read there too) and fuses none, the last one included (the z~ copy for flexible GMRES is
+    a launch of its own); unlisted, the last update also stores z~, reading all of z and writing
+    the copy.  dot_rows / core_nodes (per level, from the library's
     statistics): the rows whose W^T z an unfused dot forms and the nodes whose K^-1 block is read
     (the others meet a zero Y: a child without contrast).  per_level: ({class: {level: GB}},
     ranks) instead of the averages."""
@@ -139,7 +140,9 @@ def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok, act=1
             rows = dot_rows[l] if dot_rows else N
             cls["hodlr_dot"][l] = rows * ranks[l] * fsz + rows * 16
         pend = l
-    cls["hodlr_update"][pend] = act * N * ranks[pend] * fsz + (2 + act) * N * 16
+    # the last update: listed like the others (the z~ copy is a launch of its own), else it
+    # also reads all of z and writes the copy
+    cls["hodlr_update"][pend] = upd(ranks[pend]) if listed else act * N * ranks[pend] * fsz + (2 + act) * N * 16
     # SMW core products: the complex128 core inverses (2^l nodes of (2 r_l)^2), the chunk
     # partials of W^T z read once, s written
     cls["hodlr_core"] = {l: (core_nodes[l] if core_nodes else 1 << l) * (2 * ranks[l]) ** 2 * 16

@@ -1313,7 +1313,9 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
   auto update = [&](int a, bool last) {
     const void* Y = fmt == 2 ? H.Y16[a].p : (fmt == 1 ? H.Y32[a].p : H.Y64[a].p);
     ProfScope ps(P, 1, s, tm, a);
-    if (H.sparse && nrhs == 1 && fmt >= 1 && !(last && zcopy)) {
+    // the listed update also for the last level when z~ is stored: the copy follows in its own
+    // launch (the wide kernel's one-wave-per-SIMD column loop is the slower of the two there)
+    if (H.sparse && nrhs == 1 && fmt >= 1) {
       lsk::launch_hodlr_update_list(fmt, Y, svec, z, H.N, H.rank[a], H.N >> a, H.alist.as<int>(),
                                     H.nact, s);
       copied = false;
