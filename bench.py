@@ -497,6 +497,9 @@ def main():
         "near_m2l32": ("mfma", "f32", 8.0 * st["entries_mid32"] / 1e12),
         # HODLR level launches (unfused dot, unfused update, update fused with the next dot)
         **{c: ("hbm", None, v) for c, v in hb.items()},
+        # leaf solves: the complex128 inverses of the leaves with contrast (leaf_side^2 points
+        # each), b read and z written
+        "leaf_solve": ("hbm", None, (st["hodlr_dense_leaves"] * (st["leaf_side"] ** 2) ** 2 * 16 + 2 * N * 16) / 1e9),
     }
     cand = {c: prof[c] for c in per_launch if prof[c][1] > 0}
 
@@ -525,7 +528,8 @@ def main():
                                       "(HODLR z -= Y s)",
                       "hodlr_dot": f"k_hodlr_dot_seg<{'bf16, 4' if args.pc_bf16 else 'float, 2'}> (HODLR W^T z)",
                       "hodlr_upd_dot": "k_hodlr_upd_dot<1024> (HODLR z -= Y s fused with the next level's W^T z)",
-                      "hodlr_core": "k_hodlr_core_rows (HODLR SMW core products s = K^-1 t)"}[dom]
+                      "hodlr_core": "k_hodlr_core_rows (HODLR SMW core products s = K^-1 t)",
+                      "leaf_solve": "k_leaf_apply<double> (HODLR leaf inverses)"}[dom]
     roof["avg_launch_us"] = round(tot_ms / launches * 1e3, 2)
     roof["launches_timed"] = launches
     roof["launches"] = all_launches
