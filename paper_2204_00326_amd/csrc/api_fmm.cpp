@@ -879,12 +879,13 @@ void fmm_apply(ls_problem* P, bool fp32, const double2* x, long long ldx, double
   }
   const int span = kProfSpan + (fp32 ? 5 : 0);
   const ls::Plan& p = P->plan;
-  // with io_fold the gather is P2M's and the epilogue L2P's (their spans stay empty)
+  // with io_fold the gather is P2M's and the epilogue L2P's (their spans are not opened: an
+  // empty span would read the cost of two event records, about 4 us)
   const bool fold = F.io_fold && p.top <= p.leaf;
   lsk::IoArgs io{x, ldx, y, ldy, gidx, q, alpha, coef, F.xs.p, F.ys.p};
-  {
+  if (!fold) {
     SpanScope sp(P, span + 0, s);
-    if (!fold) lsk::launch_gather(fp32, x, ldx, F.xs.p, gidx, N, nrhs, s);
+    lsk::launch_gather(fp32, x, ldx, F.xs.p, gidx, N, nrhs, s);
   }
   if (p.top <= p.leaf) {
     SpanScope sp(P, span + 1, s);
@@ -900,9 +901,9 @@ void fmm_apply(ls_problem* P, bool fp32, const double2* x, long long ldx, double
     for (auto& ph : F.down) run_phase(P, F, ph, nrhs, s);
     run_phase(P, F, F.l2p, nrhs, s, -1, fold ? &io : nullptr);
   }
-  {
+  if (!fold) {
     SpanScope sp(P, span + 4, s);
-    if (!fold) lsk::launch_epilogue(fp32, x, ldx, F.ys.p, eidx, q, alpha, coef, y, ldy, N, nrhs, s);
+    lsk::launch_epilogue(fp32, x, ldx, F.ys.p, eidx, q, alpha, coef, y, ldy, N, nrhs, s);
   }
   hip_check(hipGetLastError(), "fmm kernels");
 }

@@ -89,6 +89,8 @@ def test_pass_spans_of_the_product_cover_every_pass_once():
             P.profile_enable(k, 0)
         say(b, {k: (round(v[0], 4), v[1], v[2]) for k, v in got.items()}, "whole", e0.elapsed_time(e1))
         for k, (ms, timed, launches) in got.items():
+            if k.endswith(("_gather", "_epilogue")) and launches == 0:
+                continue  # folded into P2M and L2P: no launch, no span
             assert timed == launches == 4 and ms > 0.0, k
         assert sum(v[0] for v in got.values()) <= e0.elapsed_time(e1)
         if prec == ls.LS_FP64:
