@@ -268,6 +268,36 @@ def rhs_block(args, torch, np, inputs, ls):
     return out
 
 
+def matvec_block(P, st, n, torch, np, ls, nrhs):
+    """The product on a block of nrhs columns (the batched form: one launch per pass for every
+    column): median of 10 event-timed block products per precision, per-column time and the
+    matrix-core roof of the whole block."""
+    stream = torch.cuda.current_stream()
+    x = torch.randn(nrhs, n * n, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    out = {}
+    for name, prec, dt, far in (("fp64", ls.LS_FP64, "f64", "entries_far64"), ("fp32", ls.LS_FP32, "f32", "entries_far32")):
+        for _ in range(3):
+            P.matvec(x, y, prec=prec)
+        ts = []
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            P.matvec(x, y, prec=prec)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        flops = 8.0 * (st["entries_near"] + st[far]) * nrhs
+        ach = flops / (ms * 1e-3) / 1e12
+        out[name] = {"bound": "mfma", "achieved": round(ach, 3), "peak": MFMA_PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+                     "frac": round(ach / MFMA_PEAK_TFLOPS[dt], 4), "nrhs": nrhs, "us_per_block": round(1e3 * ms, 1),
+                     "us_per_column": round(1e3 * ms / nrhs, 2), "columns_per_s": round(nrhs / (ms * 1e-3), 1)}
+    del x, y
+    log(f"matvec block of {nrhs}", out)
+    return out
+
+
 def matvec_rates(P, st, n, torch, np, ls):
     """Median time of the FP64 and FP32 products (30 event-timed products each after 3 warm-up
     ones), their per-pass split and the whole product against the matrix-core roof."""
@@ -347,6 +377,8 @@ def main():
                     help="also solve this many plane waves on Gaussian bumps as one block (0: skip)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"),
                     help="summarise two rocprofv3 --pmc runs of this bench into the traffic file and exit")
+    ap.add_argument("--mv-block", type=int, default=64,
+                    help="columns of the block product measured beside the single-column one (0: none)")
     ap.add_argument("--matvec-only", action="store_true",
                     help="time only the DAFMM products (no preconditioner, no solve) and print their line")
     args = ap.parse_args()
@@ -371,12 +403,13 @@ def main():
         P = ls.Problem(pb.points(), pb.q, kappa, 1e-10, ls.Options(hodlr_rank=0, eps_inner=1e-7))
         st = P.stats()
         rates, _, roof_mv = matvec_rates(P, st, n, torch, np, ls)
+        blk = matvec_block(P, st, n, torch, np, ls, args.mv_block) if args.mv_block > 0 else None
         print(json.dumps({"metric": "DAFMM matvec/s", "value": round(rates["fp64"], 1), "unit": "matvec/s",
                           "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
                           "config": {"workload": f"disc{n}_k{kappa:g}_matvec", "n": n, "kappa": kappa,
                                      "eps_nca": 1e-10, "eps_inner": 1e-7},
                           "matvec_per_s": {k: round(v, 1) for k, v in rates.items()},
-                          "roofline_matvec": roof_mv}), flush=True)
+                          "roofline_matvec": roof_mv, "roofline_matvec_block": blk}), flush=True)
         P.close()
         return
     t0 = time.perf_counter()
@@ -472,6 +505,9 @@ def main():
     log("error function", err_fn)
 
     rates, passes, roof_mv = matvec_rates(P, st, n, torch, np, ls)
+    # the batched form: one block of right-hand sides per product (operator tiles reused across
+    # the columns, the passes' latency shared by all of them)
+    roof_blk = matvec_block(P, st, n, torch, np, ls, args.mv_block) if args.mv_block > 0 else None
 
     # calibration copy of COPY_BYTES for the HBM counters (read and written once)
     src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
@@ -608,6 +644,7 @@ def main():
         "matvec_per_s": {k: round(v, 1) for k, v in rates.items()},
         # the spec roof of the matvec: the whole ls_matvec (all passes) against the MFMA peak
         "roofline_matvec": roof_mv,
+        "roofline_matvec_block": roof_blk,
         "setup_s": round(t_setup, 3),
         "setup_ms": {k: round(st[f"t_{k}_ms"], 1) for k in ("plan", "nca", "hodlr", "hodlr_aca", "hodlr_apply",
                                                              "hodlr_cores")},

@@ -122,8 +122,12 @@ void build_phases(ls_problem* P, FmmDev& F) {
   };
   const long long N = P->N;
   // longest chain of k-blocks one wave of the matrix-core form should carry (longer tasks split
-  // over more waves, then over more workgroups), so that no block forms a long tail
-  const int kMaxChain = F.fp32 ? 144 : 72;
+  // over more waves, then over more workgroups), so that no block forms a long tail; row tiles
+  // per block in the chain passes; set per pass layout below
+  int kMaxChain = F.fp32 ? 144 : 72;
+  int chain_rpg = 1;
+  bool record_hps = true;  // the narrow layout's task lists also feed the fused launch
+  Passes* S = &F.narrow;
   // stages of the fused launch: P2M, near field, M2M per parent level, M2L per level, L2L per
   // parent level, L2P; a task's stage and prerequisites are set where the task is made
   const int nup = p.top <= leaf ? leaf - p.top : 0;
@@ -338,7 +342,7 @@ void build_phases(ls_problem* P, FmmDev& F) {
     ph.nblocks = (int)blk.size();
     ph.ntasks = (int)tasks.size();
     ph.mfma = true;
-    hps.push_back({tasks, terms, pairs});
+    if (record_hps) hps.push_back({tasks, terms, pairs});
   };
   auto mk_phase = [&](Phase& ph, std::vector<lsk::DTask>& tasks, std::vector<lsk::DTerm>& terms, int rpg = 1) {
     if (P->opt.stencil_mfma)
@@ -588,215 +592,229 @@ void build_phases(ls_problem* P, FmmDev& F) {
     F.fused_wg = W;
   };
   if (p.top > leaf) {
-    // no far field: the near field is the whole product
-    F.io_fold = false;
-    std::vector<lsk::DTask> tasks;
-    std::vector<lsk::DTerm> terms;
-    std::vector<int> prio;
-    std::vector<std::array<int, 2>> chunk;
-    for (const Group& g : near_g) append(tasks, terms, prio, chunk, g, 0);
-    mk_phase(F.nearm2l, tasks, terms, 4);
-    F.nearm2l.tag = 0;
+    // no far field: the near field is the whole product (the same in both layouts)
+    for (Passes* T : {&F.narrow, &F.wide}) {
+      record_hps = T == &F.narrow;
+      T->io_fold = false;
+      T->up.clear();
+      T->down.clear();
+      std::vector<lsk::DTask> tasks;
+      std::vector<lsk::DTerm> terms;
+      std::vector<int> prio;
+      std::vector<std::array<int, 2>> chunk;
+      for (const Group& g : near_g) append(tasks, terms, prio, chunk, g, 0);
+      mk_phase(T->nearm2l, tasks, terms, 4);
+      T->nearm2l.tag = 0;
+    }
     F.entries_mid = 0;
     for (const Group& g : near_g) F.entries_mid += g.work;
     build_fused();
     return;
   }
-  // ---- P2M ----
-  F.io_fold = P->opt.stencil_mfma && !P->opt.fmm_fused;
-  Group p2m_g;
-  for (int c = 0; c < 4; ++c) {
-    lsk::DTask tk{};
-    tk.io = F.io_fold ? lsk::IO_GATHER : 0;
-    tk.out = lvl_ptr(mult, leaf, 0);
-    tk.out_rhs = F.ml_rhs;
-    tk.M = F.kleaf;
-    tk.nh = nhL;
-    tk.cout = c;
-    tk.beta = 0;
-    set_stage(tk, S_P2M, -1, -1, -1, 1);
-    tk.t0 = (int)p2m_g.terms.size();
-    lsk::DTerm tm{};
-    tm.mode = lsk::MODE_SAME;
-    tm.op = opp(F.off_U);
-    tm.in = F.xs.p;
-    tm.in_rhs = N;
-    tm.K = s2;
-    tm.nh_in = nhL;
-    p2m_g.terms.push_back(tm);
-    tk.t1 = (int)p2m_g.terms.size();
-    p2m_g.tasks.push_back(tk);
-  }
-  // ---- M2M (parent nu from children nu+1) ----
-  std::vector<Group> m2m_g(leaf + 1);
-  for (int nu = leaf - 1; nu >= p.top; --nu) {
-    Group& g = m2m_g[nu];
-    const ls::Level& l = p.lv[nu];
-    const ls::Level& cl = p.lv[nu + 1];
-    int nh = l.nb / 2;
-    for (int dir = 0; dir < l.ndir; ++dir) {
-      int cd = cl.hf ? dir / 2 : 0;
-      for (int c = 0; c < 4; ++c) {
-        lsk::DTask tk{};
-        tk.out = lvl_ptr(mult, nu, dir);
-        tk.out_rhs = F.ml_rhs;
-        tk.M = F.rank[nu][dir];
-        tk.nh = nh;
-        tk.cout = c;
-        tk.beta = 0;
-        set_stage(tk, S_UP(nu), nu == leaf - 1 ? S_P2M : S_UP(nu + 1), -1, -1, 1);
-        tk.t0 = (int)g.terms.size();
-        for (int cc = 0; cc < 4; ++cc) {
-          lsk::DTerm tm{};
-          tm.mode = lsk::MODE_CHILD;
-          tm.cin = cc;
-          tm.op = opp(F.off_C[nu][dir][cc]);
-          tm.in = lvl_ptr(mult, nu + 1, cd);
-          tm.in_rhs = F.ml_rhs;
-          tm.coh = 1;
-          tm.K = F.rank[nu + 1][cd];
-          tm.nh_in = cl.nb / 2;
-          if (tm.K > 0) g.terms.push_back(tm);
-        }
-        tk.t1 = (int)g.terms.size();
-        if (tk.M > 0) g.tasks.push_back(tk);
-      }
-    }
-  }
-  // ---- launches up to the middle one: U_0 = P2M, U_j = M2M of level leaf - j (j = 1..nup),
-  // U_{nup+1} = the middle launch.  Independent work is packed into the upward launches, whose
-  // own dependent chain leaves most of the chip idle: the near field (it needs only the
-  // gathered input) in kNearChunks chunks of box blocks per class, spread over U_0..U_nup, in
-  // short blocks (one row tile each, no split K); with kPackM2L also the M2L of level nu, which
-  // needs the multipoles of nu, in the launch after the one that completes them.  What is not
-  // packed forms the middle launch (M2L of the top level at least).  The chain's blocks are
-  // dispatched first, and the split-K reductions of all packed work run once, after the middle
-  // launch (nothing reads those outputs before the downward pass).  Without the matrix-core form
-  // (or in the fused launch) the near field and every M2L form the middle launch.
-  F.up.clear();
-  F.up.resize(leaf - p.top);
-  {
-    // measured on the 512^2 disc at kappa 80: packing the near field (4, 8 or 16 chunks per
-    // class, one or four row tiles per block) or also the M2L made the FP64 product 7-40% and
-    // the FP32 one 15-50% slower than one middle launch with all of it, so both are off
-    constexpr int kNearChunks = 0;
-    constexpr bool kPackM2L = false;
-    constexpr int kFillRpg = 1;
-    const bool pack = P->opt.stencil_mfma && !P->opt.fmm_fused;
-    const int nU = nup + 1;
-    struct Fill {
-      const Group* g;
-      int ci, nc, rpg;
-    };
-    std::vector<std::vector<Fill>> fill(nU + 1);
-    std::vector<double> load(nU + 1, 0.0);
-    for (int nu = p.top; nu <= leaf; ++nu) {
-      const int u = (pack && kPackM2L) ? leaf - nu + 1 : nU;
-      fill[u].push_back({&m2l_g[nu], 0, 1, 0});
-      load[u] += m2l_g[nu].work;
-    }
-    for (int c = 0; c < 4; ++c) {
-      if (pack && kNearChunks > 0) {
-        for (int k = 0; k < kNearChunks; ++k) {
-          const int u = (int)((long long)k * nU / kNearChunks);
-          fill[u].push_back({&near_g[c], k, kNearChunks, kFillRpg});
-          load[u] += near_g[c].work / kNearChunks;
-        }
-      } else {
-        fill[nU].push_back({&near_g[c], 0, 1, 0});
-        load[nU] += near_g[c].work;
-      }
-    }
-    std::vector<lsk::SplitK> acc;
-    long long acc_elems = 0;
-    for (int u = 0; u <= nU; ++u) {
-      std::vector<lsk::DTask> tasks;
-      std::vector<lsk::DTerm> terms;
-      std::vector<int> prio;
-      std::vector<std::array<int, 2>> chunk;
-      if (u == 0) append(tasks, terms, prio, chunk, p2m_g, 1);
-      if (u >= 1 && u < nU) append(tasks, terms, prio, chunk, m2m_g[leaf - u], 1);
-      for (const Fill& f : fill[u]) append(tasks, terms, prio, chunk, *f.g, 0, f.ci, f.nc, f.rpg);
-      Phase& ph = u == 0 ? F.p2m : (u < nU ? F.up[u - 1] : F.nearm2l);
-      if (P->opt.stencil_mfma)
-        make_phase_mfma(ph, tasks, terms, u == nU ? 4 : 1, prio, &acc, &acc_elems, u == nU, chunk);
-      else
-        make_phase(ph, tasks, terms);
-      ph.tag = u == 0 ? 1 : (u < nU ? 2 : 0);
-    }
-    // middle-launch work: chunk shares of a class are counted by box blocks, near enough for a
-    // rate (the classes have equal box counts up to the domain edge)
-    F.entries_mid = load[nU];
-  }
-  // ---- L2P (accumulates onto the near field) ----
-  {
-    std::vector<lsk::DTask> tasks;
-    std::vector<lsk::DTerm> terms;
+  // two layouts of the same tasks: narrow (latency first) and wide (throughput first, for blocks
+  // of at least kWideRhs columns; longer chains, four row tiles per block, separate gather and
+  // epilogue), measured best at one and at 64 columns of the 512^2 disc
+  for (int wide = 0; wide < 2; ++wide) {
+    S = wide ? &F.wide : &F.narrow;
+    record_hps = !wide;
+    kMaxChain = wide ? 288 : (F.fp32 ? 144 : 72);
+    chain_rpg = wide ? 4 : 1;
+    // ---- P2M ----
+    S->io_fold = !wide && P->opt.stencil_mfma && !P->opt.fmm_fused;
+    Group p2m_g;
     for (int c = 0; c < 4; ++c) {
       lsk::DTask tk{};
-      tk.out = F.ys.p;
-      tk.out_rhs = N;
-      tk.M = s2;
+      tk.io = S->io_fold ? lsk::IO_GATHER : 0;
+      tk.out = lvl_ptr(mult, leaf, 0);
+      tk.out_rhs = F.ml_rhs;
+      tk.M = F.kleaf;
       tk.nh = nhL;
       tk.cout = c;
-      tk.beta = 1;
-      tk.io = F.io_fold ? lsk::IO_EPILOGUE : 0;
-      set_stage(tk, S_L2P, nup > 0 ? S_DOWN(leaf - 1) : -1, S_M2L(leaf), S_NEAR, 0);
-      tk.t0 = (int)terms.size();
+      tk.beta = 0;
+      set_stage(tk, S_P2M, -1, -1, -1, 1);
+      tk.t0 = (int)p2m_g.terms.size();
       lsk::DTerm tm{};
       tm.mode = lsk::MODE_SAME;
-      tm.op = opp(F.off_Ut);
-      tm.in = lvl_ptr(loc, leaf, 0);
-      tm.in_rhs = F.ml_rhs;
-      tm.K = F.kleaf;
-      tm.coh = 1;
+      tm.op = opp(F.off_U);
+      tm.in = F.xs.p;
+      tm.in_rhs = N;
+      tm.K = s2;
       tm.nh_in = nhL;
-      terms.push_back(tm);
-      tk.t1 = (int)terms.size();
-      tasks.push_back(tk);
+      p2m_g.terms.push_back(tm);
+      tk.t1 = (int)p2m_g.terms.size();
+      p2m_g.tasks.push_back(tk);
     }
-    mk_phase(F.l2p, tasks, terms);
-    F.l2p.tag = 4;
-  }
-  // ---- L2L (parent nu -> children nu+1), top first ----
-  F.down.clear();
-  F.down.resize(leaf - p.top);
-  for (int nu = p.top; nu < leaf; ++nu) {
-    const ls::Level& l = p.lv[nu];
-    const ls::Level& cl = p.lv[nu + 1];
-    std::vector<lsk::DTask> tasks;
-    std::vector<lsk::DTerm> terms;
-    int nhc = cl.nb / 2;
-    for (int cdir = 0; cdir < cl.ndir; ++cdir) {
-      for (int c = 0; c < 4; ++c) {
-        lsk::DTask tk{};
-        tk.out = lvl_ptr(loc, nu + 1, cdir);
-        tk.out_rhs = F.ml_rhs;
-        tk.M = F.rank[nu + 1][cdir];
-        tk.nh = nhc;
-        tk.cout = c;
-        tk.beta = 1;
-        set_stage(tk, S_DOWN(nu), S_M2L(nu), S_M2L(nu + 1), nu > p.top ? S_DOWN(nu - 1) : -1, 1);
-        tk.t0 = (int)terms.size();
-        for (int dir = 0; dir < l.ndir; ++dir) {
-          int cd = cl.hf ? dir / 2 : 0;
-          if (cd != cdir) continue;
-          lsk::DTerm tm{};
-          tm.mode = lsk::MODE_PARENT;
-          tm.op = opp(F.off_Ct[nu][dir][c]);
-          tm.in = lvl_ptr(loc, nu, dir);
-          tm.in_rhs = F.ml_rhs;
-          tm.coh = 1;
-          tm.K = F.rank[nu][dir];
-          tm.nh_in = l.nb / 2;
-          if (tm.K > 0) terms.push_back(tm);
+    // ---- M2M (parent nu from children nu+1) ----
+    std::vector<Group> m2m_g(leaf + 1);
+    for (int nu = leaf - 1; nu >= p.top; --nu) {
+      Group& g = m2m_g[nu];
+      const ls::Level& l = p.lv[nu];
+      const ls::Level& cl = p.lv[nu + 1];
+      int nh = l.nb / 2;
+      for (int dir = 0; dir < l.ndir; ++dir) {
+        int cd = cl.hf ? dir / 2 : 0;
+        for (int c = 0; c < 4; ++c) {
+          lsk::DTask tk{};
+          tk.out = lvl_ptr(mult, nu, dir);
+          tk.out_rhs = F.ml_rhs;
+          tk.M = F.rank[nu][dir];
+          tk.nh = nh;
+          tk.cout = c;
+          tk.beta = 0;
+          set_stage(tk, S_UP(nu), nu == leaf - 1 ? S_P2M : S_UP(nu + 1), -1, -1, 1);
+          tk.t0 = (int)g.terms.size();
+          for (int cc = 0; cc < 4; ++cc) {
+            lsk::DTerm tm{};
+            tm.mode = lsk::MODE_CHILD;
+            tm.cin = cc;
+            tm.op = opp(F.off_C[nu][dir][cc]);
+            tm.in = lvl_ptr(mult, nu + 1, cd);
+            tm.in_rhs = F.ml_rhs;
+            tm.coh = 1;
+            tm.K = F.rank[nu + 1][cd];
+            tm.nh_in = cl.nb / 2;
+            if (tm.K > 0) g.terms.push_back(tm);
+          }
+          tk.t1 = (int)g.terms.size();
+          if (tk.M > 0) g.tasks.push_back(tk);
         }
-        tk.t1 = (int)terms.size();
-        if (tk.M > 0) tasks.push_back(tk);
       }
     }
-    mk_phase(F.down[nu - p.top], tasks, terms);
-    F.down[nu - p.top].tag = 3;
+    // ---- launches up to the middle one: U_0 = P2M, U_j = M2M of level leaf - j (j = 1..nup),
+    // U_{nup+1} = the middle launch.  Independent work is packed into the upward launches, whose
+    // own dependent chain leaves most of the chip idle: the near field (it needs only the
+    // gathered input) in kNearChunks chunks of box blocks per class, spread over U_0..U_nup, in
+    // short blocks (one row tile each, no split K); with kPackM2L also the M2L of level nu, which
+    // needs the multipoles of nu, in the launch after the one that completes them.  What is not
+    // packed forms the middle launch (M2L of the top level at least).  The chain's blocks are
+    // dispatched first, and the split-K reductions of all packed work run once, after the middle
+    // launch (nothing reads those outputs before the downward pass).  Without the matrix-core form
+    // (or in the fused launch) the near field and every M2L form the middle launch.
+    S->up.clear();
+    S->up.resize(leaf - p.top);
+    {
+      // measured on the 512^2 disc at kappa 80: packing the near field (4, 8 or 16 chunks per
+      // class, one or four row tiles per block) or also the M2L made the FP64 product 7-40% and
+      // the FP32 one 15-50% slower than one middle launch with all of it, so both are off
+      constexpr int kNearChunks = 0;
+      constexpr bool kPackM2L = false;
+      constexpr int kFillRpg = 1;
+      const bool pack = P->opt.stencil_mfma && !P->opt.fmm_fused;
+      const int nU = nup + 1;
+      struct Fill {
+        const Group* g;
+        int ci, nc, rpg;
+      };
+      std::vector<std::vector<Fill>> fill(nU + 1);
+      std::vector<double> load(nU + 1, 0.0);
+      for (int nu = p.top; nu <= leaf; ++nu) {
+        const int u = (pack && kPackM2L) ? leaf - nu + 1 : nU;
+        fill[u].push_back({&m2l_g[nu], 0, 1, 0});
+        load[u] += m2l_g[nu].work;
+      }
+      for (int c = 0; c < 4; ++c) {
+        if (pack && kNearChunks > 0) {
+          for (int k = 0; k < kNearChunks; ++k) {
+            const int u = (int)((long long)k * nU / kNearChunks);
+            fill[u].push_back({&near_g[c], k, kNearChunks, kFillRpg});
+            load[u] += near_g[c].work / kNearChunks;
+          }
+        } else {
+          fill[nU].push_back({&near_g[c], 0, 1, 0});
+          load[nU] += near_g[c].work;
+        }
+      }
+      std::vector<lsk::SplitK> acc;
+      long long acc_elems = 0;
+      for (int u = 0; u <= nU; ++u) {
+        std::vector<lsk::DTask> tasks;
+        std::vector<lsk::DTerm> terms;
+        std::vector<int> prio;
+        std::vector<std::array<int, 2>> chunk;
+        if (u == 0) append(tasks, terms, prio, chunk, p2m_g, 1);
+        if (u >= 1 && u < nU) append(tasks, terms, prio, chunk, m2m_g[leaf - u], 1);
+        for (const Fill& f : fill[u]) append(tasks, terms, prio, chunk, *f.g, 0, f.ci, f.nc, f.rpg);
+        Phase& ph = u == 0 ? S->p2m : (u < nU ? S->up[u - 1] : S->nearm2l);
+        if (P->opt.stencil_mfma)
+          make_phase_mfma(ph, tasks, terms, u == nU ? 4 : chain_rpg, prio, &acc, &acc_elems, u == nU, chunk);
+        else
+          make_phase(ph, tasks, terms);
+        ph.tag = u == 0 ? 1 : (u < nU ? 2 : 0);
+      }
+      // middle-launch work: chunk shares of a class are counted by box blocks, near enough for a
+      // rate (the classes have equal box counts up to the domain edge)
+      F.entries_mid = load[nU];
+    }
+    // ---- L2P (accumulates onto the near field) ----
+    {
+      std::vector<lsk::DTask> tasks;
+      std::vector<lsk::DTerm> terms;
+      for (int c = 0; c < 4; ++c) {
+        lsk::DTask tk{};
+        tk.out = F.ys.p;
+        tk.out_rhs = N;
+        tk.M = s2;
+        tk.nh = nhL;
+        tk.cout = c;
+        tk.beta = 1;
+        tk.io = S->io_fold ? lsk::IO_EPILOGUE : 0;
+        set_stage(tk, S_L2P, nup > 0 ? S_DOWN(leaf - 1) : -1, S_M2L(leaf), S_NEAR, 0);
+        tk.t0 = (int)terms.size();
+        lsk::DTerm tm{};
+        tm.mode = lsk::MODE_SAME;
+        tm.op = opp(F.off_Ut);
+        tm.in = lvl_ptr(loc, leaf, 0);
+        tm.in_rhs = F.ml_rhs;
+        tm.K = F.kleaf;
+        tm.coh = 1;
+        tm.nh_in = nhL;
+        terms.push_back(tm);
+        tk.t1 = (int)terms.size();
+        tasks.push_back(tk);
+      }
+      mk_phase(S->l2p, tasks, terms, chain_rpg);
+      S->l2p.tag = 4;
+    }
+    // ---- L2L (parent nu -> children nu+1), top first ----
+    S->down.clear();
+    S->down.resize(leaf - p.top);
+    for (int nu = p.top; nu < leaf; ++nu) {
+      const ls::Level& l = p.lv[nu];
+      const ls::Level& cl = p.lv[nu + 1];
+      std::vector<lsk::DTask> tasks;
+      std::vector<lsk::DTerm> terms;
+      int nhc = cl.nb / 2;
+      for (int cdir = 0; cdir < cl.ndir; ++cdir) {
+        for (int c = 0; c < 4; ++c) {
+          lsk::DTask tk{};
+          tk.out = lvl_ptr(loc, nu + 1, cdir);
+          tk.out_rhs = F.ml_rhs;
+          tk.M = F.rank[nu + 1][cdir];
+          tk.nh = nhc;
+          tk.cout = c;
+          tk.beta = 1;
+          set_stage(tk, S_DOWN(nu), S_M2L(nu), S_M2L(nu + 1), nu > p.top ? S_DOWN(nu - 1) : -1, 1);
+          tk.t0 = (int)terms.size();
+          for (int dir = 0; dir < l.ndir; ++dir) {
+            int cd = cl.hf ? dir / 2 : 0;
+            if (cd != cdir) continue;
+            lsk::DTerm tm{};
+            tm.mode = lsk::MODE_PARENT;
+            tm.op = opp(F.off_Ct[nu][dir][c]);
+            tm.in = lvl_ptr(loc, nu, dir);
+            tm.in_rhs = F.ml_rhs;
+            tm.coh = 1;
+            tm.K = F.rank[nu][dir];
+            tm.nh_in = l.nb / 2;
+            if (tm.K > 0) terms.push_back(tm);
+          }
+          tk.t1 = (int)terms.size();
+          if (tk.M > 0) tasks.push_back(tk);
+        }
+      }
+      mk_phase(S->down[nu - p.top], tasks, terms, chain_rpg);
+      S->down[nu - p.top].tag = 3;
+    }
   }
   build_fused();
 }
@@ -848,7 +866,6 @@ void run_phase(ls_problem* P, FmmDev& F, Phase& ph, int nrhs, hipStream_t s, int
   }
 }
 
-// y = alpha x + coef diag(q) (V x) in Morton (mode 0) or caller (mode 1) order.
 // y = alpha x + coef diag(q) (V x) in Morton (mode 0) or caller (mode 1) order; with_q = false:
 // y = alpha x + coef (V x).
 void fmm_apply(ls_problem* P, bool fp32, const double2* x, long long ldx, double2* y, long long ldy, int nrhs,
@@ -881,7 +898,8 @@ void fmm_apply(ls_problem* P, bool fp32, const double2* x, long long ldx, double
   const ls::Plan& p = P->plan;
   // with io_fold the gather is P2M's and the epilogue L2P's (their spans are not opened: an
   // empty span would read the cost of two event records, about 4 us)
-  const bool fold = F.io_fold && p.top <= p.leaf;
+  Passes& S = nrhs >= kWideRhs ? F.wide : F.narrow;
+  const bool fold = S.io_fold && p.top <= p.leaf;
   lsk::IoArgs io{x, ldx, y, ldy, gidx, q, alpha, coef, F.xs.p, F.ys.p};
   if (!fold) {
     SpanScope sp(P, span + 0, s);
@@ -889,17 +907,17 @@ void fmm_apply(ls_problem* P, bool fp32, const double2* x, long long ldx, double
   }
   if (p.top <= p.leaf) {
     SpanScope sp(P, span + 1, s);
-    run_phase(P, F, F.p2m, nrhs, s, -1, fold ? &io : nullptr);
-    for (auto& ph : F.up) run_phase(P, F, ph, nrhs, s);
+    run_phase(P, F, S.p2m, nrhs, s, -1, fold ? &io : nullptr);
+    for (auto& ph : S.up) run_phase(P, F, ph, nrhs, s);
   }
   {
     SpanScope sp(P, span + 2, s);
-    run_phase(P, F, F.nearm2l, nrhs, s, fp32 ? 4 : 0);
+    run_phase(P, F, S.nearm2l, nrhs, s, fp32 ? 4 : 0);
   }
   if (p.top <= p.leaf) {
     SpanScope sp(P, span + 3, s);
-    for (auto& ph : F.down) run_phase(P, F, ph, nrhs, s);
-    run_phase(P, F, F.l2p, nrhs, s, -1, fold ? &io : nullptr);
+    for (auto& ph : S.down) run_phase(P, F, ph, nrhs, s);
+    run_phase(P, F, S.l2p, nrhs, s, -1, fold ? &io : nullptr);
   }
   if (!fold) {
     SpanScope sp(P, span + 4, s);

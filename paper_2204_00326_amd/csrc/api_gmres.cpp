@@ -329,11 +329,14 @@ void kd_key_phase(std::vector<uintptr_t>& k, const Phase& ph) {
 void kd_key_fmm(std::vector<uintptr_t>& k, const FmmDev& F) {
   for (const DevBuf* b : {&F.ops, &F.mult, &F.loc, &F.xs, &F.ys}) k.push_back((uintptr_t)b->p);
   k.push_back((uintptr_t)F.nrhs_cap);
-  kd_key_phase(k, F.p2m);
-  kd_key_phase(k, F.nearm2l);
-  kd_key_phase(k, F.l2p);
-  for (const Phase& ph : F.up) kd_key_phase(k, ph);
-  for (const Phase& ph : F.down) kd_key_phase(k, ph);
+  for (const Passes* S : {&F.narrow, &F.wide}) {
+    kd_key_phase(k, S->p2m);
+    kd_key_phase(k, S->nearm2l);
+    kd_key_phase(k, S->l2p);
+    for (const Phase& ph : S->up) kd_key_phase(k, ph);
+    for (const Phase& ph : S->down) kd_key_phase(k, ph);
+    k.push_back((uintptr_t)S->io_fold);
+  }
   kd_key_phase(k, F.fused);
   for (const DevBuf* b : {&F.fneed, &F.fctr}) k.push_back((uintptr_t)b->p);
   k.push_back((uintptr_t)F.fused_wg);

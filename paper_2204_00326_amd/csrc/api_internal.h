@@ -137,6 +137,20 @@ struct Phase {
   bool mfma = false;  // matrix-core form of the stencil
 };
 
+// The passes of the product in one launch layout (task lists of P2M, M2M, the middle launch,
+// L2L, L2P).
+struct Passes {
+  Phase p2m, nearm2l, l2p;
+  std::vector<Phase> up;    // M2M, deepest parent first
+  std::vector<Phase> down;  // L2L, top parent first
+  // P2M reads the product's input through the tree-order map (and stores the tree-order copy
+  // for the near field) and L2P finishes the output: no separate gather and epilogue launches
+  bool io_fold = false;
+};
+
+// products of at least this many right-hand sides use the wide layout
+constexpr int kWideRhs = 8;
+
 struct FmmDev {
   bool fp32 = false;
   int esz = 16;  // bytes per complex element
@@ -147,9 +161,10 @@ struct FmmDev {
   std::vector<long long> lvl_size;   // elements per rhs of level nu
   long long ml_rhs = 0;              // rhs stride of mult/loc
   int nrhs_cap = 0;
-  Phase p2m, nearm2l, l2p;
-  std::vector<Phase> up;    // M2M, deepest parent first
-  std::vector<Phase> down;  // L2L, top parent first
+  // narrow: products of fewer than kWideRhs columns (short chains and blocks, P2M and L2P with the
+  // gather and epilogue folded in: latency first); wide: blocks of columns (longer chains, four
+  // row tiles per block in every pass, separate gather and epilogue: throughput first)
+  Passes narrow, wide;
   // every pass in one persistent launch (matrix-core form): all tasks and terms, the queue of
   // (task, block) pairs, stage sizes, and the counters (ticket, one per stage, error flag)
   Phase fused;
@@ -169,9 +184,6 @@ struct FmmDev {
   int64_t entries_far = 0;
   int64_t entries_m2l = 0;
   double entries_mid = 0;  // complex multiply-adds of the middle launch (one right-hand side)
-  // P2M reads the product's input through the tree-order map (and stores the tree-order copy
-  // for the near field) and L2P finishes the output: no separate gather and epilogue launches
-  bool io_fold = false;
   int64_t stored_bytes = 0;
 };
 

@@ -93,6 +93,27 @@ def test_matvec_dense_gaussian32():
     assert rel(Y32[0], A @ X[:, 0]) < 2e-5
 
 
+@pytest.mark.parametrize("n,kappa,seed", [(32, 20.0, 5), (128, 80.0, 6)])
+def test_matvec_wide_block(n, kappa, seed):
+    # blocks of 8 or more columns run the passes in their wide layout (longer chains, four row
+    # tiles per block, separate gather and epilogue): every column against the oracle, and
+    # column 0 against the same column applied alone (narrow layout)
+    pb = inputs.problem_bumps(n, kappa, seed)
+    P = problem(pb.name, n, kappa, pb.q)
+    nrhs = 9
+    X = inputs.random_vector(n * n, nrhs=nrhs, seed=seed + 200)
+    Vx = lsop.FFTApplyV(n, 1.0, kappa)
+    say(f"wide block n={n} nrhs={nrhs}")
+    Y = host(P.matvec(dev(np.ascontiguousarray(X.T))))
+    Y32 = host(P.matvec(dev(np.ascontiguousarray(X.T)), prec=ls.LS_FP32))
+    for j in range(nrhs):
+        ref = X[:, j] - kappa * kappa * pb.q * Vx(X[:, j])
+        assert rel(Y[j], ref) < 1e-8, j
+        assert rel(Y32[j], ref) < 2e-5, j
+    y0 = host(P.matvec(dev(np.ascontiguousarray(X[:, 0]))))
+    assert rel(Y[0], y0) < 1e-12
+
+
 @pytest.mark.parametrize("n,kappa,seed", [(64, 40.0, 3), (128, 80.0, 4), (256, 40.0, 0)])
 def test_matvec_fft(n, kappa, seed):
     pb = inputs.problem_bumps(n, kappa, seed, count=8 if seed == 0 else None)
