@@ -101,11 +101,12 @@ KERNELS_SRC = os.path.join(ROOT, "paper_2204_00326_amd", "csrc", "kernels.hip")
 # (the HBM-bound ones; the matrix-core stencil kernel serves every DAFMM pass under one name)
 COUNTED = {"hodlr_dot": ("lsk::k_hodlr_dot_seg<lsk::bf16, 4, 8>",),
            "hodlr_update": ("lsk::k_hodlr_update_wide<lsk::bf16>", "lsk::k_hodlr_update_list<lsk::bf16>"),
-           "hodlr_upd_dot": ("lsk::k_hodlr_upd_dot<",)}
+           "hodlr_upd_dot": ("lsk::k_hodlr_upd_dot<",),
+           "hodlr_subtree": ("lsk::k_hodlr_subtree<lsk::bf16, 512>", "lsk::k_hodlr_subtree<lsk::bf16, 256>")}
 
 
 def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok, act=1.0, listed=False, dot_rows=None,
-                       core_nodes=None, per_level=False):
+                       core_nodes=None, per_level=False, sub_level=-1, dense_leaves=0, leaf_rows=64):
     """Algorithmic HBM bytes per launch of the HODLR level kernels of one apply (one right-hand
     side), averaged over the launches of each class: a level's factor (N x r_l entries of fsz
     bytes) plus z (complex128) read, and z written by an update.  Mirrors the library's level
@@ -118,7 +119,10 @@ def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok, act=1
     the copy.  dot_rows / core_nodes (per level, from the library's
     statistics): the rows whose W^T z an unfused dot forms and the nodes whose K^-1 block is read
     (the others meet a zero Y: a child without contrast).  per_level: ({class: {level: GB}},
-    ranks) instead of the averages."""
+    ranks) instead of the averages.  sub_level >= 0: the leaf solves and the levels sub_level..levels-1
+    run in one launch per apply (class hodlr_subtree: b read, z written, the complex128 inverses
+    of the dense_leaves leaves with contrast, W and Y on the dot_rows rows of each such level,
+    the core inverses of its core_nodes); the level launches start one level above."""
     ranks = [max(1, min(rank, (N >> (l + 1)) // rank_div)) if rank_div > 0 else rank for l in range(levels)]
     def chunk(l):
         ch = N >> (l + 1)
@@ -130,8 +134,16 @@ def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok, act=1
     cls = {"hodlr_dot": {}, "hodlr_update": {}, "hodlr_upd_dot": {}}
     upd = (lambda ra: act * N * ra * fsz + 2 * act * N * 16) if listed else \
           (lambda ra: act * N * ra * fsz + (1 + act) * N * 16)
+    top = levels if sub_level < 0 else sub_level
+    if sub_level >= 0:
+        b = 2 * N * 16 + dense_leaves * leaf_rows * leaf_rows * 16
+        for l in range(sub_level, levels):
+            rows = dot_rows[l] if dot_rows else N
+            b += 2 * rows * ranks[l] * fsz
+            b += (core_nodes[l] if core_nodes else 1 << l) * ((2 * ranks[l] + 15) // 16 * 16) * 2 * ranks[l] * 16
+        cls["hodlr_subtree"] = {sub_level: b}
     pend = -1
-    for l in range(levels - 1, -1, -1):
+    for l in range(top - 1, -1, -1):
         if pend >= 0 and fused_ok and not listed and N % 1024 == 0 and (N >> pend) % 128 == 0 and chunk(l) == 1024:
             cls["hodlr_upd_dot"][l] = N * (act * ranks[pend] + ranks[l]) * fsz + (1 + act) * N * 16
         else:
@@ -147,7 +159,7 @@ def hodlr_launch_bytes(N, levels, rank, rank_div, max_rows, fsz, fused_ok, act=1
     # partials of W^T z read once, s written
     cls["hodlr_core"] = {l: (core_nodes[l] if core_nodes else 1 << l) * (2 * ranks[l]) ** 2 * 16
                          + (N // chunk(l)) * ranks[l] * 16
-                         + (1 << l) * 2 * ranks[l] * 16 for l in range(levels)}
+                         + (1 << l) * 2 * ranks[l] * 16 for l in range(top)}
     if per_level:
         return {c: {l: b / 1e9 for l, b in v.items()} for c, v in cls.items()}, ranks
     return {c: sum(v.values()) / len(v) / 1e9 for c, v in cls.items() if v}
@@ -524,8 +536,11 @@ def main():
     fsz = {"bf16": 4, "c64": 8}[pc_fmt]   # bytes per stored HODLR factor entry in mixed solves
     act = st["hodlr_rows_active"] / N
     listed = N % 256 == 0 and st["hodlr_rows_active"] * 4 < 3 * N   # the library's rule
+    sub = dict(sub_level=st["hodlr_subtree_level"], dense_leaves=st["hodlr_dense_leaves"],
+               leaf_rows=st["leaf_side"] ** 2)
     hb = hodlr_launch_bytes(N, lb, args.rank, args.rank_div, tune["hodlr_rows"] if tune else 1024, fsz,
-                            pc_fmt == "bf16", act, listed, st["hodlr_dot_rows"][:lb], st["hodlr_core_nodes"][:lb])
+                            pc_fmt == "bf16", act, listed, st["hodlr_dot_rows"][:lb], st["hodlr_core_nodes"][:lb],
+                            **sub)
     per_launch = {
         # flops of the product's middle launch (8 real flops per complex multiply-add), matrix
         # cores: the top-level M2L and the near-field classes not packed into the upward pass
@@ -565,7 +580,8 @@ def main():
                       "hodlr_dot": f"k_hodlr_dot_seg<{'bf16, 4' if args.pc_bf16 else 'float, 2'}> (HODLR W^T z)",
                       "hodlr_upd_dot": "k_hodlr_upd_dot<1024> (HODLR z -= Y s fused with the next level's W^T z)",
                       "hodlr_core": "k_hodlr_core_rows (HODLR SMW core products s = K^-1 t)",
-                      "leaf_solve": "k_leaf_apply<double> (HODLR leaf inverses)"}[dom]
+                      "leaf_solve": "k_leaf_apply<double> (HODLR leaf inverses)",
+                      "hodlr_subtree": "k_hodlr_subtree (HODLR leaf solves and deepest levels, one launch)"}[dom]
     roof["avg_launch_us"] = round(tot_ms / launches * 1e3, 2)
     roof["launches_timed"] = launches
     roof["launches"] = all_launches
@@ -577,7 +593,7 @@ def main():
     # region), averaged per (class, level), against the level's algorithmic bytes
     lvl_bytes, lvl_ranks = hodlr_launch_bytes(N, lb, args.rank, args.rank_div, tune["hodlr_rows"] if tune else 1024,
                                               fsz, pc_fmt == "bf16", act, listed, st["hodlr_dot_rows"][:lb],
-                                              st["hodlr_core_nodes"][:lb], per_level=True)
+                                              st["hodlr_core_nodes"][:lb], per_level=True, **sub)
     hcls = ("hodlr_dot", "hodlr_update", "hodlr_upd_dot", "hodlr_core")
     for c in hcls:
         P.profile_enable(c, 1)

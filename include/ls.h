@@ -172,6 +172,10 @@ typedef struct {
    * packed into the upward-pass launches (all of the near field and M2L without the
    * matrix-core form or in the fused launch) */
   int64_t entries_mid64, entries_mid32;
+  /* binary level F from which a preconditioner apply of one right-hand side (complex128 leaf
+   * and core solves) runs the leaf solves and the levels F..hodlr_levels-1 in one launch, one
+   * workgroup per level-F node (kernel timing class 20); -1: every level in its own launches */
+  int hodlr_subtree_level;
 } ls_stats_t;
 
 /* Plan description for a uniform n x n grid on [-L, L]^2 (host only, no device use).
@@ -336,7 +340,8 @@ ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt,
  * 10..14 time spans of the per-pass DAFMM product with the FP64 operator between two events
  * recorded on the stream (launch gaps included): 10 = gather into the tree order, 11 = upward
  * pass (P2M, M2M), 12 = near field + M2L, 13 = downward pass (L2L, L2P), 14 = epilogue
- * (y = alpha x + coef q V x); 15..19 the same with the FP32 operator.  every > 0
+ * (y = alpha x + coef q V x); 15..19 the same with the FP32 operator; 20 = HODLR leaf
+ * solves and deepest levels in one launch (ls_stats_t.hodlr_subtree_level).  every > 0
  * starts (and clears) the counters and times every every-th
  * launch of the class (timed dispatches run one at a time, so sparse sampling keeps the
  * timed run close to an untimed one); 0 stops.  ls_profile_read synchronises and returns the

@@ -39,7 +39,24 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
   double2* const partial = ws ? ws->partial : H.partial.as<double2>();
   double2* const svec = ws ? ws->svec : H.svec.as<double2>();
   const bool tm = ws ? ws->timers : true;
-  {
+  // one right-hand side with complex128 leaf and core solves: the leaf solves and the deepest
+  // levels (F .. Lb-1, whose nodes lie inside one level-F node) in one launch
+  const int sf = nrhs == 1 && !P->opt.pc_lowp_solves ? H.sub_rows : 0;
+  const int F = sf ? H.Lb - (sf == 512 ? 3 : 2) : H.Lb;
+  const bool sub = sf > 0 && lstop < F;
+  if (sub) {
+    lsk::SubtreeLevels lv{};
+    for (int l = F; l < H.Lb; ++l) {
+      const int i = l - F;
+      lv.W[i] = fmt == 2 ? H.W16[l].p : (fmt == 1 ? H.W32[l].p : H.W64[l].p);
+      lv.Y[i] = fmt == 2 ? H.Y16[l].p : (fmt == 1 ? H.Y32[l].p : H.Y64[l].p);
+      lv.K[i] = H.coreinv[l].as<double2>();
+      lv.r[i] = H.rank[l];
+    }
+    ProfScope ps(P, kProfSubtree, s, tm);
+    lsk::launch_hodlr_subtree(fmt, sf, H.Dinv.as<double2>(), H.ident.as<unsigned char>(), b, jdev, bldj, z, H.N,
+                              H.Lb, lv, H.nodeact.p ? H.nodeact.as<unsigned char>() : nullptr, s);
+  } else {
     ProfScope ps(P, 2, s, tm);
     // leaf inverses in complex128, or in the factors' precision on request
     const int lf = P->opt.pc_lowp_solves ? fmt : 0;
@@ -67,7 +84,7 @@ void hodlr_apply(ls_problem* P, int fmt, const double2* b, long long ldb, double
     copied = lsk::launch_hodlr_update(fmt, Y, svec, z, ldz, H.N, H.rank[a], H.N >> a, 1 << a, nrhs,
                                       s, last ? zcopy : nullptr, zldr, jdev, zldj, H.ract.as<unsigned char>());
   };
-  for (int l = H.Lb - 1; l >= lstop; --l) {
+  for (int l = (sub ? F : H.Lb) - 1; l >= lstop; --l) {
     const void* W = fmt == 2 ? H.W16[l].p : (fmt == 1 ? H.W32[l].p : H.W64[l].p);
     int nodes = 1 << l;
     const int rl = H.rank[l];
@@ -399,6 +416,7 @@ void build_hodlr(ls_problem* P, const ls::WTable& W, const std::vector<int>& mor
     if (dl.empty()) dl.push_back(0);
     H.dlist.upload(dl);
   }
+  H.sub_rows = lsk::hodlr_subtree_rows(N, H.lp, H.Lb, H.rank.data());
   // FP32 copies of the leaf inverses, the off-diagonal factors and the core inverses
   const long long nd = (long long)H.nleaves * H.lp * H.lp;
   H.Dinv32.alloc((size_t)nd * 8);

@@ -216,6 +216,8 @@ struct HodlrDev {
   std::vector<int64_t> dot_rows;  // per level: rows whose W^T z the masked apply forms
   std::vector<int> core_nodes;    // per level: nodes whose two children both hold contrast
   DevBuf partial, svec;
+  // rows per level-F node of the one-launch deep-level apply (0: every level in its own launches)
+  int sub_rows = 0;
   std::vector<long long> chunk;  // per level
   std::vector<int> nchunks, cpc;
   int64_t bytes = 0;
@@ -251,8 +253,9 @@ struct KrylovDev {
 
 // kernel classes 0..9 time one launch each; 10..19 time a span of launches of the unfused DAFMM
 // product (gather, upward pass, near field + M2L, downward pass, epilogue; FP64 then FP32)
-constexpr int kProfClasses = 20;
+constexpr int kProfClasses = 21;
 constexpr int kProfSpan = 10;
+constexpr int kProfSubtree = 20;  // the one-launch leaf solves and deepest HODLR levels
 
 struct ProfileClass {
   bool enabled = false;

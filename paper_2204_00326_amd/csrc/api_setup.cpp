@@ -331,6 +331,8 @@ ls_status ls_setup(const double* points, int64_t N, const double* q, double kapp
       S.hodlr_dot_rows[l] = l < (int)P->hod.dot_rows.size() ? P->hod.dot_rows[l] : P->N;
       S.hodlr_core_nodes[l] = l < (int)P->hod.core_nodes.size() ? P->hod.core_nodes[l] : (1 << l);
     }
+    S.hodlr_subtree_level =
+        P->have_hodlr && P->hod.sub_rows ? P->hod.Lb - (P->hod.sub_rows == 512 ? 3 : 2) : -1;
     S.t_hodlr_aca_ms = P->hod.t_aca_ms;
     S.t_hodlr_apply_ms = P->hod.t_apply_ms;
     S.t_hodlr_cores_ms = P->hod.t_cores_ms;

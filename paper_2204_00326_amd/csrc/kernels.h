@@ -212,6 +212,26 @@ bool launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, 
                          long long z2ldr = 0, const int* jdev = nullptr, long long z2ldj = 0,
                          const unsigned char* ract = nullptr);
 
+// The leaf solves and the deepest binary levels of one right-hand side in one launch: one
+// workgroup per node of level F = Lb - 3 (512 rows) or Lb - 2 (256 rows) runs the leaf solves
+// (complex128 inverses) and the levels Lb-1 .. F (fmt: factors as for launch_hodlr_dot;
+// complex128 core inverses) with that node's rows of z in LDS.  nodeact as in the level
+// launches (NULL: every node active).  b and z may be the same buffer; jdev as for
+// launch_leaf_apply.  Needs 64-row leaves, N = 64 * 2^Lb and ranks of at most 64 on those levels.
+constexpr int kSubtreeMaxLevels = 3;
+constexpr int kSubtreeRows = 512;  // rows per subtree (512: levels Lb-3..Lb-1; 256: Lb-2..Lb-1)
+struct SubtreeLevels {
+  const void* W[kSubtreeMaxLevels];     // index i: level F + i
+  const void* Y[kSubtreeMaxLevels];
+  const double2* K[kSubtreeMaxLevels];  // 16-row blocks, as for launch_hodlr_core
+  int r[kSubtreeMaxLevels];
+};
+// rows per subtree the one-launch form takes for this tree (0: not applicable)
+int hodlr_subtree_rows(long long N, int lp, int Lb, const int* ranks);
+void launch_hodlr_subtree(int fmt, int sf, const double2* Dinv, const unsigned char* ident, const double2* b,
+                          const int* jdev, long long bldj, double2* z, long long N, int Lb,
+                          const SubtreeLevels& lv, const unsigned char* nodeact, hipStream_t s);
+
 // ---- Krylov vector kernels (complex128) ----
 void launch_gs_dot(const double2* Q, long long ldq_vec, long long ldq_rhs, int nv, const double2* w, long long ldw,
                    double2* partial, long long N, int nchunks, int maxv, int nrhs, hipStream_t s);

@@ -1936,6 +1936,261 @@ void launch_hodlr_update_list(int fmt, const void* Y, const double2* sv, double2
   }
 }
 
+// =====================================================================================
+// The deep HODLR levels in one launch.  The leaf solves and the levels F..Lb-1 of the binary
+// tree read and write only the rows of their level-F ancestor, so one workgroup per level-F
+// node (SF rows, one thread per row) runs them in order with that node's rows of z in LDS:
+// the leaf solves (a wave per 64-row leaf), then per level, deepest first, W^T z for both
+// children of every node (4-row packs, butterfly sums over the lanes of one child), s = K^-1 t
+// (one 16-row block of K^-1 per wave; the masked identity for a node with one child holding
+// contrast, zero for none) and z -= Y s.  The same operations as launch_leaf_apply and the
+// per-level dot, core and update launches, with every sum in FP64 (in another order).
+// =====================================================================================
+template <typename T, int SF>
+__global__ __launch_bounds__(SF) void k_hodlr_subtree(const double2* __restrict__ Dinv,
+                                                      const unsigned char* __restrict__ ident, const double2* b,
+                                                      const int* __restrict__ jdev, long long bldj, double2* z,
+                                                      long long N, int Lb, int F, SubtreeLevels lv,
+                                                      const unsigned char* __restrict__ nodeact) {
+  using VT = typename V2<T>::type;
+  constexpr int NP = SF / 4;  // 4-row packs; SF / NP = 4 column groups
+  constexpr int PB = 32 / (int)sizeof(VT);  // 4-row packs per batch of loads: 8 bf16, 4 complex64, 2 complex128
+  constexpr int kTv = 512;    // entries of t (and s) of one level: nodes x 2r <= (SF / 128) x 128
+  __shared__ double2 zl[SF];
+  __shared__ double2 tv[kTv];
+  __shared__ double2 sv[kTv];
+  __shared__ double2 part[4][SF];
+  __shared__ int mk[SF / 128];
+  const int g = blockIdx.x, t = threadIdx.x;
+  const long long R0 = (long long)g * SF;
+  const double2* bb = jdev ? b + (long long)(*jdev) * bldj : b;
+  const double2 bv = bb[R0 + t];
+  if (nodeact && !nodeact[(1LL << F) + g]) {  // no contrast below this node: every step is the identity
+    z[R0 + t] = bv;
+    return;
+  }
+  zl[t] = bv;
+  __syncthreads();
+  {
+    const long long leaf = (R0 >> 6) + (t >> 6);
+    double2 o = bv;
+    if (!ident[leaf]) {
+      const double2* D = Dinv + leaf * 4096;
+      const int row = t & 63, base = t & ~63;
+      double re = 0, im = 0;
+#pragma unroll 16
+      for (int k = 0; k < 64; ++k) {
+        const double2 a = D[k * 64 + row];
+        const double2 x = zl[base + k];
+        re = fma(a.x, x.x, re);
+        re = fma(-a.y, x.y, re);
+        im = fma(a.x, x.y, im);
+        im = fma(a.y, x.x, im);
+      }
+      o = make_double2(re, im);
+    }
+    __syncthreads();
+    zl[t] = o;
+  }
+  const int wave = t >> 6, lane = t & 63;
+  for (int l = Lb - 1; l >= F; --l) {
+    const int li = l - F;
+    const int r = lv.r[li];
+    if (r == 0) continue;
+    const int nn = 1 << li;     // nodes of level l below this workgroup's node
+    const int Sl = SF >> li;    // rows per node
+    const int h = Sl >> 1;      // rows per child
+    const int r2 = 2 * r;
+    const long long J0 = (long long)g * nn;
+    if (t < nn) {
+      const unsigned char* c = nodeact ? nodeact + (2LL << l) + 2 * (J0 + t) : nullptr;
+      mk[t] = c ? (c[0] ? 1 : 0) | (c[1] ? 2 : 0) : 3;
+    }
+    __syncthreads();
+    const VT* W = (const VT*)lv.W[li];
+    const VT* Y = (const VT*)lv.Y[li];
+    const int p = t % NP, cg = t / NP;  // column group: uniform per wave
+    const int row = 4 * p, j = row / Sl, half = (row % Sl) >= h ? 1 : 0;
+    // t_A (entries 0..r-1) sums W^T z over the second child and feeds the first child's update,
+    // t_B (r..2r-1) the first child's rows for the second.  Loads go out in batches of PB packs
+    // (64 registers) before their first use; columns cg, cg + 4, ... < r <= 64
+    {
+      const bool need = (mk[j] & (half ? 1 : 2)) != 0;
+      const int seg = h >> 2;  // lanes of one child: 16, 32 or 64
+      const double2 x0 = zl[row], x1 = zl[row + 1], x2 = zl[row + 2], x3 = zl[row + 3];
+#pragma unroll 1
+      for (int u0 = 0; u0 < 16 && cg + 4 * u0 < r; u0 += PB) {
+        Pack<T, 4> wa[PB];
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+          const int c = cg + 4 * (u0 + u);
+          if (need && c < r) wa[u] = *reinterpret_cast<const Pack<T, 4>*>(W + (long long)c * N + R0 + row);
+        }
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+          const int c = cg + 4 * (u0 + u);
+          if (c < r) {  // uniform per wave
+            double re = 0, im = 0;
+            if (need) {
+              const double2 a0 = to_d2(wa[u].v[0]), a1 = to_d2(wa[u].v[1]), a2 = to_d2(wa[u].v[2]),
+                            a3 = to_d2(wa[u].v[3]);
+              re = fma(a0.x, x0.x, re);
+              re = fma(-a0.y, x0.y, re);
+              im = fma(a0.x, x0.y, im);
+              im = fma(a0.y, x0.x, im);
+              re = fma(a1.x, x1.x, re);
+              re = fma(-a1.y, x1.y, re);
+              im = fma(a1.x, x1.y, im);
+              im = fma(a1.y, x1.x, im);
+              re = fma(a2.x, x2.x, re);
+              re = fma(-a2.y, x2.y, re);
+              im = fma(a2.x, x2.y, im);
+              im = fma(a2.y, x2.x, im);
+              re = fma(a3.x, x3.x, re);
+              re = fma(-a3.y, x3.y, re);
+              im = fma(a3.x, x3.y, im);
+              im = fma(a3.y, x3.x, im);
+            }
+            for (int off = seg >> 1; off > 0; off >>= 1) {
+              re += __shfl_xor(re, off, 64);
+              im += __shfl_xor(im, off, 64);
+            }
+            if (need && (p & (seg - 1)) == 0) tv[j * r2 + (half ? c : r + c)] = make_double2(re, im);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // s = K^-1 t where both children hold contrast; else the half of t the child with contrast
+    // uses, zeros elsewhere (no K^-1 read)
+    for (int e = t; e < nn * r2; e += SF) {
+      const int jj = e / r2, i = e - jj * r2;
+      if (mk[jj] != 3) sv[e] = (mk[jj] & (i < r ? 1 : 2)) ? tv[e] : make_double2(0.0, 0.0);
+    }
+    {
+      const int nb = (r2 + 15) / 16;
+      const int l16 = lane & 15, jq = lane >> 4;
+      for (int pr = wave; pr < nn * nb; pr += SF / 64) {
+        const int jj = pr / nb, blk = pr - jj * nb;
+        if (mk[jj] != 3) continue;
+        const double2* Cb = lv.K[li] + ((J0 + jj) * nb + blk) * 16 * r2;
+        const double2* tj = tv + jj * r2;
+        double re = 0, im = 0;
+        // columns jq, jq + 4, ... < 2r <= 128, 16 loads in flight
+#pragma unroll 1
+        for (int u0 = 0; u0 < 32 && jq + 4 * u0 < r2; u0 += 8) {
+          double2 ka[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int k = jq + 4 * (u0 + u);
+            if (k < r2) ka[u] = Cb[k * 16 + l16];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int k = jq + 4 * (u0 + u);
+            if (k < r2) {
+              const double2 x = tj[k];
+              re = fma(ka[u].x, x.x, re);
+              re = fma(-ka[u].y, x.y, re);
+              im = fma(ka[u].x, x.y, im);
+              im = fma(ka[u].y, x.x, im);
+            }
+          }
+        }
+        re += __shfl_xor(re, 16, 64);
+        im += __shfl_xor(im, 16, 64);
+        re += __shfl_xor(re, 32, 64);
+        im += __shfl_xor(im, 32, 64);
+        const int i = blk * 16 + l16;
+        if (jq == 0 && i < r2) sv[jj * r2 + i] = make_double2(re, im);
+      }
+    }
+    __syncthreads();
+    // z -= Y s on the rows of children with contrast (Y is zero on the others)
+    {
+      double re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
+      if (mk[j] & (half ? 2 : 1)) {
+        const double2* sj = sv + j * r2 + half * r;
+  #pragma unroll 1
+      for (int u0 = 0; u0 < 16 && cg + 4 * u0 < r; u0 += PB) {
+          Pack<T, 4> ya[PB];
+#pragma unroll
+          for (int u = 0; u < PB; ++u) {
+            const int c = cg + 4 * (u0 + u);
+            if (c < r) ya[u] = *reinterpret_cast<const Pack<T, 4>*>(Y + (long long)c * N + R0 + row);
+          }
+#pragma unroll
+          for (int u = 0; u < PB; ++u) {
+            const int c = cg + 4 * (u0 + u);
+            if (c < r) {
+              const double2 x = sj[c];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const double2 yv = to_d2(ya[u].v[q]);
+                re[q] = fma(yv.x, x.x, re[q]);
+                re[q] = fma(-yv.y, x.y, re[q]);
+                im[q] = fma(yv.x, x.y, im[q]);
+                im[q] = fma(yv.y, x.x, im[q]);
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) part[cg][row + q] = make_double2(re[q], im[q]);
+    }
+    __syncthreads();
+    {
+      double2 o = zl[t];
+      o.x -= ((part[0][t].x + part[1][t].x) + part[2][t].x) + part[3][t].x;
+      o.y -= ((part[0][t].y + part[1][t].y) + part[2][t].y) + part[3][t].y;
+      zl[t] = o;
+    }
+  }
+  __syncthreads();
+  z[R0 + t] = zl[t];
+}
+
+int hodlr_subtree_rows(long long N, int lp, int Lb, const int* ranks) {
+  const int sf = kSubtreeRows, nlev = sf == 512 ? 3 : 2;
+  if (lp != 64 || Lb - nlev < 1 || N != (64LL << Lb)) return 0;
+  for (int l = Lb - nlev; l < Lb; ++l)
+    if (ranks[l] < 0 || ranks[l] > 64) return 0;
+  return sf;
+}
+
+template <typename T>
+static void subtree_launch(int sf, const double2* Dinv, const unsigned char* ident, const double2* b,
+                           const int* jdev, long long bldj, double2* z, long long N, int Lb, int F,
+                           const SubtreeLevels& lv, const unsigned char* nodeact, hipStream_t s) {
+  const unsigned grid = (unsigned)(N / sf);
+  if (sf == 512) {
+    auto kern = k_hodlr_subtree<T, 512>;
+    LSK_LAUNCH(kern, grid, 512, 0, s, Dinv, ident, b, jdev, bldj, z, N, Lb, F, lv, nodeact);
+  } else {
+    auto kern = k_hodlr_subtree<T, 256>;
+    LSK_LAUNCH(kern, grid, 256, 0, s, Dinv, ident, b, jdev, bldj, z, N, Lb, F, lv, nodeact);
+  }
+}
+
+void launch_hodlr_subtree(int fmt, int sf, const double2* Dinv, const unsigned char* ident, const double2* b,
+                          const int* jdev, long long bldj, double2* z, long long N, int Lb,
+                          const SubtreeLevels& lv, const unsigned char* nodeact, hipStream_t s) {
+  const int nlev = sf == 512 ? 3 : (sf == 256 ? 2 : 0);
+  const int F = Lb - nlev;
+  if (nlev == 0 || F < 1 || N != (64LL << Lb))
+    throw std::runtime_error("hodlr subtree: needs 64-row leaves, N = 64 * 2^Lb and 256 or 512 rows per subtree");
+  for (int i = 0; i < nlev; ++i)
+    if (lv.r[i] < 0 || lv.r[i] > 64 || (lv.r[i] > 0 && (!lv.W[i] || !lv.Y[i] || !lv.K[i])))
+      throw std::runtime_error("hodlr subtree: ranks of at most 64 with their factors");
+  if (fmt == 2)
+    subtree_launch<bf16>(sf, Dinv, ident, b, jdev, bldj, z, N, Lb, F, lv, nodeact, s);
+  else if (fmt == 1)
+    subtree_launch<float>(sf, Dinv, ident, b, jdev, bldj, z, N, Lb, F, lv, nodeact, s);
+  else
+    subtree_launch<double>(sf, Dinv, ident, b, jdev, bldj, z, N, Lb, F, lv, nodeact, s);
+}
+
 bool launch_hodlr_update(int fmt, const void* Y, const double2* sv, double2* z, long long ldz, long long N, int r,
                          long long nodesize, int nodes, int nrhs, hipStream_t s, double2* z2, long long z2ldr,
                          const int* jdev, long long z2ldj, const unsigned char* ract) {

@@ -19,7 +19,8 @@ LS_OK, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_ENOTSUP = 0, -1, -2, -3, -4
 LS_FP64, LS_FP32, LS_MIXED = 0, 1, 2
 STATUS = {0: "CONVERGED", 1: "MAXIT", 2: "BREAKDOWN", 3: "NAN", 4: "REFINE_STAGNATED", 5: "WARMSTART_REJECTED"}
 PROFILE_CLASSES = {"near_m2l64": 0, "hodlr_update": 1, "leaf_solve": 2, "gs_dot": 3, "near_m2l32": 4,
-                   "hodlr_dot": 5, "hodlr_upd_dot": 6, "hodlr_core": 7, "dafmm64": 8, "dafmm32": 9}
+                   "hodlr_dot": 5, "hodlr_upd_dot": 6, "hodlr_core": 7, "dafmm64": 8, "dafmm32": 9,
+                   "hodlr_subtree": 20}
 # spans of the per-pass DAFMM product (every launch between two stream events)
 PROFILE_SPANS = {f"mv{b}_{k}": o + i for b, o in (("64", 10), ("32", 15))
                  for i, k in enumerate(("gather", "up", "near_m2l", "down", "epilogue"))}
@@ -61,7 +62,8 @@ class _Stats(C.Structure):
                 ("hodlr_rank_used_sum", C.c_int64), ("hodlr_blocks", C.c_int64), ("hodlr_rank_used_max", C.c_int),
                 ("t_hodlr_aca_ms", C.c_double), ("t_hodlr_apply_ms", C.c_double), ("t_hodlr_cores_ms", C.c_double),
                 ("hodlr_rows_active", C.c_int64), ("hodlr_dot_rows", C.c_int64 * 32),
-                ("hodlr_core_nodes", C.c_int * 32), ("entries_mid64", C.c_int64), ("entries_mid32", C.c_int64)]
+                ("hodlr_core_nodes", C.c_int * 32), ("entries_mid64", C.c_int64), ("entries_mid32", C.c_int64),
+                ("hodlr_subtree_level", C.c_int)]
 
 
 class _PlanInfo(C.Structure):
