@@ -240,6 +240,45 @@ def measured_traffic(cls, workload):
         return None
 
 
+def panels_bench(args, torch, np, ls):
+    """High-order panels (p = 4 Chebyshev nodes per box side) on a uniform tree of args.panels^2
+    boxes of [-1, 1]^2, kappa / 2, the disc contrast at the nodes: table setup time and the dense
+    product A x (event-timed median of 20), against the FP64 vector peak (8 flops per complex
+    multiply-add of the nb^2 p^4 operator entries)."""
+    nside, p, kappa = args.panels, 4, args.kappa / 2
+    beta = 1.0 / nside
+    c = -1.0 + (2 * np.arange(nside) + 1) * beta
+    xi = np.sort(np.cos((2 * np.arange(p) + 1) * np.pi / (2 * p)))
+    X = np.array([(cx + beta * u, cy + beta * v) for cx in c for cy in c for u in xi for v in xi])
+    q = (np.hypot(X[:, 0], X[:, 1]) < 0.6).astype(float)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Pp = ls.Panels(nside, 1.0, p, kappa, q)
+    t_setup = time.perf_counter() - t0
+    x = torch.from_numpy(np.random.default_rng(1).standard_normal(Pp.N) + 0j).cuda()
+    y = torch.empty_like(x)
+    s = torch.cuda.current_stream()
+    for _ in range(3):
+        Pp.apply(x, y)
+    ts = []
+    for _ in range(20):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        Pp.apply(x, y)
+        e1.record(s)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    us = 1e3 * float(np.median(ts))
+    flops = 8.0 * (nside * nside) ** 2 * (p * p) ** 2
+    out = {"workload": f"uniform {nside}x{nside} boxes, p={p} ({Pp.N} unknowns), kappa={kappa}, disc R=0.6",
+           "setup_s": round(t_setup, 3), "apply_us": round(us, 1), "far_rule_points": Pp.nfar,
+           "roofline": {"bound": "alu", "achieved": round(flops / (us * 1e-6) / 1e12, 3), "peak": 78.6,
+                        "unit": "TFLOP/s", "frac": round(flops / (us * 1e-6) / 1e12 / 78.6, 4)}}
+    log("panels", out)
+    Pp.close()
+    return out
+
+
 def rhs_block(args, torch, np, inputs, ls):
     """Many incidence angles as one right-hand-side block: Gaussian bumps (8, seed 1) on the same
     grid and wavenumber, theta_j = 2 pi j / nrhs, one mixed solve of the block after a warmup
@@ -385,6 +424,8 @@ def main():
     ap.add_argument("--tradeoff-rank", type=int, default=128,
                     help="also time the mixed solve with this HODLR rank (setup against solve time); 0: skip")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--panels", type=int, default=32,
+                    help="also time the high-order panel operator on this many boxes per side (0: skip)")
     ap.add_argument("--block-rhs", type=int, default=64,
                     help="also solve this many plane waves on Gaussian bumps as one block (0: skip)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"),
@@ -698,6 +739,8 @@ def main():
                                  "headline_setup_s": round(t_setup, 3), "headline_ms": round(ms_step, 3)}
         log("rank tradeoff", line["rank_tradeoff"])
         P2.close()
+    if args.panels > 0:
+        line["panels"] = panels_bench(args, torch, np, ls)
     if args.block_rhs > 0:
         P.close()
         line["rhs_block"] = rhs_block(args, torch, np, inputs, ls)

@@ -413,6 +413,43 @@ ls_status ls_nop_warmstart(int n, double L, const double* q, double kappa, doubl
                            const void* f, void* psi0, void* stream);
 void ls_nop_destroy(ls_nop* N);
 
+/* ---------------------------------------------------------------------------------------
+ * High-order leaf panels (Section 2.2, Eqs. (eq:7)-(eq:13); the moment tables of Section 2.3)
+ * on a uniform tree: nside x nside leaf boxes of half-width beta = L / nside tile [-L, L]^2; box
+ * k = ix * nside + iy has centre (-L + (2 ix + 1) beta, -L + (2 iy + 1) beta) and carries the
+ * p x p tensor Chebyshev points of the first kind, ascending: node a = i * p + j sits at the
+ * centre + beta (x_i, x_j).  The density on a box is the interpolant in the N_p = p (p + 1) / 2
+ * polynomials T_a(u) T_b(v), a + b < p (ordered by total degree, then by a), through the
+ * pseudo-inverse of the interpolation matrix (Eqs. (eq:9)-(eq:10)), and the operator is
+ *     A_ij = delta_ij + sign kappa^2 q_i sum_l Qdag[l, j'] M_l(x_i, B(j)),
+ *     M_l(x, B) = int_B G(|x - y|) b_l((y - c_B) / beta) dy,   G(r) = (i/4) H0^(1)(kappa r).
+ * Unknowns: box-major, node-minor (N = nside^2 p^2).  The moments of a box at a node at least
+ * beta away from it take the tensor Gauss-Legendre rule of max(16, ceil(2 kappa beta) + 12)
+ * points per direction; nearer nodes (the box's own included) split the box into the four
+ * signed triangles with apex at the node, Duffy-mapped (48 Gauss-Legendre points along the ray)
+ * and integrated across with 48 points after a sinh map on each side of the perpendicular's
+ * foot.  On a uniform tree the moments depend only on the box offset, so the device holds one
+ * table row per offset ((2 nside - 1)^2 rows of p^2 x N_p moments, and of p^2 x p^2 operator
+ * blocks).  The product is the dense sum over all box pairs (no far-field compression).
+ * ---------------------------------------------------------------------------------------*/
+typedef struct ls_panels ls_panels;
+/* nside in 1..1024, p in 1..8, L > 0, kappa > 0, sign +1 or -1 (see ls_options.sign);
+ * q: host, N node values of the contrast (box-major, node-minor), copied.  Forms the tables
+ * on the current device (synchronous).  Errors: LS_EINVAL (bad argument, non-finite q),
+ * LS_ENOTSUP (tables above 64 GB), LS_ENOMEM / LS_EDEVICE. */
+ls_status ls_panels_setup(int nside, double L, int p, double kappa, const double* q, int sign, ls_panels** out);
+/* op 0: y = A x; op 1: y = V x (the volume potential of the density x at the nodes).  x, y:
+ * device complex128, nrhs columns of leading dimension ld >= N, not overlapping; asynchronous on
+ * stream (NULL: the default stream). */
+ls_status ls_panels_apply(ls_panels* P, const void* x, void* y, int nrhs, int64_t ld, int op, void* stream);
+/* host copy of the moment table row of box offset (dx, dy) = target box - source box,
+ * |dx|, |dy| < nside: out[(a * N_p + l) * 2 + {0, 1}] = M_l(node a of the target box, source
+ * box), real and imaginary parts.  Synchronous. */
+ls_status ls_panels_moments(const ls_panels* P, int dx, int dy, double* out);
+/* number of unknowns, N_p, and the far rule's points per direction */
+ls_status ls_panels_info(const ls_panels* P, int64_t* n_unknowns, int* np, int* nfar);
+void ls_panels_destroy(ls_panels* P);
+
 #ifdef __cplusplus
 }
 #endif

@@ -533,8 +533,13 @@ void gmres_graph(ls_problem* P, const GmresCfg& cfg, const double2* f, double2* 
         hip_check(hipGraphLaunch(kd_graph(P, cfg, use32, v, steps), s), "hipGraphLaunch");
       }
       hip_check(hipMemcpyAsync(K.host, K.ictl.p, (size_t)(1 + 3 * nrhs) * 4, hipMemcpyDeviceToHost, s), "ctl d2h");
-      hip_check(hipMemcpyAsync(est.data(), v.est, (size_t)nrhs * 8, hipMemcpyDeviceToHost, s), "est d2h");
+      // the estimates into the pinned mirror too (after the control words, 8-byte aligned): a
+      // pageable destination would make the copy a staged, blocking one
+      double* hest = reinterpret_cast<double*>(reinterpret_cast<char*>(K.host) +
+                                               ((size_t)(1 + 3 * nrhs) * 4 + 7) / 8 * 8);
+      hip_check(hipMemcpyAsync(hest, v.est, (size_t)nrhs * 8, hipMemcpyDeviceToHost, s), "est d2h");
       hip_check(hipStreamSynchronize(s), "gmres steps");
+      for (int c = 0; c < nrhs; ++c) est[c] = hest[c];
       bool active = false;
       for (int c = 0; c < nrhs; ++c) active |= K.host[1 + c] == 0;
       if (!active) break;

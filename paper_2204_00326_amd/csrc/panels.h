@@ -1,0 +1,46 @@
+// High-order leaf panels (paper, Section 2.2, Eqs. (eq:7)-(eq:13)) on a uniform tree: device
+// tables of the box moments of G against the Chebyshev basis, the blocks of the discrete volume
+// operator, and its product.
+//
+// Geometry: nside x nside leaf boxes of half-width beta tile [-L, L]^2; box k = ix * nside + iy
+// has centre (-L + (2 ix + 1) beta, -L + (2 iy + 1) beta).  Each box carries the p x p tensor
+// Chebyshev points of the first kind (ascending), node a = i * p + j at centre + beta (x_i, x_j).
+// The basis b_l(u, v) = T_a(u) T_b(v), a + b < p, is ordered by total degree, then by a
+// (N_p = p (p + 1) / 2 members).  On a uniform tree the moment of source box B at a node of
+// box A depends only on the box offset d = A - B, so one table row per offset serves every pair.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace lsp {
+
+constexpr int kMaxP = 8;                        // nodes per box side
+constexpr int kMaxNp = kMaxP * (kMaxP + 1) / 2;  // basis functions
+constexpr int kRay = 48;                        // Gauss-Legendre points along a Duffy ray
+constexpr int kAcross = 48;                     // points across a triangle, per side of the foot
+
+struct PanelGeom {
+  int nside, p, np, n2;  // n2 = p * p
+  double beta, kappa;
+  int nfar;               // Gauss-Legendre points per direction of the far rule
+};
+
+// Reference data the host computes once (Gauss-Legendre rules, Chebyshev nodes, the basis
+// exponents), uploaded as one buffer.
+struct PanelRef {
+  double node[kMaxP];               // Chebyshev points of the first kind, ascending
+  int ba[kMaxNp], bb[kMaxNp];       // basis l = T_ba(u) T_bb(v)
+  double ray_t[kRay], ray_w[kRay];  // Gauss-Legendre on [0, 1]
+  double acr_t[kAcross], acr_w[kAcross];
+};
+
+// M[d][a][l] (complex, interleaved) for every offset d = (dx + nside - 1) * (2 nside - 1) +
+// (dy + nside - 1).  far_x / far_w: the nfar-point Gauss-Legendre rule on [-1, 1].
+void launch_panel_moments(const PanelGeom& g, const PanelRef* ref, const double* far_x, const double* far_w,
+                          double2* M, hipStream_t s);
+// T[d] = M[d] Qdag (n2 x n2 per offset, row = target node, column = source node); Qdag: N_p x n2.
+void launch_panel_blocks(const PanelGeom& g, const double2* M, const double* Qdag, double2* T, hipStream_t s);
+// y = alpha x + coef diag(q) (V x) for nrhs columns (leading dimension ld); q may be NULL (= 1).
+void launch_panel_apply(const PanelGeom& g, const double2* T, const double* q, const double2* x, long long ldx,
+                        double2* y, long long ldy, int nrhs, double alpha, double coef, hipStream_t s);
+
+}  // namespace lsp

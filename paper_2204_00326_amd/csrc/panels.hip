@@ -1,0 +1,210 @@
+// High-order leaf panels on a uniform tree (paper, Section 2.2, Eqs. (eq:7)-(eq:13); the moment
+// tables of Section 2.3): device kernels.  Layouts and geometry are described in panels.h.
+#include <hip/hip_runtime.h>
+
+#include "h0.h"
+#include "panels.h"
+
+namespace lsp {
+
+static_assert(sizeof(PanelRef) % sizeof(double) == 0, "PanelRef is copied as doubles");
+
+namespace {
+
+// G(r) = (i/4) H0^(1)(kappa r)
+__device__ inline double2 green(double kappa, double r) {
+  const lsk::cplx h = lsk::hankel0(kappa * r);
+  return make_double2(-0.25 * h.im, 0.25 * h.re);
+}
+
+// T_0..T_{p-1} at x by the three-term recurrence
+__device__ inline void cheb_all(int p, double x, double* T) {
+  T[0] = 1.0;
+  if (p > 1) T[1] = x;
+  for (int n = 2; n < p; ++n) T[n] = 2.0 * x * T[n - 1] - T[n - 2];
+}
+
+// acc[l] += g * b_l(u, v)
+__device__ inline void add_basis(const PanelRef& R, int p, int np, double u, double v, double2 g, double2* acc) {
+  double Tu[kMaxP], Tv[kMaxP];
+  cheb_all(p, u, Tu);
+  cheb_all(p, v, Tv);
+#pragma unroll
+  for (int l = 0; l < kMaxNp; ++l) {
+    if (l < np) {
+      const double b = Tu[R.ba[l]] * Tv[R.bb[l]];
+      acc[l].x = fma(g.x, b, acc[l].x);
+      acc[l].y = fma(g.y, b, acc[l].y);
+    }
+  }
+}
+
+}  // namespace
+
+// One workgroup per (offset d, target node a): M[d][a][l] = int_B G(|x - y|) b_l((y - c_B) / beta) dy
+// with x the target node relative to the source box centre c_B.  Targets at least beta away from
+// the box take the tensor Gauss-Legendre rule (nfar points per direction); nearer ones split the
+// box into the four signed triangles with apex at the target, each mapped to the unit square with
+// y = x + s (a + t (b - a) - x), s = u^2 (the Jacobian s ds = 2 u^3 du removes the logarithmic
+// singularity at the apex), Gauss-Legendre in u and, across the triangle, Gauss-Legendre after
+// t = t0 + mu sinh(tau) on each side of the foot t0 of the perpendicular from the apex (mu: the
+// apex's distance to the edge line over the edge length), which spreads the peak of the integrand
+// at the foot (the sinh transformation for nearly singular integrals, Johnston and Elliott 2005).
+__global__ __launch_bounds__(256) void k_panel_moments(PanelGeom g, const PanelRef* __restrict__ ref,
+                                                       const double* __restrict__ far_x,
+                                                       const double* __restrict__ far_w, double2* __restrict__ M) {
+  __shared__ PanelRef R;
+  __shared__ double2 red[4][kMaxNp];
+  const int d = blockIdx.x, a = blockIdx.y, t = threadIdx.x;
+  for (int i = t; i < (int)(sizeof(PanelRef) / sizeof(double)); i += 256)
+    reinterpret_cast<double*>(&R)[i] = reinterpret_cast<const double*>(ref)[i];
+  __syncthreads();
+  const int w2 = 2 * g.nside - 1;
+  const int dx = d / w2 - (g.nside - 1), dy = d % w2 - (g.nside - 1);
+  const double be = g.beta;
+  const double tx = 2.0 * be * dx + be * R.node[a / g.p], ty = 2.0 * be * dy + be * R.node[a % g.p];
+  const double ox = fmax(fabs(tx) - be, 0.0), oy = fmax(fabs(ty) - be, 0.0);
+  const bool far = sqrt(ox * ox + oy * oy) >= be;
+  double2 acc[kMaxNp];
+#pragma unroll
+  for (int l = 0; l < kMaxNp; ++l) acc[l] = make_double2(0.0, 0.0);
+  if (far) {
+    const int nq = g.nfar * g.nfar;
+    for (int q = t; q < nq; q += 256) {
+      const double u = far_x[q / g.nfar], v = far_x[q % g.nfar];
+      const double w = far_w[q / g.nfar] * far_w[q % g.nfar] * be * be;
+      const double rx = tx - be * u, ry = ty - be * v;
+      const double2 G = green(g.kappa, sqrt(rx * rx + ry * ry));
+      add_basis(R, g.p, g.np, u, v, make_double2(G.x * w, G.y * w), acc);
+    }
+  } else {
+    // items: (triangle k, side of the foot, point across)
+    for (int it = t; it < 4 * 2 * kAcross; it += 256) {
+      const int k = it / (2 * kAcross), side = (it / kAcross) & 1, ia = it % kAcross;
+      const double cxk[4] = {-be, be, be, -be}, cyk[4] = {-be, -be, be, be};
+      const double ax = cxk[k], ay = cyk[k], bx = cxk[(k + 1) & 3], by = cyk[(k + 1) & 3];
+      const double ex = bx - ax, ey = by - ay;
+      const double J = (ax - tx) * ey - (ay - ty) * ex;
+      if (fabs(J) <= 1e-15 * be * be) continue;
+      const double dd = ex * ex + ey * ey;
+      const double t0 = ((tx - ax) * ex + (ty - ay) * ey) / dd;
+      const double mu = fabs(J) / dd;
+      // the two sides of the foot inside [0, 1] (one empty when the foot lies outside)
+      const double f = fmin(fmax(t0, 0.0), 1.0);
+      const double lo = side ? f : 0.0, hi = side ? 1.0 : f;
+      if (hi <= lo) continue;
+      const double tl = asinh((lo - t0) / mu), th = asinh((hi - t0) / mu);
+      const double tau = tl + (th - tl) * R.acr_t[ia];
+      const double tt = t0 + mu * sinh(tau);
+      const double wt = (th - tl) * R.acr_w[ia] * mu * cosh(tau) * J;
+      const double px = ax + tt * ex - tx, py = ay + tt * ey - ty;
+      const double rho = sqrt(px * px + py * py);
+      for (int iu = 0; iu < kRay; ++iu) {
+        const double u = R.ray_t[iu], s = u * u, ws = 2.0 * u * u * u * R.ray_w[iu] * wt;
+        const double2 G = green(g.kappa, s * rho);
+        add_basis(R, g.p, g.np, (tx + s * px) / be, (ty + s * py) / be, make_double2(G.x * ws, G.y * ws), acc);
+      }
+    }
+  }
+  // workgroup sum in a fixed order: butterfly within each wave, then the four waves
+  const int wave = t >> 6, lane = t & 63;
+#pragma unroll
+  for (int l = 0; l < kMaxNp; ++l) {
+    if (l < g.np) {
+      double re = acc[l].x, im = acc[l].y;
+      for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_xor(re, off, 64);
+        im += __shfl_xor(im, off, 64);
+      }
+      if (lane == 0) red[wave][l] = make_double2(re, im);
+    }
+  }
+  __syncthreads();
+  if (t < g.np) {
+    double2 o = red[0][t];
+    for (int w = 1; w < 4; ++w) {
+      o.x += red[w][t].x;
+      o.y += red[w][t].y;
+    }
+    M[((long long)d * g.n2 + a) * g.np + t] = o;
+  }
+}
+
+// T[d][a][b] = sum_l M[d][a][l] Qdag[l][b]
+__global__ __launch_bounds__(256) void k_panel_blocks(PanelGeom g, const double2* __restrict__ M,
+                                                      const double* __restrict__ Qdag, double2* __restrict__ T) {
+  const long long d = blockIdx.x;
+  for (int e = threadIdx.x; e < g.n2 * g.n2; e += 256) {
+    const int a = e / g.n2, b = e % g.n2;
+    const double2* m = M + (d * g.n2 + a) * g.np;
+    double re = 0, im = 0;
+    for (int l = 0; l < g.np; ++l) {
+      const double q = Qdag[l * g.n2 + b];
+      re = fma(m[l].x, q, re);
+      im = fma(m[l].y, q, im);
+    }
+    T[(d * g.n2 + a) * g.n2 + b] = make_double2(re, im);
+  }
+}
+
+// One workgroup per (target box A, right-hand side): thread (a, part) sums the source boxes
+// B = part, part + S, ... (S = 256 / n2 parts) over the source nodes b of T[A - B][a][b] x_B[b];
+// the parts are added in a fixed order, then y = alpha x + coef q (V x).
+__global__ __launch_bounds__(256) void k_panel_apply(PanelGeom g, const double2* __restrict__ T,
+                                                     const double* __restrict__ q, const double2* __restrict__ x,
+                                                     long long ldx, double2* __restrict__ y, long long ldy,
+                                                     double alpha, double coef) {
+  __shared__ double2 part[256];
+  const int A = blockIdx.x, rhs = blockIdx.y, t = threadIdx.x;
+  const int n2 = g.n2, S = 256 / n2, nb = g.nside * g.nside, w2 = 2 * g.nside - 1;
+  const int a = t % n2, sp = t / n2;
+  const int ax = A / g.nside, ay = A % g.nside;
+  const double2* xr = x + rhs * ldx;
+  double re = 0, im = 0;
+  if (sp < S) {
+    for (int B = sp; B < nb; B += S) {
+      const int dx = ax - B / g.nside, dy = ay - B % g.nside;
+      const long long d = (long long)(dx + g.nside - 1) * w2 + (dy + g.nside - 1);
+      const double2* Tr = T + (d * n2 + a) * n2;
+      const double2* xb = xr + (long long)B * n2;
+      for (int b = 0; b < n2; ++b) {
+        const double2 m = Tr[b], v = xb[b];
+        re = fma(m.x, v.x, re);
+        re = fma(-m.y, v.y, re);
+        im = fma(m.x, v.y, im);
+        im = fma(m.y, v.x, im);
+      }
+    }
+  }
+  part[t] = make_double2(re, im);
+  __syncthreads();
+  if (t < n2) {
+    for (int k = 1; k < S; ++k) {
+      re += part[k * n2 + t].x;
+      im += part[k * n2 + t].y;
+    }
+    const long long i = (long long)A * n2 + t;
+    const double2 xi = xr[i];
+    const double c = q ? coef * q[i] : coef;
+    y[rhs * ldy + i] = make_double2(alpha * xi.x + c * re, alpha * xi.y + c * im);
+  }
+}
+
+void launch_panel_moments(const PanelGeom& g, const PanelRef* ref, const double* far_x, const double* far_w,
+                          double2* M, hipStream_t s) {
+  const int w2 = 2 * g.nside - 1;
+  k_panel_moments<<<dim3((unsigned)(w2 * w2), (unsigned)g.n2), 256, 0, s>>>(g, ref, far_x, far_w, M);
+}
+
+void launch_panel_blocks(const PanelGeom& g, const double2* M, const double* Qdag, double2* T, hipStream_t s) {
+  const int w2 = 2 * g.nside - 1;
+  k_panel_blocks<<<(unsigned)(w2 * w2), 256, 0, s>>>(g, M, Qdag, T);
+}
+
+void launch_panel_apply(const PanelGeom& g, const double2* T, const double* q, const double2* x, long long ldx,
+                        double2* y, long long ldy, int nrhs, double alpha, double coef, hipStream_t s) {
+  k_panel_apply<<<dim3((unsigned)(g.nside * g.nside), (unsigned)nrhs), 256, 0, s>>>(g, T, q, x, ldx, y, ldy, alpha,
+                                                                                    coef);
+}
+
+}  // namespace lsp

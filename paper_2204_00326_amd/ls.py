@@ -131,6 +131,14 @@ def lib():
     for name in ("ls_nop_create", "ls_nop_forward", "ls_nop_backward", "ls_nop_loss", "ls_nop_adam_step",
                  "ls_nop_features", "ls_nop_warmstart"):
         getattr(L, name).restype = C.c_int
+    L.ls_panels_setup.argtypes = [ci, cd, ci, cd, vp, ci, C.POINTER(vp)]
+    L.ls_panels_apply.argtypes = [vp, vp, vp, ci, i64, ci, vp]
+    L.ls_panels_moments.argtypes = [vp, ci, ci, vp]
+    L.ls_panels_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.ls_panels_destroy.argtypes = [vp]
+    L.ls_panels_destroy.restype = None
+    for name in ("ls_panels_setup", "ls_panels_apply", "ls_panels_moments", "ls_panels_info"):
+        getattr(L, name).restype = C.c_int
     for name in ("ls_setup", "ls_matvec", "ls_apply_V", "ls_precond_apply", "ls_precond_apply_noalloc",
                  "ls_rhs_planewave", "ls_solve",
                  "ls_stats", "ls_plan_describe", "ls_profile_enable", "ls_profile_read", "ls_profile_read_each",
@@ -489,3 +497,44 @@ def solve_queue(problems, fs, tol: float = 1e-8, prec: int = -1, nworkers: int =
     _check(lib().ls_solve_queue(hs, n, fp, pp, float(tol), int(prec), int(nworkers), int(graph_iters), infos))
     return psis, [_info_dict(i) for i in infos]
 
+
+class Panels:
+    """Handle of an ls_panels_setup()-built high-order panel operator on a uniform tree (nside x
+    nside boxes of [-L, L]^2, p x p Chebyshev nodes per box; unknowns box-major, node-minor)."""
+
+    def __init__(self, nside: int, L: float, p: int, kappa: float, q: np.ndarray, sign: int = -1):
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        if q.shape != (nside * nside * p * p,):
+            raise ValueError("q must hold one value per node")
+        self._h = C.c_void_p()
+        _check(lib().ls_panels_setup(int(nside), float(L), int(p), float(kappa), q.ctypes.data, int(sign),
+                                     C.byref(self._h)))
+        n, npb, nf = C.c_int64(), C.c_int(), C.c_int()
+        _check(lib().ls_panels_info(self._h, C.byref(n), C.byref(npb), C.byref(nf)))
+        self.N, self.np, self.nfar = n.value, npb.value, nf.value
+        self.nside, self.p = nside, p
+
+    def apply(self, x, y=None, op: int = 0, stream=None):
+        """op 0: y = A x; op 1: y = V x (complex128 CUDA tensors, shape (N,) or (nrhs, N))"""
+        import torch
+        nrhs = _vec(x, self.N)
+        y = torch.empty_like(x) if y is None else y
+        _check(lib().ls_panels_apply(self._h, x.data_ptr(), y.data_ptr(), nrhs, self.N, int(op), _stream(stream)))
+        return y
+
+    def moments(self, dx: int, dy: int) -> np.ndarray:
+        """M_l(node a of the target box, source box) for box offset (dx, dy): array (p^2, N_p)"""
+        out = np.empty((self.p * self.p, self.np), dtype=np.complex128)
+        _check(lib().ls_panels_moments(self._h, int(dx), int(dy), out.ctypes.data))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().ls_panels_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

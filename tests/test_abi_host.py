@@ -154,3 +154,25 @@ def test_profile_readers_reject_bad_arguments():
     assert L.ls_profile_read_each(None, 5, None, None, 0, C.byref(n)) == ls.LS_EINVAL
     assert L.ls_profile_read(None, 0, C.byref(ms), C.byref(n), None) == ls.LS_EINVAL
     assert L.ls_profile_enable(None, 0, 1) == ls.LS_EINVAL
+
+
+def test_panels_reject_invalid_inputs():
+    # argument checks of the high-order panel calls run before any device use
+    L = ls.lib()
+    h = C.c_void_p()
+    q = np.zeros(16 * 9)
+    for args in ((0, 1.0, 3, 10.0, 1), (4, 1.0, 0, 10.0, -1), (4, 1.0, 9, 10.0, -1), (4, -1.0, 3, 10.0, -1),
+                 (4, 1.0, 3, 0.0, -1), (4, 1.0, 3, 10.0, 0), (2000, 1.0, 3, 10.0, -1)):
+        nside, Lh, p, kappa, sign = args
+        assert L.ls_panels_setup(nside, Lh, p, kappa, q.ctypes.data, sign, C.byref(h)) == ls.LS_EINVAL, args
+        assert not h
+    assert L.ls_panels_setup(4, 1.0, 3, 10.0, None, -1, C.byref(h)) == ls.LS_EINVAL
+    bad = q.copy()
+    bad[5] = np.nan
+    assert L.ls_panels_setup(4, 1.0, 3, 10.0, bad.ctypes.data, -1, C.byref(h)) == ls.LS_EINVAL
+    assert L.ls_panels_setup(4, 1.0, 3, 10.0, q.ctypes.data, -1, None) == ls.LS_EINVAL
+    x = np.zeros(4)
+    assert L.ls_panels_apply(None, x.ctypes.data, x.ctypes.data, 1, 144, 0, None) == ls.LS_EINVAL
+    assert L.ls_panels_moments(None, 0, 0, x.ctypes.data) == ls.LS_EINVAL
+    n, npb, nf = C.c_int64(), C.c_int(), C.c_int()
+    assert L.ls_panels_info(None, C.byref(n), C.byref(npb), C.byref(nf)) == ls.LS_EINVAL

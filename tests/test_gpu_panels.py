@@ -1,0 +1,115 @@
+"""High-order leaf panels on the device (ls_panels_*, Section 2.2, Eqs. (eq:7)-(eq:13)) against the
+panel oracle (oracle/panels.py): the moment tables row by row (far Gauss-Legendre rule, near
+Duffy-mapped triangles, the box's own nodes included) and the dense operator A and volume
+potential V element by element, on uniform trees at several p (p = 1: one node per box, the
+cell-centred rule with the exact self-cell integral), both signs, one box and a block of
+right-hand sides."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import panels, special
+from paper_2204_00326_amd import ls
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def qfun(x, y):
+    return 1.5 * np.exp(-8.0 * (x * x + (y - 0.1) ** 2))
+
+
+def node_q(boxes, p):
+    X = panels.all_nodes(boxes, p)
+    return qfun(X[:, 0], X[:, 1])
+
+
+@pytest.mark.parametrize("nside,p,kappa", [(4, 3, 10.0), (3, 4, 25.0), (2, 6, 8.0)])
+def test_moment_rows_match_oracle(nside, p, kappa):
+    L = 1.0
+    boxes = panels.uniform_tree(nside, L)
+    say(f"panels moments nside={nside} p={p} kappa={kappa}")
+    P = ls.Panels(nside, L, p, kappa, node_q(boxes, p))
+    assert P.np == p * (p + 1) // 2
+    src = boxes[0]                 # box (0, 0); the target box (dx, dy) sits at index dx * nside + dy
+    offsets = {(0, 0), (1, 0), (0, 1), (1, 1)}
+    if nside > 2:
+        offsets |= {(2, 1), (nside - 1, nside - 1)}
+    for dx, dy in sorted(offsets):
+        tgt = boxes[dx * nside + dy]
+        ref = panels.moments(tgt.nodes(p), src, p, kappa)
+        got = P.moments(dx, dy)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        say((dx, dy), err)
+        assert err < 1e-10, (dx, dy, err)
+        # the table is shared by every pair at that offset (the reversed offset: the source box
+        # to the left of the target instead of the right)
+        ref2 = panels.moments(boxes[0].nodes(p), boxes[dx * nside + dy], p, kappa)
+        got2 = P.moments(-dx, -dy)
+        assert np.abs(got2 - ref2).max() < 1e-10 * np.abs(ref2).max()
+    P.close()
+
+
+def test_single_node_box_is_the_cell_rule():
+    # p = 1: one node at the box centre, N_p = 1 and Qdag = [1]; the own-box moment is the exact
+    # integral of G over the cell (closed form) and far boxes take the Gauss-Legendre rule
+    nside, kappa = 8, 12.0
+    P = ls.Panels(nside, 1.0, 1, kappa, np.ones(nside * nside))
+    w0 = special.self_cell(2.0 / nside, kappa)
+    m = P.moments(0, 0)[0, 0]
+    assert abs(m - w0) < 1e-11 * abs(w0)
+    P.close()
+
+
+@pytest.mark.parametrize("nside,p,kappa,sign", [(4, 3, 10.0, -1), (3, 4, 25.0, 1), (1, 5, 6.0, -1)])
+def test_operator_matches_dense_oracle(nside, p, kappa, sign):
+    L = 1.0
+    boxes = panels.uniform_tree(nside, L)
+    q = node_q(boxes, p)
+    say(f"panels operator nside={nside} p={p} kappa={kappa} sign={sign}")
+    A = panels.dense_A(boxes, p, kappa, qfun, sign=sign)
+    V = panels.dense_V(boxes, p, kappa)
+    P = ls.Panels(nside, L, p, kappa, q, sign=sign)
+    N = P.N
+    assert N == len(boxes) * p * p == A.shape[0]
+    rng = np.random.default_rng(nside * 100 + p)
+    X = rng.standard_normal((3, N)) + 1j * rng.standard_normal((3, N))
+    Xd = torch.from_numpy(X).cuda()
+    Y = P.apply(Xd, op=0).cpu().numpy()
+    U = P.apply(Xd, op=1).cpu().numpy()
+    for j in range(3):
+        ref = A @ X[j]
+        refv = V @ X[j]
+        ea = np.linalg.norm(Y[j] - ref) / np.linalg.norm(ref)
+        ev = np.linalg.norm(U[j] - refv) / np.linalg.norm(refv)
+        say(j, ea, ev)
+        assert ea < 1e-10 and ev < 1e-10
+    # a single column equals the same column of the block
+    y0 = P.apply(Xd[0].contiguous(), op=0).cpu().numpy()
+    assert np.abs(y0 - Y[0]).max() <= 1e-14 * np.abs(Y[0]).max()
+    P.close()
+
+
+def test_apply_on_a_polynomial_density_integrates_it():
+    # V of a density that is a polynomial of total degree < p on every box integrates that
+    # polynomial exactly (the interpolant reproduces it): compare against the moments summed
+    # with the polynomial's basis coefficients
+    nside, p, kappa = 2, 4, 9.0
+    boxes = panels.uniform_tree(nside)
+    P = ls.Panels(nside, 1.0, p, kappa, np.ones(nside * nside * p * p))
+    X = panels.all_nodes(boxes, p)
+    c = np.zeros(P.np)
+    c[0], c[2], c[4] = 1.0, -0.5, 0.25     # T0, T0(u) T1(v), T1(u) T1(v)
+    dens = np.concatenate([panels.basis_values(p, (b.nodes(p)[:, 0] - b.cx) / b.beta,
+                                               (b.nodes(p)[:, 1] - b.cy) / b.beta) @ c for b in boxes])
+    u = P.apply(torch.from_numpy(dens.astype(np.complex128)).cuda(), op=1).cpu().numpy()
+    ref = sum(panels.moments(X, b, p, kappa) @ c for b in boxes)
+    assert np.linalg.norm(u - ref) < 1e-10 * np.linalg.norm(ref)
+    P.close()
