@@ -243,8 +243,8 @@ def measured_traffic(cls, workload):
 def panels_bench(args, torch, np, ls):
     """High-order panels (p = 4 Chebyshev nodes per box side) on a uniform tree of args.panels^2
     boxes of [-1, 1]^2, kappa / 2, the disc contrast at the nodes: table setup time and the dense
-    product A x (event-timed median of 20), against the FP64 vector peak (8 flops per complex
-    multiply-add of the nb^2 p^4 operator entries)."""
+    product A x (event-timed median of 20; FP64 matrix cores), against the FP64 MFMA peak (8
+    flops per complex multiply-add of the nb^2 p^4 operator entries)."""
     nside, p, kappa = args.panels, 4, args.kappa / 2
     beta = 1.0 / nside
     c = -1.0 + (2 * np.arange(nside) + 1) * beta
@@ -272,7 +272,7 @@ def panels_bench(args, torch, np, ls):
     flops = 8.0 * (nside * nside) ** 2 * (p * p) ** 2
     out = {"workload": f"uniform {nside}x{nside} boxes, p={p} ({Pp.N} unknowns), kappa={kappa}, disc R=0.6",
            "setup_s": round(t_setup, 3), "apply_us": round(us, 1), "far_rule_points": Pp.nfar,
-           "roofline": {"bound": "alu", "achieved": round(flops / (us * 1e-6) / 1e12, 3), "peak": 78.6,
+           "roofline": {"bound": "mfma", "achieved": round(flops / (us * 1e-6) / 1e12, 3), "peak": 78.6,
                         "unit": "TFLOP/s", "frac": round(flops / (us * 1e-6) / 1e12 / 78.6, 4)}}
     log("panels", out)
     Pp.close()

@@ -43,4 +43,12 @@ void launch_panel_blocks(const PanelGeom& g, const double2* M, const double* Qda
 void launch_panel_apply(const PanelGeom& g, const double2* T, const double* q, const double2* x, long long ldx,
                         double2* y, long long ldy, int nrhs, double alpha, double coef, hipStream_t s);
 
+// The same product on the matrix cores (FP64 MFMA, p <= kMfmaMaxP): partial planes of nchunks
+// chunks of the offsets (part: nchunks x nrhs x N complex), then their sum in chunk order.
+constexpr int kMfmaMaxP = 5;
+int panel_chunks(const PanelGeom& g, int nrhs);
+void launch_panel_apply_mfma(const PanelGeom& g, const double2* T, const double* q, const double2* x, long long ldx,
+                             double2* y, long long ldy, int nrhs, double alpha, double coef, double2* part,
+                             int nchunks, hipStream_t s);
+
 }  // namespace lsp

@@ -2,6 +2,8 @@
 // tables of Section 2.3): device kernels.  Layouts and geometry are described in panels.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "h0.h"
 #include "panels.h"
 
@@ -187,6 +189,159 @@ __global__ __launch_bounds__(256) void k_panel_apply(PanelGeom g, const double2*
     const double2 xi = xr[i];
     const double c = q ? coef * q[i] : coef;
     y[rhs * ldy + i] = make_double2(alpha * xi.x + c * re, alpha * xi.y + c * im);
+  }
+}
+
+// The same product on the matrix cores: for a tile of 16 target boxes and an offset d, the
+// sources are the tile shifted by d (boxes outside the grid masked), and the products of that
+// offset are one (n2 x n2) by (n2 x 16 boxes) complex GEMM, RT 16-row tiles by KB 4-deep k-blocks
+// of 16 x 16 x 4 FP64 MFMAs (four real ones per complex product; rows and k past n2 padded with
+// zeros).  A workgroup takes one tile and a chunk of the offsets, its 4 waves every 4th offset
+// of the chunk, with the next offset's operands loaded before the current products; the waves'
+// sums are added through LDS in a fixed order into the chunk's partial plane, and
+// k_panel_reduce adds the chunks in order.  Lane l: T element (row l % 16, k l / 16), x element
+// (k l / 16, box l % 16); accumulator element v: row l / 16 + 4 v, box l % 16.
+typedef double pf64x4 __attribute__((ext_vector_type(4)));
+
+template <int RT, int KB>
+__global__ __launch_bounds__(256) void k_panel_apply_mfma(PanelGeom g, const double2* __restrict__ T,
+                                                          const double2* __restrict__ x, long long ldx,
+                                                          double2* __restrict__ part, int nchunks, long long N) {
+  __shared__ double2 red[4][RT][4][64];
+  const int tile = blockIdx.x, chunk = blockIdx.y, rhs = blockIdx.z;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n2 = g.n2, nside = g.nside, nb = nside * nside, w2 = 2 * nside - 1;
+  const int noff = w2 * w2;
+  const int d0 = (int)((long long)noff * chunk / nchunks), d1 = (int)((long long)noff * (chunk + 1) / nchunks);
+  const int j = lane & 15, kq = lane >> 4;
+  const int A = tile * 16 + j;
+  const bool aok = A < nb;
+  const int ax = aok ? A / nside : 0, ay = aok ? A % nside : 0;
+  const double2* xr = x + rhs * ldx;
+  pf64x4 accr[RT], acci[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    accr[rt] = pf64x4{0, 0, 0, 0};
+    acci[rt] = pf64x4{0, 0, 0, 0};
+  }
+  // operands of offset d: T fragments (row rt * 16 + j, k kb * 4 + kq) and x fragments
+  // (k kb * 4 + kq, box j shifted by d)
+  auto load = [&](int d, double2 (&ta)[RT][KB], double2 (&xa)[KB]) -> bool {
+    const int dx = d / w2 - (nside - 1), dy = d % w2 - (nside - 1);
+    const int bx = ax - dx, by = ay - dy;
+    const bool ok = aok && bx >= 0 && bx < nside && by >= 0 && by < nside;
+    const long long B = ok ? (long long)bx * nside + by : 0;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int b = kb * 4 + kq;
+      xa[kb] = ok && b < n2 ? xr[B * n2 + b] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const int a = rt * 16 + j;
+        ta[rt][kb] = a < n2 && b < n2 ? T[((long long)d * n2 + a) * n2 + b] : make_double2(0.0, 0.0);
+      }
+    }
+    return __any(ok);
+  };
+  double2 ta[RT][KB], xa[KB], tb[RT][KB], xb[KB];
+  int d = d0 + wave;
+  bool live = d < d1 ? load(d, ta, xa) : false;
+  while (d < d1) {
+    const int dn = d + 4;
+    const bool nlive = dn < d1 ? load(dn, tb, xb) : false;
+    if (live) {
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+          accr[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[rt][kb].x, xa[kb].x, accr[rt], 0, 0, 0);
+          accr[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ta[rt][kb].y, xa[kb].y, accr[rt], 0, 0, 0);
+          acci[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[rt][kb].x, xa[kb].y, acci[rt], 0, 0, 0);
+          acci[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[rt][kb].y, xa[kb].x, acci[rt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      xa[kb] = xb[kb];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) ta[rt][kb] = tb[rt][kb];
+    }
+    live = nlive;
+    d = dn;
+  }
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave][rt][v][lane] = make_double2(accr[rt][v], acci[rt][v]);
+  __syncthreads();
+  if (wave == 0 && aok) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = rt * 16 + kq + 4 * v;
+        if (a >= n2) continue;
+        double2 o = red[0][rt][v][lane];
+        for (int w = 1; w < 4; ++w) {
+          o.x += red[w][rt][v][lane].x;
+          o.y += red[w][rt][v][lane].y;
+        }
+        part[((long long)chunk * gridDim.z + rhs) * N + (long long)A * n2 + a] = o;
+      }
+  }
+}
+
+// y = alpha x + coef q (sum over the chunks of the partial planes, in chunk order)
+__global__ __launch_bounds__(256) void k_panel_reduce(const double2* __restrict__ part, int nchunks, int nrhs,
+                                                      long long N, const double* __restrict__ q,
+                                                      const double2* __restrict__ x, long long ldx,
+                                                      double2* __restrict__ y, long long ldy, double alpha,
+                                                      double coef) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (i >= N) return;
+  double re = 0, im = 0;
+  for (int c = 0; c < nchunks; ++c) {
+    const double2 v = part[((long long)c * nrhs + rhs) * N + i];
+    re += v.x;
+    im += v.y;
+  }
+  const double2 xi = x[rhs * ldx + i];
+  const double cf = q ? coef * q[i] : coef;
+  y[rhs * ldy + i] = make_double2(alpha * xi.x + cf * re, alpha * xi.y + cf * im);
+}
+
+int panel_chunks(const PanelGeom& g, int nrhs) {
+  const int nb = g.nside * g.nside, ntiles = (nb + 15) / 16, w2 = 2 * g.nside - 1;
+  const long long N = (long long)nb * g.n2;
+  int c = std::max(1, std::min(w2 * w2 / 4, (2048 + ntiles - 1) / ntiles));
+  // partial planes of at most 512 MB
+  while (c > 1 && (long long)c * nrhs * N * 16 > (512LL << 20)) c /= 2;
+  return c;
+}
+
+template <int RT, int KB>
+static void apply_mfma(const PanelGeom& g, const double2* T, const double* q, const double2* x, long long ldx,
+                       double2* y, long long ldy, int nrhs, double alpha, double coef, double2* part, int nchunks,
+                       hipStream_t s) {
+  const int nb = g.nside * g.nside;
+  const long long N = (long long)nb * g.n2;
+  k_panel_apply_mfma<RT, KB><<<dim3((unsigned)((nb + 15) / 16), (unsigned)nchunks, (unsigned)nrhs), 256, 0, s>>>(
+      g, T, x, ldx, part, nchunks, N);
+  k_panel_reduce<<<dim3((unsigned)((N + 255) / 256), (unsigned)nrhs), 256, 0, s>>>(part, nchunks, nrhs, N, q, x, ldx,
+                                                                                 y, ldy, alpha, coef);
+}
+
+void launch_panel_apply_mfma(const PanelGeom& g, const double2* T, const double* q, const double2* x, long long ldx,
+                             double2* y, long long ldy, int nrhs, double alpha, double coef, double2* part,
+                             int nchunks, hipStream_t s) {
+  switch (g.p) {
+    case 1: apply_mfma<1, 1>(g, T, q, x, ldx, y, ldy, nrhs, alpha, coef, part, nchunks, s); break;
+    case 2: apply_mfma<1, 1>(g, T, q, x, ldx, y, ldy, nrhs, alpha, coef, part, nchunks, s); break;
+    case 3: apply_mfma<1, 3>(g, T, q, x, ldx, y, ldy, nrhs, alpha, coef, part, nchunks, s); break;
+    case 4: apply_mfma<1, 4>(g, T, q, x, ldx, y, ldy, nrhs, alpha, coef, part, nchunks, s); break;
+    case 5: apply_mfma<2, 7>(g, T, q, x, ldx, y, ldy, nrhs, alpha, coef, part, nchunks, s); break;
+    default: break;  // p > 5: the double-buffered operands would not fit the registers (VALU form)
   }
 }
 

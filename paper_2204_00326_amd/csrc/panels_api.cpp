@@ -15,6 +15,8 @@ struct ls_panels {
   double L = 1.0;
   int sign = -1;
   lsi::DevBuf ref, far_x, far_w, qdag, M, T, q;
+  lsi::DevBuf part;  // partial planes of the matrix-core product (one stream at a time)
+  bool mfma = true;
 };
 
 namespace {
@@ -176,9 +178,18 @@ ls_status ls_panels_apply(ls_panels* P, const void* x, void* y, int nrhs, int64_
     if (op != 0 && op != 1) throw LsError(LS_EINVAL, "op must be 0 (A) or 1 (V)");
     if (x == y) throw LsError(LS_EINVAL, "x and y must not overlap");
     const double k2 = P->g.kappa * P->g.kappa;
-    lsp::launch_panel_apply(P->g, P->T.as<double2>(), op == 0 ? P->q.as<double>() : nullptr, (const double2*)x, ld,
-                            (double2*)y, ld, nrhs, op == 0 ? 1.0 : 0.0, op == 0 ? P->sign * k2 : 1.0,
-                            (hipStream_t)stream);
+    const double* q = op == 0 ? P->q.as<double>() : nullptr;
+    const double alpha = op == 0 ? 1.0 : 0.0, coef = op == 0 ? P->sign * k2 : 1.0;
+    if (P->mfma && P->g.p <= lsp::kMfmaMaxP) {
+      const int nc = lsp::panel_chunks(P->g, nrhs);
+      const int64_t N = (int64_t)P->g.nside * P->g.nside * P->g.n2;
+      P->part.ensure((size_t)nc * nrhs * N * 16);
+      lsp::launch_panel_apply_mfma(P->g, P->T.as<double2>(), q, (const double2*)x, ld, (double2*)y, ld, nrhs, alpha,
+                                   coef, P->part.as<double2>(), nc, (hipStream_t)stream);
+    } else {
+      lsp::launch_panel_apply(P->g, P->T.as<double2>(), q, (const double2*)x, ld, (double2*)y, ld, nrhs, alpha,
+                              coef, (hipStream_t)stream);
+    }
     lsi::hip_check(hipGetLastError(), "panel apply");
     return LS_OK;
   } catch (const LsError& e) {

@@ -68,7 +68,9 @@ def test_single_node_box_is_the_cell_rule():
     P.close()
 
 
-@pytest.mark.parametrize("nside,p,kappa,sign", [(4, 3, 10.0, -1), (3, 4, 25.0, 1), (1, 5, 6.0, -1)])
+# p <= 5 runs the matrix-core product, p = 6 the vector-ALU one
+@pytest.mark.parametrize("nside,p,kappa,sign", [(4, 3, 10.0, -1), (3, 4, 25.0, 1), (1, 5, 6.0, -1), (2, 5, 7.0, -1),
+                                                (2, 6, 8.0, -1)])
 def test_operator_matches_dense_oracle(nside, p, kappa, sign):
     L = 1.0
     boxes = panels.uniform_tree(nside, L)
