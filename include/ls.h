@@ -442,6 +442,13 @@ ls_status ls_panels_setup(int nside, double L, int p, double kappa, const double
  * device complex128, nrhs columns of leading dimension ld >= N, not overlapping; asynchronous on
  * stream (NULL: the default stream). */
 ls_status ls_panels_apply(ls_panels* P, const void* x, void* y, int nrhs, int64_t ld, int op, void* stream);
+/* psi = A^-1 f by restarted GMRES(restart) from psi = 0 (classical Gram-Schmidt with one
+ * reorthogonalisation, no preconditioner), stopping when the true ||f - A psi|| / ||f|| <= tol
+ * (recomputed at every restart) or after maxit products.  f, psi: device complex128 (N), not
+ * overlapping.  info: host (iters, relres, status LS_CONVERGED / LS_MAXIT / LS_NAN, n_refine =
+ * the GMRES cycles, t_solve_ms).  Synchronous. */
+ls_status ls_panels_solve(ls_panels* P, const void* f, void* psi, double tol, int restart, int maxit,
+                          ls_solve_info* info, void* stream);
 /* host copy of the moment table row of box offset (dx, dy) = target box - source box,
  * |dx|, |dy| < nside: out[(a * N_p + l) * 2 + {0, 1}] = M_l(node a of the target box, source
  * box), real and imaginary parts.  Synchronous. */

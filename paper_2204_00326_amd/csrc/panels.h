@@ -51,4 +51,13 @@ void launch_panel_apply_mfma(const PanelGeom& g, const double2* T, const double*
                              double2* y, long long ldy, int nrhs, double alpha, double coef, double2* part,
                              int nchunks, hipStream_t s);
 
+// Krylov vectors of the panel solver: part[i * nch + c] = chunk c of Q_i^H w (the host adds the
+// chunks in order); w -= sum_i c[i] Q_i (c on the device); y = alpha a + beta b.
+void launch_panel_dots(const double2* Q, long long ldq, int nvec, const double2* w, long long N, double2* part,
+                       int nch, hipStream_t s);
+void launch_panel_update(double2* w, const double2* Q, long long ldq, int nvec, const double2* c, long long N,
+                         hipStream_t s);
+void launch_panel_combo(double2* y, const double2* a, double alpha, const double2* b, double beta, long long N,
+                        hipStream_t s);
+
 }  // namespace lsp

@@ -345,6 +345,77 @@ void launch_panel_apply_mfma(const PanelGeom& g, const double2* T, const double*
   }
 }
 
+// ---- Krylov vector kernels of the panel solver (complex128, one right-hand side) ----
+// part[i * nch + c] = sum over chunk c of conj(Q_i[k]) w[k]; workgroup sums in a fixed order
+__global__ __launch_bounds__(256) void k_panel_dots(const double2* __restrict__ Q, long long ldq, int nvec,
+                                                    const double2* __restrict__ w, long long N,
+                                                    double2* __restrict__ part, int nch) {
+  __shared__ double2 red[4];
+  const int c = blockIdx.x, i = blockIdx.y, t = threadIdx.x;
+  const long long k0 = N * c / nch, k1 = N * (c + 1) / nch;
+  const double2* q = Q + i * ldq;
+  double re = 0, im = 0;
+  for (long long k = k0 + t; k < k1; k += 256) {
+    const double2 a = q[k], b = w[k];
+    re = fma(a.x, b.x, re);
+    re = fma(a.y, b.y, re);
+    im = fma(a.x, b.y, im);
+    im = fma(-a.y, b.x, im);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if ((t & 63) == 0) red[t >> 6] = make_double2(re, im);
+  __syncthreads();
+  if (t == 0) {
+    double2 o = red[0];
+    for (int w2 = 1; w2 < 4; ++w2) {
+      o.x += red[w2].x;
+      o.y += red[w2].y;
+    }
+    part[(long long)i * nch + c] = o;
+  }
+}
+
+// w[k] -= sum_i c[i] Q_i[k]
+__global__ __launch_bounds__(256) void k_panel_update(double2* __restrict__ w, const double2* __restrict__ Q,
+                                                      long long ldq, int nvec, const double2* __restrict__ c,
+                                                      long long N) {
+  const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (k >= N) return;
+  double2 o = w[k];
+  for (int i = 0; i < nvec; ++i) {
+    const double2 a = c[i], q = Q[i * ldq + k];
+    o.x -= a.x * q.x - a.y * q.y;
+    o.y -= a.x * q.y + a.y * q.x;
+  }
+  w[k] = o;
+}
+
+// y = alpha a + beta b (real coefficients)
+__global__ __launch_bounds__(256) void k_panel_combo(double2* __restrict__ y, const double2* __restrict__ a,
+                                                     double alpha, const double2* __restrict__ b, double beta,
+                                                     long long N) {
+  const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (k >= N) return;
+  const double2 u = a[k], v = b[k];
+  y[k] = make_double2(alpha * u.x + beta * v.x, alpha * u.y + beta * v.y);
+}
+
+void launch_panel_dots(const double2* Q, long long ldq, int nvec, const double2* w, long long N, double2* part,
+                       int nch, hipStream_t s) {
+  k_panel_dots<<<dim3((unsigned)nch, (unsigned)nvec), 256, 0, s>>>(Q, ldq, nvec, w, N, part, nch);
+}
+void launch_panel_update(double2* w, const double2* Q, long long ldq, int nvec, const double2* c, long long N,
+                         hipStream_t s) {
+  k_panel_update<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(w, Q, ldq, nvec, c, N);
+}
+void launch_panel_combo(double2* y, const double2* a, double alpha, const double2* b, double beta, long long N,
+                        hipStream_t s) {
+  k_panel_combo<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(y, a, alpha, b, beta, N);
+}
+
 void launch_panel_moments(const PanelGeom& g, const PanelRef* ref, const double* far_x, const double* far_w,
                           double2* M, hipStream_t s) {
   const int w2 = 2 * g.nside - 1;

@@ -17,6 +17,7 @@ struct ls_panels {
   lsi::DevBuf ref, far_x, far_w, qdag, M, T, q;
   lsi::DevBuf part;  // partial planes of the matrix-core product (one stream at a time)
   bool mfma = true;
+  lsi::DevBuf kq, kw, kr, kpart, kc;  // GMRES basis, work vectors, dot partials, coefficients
 };
 
 namespace {
@@ -191,6 +192,160 @@ ls_status ls_panels_apply(ls_panels* P, const void* x, void* y, int nrhs, int64_
                               coef, (hipStream_t)stream);
     }
     lsi::hip_check(hipGetLastError(), "panel apply");
+    return LS_OK;
+  } catch (const LsError& e) {
+    return lsi::fail(e);
+  }
+}
+
+// Restarted GMRES (Section 6 without the preconditioner) on A psi = f from psi = 0: classical
+// Gram-Schmidt with one reorthogonalisation, Givens rotations and the triangular solve on the
+// host, every vector operation on the device; each restart (and the end) recomputes the true
+// residual f - A psi.
+ls_status ls_panels_solve(ls_panels* P, const void* f, void* psi, double tol, int restart, int maxit,
+                          ls_solve_info* info, void* stream) {
+  try {
+    if (!P || !f || !psi || !info) throw LsError(LS_EINVAL, "handle, f, psi or info is NULL");
+    if (!(tol > 0 && tol < 1)) throw LsError(LS_EINVAL, "tol must be in (0, 1)");
+    if (restart < 1 || restart > 2000 || maxit < 1) throw LsError(LS_EINVAL, "restart in 1..2000 and maxit >= 1");
+    if (f == psi) throw LsError(LS_EINVAL, "f and psi must not overlap");
+    const double t0 = lsi::now_ms();
+    hipStream_t s = (hipStream_t)stream;
+    const long long N = (long long)P->g.nside * P->g.nside * P->g.n2;
+    const int m = restart;
+    const int nch = (int)std::max(1LL, std::min(1024LL, (N + 4095) / 4096));
+    P->kq.ensure((size_t)(m + 1) * N * 16);
+    P->kw.ensure((size_t)N * 16);
+    P->kr.ensure((size_t)N * 16);
+    P->kpart.ensure((size_t)(m + 1) * nch * 16);
+    P->kc.ensure((size_t)(m + 1) * 16);
+    double2* Q = P->kq.as<double2>();
+    double2* w = P->kw.as<double2>();
+    double2* r = P->kr.as<double2>();
+    double2* x = (double2*)psi;
+    const double2* fd = (const double2*)f;
+    std::vector<double2> hp((size_t)(m + 1) * nch);
+    // Q_0..Q_{nvec-1} (or v itself) against v, chunks added in order
+    auto dots = [&](const double2* base, int nvec, const double2* v, std::vector<zd>& out) {
+      lsp::launch_panel_dots(base, N, nvec, v, N, P->kpart.as<double2>(), nch, s);
+      lsi::hip_check(hipMemcpyAsync(hp.data(), P->kpart.p, (size_t)nvec * nch * 16, hipMemcpyDeviceToHost, s), "dots");
+      lsi::hip_check(hipStreamSynchronize(s), "dots");
+      out.assign(nvec, zd(0));
+      for (int i = 0; i < nvec; ++i)
+        for (int c = 0; c < nch; ++c) out[i] += zd(hp[(size_t)i * nch + c].x, hp[(size_t)i * nch + c].y);
+    };
+    auto norm = [&](const double2* v) {
+      std::vector<zd> d;
+      dots(v, 1, v, d);
+      return std::sqrt(std::max(d[0].real(), 0.0));
+    };
+    // w -= sum_i c_i Q_i (c on the host)
+    std::vector<double2> ch(m + 1);
+    auto update = [&](double2* v, int nvec, const std::vector<zd>& c, double sgn) {
+      for (int i = 0; i < nvec; ++i) ch[i] = make_double2(sgn * c[i].real(), sgn * c[i].imag());
+      lsi::hip_check(hipMemcpy(P->kc.p, ch.data(), (size_t)nvec * 16, hipMemcpyHostToDevice), "coefficients");
+      lsp::launch_panel_update(v, Q, N, nvec, P->kc.as<double2>(), N, s);
+    };
+    const double k2 = P->g.kappa * P->g.kappa;
+    auto applyA = [&](const double2* in, double2* out) {
+      if (P->mfma && P->g.p <= lsp::kMfmaMaxP) {
+        const int nc = lsp::panel_chunks(P->g, 1);
+        P->part.ensure((size_t)nc * N * 16);
+        lsp::launch_panel_apply_mfma(P->g, P->T.as<double2>(), P->q.as<double>(), in, N, out, N, 1, 1.0,
+                                     P->sign * k2, P->part.as<double2>(), nc, s);
+      } else {
+        lsp::launch_panel_apply(P->g, P->T.as<double2>(), P->q.as<double>(), in, N, out, N, 1, 1.0, P->sign * k2, s);
+      }
+    };
+    lsp::launch_panel_combo(x, fd, 0.0, fd, 0.0, N, s);  // x0 = 0
+    lsp::launch_panel_combo(r, fd, 1.0, fd, 0.0, N, s);  // r0 = f
+    const double fnorm = norm(fd);
+    info->iters = 0;
+    info->n_refine = 0;
+    info->relres0 = 1.0;
+    info->relres = 0.0;
+    info->status = LS_CONVERGED;
+    if (!(fnorm > 0)) {
+      if (!std::isfinite(fnorm)) info->status = LS_NAN;
+      info->t_solve_ms = lsi::now_ms() - t0;
+      return LS_OK;
+    }
+    std::vector<zd> H((size_t)(m + 1) * m), g(m + 1), sn(m), h, h2;
+    std::vector<double> cs(m);
+    int it = 0;
+    for (;;) {
+      const double beta = norm(r);
+      const double rel = beta / fnorm;
+      info->relres = rel;
+      if (!std::isfinite(rel)) {
+        info->status = LS_NAN;
+        break;
+      }
+      if (rel <= tol) {
+        info->status = LS_CONVERGED;
+        break;
+      }
+      if (it >= maxit) {
+        info->status = LS_MAXIT;
+        break;
+      }
+      info->n_refine += 1;
+      lsp::launch_panel_combo(Q, r, 1.0 / beta, r, 0.0, N, s);
+      std::fill(H.begin(), H.end(), zd(0));
+      std::fill(g.begin(), g.end(), zd(0));
+      g[0] = beta;
+      int k = 0;
+      for (int j = 0; j < m && it < maxit; ++j) {
+        applyA(Q + (size_t)j * N, w);
+        ++it;
+        dots(Q, j + 1, w, h);
+        update(w, j + 1, h, 1.0);
+        dots(Q, j + 1, w, h2);
+        update(w, j + 1, h2, 1.0);
+        for (int i = 0; i <= j; ++i) h[i] += h2[i];
+        const double hn = norm(w);
+        if (hn > 0) lsp::launch_panel_combo(Q + (size_t)(j + 1) * N, w, 1.0 / hn, w, 0.0, N, s);
+        // rotations of the previous columns, then the one that removes the subdiagonal entry
+        zd hj1 = hn;
+        for (int i = 0; i < j; ++i) {
+          const zd a = h[i], b = h[i + 1];
+          h[i] = cs[i] * a + sn[i] * b;
+          h[i + 1] = -std::conj(sn[i]) * a + cs[i] * b;
+        }
+        const zd a = h[j];
+        const double rho = std::sqrt(std::norm(a) + std::norm(hj1));
+        if (rho == 0) {
+          cs[j] = 1.0;
+          sn[j] = 0.0;
+        } else if (std::abs(a) == 0) {
+          cs[j] = 0.0;
+          sn[j] = std::conj(hj1) / rho;
+        } else {
+          cs[j] = std::abs(a) / rho;
+          sn[j] = (a / std::abs(a)) * std::conj(hj1) / rho;
+        }
+        h[j] = cs[j] * a + sn[j] * hj1;
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i];
+        g[j + 1] = -std::conj(sn[j]) * g[j];
+        g[j] = cs[j] * g[j];
+        k = j + 1;
+        if (std::abs(g[j + 1]) <= tol * fnorm || hn == 0) break;
+      }
+      // psi += Q y with R y = g
+      std::vector<zd> y(k);
+      for (int i = k - 1; i >= 0; --i) {
+        zd acc = g[i];
+        for (int jj = i + 1; jj < k; ++jj) acc -= H[(size_t)i * m + jj] * y[jj];
+        y[i] = acc / H[(size_t)i * m + i];
+      }
+      update(x, k, y, -1.0);
+      applyA(x, w);
+      lsp::launch_panel_combo(r, fd, 1.0, w, -1.0, N, s);
+    }
+    info->iters = it;
+    lsi::hip_check(hipGetLastError(), "panel solve");
+    lsi::hip_check(hipStreamSynchronize(s), "panel solve");
+    info->t_solve_ms = lsi::now_ms() - t0;
     return LS_OK;
   } catch (const LsError& e) {
     return lsi::fail(e);

@@ -134,10 +134,11 @@ def lib():
     L.ls_panels_setup.argtypes = [ci, cd, ci, cd, vp, ci, C.POINTER(vp)]
     L.ls_panels_apply.argtypes = [vp, vp, vp, ci, i64, ci, vp]
     L.ls_panels_moments.argtypes = [vp, ci, ci, vp]
+    L.ls_panels_solve.argtypes = [vp, vp, vp, cd, ci, ci, C.POINTER(_Info), vp]
     L.ls_panels_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.ls_panels_destroy.argtypes = [vp]
     L.ls_panels_destroy.restype = None
-    for name in ("ls_panels_setup", "ls_panels_apply", "ls_panels_moments", "ls_panels_info"):
+    for name in ("ls_panels_setup", "ls_panels_apply", "ls_panels_moments", "ls_panels_info", "ls_panels_solve"):
         getattr(L, name).restype = C.c_int
     for name in ("ls_setup", "ls_matvec", "ls_apply_V", "ls_precond_apply", "ls_precond_apply_noalloc",
                  "ls_rhs_planewave", "ls_solve",
@@ -521,6 +522,17 @@ class Panels:
         y = torch.empty_like(x) if y is None else y
         _check(lib().ls_panels_apply(self._h, x.data_ptr(), y.data_ptr(), nrhs, self.N, int(op), _stream(stream)))
         return y
+
+    def solve(self, f, tol: float = 1e-10, restart: int = 200, maxit: int = 2000, stream=None):
+        """ls_panels_solve: psi = A^-1 f (complex128 CUDA tensor of N entries) and the info dict"""
+        import torch
+        if _vec(f, self.N) != 1:
+            raise ValueError("one right-hand side")
+        psi = torch.empty_like(f)
+        info = _Info()
+        _check(lib().ls_panels_solve(self._h, f.data_ptr(), psi.data_ptr(), float(tol), int(restart), int(maxit),
+                                     C.byref(info), _stream(stream)))
+        return psi, _info_dict(info)
 
     def moments(self, dx: int, dy: int) -> np.ndarray:
         """M_l(node a of the target box, source box) for box offset (dx, dy): array (p^2, N_p)"""

@@ -115,3 +115,58 @@ def test_apply_on_a_polynomial_density_integrates_it():
     ref = sum(panels.moments(X, b, p, kappa) @ c for b in boxes)
     assert np.linalg.norm(u - ref) < 1e-10 * np.linalg.norm(ref)
     P.close()
+
+
+def test_solve_matches_dense_solve():
+    nside, p, kappa = 4, 3, 10.0
+    boxes = panels.uniform_tree(nside)
+    A = panels.dense_A(boxes, p, kappa, qfun)
+    f = panels.rhs_planewave(boxes, p, kappa, qfun, theta=0.3)
+    P = ls.Panels(nside, 1.0, p, kappa, node_q(boxes, p))
+    psi, info = P.solve(torch.from_numpy(f).cuda(), tol=1e-12, restart=8)   # restarts from true residuals
+    psi = psi.cpu().numpy()
+    ref = np.linalg.solve(A, f)
+    say("panel solve", info, np.linalg.norm(psi - ref) / np.linalg.norm(ref))
+    assert info["status"] == "CONVERGED" and info["relres"] <= 1e-12 and info["n_refine"] >= 2
+    assert np.linalg.norm(A @ psi - f) <= 1.2e-12 * np.linalg.norm(f)
+    assert np.linalg.norm(psi - ref) <= 1e-9 * np.linalg.norm(ref)
+    # a zero right-hand side gives psi = 0 without iterating
+    z, iz = P.solve(torch.zeros(P.N, dtype=torch.complex128, device="cuda"))
+    assert iz["iters"] == 0 and torch.count_nonzero(z).item() == 0
+    P.close()
+
+
+def _bump(q0, R):
+    def q_r(r):
+        x = np.clip(np.asarray(r, dtype=float) / R, 0, 1)
+        with np.errstate(divide="ignore", over="ignore"):
+            return np.where(x < 1, q0 * np.exp(1.0 - 1.0 / np.maximum(1.0 - x * x, 1e-300)), 0.0)
+    return q_r
+
+
+def test_device_solution_converges_to_the_radial_reference():
+    # the high-order accuracy of Section 2 on the device: for a smooth radial contrast the panel
+    # solution approaches the separation-of-variables reference as p grows, and equals the
+    # oracle's dense solve of the same discretisation
+    from oracle import radial
+    kappa, R, q0 = 6.0, 0.8, 1.0
+    q_r = _bump(q0, R)
+    q_fn = lambda x, y: q_r(np.hypot(x, y))
+    boxes = panels.uniform_tree(4)
+    errs = []
+    for p in (2, 4, 6):
+        X = panels.all_nodes(boxes, p)
+        q = q_fn(X[:, 0], X[:, 1])
+        f = panels.rhs_planewave(boxes, p, kappa, q_fn)
+        P = ls.Panels(4, 1.0, p, kappa, q)
+        psi, info = P.solve(torch.from_numpy(f).cuda(), tol=1e-12, restart=100)
+        psi = psi.cpu().numpy()
+        P.close()
+        dense = np.linalg.solve(panels.dense_A(boxes, p, kappa, q_fn), f)
+        assert np.linalg.norm(psi - dense) <= 1e-8 * np.linalg.norm(dense), p
+        m = q > 1e-12
+        ref = kappa ** 2 * q[m] * radial.total_field(X[m], kappa, lambda r: float(q_r(r)), R, q0)
+        errs.append(np.linalg.norm(psi[m] - ref) / np.linalg.norm(ref))
+        say("p", p, info, "error vs radial reference", errs[-1])
+    assert errs[0] > 5 * errs[1] > 5 * 5 * errs[2]
+    assert errs[2] < 5e-3
