@@ -438,6 +438,16 @@ typedef struct ls_panels ls_panels;
  * on the current device (synchronous).  Errors: LS_EINVAL (bad argument, non-finite q),
  * LS_ENOTSUP (tables above 64 GB), LS_ENOMEM / LS_EDEVICE. */
 ls_status ls_panels_setup(int nside, double L, int p, double kappa, const double* q, int sign, ls_panels** out);
+/* The same discretisation on the leaves of any tree, for instance the adaptive, level-restricted
+ * quadtree of Section 2.1: boxes: host, nboxes x 3 (centre x, centre y, half-width), leaves that
+ * tile the domain without overlap (not checked); unknowns box-major in that order, node-minor
+ * (N = nboxes p^2 <= 20000).  The moments of every box at every node use the rules above (the far
+ * rule's point count taken from each box's half-width), and the device keeps the dense V (N^2
+ * complex entries).  ls_panels_apply and ls_panels_solve work as for the uniform tree;
+ * ls_panels_moments returns LS_ENOTSUP.  Errors as for ls_panels_setup, LS_ENOTSUP above 20000
+ * unknowns. */
+ls_status ls_panels_setup_leaves(int nboxes, const double* boxes, int p, double kappa, const double* q, int sign,
+                                 ls_panels** out);
 /* op 0: y = A x; op 1: y = V x (the volume potential of the density x at the nodes).  x, y:
  * device complex128, nrhs columns of leading dimension ld >= N, not overlapping; asynchronous on
  * stream (NULL: the default stream). */

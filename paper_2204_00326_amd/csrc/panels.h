@@ -17,6 +17,7 @@ constexpr int kMaxP = 8;                        // nodes per box side
 constexpr int kMaxNp = kMaxP * (kMaxP + 1) / 2;  // basis functions
 constexpr int kRay = 48;                        // Gauss-Legendre points along a Duffy ray
 constexpr int kAcross = 48;                     // points across a triangle, per side of the foot
+constexpr long long kDenseMaxN = 20000;         // unknowns of the dense operator of a general tree
 
 struct PanelGeom {
   int nside, p, np, n2;  // n2 = p * p
@@ -50,6 +51,17 @@ int panel_chunks(const PanelGeom& g, int nrhs);
 void launch_panel_apply_mfma(const PanelGeom& g, const double2* T, const double* q, const double2* x, long long ldx,
                              double2* y, long long ldy, int nrhs, double alpha, double coef, double2* part,
                              int nchunks, hipStream_t s);
+
+// Leaves of any tree (an adaptive, level-restricted one included): boxes[5 B ..] = (cx, cy, beta,
+// offset of the box's far rule in far_x / far_w, its points per direction); X: the N nodes (x, y).
+// M[i][B][l] for every target node i and box B (same rules as launch_panel_moments), then the
+// dense V (N x N row-major, column B * n2 + b) and its product.
+void launch_panel_moments_leaves(const PanelRef* ref, int p, int np, double kappa, const double* boxes, int nboxes,
+                                 const double2* X, long long N, const double* far_x, const double* far_w, double2* M,
+                                 hipStream_t s);
+void launch_panel_dense_V(const double2* M, const double* Qdag, int nboxes, int np, int n2, double2* V, hipStream_t s);
+void launch_panel_dense_apply(const double2* V, long long N, const double* q, const double2* x, long long ldx,
+                              double2* y, long long ldy, int nrhs, double alpha, double coef, hipStream_t s);
 
 // Krylov vectors of the panel solver: part[i * nch + c] = chunk c of Q_i^H w (the host adds the
 // chunks in order); w -= sum_i c[i] Q_i (c on the device); y = alpha a + beta b.

@@ -52,67 +52,58 @@ __device__ inline void add_basis(const PanelRef& R, int p, int np, double u, dou
 // t = t0 + mu sinh(tau) on each side of the foot t0 of the perpendicular from the apex (mu: the
 // apex's distance to the edge line over the edge length), which spreads the peak of the integrand
 // at the foot (the sinh transformation for nearly singular integrals, Johnston and Elliott 2005).
-__global__ __launch_bounds__(256) void k_panel_moments(PanelGeom g, const PanelRef* __restrict__ ref,
-                                                       const double* __restrict__ far_x,
-                                                       const double* __restrict__ far_w, double2* __restrict__ M) {
-  __shared__ PanelRef R;
-  __shared__ double2 red[4][kMaxNp];
-  const int d = blockIdx.x, a = blockIdx.y, t = threadIdx.x;
-  for (int i = t; i < (int)(sizeof(PanelRef) / sizeof(double)); i += 256)
-    reinterpret_cast<double*>(&R)[i] = reinterpret_cast<const double*>(ref)[i];
-  __syncthreads();
-  const int w2 = 2 * g.nside - 1;
-  const int dx = d / w2 - (g.nside - 1), dy = d % w2 - (g.nside - 1);
-  const double be = g.beta;
-  const double tx = 2.0 * be * dx + be * R.node[a / g.p], ty = 2.0 * be * dy + be * R.node[a % g.p];
+// One thread's share of the moments of a box of half-width be at the target (tx, ty) taken
+// relative to the box centre, added into acc[0..np): the far rule's points or the near rule's
+// (triangle, side of the foot, point across) items, strided over the 256 threads.
+__device__ void moment_part(const PanelRef& R, int p, int np, double kappa, double be, double tx, double ty,
+                            const double* __restrict__ far_x, const double* __restrict__ far_w, int nfar, int t,
+                            double2* acc) {
   const double ox = fmax(fabs(tx) - be, 0.0), oy = fmax(fabs(ty) - be, 0.0);
-  const bool far = sqrt(ox * ox + oy * oy) >= be;
-  double2 acc[kMaxNp];
-#pragma unroll
-  for (int l = 0; l < kMaxNp; ++l) acc[l] = make_double2(0.0, 0.0);
-  if (far) {
-    const int nq = g.nfar * g.nfar;
+  if (sqrt(ox * ox + oy * oy) >= be) {
+    const int nq = nfar * nfar;
     for (int q = t; q < nq; q += 256) {
-      const double u = far_x[q / g.nfar], v = far_x[q % g.nfar];
-      const double w = far_w[q / g.nfar] * far_w[q % g.nfar] * be * be;
+      const double u = far_x[q / nfar], v = far_x[q % nfar];
+      const double w = far_w[q / nfar] * far_w[q % nfar] * be * be;
       const double rx = tx - be * u, ry = ty - be * v;
-      const double2 G = green(g.kappa, sqrt(rx * rx + ry * ry));
-      add_basis(R, g.p, g.np, u, v, make_double2(G.x * w, G.y * w), acc);
+      const double2 G = green(kappa, sqrt(rx * rx + ry * ry));
+      add_basis(R, p, np, u, v, make_double2(G.x * w, G.y * w), acc);
     }
-  } else {
-    // items: (triangle k, side of the foot, point across)
-    for (int it = t; it < 4 * 2 * kAcross; it += 256) {
-      const int k = it / (2 * kAcross), side = (it / kAcross) & 1, ia = it % kAcross;
-      const double cxk[4] = {-be, be, be, -be}, cyk[4] = {-be, -be, be, be};
-      const double ax = cxk[k], ay = cyk[k], bx = cxk[(k + 1) & 3], by = cyk[(k + 1) & 3];
-      const double ex = bx - ax, ey = by - ay;
-      const double J = (ax - tx) * ey - (ay - ty) * ex;
-      if (fabs(J) <= 1e-15 * be * be) continue;
-      const double dd = ex * ex + ey * ey;
-      const double t0 = ((tx - ax) * ex + (ty - ay) * ey) / dd;
-      const double mu = fabs(J) / dd;
-      // the two sides of the foot inside [0, 1] (one empty when the foot lies outside)
-      const double f = fmin(fmax(t0, 0.0), 1.0);
-      const double lo = side ? f : 0.0, hi = side ? 1.0 : f;
-      if (hi <= lo) continue;
-      const double tl = asinh((lo - t0) / mu), th = asinh((hi - t0) / mu);
-      const double tau = tl + (th - tl) * R.acr_t[ia];
-      const double tt = t0 + mu * sinh(tau);
-      const double wt = (th - tl) * R.acr_w[ia] * mu * cosh(tau) * J;
-      const double px = ax + tt * ex - tx, py = ay + tt * ey - ty;
-      const double rho = sqrt(px * px + py * py);
-      for (int iu = 0; iu < kRay; ++iu) {
-        const double u = R.ray_t[iu], s = u * u, ws = 2.0 * u * u * u * R.ray_w[iu] * wt;
-        const double2 G = green(g.kappa, s * rho);
-        add_basis(R, g.p, g.np, (tx + s * px) / be, (ty + s * py) / be, make_double2(G.x * ws, G.y * ws), acc);
-      }
+    return;
+  }
+  for (int it = t; it < 4 * 2 * kAcross; it += 256) {
+    const int k = it / (2 * kAcross), side = (it / kAcross) & 1, ia = it % kAcross;
+    const double cxk[4] = {-be, be, be, -be}, cyk[4] = {-be, -be, be, be};
+    const double ax = cxk[k], ay = cyk[k], bx = cxk[(k + 1) & 3], by = cyk[(k + 1) & 3];
+    const double ex = bx - ax, ey = by - ay;
+    const double J = (ax - tx) * ey - (ay - ty) * ex;
+    if (fabs(J) <= 1e-15 * be * be) continue;
+    const double dd = ex * ex + ey * ey;
+    const double t0 = ((tx - ax) * ex + (ty - ay) * ey) / dd;
+    const double mu = fabs(J) / dd;
+    // the two sides of the foot inside [0, 1] (one empty when the foot lies outside)
+    const double f = fmin(fmax(t0, 0.0), 1.0);
+    const double lo = side ? f : 0.0, hi = side ? 1.0 : f;
+    if (hi <= lo) continue;
+    const double tl = asinh((lo - t0) / mu), th = asinh((hi - t0) / mu);
+    const double tau = tl + (th - tl) * R.acr_t[ia];
+    const double tt = t0 + mu * sinh(tau);
+    const double wt = (th - tl) * R.acr_w[ia] * mu * cosh(tau) * J;
+    const double px = ax + tt * ex - tx, py = ay + tt * ey - ty;
+    const double rho = sqrt(px * px + py * py);
+    for (int iu = 0; iu < kRay; ++iu) {
+      const double u = R.ray_t[iu], s = u * u, ws = 2.0 * u * u * u * R.ray_w[iu] * wt;
+      const double2 G = green(kappa, s * rho);
+      add_basis(R, p, np, (tx + s * px) / be, (ty + s * py) / be, make_double2(G.x * ws, G.y * ws), acc);
     }
   }
-  // workgroup sum in a fixed order: butterfly within each wave, then the four waves
-  const int wave = t >> 6, lane = t & 63;
+}
+
+// workgroup sum in a fixed order (butterfly within each wave, then the four waves) into out[0..np)
+__device__ void moment_reduce(double2* acc, int np, double2 (*red)[kMaxNp], double2* out) {
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
 #pragma unroll
   for (int l = 0; l < kMaxNp; ++l) {
-    if (l < g.np) {
+    if (l < np) {
       double re = acc[l].x, im = acc[l].y;
       for (int off = 32; off > 0; off >>= 1) {
         re += __shfl_xor(re, off, 64);
@@ -122,13 +113,118 @@ __global__ __launch_bounds__(256) void k_panel_moments(PanelGeom g, const PanelR
     }
   }
   __syncthreads();
-  if (t < g.np) {
+  if (t < np) {
     double2 o = red[0][t];
     for (int w = 1; w < 4; ++w) {
       o.x += red[w][t].x;
       o.y += red[w][t].y;
     }
-    M[((long long)d * g.n2 + a) * g.np + t] = o;
+    out[t] = o;
+  }
+}
+
+__device__ void load_ref(const PanelRef* __restrict__ ref, PanelRef& R) {
+  for (int i = threadIdx.x; i < (int)(sizeof(PanelRef) / sizeof(double)); i += 256)
+    reinterpret_cast<double*>(&R)[i] = reinterpret_cast<const double*>(ref)[i];
+  __syncthreads();
+}
+
+// One workgroup per (offset d, target node a): M[d][a][l] = int_B G(|x - y|) b_l((y - c_B) / beta) dy
+// with x the target node relative to the source box centre c_B.  Targets at least beta away from
+// the box take the tensor Gauss-Legendre rule (nfar points per direction); nearer ones split the
+// box into the four signed triangles with apex at the target, each mapped to the unit square with
+// y = x + s (a + t (b - a) - x), s = u^2 (the Jacobian s ds = 2 u^3 du removes the logarithmic
+// singularity at the apex), Gauss-Legendre in u and, across the triangle, Gauss-Legendre after
+// t = t0 + mu sinh(tau) on each side of the foot t0 of the perpendicular from the apex (mu: the
+// apex's distance to the edge line over the edge length), which spreads the peak of the integrand
+// at the foot (the sinh transformation for nearly singular integrals, Johnston and Elliott 2005).
+__global__ __launch_bounds__(256) void k_panel_moments(PanelGeom g, const PanelRef* __restrict__ ref,
+                                                       const double* __restrict__ far_x,
+                                                       const double* __restrict__ far_w, double2* __restrict__ M) {
+  __shared__ PanelRef R;
+  __shared__ double2 red[4][kMaxNp];
+  const int d = blockIdx.x, a = blockIdx.y;
+  load_ref(ref, R);
+  const int w2 = 2 * g.nside - 1;
+  const int dx = d / w2 - (g.nside - 1), dy = d % w2 - (g.nside - 1);
+  const double be = g.beta;
+  const double tx = 2.0 * be * dx + be * R.node[a / g.p], ty = 2.0 * be * dy + be * R.node[a % g.p];
+  double2 acc[kMaxNp];
+#pragma unroll
+  for (int l = 0; l < kMaxNp; ++l) acc[l] = make_double2(0.0, 0.0);
+  moment_part(R, g.p, g.np, g.kappa, be, tx, ty, far_x, far_w, g.nfar, threadIdx.x, acc);
+  moment_reduce(acc, g.np, red, M + ((long long)d * g.n2 + a) * g.np);
+}
+
+// Leaves of any tree (boxes[B] = (cx, cy, beta, far rule offset, far rule points)): one workgroup
+// per (source box B, target node i at X[i]): M[i][B][l], same rules as k_panel_moments
+__global__ __launch_bounds__(256) void k_panel_moments_leaves(const PanelRef* __restrict__ ref, int p, int np,
+                                                              double kappa, const double* __restrict__ boxes,
+                                                              int nboxes, const double2* __restrict__ X,
+                                                              const double* __restrict__ far_x,
+                                                              const double* __restrict__ far_w,
+                                                              double2* __restrict__ M) {
+  __shared__ PanelRef R;
+  __shared__ double2 red[4][kMaxNp];
+  const int B = blockIdx.x, i = blockIdx.y;
+  load_ref(ref, R);
+  const double* bx = boxes + 5 * B;
+  const double be = bx[2];
+  const int off = (int)bx[3], nfar = (int)bx[4];
+  const double2 xi = X[i];
+  double2 acc[kMaxNp];
+#pragma unroll
+  for (int l = 0; l < kMaxNp; ++l) acc[l] = make_double2(0.0, 0.0);
+  moment_part(R, p, np, kappa, be, xi.x - bx[0], xi.y - bx[1], far_x + off, far_w + off, nfar, threadIdx.x, acc);
+  moment_reduce(acc, np, red, M + ((long long)i * nboxes + B) * np);
+}
+
+// V[i][B * n2 + b] = sum_l M[i][B][l] Qdag[l][b] (row-major, N x N)
+__global__ __launch_bounds__(256) void k_panel_dense_V(const double2* __restrict__ M, const double* __restrict__ Qdag,
+                                                       int nboxes, int np, int n2, double2* __restrict__ V) {
+  const long long i = blockIdx.x;
+  const int ncol = nboxes * n2;
+  for (int c = threadIdx.x; c < ncol; c += 256) {
+    const int B = c / n2, b = c % n2;
+    const double2* m = M + (i * nboxes + B) * np;
+    double re = 0, im = 0;
+    for (int l = 0; l < np; ++l) {
+      const double q = Qdag[l * n2 + b];
+      re = fma(m[l].x, q, re);
+      im = fma(m[l].y, q, im);
+    }
+    V[i * ncol + c] = make_double2(re, im);
+  }
+}
+
+// y = alpha x + coef q (V x) with the dense V: one wave per row and right-hand side, its lanes
+// striding over the columns (coalesced), butterfly sum
+__global__ __launch_bounds__(256) void k_panel_dense_apply(const double2* __restrict__ V, long long N,
+                                                           const double* __restrict__ q,
+                                                           const double2* __restrict__ x, long long ldx,
+                                                           double2* __restrict__ y, long long ldy, double alpha,
+                                                           double coef) {
+  const long long i = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, rhs = blockIdx.y;
+  if (i >= N) return;
+  const double2* row = V + i * N;
+  const double2* xr = x + rhs * ldx;
+  double re = 0, im = 0;
+  for (long long j = lane; j < N; j += 64) {
+    const double2 a = row[j], v = xr[j];
+    re = fma(a.x, v.x, re);
+    re = fma(-a.y, v.y, re);
+    im = fma(a.x, v.y, im);
+    im = fma(a.y, v.x, im);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if (lane == 0) {
+    const double2 xi = xr[i];
+    const double c = q ? coef * q[i] : coef;
+    y[rhs * ldy + i] = make_double2(alpha * xi.x + c * re, alpha * xi.y + c * im);
   }
 }
 
@@ -414,6 +510,23 @@ void launch_panel_update(double2* w, const double2* Q, long long ldq, int nvec, 
 void launch_panel_combo(double2* y, const double2* a, double alpha, const double2* b, double beta, long long N,
                         hipStream_t s) {
   k_panel_combo<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(y, a, alpha, b, beta, N);
+}
+
+void launch_panel_moments_leaves(const PanelRef* ref, int p, int np, double kappa, const double* boxes, int nboxes,
+                                 const double2* X, long long N, const double* far_x, const double* far_w, double2* M,
+                                 hipStream_t s) {
+  k_panel_moments_leaves<<<dim3((unsigned)nboxes, (unsigned)N), 256, 0, s>>>(ref, p, np, kappa, boxes, nboxes, X,
+                                                                             far_x, far_w, M);
+}
+
+void launch_panel_dense_V(const double2* M, const double* Qdag, int nboxes, int np, int n2, double2* V, hipStream_t s) {
+  k_panel_dense_V<<<(unsigned)((long long)nboxes * n2), 256, 0, s>>>(M, Qdag, nboxes, np, n2, V);
+}
+
+void launch_panel_dense_apply(const double2* V, long long N, const double* q, const double2* x, long long ldx,
+                              double2* y, long long ldy, int nrhs, double alpha, double coef, hipStream_t s) {
+  k_panel_dense_apply<<<dim3((unsigned)((N + 3) / 4), (unsigned)nrhs), 256, 0, s>>>(V, N, q, x, ldx, y, ldy, alpha,
+                                                                                   coef);
 }
 
 void launch_panel_moments(const PanelGeom& g, const PanelRef* ref, const double* far_x, const double* far_w,

@@ -14,6 +14,10 @@ struct ls_panels {
   lsp::PanelGeom g{};
   double L = 1.0;
   int sign = -1;
+  int64_t N = 0;       // unknowns
+  bool dense = false;  // leaves of a general tree: the dense V instead of per-offset blocks
+  int nboxes = 0;
+  lsi::DevBuf V, X, boxes;
   lsi::DevBuf ref, far_x, far_w, qdag, M, T, q;
   lsi::DevBuf part;  // partial planes of the matrix-core product (one stream at a time)
   bool mfma = true;
@@ -73,8 +77,57 @@ double cheb(int n, double x) {
 void check_vec(const ls_panels* P, const void* x, const void* y, int nrhs, int64_t ld) {
   if (!P) throw LsError(LS_EINVAL, "panels handle is NULL");
   if (!x || !y) throw LsError(LS_EINVAL, "x or y is NULL");
-  const int64_t N = (int64_t)P->g.nside * P->g.nside * P->g.n2;
+  const int64_t N = P->N;
   if (nrhs < 1 || ld < N) throw LsError(LS_EINVAL, "nrhs must be >= 1 and ld >= the number of unknowns");
+}
+
+// Chebyshev nodes (first kind, ascending), the basis (by total degree, then first index) and
+// the Gauss-Legendre rules on [0, 1] along the ray and across the triangles; uploads them with
+// Qdag = (Q^T Q)^-1 Q^T.  Q (n2 x np): Q[i][l] = b_l(node i); its columns are orthogonal at the
+// Chebyshev points of the first kind (discrete orthogonality of T_0..T_{p-1}), so Qdag is the
+// transpose scaled by the diagonal of Q^T Q.
+lsp::PanelRef reference_data(ls_panels* P) {
+  const lsp::PanelGeom& g = P->g;
+  const int p = g.p;
+  lsp::PanelRef R{};
+  for (int i = 0; i < p; ++i) R.node[i] = std::cos((2.0 * (p - 1 - i) + 1.0) * M_PI / (2.0 * p));
+  int l = 0;
+  for (int dgr = 0; dgr < p; ++dgr)
+    for (int a = 0; a <= dgr; ++a, ++l) {
+      R.ba[l] = a;
+      R.bb[l] = dgr - a;
+    }
+  std::vector<double> gx, gw;
+  gauss_legendre(lsp::kRay, gx, gw);
+  for (int i = 0; i < lsp::kRay; ++i) {
+    R.ray_t[i] = 0.5 * (gx[i] + 1.0);
+    R.ray_w[i] = 0.5 * gw[i];
+  }
+  gauss_legendre(lsp::kAcross, gx, gw);
+  for (int i = 0; i < lsp::kAcross; ++i) {
+    R.acr_t[i] = 0.5 * (gx[i] + 1.0);
+    R.acr_w[i] = 0.5 * gw[i];
+  }
+  const int n2 = g.n2, np = g.np;
+  std::vector<double> Q((size_t)n2 * np), Qd((size_t)np * n2);
+  for (int i = 0; i < p; ++i)
+    for (int j = 0; j < p; ++j)
+      for (int k = 0; k < np; ++k) Q[(size_t)(i * p + j) * np + k] = cheb(R.ba[k], R.node[i]) * cheb(R.bb[k], R.node[j]);
+  for (int k = 0; k < np; ++k) {
+    double dkk = 0;
+    for (int i = 0; i < n2; ++i) dkk += Q[(size_t)i * np + k] * Q[(size_t)i * np + k];
+    for (int k2 = 0; k2 < np; ++k2) {
+      if (k2 == k) continue;
+      double off = 0;
+      for (int i = 0; i < n2; ++i) off += Q[(size_t)i * np + k] * Q[(size_t)i * np + k2];
+      if (std::fabs(off) > 1e-12 * dkk) throw LsError(LS_ENOTSUP, "interpolation matrix without orthogonal columns");
+    }
+    for (int i = 0; i < n2; ++i) Qd[(size_t)k * n2 + i] = Q[(size_t)i * np + k] / dkk;
+  }
+  P->ref.alloc(sizeof(R));
+  lsi::hip_check(hipMemcpy(P->ref.p, &R, sizeof(R), hipMemcpyHostToDevice), "panels ref");
+  P->qdag.upload(Qd);
+  return R;
 }
 
 }  // namespace
@@ -107,53 +160,13 @@ ls_status ls_panels_setup(int nside, double L, int p, double kappa, const double
     g.nfar = std::max(16, (int)std::ceil(2.0 * kappa * g.beta) + 12);
     P->L = L;
     P->sign = sign;
-    // reference data: nodes (first kind, ascending), basis by total degree then first index,
-    // Gauss-Legendre rules on [0, 1] along the ray and across the triangles
-    lsp::PanelRef R{};
-    for (int i = 0; i < p; ++i) R.node[i] = std::cos((2.0 * (p - 1 - i) + 1.0) * M_PI / (2.0 * p));
-    int l = 0;
-    for (int dgr = 0; dgr < p; ++dgr)
-      for (int a = 0; a <= dgr; ++a, ++l) {
-        R.ba[l] = a;
-        R.bb[l] = dgr - a;
-      }
-    std::vector<double> gx, gw;
-    gauss_legendre(lsp::kRay, gx, gw);
-    for (int i = 0; i < lsp::kRay; ++i) {
-      R.ray_t[i] = 0.5 * (gx[i] + 1.0);
-      R.ray_w[i] = 0.5 * gw[i];
-    }
-    gauss_legendre(lsp::kAcross, gx, gw);
-    for (int i = 0; i < lsp::kAcross; ++i) {
-      R.acr_t[i] = 0.5 * (gx[i] + 1.0);
-      R.acr_w[i] = 0.5 * gw[i];
-    }
+    P->N = N;
+    const int n2 = g.n2, np = g.np;
+    reference_data(P.get());
     std::vector<double> fx, fw;
     gauss_legendre(g.nfar, fx, fw);
-    // Q (n2 x np): Q[i][l] = b_l(node i); its columns are orthogonal at the Chebyshev points of the
-    // first kind (discrete orthogonality of T_0..T_{p-1}), so Qdag = (Q^T Q)^-1 Q^T is the
-    // transpose scaled by the diagonal of Q^T Q
-    const int n2 = g.n2, np = g.np;
-    std::vector<double> Q((size_t)n2 * np), Qd((size_t)np * n2);
-    for (int i = 0; i < p; ++i)
-      for (int j = 0; j < p; ++j)
-        for (int k = 0; k < np; ++k) Q[(size_t)(i * p + j) * np + k] = cheb(R.ba[k], R.node[i]) * cheb(R.bb[k], R.node[j]);
-    for (int k = 0; k < np; ++k) {
-      double dkk = 0;
-      for (int i = 0; i < n2; ++i) dkk += Q[(size_t)i * np + k] * Q[(size_t)i * np + k];
-      for (int k2 = 0; k2 < np; ++k2) {
-        if (k2 == k) continue;
-        double off = 0;
-        for (int i = 0; i < n2; ++i) off += Q[(size_t)i * np + k] * Q[(size_t)i * np + k2];
-        if (std::fabs(off) > 1e-12 * dkk) throw LsError(LS_ENOTSUP, "interpolation matrix without orthogonal columns");
-      }
-      for (int i = 0; i < n2; ++i) Qd[(size_t)k * n2 + i] = Q[(size_t)i * np + k] / dkk;
-    }
-    P->ref.alloc(sizeof(R));
-    lsi::hip_check(hipMemcpy(P->ref.p, &R, sizeof(R), hipMemcpyHostToDevice), "panels ref");
     P->far_x.upload(fx);
     P->far_w.upload(fw);
-    P->qdag.upload(Qd);
     std::vector<double> qv(q, q + N);
     P->q.upload(qv);
     const size_t noff = (size_t)w2 * w2;
@@ -173,6 +186,89 @@ ls_status ls_panels_setup(int nside, double L, int p, double kappa, const double
   }
 }
 
+ls_status ls_panels_setup_leaves(int nboxes, const double* boxes, int p, double kappa, const double* q, int sign,
+                                 ls_panels** out) {
+  try {
+    if (!out) throw LsError(LS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nboxes < 1 || !boxes) throw LsError(LS_EINVAL, "nboxes must be >= 1 and boxes not NULL");
+    if (p < 1 || p > lsp::kMaxP) throw LsError(LS_EINVAL, "p must be in 1..8");
+    if (!(kappa > 0) || !std::isfinite(kappa)) throw LsError(LS_EINVAL, "kappa must be positive and finite");
+    if (sign != 1 && sign != -1) throw LsError(LS_EINVAL, "sign must be +1 or -1");
+    if (!q) throw LsError(LS_EINVAL, "q is NULL");
+    const int64_t N = (int64_t)nboxes * p * p;
+    if (N > lsp::kDenseMaxN) throw LsError(LS_ENOTSUP, "more unknowns than the dense operator takes (20000)");
+    for (int B = 0; B < nboxes; ++B)
+      if (!std::isfinite(boxes[3 * B]) || !std::isfinite(boxes[3 * B + 1]) || !(boxes[3 * B + 2] > 0) ||
+          !std::isfinite(boxes[3 * B + 2]))
+        throw LsError(LS_EINVAL, "box centres must be finite and half-widths positive");
+    for (int64_t i = 0; i < N; ++i)
+      if (!std::isfinite(q[i])) throw LsError(LS_EINVAL, "q has a non-finite value");
+    auto P = std::make_unique<ls_panels>();
+    lsp::PanelGeom& g = P->g;
+    g.nside = 0;
+    g.p = p;
+    g.np = p * (p + 1) / 2;
+    g.n2 = p * p;
+    g.kappa = kappa;
+    g.beta = 0;
+    g.nfar = 0;
+    P->sign = sign;
+    P->N = N;
+    P->dense = true;
+    P->nboxes = nboxes;
+    const lsp::PanelRef R = reference_data(P.get());
+    // per box: its far rule (one Gauss-Legendre rule per distinct point count) and its nodes
+    std::vector<double> fx, fw, bx((size_t)5 * nboxes);
+    std::vector<double2> X((size_t)N);
+    std::vector<int> rule_n;
+    std::vector<size_t> rule_off;
+    for (int B = 0; B < nboxes; ++B) {
+      const double cx = boxes[3 * B], cy = boxes[3 * B + 1], be = boxes[3 * B + 2];
+      const int nf = std::max(16, (int)std::ceil(2.0 * kappa * be) + 12);
+      size_t r = 0;
+      while (r < rule_n.size() && rule_n[r] != nf) ++r;
+      if (r == rule_n.size()) {
+        std::vector<double> x1, w1;
+        gauss_legendre(nf, x1, w1);
+        rule_n.push_back(nf);
+        rule_off.push_back(fx.size());
+        fx.insert(fx.end(), x1.begin(), x1.end());
+        fw.insert(fw.end(), w1.begin(), w1.end());
+      }
+      g.nfar = std::max(g.nfar, nf);
+      bx[5 * B] = cx;
+      bx[5 * B + 1] = cy;
+      bx[5 * B + 2] = be;
+      bx[5 * B + 3] = (double)rule_off[r];
+      bx[5 * B + 4] = (double)nf;
+      for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j)
+          X[(size_t)B * g.n2 + i * p + j] = make_double2(cx + be * R.node[i], cy + be * R.node[j]);
+    }
+    P->far_x.upload(fx);
+    P->far_w.upload(fw);
+    P->boxes.upload(bx);
+    P->X.upload(X);
+    std::vector<double> qv(q, q + N);
+    P->q.upload(qv);
+    P->M.alloc((size_t)N * nboxes * g.np * 16);
+    P->V.alloc((size_t)N * N * 16);
+    hipStream_t s = nullptr;
+    lsp::launch_panel_moments_leaves(P->ref.as<lsp::PanelRef>(), p, g.np, kappa, P->boxes.as<double>(), nboxes,
+                                     P->X.as<double2>(), N, P->far_x.as<double>(), P->far_w.as<double>(),
+                                     P->M.as<double2>(), s);
+    lsi::hip_check(hipGetLastError(), "panel moments (leaves)");
+    lsp::launch_panel_dense_V(P->M.as<double2>(), P->qdag.as<double>(), nboxes, g.np, g.n2, P->V.as<double2>(), s);
+    lsi::hip_check(hipGetLastError(), "panel dense V");
+    lsi::hip_check(hipDeviceSynchronize(), "panels setup (leaves)");
+    *out = P.release();
+    return LS_OK;
+  } catch (const LsError& e) {
+    return lsi::fail(e);
+  }
+}
+
 ls_status ls_panels_apply(ls_panels* P, const void* x, void* y, int nrhs, int64_t ld, int op, void* stream) {
   try {
     check_vec(P, x, y, nrhs, ld);
@@ -181,9 +277,12 @@ ls_status ls_panels_apply(ls_panels* P, const void* x, void* y, int nrhs, int64_
     const double k2 = P->g.kappa * P->g.kappa;
     const double* q = op == 0 ? P->q.as<double>() : nullptr;
     const double alpha = op == 0 ? 1.0 : 0.0, coef = op == 0 ? P->sign * k2 : 1.0;
-    if (P->mfma && P->g.p <= lsp::kMfmaMaxP) {
+    if (P->dense) {
+      lsp::launch_panel_dense_apply(P->V.as<double2>(), P->N, q, (const double2*)x, ld, (double2*)y, ld, nrhs, alpha,
+                                    coef, (hipStream_t)stream);
+    } else if (P->mfma && P->g.p <= lsp::kMfmaMaxP) {
       const int nc = lsp::panel_chunks(P->g, nrhs);
-      const int64_t N = (int64_t)P->g.nside * P->g.nside * P->g.n2;
+      const int64_t N = P->N;
       P->part.ensure((size_t)nc * nrhs * N * 16);
       lsp::launch_panel_apply_mfma(P->g, P->T.as<double2>(), q, (const double2*)x, ld, (double2*)y, ld, nrhs, alpha,
                                    coef, P->part.as<double2>(), nc, (hipStream_t)stream);
@@ -211,7 +310,7 @@ ls_status ls_panels_solve(ls_panels* P, const void* f, void* psi, double tol, in
     if (f == psi) throw LsError(LS_EINVAL, "f and psi must not overlap");
     const double t0 = lsi::now_ms();
     hipStream_t s = (hipStream_t)stream;
-    const long long N = (long long)P->g.nside * P->g.nside * P->g.n2;
+    const long long N = P->N;
     const int m = restart;
     const int nch = (int)std::max(1LL, std::min(1024LL, (N + 4095) / 4096));
     P->kq.ensure((size_t)(m + 1) * N * 16);
@@ -248,7 +347,10 @@ ls_status ls_panels_solve(ls_panels* P, const void* f, void* psi, double tol, in
     };
     const double k2 = P->g.kappa * P->g.kappa;
     auto applyA = [&](const double2* in, double2* out) {
-      if (P->mfma && P->g.p <= lsp::kMfmaMaxP) {
+      if (P->dense) {
+        lsp::launch_panel_dense_apply(P->V.as<double2>(), N, P->q.as<double>(), in, N, out, N, 1, 1.0, P->sign * k2,
+                                      s);
+      } else if (P->mfma && P->g.p <= lsp::kMfmaMaxP) {
         const int nc = lsp::panel_chunks(P->g, 1);
         P->part.ensure((size_t)nc * N * 16);
         lsp::launch_panel_apply_mfma(P->g, P->T.as<double2>(), P->q.as<double>(), in, N, out, N, 1, 1.0,
@@ -355,6 +457,7 @@ ls_status ls_panels_solve(ls_panels* P, const void* f, void* psi, double tol, in
 ls_status ls_panels_moments(const ls_panels* P, int dx, int dy, double* out) {
   try {
     if (!P || !out) throw LsError(LS_EINVAL, "handle or out is NULL");
+    if (P->dense) throw LsError(LS_ENOTSUP, "moment table rows exist for uniform trees only");
     const int n = P->g.nside;
     if (dx <= -n || dx >= n || dy <= -n || dy >= n) throw LsError(LS_EINVAL, "box offset outside the grid");
     const size_t row = (size_t)P->g.n2 * P->g.np;
@@ -371,7 +474,7 @@ ls_status ls_panels_info(const ls_panels* P, int64_t* n_unknowns, int* np, int* 
     lsi::g_last_error = "bad arguments";
     return LS_EINVAL;
   }
-  *n_unknowns = (int64_t)P->g.nside * P->g.nside * P->g.n2;
+  *n_unknowns = P->N;
   *np = P->g.np;
   *nfar = P->g.nfar;
   return LS_OK;

@@ -133,12 +133,14 @@ def lib():
         getattr(L, name).restype = C.c_int
     L.ls_panels_setup.argtypes = [ci, cd, ci, cd, vp, ci, C.POINTER(vp)]
     L.ls_panels_apply.argtypes = [vp, vp, vp, ci, i64, ci, vp]
+    L.ls_panels_setup_leaves.argtypes = [ci, vp, ci, cd, vp, ci, C.POINTER(vp)]
     L.ls_panels_moments.argtypes = [vp, ci, ci, vp]
     L.ls_panels_solve.argtypes = [vp, vp, vp, cd, ci, ci, C.POINTER(_Info), vp]
     L.ls_panels_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.ls_panels_destroy.argtypes = [vp]
     L.ls_panels_destroy.restype = None
-    for name in ("ls_panels_setup", "ls_panels_apply", "ls_panels_moments", "ls_panels_info", "ls_panels_solve"):
+    for name in ("ls_panels_setup", "ls_panels_apply", "ls_panels_moments", "ls_panels_info", "ls_panels_solve",
+                 "ls_panels_setup_leaves"):
         getattr(L, name).restype = C.c_int
     for name in ("ls_setup", "ls_matvec", "ls_apply_V", "ls_precond_apply", "ls_precond_apply_noalloc",
                  "ls_rhs_planewave", "ls_solve",
@@ -503,13 +505,21 @@ class Panels:
     """Handle of an ls_panels_setup()-built high-order panel operator on a uniform tree (nside x
     nside boxes of [-L, L]^2, p x p Chebyshev nodes per box; unknowns box-major, node-minor)."""
 
-    def __init__(self, nside: int, L: float, p: int, kappa: float, q: np.ndarray, sign: int = -1):
+    def __init__(self, nside: int, L: float, p: int, kappa: float, q: np.ndarray, sign: int = -1, boxes=None):
+        """boxes (optional, array nboxes x 3 of centre x, centre y, half-width): the leaves of any
+        tree (ls_panels_setup_leaves); nside and L are then ignored"""
         q = np.ascontiguousarray(q, dtype=np.float64)
-        if q.shape != (nside * nside * p * p,):
+        nb = nside * nside if boxes is None else len(boxes)
+        if q.shape != (nb * p * p,):
             raise ValueError("q must hold one value per node")
         self._h = C.c_void_p()
-        _check(lib().ls_panels_setup(int(nside), float(L), int(p), float(kappa), q.ctypes.data, int(sign),
-                                     C.byref(self._h)))
+        if boxes is None:
+            _check(lib().ls_panels_setup(int(nside), float(L), int(p), float(kappa), q.ctypes.data, int(sign),
+                                         C.byref(self._h)))
+        else:
+            bx = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 3)
+            _check(lib().ls_panels_setup_leaves(len(bx), bx.ctypes.data, int(p), float(kappa), q.ctypes.data,
+                                                int(sign), C.byref(self._h)))
         n, npb, nf = C.c_int64(), C.c_int(), C.c_int()
         _check(lib().ls_panels_info(self._h, C.byref(n), C.byref(npb), C.byref(nf)))
         self.N, self.np, self.nfar = n.value, npb.value, nf.value

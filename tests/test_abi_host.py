@@ -176,3 +176,20 @@ def test_panels_reject_invalid_inputs():
     assert L.ls_panels_moments(None, 0, 0, x.ctypes.data) == ls.LS_EINVAL
     n, npb, nf = C.c_int64(), C.c_int(), C.c_int()
     assert L.ls_panels_info(None, C.byref(n), C.byref(npb), C.byref(nf)) == ls.LS_EINVAL
+
+
+def test_panels_leaves_reject_invalid_inputs():
+    L = ls.lib()
+    h = C.c_void_p()
+    q = np.zeros(2 * 9)
+    good = np.array([[-0.5, 0.0, 0.5], [0.5, 0.0, 0.5]])
+    bad = good.copy()
+    bad[1, 2] = -0.5
+    assert L.ls_panels_setup_leaves(0, good.ctypes.data, 3, 10.0, q.ctypes.data, -1, C.byref(h)) == ls.LS_EINVAL
+    assert L.ls_panels_setup_leaves(2, bad.ctypes.data, 3, 10.0, q.ctypes.data, -1, C.byref(h)) == ls.LS_EINVAL
+    assert L.ls_panels_setup_leaves(2, good.ctypes.data, 9, 10.0, q.ctypes.data, -1, C.byref(h)) == ls.LS_EINVAL
+    assert L.ls_panels_setup_leaves(2, good.ctypes.data, 3, 10.0, None, -1, C.byref(h)) == ls.LS_EINVAL
+    many = np.tile(good, (2000, 1))
+    assert L.ls_panels_setup_leaves(4000, many.ctypes.data, 3, 10.0, np.zeros(36000).ctypes.data, -1,
+                                    C.byref(h)) == ls.LS_ENOTSUP
+    assert not h

@@ -170,3 +170,62 @@ def test_device_solution_converges_to_the_radial_reference():
         say("p", p, info, "error vs radial reference", errs[-1])
     assert errs[0] > 5 * errs[1] > 5 * 5 * errs[2]
     assert errs[2] < 5e-3
+
+
+def _leaves_array(leaves):
+    return np.array([[b.cx, b.cy, b.beta] for b in leaves])
+
+
+def _compact_bump(x, y, cx=0.3, cy=-0.2, R=0.35):
+    r = np.hypot(x - cx, y - cy) / R
+    with np.errstate(divide="ignore", over="ignore"):
+        return np.where(r < 1, 1.5 * np.exp(1.0 - 1.0 / np.maximum(1.0 - r * r, 1e-300)), 0.0)
+
+
+def test_adaptive_tree_operator_and_solve_match_dense_oracle():
+    # the adaptive, level-restricted quadtree of Section 2.1 (built by the oracle from q and the
+    # incident field; a contrast of compact support, so boxes away from it are resolved early),
+    # its leaves handed to the device: moments per (node, box) with the box's own far rule, the
+    # dense operator, and GMRES on it
+    kappa, p = 5.0, 4
+    q_fn = _compact_bump
+    u_fn = lambda x, y: np.exp(1j * kappa * x)
+    leaves = panels.build_tree(q_fn, u_fn, p, 3e-2, kappa, T=16.0, max_level=4)
+    levels = sorted({b.level for b in leaves})
+    X = panels.all_nodes(leaves, p)
+    q = q_fn(X[:, 0], X[:, 1])
+    say("adaptive tree:", len(leaves), "leaves on levels", levels)
+    assert len(levels) > 1
+    P = ls.Panels(0, 1.0, p, kappa, q, boxes=_leaves_array(leaves))
+    assert P.N == len(X)
+    A = panels.dense_A(leaves, p, kappa, q_fn)
+    V = panels.dense_V(leaves, p, kappa)
+    rng = np.random.default_rng(7)
+    Xr = rng.standard_normal((2, P.N)) + 1j * rng.standard_normal((2, P.N))
+    Y = P.apply(torch.from_numpy(Xr).cuda(), op=0).cpu().numpy()
+    U = P.apply(torch.from_numpy(Xr).cuda(), op=1).cpu().numpy()
+    for j in range(2):
+        assert np.linalg.norm(Y[j] - A @ Xr[j]) <= 1e-10 * np.linalg.norm(A @ Xr[j])
+        assert np.linalg.norm(U[j] - V @ Xr[j]) <= 1e-10 * np.linalg.norm(V @ Xr[j])
+    f = panels.rhs_planewave(leaves, p, kappa, q_fn)
+    psi, info = P.solve(torch.from_numpy(f).cuda(), tol=1e-12, restart=50)
+    ref = np.linalg.solve(A, f)
+    say("adaptive solve", info)
+    assert info["status"] == "CONVERGED"
+    assert np.linalg.norm(psi.cpu().numpy() - ref) <= 1e-9 * np.linalg.norm(ref)
+    with pytest.raises(ls.LsError):
+        P.moments(0, 0)           # table rows exist for uniform trees only
+    P.close()
+
+
+def test_uniform_leaves_equal_the_uniform_tables():
+    nside, p, kappa = 4, 4, 15.0
+    boxes = panels.uniform_tree(nside)
+    q = node_q(boxes, p)
+    U = ls.Panels(nside, 1.0, p, kappa, q)
+    G = ls.Panels(0, 1.0, p, kappa, q, boxes=_leaves_array(boxes))
+    x = torch.from_numpy(np.random.default_rng(3).standard_normal(U.N) + 0j).cuda()
+    yu, yg = U.apply(x).cpu().numpy(), G.apply(x).cpu().numpy()
+    assert np.abs(yu - yg).max() <= 1e-12 * np.abs(yu).max()
+    U.close()
+    G.close()
