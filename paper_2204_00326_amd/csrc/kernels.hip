@@ -993,9 +993,16 @@ __global__ __launch_bounds__(256) void k_tsdot(const typename V2<T>::type* __res
   __shared__ double lds[4][2 * G];
   const int ch = blockIdx.x, rhs = blockIdx.z;
   if (skip && skip[rhs] != 0) return;  // uniform per block
-  if (jdev) ncols = *jdev + 1;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int gpb = 4 / wpg;                           // column groups per block
+  const int gpb = 4 / wpg;  // column groups per block (the launch's layout)
+  if (jdev) {
+    // a column count known only on the device (the launch is laid out for the most columns):
+    // the waves of a block split among the groups that hold columns, the rest take row parts
+    ncols = *jdev + 1;
+    const int active = min(gpb, (ncols + G - 1) / G - (int)blockIdx.y * gpb);
+    if (active <= 0) return;  // uniform per block
+    wpg = active > 2 ? 1 : (active == 2 ? 2 : 4);
+  }
   const int grp = blockIdx.y * gpb + w / wpg;        // this wave's column group
   const int rp = w % wpg;                            // this wave's row part
   const int c0 = grp * G;
