@@ -13,8 +13,10 @@ solve as the paper's totals, and the same solve with a rank-128 preconditioner b
 
 Also reported (outside the timed region): the same solve in FP64 (warmed up and timed over the
 same number of steps), DAFMM matvec/s for the FP64 and FP32 operators (median of 30 applies)
-with their roofline, the error of the mixed solution against the FP64 one, a block of 64 plane
-waves on Gaussian bumps solved as one right-hand-side block (right-hand-side columns/s), the
+with their roofline (one column, and a block of 64 columns against the matrix-core peak), the
+error of the mixed solution against the FP64 one, a block of 64 plane waves on Gaussian bumps
+solved as one right-hand-side block (right-hand-side columns/s), the high-order panel operator
+(p = 4) on a uniform tree (table setup and the dense product against the FP64 matrix-core peak), the
 roofline of the dominant kernel class (timed with HIP events on the launch stream during the
 timed region), and the CPU oracle on the host cores: its FFT product of A timed, its GMRES run
 for a bounded time, and the residual of the GPU solutions under the oracle operator.
