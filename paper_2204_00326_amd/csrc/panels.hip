@@ -307,8 +307,17 @@ __global__ __launch_bounds__(256) void k_panel_apply_mfma(PanelGeom g, const dou
   const int tile = blockIdx.x, chunk = blockIdx.y, rhs = blockIdx.z;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n2 = g.n2, nside = g.nside, nb = nside * nside, w2 = 2 * nside - 1;
-  const int noff = w2 * w2;
-  const int d0 = (int)((long long)noff * chunk / nchunks), d1 = (int)((long long)noff * (chunk + 1) / nchunks);
+  // the offsets that pair some box of the tile with a box of the grid: a rectangle of
+  // (x extent + nside) x (y extent + nside) offsets around the tile's bounding box; chunk c of
+  // the launch takes its share of them
+  const int A0 = tile * 16, A1 = min(A0 + 15, nb - 1);
+  const int x0 = A0 / nside, x1 = A1 / nside;
+  const int y0 = x0 == x1 ? A0 % nside : 0, y1 = x0 == x1 ? A1 % nside : nside - 1;
+  const int wx = x1 - x0 + nside, wy = y1 - y0 + nside;
+  const int dxlo = x0 - (nside - 1), dylo = y0 - (nside - 1);
+  const int nrect = wx * wy;
+  const int d0 = (int)((long long)nrect * chunk / nchunks), d1 = (int)((long long)nrect * (chunk + 1) / nchunks);
+  auto offset = [&](int e) { return (dxlo + e / wy + nside - 1) * w2 + (dylo + e % wy + nside - 1); };
   const int j = lane & 15, kq = lane >> 4;
   const int A = tile * 16 + j;
   const bool aok = A < nb;
@@ -341,10 +350,10 @@ __global__ __launch_bounds__(256) void k_panel_apply_mfma(PanelGeom g, const dou
   };
   double2 ta[RT][KB], xa[KB], tb[RT][KB], xb[KB];
   int d = d0 + wave;
-  bool live = d < d1 ? load(d, ta, xa) : false;
+  bool live = d < d1 ? load(offset(d), ta, xa) : false;
   while (d < d1) {
     const int dn = d + 4;
-    const bool nlive = dn < d1 ? load(dn, tb, xb) : false;
+    const bool nlive = dn < d1 ? load(offset(dn), tb, xb) : false;
     if (live) {
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb)
@@ -410,7 +419,8 @@ __global__ __launch_bounds__(256) void k_panel_reduce(const double2* __restrict_
 int panel_chunks(const PanelGeom& g, int nrhs) {
   const int nb = g.nside * g.nside, ntiles = (nb + 15) / 16, w2 = 2 * g.nside - 1;
   const long long N = (long long)nb * g.n2;
-  int c = std::max(1, std::min(w2 * w2 / 4, (2048 + ntiles - 1) / ntiles));
+  const int rect = (g.nside + 15) * g.nside;  // offsets per tile (a tile within one row of boxes)
+  int c = std::max(1, std::min(rect / 4, (2048 + ntiles - 1) / ntiles));
   // partial planes of at most 512 MB
   while (c > 1 && (long long)c * nrhs * N * 16 > (512LL << 20)) c /= 2;
   return c;
