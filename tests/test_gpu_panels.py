@@ -229,3 +229,19 @@ def test_uniform_leaves_equal_the_uniform_tables():
     assert np.abs(yu - yg).max() <= 1e-12 * np.abs(yu).max()
     U.close()
     G.close()
+
+
+def test_solve_reports_maxit_and_nan():
+    # failure statuses forced from the host: too few products for the tolerance, and a
+    # non-finite right-hand side (no kernel faults or waits on them)
+    nside, p, kappa = 4, 3, 10.0
+    boxes = panels.uniform_tree(nside)
+    P = ls.Panels(nside, 1.0, p, kappa, node_q(boxes, p))
+    f = torch.from_numpy(panels.rhs_planewave(boxes, p, kappa, qfun)).cuda()
+    _, info = P.solve(f, tol=1e-12, restart=3, maxit=3)
+    assert info["status"] == "MAXIT" and info["iters"] == 3 and info["relres"] > 1e-12
+    fn = f.clone()
+    fn[5] = float("nan")
+    _, info = P.solve(fn)
+    assert info["status"] == "NAN" and info["iters"] == 0
+    P.close()
