@@ -80,7 +80,9 @@ def cpu_baseline(n, kappa, q, psis, seconds=20.0):
     _, its, hist = og.gmres(A, f, 1e-8, restart=200, maxit=nit)
     t_run = time.perf_counter() - t1
     r_end = hist[-1]
+    small = cpu_small_configs(cores)
     return {
+        "small_configs": small,
         "value": round(1.0 / t_mv, 3),
         "unit": "matvec/s",
         "cores": cores,
@@ -94,6 +96,57 @@ def cpu_baseline(n, kappa, q, psis, seconds=20.0):
                   "converged_to_1e-8": bool(r_end <= 1e-8)},
         "oracle_relres": oracle_relres,
     }
+
+
+def cpu_small_configs(cores, seconds=10.0):
+    """The oracle on the two smaller configurations: the 32^2 Gaussian problem (kappa 10: the
+    dense 1024 x 1024 product, the FFT product, unpreconditioned GMRES(200) to 1e-10) and the
+    256^2 problem with 8 Gaussian bumps (seed 0, kappa 40: the FFT product, unpreconditioned
+    GMRES(200) towards 1e-8 for a bounded number of iterations sized to about `seconds`)."""
+    import numpy as np
+
+    from oracle import gmres as og
+    from oracle import lsop
+    from paper_2204_00326_amd import inputs
+
+    def med(fn, reps):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    out = {}
+    pb = inputs.problem_gaussian_small()
+    Ad = lsop.dense_A(pb.n, pb.L, pb.kappa, pb.q)
+    Vop = lsop.FFTApplyV(pb.n, pb.L, pb.kappa, workers=cores)
+    x = np.random.default_rng(4).standard_normal(pb.n ** 2) + 0j
+    f = lsop.rhs_planewave(pb.n, pb.L, pb.kappa, pb.q, 0.0)
+    t0 = time.perf_counter()
+    _, its, hist = og.gmres(lambda v: Ad @ v, f, 1e-10, restart=200)
+    out[pb.name] = {"dense_matvec_ms": round(1e3 * med(lambda: Ad @ x, 20), 4),
+                    "fft_matvec_ms": round(1e3 * med(lambda: lsop.apply_A(Vop, x, pb.q, pb.kappa), 20), 4),
+                    "gmres_to_1e-10": {"iters": its, "seconds": round(time.perf_counter() - t0, 3),
+                                       "relres": hist[-1]}}
+    pb = inputs.problem_bumps(256, 40.0, 0, count=8)
+    Vop = lsop.FFTApplyV(pb.n, pb.L, pb.kappa, workers=cores)
+    A = lambda v: lsop.apply_A(Vop, v, pb.q, pb.kappa)
+    x = np.random.default_rng(5).standard_normal(pb.n ** 2) + 0j
+    f = lsop.rhs_planewave(pb.n, pb.L, pb.kappa, pb.q, 0.0)
+    t_mv = med(lambda: A(x), 5)
+    n1 = 20
+    t0 = time.perf_counter()
+    og.gmres(A, f, 1e-8, restart=200, maxit=n1)
+    t1 = time.perf_counter() - t0
+    nit = int(max(n1, min(2000, n1 * math.sqrt(max(seconds, t1) / t1))))
+    t0 = time.perf_counter()
+    _, its, hist = og.gmres(A, f, 1e-8, restart=200, maxit=nit)
+    out[pb.name] = {"fft_matvec_ms": round(1e3 * t_mv, 3),
+                    "gmres_to_1e-8": {"iters": its, "seconds": round(time.perf_counter() - t0, 2),
+                                      "relres_reached": hist[-1], "converged": bool(hist[-1] <= 1e-8)}}
+    return out
 
 
 COPY_BYTES = 256 << 20   # calibration copy: bytes read and bytes written
