@@ -495,8 +495,8 @@ def main():
         pmc_summary(*args.pmc_summary, workload)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the batch axes shard without exchange; "
-              "see the multi-GPU paragraph of the design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only (the batch axes, right-hand sides and queued problems, "
+              "shard across GPUs without exchange); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -44,7 +44,7 @@ typedef enum {
   LS_EINVAL = -1,  /* invalid argument (message in ls_last_error) */
   LS_ENOMEM = -2,  /* host or device allocation failed */
   LS_EDEVICE = -3, /* a HIP runtime call failed */
-  LS_ENOTSUP = -4  /* input valid but outside what this build supports */
+  LS_ENOTSUP = -4  /* input valid but outside what the library supports */
 } ls_status;
 
 typedef enum {
