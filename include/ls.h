@@ -282,15 +282,15 @@ ls_status ls_solve_queue(ls_problem* const* probs, int nprob, const void* const*
                          int prec, int nworkers, int graph_iters, ls_solve_info* info);
 
 /* Launch-shape autotuner: times the Arnoldi reductions (dot products of 32 basis vectors and a
- * norm) for 128/256/512/1024/2048 rows per workgroup chunk, and the HODLR preconditioner apply
- * for at most 64/128/256/512/1024 rows per level-reduction chunk, on this problem's sizes, and
+ * norm) for 256/512/1024/2048/4096 rows per workgroup chunk, and the HODLR preconditioner apply
+ * for at most 128/256/512/1024/2048 rows per level-reduction chunk, on this problem's sizes, and
  * keeps the fastest of each for all later calls on P.  out (may be NULL) receives the choices
  * and the measured times.  Synchronous on `stream`. */
 typedef struct {
   int gs_rows;       /* chosen rows per chunk, Arnoldi reductions */
   int hodlr_rows;    /* chosen max rows per chunk, HODLR level reductions */
-  double gs_us[5];   /* microseconds per candidate 128, 256, 512, 1024, 2048 */
-  double pc_us[5];   /* microseconds per candidate 64, 128, 256, 512, 1024 (0 without HODLR) */
+  double gs_us[5];   /* microseconds per candidate 256, 512, 1024, 2048, 4096 */
+  double pc_us[5];   /* microseconds per candidate 128, 256, 512, 1024, 2048 (0 without HODLR) */
 } ls_tune_info;
 ls_status ls_autotune(ls_problem* P, ls_tune_info* out, void* stream);
 

@@ -11,8 +11,8 @@ extern "C" {
 // and keeps the fastest (rows per workgroup chunk of the Arnoldi dot products and norms; max
 // rows per chunk of the HODLR level reductions).  Small problems want short chunks (more
 // workgroups), large ones long chunks (fewer partial sums).
-static const int kGsRows[5] = {128, 256, 512, 1024, 2048};
-static const int kPcRows[5] = {64, 128, 256, 512, 1024};
+static const int kGsRows[5] = {256, 512, 1024, 2048, 4096};
+static const int kPcRows[5] = {128, 256, 512, 1024, 2048};
 
 static void autotune_impl(ls_problem* P, ls_tune_info* out, hipStream_t s) {
   const long long N = P->N;
