@@ -16,7 +16,8 @@ same number of steps), DAFMM matvec/s for the FP64 and FP32 operators (median of
 with their roofline (one column, and a block of 64 columns against the matrix-core peak), the
 error of the mixed solution against the FP64 one, a block of 64 plane waves on Gaussian bumps
 solved as one right-hand-side block (right-hand-side columns/s), the high-order panel operator
-(p = 4) on a uniform tree (table setup and the dense product against the FP64 matrix-core peak), the
+(p = 4) on a uniform tree (table setup, the dense product against the FP64 matrix-core peak, a
+plane-wave solve without and with its HODLR preconditioner), the
 roofline of the dominant kernel class (timed with HIP events on the launch stream during the
 timed region), and the CPU oracle on the host cores: its FFT product of A timed, its GMRES run
 for a bounded time, and the residual of the GPU solutions under the oracle operator.
@@ -299,7 +300,8 @@ def panels_bench(args, torch, np, ls):
     """High-order panels (p = 4 Chebyshev nodes per box side) on a uniform tree of args.panels^2
     boxes of [-1, 1]^2, kappa / 2, the disc contrast at the nodes: table setup time and the dense
     product A x (event-timed median of 20; FP64 matrix cores), against the FP64 MFMA peak (8
-    flops per complex multiply-add of the nb^2 p^4 operator entries)."""
+    flops per complex multiply-add of the nb^2 p^4 operator entries); then a plane-wave solve to
+    1e-8 without and with the panel system's HODLR preconditioner (rank args.panels_rank)."""
     nside, p, kappa = args.panels, 4, args.kappa / 2
     beta = 1.0 / nside
     c = -1.0 + (2 * np.arange(nside) + 1) * beta
@@ -329,6 +331,24 @@ def panels_bench(args, torch, np, ls):
            "setup_s": round(t_setup, 3), "apply_us": round(us, 1), "far_rule_points": Pp.nfar,
            "roofline": {"bound": "mfma", "achieved": round(flops / (us * 1e-6) / 1e12, 3), "peak": 78.6,
                         "unit": "TFLOP/s", "frac": round(flops / (us * 1e-6) / 1e12 / 78.6, 4)}}
+    # plane-wave solve to 1e-8 (theta = 0): unpreconditioned GMRES, then right-preconditioned by
+    # the panel system's HODLR approximation (fixed rank)
+    u = np.exp(1j * kappa * X[:, 0])
+    f = torch.from_numpy(kappa ** 2 * q * u).cuda()
+    solves = {}
+    if args.panels_rank > 0:
+        for name in ("none", "hodlr"):
+            if name == "hodlr":
+                pinfo = Pp.precondition(args.panels_rank)
+            Pp.solve(f, tol=1e-8, restart=100, maxit=3000)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info = Pp.solve(f, tol=1e-8, restart=100, maxit=3000)
+            torch.cuda.synchronize()
+            solves[name] = {"ms": round(1e3 * (time.perf_counter() - t1), 2), "iters": info["iters"],
+                            "relres": info["relres"], "status": info["status"]}
+        solves["hodlr_factors"] = {k: (round(v, 2) if isinstance(v, float) else v) for k, v in pinfo.items()}
+        out["solve_1e-8"] = solves
     log("panels", out)
     Pp.close()
     return out
@@ -481,6 +501,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--panels", type=int, default=32,
                     help="also time the high-order panel operator on this many boxes per side (0: skip)")
+    ap.add_argument("--panels-rank", type=int, default=64,
+                    help="rank of the panel system's HODLR preconditioner for the panel solves (0: no solves)")
     ap.add_argument("--block-rhs", type=int, default=64,
                     help="also solve this many plane waves on Gaussian bumps as one block (0: skip)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CMD_FETCH", "CMD_WRITE"),

@@ -452,8 +452,26 @@ ls_status ls_panels_setup_leaves(int nboxes, const double* boxes, int p, double 
  * device complex128, nrhs columns of leading dimension ld >= N, not overlapping; asynchronous on
  * stream (NULL: the default stream). */
 ls_status ls_panels_apply(ls_panels* P, const void* x, void* y, int nrhs, int64_t ld, int op, void* stream);
+/* HODLR preconditioner of the panel system (Section 6, on the discretisation of Section 2.2):
+ * unknowns reordered by boxes in Morton order (the bits of the box's y index at the even, those
+ * of its x index at the odd positions of the code), nodes inside a box unchanged; leaves of 4^j
+ * whole boxes with at most 64 unknowns; a binary tree that halves the index range; every
+ * off-diagonal block compressed by partially pivoted ACA at rank min(rank, half the node);
+ * Sherman-Morrison-Woodbury per node.  Factors built on the host (ACA, leaf inverses) and the
+ * device (Y, cores); synchronous.  rank <= 0 drops the factors.  Errors: LS_EINVAL (NULL handle,
+ * rank > 256, a singular leaf block or core), LS_ENOTSUP (leaves of a general tree, nside not a
+ * power of two), LS_ENOMEM / LS_EDEVICE.  Once built, ls_panels_solve is right-preconditioned. */
+ls_status ls_panels_precond_setup(ls_panels* P, int rank);
+/* z = A~^-1 r.  r, z: device complex128, nrhs columns of leading dimension ld >= N, box-major
+ * order (r and z may be the same buffer); asynchronous on stream.  LS_EINVAL without factors. */
+ls_status ls_panels_precond_apply(ls_panels* P, const void* r, void* z, int nrhs, int64_t ld, void* stream);
+/* The preconditioner's rank cap, leaf size, binary levels, the mean and largest rank the ACA
+ * reached over the off-diagonal blocks and the setup time (all zero without factors). */
+ls_status ls_panels_precond_info(const ls_panels* P, int* rank, int* leaf, int* levels, double* mean_rank,
+                                 int* max_rank, double* setup_ms);
 /* psi = A^-1 f by restarted GMRES(restart) from psi = 0 (classical Gram-Schmidt with one
- * reorthogonalisation, no preconditioner), stopping when the true ||f - A psi|| / ||f|| <= tol
+ * reorthogonalisation; right-preconditioned by the HODLR factors of ls_panels_precond_setup when
+ * they exist, else unpreconditioned), stopping when the true ||f - A psi|| / ||f|| <= tol
  * (recomputed at every restart) or after maxit products.  f, psi: device complex128 (N), not
  * overlapping.  info: host (iters, relres, status LS_CONVERGED / LS_MAXIT / LS_NAN, n_refine =
  * the GMRES cycles, t_solve_ms).  Synchronous. */

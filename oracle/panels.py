@@ -315,3 +315,26 @@ def interpolate(boxes: list[Box], p: int, psi: np.ndarray, pts: np.ndarray) -> n
             Bv = basis_values(p, (pts[inside, 0] - b.cx) / b.beta, (pts[inside, 1] - b.cy) / b.beta)
             out[inside] = Bv @ c
     return out
+
+
+# ---------------------------------------------------------------------------------------------
+# HODLR order of a uniform tree's unknowns (Section 6 applied to the panel system)
+# ---------------------------------------------------------------------------------------------
+def hodlr_order(nside: int, p: int) -> np.ndarray:
+    """perm[t] = box-major index of the unknown at HODLR position t: boxes in Morton order (as
+    the cell-centred grid's leaves), the p^2 nodes of a box in their own order."""
+    from .hodlr import morton_permutation
+    order = morton_permutation(nside, 1)
+    n2 = p * p
+    return (order[:, None] * n2 + np.arange(n2)[None, :]).ravel()
+
+
+def hodlr_leaf(nside: int, p: int) -> int:
+    """Leaf size of the panel HODLR: 4^j whole boxes, the largest such group of at most 64
+    unknowns (a reading: leaves of about the cell-centred grid's size)."""
+    n2 = p * p
+    lb = 1
+    while lb * 4 * n2 <= 64 and lb * 4 <= nside * nside:
+        lb *= 4
+    return lb * n2
+

@@ -500,9 +500,9 @@ __global__ __launch_bounds__(256) void k_panel_update(double2* __restrict__ w, c
 }
 
 // y = alpha a + beta b (real coefficients)
-__global__ __launch_bounds__(256) void k_panel_combo(double2* __restrict__ y, const double2* __restrict__ a,
-                                                     double alpha, const double2* __restrict__ b, double beta,
-                                                     long long N) {
+// y may be a or b (each thread reads its entries before it writes)
+__global__ __launch_bounds__(256) void k_panel_combo(double2* y, const double2* a, double alpha, const double2* b,
+                                                     double beta, long long N) {
   const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
   if (k >= N) return;
   const double2 u = a[k], v = b[k];

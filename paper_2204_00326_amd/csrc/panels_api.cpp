@@ -8,7 +8,30 @@
 #include <vector>
 
 #include "api_internal.h"
+#include "hodlr_setup.h"
+#include "kernels.h"
 #include "panels.h"
+
+// HODLR approximation of the panel system on a uniform tree (Section 6 for the discretisation of
+// Section 2.2): unknowns in HODLR order (boxes in Morton order, nodes inside a box in their own
+// order), leaves of lp <= 64 unknowns (4^j whole boxes), a binary tree that halves the index range.
+// Factors as for the cell-centred grid: U, W per binary level (column c of block b at c * N + its
+// row / column offset), Y = (the levels below)^-1 U, SMW core inverses per node, leaf inverses
+// column-major.
+struct PanelHodlr {
+  int Lb = 0, lp = 0, nleaves = 0, r = 0;
+  std::vector<int> rank;           // per binary level: min(r, half of a node)
+  std::vector<long long> chunk;    // rows per chunk of the W^T z reductions
+  std::vector<int> nchunks, cpc;
+  lsi::DevBuf perm;                // perm[t] = box-major index of HODLR position t
+  lsi::DevBuf qh;                  // contrast in HODLR order
+  lsi::DevBuf Dinv, ident;
+  std::vector<lsi::DevBuf> Y, W, core;
+  lsi::DevBuf partial, svec, zh;
+  int64_t used_rank_sum = 0, blocks = 0;
+  int used_rank_max = 0;
+  double t_setup_ms = 0;
+};
 
 struct ls_panels {
   lsp::PanelGeom g{};
@@ -22,6 +45,8 @@ struct ls_panels {
   lsi::DevBuf part;  // partial planes of the matrix-core product (one stream at a time)
   bool mfma = true;
   lsi::DevBuf kq, kw, kr, kpart, kc;  // GMRES basis, work vectors, dot partials, coefficients
+  lsi::DevBuf kz;                     // preconditioned vector of the GMRES
+  std::unique_ptr<PanelHodlr> hod;    // HODLR preconditioner (uniform trees), when built
 };
 
 namespace {
@@ -128,6 +153,261 @@ lsp::PanelRef reference_data(ls_panels* P) {
   lsi::hip_check(hipMemcpy(P->ref.p, &R, sizeof(R), hipMemcpyHostToDevice), "panels ref");
   P->qdag.upload(Qd);
   return R;
+}
+
+// Morton (Z) order of the nside x nside boxes (nside a power of two): box k = ix * nside + iy has
+// the code with the bits of iy at the even and those of ix at the odd positions; boxes sorted by it.
+std::vector<int> morton_boxes(int nside) {
+  std::vector<std::pair<unsigned long long, int>> c;
+  c.reserve((size_t)nside * nside);
+  for (int ix = 0; ix < nside; ++ix)
+    for (int iy = 0; iy < nside; ++iy) {
+      unsigned long long code = 0;
+      for (int bit = 0; bit < 16; ++bit) {
+        code |= (unsigned long long)((iy >> bit) & 1) << (2 * bit);
+        code |= (unsigned long long)((ix >> bit) & 1) << (2 * bit + 1);
+      }
+      c.push_back({code, ix * nside + iy});
+    }
+  std::sort(c.begin(), c.end());
+  std::vector<int> out(c.size());
+  for (size_t i = 0; i < c.size(); ++i) out[i] = c[i].second;
+  return out;
+}
+
+// In-place inverse of the n x n row-major matrix a by Gauss-Jordan elimination with partial
+// pivoting; false when a pivot is exactly zero.
+bool invert_dense(std::vector<zd>& a, int n) {
+  std::vector<int> piv(n);
+  for (int k = 0; k < n; ++k) {
+    int pr = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::abs(a[(size_t)i * n + k]) > std::abs(a[(size_t)pr * n + k])) pr = i;
+    if (a[(size_t)pr * n + k] == zd(0)) return false;
+    piv[k] = pr;
+    if (pr != k)
+      for (int j = 0; j < n; ++j) std::swap(a[(size_t)k * n + j], a[(size_t)pr * n + j]);
+    const zd d = zd(1) / a[(size_t)k * n + k];
+    a[(size_t)k * n + k] = zd(1);
+    for (int j = 0; j < n; ++j) a[(size_t)k * n + j] *= d;
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const zd f = a[(size_t)i * n + k];
+      if (f == zd(0)) continue;
+      a[(size_t)i * n + k] = zd(0);
+      for (int j = 0; j < n; ++j) a[(size_t)i * n + j] -= f * a[(size_t)k * n + j];
+    }
+  }
+  // undo the row exchanges as column exchanges, last first
+  for (int k = n - 1; k >= 0; --k)
+    if (piv[k] != k)
+      for (int i = 0; i < n; ++i) std::swap(a[(size_t)i * n + k], a[(size_t)i * n + piv[k]]);
+  return true;
+}
+
+void phod_ws(PanelHodlr& H, long long N, int nrhs) {
+  size_t np = 1, ns = 1;
+  for (int l = 0; l < H.Lb; ++l) {
+    np = std::max(np, (size_t)H.nchunks[l] * H.rank[l]);
+    ns = std::max(ns, (size_t)(1LL << l) * 2 * H.rank[l]);
+  }
+  H.partial.ensure(np * nrhs * 16);
+  H.svec.ensure(ns * nrhs * 16);
+  (void)N;
+}
+
+// z = (the HODLR levels lstop .. Lb-1 and the leaves)^-1 b in HODLR order, nrhs columns of
+// leading dimension N; b and z may be the same buffer.
+void phod_apply(PanelHodlr& H, long long N, const double2* b, double2* z, int nrhs, int lstop, hipStream_t s) {
+  phod_ws(H, N, nrhs);
+  double2* partial = H.partial.as<double2>();
+  double2* svec = H.svec.as<double2>();
+  lsk::launch_leaf_apply(0, H.Dinv.p, H.ident.as<unsigned char>(), b, N, z, N, H.lp, H.nleaves, nrhs, s);
+  for (int l = H.Lb - 1; l >= lstop; --l) {
+    const int rl = H.rank[l];
+    if (rl == 0) continue;
+    lsk::launch_hodlr_dot(0, H.W[l].p, z, N, partial, N, rl, H.chunk[l], H.nchunks[l], nrhs, s);
+    lsk::launch_hodlr_core(0, H.core[l].p, partial, svec, rl, 1 << l, H.cpc[l], H.nchunks[l], true, nrhs, s);
+    lsk::launch_hodlr_update(0, H.Y[l].p, svec, z, N, N, rl, N >> l, 1 << l, nrhs, s);
+  }
+}
+
+// z = A~^-1 r in box-major order (ld per column), through the HODLR order
+void phod_apply_user(ls_panels* P, const double2* r, long long ldr, double2* z, long long ldz, int nrhs,
+                     hipStream_t s) {
+  PanelHodlr& H = *P->hod;
+  const long long N = P->N;
+  H.zh.ensure((size_t)N * nrhs * 16);
+  double2* zh = H.zh.as<double2>();
+  lsk::launch_permute(r, ldr, zh, N, H.perm.as<int>(), N, nrhs, false, s);
+  phod_apply(H, N, zh, zh, nrhs, 0, s);
+  lsk::launch_permute(zh, N, z, ldz, H.perm.as<int>(), N, nrhs, true, s);
+}
+
+// HODLR factors of A = I + sign kappa^2 diag(q) V on a uniform tree: the off-diagonal blocks by
+// partially pivoted ACA on the host at rank min(r, block side) (entries from the operator blocks
+// T), leaf inverses on the host, Y and the SMW cores on the device.
+void build_panel_hodlr(ls_panels* P, int r) {
+  const double t0 = lsi::now_ms();
+  const lsp::PanelGeom& g = P->g;
+  const int ns = g.nside, n2 = g.n2, w2 = 2 * ns - 1;
+  const long long N = P->N;
+  auto H = std::make_unique<PanelHodlr>();
+  H->r = r;
+  // leaves of 4^j whole boxes, at most 64 unknowns
+  int lb = 1;
+  while ((long long)lb * 4 * n2 <= 64 && (long long)lb * 4 <= (long long)ns * ns) lb *= 4;
+  H->lp = lb * n2;
+  H->nleaves = (int)(N / H->lp);
+  H->Lb = 0;
+  while ((1 << H->Lb) < H->nleaves) ++H->Lb;
+  const int lp = H->lp, Lb = H->Lb;
+  // HODLR order
+  const std::vector<int> mb = morton_boxes(ns);
+  std::vector<int> perm((size_t)N);
+  for (long long t = 0; t < N; ++t) perm[t] = mb[t / n2] * n2 + (int)(t % n2);
+  std::vector<double> qd((size_t)N), qh((size_t)N);
+  lsi::hip_check(hipMemcpy(qd.data(), P->q.p, (size_t)N * 8, hipMemcpyDeviceToHost), "q d2h");
+  for (long long t = 0; t < N; ++t) qh[t] = qd[perm[t]];
+  const size_t tsz = (size_t)w2 * w2 * n2 * n2;
+  std::vector<zd> T(tsz);
+  lsi::hip_check(hipMemcpy(T.data(), P->T.p, tsz * 16, hipMemcpyDeviceToHost), "operator blocks d2h");
+  const double coef = P->sign * g.kappa * g.kappa;
+  // entry (i, j) of A in HODLR order, i != j off the leaf blocks
+  std::vector<int> bx((size_t)N), by((size_t)N), nd((size_t)N);
+  for (long long t = 0; t < N; ++t) {
+    const int k = perm[t] / n2;
+    bx[t] = k / ns;
+    by[t] = k % ns;
+    nd[t] = perm[t] % n2;
+  }
+  auto Vij = [&](long long i, long long j) {
+    const long long d = (long long)(bx[i] - bx[j] + ns - 1) * w2 + (by[i] - by[j] + ns - 1);
+    return T[(size_t)((d * n2 + nd[i]) * n2 + nd[j])];
+  };
+  // leaf inverses (column-major per leaf); leaves without contrast are the identity
+  std::vector<zd> Dinv((size_t)H->nleaves * lp * lp);
+  std::vector<unsigned char> ident(H->nleaves, 0);
+  std::vector<char> bad(H->nleaves, 0);
+  lsi::parallel_for(H->nleaves, [&](int k) {
+    const long long o = (long long)k * lp;
+    bool any = false;
+    for (int i = 0; i < lp; ++i) any |= qh[o + i] != 0.0;
+    if (!any) {
+      ident[k] = 1;
+      return;
+    }
+    std::vector<zd> a((size_t)lp * lp);
+    for (int i = 0; i < lp; ++i)
+      for (int j = 0; j < lp; ++j)
+        a[(size_t)i * lp + j] = (i == j ? zd(1) : zd(0)) + coef * qh[o + i] * Vij(o + i, o + j);
+    if (!invert_dense(a, lp)) {
+      bad[k] = 1;
+      return;
+    }
+    zd* D = Dinv.data() + (size_t)k * lp * lp;
+    for (int i = 0; i < lp; ++i)
+      for (int j = 0; j < lp; ++j) D[(size_t)j * lp + i] = a[(size_t)i * lp + j];
+  });
+  for (char b : bad)
+    if (b) throw LsError(LS_EINVAL, "singular HODLR leaf block of the panel system");
+  // off-diagonal blocks of every binary level
+  H->rank.assign(Lb, 0);
+  for (int l = 0; l < Lb; ++l) H->rank[l] = (int)std::min<long long>(r, N >> (l + 1));
+  std::vector<std::vector<zd>> Uh(Lb), Wh(Lb);
+  for (int l = 0; l < Lb; ++l) {
+    Uh[l].assign((size_t)N * H->rank[l], zd(0));
+    Wh[l].assign((size_t)N * H->rank[l], zd(0));
+  }
+  std::vector<std::pair<int, int>> work;
+  for (int l = 0; l < Lb; ++l)
+    for (int b = 0; b < (1 << l); ++b) work.push_back({l, b});
+  std::vector<int> used(work.size() * 2, 0);
+  lsi::parallel_for((int)work.size() * 2, [&](int wi) {
+    const int l = work[wi / 2].first, b = work[wi / 2].second, which = wi % 2;
+    const long long sz = N >> l, lo = (long long)b * sz, mid = lo + sz / 2;
+    // which = 0: A[I1, I2] ~ U W^T (U rows in the first child); which = 1: A[I2, I1]
+    const long long r0 = which ? mid : lo, c0 = which ? lo : mid;
+    const int m = (int)(sz / 2), n = (int)(sz / 2);
+    std::vector<char> rz(m);
+    for (int i = 0; i < m; ++i) rz[i] = qh[r0 + i] == 0.0;
+    auto rowfn = [&](int i, zd* out) {
+      const double cq = coef * qh[r0 + i];
+      for (int j = 0; j < n; ++j) out[j] = cq * Vij(r0 + i, c0 + j);
+    };
+    auto colfn = [&](int j, zd* out) {
+      for (int i = 0; i < m; ++i) out[i] = coef * qh[r0 + i] * Vij(r0 + i, c0 + j);
+    };
+    ls::ACAResult R = ls::aca(m, n, H->rank[l], 0.0, &rz, rowfn, colfn);
+    const int k = (int)R.u.size();
+    used[wi] = k;
+    for (int c = 0; c < k; ++c) {
+      for (int i = 0; i < m; ++i) Uh[l][(size_t)c * N + r0 + i] = R.u[c][i];
+      for (int j = 0; j < n; ++j) Wh[l][(size_t)c * N + c0 + j] = R.v[c][j];
+    }
+  });
+  for (int k : used) {
+    H->used_rank_sum += k;
+    H->used_rank_max = std::max(H->used_rank_max, k);
+  }
+  H->blocks = (int64_t)used.size();
+  // device factors
+  H->perm.upload(perm);
+  H->qh.upload(qh);
+  H->Dinv.upload(Dinv);
+  H->ident.upload(ident);
+  H->chunk.assign(Lb, 0);
+  H->nchunks.assign(Lb, 0);
+  H->cpc.assign(Lb, 0);
+  for (int l = 0; l < Lb; ++l) {
+    const long long cs = N >> (l + 1);
+    long long ch = cs;
+    while (ch > 1024 && ch % 2 == 0) ch /= 2;
+    H->chunk[l] = ch;
+    H->nchunks[l] = (int)(N / ch);
+    H->cpc[l] = (int)(cs / ch);
+  }
+  H->Y.resize(Lb);
+  H->W.resize(Lb);
+  H->core.resize(Lb);
+  int rmax = 1;
+  size_t kel = 1;
+  for (int l = 0; l < Lb; ++l) {
+    H->Y[l].upload(Uh[l]);
+    H->W[l].upload(Wh[l]);
+    Uh[l] = std::vector<zd>();
+    Wh[l] = std::vector<zd>();
+    rmax = std::max(rmax, H->rank[l]);
+    kel = std::max(kel, (size_t)(1LL << l) * 4 * H->rank[l] * H->rank[l]);
+  }
+  phod_ws(*H, N, rmax);
+  lsi::DevBuf kA, kB, kbad;
+  kA.alloc(kel * 16);
+  kB.alloc(kel * 16);
+  kbad.alloc((size_t)std::max(1, 1 << std::max(Lb - 1, 0)) * 4);
+  std::vector<int> hb((size_t)std::max(1, 1 << std::max(Lb - 1, 0)));
+  hipStream_t s = nullptr;
+  for (int l = Lb - 1; l >= 0; --l) {
+    const int rl = H->rank[l], nodes = 1 << l;
+    double2* Y = H->Y[l].as<double2>();
+    phod_apply(*H, N, Y, Y, rl, l + 1, s);  // Y = (levels below)^-1 U
+    lsk::launch_zero_rows(Y, N, rl, H->qh.as<double>(), s);
+    lsk::launch_hodlr_dot(0, H->W[l].p, Y, N, H->partial.as<double2>(), N, rl, H->chunk[l], H->nchunks[l], rl, s);
+    lsk::launch_hodlr_core(0, nullptr, H->partial.as<double2>(), H->svec.as<double2>(), rl, nodes, H->cpc[l],
+                           H->nchunks[l], false, rl, s);
+    H->core[l].alloc((size_t)nodes * lsk::hodlr_core_elems(rl) * 16);
+    lsi::hip_check(hipMemsetAsync(kbad.p, 0, (size_t)nodes * 4, s), "memset");
+    lsk::launch_core_invert(H->svec.as<double2>(), rl, nodes, kA.as<double2>(), kB.as<double2>(),
+                            H->core[l].as<double2>(), kbad.as<int>(), s);
+    lsi::hip_check(hipGetLastError(), "panel HODLR cores");
+    lsi::hip_check(hipMemcpyAsync(hb.data(), kbad.p, (size_t)nodes * 4, hipMemcpyDeviceToHost, s), "core status");
+    lsi::hip_check(hipStreamSynchronize(s), "panel HODLR cores");
+    for (int k = 0; k < nodes; ++k)
+      if (hb[k]) throw LsError(LS_EINVAL, "singular HODLR core of the panel system");
+  }
+  lsi::hip_check(hipDeviceSynchronize(), "panel HODLR setup");
+  H->t_setup_ms = lsi::now_ms() - t0;
+  P->hod = std::move(H);
 }
 
 }  // namespace
@@ -297,10 +577,59 @@ ls_status ls_panels_apply(ls_panels* P, const void* x, void* y, int nrhs, int64_
   }
 }
 
-// Restarted GMRES (Section 6 without the preconditioner) on A psi = f from psi = 0: classical
-// Gram-Schmidt with one reorthogonalisation, Givens rotations and the triangular solve on the
-// host, every vector operation on the device; each restart (and the end) recomputes the true
-// residual f - A psi.
+// HODLR preconditioner of the panel system (Section 6): fixed off-diagonal rank, uniform trees
+// whose side is a power of two.  rank <= 0 drops the factors.
+ls_status ls_panels_precond_setup(ls_panels* P, int rank) {
+  try {
+    if (!P) throw LsError(LS_EINVAL, "panels handle is NULL");
+    if (rank <= 0) {
+      P->hod.reset();
+      return LS_OK;
+    }
+    if (rank > 256) throw LsError(LS_EINVAL, "rank must be <= 256");
+    if (P->dense) throw LsError(LS_ENOTSUP, "the HODLR preconditioner needs a uniform tree");
+    const int ns = P->g.nside;
+    if ((ns & (ns - 1)) != 0) throw LsError(LS_ENOTSUP, "the HODLR preconditioner needs nside a power of two");
+    P->hod.reset();
+    build_panel_hodlr(P, rank);
+    return LS_OK;
+  } catch (const LsError& e) {
+    return lsi::fail(e);
+  }
+}
+
+ls_status ls_panels_precond_apply(ls_panels* P, const void* r, void* z, int nrhs, int64_t ld, void* stream) {
+  try {
+    check_vec(P, r, z, nrhs, ld);
+    if (!P->hod) throw LsError(LS_EINVAL, "no HODLR preconditioner (ls_panels_precond_setup)");
+    phod_apply_user(P, (const double2*)r, ld, (double2*)z, ld, nrhs, (hipStream_t)stream);
+    lsi::hip_check(hipGetLastError(), "panel HODLR apply");
+    return LS_OK;
+  } catch (const LsError& e) {
+    return lsi::fail(e);
+  }
+}
+
+ls_status ls_panels_precond_info(const ls_panels* P, int* rank, int* leaf, int* levels, double* mean_rank,
+                                 int* max_rank, double* setup_ms) {
+  if (!P || !rank || !leaf || !levels || !mean_rank || !max_rank || !setup_ms) {
+    lsi::g_last_error = "bad arguments";
+    return LS_EINVAL;
+  }
+  const PanelHodlr* H = P->hod.get();
+  *rank = H ? H->r : 0;
+  *leaf = H ? H->lp : 0;
+  *levels = H ? H->Lb : 0;
+  *mean_rank = H && H->blocks ? (double)H->used_rank_sum / (double)H->blocks : 0.0;
+  *max_rank = H ? H->used_rank_max : 0;
+  *setup_ms = H ? H->t_setup_ms : 0.0;
+  return LS_OK;
+}
+
+// Restarted GMRES (Section 6) on A psi = f from psi = 0, right-preconditioned by the HODLR
+// approximation when one is built (A A~^-1 u = f, psi = A~^-1 u): classical Gram-Schmidt with
+// one reorthogonalisation, Givens rotations and the triangular solve on the host, every vector
+// operation on the device; each restart (and the end) recomputes the true residual f - A psi.
 ls_status ls_panels_solve(ls_panels* P, const void* f, void* psi, double tol, int restart, int maxit,
                           ls_solve_info* info, void* stream) {
   try {
@@ -318,6 +647,8 @@ ls_status ls_panels_solve(ls_panels* P, const void* f, void* psi, double tol, in
     P->kr.ensure((size_t)N * 16);
     P->kpart.ensure((size_t)(m + 1) * nch * 16);
     P->kc.ensure((size_t)(m + 1) * 16);
+    const bool pc = P->hod != nullptr;
+    if (pc) P->kz.ensure((size_t)N * 16);
     double2* Q = P->kq.as<double2>();
     double2* w = P->kw.as<double2>();
     double2* r = P->kr.as<double2>();
@@ -398,7 +729,12 @@ ls_status ls_panels_solve(ls_panels* P, const void* f, void* psi, double tol, in
       g[0] = beta;
       int k = 0;
       for (int j = 0; j < m && it < maxit; ++j) {
-        applyA(Q + (size_t)j * N, w);
+        if (pc) {
+          phod_apply_user(P, Q + (size_t)j * N, N, P->kz.as<double2>(), N, 1, s);
+          applyA(P->kz.as<double2>(), w);
+        } else {
+          applyA(Q + (size_t)j * N, w);
+        }
         ++it;
         dots(Q, j + 1, w, h);
         update(w, j + 1, h, 1.0);
@@ -440,7 +776,16 @@ ls_status ls_panels_solve(ls_panels* P, const void* f, void* psi, double tol, in
         for (int jj = i + 1; jj < k; ++jj) acc -= H[(size_t)i * m + jj] * y[jj];
         y[i] = acc / H[(size_t)i * m + i];
       }
-      update(x, k, y, -1.0);
+      if (pc) {
+        // psi += A~^-1 (Q y)
+        double2* z = P->kz.as<double2>();
+        lsp::launch_panel_combo(z, fd, 0.0, fd, 0.0, N, s);
+        update(z, k, y, -1.0);
+        phod_apply_user(P, z, N, z, N, 1, s);
+        lsp::launch_panel_combo(x, x, 1.0, z, 1.0, N, s);
+      } else {
+        update(x, k, y, -1.0);
+      }
       applyA(x, w);
       lsp::launch_panel_combo(r, fd, 1.0, w, -1.0, N, s);
     }

@@ -137,10 +137,15 @@ def lib():
     L.ls_panels_moments.argtypes = [vp, ci, ci, vp]
     L.ls_panels_solve.argtypes = [vp, vp, vp, cd, ci, ci, C.POINTER(_Info), vp]
     L.ls_panels_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.ls_panels_precond_setup.argtypes = [vp, ci]
+    L.ls_panels_precond_apply.argtypes = [vp, vp, vp, ci, i64, vp]
+    L.ls_panels_precond_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.ls_panels_destroy.argtypes = [vp]
     L.ls_panels_destroy.restype = None
     for name in ("ls_panels_setup", "ls_panels_apply", "ls_panels_moments", "ls_panels_info", "ls_panels_solve",
-                 "ls_panels_setup_leaves"):
+                 "ls_panels_setup_leaves", "ls_panels_precond_setup", "ls_panels_precond_apply",
+                 "ls_panels_precond_info"):
         getattr(L, name).restype = C.c_int
     for name in ("ls_setup", "ls_matvec", "ls_apply_V", "ls_precond_apply", "ls_precond_apply_noalloc",
                  "ls_rhs_planewave", "ls_solve",
@@ -543,6 +548,27 @@ class Panels:
         _check(lib().ls_panels_solve(self._h, f.data_ptr(), psi.data_ptr(), float(tol), int(restart), int(maxit),
                                      C.byref(info), _stream(stream)))
         return psi, _info_dict(info)
+
+    def precondition(self, rank: int) -> dict:
+        """ls_panels_precond_setup (rank <= 0 drops the factors); returns ls_panels_precond_info"""
+        _check(lib().ls_panels_precond_setup(self._h, int(rank)))
+        return self.precond_info()
+
+    def precond_info(self) -> dict:
+        r, lf, lv, mx = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        mr, ms = C.c_double(), C.c_double()
+        _check(lib().ls_panels_precond_info(self._h, C.byref(r), C.byref(lf), C.byref(lv), C.byref(mr), C.byref(mx),
+                                            C.byref(ms)))
+        return {"rank": r.value, "leaf": lf.value, "levels": lv.value, "mean_rank": mr.value,
+                "max_rank": mx.value, "setup_ms": ms.value}
+
+    def precond_apply(self, r, z=None, stream=None):
+        """z = A~^-1 r (complex128 CUDA tensors, shape (N,) or (nrhs, N), box-major order)"""
+        import torch
+        nrhs = _vec(r, self.N)
+        z = torch.empty_like(r) if z is None else z
+        _check(lib().ls_panels_precond_apply(self._h, r.data_ptr(), z.data_ptr(), nrhs, self.N, _stream(stream)))
+        return z
 
     def moments(self, dx: int, dy: int) -> np.ndarray:
         """M_l(node a of the target box, source box) for box offset (dx, dy): array (p^2, N_p)"""

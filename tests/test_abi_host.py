@@ -176,6 +176,11 @@ def test_panels_reject_invalid_inputs():
     assert L.ls_panels_moments(None, 0, 0, x.ctypes.data) == ls.LS_EINVAL
     n, npb, nf = C.c_int64(), C.c_int(), C.c_int()
     assert L.ls_panels_info(None, C.byref(n), C.byref(npb), C.byref(nf)) == ls.LS_EINVAL
+    assert L.ls_panels_precond_setup(None, 8) == ls.LS_EINVAL
+    assert L.ls_panels_precond_apply(None, x.ctypes.data, x.ctypes.data, 1, 144, None) == ls.LS_EINVAL
+    r, lf, lv, mx, mr, ms = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_double(), C.c_double()
+    assert L.ls_panels_precond_info(None, C.byref(r), C.byref(lf), C.byref(lv), C.byref(mr), C.byref(mx),
+                                    C.byref(ms)) == ls.LS_EINVAL
 
 
 def test_panels_leaves_reject_invalid_inputs():

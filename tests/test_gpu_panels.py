@@ -245,3 +245,110 @@ def test_solve_reports_maxit_and_nan():
     _, info = P.solve(fn)
     assert info["status"] == "NAN" and info["iters"] == 0
     P.close()
+
+
+# ---- HODLR preconditioner of the panel system (Section 6 on the discretisation of Section 2.2) ----
+@pytest.mark.parametrize("nside,p,kappa", [(4, 4, 12.0), (4, 5, 8.0)])
+def test_panel_hodlr_at_full_rank_is_the_dense_inverse(nside, p, kappa):
+    # a rank cap no off-diagonal block exceeds: A~ = A, so A~^-1 r is the dense solve
+    boxes = panels.uniform_tree(nside)
+    A = panels.dense_A(boxes, p, kappa, qfun)
+    say(f"panel HODLR full rank nside={nside} p={p} kappa={kappa}")
+    P = ls.Panels(nside, 1.0, p, kappa, node_q(boxes, p))
+    N = P.N
+    info = P.precondition(256)
+    lp = panels.hodlr_leaf(nside, p)
+    assert info["leaf"] == lp and 2 ** info["levels"] * lp == N and info["rank"] == 256
+    assert info["max_rank"] <= N // 2
+    rng = np.random.default_rng(nside * 10 + p)
+    R = rng.standard_normal((3, N)) + 1j * rng.standard_normal((3, N))
+    Z = P.precond_apply(torch.from_numpy(R).cuda()).cpu().numpy()
+    for j in range(3):
+        ref = np.linalg.solve(A, R[j])
+        err = np.linalg.norm(Z[j] - ref) / np.linalg.norm(ref)
+        say(j, err)
+        assert err < 1e-9, err
+    # one column alone = the same column of the block; in place = out of place
+    z0 = P.precond_apply(torch.from_numpy(R[0].copy()).cuda()).cpu().numpy()
+    assert np.abs(z0 - Z[0]).max() <= 1e-13 * np.abs(Z[0]).max()
+    r1 = torch.from_numpy(R[1].copy()).cuda()
+    P.precond_apply(r1, r1)
+    assert np.abs(r1.cpu().numpy() - Z[1]).max() <= 1e-13 * np.abs(Z[1]).max()
+    P.close()
+
+
+@pytest.mark.parametrize("rank", [3, 12])
+def test_panel_hodlr_truncated_matches_the_oracle_hodlr(rank):
+    # below the numerical rank: the device factors (ACA at a fixed rank, same pivoting rules)
+    # against the oracle HODLR of the oracle's dense panel matrix in the same order
+    from oracle.hodlr import HODLR
+    nside, p, kappa = 8, 3, 10.0
+    boxes = panels.uniform_tree(nside)
+    A = panels.dense_A(boxes, p, kappa, qfun)
+    perm = panels.hodlr_order(nside, p)
+    lp = panels.hodlr_leaf(nside, p)
+    H = HODLR(A[np.ix_(perm, perm)], lp, rank=rank)
+    say(f"panel HODLR rank={rank} nside={nside} p={p}")
+    P = ls.Panels(nside, 1.0, p, kappa, node_q(boxes, p))
+    info = P.precondition(rank)
+    assert info["levels"] == 4 and info["leaf"] == lp == 36 and info["max_rank"] == rank
+    rng = np.random.default_rng(rank)
+    r = rng.standard_normal(P.N) + 1j * rng.standard_normal(P.N)
+    z = P.precond_apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    ref = np.empty_like(r)
+    ref[perm] = H.solve(r[perm])
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    say("vs oracle HODLR", err, info)
+    assert err < 1e-8, err
+    P.close()
+
+
+def test_panel_hodlr_preconditioned_solve():
+    # right preconditioning: the same solution as the dense solve, in far fewer products
+    nside, p, kappa = 8, 3, 10.0
+    boxes = panels.uniform_tree(nside)
+    A = panels.dense_A(boxes, p, kappa, qfun)
+    f = panels.rhs_planewave(boxes, p, kappa, qfun, theta=0.7)
+    ref = np.linalg.solve(A, f)
+    P = ls.Panels(nside, 1.0, p, kappa, node_q(boxes, p))
+    fd = torch.from_numpy(f).cuda()
+    psi0, info0 = P.solve(fd, tol=1e-11)
+    P.precondition(16)
+    psi1, info1 = P.solve(fd, tol=1e-11)
+    say("unpreconditioned", info0, "HODLR rank 16", info1)
+    for psi, info in ((psi0, info0), (psi1, info1)):
+        psi = psi.cpu().numpy()
+        assert info["status"] == "CONVERGED"
+        assert np.linalg.norm(A @ psi - f) <= 1.2e-11 * np.linalg.norm(f)
+        assert np.linalg.norm(psi - ref) <= 1e-9 * np.linalg.norm(ref)
+    assert info1["iters"] * 2 <= info0["iters"], (info0["iters"], info1["iters"])
+    # dropping the factors restores the unpreconditioned iteration
+    assert P.precondition(0)["rank"] == 0
+    _, info2 = P.solve(fd, tol=1e-11)
+    assert info2["iters"] == info0["iters"]
+    P.close()
+
+
+def test_panel_hodlr_invalid_uses():
+    boxes = panels.uniform_tree(4)
+    P = ls.Panels(4, 1.0, 3, 10.0, node_q(boxes, 3))
+    r = torch.zeros(P.N, dtype=torch.complex128, device="cuda")
+    with pytest.raises(ls.LsError) as e:
+        P.precond_apply(r)                 # no factors yet
+    assert e.value.code == ls.LS_EINVAL
+    with pytest.raises(ls.LsError) as e:
+        P.precondition(300)
+    assert e.value.code == ls.LS_EINVAL
+    P.close()
+    b6 = panels.uniform_tree(6)
+    P6 = ls.Panels(6, 1.0, 2, 10.0, node_q(b6, 2))
+    with pytest.raises(ls.LsError) as e:
+        P6.precondition(8)                 # nside not a power of two
+    assert e.value.code == ls.LS_ENOTSUP
+    P6.close()
+    leaves = panels.uniform_tree(2)
+    G = ls.Panels(0, 1.0, 2, 10.0, node_q(leaves, 2), boxes=_leaves_array(leaves))
+    with pytest.raises(ls.LsError) as e:
+        G.precondition(8)                  # leaves of a general tree
+    assert e.value.code == ls.LS_ENOTSUP
+    G.close()

@@ -152,3 +152,48 @@ def test_adaptive_tree_is_level_restricted_and_resolves_the_contrast():
         for b in leaves:
             if panels.neighbours(a, b):
                 assert abs(a.level - b.level) <= 1
+
+
+def test_hodlr_order_halves_the_boxes_into_rectangles():
+    # the HODLR order of a uniform tree: whole boxes per leaf, and every node of the binary tree
+    # (a half of its parent's index range) holds the boxes of one axis-aligned rectangle
+    nside, p = 8, 2
+    perm = panels.hodlr_order(nside, p)
+    n2, N = p * p, nside * nside * p * p
+    assert sorted(perm.tolist()) == list(range(N))
+    box = perm.reshape(-1, n2) // n2
+    assert (box == box[:, :1]).all()                     # a box's nodes stay together
+    order = box[:, 0]
+    lp = panels.hodlr_leaf(nside, p)
+    assert lp == 64 and lp % n2 == 0
+    size = len(order)
+    while size >= 1:
+        for lo in range(0, len(order), size):
+            ix, iy = order[lo:lo + size] // nside, order[lo:lo + size] % nside
+            area = (ix.max() - ix.min() + 1) * (iy.max() - iy.min() + 1)
+            assert area == size, (size, lo)
+        size //= 2 if size > 1 else 2
+    assert [panels.hodlr_leaf(8, q) for q in (1, 3, 4, 5, 8)] == [64, 36, 64, 25, 64]
+
+
+def test_panel_hodlr_at_full_rank_is_the_inverse():
+    # the fixed-rank HODLR of the panel matrix (HODLR order, leaves of hodlr_leaf unknowns):
+    # at a rank no off-diagonal block exceeds, A~ = A and its solve is the dense solve; below
+    # it the approximation error falls as the rank grows
+    from oracle.hodlr import HODLR
+    nside, p, kappa = 8, 2, 10.0
+    boxes = panels.uniform_tree(nside)
+    q_fn = lambda x, y: 1.5 * np.exp(-8.0 * (x * x + (y - 0.1) ** 2))
+    A = panels.dense_A(boxes, p, kappa, q_fn)
+    perm = panels.hodlr_order(nside, p)
+    Ah = A[np.ix_(perm, perm)]
+    lp = panels.hodlr_leaf(nside, p)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(len(A)) + 1j * rng.standard_normal(len(A))
+    H = HODLR(Ah, lp, rank=len(A) // 2)
+    assert np.abs(H.dense() - Ah).max() <= 1e-12 * np.abs(Ah).max()
+    ref = np.linalg.solve(Ah, b)
+    assert np.linalg.norm(H.solve(b) - ref) <= 1e-10 * np.linalg.norm(ref)
+    errs = [np.linalg.norm(HODLR(Ah, lp, rank=k).dense() - Ah) / np.linalg.norm(Ah) for k in (4, 8, 16, 32)]
+    assert all(e2 < e1 for e1, e2 in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-5, errs
