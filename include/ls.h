@@ -433,6 +433,26 @@ void ls_nop_destroy(ls_nop* N);
  * blocks).  The product is the dense sum over all box pairs (no far-field compression).
  * ---------------------------------------------------------------------------------------*/
 typedef struct ls_panels ls_panels;
+/* A function the host evaluates at n points (x[k], y[k]): real and imaginary parts into re[k],
+ * im[k] (the contrast q: im = 0).  ctx is passed through unchanged. */
+typedef void (*ls_point_fn)(int n, const double* x, const double* y, double* re, double* im, void* ctx);
+/* The adaptive, level-restricted quadtree of Section 2.1 on [-L, L]^2 (host, synchronous; calls
+ * q and uinc on the host).  A box is split below min_level, and below max_level while
+ * (kappa w)^2 > T (w its half-width: the high-frequency regime of Section 3) or while q or uinc is
+ * not resolved: the p-th order interpolant of the function on the box (Qdag of its p x p node
+ * values, Eqs. (eq:9)-(eq:10)), evaluated at the nodes of its four children, differs from the
+ * function there by more than eps_grid times the largest magnitude among those values and the
+ * box's own.  Then every leaf with a neighbour (a shared boundary segment) more than one level
+ * finer is split, pass after pass, until none is.  Output: *nboxes = the number of leaves and,
+ * when it is at most max_boxes, boxes[4 k ..] = (centre x, centre y, half-width, level) of leaf
+ * k, depth first with the children of a box in the order (-x, -y), (-x, +y), (+x, -y), (+x, +y)
+ * (the first three columns are the input of ls_panels_setup_leaves).  Errors: LS_EINVAL (NULL
+ * function or count, p outside 1..8, L, kappa, eps_grid or T not positive and finite, levels not
+ * 0 <= min_level <= max_level <= 12, a non-finite function value, more leaves than max_boxes:
+ * *nboxes still holds the count). */
+ls_status ls_panels_build_tree(double L, int p, double kappa, double eps_grid, double T, int min_level, int max_level,
+                               ls_point_fn q, ls_point_fn uinc, void* ctx, int max_boxes, double* boxes,
+                               int* nboxes);
 /* nside in 1..1024, p in 1..8, L > 0, kappa > 0, sign +1 or -1 (see ls_options.sign);
  * q: host, N node values of the contrast (box-major, node-minor), copied.  Forms the tables
  * on the current device (synchronous).  Errors: LS_EINVAL (bad argument, non-finite q),

@@ -107,14 +107,10 @@ void check_vec(const ls_panels* P, const void* x, const void* y, int nrhs, int64
 }
 
 // Chebyshev nodes (first kind, ascending), the basis (by total degree, then first index) and
-// the Gauss-Legendre rules on [0, 1] along the ray and across the triangles; uploads them with
 // Qdag = (Q^T Q)^-1 Q^T.  Q (n2 x np): Q[i][l] = b_l(node i); its columns are orthogonal at the
 // Chebyshev points of the first kind (discrete orthogonality of T_0..T_{p-1}), so Qdag is the
 // transpose scaled by the diagonal of Q^T Q.
-lsp::PanelRef reference_data(ls_panels* P) {
-  const lsp::PanelGeom& g = P->g;
-  const int p = g.p;
-  lsp::PanelRef R{};
+void basis_tables(int p, lsp::PanelRef& R, std::vector<double>& Qd) {
   for (int i = 0; i < p; ++i) R.node[i] = std::cos((2.0 * (p - 1 - i) + 1.0) * M_PI / (2.0 * p));
   int l = 0;
   for (int dgr = 0; dgr < p; ++dgr)
@@ -122,19 +118,9 @@ lsp::PanelRef reference_data(ls_panels* P) {
       R.ba[l] = a;
       R.bb[l] = dgr - a;
     }
-  std::vector<double> gx, gw;
-  gauss_legendre(lsp::kRay, gx, gw);
-  for (int i = 0; i < lsp::kRay; ++i) {
-    R.ray_t[i] = 0.5 * (gx[i] + 1.0);
-    R.ray_w[i] = 0.5 * gw[i];
-  }
-  gauss_legendre(lsp::kAcross, gx, gw);
-  for (int i = 0; i < lsp::kAcross; ++i) {
-    R.acr_t[i] = 0.5 * (gx[i] + 1.0);
-    R.acr_w[i] = 0.5 * gw[i];
-  }
-  const int n2 = g.n2, np = g.np;
-  std::vector<double> Q((size_t)n2 * np), Qd((size_t)np * n2);
+  const int n2 = p * p, np = p * (p + 1) / 2;
+  std::vector<double> Q((size_t)n2 * np);
+  Qd.assign((size_t)np * n2, 0.0);
   for (int i = 0; i < p; ++i)
     for (int j = 0; j < p; ++j)
       for (int k = 0; k < np; ++k) Q[(size_t)(i * p + j) * np + k] = cheb(R.ba[k], R.node[i]) * cheb(R.bb[k], R.node[j]);
@@ -149,10 +135,137 @@ lsp::PanelRef reference_data(ls_panels* P) {
     }
     for (int i = 0; i < n2; ++i) Qd[(size_t)k * n2 + i] = Q[(size_t)i * np + k] / dkk;
   }
+}
+
+// The reference data above with the Gauss-Legendre rules on [0, 1] along the ray and across the
+// triangles, uploaded (Qdag too).
+lsp::PanelRef reference_data(ls_panels* P) {
+  const lsp::PanelGeom& g = P->g;
+  lsp::PanelRef R{};
+  std::vector<double> Qd;
+  basis_tables(g.p, R, Qd);
+  std::vector<double> gx, gw;
+  gauss_legendre(lsp::kRay, gx, gw);
+  for (int i = 0; i < lsp::kRay; ++i) {
+    R.ray_t[i] = 0.5 * (gx[i] + 1.0);
+    R.ray_w[i] = 0.5 * gw[i];
+  }
+  gauss_legendre(lsp::kAcross, gx, gw);
+  for (int i = 0; i < lsp::kAcross; ++i) {
+    R.acr_t[i] = 0.5 * (gx[i] + 1.0);
+    R.acr_w[i] = 0.5 * gw[i];
+  }
   P->ref.alloc(sizeof(R));
   lsi::hip_check(hipMemcpy(P->ref.p, &R, sizeof(R), hipMemcpyHostToDevice), "panels ref");
   P->qdag.upload(Qd);
   return R;
+}
+
+// Adaptive, level-restricted quadtree of Section 2.1 on [-L, L]^2.  A box is split below
+// min_level, and up to max_level while it is in the high-frequency regime ((kappa w)^2 > T, w the
+// half-width) or while q or the incident field is not resolved: the p-th order interpolant of the
+// function on the box (Qdag applied to its node values), evaluated at the nodes of its four
+// children, differs from the function there by more than eps relative to the largest magnitude
+// among those values and the box's own.  Then every leaf with a neighbour (a shared boundary
+// segment) more than one level finer is split, pass after pass, until none is.  Leaves are
+// returned depth first, children in the order (-x, -y), (-x, +y), (+x, -y), (+x, +y).
+struct TreeNode {
+  double cx, cy, beta;
+  int level, child;  // child: index of the first of four children, -1 for a leaf
+};
+
+bool box_resolved(ls_point_fn fn, void* ctx, const TreeNode& b, int p, double eps, const lsp::PanelRef& R,
+                  const std::vector<double>& Qd) {
+  const int n2 = p * p, np = p * (p + 1) / 2;
+  std::vector<double> x((size_t)5 * n2), y((size_t)5 * n2), re((size_t)5 * n2, 0.0), im((size_t)5 * n2, 0.0);
+  // the box's nodes, then its children's (in the child order above)
+  for (int c = 0; c < 5; ++c) {
+    const double h = c == 0 ? b.beta : 0.5 * b.beta;
+    const double ox = c == 0 ? b.cx : b.cx + (c <= 2 ? -h : h);
+    const double oy = c == 0 ? b.cy : b.cy + (c % 2 == 1 ? -h : h);
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < p; ++j) {
+        x[(size_t)c * n2 + i * p + j] = ox + h * R.node[i];
+        y[(size_t)c * n2 + i * p + j] = oy + h * R.node[j];
+      }
+  }
+  fn(5 * n2, x.data(), y.data(), re.data(), im.data(), ctx);
+  std::vector<zd> coef(np, zd(0));
+  double scale = 0;
+  for (int k = 0; k < np; ++k)
+    for (int i = 0; i < n2; ++i) coef[k] += Qd[(size_t)k * n2 + i] * zd(re[i], im[i]);
+  for (int i = 0; i < 5 * n2; ++i) {
+    if (!std::isfinite(re[i]) || !std::isfinite(im[i])) throw LsError(LS_EINVAL, "a field value is not finite");
+    scale = std::max(scale, std::abs(zd(re[i], im[i])));
+  }
+  scale = std::max(scale, 1e-300);
+  double err = 0;
+  for (int i = n2; i < 5 * n2; ++i) {
+    const double u = (x[i] - b.cx) / b.beta, v = (y[i] - b.cy) / b.beta;
+    zd a(0);
+    for (int k = 0; k < np; ++k) a += coef[k] * (cheb(R.ba[k], u) * cheb(R.bb[k], v));
+    err = std::max(err, std::abs(a - zd(re[i], im[i])));
+  }
+  return err <= eps * scale;
+}
+
+bool neighbours(const TreeNode& a, const TreeNode& b) {
+  const double dx = std::fabs(a.cx - b.cx), dy = std::fabs(a.cy - b.cy), sw = a.beta + b.beta;
+  const double tol = 1e-12 * sw;
+  return (std::fabs(dx - sw) <= tol && dy < sw - tol) || (std::fabs(dy - sw) <= tol && dx < sw - tol);
+}
+
+void split_node(std::vector<TreeNode>& t, int i) {
+  const TreeNode b = t[i];
+  const double h = 0.5 * b.beta;
+  t[i].child = (int)t.size();
+  for (int sx = -1; sx <= 1; sx += 2)
+    for (int sy = -1; sy <= 1; sy += 2) t.push_back({b.cx + sx * h, b.cy + sy * h, h, b.level + 1, -1});
+}
+
+std::vector<TreeNode> build_quadtree(double L, int p, double kappa, double eps, double T, int min_level,
+                                     int max_level, ls_point_fn q, ls_point_fn uinc, void* ctx) {
+  lsp::PanelRef R{};
+  std::vector<double> Qd;
+  basis_tables(p, R, Qd);
+  std::vector<TreeNode> t{{0.0, 0.0, L, 0, -1}};
+  for (size_t i = 0; i < t.size(); ++i) {
+    const TreeNode b = t[i];
+    if (b.level >= max_level) continue;
+    bool split = b.level < min_level;
+    if (!split) {
+      const double kw = kappa * b.beta;
+      split = kw * kw > T || !box_resolved(q, ctx, b, p, eps, R, Qd) || !box_resolved(uinc, ctx, b, p, eps, R, Qd);
+    }
+    if (split) split_node(t, (int)i);
+  }
+  // level restriction, pass after pass against the leaves at the start of the pass
+  for (;;) {
+    std::vector<int> leaves, to_split;
+    for (size_t i = 0; i < t.size(); ++i)
+      if (t[i].child < 0) leaves.push_back((int)i);
+    for (int a : leaves)
+      for (int o : leaves)
+        if (t[o].level > t[a].level + 1 && neighbours(t[a], t[o])) {
+          to_split.push_back(a);
+          break;
+        }
+    if (to_split.empty()) break;
+    for (int a : to_split) split_node(t, a);
+  }
+  // leaves depth first
+  std::vector<TreeNode> out;
+  std::vector<int> stack{0};
+  while (!stack.empty()) {
+    const int i = stack.back();
+    stack.pop_back();
+    if (t[i].child < 0) {
+      out.push_back(t[i]);
+      continue;
+    }
+    for (int c = 3; c >= 0; --c) stack.push_back(t[i].child + c);
+  }
+  return out;
 }
 
 // Morton (Z) order of the nside x nside boxes (nside a power of two): box k = ix * nside + iy has
@@ -460,6 +573,34 @@ ls_status ls_panels_setup(int nside, double L, int p, double kappa, const double
     lsi::hip_check(hipGetLastError(), "panel blocks");
     lsi::hip_check(hipDeviceSynchronize(), "panels setup");
     *out = P.release();
+    return LS_OK;
+  } catch (const LsError& e) {
+    return lsi::fail(e);
+  }
+}
+
+ls_status ls_panels_build_tree(double L, int p, double kappa, double eps_grid, double T, int min_level, int max_level,
+                               ls_point_fn q, ls_point_fn uinc, void* ctx, int max_boxes, double* boxes,
+                               int* nboxes) {
+  try {
+    if (!q || !uinc || !nboxes) throw LsError(LS_EINVAL, "q, uinc or nboxes is NULL");
+    if (p < 1 || p > lsp::kMaxP) throw LsError(LS_EINVAL, "p must be in 1..8");
+    if (!(L > 0) || !std::isfinite(L) || !(kappa > 0) || !std::isfinite(kappa))
+      throw LsError(LS_EINVAL, "L and kappa must be positive and finite");
+    if (!(eps_grid > 0) || !std::isfinite(eps_grid) || !(T > 0) || !std::isfinite(T))
+      throw LsError(LS_EINVAL, "eps_grid and T must be positive and finite");
+    if (min_level < 0 || max_level < min_level || max_level > 12)
+      throw LsError(LS_EINVAL, "levels must satisfy 0 <= min_level <= max_level <= 12");
+    if (max_boxes < 0 || (max_boxes > 0 && !boxes)) throw LsError(LS_EINVAL, "boxes is NULL");
+    const std::vector<TreeNode> lv = build_quadtree(L, p, kappa, eps_grid, T, min_level, max_level, q, uinc, ctx);
+    *nboxes = (int)lv.size();
+    if ((int)lv.size() > max_boxes) throw LsError(LS_EINVAL, "more leaves than max_boxes (nboxes holds the count)");
+    for (size_t i = 0; i < lv.size(); ++i) {
+      boxes[4 * i] = lv[i].cx;
+      boxes[4 * i + 1] = lv[i].cy;
+      boxes[4 * i + 2] = lv[i].beta;
+      boxes[4 * i + 3] = lv[i].level;
+    }
     return LS_OK;
   } catch (const LsError& e) {
     return lsi::fail(e);

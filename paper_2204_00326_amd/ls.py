@@ -141,11 +141,13 @@ def lib():
     L.ls_panels_precond_apply.argtypes = [vp, vp, vp, ci, i64, vp]
     L.ls_panels_precond_info.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                          C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    L.ls_panels_build_tree.argtypes = [cd, ci, cd, cd, cd, ci, ci, _POINT_FN, _POINT_FN, vp, ci, vp,
+                                       C.POINTER(C.c_int)]
     L.ls_panels_destroy.argtypes = [vp]
     L.ls_panels_destroy.restype = None
     for name in ("ls_panels_setup", "ls_panels_apply", "ls_panels_moments", "ls_panels_info", "ls_panels_solve",
                  "ls_panels_setup_leaves", "ls_panels_precond_setup", "ls_panels_precond_apply",
-                 "ls_panels_precond_info"):
+                 "ls_panels_precond_info", "ls_panels_build_tree"):
         getattr(L, name).restype = C.c_int
     for name in ("ls_setup", "ls_matvec", "ls_apply_V", "ls_precond_apply", "ls_precond_apply_noalloc",
                  "ls_rhs_planewave", "ls_solve",
@@ -504,6 +506,41 @@ def solve_queue(problems, fs, tol: float = 1e-8, prec: int = -1, nworkers: int =
     infos = (_Info * n)()
     _check(lib().ls_solve_queue(hs, n, fp, pp, float(tol), int(prec), int(nworkers), int(graph_iters), infos))
     return psis, [_info_dict(i) for i in infos]
+
+
+_POINT_FN = C.CFUNCTYPE(None, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                       C.POINTER(C.c_double), C.c_void_p)
+
+
+def build_tree(q_fn, uinc_fn, p: int, eps_grid: float, kappa: float, T: float = 16.0, L: float = 1.0,
+               max_level: int = 6, min_level: int = 1) -> np.ndarray:
+    """ls_panels_build_tree: the adaptive, level-restricted quadtree's leaves, array (nboxes, 4) of
+    (centre x, centre y, half-width, level).  q_fn, uinc_fn take coordinate arrays (x, y) and
+    return values (an exception becomes NaN values, which the library rejects)."""
+    def wrap(fn):
+        def cb(n, x, y, re, im, ctx):
+            try:
+                xs = np.ctypeslib.as_array(x, shape=(n,)).copy()
+                ys = np.ctypeslib.as_array(y, shape=(n,)).copy()
+                v = np.broadcast_to(np.asarray(fn(xs, ys), dtype=np.complex128), (n,))
+                np.ctypeslib.as_array(re, shape=(n,))[:] = v.real
+                np.ctypeslib.as_array(im, shape=(n,))[:] = v.imag
+            except Exception:
+                np.ctypeslib.as_array(re, shape=(n,))[:] = np.nan
+        return _POINT_FN(cb)
+
+    cq, cu = wrap(q_fn), wrap(uinc_fn)
+    cap = 4096
+    while True:
+        out = np.empty((cap, 4))
+        n = C.c_int(0)
+        code = lib().ls_panels_build_tree(float(L), int(p), float(kappa), float(eps_grid), float(T), int(min_level),
+                                          int(max_level), cq, cu, None, cap, out.ctypes.data, C.byref(n))
+        if code == LS_EINVAL and n.value > cap:
+            cap = n.value
+            continue
+        _check(code)
+        return out[:n.value].copy()
 
 
 class Panels:
