@@ -474,13 +474,17 @@ ls_status ls_panels_setup_leaves(int nboxes, const double* boxes, int p, double 
 ls_status ls_panels_apply(ls_panels* P, const void* x, void* y, int nrhs, int64_t ld, int op, void* stream);
 /* HODLR preconditioner of the panel system (Section 6, on the discretisation of Section 2.2):
  * unknowns reordered by boxes in Morton order (the bits of the box's y index at the even, those
- * of its x index at the odd positions of the code), nodes inside a box unchanged; leaves of 4^j
- * whole boxes with at most 64 unknowns; a binary tree that halves the index range; every
+ * of its x index at the odd positions of the code; for the leaves of any tree the code of the
+ * box's lower-left corner on the grid of the smallest box width, ties kept in the given order),
+ * nodes inside a box unchanged; leaves of whole boxes with at most 64 unknowns (uniform trees:
+ * 4^j boxes; any tree: floor(64 / p^2) boxes, then padding unknowns, identity rows and columns,
+ * up to a power-of-two number of leaves); a binary tree that halves the index range; every
  * off-diagonal block compressed by partially pivoted ACA at rank min(rank, half the node);
- * Sherman-Morrison-Woodbury per node.  Factors built on the host (ACA, leaf inverses) and the
- * device (Y, cores); synchronous.  rank <= 0 drops the factors.  Errors: LS_EINVAL (NULL handle,
- * rank > 256, a singular leaf block or core), LS_ENOTSUP (leaves of a general tree, nside not a
- * power of two), LS_ENOMEM / LS_EDEVICE.  Once built, ls_panels_solve is right-preconditioned. */
+ * Sherman-Morrison-Woodbury per node.  Factors built on the host (ACA, leaf inverses; entries
+ * from the operator blocks, or from the dense V copied to the host) and the device (Y, cores);
+ * synchronous.  rank <= 0 drops the factors.  Errors: LS_EINVAL (NULL handle, rank > 256, a
+ * singular leaf block or core), LS_ENOTSUP (a uniform tree whose side is not a power of two),
+ * LS_ENOMEM / LS_EDEVICE.  Once built, ls_panels_solve is right-preconditioned. */
 ls_status ls_panels_precond_setup(ls_panels* P, int rank);
 /* z = A~^-1 r.  r, z: device complex128, nrhs columns of leading dimension ld >= N, box-major
  * order (r and z may be the same buffer); asynchronous on stream.  LS_EINVAL without factors. */

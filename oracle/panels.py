@@ -338,3 +338,44 @@ def hodlr_leaf(nside: int, p: int) -> int:
         lb *= 4
     return lb * n2
 
+
+
+def hodlr_order_leaves(boxes: list[Box], p: int):
+    """HODLR order of the unknowns on the leaves of any tree: boxes sorted (stably) by the Morton
+    code of their lower-left corner on the grid of the smallest box width (y bits at even, x bits
+    at odd positions), nodes inside a box in their own order, leaves of floor(64 / p^2) whole
+    boxes, and padding positions (-1: an identity row and column) after the last box up to a
+    power-of-two number of leaves.  Returns (perm, lp): perm[t] = index of the unknown at position
+    t in the given box order, or -1."""
+    n2 = p * p
+    xmin = min(b.cx - b.beta for b in boxes)
+    ymin = min(b.cy - b.beta for b in boxes)
+    hmin = min(b.beta for b in boxes)
+
+    def code(b):
+        ix = int(math.floor((b.cx - b.beta - xmin) / (2 * hmin) + 0.5))
+        iy = int(math.floor((b.cy - b.beta - ymin) / (2 * hmin) + 0.5))
+        c = 0
+        for bit in range(31):
+            c |= ((iy >> bit) & 1) << (2 * bit)
+            c |= ((ix >> bit) & 1) << (2 * bit + 1)
+        return c
+
+    order = sorted(range(len(boxes)), key=lambda k: code(boxes[k]))
+    lp = max(1, 64 // n2) * n2
+    nleaves = 1
+    while nleaves * lp < len(boxes) * n2:
+        nleaves *= 2
+    perm = -np.ones(nleaves * lp, dtype=np.int64)
+    for t, k in enumerate(order):
+        perm[t * n2:(t + 1) * n2] = k * n2 + np.arange(n2)
+    return perm, lp
+
+
+def padded(A: np.ndarray, perm: np.ndarray) -> np.ndarray:
+    """A in the order perm, with identity rows and columns at the padding positions (-1)."""
+    M = len(perm)
+    out = np.eye(M, dtype=complex)
+    real = np.nonzero(perm >= 0)[0]
+    out[np.ix_(real, real)] = A[np.ix_(perm[real], perm[real])]
+    return out

@@ -69,6 +69,10 @@ void launch_panel_dots(const double2* Q, long long ldq, int nvec, const double2*
                        int nch, hipStream_t s);
 void launch_panel_update(double2* w, const double2* Q, long long ldq, int nvec, const double2* c, long long N,
                          hipStream_t s);
+// HODLR order with padding (perm[t] < 0: a padding unknown): gather into M rows (zeros at the
+// padding) or scatter back (padding rows dropped)
+void launch_panel_permute(const double2* x, long long ldx, double2* y, long long ldy, const int* perm, long long M,
+                          int nrhs, bool scatter, hipStream_t s);
 void launch_panel_combo(double2* y, const double2* a, double alpha, const double2* b, double beta, long long N,
                         hipStream_t s);
 

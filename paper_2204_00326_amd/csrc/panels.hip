@@ -517,6 +517,29 @@ void launch_panel_update(double2* w, const double2* Q, long long ldq, int nvec, 
                          hipStream_t s) {
   k_panel_update<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(w, Q, ldq, nvec, c, N);
 }
+// gather: y[rhs * ldy + t] = x[rhs * ldx + perm[t]], zero where perm[t] < 0 (padding);
+// scatter: y[rhs * ldy + perm[t]] = x[rhs * ldx + t] where perm[t] >= 0.  t < M.
+__global__ __launch_bounds__(256) void k_panel_permute(const double2* __restrict__ x, long long ldx,
+                                                       double2* __restrict__ y, long long ldy,
+                                                       const int* __restrict__ perm, long long M, int scatter) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (t >= M) return;
+  const int k = perm[t];
+  if (scatter) {
+    if (k >= 0) y[rhs * ldy + k] = x[rhs * ldx + t];
+  } else {
+    y[rhs * ldy + t] = k >= 0 ? x[rhs * ldx + k] : make_double2(0.0, 0.0);
+  }
+}
+
+void launch_panel_permute(const double2* x, long long ldx, double2* y, long long ldy, const int* perm, long long M,
+                          int nrhs, bool scatter, hipStream_t s) {
+  if (M > 0 && nrhs > 0)
+    k_panel_permute<<<dim3((unsigned)((M + 255) / 256), (unsigned)nrhs), 256, 0, s>>>(x, ldx, y, ldy, perm, M,
+                                                                                       scatter ? 1 : 0);
+}
+
 void launch_panel_combo(double2* y, const double2* a, double alpha, const double2* b, double beta, long long N,
                         hipStream_t s) {
   k_panel_combo<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(y, a, alpha, b, beta, N);

@@ -12,18 +12,18 @@
 #include "kernels.h"
 #include "panels.h"
 
-// HODLR approximation of the panel system on a uniform tree (Section 6 for the discretisation of
-// Section 2.2): unknowns in HODLR order (boxes in Morton order, nodes inside a box in their own
-// order), leaves of lp <= 64 unknowns (4^j whole boxes), a binary tree that halves the index range.
-// Factors as for the cell-centred grid: U, W per binary level (column c of block b at c * N + its
-// row / column offset), Y = (the levels below)^-1 U, SMW core inverses per node, leaf inverses
-// column-major.
+// HODLR approximation of the panel system (Section 6 for the discretisation of Section 2.2):
+// unknowns in HODLR order (boxes in Morton order, nodes inside a box in their own order, padding
+// unknowns after the last box up to 2^L leaves), leaves of lp <= 64 unknowns (whole boxes), a
+// binary tree that halves the index range.  Factors as for the cell-centred grid over the M =
+// 2^L lp positions: U, W per binary level (column c of block b at c * M + its row / column
+// offset), Y = (the levels below)^-1 U, SMW core inverses per node, leaf inverses column-major.
 struct PanelHodlr {
   int Lb = 0, lp = 0, nleaves = 0, r = 0;
   std::vector<int> rank;           // per binary level: min(r, half of a node)
   std::vector<long long> chunk;    // rows per chunk of the W^T z reductions
   std::vector<int> nchunks, cpc;
-  lsi::DevBuf perm;                // perm[t] = box-major index of HODLR position t
+  lsi::DevBuf perm;                // perm[t] = the caller's index of HODLR position t (-1: padding)
   lsi::DevBuf qh;                  // contrast in HODLR order
   lsi::DevBuf Dinv, ident;
   std::vector<lsi::DevBuf> Y, W, core;
@@ -46,7 +46,7 @@ struct ls_panels {
   bool mfma = true;
   lsi::DevBuf kq, kw, kr, kpart, kc;  // GMRES basis, work vectors, dot partials, coefficients
   lsi::DevBuf kz;                     // preconditioned vector of the GMRES
-  std::unique_ptr<PanelHodlr> hod;    // HODLR preconditioner (uniform trees), when built
+  std::unique_ptr<PanelHodlr> hod;    // HODLR preconditioner, when built
 };
 
 namespace {
@@ -345,58 +345,44 @@ void phod_apply(PanelHodlr& H, long long N, const double2* b, double2* z, int nr
   }
 }
 
-// z = A~^-1 r in box-major order (ld per column), through the HODLR order
+// z = A~^-1 r in the caller's order (ld per column), through the padded HODLR order
 void phod_apply_user(ls_panels* P, const double2* r, long long ldr, double2* z, long long ldz, int nrhs,
                      hipStream_t s) {
   PanelHodlr& H = *P->hod;
-  const long long N = P->N;
-  H.zh.ensure((size_t)N * nrhs * 16);
+  const long long M = (long long)H.nleaves * H.lp;
+  H.zh.ensure((size_t)M * nrhs * 16);
   double2* zh = H.zh.as<double2>();
-  lsk::launch_permute(r, ldr, zh, N, H.perm.as<int>(), N, nrhs, false, s);
-  phod_apply(H, N, zh, zh, nrhs, 0, s);
-  lsk::launch_permute(zh, N, z, ldz, H.perm.as<int>(), N, nrhs, true, s);
+  lsp::launch_panel_permute(r, ldr, zh, M, H.perm.as<int>(), M, nrhs, false, s);
+  phod_apply(H, M, zh, zh, nrhs, 0, s);
+  lsp::launch_panel_permute(zh, M, z, ldz, H.perm.as<int>(), M, nrhs, true, s);
 }
 
-// HODLR factors of A = I + sign kappa^2 diag(q) V on a uniform tree: the off-diagonal blocks by
-// partially pivoted ACA on the host at rank min(r, block side) (entries from the operator blocks
-// T), leaf inverses on the host, Y and the SMW cores on the device.
-void build_panel_hodlr(ls_panels* P, int r) {
+// HODLR factors of A = I + sign kappa^2 diag(q) V in the HODLR order perm (M = nleaves * lp
+// positions, nleaves a power of two; perm[t] = the caller's index of position t, -1 for a padding
+// unknown: an identity row and column).  Vij(i, j): V between the caller's unknowns i and j.
+// The off-diagonal blocks by partially pivoted ACA on the host at rank min(r, block side), leaf
+// inverses on the host, Y and the SMW cores on the device.
+template <class VFn>
+void build_panel_hodlr(ls_panels* P, int r, int lp, const std::vector<int>& perm, VFn Vij) {
   const double t0 = lsi::now_ms();
-  const lsp::PanelGeom& g = P->g;
-  const int ns = g.nside, n2 = g.n2, w2 = 2 * ns - 1;
-  const long long N = P->N;
+  const long long M = (long long)perm.size();
   auto H = std::make_unique<PanelHodlr>();
   H->r = r;
-  // leaves of 4^j whole boxes, at most 64 unknowns
-  int lb = 1;
-  while ((long long)lb * 4 * n2 <= 64 && (long long)lb * 4 <= (long long)ns * ns) lb *= 4;
-  H->lp = lb * n2;
-  H->nleaves = (int)(N / H->lp);
+  H->lp = lp;
+  H->nleaves = (int)(M / lp);
   H->Lb = 0;
   while ((1 << H->Lb) < H->nleaves) ++H->Lb;
-  const int lp = H->lp, Lb = H->Lb;
-  // HODLR order
-  const std::vector<int> mb = morton_boxes(ns);
-  std::vector<int> perm((size_t)N);
-  for (long long t = 0; t < N; ++t) perm[t] = mb[t / n2] * n2 + (int)(t % n2);
-  std::vector<double> qd((size_t)N), qh((size_t)N);
-  lsi::hip_check(hipMemcpy(qd.data(), P->q.p, (size_t)N * 8, hipMemcpyDeviceToHost), "q d2h");
-  for (long long t = 0; t < N; ++t) qh[t] = qd[perm[t]];
-  const size_t tsz = (size_t)w2 * w2 * n2 * n2;
-  std::vector<zd> T(tsz);
-  lsi::hip_check(hipMemcpy(T.data(), P->T.p, tsz * 16, hipMemcpyDeviceToHost), "operator blocks d2h");
-  const double coef = P->sign * g.kappa * g.kappa;
-  // entry (i, j) of A in HODLR order, i != j off the leaf blocks
-  std::vector<int> bx((size_t)N), by((size_t)N), nd((size_t)N);
-  for (long long t = 0; t < N; ++t) {
-    const int k = perm[t] / n2;
-    bx[t] = k / ns;
-    by[t] = k % ns;
-    nd[t] = perm[t] % n2;
-  }
-  auto Vij = [&](long long i, long long j) {
-    const long long d = (long long)(bx[i] - bx[j] + ns - 1) * w2 + (by[i] - by[j] + ns - 1);
-    return T[(size_t)((d * n2 + nd[i]) * n2 + nd[j])];
+  if ((long long)H->nleaves * lp != M || (1 << H->Lb) != H->nleaves)
+    throw LsError(LS_EINVAL, "HODLR order: 2^L leaves of lp positions");
+  const int Lb = H->Lb;
+  std::vector<double> qd((size_t)P->N), qh((size_t)M, 0.0);
+  lsi::hip_check(hipMemcpy(qd.data(), P->q.p, (size_t)P->N * 8, hipMemcpyDeviceToHost), "q d2h");
+  for (long long t = 0; t < M; ++t)
+    if (perm[t] >= 0) qh[t] = qd[perm[t]];
+  const double coef = P->sign * P->g.kappa * P->g.kappa;
+  // A - I at HODLR positions (zero in the rows and columns of the padding)
+  auto Aoff = [&](long long i, long long j) {
+    return perm[i] < 0 || perm[j] < 0 || qh[i] == 0.0 ? zd(0) : coef * qh[i] * Vij(perm[i], perm[j]);
   };
   // leaf inverses (column-major per leaf); leaves without contrast are the identity
   std::vector<zd> Dinv((size_t)H->nleaves * lp * lp);
@@ -412,8 +398,7 @@ void build_panel_hodlr(ls_panels* P, int r) {
     }
     std::vector<zd> a((size_t)lp * lp);
     for (int i = 0; i < lp; ++i)
-      for (int j = 0; j < lp; ++j)
-        a[(size_t)i * lp + j] = (i == j ? zd(1) : zd(0)) + coef * qh[o + i] * Vij(o + i, o + j);
+      for (int j = 0; j < lp; ++j) a[(size_t)i * lp + j] = (i == j ? zd(1) : zd(0)) + Aoff(o + i, o + j);
     if (!invert_dense(a, lp)) {
       bad[k] = 1;
       return;
@@ -426,11 +411,11 @@ void build_panel_hodlr(ls_panels* P, int r) {
     if (b) throw LsError(LS_EINVAL, "singular HODLR leaf block of the panel system");
   // off-diagonal blocks of every binary level
   H->rank.assign(Lb, 0);
-  for (int l = 0; l < Lb; ++l) H->rank[l] = (int)std::min<long long>(r, N >> (l + 1));
+  for (int l = 0; l < Lb; ++l) H->rank[l] = (int)std::min<long long>(r, M >> (l + 1));
   std::vector<std::vector<zd>> Uh(Lb), Wh(Lb);
   for (int l = 0; l < Lb; ++l) {
-    Uh[l].assign((size_t)N * H->rank[l], zd(0));
-    Wh[l].assign((size_t)N * H->rank[l], zd(0));
+    Uh[l].assign((size_t)M * H->rank[l], zd(0));
+    Wh[l].assign((size_t)M * H->rank[l], zd(0));
   }
   std::vector<std::pair<int, int>> work;
   for (int l = 0; l < Lb; ++l)
@@ -438,25 +423,24 @@ void build_panel_hodlr(ls_panels* P, int r) {
   std::vector<int> used(work.size() * 2, 0);
   lsi::parallel_for((int)work.size() * 2, [&](int wi) {
     const int l = work[wi / 2].first, b = work[wi / 2].second, which = wi % 2;
-    const long long sz = N >> l, lo = (long long)b * sz, mid = lo + sz / 2;
+    const long long sz = M >> l, lo = (long long)b * sz, mid = lo + sz / 2;
     // which = 0: A[I1, I2] ~ U W^T (U rows in the first child); which = 1: A[I2, I1]
     const long long r0 = which ? mid : lo, c0 = which ? lo : mid;
     const int m = (int)(sz / 2), n = (int)(sz / 2);
     std::vector<char> rz(m);
     for (int i = 0; i < m; ++i) rz[i] = qh[r0 + i] == 0.0;
     auto rowfn = [&](int i, zd* out) {
-      const double cq = coef * qh[r0 + i];
-      for (int j = 0; j < n; ++j) out[j] = cq * Vij(r0 + i, c0 + j);
+      for (int j = 0; j < n; ++j) out[j] = Aoff(r0 + i, c0 + j);
     };
     auto colfn = [&](int j, zd* out) {
-      for (int i = 0; i < m; ++i) out[i] = coef * qh[r0 + i] * Vij(r0 + i, c0 + j);
+      for (int i = 0; i < m; ++i) out[i] = Aoff(r0 + i, c0 + j);
     };
     ls::ACAResult R = ls::aca(m, n, H->rank[l], 0.0, &rz, rowfn, colfn);
     const int k = (int)R.u.size();
     used[wi] = k;
     for (int c = 0; c < k; ++c) {
-      for (int i = 0; i < m; ++i) Uh[l][(size_t)c * N + r0 + i] = R.u[c][i];
-      for (int j = 0; j < n; ++j) Wh[l][(size_t)c * N + c0 + j] = R.v[c][j];
+      for (int i = 0; i < m; ++i) Uh[l][(size_t)c * M + r0 + i] = R.u[c][i];
+      for (int j = 0; j < n; ++j) Wh[l][(size_t)c * M + c0 + j] = R.v[c][j];
     }
   });
   for (int k : used) {
@@ -473,11 +457,11 @@ void build_panel_hodlr(ls_panels* P, int r) {
   H->nchunks.assign(Lb, 0);
   H->cpc.assign(Lb, 0);
   for (int l = 0; l < Lb; ++l) {
-    const long long cs = N >> (l + 1);
+    const long long cs = M >> (l + 1);
     long long ch = cs;
     while (ch > 1024 && ch % 2 == 0) ch /= 2;
     H->chunk[l] = ch;
-    H->nchunks[l] = (int)(N / ch);
+    H->nchunks[l] = (int)(M / ch);
     H->cpc[l] = (int)(cs / ch);
   }
   H->Y.resize(Lb);
@@ -493,7 +477,7 @@ void build_panel_hodlr(ls_panels* P, int r) {
     rmax = std::max(rmax, H->rank[l]);
     kel = std::max(kel, (size_t)(1LL << l) * 4 * H->rank[l] * H->rank[l]);
   }
-  phod_ws(*H, N, rmax);
+  phod_ws(*H, M, rmax);
   lsi::DevBuf kA, kB, kbad;
   kA.alloc(kel * 16);
   kB.alloc(kel * 16);
@@ -503,9 +487,9 @@ void build_panel_hodlr(ls_panels* P, int r) {
   for (int l = Lb - 1; l >= 0; --l) {
     const int rl = H->rank[l], nodes = 1 << l;
     double2* Y = H->Y[l].as<double2>();
-    phod_apply(*H, N, Y, Y, rl, l + 1, s);  // Y = (levels below)^-1 U
-    lsk::launch_zero_rows(Y, N, rl, H->qh.as<double>(), s);
-    lsk::launch_hodlr_dot(0, H->W[l].p, Y, N, H->partial.as<double2>(), N, rl, H->chunk[l], H->nchunks[l], rl, s);
+    phod_apply(*H, M, Y, Y, rl, l + 1, s);  // Y = (levels below)^-1 U
+    lsk::launch_zero_rows(Y, M, rl, H->qh.as<double>(), s);
+    lsk::launch_hodlr_dot(0, H->W[l].p, Y, M, H->partial.as<double2>(), M, rl, H->chunk[l], H->nchunks[l], rl, s);
     lsk::launch_hodlr_core(0, nullptr, H->partial.as<double2>(), H->svec.as<double2>(), rl, nodes, H->cpc[l],
                            H->nchunks[l], false, rl, s);
     H->core[l].alloc((size_t)nodes * lsk::hodlr_core_elems(rl) * 16);
@@ -521,6 +505,68 @@ void build_panel_hodlr(ls_panels* P, int r) {
   lsi::hip_check(hipDeviceSynchronize(), "panel HODLR setup");
   H->t_setup_ms = lsi::now_ms() - t0;
   P->hod = std::move(H);
+}
+
+// Uniform tree (nside a power of two): boxes in Morton order, leaves of 4^j whole boxes with at
+// most 64 unknowns, no padding; V from the per-offset blocks T (copied to the host).
+void build_panel_hodlr_uniform(ls_panels* P, int r) {
+  const lsp::PanelGeom& g = P->g;
+  const int ns = g.nside, n2 = g.n2, w2 = 2 * ns - 1;
+  const long long N = P->N;
+  int lb = 1;
+  while ((long long)lb * 4 * n2 <= 64 && (long long)lb * 4 <= (long long)ns * ns) lb *= 4;
+  const std::vector<int> mb = morton_boxes(ns);
+  std::vector<int> perm((size_t)N);
+  for (long long t = 0; t < N; ++t) perm[t] = mb[t / n2] * n2 + (int)(t % n2);
+  const size_t tsz = (size_t)w2 * w2 * n2 * n2;
+  std::vector<zd> T(tsz);
+  lsi::hip_check(hipMemcpy(T.data(), P->T.p, tsz * 16, hipMemcpyDeviceToHost), "operator blocks d2h");
+  auto Vij = [&](int i, int j) {
+    const int A = i / n2, B = j / n2;
+    const long long d = (long long)(A / ns - B / ns + ns - 1) * w2 + (A % ns - B % ns + ns - 1);
+    return T[(size_t)((d * n2 + i % n2) * n2 + j % n2)];
+  };
+  build_panel_hodlr(P, r, lb * n2, perm, Vij);
+}
+
+// Leaves of any tree: boxes sorted by the Morton code of their lower-left corner on the grid of
+// the smallest half-width, leaves of floor(64 / p^2) whole boxes, padding up to 2^L leaves; V from
+// the dense device matrix (copied to the host).
+void build_panel_hodlr_leaves(ls_panels* P, int r) {
+  const int n2 = P->g.n2, nb = P->nboxes;
+  const long long N = P->N;
+  std::vector<double> bx((size_t)5 * nb);
+  lsi::hip_check(hipMemcpy(bx.data(), P->boxes.p, bx.size() * 8, hipMemcpyDeviceToHost), "boxes d2h");
+  double xmin = 1e300, ymin = 1e300, hmin = 1e300;
+  for (int B = 0; B < nb; ++B) {
+    xmin = std::min(xmin, bx[5 * B] - bx[5 * B + 2]);
+    ymin = std::min(ymin, bx[5 * B + 1] - bx[5 * B + 2]);
+    hmin = std::min(hmin, bx[5 * B + 2]);
+  }
+  std::vector<std::pair<unsigned long long, int>> key((size_t)nb);
+  for (int B = 0; B < nb; ++B) {
+    const double fx = std::floor((bx[5 * B] - bx[5 * B + 2] - xmin) / (2.0 * hmin) + 0.5);
+    const double fy = std::floor((bx[5 * B + 1] - bx[5 * B + 2] - ymin) / (2.0 * hmin) + 0.5);
+    const unsigned ix = (unsigned)std::min(fx, 1e9), iy = (unsigned)std::min(fy, 1e9);
+    unsigned long long code = 0;
+    for (int bit = 0; bit < 31; ++bit) {
+      code |= (unsigned long long)((iy >> bit) & 1) << (2 * bit);
+      code |= (unsigned long long)((ix >> bit) & 1) << (2 * bit + 1);
+    }
+    key[B] = {code, B};
+  }
+  std::stable_sort(key.begin(), key.end());
+  const int per = std::max(1, 64 / n2);
+  const int lp = per * n2;
+  long long nleaves = 1;
+  while (nleaves * lp < N) nleaves *= 2;
+  std::vector<int> perm((size_t)(nleaves * lp), -1);
+  for (int t = 0; t < nb; ++t)
+    for (int a = 0; a < n2; ++a) perm[(size_t)t * n2 + a] = key[t].second * n2 + a;
+  std::vector<zd> V((size_t)N * N);
+  lsi::hip_check(hipMemcpy(V.data(), P->V.p, V.size() * 16, hipMemcpyDeviceToHost), "dense V d2h");
+  auto Vij = [&](int i, int j) { return V[(size_t)i * N + j]; };
+  build_panel_hodlr(P, r, lp, perm, Vij);
 }
 
 }  // namespace
@@ -728,11 +774,14 @@ ls_status ls_panels_precond_setup(ls_panels* P, int rank) {
       return LS_OK;
     }
     if (rank > 256) throw LsError(LS_EINVAL, "rank must be <= 256");
-    if (P->dense) throw LsError(LS_ENOTSUP, "the HODLR preconditioner needs a uniform tree");
-    const int ns = P->g.nside;
-    if ((ns & (ns - 1)) != 0) throw LsError(LS_ENOTSUP, "the HODLR preconditioner needs nside a power of two");
     P->hod.reset();
-    build_panel_hodlr(P, rank);
+    if (P->dense) {
+      build_panel_hodlr_leaves(P, rank);
+    } else {
+      const int ns = P->g.nside;
+      if ((ns & (ns - 1)) != 0) throw LsError(LS_ENOTSUP, "the HODLR preconditioner needs nside a power of two");
+      build_panel_hodlr_uniform(P, rank);
+    }
     return LS_OK;
   } catch (const LsError& e) {
     return lsi::fail(e);

@@ -329,6 +329,80 @@ def test_panel_hodlr_preconditioned_solve():
     P.close()
 
 
+def _adaptive_case():
+    kappa, p = 5.0, 4
+    u_fn = lambda x, y: np.exp(1j * kappa * x)
+    leaves = panels.build_tree(_compact_bump, u_fn, p, 3e-2, kappa, T=16.0, max_level=4)
+    X = panels.all_nodes(leaves, p)
+    return kappa, p, leaves, _compact_bump(X[:, 0], X[:, 1])
+
+
+@pytest.mark.parametrize("rank", [12, 256])
+def test_panel_hodlr_on_adaptive_leaves(rank):
+    # leaves of an adaptive tree (dense V): the padded HODLR order, against the oracle HODLR of
+    # the oracle's padded panel matrix (rank 12) and against the dense solve (rank 256, above the
+    # blocks' numerical rank)
+    from oracle.hodlr import HODLR
+    kappa, p, leaves, q = _adaptive_case()
+    A = panels.dense_A(leaves, p, kappa, _compact_bump)
+    perm, lp = panels.hodlr_order_leaves(leaves, p)
+    say(f"panel HODLR adaptive rank={rank}: {len(leaves)} leaves, {len(perm)} positions")
+    P = ls.Panels(0, 1.0, p, kappa, q, boxes=_leaves_array(leaves))
+    info = P.precondition(rank)
+    assert info["leaf"] == lp and 2 ** info["levels"] * lp == len(perm)
+    rng = np.random.default_rng(rank + 1)
+    R = rng.standard_normal((2, P.N)) + 1j * rng.standard_normal((2, P.N))
+    Z = P.precond_apply(torch.from_numpy(R).cuda()).cpu().numpy()
+    real = perm >= 0
+    if rank < 64:
+        H = HODLR(panels.padded(A, perm), lp, rank=rank)
+        for j in range(2):
+            b = np.zeros(len(perm), dtype=complex)
+            b[real] = R[j][perm[real]]
+            ref = np.empty(P.N, dtype=complex)
+            ref[perm[real]] = H.solve(b)[real]
+            err = np.linalg.norm(Z[j] - ref) / np.linalg.norm(ref)
+            say("vs oracle HODLR", err)
+            assert err < 1e-8, err
+    else:
+        for j in range(2):
+            ref = np.linalg.solve(A, R[j])
+            err = np.linalg.norm(Z[j] - ref) / np.linalg.norm(ref)
+            say("vs dense solve", err)
+            assert err < 1e-9, err
+    P.close()
+
+
+def test_panel_hodlr_adaptive_solve_and_uniform_leaves():
+    # the preconditioned solve on the adaptive leaves = the dense solve, in fewer products; and a
+    # uniform tree given as leaves gets the same preconditioner as the uniform path
+    kappa, p, leaves, q = _adaptive_case()
+    A = panels.dense_A(leaves, p, kappa, _compact_bump)
+    f = panels.rhs_planewave(leaves, p, kappa, _compact_bump, theta=0.4)
+    ref = np.linalg.solve(A, f)
+    P = ls.Panels(0, 1.0, p, kappa, q, boxes=_leaves_array(leaves))
+    fd = torch.from_numpy(f).cuda()
+    _, i0 = P.solve(fd, tol=1e-11)
+    P.precondition(16)
+    psi, i1 = P.solve(fd, tol=1e-11)
+    say("adaptive: unpreconditioned", i0, "HODLR 16", i1)
+    assert i1["status"] == "CONVERGED" and i1["iters"] < i0["iters"]
+    assert np.linalg.norm(psi.cpu().numpy() - ref) <= 1e-9 * np.linalg.norm(ref)
+    P.close()
+    nside, p2, k2 = 4, 4, 15.0
+    boxes = panels.uniform_tree(nside)
+    qn = node_q(boxes, p2)
+    U = ls.Panels(nside, 1.0, p2, k2, qn)
+    G = ls.Panels(0, 1.0, p2, k2, qn, boxes=_leaves_array(boxes))
+    iu, ig = U.precondition(8), G.precondition(8)
+    assert (iu["leaf"], iu["levels"], iu["max_rank"]) == (ig["leaf"], ig["levels"], ig["max_rank"])
+    r = torch.from_numpy(np.random.default_rng(5).standard_normal((2, U.N)) + 0j).cuda()
+    zu, zg = U.precond_apply(r).cpu().numpy(), G.precond_apply(r).cpu().numpy()
+    assert np.abs(zu - zg).max() <= 1e-10 * np.abs(zu).max()
+    U.close()
+    G.close()
+
+
 def test_panel_hodlr_invalid_uses():
     boxes = panels.uniform_tree(4)
     P = ls.Panels(4, 1.0, 3, 10.0, node_q(boxes, 3))
@@ -346,9 +420,3 @@ def test_panel_hodlr_invalid_uses():
         P6.precondition(8)                 # nside not a power of two
     assert e.value.code == ls.LS_ENOTSUP
     P6.close()
-    leaves = panels.uniform_tree(2)
-    G = ls.Panels(0, 1.0, 2, 10.0, node_q(leaves, 2), boxes=_leaves_array(leaves))
-    with pytest.raises(ls.LsError) as e:
-        G.precondition(8)                  # leaves of a general tree
-    assert e.value.code == ls.LS_ENOTSUP
-    G.close()

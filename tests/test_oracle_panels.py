@@ -197,3 +197,23 @@ def test_panel_hodlr_at_full_rank_is_the_inverse():
     errs = [np.linalg.norm(HODLR(Ah, lp, rank=k).dense() - Ah) / np.linalg.norm(Ah) for k in (4, 8, 16, 32)]
     assert all(e2 < e1 for e1, e2 in zip(errs, errs[1:])), errs
     assert errs[-1] < 1e-5, errs
+
+
+def test_leaf_order_of_a_uniform_tree_is_the_uniform_order():
+    # on the leaves of a uniform tree the general HODLR order is the uniform one (same Morton
+    # order of boxes, no padding at p = 4); on an adaptive tree every position holds a distinct
+    # unknown or padding, padding only at the end, whole boxes in every leaf
+    p = 4
+    perm, lp = panels.hodlr_order_leaves(panels.uniform_tree(8), p)
+    assert lp == panels.hodlr_leaf(8, p) == 64
+    assert (perm == panels.hodlr_order(8, p)).all()
+    q_fn = lambda x, y: 1.5 * np.exp(-60.0 * ((x - 0.3) ** 2 + (y + 0.2) ** 2))
+    leaves = panels.build_tree(q_fn, lambda x, y: np.exp(12j * x), 3, 1e-3, 12.0, T=16.0, max_level=5)
+    perm, lp = panels.hodlr_order_leaves(leaves, 3)
+    N = len(leaves) * 9
+    assert lp == 63 and len(perm) % lp == 0 and (len(perm) // lp) & (len(perm) // lp - 1) == 0
+    assert sorted(perm[:N].tolist()) == list(range(N)) and (perm[N:] == -1).all() and len(perm) - N < len(perm) / 2
+    assert all(perm[t] // 9 == perm[t - t % 9] // 9 for t in range(N))
+    A = np.arange(16.0).reshape(4, 4)
+    P = panels.padded(A, np.array([2, -1, 0, 3, 1, -1]))
+    assert P[0, 0] == A[2, 2] and P[0, 2] == A[2, 0] and P[1, 1] == 1 and P[1, 0] == 0 and P[5, 5] == 1
