@@ -44,13 +44,17 @@ void launch_panel_blocks(const PanelGeom& g, const double2* M, const double* Qda
 void launch_panel_apply(const PanelGeom& g, const double2* T, const double* q, const double2* x, long long ldx,
                         double2* y, long long ldy, int nrhs, double alpha, double coef, hipStream_t s);
 
-// The same product on the matrix cores (FP64 MFMA, p <= kMfmaMaxP): partial planes of nchunks
-// chunks of the offsets (part: nchunks x nrhs x N complex), then their sum in chunk order.
+// The same product on the matrix cores (FP64 MFMA, p <= kMfmaMaxP) from the column-major blocks
+// Tt[d] = T[d]^T (launch_panel_blocks_t): x copied node-major into xt (nrhs x N), partial planes
+// of nchunks chunks of the offsets (part: nchunks x nrhs x N complex), then their sum in chunk
+// order.  Tiles of 16 target boxes, panel_tile_y(g) of them along y.
 constexpr int kMfmaMaxP = 5;
+int panel_tile_y(const PanelGeom& g);
 int panel_chunks(const PanelGeom& g, int nrhs);
-void launch_panel_apply_mfma(const PanelGeom& g, const double2* T, const double* q, const double2* x, long long ldx,
+void launch_panel_blocks_t(const PanelGeom& g, const double2* T, double2* Tt, hipStream_t s);
+void launch_panel_apply_mfma(const PanelGeom& g, const double2* Tt, const double* q, const double2* x, long long ldx,
                              double2* y, long long ldy, int nrhs, double alpha, double coef, double2* part,
-                             int nchunks, hipStream_t s);
+                             double2* xt, int nchunks, hipStream_t s);
 
 // Leaves of any tree (an adaptive, level-restricted one included): boxes[5 B ..] = (cx, cy, beta,
 // offset of the box's far rule in far_x / far_w, its points per direction); X: the N nodes (x, y).

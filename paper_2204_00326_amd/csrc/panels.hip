@@ -288,72 +288,80 @@ __global__ __launch_bounds__(256) void k_panel_apply(PanelGeom g, const double2*
   }
 }
 
-// The same product on the matrix cores: for a tile of 16 target boxes and an offset d, the
-// sources are the tile shifted by d (boxes outside the grid masked), and the products of that
-// offset are one (n2 x n2) by (n2 x 16 boxes) complex GEMM, RT 16-row tiles by KB 4-deep k-blocks
-// of 16 x 16 x 4 FP64 MFMAs (four real ones per complex product; rows and k past n2 padded with
-// zeros).  A workgroup takes one tile and a chunk of the offsets, its 4 waves every 4th offset
-// of the chunk, with the next offset's operands loaded before the current products; the waves'
-// sums are added through LDS in a fixed order into the chunk's partial plane, and
-// k_panel_reduce adds the chunks in order.  Lane l: T element (row l % 16, k l / 16), x element
-// (k l / 16, box l % 16); accumulator element v: row l / 16 + 4 v, box l % 16.
+// The same product on the matrix cores: for a tile of TX x TY = 16 target boxes and an offset d,
+// the sources are the tile shifted by d (boxes outside the grid masked), and the products of
+// that offset are one (n2 x n2) by (n2 x 16 boxes) complex GEMM, RT 16-row tiles by KB 4-deep
+// k-blocks of 16 x 16 x 4 FP64 MFMAs (four real ones per complex product; rows and k past n2
+// padded with zeros).  The operands are read from node-major copies, so that the 64 lanes of
+// every load take consecutive addresses: the blocks column by column (Tt[d][b][a] = T[d][a][b])
+// and the densities node by node (xt[b][B] = x[B n2 + b]).  A workgroup takes one tile and a
+// chunk of the tile's offsets, its 4 waves every 4th offset of the chunk, with the next offset's
+// operands loaded before the current products; the waves' sums are added through LDS in a fixed
+// order into the chunk's partial plane, and k_panel_reduce adds the chunks in order.  Lane l:
+// T element (row l % 16, k l / 16), x element (k l / 16, box l % 16); accumulator element v:
+// row l / 16 + 4 v, box l % 16.  Box j of a tile sits at (x0 + j / TY, y0 + j % TY).
 typedef double pf64x4 __attribute__((ext_vector_type(4)));
 
 template <int RT, int KB>
-__global__ __launch_bounds__(256) void k_panel_apply_mfma(PanelGeom g, const double2* __restrict__ T,
-                                                          const double2* __restrict__ x, long long ldx,
-                                                          double2* __restrict__ part, int nchunks, long long N) {
+__global__ __launch_bounds__(256) void k_panel_apply_mfma(PanelGeom g, const double2* __restrict__ Tt,
+                                                          const double2* __restrict__ xt,
+                                                          double2* __restrict__ part, int nchunks, long long N,
+                                                          int TY) {
   __shared__ double2 red[4][RT][4][64];
   const int tile = blockIdx.x, chunk = blockIdx.y, rhs = blockIdx.z;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n2 = g.n2, nside = g.nside, nb = nside * nside, w2 = 2 * nside - 1;
+  const int TX = 16 / TY, nty = (nside + TY - 1) / TY;
   // the offsets that pair some box of the tile with a box of the grid: a rectangle of
-  // (x extent + nside) x (y extent + nside) offsets around the tile's bounding box; chunk c of
-  // the launch takes its share of them
-  const int A0 = tile * 16, A1 = min(A0 + 15, nb - 1);
-  const int x0 = A0 / nside, x1 = A1 / nside;
-  const int y0 = x0 == x1 ? A0 % nside : 0, y1 = x0 == x1 ? A1 % nside : nside - 1;
+  // (x extent + nside - 1) x (y extent + nside - 1) offsets; chunk c of the launch takes its share
+  const int x0 = (tile / nty) * TX, y0 = (tile % nty) * TY;
+  const int x1 = min(x0 + TX, nside) - 1, y1 = min(y0 + TY, nside) - 1;
   const int wx = x1 - x0 + nside, wy = y1 - y0 + nside;
   const int dxlo = x0 - (nside - 1), dylo = y0 - (nside - 1);
   const int nrect = wx * wy;
   const int d0 = (int)((long long)nrect * chunk / nchunks), d1 = (int)((long long)nrect * (chunk + 1) / nchunks);
-  auto offset = [&](int e) { return (dxlo + e / wy + nside - 1) * w2 + (dylo + e % wy + nside - 1); };
   const int j = lane & 15, kq = lane >> 4;
-  const int A = tile * 16 + j;
-  const bool aok = A < nb;
-  const int ax = aok ? A / nside : 0, ay = aok ? A % nside : 0;
-  const double2* xr = x + rhs * ldx;
+  const int ax = x0 + j / TY, ay = y0 + j % TY;
+  const bool aok = ax < nside && ay < nside;
+  const double2* xr = xt + rhs * N;
   pf64x4 accr[RT], acci[RT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     accr[rt] = pf64x4{0, 0, 0, 0};
     acci[rt] = pf64x4{0, 0, 0, 0};
   }
-  // operands of offset d: T fragments (row rt * 16 + j, k kb * 4 + kq) and x fragments
-  // (k kb * 4 + kq, box j shifted by d)
-  auto load = [&](int d, double2 (&ta)[RT][KB], double2 (&xa)[KB]) -> bool {
-    const int dx = d / w2 - (nside - 1), dy = d % w2 - (nside - 1);
+  // operands of offset (dx, dy): T fragments (row rt * 16 + j, k kb * 4 + kq) and x fragments
+  // (k kb * 4 + kq, box j shifted by the offset)
+  auto load = [&](int dx, int dy, double2 (&ta)[RT][KB], double2 (&xa)[KB]) -> bool {
+    const long long d = (long long)(dx + nside - 1) * w2 + (dy + nside - 1);
     const int bx = ax - dx, by = ay - dy;
     const bool ok = aok && bx >= 0 && bx < nside && by >= 0 && by < nside;
     const long long B = ok ? (long long)bx * nside + by : 0;
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
       const int b = kb * 4 + kq;
-      xa[kb] = ok && b < n2 ? xr[B * n2 + b] : make_double2(0.0, 0.0);
+      xa[kb] = ok && b < n2 ? xr[(long long)b * nb + B] : make_double2(0.0, 0.0);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         const int a = rt * 16 + j;
-        ta[rt][kb] = a < n2 && b < n2 ? T[((long long)d * n2 + a) * n2 + b] : make_double2(0.0, 0.0);
+        ta[rt][kb] = a < n2 && b < n2 ? Tt[(d * n2 + b) * n2 + a] : make_double2(0.0, 0.0);
       }
     }
     return __any(ok);
   };
   double2 ta[RT][KB], xa[KB], tb[RT][KB], xb[KB];
-  int d = d0 + wave;
-  bool live = d < d1 ? load(offset(d), ta, xa) : false;
-  while (d < d1) {
-    const int dn = d + 4;
-    const bool nlive = dn < d1 ? load(offset(dn), tb, xb) : false;
+  // offset e of the rectangle = (dxlo + e / wy, dylo + e % wy), stepped without divisions
+  int e = d0 + wave;
+  int ex = e / wy, ey = e % wy;
+  bool live = e < d1 ? load(dxlo + ex, dylo + ey, ta, xa) : false;
+  while (e < d1) {
+    e += 4;
+    ey += 4;
+    while (ey >= wy) {
+      ey -= wy;
+      ++ex;
+    }
+    const bool nlive = e < d1 ? load(dxlo + ex, dylo + ey, tb, xb) : false;
     if (live) {
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb)
@@ -372,7 +380,6 @@ __global__ __launch_bounds__(256) void k_panel_apply_mfma(PanelGeom g, const dou
       for (int rt = 0; rt < RT; ++rt) ta[rt][kb] = tb[rt][kb];
     }
     live = nlive;
-    d = dn;
   }
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -380,6 +387,7 @@ __global__ __launch_bounds__(256) void k_panel_apply_mfma(PanelGeom g, const dou
     for (int v = 0; v < 4; ++v) red[wave][rt][v][lane] = make_double2(accr[rt][v], acci[rt][v]);
   __syncthreads();
   if (wave == 0 && aok) {
+    const long long A = (long long)ax * nside + ay;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -391,8 +399,28 @@ __global__ __launch_bounds__(256) void k_panel_apply_mfma(PanelGeom g, const dou
           o.x += red[w][rt][v][lane].x;
           o.y += red[w][rt][v][lane].y;
         }
-        part[((long long)chunk * gridDim.z + rhs) * N + (long long)A * n2 + a] = o;
+        part[((long long)chunk * gridDim.z + rhs) * N + A * n2 + a] = o;
       }
+  }
+}
+
+// xt[rhs][b][B] = x[rhs * ldx + B n2 + b]
+__global__ __launch_bounds__(256) void k_panel_node_major(const double2* __restrict__ x, long long ldx,
+                                                          double2* __restrict__ xt, int nb, int n2) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x, N = (long long)nb * n2;
+  const int rhs = blockIdx.y;
+  if (i >= N) return;
+  const long long b = i / nb, B = i - b * nb;
+  xt[rhs * N + i] = x[rhs * ldx + B * n2 + b];
+}
+
+// Tt[d][b][a] = T[d][a][b]
+__global__ __launch_bounds__(256) void k_panel_blocks_t(const double2* __restrict__ T, double2* __restrict__ Tt,
+                                                        int n2) {
+  const long long d = blockIdx.x;
+  for (int e = threadIdx.x; e < n2 * n2; e += 256) {
+    const int b = e / n2, a = e % n2;
+    Tt[(d * n2 + b) * n2 + a] = T[(d * n2 + a) * n2 + b];
   }
 }
 
@@ -416,10 +444,17 @@ __global__ __launch_bounds__(256) void k_panel_reduce(const double2* __restrict_
   y[rhs * ldy + i] = make_double2(alpha * xi.x + cf * re, alpha * xi.y + cf * im);
 }
 
+int panel_tile_y(const PanelGeom& g) {
+  int ty = 1;
+  while (ty < 4 && ty * 2 <= g.nside) ty *= 2;
+  return ty;
+}
+
 int panel_chunks(const PanelGeom& g, int nrhs) {
-  const int nb = g.nside * g.nside, ntiles = (nb + 15) / 16, w2 = 2 * g.nside - 1;
-  const long long N = (long long)nb * g.n2;
-  const int rect = (g.nside + 15) * g.nside;  // offsets per tile (a tile within one row of boxes)
+  const int ty = panel_tile_y(g), tx = 16 / ty;
+  const int ntiles = ((g.nside + tx - 1) / tx) * ((g.nside + ty - 1) / ty);
+  const long long N = (long long)g.nside * g.nside * g.n2;
+  const int rect = (std::min(tx, g.nside) - 1 + g.nside) * (std::min(ty, g.nside) - 1 + g.nside);
   int c = std::max(1, std::min(rect / 4, (2048 + ntiles - 1) / ntiles));
   // partial planes of at most 512 MB
   while (c > 1 && (long long)c * nrhs * N * 16 > (512LL << 20)) c /= 2;
@@ -427,26 +462,33 @@ int panel_chunks(const PanelGeom& g, int nrhs) {
 }
 
 template <int RT, int KB>
-static void apply_mfma(const PanelGeom& g, const double2* T, const double* q, const double2* x, long long ldx,
-                       double2* y, long long ldy, int nrhs, double alpha, double coef, double2* part, int nchunks,
-                       hipStream_t s) {
-  const int nb = g.nside * g.nside;
+static void apply_mfma(const PanelGeom& g, const double2* Tt, const double* q, const double2* x, long long ldx,
+                       double2* y, long long ldy, int nrhs, double alpha, double coef, double2* part, double2* xt,
+                       int nchunks, hipStream_t s) {
+  const int nb = g.nside * g.nside, ty = panel_tile_y(g), tx = 16 / ty;
+  const int ntiles = ((g.nside + tx - 1) / tx) * ((g.nside + ty - 1) / ty);
   const long long N = (long long)nb * g.n2;
-  k_panel_apply_mfma<RT, KB><<<dim3((unsigned)((nb + 15) / 16), (unsigned)nchunks, (unsigned)nrhs), 256, 0, s>>>(
-      g, T, x, ldx, part, nchunks, N);
+  k_panel_node_major<<<dim3((unsigned)((N + 255) / 256), (unsigned)nrhs), 256, 0, s>>>(x, ldx, xt, nb, g.n2);
+  k_panel_apply_mfma<RT, KB><<<dim3((unsigned)ntiles, (unsigned)nchunks, (unsigned)nrhs), 256, 0, s>>>(
+      g, Tt, xt, part, nchunks, N, ty);
   k_panel_reduce<<<dim3((unsigned)((N + 255) / 256), (unsigned)nrhs), 256, 0, s>>>(part, nchunks, nrhs, N, q, x, ldx,
                                                                                  y, ldy, alpha, coef);
 }
 
-void launch_panel_apply_mfma(const PanelGeom& g, const double2* T, const double* q, const double2* x, long long ldx,
+void launch_panel_blocks_t(const PanelGeom& g, const double2* T, double2* Tt, hipStream_t s) {
+  const int w2 = 2 * g.nside - 1;
+  k_panel_blocks_t<<<(unsigned)(w2 * w2), 256, 0, s>>>(T, Tt, g.n2);
+}
+
+void launch_panel_apply_mfma(const PanelGeom& g, const double2* Tt, const double* q, const double2* x, long long ldx,
                              double2* y, long long ldy, int nrhs, double alpha, double coef, double2* part,
-                             int nchunks, hipStream_t s) {
+                             double2* xt, int nchunks, hipStream_t s) {
   switch (g.p) {
-    case 1: apply_mfma<1, 1>(g, T, q, x, ldx, y, ldy, nrhs, alpha, coef, part, nchunks, s); break;
-    case 2: apply_mfma<1, 1>(g, T, q, x, ldx, y, ldy, nrhs, alpha, coef, part, nchunks, s); break;
-    case 3: apply_mfma<1, 3>(g, T, q, x, ldx, y, ldy, nrhs, alpha, coef, part, nchunks, s); break;
-    case 4: apply_mfma<1, 4>(g, T, q, x, ldx, y, ldy, nrhs, alpha, coef, part, nchunks, s); break;
-    case 5: apply_mfma<2, 7>(g, T, q, x, ldx, y, ldy, nrhs, alpha, coef, part, nchunks, s); break;
+    case 1: apply_mfma<1, 1>(g, Tt, q, x, ldx, y, ldy, nrhs, alpha, coef, part, xt, nchunks, s); break;
+    case 2: apply_mfma<1, 1>(g, Tt, q, x, ldx, y, ldy, nrhs, alpha, coef, part, xt, nchunks, s); break;
+    case 3: apply_mfma<1, 3>(g, Tt, q, x, ldx, y, ldy, nrhs, alpha, coef, part, xt, nchunks, s); break;
+    case 4: apply_mfma<1, 4>(g, Tt, q, x, ldx, y, ldy, nrhs, alpha, coef, part, xt, nchunks, s); break;
+    case 5: apply_mfma<2, 7>(g, Tt, q, x, ldx, y, ldy, nrhs, alpha, coef, part, xt, nchunks, s); break;
     default: break;  // p > 5: the double-buffered operands would not fit the registers (VALU form)
   }
 }

@@ -42,7 +42,9 @@ struct ls_panels {
   int nboxes = 0;
   lsi::DevBuf V, X, boxes;
   lsi::DevBuf ref, far_x, far_w, qdag, M, T, q;
+  lsi::DevBuf Tt;    // column-major copies of the blocks (matrix-core product)
   lsi::DevBuf part;  // partial planes of the matrix-core product (one stream at a time)
+  lsi::DevBuf xt;    // node-major copy of the product's input (one stream at a time)
   bool mfma = true;
   lsi::DevBuf kq, kw, kr, kpart, kc;  // GMRES basis, work vectors, dot partials, coefficients
   lsi::DevBuf kz;                     // preconditioned vector of the GMRES
@@ -617,6 +619,11 @@ ls_status ls_panels_setup(int nside, double L, int p, double kappa, const double
     lsi::hip_check(hipGetLastError(), "panel moments");
     lsp::launch_panel_blocks(g, P->M.as<double2>(), P->qdag.as<double>(), P->T.as<double2>(), s);
     lsi::hip_check(hipGetLastError(), "panel blocks");
+    if (p <= lsp::kMfmaMaxP) {
+      P->Tt.alloc(noff * n2 * n2 * 16);
+      lsp::launch_panel_blocks_t(g, P->T.as<double2>(), P->Tt.as<double2>(), s);
+      lsi::hip_check(hipGetLastError(), "panel blocks (column-major)");
+    }
     lsi::hip_check(hipDeviceSynchronize(), "panels setup");
     *out = P.release();
     return LS_OK;
@@ -751,8 +758,9 @@ ls_status ls_panels_apply(ls_panels* P, const void* x, void* y, int nrhs, int64_
       const int nc = lsp::panel_chunks(P->g, nrhs);
       const int64_t N = P->N;
       P->part.ensure((size_t)nc * nrhs * N * 16);
-      lsp::launch_panel_apply_mfma(P->g, P->T.as<double2>(), q, (const double2*)x, ld, (double2*)y, ld, nrhs, alpha,
-                                   coef, P->part.as<double2>(), nc, (hipStream_t)stream);
+      P->xt.ensure((size_t)nrhs * N * 16);
+      lsp::launch_panel_apply_mfma(P->g, P->Tt.as<double2>(), q, (const double2*)x, ld, (double2*)y, ld, nrhs, alpha,
+                                   coef, P->part.as<double2>(), P->xt.as<double2>(), nc, (hipStream_t)stream);
     } else {
       lsp::launch_panel_apply(P->g, P->T.as<double2>(), q, (const double2*)x, ld, (double2*)y, ld, nrhs, alpha,
                               coef, (hipStream_t)stream);
@@ -874,8 +882,9 @@ ls_status ls_panels_solve(ls_panels* P, const void* f, void* psi, double tol, in
       } else if (P->mfma && P->g.p <= lsp::kMfmaMaxP) {
         const int nc = lsp::panel_chunks(P->g, 1);
         P->part.ensure((size_t)nc * N * 16);
-        lsp::launch_panel_apply_mfma(P->g, P->T.as<double2>(), P->q.as<double>(), in, N, out, N, 1, 1.0,
-                                     P->sign * k2, P->part.as<double2>(), nc, s);
+        P->xt.ensure((size_t)N * 16);
+        lsp::launch_panel_apply_mfma(P->g, P->Tt.as<double2>(), P->q.as<double>(), in, N, out, N, 1, 1.0,
+                                     P->sign * k2, P->part.as<double2>(), P->xt.as<double2>(), nc, s);
       } else {
         lsp::launch_panel_apply(P->g, P->T.as<double2>(), P->q.as<double>(), in, N, out, N, 1, 1.0, P->sign * k2, s);
       }

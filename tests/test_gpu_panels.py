@@ -70,7 +70,7 @@ def test_single_node_box_is_the_cell_rule():
 
 # p <= 5 runs the matrix-core product, p = 6 the vector-ALU one
 @pytest.mark.parametrize("nside,p,kappa,sign", [(4, 3, 10.0, -1), (3, 4, 25.0, 1), (1, 5, 6.0, -1), (2, 5, 7.0, -1),
-                                                (2, 6, 8.0, -1)])
+                                                (2, 6, 8.0, -1), (8, 5, 12.0, -1), (6, 4, 9.0, 1)])
 def test_operator_matches_dense_oracle(nside, p, kappa, sign):
     L = 1.0
     boxes = panels.uniform_tree(nside, L)
@@ -96,6 +96,33 @@ def test_operator_matches_dense_oracle(nside, p, kappa, sign):
     # a single column equals the same column of the block
     y0 = P.apply(Xd[0].contiguous(), op=0).cpu().numpy()
     assert np.abs(y0 - Y[0]).max() <= 1e-14 * np.abs(Y[0]).max()
+    P.close()
+
+
+def test_operator_rows_at_the_benchmark_size():
+    # 32 x 32 boxes at p = 4 (16384 unknowns, the benchmark's panel workload: 4 x 4 box tiles on
+    # the matrix cores): sampled rows of y = A x against rows the oracle forms box by box
+    nside, p, kappa = 32, 4, 40.0
+    boxes = panels.uniform_tree(nside)
+    X = panels.all_nodes(boxes, p)
+    q = (np.hypot(X[:, 0], X[:, 1]) < 0.6).astype(float)
+    P = ls.Panels(nside, 1.0, p, kappa, q)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(P.N) + 1j * rng.standard_normal(P.N)
+    y = P.apply(torch.from_numpy(x).cuda(), op=0).cpu().numpy()
+    u = P.apply(torch.from_numpy(x).cuda(), op=1).cpu().numpy()
+    Qd = panels.interp_pinv(p)
+    n2 = p * p
+    rows = [0, 5, 8200, 8201 + 16 * 3, P.N // 2 + 16 * 17 + 7, P.N - 1]
+    for i in rows:
+        vi = np.concatenate([(panels.moments(X[i:i + 1], b, p, kappa) @ Qd).ravel() for b in boxes])
+        ref_u = vi @ x
+        ref_y = x[i] - kappa ** 2 * q[i] * ref_u
+        scale = np.abs(vi) @ np.abs(x)
+        say(i, abs(u[i] - ref_u) / scale, abs(y[i] - ref_y) / (abs(x[i]) + kappa ** 2 * q[i] * scale))
+        assert abs(u[i] - ref_u) <= 1e-10 * scale
+        assert abs(y[i] - ref_y) <= 1e-10 * (abs(x[i]) + kappa ** 2 * q[i] * scale)
+    assert n2 * len(boxes) == P.N
     P.close()
 
 
