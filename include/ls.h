@@ -114,6 +114,10 @@ typedef struct {
                          order (the near field fills the waits of the upward and downward chains;
                          same sums per block, bit-identical results); 0 (default): one launch per
                          pass, faster on this part (the chain blocks slow down under the filler) */
+  int nca_device;     /* 1 (default): the NCA pivots (ACA at eps_NCA, Section 4.2.2 step 2) and the
+                         interpolation operators U, C (X = V(candidates, far pivots) B^-1) are formed on
+                         the GPU, one workgroup per direction of a level; 0: on the host (same rules,
+                         other rounding, so pivots may differ where magnitudes nearly tie) */
 } ls_options;
 
 typedef struct {

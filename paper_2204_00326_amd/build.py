@@ -16,7 +16,8 @@ OUT = os.path.join(HERE, "libls.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
 SOURCES = ["kernels.hip", "plan.cpp", "api.cpp", "api_setup.cpp", "api_fmm.cpp", "api_hodlr.cpp", "api_gmres.cpp",
-           "api_queue.cpp", "nop.hip", "nop_api.cpp", "field.hip", "hodlr_setup.hip", "panels.hip", "panels_api.cpp"]
+           "api_queue.cpp", "nop.hip", "nop_api.cpp", "field.hip", "hodlr_setup.hip", "panels.hip", "panels_api.cpp",
+           "nca_device.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -1,6 +1,7 @@
 // Setup entry points of libls: default options, option validation, the host plan summary,
 // ls_setup (grid, quadtree, NCA, operators, HODLR), statistics and destruction.
 #include "api_internal.h"
+#include "nca_device.h"
 
 namespace lsi {
 
@@ -69,6 +70,7 @@ void ls_default_options(ls_options* o) {
   o->graph_iters = 0;
   o->stencil_mfma = 1;
   o->fmm_fused = 0;
+  o->nca_device = 1;
   o->pc_bf16 = 1;
   o->pc_lowp_solves = 0;
   o->hodlr_tol = 0.0;
@@ -95,6 +97,7 @@ static void validate_options(const ls_options& o) {
   if (o.pc_lowp_solves != 0 && o.pc_lowp_solves != 1) throw LsError(LS_EINVAL, "pc_lowp_solves must be 0 or 1");
   if (!(o.hodlr_tol >= 0 && o.hodlr_tol < 1)) throw LsError(LS_EINVAL, "hodlr_tol must be in [0, 1)");
   if (o.dcgs2 != 0 && o.dcgs2 != 1) throw LsError(LS_EINVAL, "dcgs2 must be 0 or 1");
+  if (o.nca_device != 0 && o.nca_device != 1) throw LsError(LS_EINVAL, "nca_device must be 0 or 1");
 }
 
 ls_status ls_plan_describe(int n, double L, double kappa, const ls_options* opt, ls_plan_info* out) {
@@ -275,11 +278,17 @@ ls_status ls_setup(const double* points, int64_t N, const double* q, double kapp
     }
     // ---- NCA factors and device operators ----
     double t_w = now_ms();
-    P->nca64 = ls::build_nca(p, W, tol);
+    DevBuf wdev;  // the table with the self-cell term, for the NCA on the device
+    if (P->opt.nca_device) wdev.upload(W.w);
+    auto nca = [&](double eps) {
+      return P->opt.nca_device ? ls::build_nca_device(p, W, wdev.as<double2>(), eps, nullptr)
+                               : ls::build_nca(p, W, eps);
+    };
+    P->nca64 = nca(tol);
     build_fmm_ops(P.get(), P->nca64, P->f64, false);
     if (P->opt.build_fp32) {
       if (P->opt.eps_inner > 0 && P->opt.eps_inner > tol)
-        P->nca32 = ls::build_nca(p, W, P->opt.eps_inner);
+        P->nca32 = nca(P->opt.eps_inner);
       else
         P->nca32 = P->nca64;
       build_fmm_ops(P.get(), P->nca32, P->f32, true);

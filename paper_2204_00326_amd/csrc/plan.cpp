@@ -303,27 +303,95 @@ void lu_solve_transposed(const std::vector<zd>& B, int k, std::vector<zd>& X, in
 
 // ---- NCA (Section 4) -------------------------------------------------------------------
 
-NCA build_nca(const Plan& p, const WTable& W, double tol) {
-  NCA out;
-  out.lv.resize(p.leaf + 1);
-  const int leaf = p.leaf;
+// V(leaf points, leaf points + d * side) for the 9 neighbour offsets d of a leaf (near field)
+void nca_near_tiles(const Plan& p, const WTable& W, NCA& out) {
   const int s = p.leaf_side;
-  auto Vent = [&](const Off& t, const Off& src) { return W(t.a - src.a, t.b - src.b); };
-  std::vector<Off> leafpts;
-  for (int a = 0; a < s; ++a)
-    for (int b = 0; b < s; ++b) leafpts.push_back({a, b});
-  // near tiles: V(leaf points, leaf points + d*side)
+  std::vector<Off> leafpts = nca_leaf_points(p);
   out.near.resize(9);
   for (int da = -1; da <= 1; ++da)
     for (int db = -1; db <= 1; ++db) {
       auto& T = out.near[(da + 1) * 3 + (db + 1)];
       T.resize((size_t)s * s * s * s);
       for (int i = 0; i < s * s; ++i)
-        for (int j = 0; j < s * s; ++j) {
-          Off src{leafpts[j].a + da * s, leafpts[j].b + db * s};
-          T[(size_t)i * s * s + j] = Vent(leafpts[i], src);
-        }
+        for (int j = 0; j < s * s; ++j)
+          T[(size_t)i * s * s + j] = W(leafpts[i].a - (leafpts[j].a + da * s), leafpts[i].b - (leafpts[j].b + db * s));
     }
+}
+
+std::vector<Off> nca_leaf_points(const Plan& p) {
+  std::vector<Off> leafpts;
+  for (int a = 0; a < p.leaf_side; ++a)
+    for (int b = 0; b < p.leaf_side; ++b) leafpts.push_back({a, b});
+  return leafpts;
+}
+
+// candidate sets of level nu, direction dir (Section 4.2.2, step 1): targets are the leaf
+// points, or the self pivots of the four children; sources are the same sets translated by
+// every offset of the direction's far set (the antipodal cone's child pivots)
+void nca_candidates(const Plan& p, const NCA& out, int nu, int dir, std::vector<Off>& tcand,
+                    std::vector<Off>& scand) {
+  const Level& l = p.lv[nu];
+  const bool is_leaf = (nu == p.leaf);
+  const int s = p.leaf_side;
+  const LevelNCA* CL = is_leaf ? nullptr : &out.lv[nu + 1];
+  const Level* cl = is_leaf ? nullptr : &p.lv[nu + 1];
+  const int cs = is_leaf ? 0 : cl->side;
+  auto child_dir = [&](int d) { return (!is_leaf && cl->hf) ? d / 2 : 0; };
+  tcand.clear();
+  scand.clear();
+  std::vector<Off> leafpts = is_leaf ? nca_leaf_points(p) : std::vector<Off>();
+  if (is_leaf) {
+    tcand = leafpts;
+  } else {
+    int cd = child_dir(dir);
+    for (int c = 0; c < 4; ++c)
+      for (const Off& q : CL->self[cd]) tcand.push_back({(c >> 1) * cs + q.a, (c & 1) * cs + q.b});
+  }
+  int ad = antipodal(dir, l.ndir);
+  for (const Off& d : l.farset[dir]) {
+    if (is_leaf) {
+      for (const Off& q : leafpts) scand.push_back({d.a * s + q.a, d.b * s + q.b});
+    } else {
+      int cd = child_dir(ad);
+      for (int c = 0; c < 4; ++c)
+        for (const Off& q : CL->self[cd])
+          scand.push_back({d.a * l.side + (c >> 1) * cs + q.a, d.b * l.side + (c & 1) * cs + q.b});
+    }
+  }
+}
+
+// M2L operators (Section 5, transverse pass): K = V(self pivots of B, self pivots of B + d)
+void nca_m2l(const Plan& p, const WTable& W, NCA& out) {
+  for (int nu = p.top; nu <= p.leaf; ++nu) {
+    const Level& l = p.lv[nu];
+    LevelNCA& L = out.lv[nu];
+    const int nd = l.ndir;
+    L.kofs.assign(nd, {});
+    L.K.assign(nd, {});
+    for (int dir = 0; dir < nd; ++dir) {
+      int ad = antipodal(dir, nd);
+      const std::vector<Off>& P = L.self[dir];
+      const std::vector<Off>& Q = L.self[ad];
+      for (const Off& d : l.farset[dir]) {
+        std::vector<zd> K(P.size() * Q.size());
+        for (size_t i = 0; i < P.size(); ++i)
+          for (size_t j = 0; j < Q.size(); ++j)
+            K[i * Q.size() + j] = W(P[i].a - (Q[j].a + d.a * l.side), P[i].b - (Q[j].b + d.b * l.side));
+        L.kofs[dir].push_back(d);
+        L.K[dir].push_back(std::move(K));
+      }
+    }
+  }
+}
+
+NCA build_nca(const Plan& p, const WTable& W, double tol) {
+  NCA out;
+  out.lv.resize(p.leaf + 1);
+  const int leaf = p.leaf;
+  const int s = p.leaf_side;
+  auto Vent = [&](const Off& t, const Off& src) { return W(t.a - src.a, t.b - src.b); };
+  std::vector<Off> leafpts = nca_leaf_points(p);
+  nca_near_tiles(p, W, out);
   if (p.top > leaf) return out;  // no far field
   int nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   for (int nu = leaf; nu >= p.top; --nu) {
@@ -342,27 +410,8 @@ NCA build_nca(const Plan& p, const WTable& W, double tol) {
     std::vector<std::string> errs(nd);
     auto work = [&](int dir) {
       try {
-        // candidate sets (Section 4.2.2, step 1)
         std::vector<Off> tcand, scand;
-        std::vector<Off> selfchild;  // for L2L: which child/pivot each candidate came from
-        if (is_leaf) {
-          tcand = leafpts;
-        } else {
-          int cd = child_dir(dir);
-          for (int c = 0; c < 4; ++c)
-            for (const Off& q : CL->self[cd]) tcand.push_back({(c >> 1) * cs + q.a, (c & 1) * cs + q.b});
-        }
-        int ad = antipodal(dir, nd);
-        for (const Off& d : l.farset[dir]) {
-          if (is_leaf) {
-            for (const Off& q : leafpts) scand.push_back({d.a * s + q.a, d.b * s + q.b});
-          } else {
-            int cd = child_dir(ad);
-            for (int c = 0; c < 4; ++c)
-              for (const Off& q : CL->self[cd])
-                scand.push_back({d.a * l.side + (c >> 1) * cs + q.a, d.b * l.side + (c & 1) * cs + q.b});
-          }
-        }
+        nca_candidates(p, out, nu, dir, tcand, scand);
         int m = (int)tcand.size(), nn = (int)scand.size();
         // step 2: ACA with accuracy tol on A(tcand, scand)
         ACAResult R = aca(
@@ -422,29 +471,7 @@ NCA build_nca(const Plan& p, const WTable& W, double tol) {
     for (int dir = 0; dir < nd; ++dir) L.kmax = std::max(L.kmax, L.rank[dir]);
     if (is_leaf) out.kleaf = L.rank[0];
   }
-  // M2L operators (Section 5, transverse pass): K = V(self pivots of B, self pivots of B + d)
-  for (int nu = p.top; nu <= leaf; ++nu) {
-    const Level& l = p.lv[nu];
-    LevelNCA& L = out.lv[nu];
-    const int nd = l.ndir;
-    L.kofs.assign(nd, {});
-    L.K.assign(nd, {});
-    for (int dir = 0; dir < nd; ++dir) {
-      int ad = antipodal(dir, nd);
-      const std::vector<Off>& P = L.self[dir];
-      const std::vector<Off>& Q = L.self[ad];
-      for (const Off& d : l.farset[dir]) {
-        std::vector<zd> K(P.size() * Q.size());
-        for (size_t i = 0; i < P.size(); ++i)
-          for (size_t j = 0; j < Q.size(); ++j) {
-            Off src{Q[j].a + d.a * l.side, Q[j].b + d.b * l.side};
-            K[i * Q.size() + j] = Vent(P[i], src);
-          }
-        L.kofs[dir].push_back(d);
-        L.K[dir].push_back(std::move(K));
-      }
-    }
-  }
+  nca_m2l(p, W, out);
   return out;
 }
 

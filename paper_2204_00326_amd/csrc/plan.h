@@ -95,6 +95,17 @@ struct WTable {
 
 NCA build_nca(const Plan& p, const WTable& W, double tol);
 
+// Pieces of the NCA shared by the host and the device builds: the leaf's points (grid offsets
+// inside a leaf), the 9 near-field tiles, the candidate sets of one level and direction
+// (targets: leaf points or the children's self pivots; sources: the far set's translates), and
+// the M2L operators from the self pivots of every level.  The interpolation operator of a
+// level and direction has one row per target candidate (the leaf points at the leaf level,
+// child c's self pivots in rows c * k_child ... at the others).
+std::vector<Off> nca_leaf_points(const Plan& p);
+void nca_near_tiles(const Plan& p, const WTable& W, NCA& out);
+void nca_candidates(const Plan& p, const NCA& out, int nu, int dir, std::vector<Off>& tcand, std::vector<Off>& scand);
+void nca_m2l(const Plan& p, const WTable& W, NCA& out);
+
 // Partially pivoted ACA on an m x n block given by entry(i, j), row(i, out), col(j, out).
 struct ACAResult {
   std::vector<int> rows, cols;

@@ -42,7 +42,7 @@ class _Options(C.Structure):
                 ("inner_tol", C.c_double), ("max_refine", C.c_int), ("build_fp32", C.c_int),
                 ("hodlr_rank_div", C.c_int), ("graph_iters", C.c_int),
                 ("stencil_mfma", C.c_int), ("pc_bf16", C.c_int), ("dcgs2", C.c_int), ("pc_lowp_solves", C.c_int),
-                ("hodlr_tol", C.c_double), ("fmm_fused", C.c_int)]
+                ("hodlr_tol", C.c_double), ("fmm_fused", C.c_int), ("nca_device", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -192,6 +192,7 @@ class Options:
     pc_lowp_solves: int = 0
     hodlr_tol: float = 0.0
     fmm_fused: int = 0
+    nca_device: int = 1
 
     def _c(self) -> _Options:
         o = _Options()
