@@ -31,7 +31,9 @@ namespace {
 
 constexpr int NT = 512, NW = NT / 64;
 constexpr double kTie = 1e-9;
-constexpr int kRankCap = 256;  // workspace columns per direction (ranks here are 15-60)
+// workspace columns per direction: min(m, nn) (the host routine's rank limit) up to this cap; ranks at
+// eps_NCA >= 1e-15 stay far below it (15-60 on the benchmark grids, 46 at eps 1e-15 on 32 x 32)
+constexpr int kRankCap = 4096;
 
 struct NcaArgs {
   const double2* W;  // (2n-1)^2 table, offset (da, db) at (da+n-1)(2n-1) + db+n-1
