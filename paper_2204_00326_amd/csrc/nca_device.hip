@@ -29,7 +29,7 @@
 
 namespace {
 
-constexpr int NT = 512, NW = NT / 64;
+constexpr int NT = 1024, NW = NT / 64;
 constexpr double kTie = 1e-9;
 // workspace columns per direction: min(m, nn) (the host routine's rank limit) up to this cap; ranks at
 // eps_NCA >= 1e-15 stay far below it (15-60 on the benchmark grids, 46 at eps 1e-15 on 32 x 32)
