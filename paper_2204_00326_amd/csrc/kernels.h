@@ -196,6 +196,8 @@ long long hodlr_core_elems(int r);
 // zero and K^-1 reduces to the identity on the half of s the other child uses (s_A = t_A when
 // only the first child holds contrast, s_B = t_B when only the second does); that half is
 // written as t, the unused half as zeros, without reading K^-1; nodes without contrast get s = 0.
+// With apply, one right-hand side and chunks_per_child >= 16 the partials are folded in place (each
+// child's sum lands in its first partial) before the core products: they are scratch to the caller.
 void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, double2* sout, int r, int nodes,
                        int chunks_per_child, int nchunks, bool apply, int nrhs, hipStream_t s,
                        const unsigned char* cact = nullptr);

@@ -1411,7 +1411,8 @@ template <typename TC, int NT, int R2MAX = 256, int RB = 1>
 __global__ __launch_bounds__(NT) void k_hodlr_core_rows(const double2* __restrict__ partial,
                                                         const typename V2<TC>::type* __restrict__ coreinv,
                                                         double2* __restrict__ sout, int r, int nodes, int cpc,
-                                                        int nchunks, int nrf, const unsigned char* __restrict__ cact) {
+                                                        int nchunks, int nrf, const unsigned char* __restrict__ cact,
+                                                        int cstr) {
   constexpr int CG = NT / 16;
   constexpr int MAXU = R2MAX / CG;  // columns per thread at 2r = R2MAX
   using VT = typename V2<TC>::type;
@@ -1454,7 +1455,7 @@ __global__ __launch_bounds__(NT) void k_hodlr_core_rows(const double2* __restric
       const int v = threadIdx.x % r2, ks = threadIdx.x / r2;
       const int half = v < r ? 1 : 0;  // t_A sums the second child
       const int c = v < r ? v : v - r;
-      const long long ch0 = (long long)node * 2 * cpc + (long long)half * cpc;
+      const long long ch0 = (long long)node * 2 * cstr + (long long)half * cstr;  // cstr: chunks per child in the layout
       // a one-sided node uses only the half of t that its child with contrast multiplies; the
       // chunk partials of the other half were not formed by the masked W^T z (stale) and are not read
       const int kend = (m == 3 || (m & (v < r ? 1 : 2))) ? cpc : 0;
@@ -1512,11 +1513,45 @@ __global__ __launch_bounds__(NT) void k_hodlr_core_rows(const double2* __restric
   }
 }
 
+// One right-hand side: the cpc chunk partials of W^T z over one child, summed into the child's first
+// partial.  Workgroup (2 node + half, 64-column block); thread (c, ks) adds the chunks ks, ks + 16, ...
+// and the 16 slices are added in slice order.  Halves that the core does not read (the child without
+// contrast of a one-sided node, both of a node without contrast) are skipped.
+__global__ __launch_bounds__(1024) void k_hodlr_tsum_inplace(double2* __restrict__ partial, int r, int cpc,
+                                                             const unsigned char* __restrict__ cact) {
+  __shared__ double2 sl[16][64];
+  const int nh = blockIdx.x, node = nh >> 1, half = nh & 1;
+  const int ci = threadIdx.x & 63, ks = threadIdx.x >> 6;
+  const int c = blockIdx.y * 64 + ci;
+  // the partials of half 1 (the second child's rows) make t_A, which the core reads when the first
+  // child has contrast; those of half 0 make t_B, read when the second child has contrast
+  const int m = cact ? (cact[2 * node] ? 1 : 0) | (cact[2 * node + 1] ? 2 : 0) : 3;
+  if (!(m & (half ? 1 : 2))) return;
+  double2* P = partial + ((long long)node * 2 * cpc + (long long)half * cpc) * r;
+  double re = 0, im = 0;
+  if (c < r)
+#pragma unroll 4
+    for (int k = ks; k < cpc; k += 16) {
+      const double2 v = P[(long long)k * r + c];
+      re += v.x;
+      im += v.y;
+    }
+  sl[ks][ci] = make_double2(re, im);
+  __syncthreads();
+  if (ks == 0 && c < r) {
+    for (int q = 1; q < 16; ++q) {
+      re += sl[q][ci].x;
+      im += sl[q][ci].y;
+    }
+    P[c] = make_double2(re, im);
+  }
+}
+
 long long hodlr_core_elems(int r) { return (long long)((2 * r + 15) / 16) * 16 * (2 * r); }
 
 template <typename TC, int RB>
 static void core_rows_shape(const void* coreinv, const double2* partial, double2* sout, int r, int nodes, int cpc,
-                            int nchunks, int nrhs, hipStream_t s, const unsigned char* cact) {
+                            int nchunks, int nrhs, hipStream_t s, const unsigned char* cact, int cstr) {
   const int nrf = nrhs > 1 ? nrhs : 0;
   const int nrb = (nrhs + RB - 1) / RB;
   dim3 grid(nrf ? nodes * nrb : nodes, (2 * r + 15) / 16, nrf ? 1 : nrhs);
@@ -1525,31 +1560,41 @@ static void core_rows_shape(const void* coreinv, const double2* partial, double2
   if (2 * r > 256) {
     if (cpc >= 16) {
       auto kern = k_hodlr_core_rows<TC, 1024, 512, RB>;
-      LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf, cact);
+      LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf, cact, cstr);
     } else {
       auto kern = k_hodlr_core_rows<TC, 512, 512, RB>;
-      LSK_LAUNCH(kern, grid, 512, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf, cact);
+      LSK_LAUNCH(kern, grid, 512, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf, cact, cstr);
     }
     return;
   }
   // many partials per node (the coarse levels): 1024 threads share the sums of t
   if (cpc >= 16) {
     auto kern = k_hodlr_core_rows<TC, 1024, 256, RB>;
-    LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf, cact);
+    LSK_LAUNCH(kern, grid, 1024, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf, cact, cstr);
   } else {
     auto kern = k_hodlr_core_rows<TC, 256, 256, RB>;
-    LSK_LAUNCH(kern, grid, 256, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf, cact);
+    LSK_LAUNCH(kern, grid, 256, 0, s, partial, C, sout, r, nodes, cpc, nchunks, nrf, cact, cstr);
   }
 }
 
 template <typename TC>
-static void core_rows_pick(const void* coreinv, const double2* partial, double2* sout, int r, int nodes, int cpc,
+static void core_rows_pick(const void* coreinv, double2* partial, double2* sout, int r, int nodes, int cpc,
                            int nchunks, int nrhs, hipStream_t s, const unsigned char* cact) {
   // many right-hand sides: 8 per workgroup share each block of K^-1 (same sums per column)
-  if (nrhs >= 8)
-    core_rows_shape<TC, 8>(coreinv, partial, sout, r, nodes, cpc, nchunks, nrhs, s, cact);
-  else
-    core_rows_shape<TC, 1>(coreinv, partial, sout, r, nodes, cpc, nchunks, nrhs, s, cact);
+  if (nrhs >= 8) {
+    core_rows_shape<TC, 8>(coreinv, partial, sout, r, nodes, cpc, nchunks, nrhs, s, cact, cpc);
+    return;
+  }
+  // one right-hand side and many chunk partials per child (the coarse levels): every row block of
+  // a node would sum all of them again, so one launch first folds them into the first partial of
+  // each child, and the core reads that one
+  if (nrhs == 1 && cpc >= 16) {
+    const dim3 grid((unsigned)(nodes * 2), (unsigned)((r + 63) / 64));
+    LSK_LAUNCH(k_hodlr_tsum_inplace, grid, 1024, 0, s, partial, r, cpc, cact);
+    core_rows_shape<TC, 1>(coreinv, partial, sout, r, nodes, 1, nchunks, nrhs, s, cact, cpc);
+    return;
+  }
+  core_rows_shape<TC, 1>(coreinv, partial, sout, r, nodes, cpc, nchunks, nrhs, s, cact, cpc);
 }
 
 void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, double2* sout, int r, int nodes,
@@ -1557,12 +1602,15 @@ void launch_hodlr_core(int cfmt, const void* coreinv, const double2* partial, do
                        const unsigned char* cact) {
   if (2 * r > 512) throw std::runtime_error("HODLR cores need rank <= 256");
   if (apply) {
+    // the partials are consumed here: with one right-hand side and 16 or more chunks per child they
+    // are folded in place (every caller owns them as writable scratch)
+    double2* pw = const_cast<double2*>(partial);
     if (cfmt == 2)
-      core_rows_pick<bf16>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s, cact);
+      core_rows_pick<bf16>(coreinv, pw, sout, r, nodes, chunks_per_child, nchunks, nrhs, s, cact);
     else if (cfmt == 1)
-      core_rows_pick<float>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s, cact);
+      core_rows_pick<float>(coreinv, pw, sout, r, nodes, chunks_per_child, nchunks, nrhs, s, cact);
     else
-      core_rows_pick<double>(coreinv, partial, sout, r, nodes, chunks_per_child, nchunks, nrhs, s, cact);
+      core_rows_pick<double>(coreinv, pw, sout, r, nodes, chunks_per_child, nchunks, nrhs, s, cact);
     return;
   }
   dim3 grid(nodes, nrhs);
